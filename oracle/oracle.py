@@ -1,0 +1,105 @@
+"""ctypes front of the C oracle (fh_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the CPU
+baseline leg of the benchmark are the only importers.  The product package
+never imports this module.
+
+All arrays are numpy float64, C-contiguous, on the host.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fh_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+STATUS = {0: "ok", 1: "bad argument", 2: "bad degree", 3: "nodes not strictly increasing",
+          4: "non-finite node", 5: "weight out of range"}
+
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with the flags its header states; returns the path."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        cmd = ["gcc", "-O2", "-std=c11", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
+               "-shared", "-fPIC", _SRC, "-o", _LIB + ".tmp", "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        i64, i32 = ctypes.c_int64, ctypes.c_int32
+        lib.fho_weights.argtypes = [dp, i64, i32, dp]
+        lib.fho_eval.argtypes = [dp, dp, i64, i32, dp, dp, i64, dp, dp, dp, i32, i32]
+        lib.fho_backward.argtypes = [dp, dp, i64, i32, dp, i64, dp, dp, dp, dp, dp, i32]
+        lib.fho_threads.argtypes = [i32]
+        for fn in (lib.fho_weights, lib.fho_eval, lib.fho_backward, lib.fho_threads):
+            fn.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code):
+        super().__init__(f"oracle status {code}: {STATUS.get(code, '?')}")
+        self.code = code
+
+
+def _p(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def weights(nodes, d):
+    x = _f64(nodes)
+    w = np.empty_like(x)
+    st = _load().fho_weights(_p(x), x.size, int(d), _p(w))
+    if st:
+        raise OracleError(st)
+    return w
+
+
+def evaluate(nodes, values, d, pts, w=None, lebesgue=True, scale=True, compensated=True,
+             nthreads=0):
+    """Returns (r, Lambda or None, S or None)."""
+    x, f, t = _f64(nodes), _f64(values), _f64(pts)
+    wv = None if w is None else _f64(w)
+    r = np.empty_like(t)
+    lam = np.empty_like(t) if lebesgue else None
+    sc = np.empty_like(t) if scale else None
+    st = _load().fho_eval(_p(x), _p(f), x.size, int(d), _p(wv), _p(t), t.size, _p(r), _p(lam),
+                          _p(sc), int(bool(compensated)), int(nthreads))
+    if st:
+        raise OracleError(st)
+    return r, lam, sc
+
+
+def backward(nodes, values, d, pts, grad, nthreads=0):
+    """Returns dict with d_values, d_points, d_weights, d_nodes (total)."""
+    x, f, t, g = _f64(nodes), _f64(values), _f64(pts), _f64(grad)
+    df, dw, dx = np.empty_like(x), np.empty_like(x), np.empty_like(x)
+    dp = np.empty_like(t)
+    st = _load().fho_backward(_p(x), _p(f), x.size, int(d), _p(t), t.size, _p(g), _p(df),
+                              _p(dp), _p(dw), _p(dx), int(nthreads))
+    if st:
+        raise OracleError(st)
+    return {"d_values": df, "d_points": dp, "d_weights": dw, "d_nodes": dx}
+
+
+def threads(nthreads=0):
+    return int(_load().fho_threads(int(nthreads)))
