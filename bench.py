@@ -1,0 +1,233 @@
+#!/usr/bin/env python3
+"""Throughput of Floater-Hormann evaluation on one MI355X, in node-point
+pairs per second (Gpair/s), at a stated max error against the FP64 oracle.
+
+Workload of the headline line ("sines"): n = 1001 equispaced nodes on
+[-1,1], f = sum of 8 seeded sines, 10^6 uniform points, blending degree d
+swept 0..8.  One step = for every d: the weight pass and node-table packing
+(fh_prepare) and the fused r + Lebesgue evaluation (fh_eval_prepared) of all
+10^6 points.  value = 9 * n * m pairs per step / step time.  Inputs are
+resident in HBM before timing starts.
+
+Also reported in the same JSON line:
+  roofline      the evaluation kernel (the dominant kernel), timed live with
+                HIP events on its launch stream, against the FP64 vector peak
+                (78.6 TFLOP/s) with 7 algorithmic flops per pair;
+  cpu_baseline  the FP64 oracle on the host cores, on a bounded sample;
+  max_error     parity of the timed outputs against the oracle on the sample;
+  forms         the other forms of the path on their own workloads (FP64 vs
+                FP32-split on the 4097-node, 10^7-point clustered workload).
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_1606_06508_amd import fh, inputs  # noqa: E402
+
+FP64_PEAK_TFLOPS = 78.6       # MI355X FP64 vector, published
+FLOPS_PER_PAIR_RL = 7         # sub, div, mul+add (N), add (D), add (L)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_eval_f64_sines.json")
+EVAL_SRC = os.path.join(ROOT, "paper_1606_06508_amd", "csrc", "eval_f64.hip")
+
+
+def _t(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _src_hash(path):
+    with open(path, "rb") as fh_:
+        return hashlib.sha256(fh_.read()).hexdigest()[:16]
+
+
+def measured_traffic(n_launch_pairs):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when it is missing or was taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("eval_f64_src_sha256_16") != _src_hash(EVAL_SRC):
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def run_sines(dev, steps, warmup):
+    c = inputs.sines_workload()
+    n, m, degrees = c["nodes"].size, c["points"].size, c["degrees"]
+    nodes, vals, x = _t(c["nodes"], dev), _t(c["values"], dev), _t(c["points"], dev)
+    r = torch.empty(m, dtype=torch.float64, device=dev)
+    lam = torch.empty(m, dtype=torch.float64, device=dev)
+    ws = fh.Workspace(dev, fh.workspace_size(fh.FH_OP_EVAL, n, m, 8))
+    lib = fh.load()
+    buf = ws.buf
+    stream = torch.cuda.current_stream(dev)
+    sptr = fh._stream(dev)
+    P = fh._ptr
+
+    def step(evs=None):
+        for d in degrees:
+            st = lib.fh_prepare(P(nodes), P(vals), n, d, None, fh.FH_FP64, P(buf), buf.numel(), sptr)
+            if evs is not None:
+                evs.append(torch.cuda.Event(enable_timing=True))
+                evs[-1].record(stream)
+            st |= lib.fh_eval_prepared(P(buf), buf.numel(), n, fh.FH_FP64, P(x), m, P(r), P(lam),
+                                       sptr)
+            if evs is not None:
+                evs.append(torch.cuda.Event(enable_timing=True))
+                evs[-1].record(stream)
+            if st:
+                raise fh.FhError(st, "bench step")
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = []
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(steps):
+        step(evs)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = t0.elapsed_time(t1)
+    kern_ms = [evs[i].elapsed_time(evs[i + 1]) for i in range(0, len(evs), 2)]
+    per_d = {d: float(np.mean(kern_ms[i::len(degrees)])) for i, d in enumerate(degrees)}
+    # outputs of the last timed launch (d = 8) for the parity sample
+    return {
+        "n": n, "m": m, "degrees": degrees, "total_ms": total_ms, "kernel_ms": kern_ms,
+        "per_d_ms": per_d, "r_last": r, "lam_last": lam, "case": c,
+    }
+
+
+def cpu_baseline(case, gpu_r, gpu_lam, target_s):
+    """The FP64 oracle on the host cores over a bounded sample of the same
+    workload (the first m_s points, every d), plus parity on that sample for
+    the last degree (whose GPU outputs are at hand)."""
+    from oracle import metrics, oracle
+    nodes, vals, pts = case["nodes"], case["values"], case["points"]
+    n = nodes.size
+    probe = pts[:4000]
+    t = time.perf_counter()
+    oracle.evaluate(nodes, vals, 4, probe)
+    per_point = (time.perf_counter() - t) / probe.size
+    m_s = int(min(pts.size, max(4000, target_s / (9 * per_point))))
+    sample = pts[:m_s]
+    t = time.perf_counter()
+    for d in case["degrees"]:
+        r_o, lam_o, s_o = oracle.evaluate(nodes, vals, d, sample)
+    el = time.perf_counter() - t
+    pairs = 9 * n * m_s
+    stats = metrics.parity(gpu_r[:m_s], gpu_lam[:m_s], r_o, lam_o, s_o)
+    base = {"value": pairs / el / 1e9, "unit": "Gpair/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"first {m_s} of the 10^6 points, all 9 degrees, n={n} "
+                      f"(compensated FP64, {el:.1f} s)"}
+    return base, stats
+
+
+def run_split_forms(dev, reps, with_cpu):
+    """FP64 vs FP32-split on the clustered 4097-node, 10^7-point workload
+    (eval kernel only, node table prepared once)."""
+    c = inputs.split_workload()
+    n, m = c["nodes"].size, c["points"].size
+    nodes, vals, x = _t(c["nodes"], dev), _t(c["values"], dev), _t(c["points"], dev)
+    out = {}
+    res = {}
+    for prec in ("fp64", "split"):
+        prep = fh.Prepared(nodes, vals, c["d"], precision=prec, m_hint=m)
+        r = torch.empty(m, dtype=torch.float64, device=dev)
+        lam = torch.empty(m, dtype=torch.float64, device=dev)
+        prep(x, lebesgue=True, out=r, lambda_out=lam)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            prep(x, lebesgue=True, out=r, lambda_out=lam)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[prec] = {"Gpair_s": n * m / (ms * 1e-3) / 1e9, "ms": ms}
+        res[prec] = (r, lam)
+    out["split_speedup_vs_fp64"] = out["split"]["Gpair_s"] / out["fp64"]["Gpair_s"]
+    if with_cpu:
+        from oracle import metrics, oracle
+        idx = np.random.default_rng(0).choice(m, 4000, replace=False)
+        r_o, lam_o, s_o = oracle.evaluate(c["nodes"], c["values"], c["d"], c["points"][idx])
+        for prec in ("fp64", "split"):
+            r, lam = res[prec]
+            st = metrics.parity(r.cpu().numpy()[idx], lam.cpu().numpy()[idx], r_o, lam_o, s_o)
+            out[prec]["max_error_sample4000"] = {k: v for k, v in st.items() if k.startswith("e_")}
+    out["workload"] = f"split: n={n} jittered, d={c['d']}, m={m} (10% within 1e-8 of a node)"
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the path needs no exchange between GPUs; see the design notes on sharding).",
+              file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda:0")
+    print(f"[bench] sines workload, steps={args.steps} warmup={args.warmup}", file=sys.stderr,
+          flush=True)
+    res = run_sines(dev, args.steps, args.warmup)
+    n, m = res["n"], res["m"]
+    pairs_step = len(res["degrees"]) * n * m
+    ms_step = res["total_ms"] / args.steps
+    value = pairs_step / (ms_step * 1e-3) / 1e9
+    k_ms = float(np.mean(res["kernel_ms"]))
+    achieved = FLOPS_PER_PAIR_RL * n * m / (k_ms * 1e-3) / 1e12
+    line = {
+        "metric": "node-point pairs/sec (Gpair/s) FP64 vs FP32-split vs batched at stated max error",
+        "value": value, "unit": "Gpair/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "sines: n=1001 equispaced, f=sum of 8 seeded sines, "
+                               "m=1e6 uniform points, d=0..8, r and Lebesgue function",
+                   "n": n, "m": m, "degrees": "0..8", "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": measured_traffic(n * m),
+                     "kernel": "k_eval_f64 (fused r + Lebesgue, FP64)",
+                     "kernel_ms_avg": k_ms,
+                     "kernel_Gpair_s": n * m / (k_ms * 1e-3) / 1e9,
+                     "per_d_kernel_ms": res["per_d_ms"]},
+    }
+    print(f"[bench] sines done: {value:.1f} Gpair/s, kernel {k_ms:.3f} ms", file=sys.stderr,
+          flush=True)
+    if not args.no_cpu_baseline:
+        base, stats = cpu_baseline(res["case"], res["r_last"].cpu().numpy(),
+                                   res["lam_last"].cpu().numpy(), args.cpu_seconds)
+        line["cpu_baseline"] = base
+        line["max_error"] = {"vs": "FP64 oracle on the CPU-baseline sample, d=8",
+                             **{k: v for k, v in stats.items() if k.startswith("e_")}}
+        print("[bench] cpu baseline done", file=sys.stderr, flush=True)
+    if not args.no_forms:
+        line["forms"] = {"split_workload": run_split_forms(dev, 5, not args.no_cpu_baseline)}
+        print("[bench] forms done", file=sys.stderr, flush=True)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

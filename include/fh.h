@@ -1,0 +1,197 @@
+/*
+ * fh.h -- C ABI of the MI355X (gfx950) Floater-Hormann interpolation library
+ * (libfh.so).
+ *
+ * The library evaluates linear barycentric rational interpolants of the
+ * Floater-Hormann family (M. S. Floater, K. Hormann, "Barycentric rational
+ * interpolation with no poles and high rates of approximation", Numer. Math.
+ * 107, 2007):
+ *
+ *   nodes x_0 < x_1 < ... < x_{n-1}, data f_k, blending degree 0 <= d <= n-1,
+ *   weights  w_k = sum_{i in J_k} (-1)^i prod_{j=i..i+d, j!=k} 1/(x_k - x_j),
+ *            J_k = { i : max(0, k-d) <= i <= min(k, n-1-d) },
+ *   value    r(x) = sum_k a_k(x) f_k / sum_k a_k(x),   a_k(x) = w_k / (x - x_k),
+ *   Lebesgue Lambda(x) = sum_k |a_k(x)| / |sum_k a_k(x)|,
+ *   exact hit x == x_j (binary64 equality): r = f_j bit-for-bit, Lambda = 1.
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ *  - Every array argument is a DEVICE pointer (HBM of the current HIP
+ *    device), owned by the caller.  The library never frees, retains or
+ *    reallocates caller memory (except that an fh_batch keeps the pointers
+ *    it was created with, see below).
+ *  - Arrays are dense, contiguous binary64 unless stated otherwise.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *    Every call only enqueues work on `stream` and returns; results are
+ *    valid once the stream has reached that point.
+ *  - `ws` / `ws_bytes` is a caller-owned device workspace of at least
+ *    fh_workspace_size(op, n, m, d, prec) bytes, 256-byte aligned.  Its first
+ *    256 bytes hold the device status word (sticky error bits, see
+ *    fh_device_status); they must be zero before the first use of a
+ *    workspace (allocate it zeroed).  Calls that share a workspace must be
+ *    ordered (same stream); concurrent calls need separate workspaces.
+ *  - Host-checkable errors are returned synchronously and no work is
+ *    enqueued: FH_E_ARG (n < 1, m < 0, a NULL pointer that is needed -- point
+ *    and output arrays are needed only when m > 0 -- a bad precision or op
+ *    code), FH_E_DEGREE (d < 0 or d > n-1), FH_E_WORKSPACE
+ *    (workspace missing, too small or misaligned).
+ *  - Properties of the node VALUES (strictly increasing, finite, weights
+ *    representable) are checked on the device.  A violation sets bits in the
+ *    workspace status word; the outputs are then unspecified.  The bits are
+ *    read back by fh_device_status; with the environment variable
+ *    FH_SYNC_CHECK=1 every call synchronizes and returns them as a status.
+ *  - NaN conventions (the paper's scaling algorithms propagate NaNs; the same
+ *    rule here): a NaN point gives r = Lambda = NaN; a NaN value f_k gives NaN
+ *    at every point except exact hits on other nodes; an infinite point makes
+ *    every a_k zero, hence r = 0/0 = NaN.
+ *  - Results are specified for points whose distance to every node is either
+ *    zero (a hit) or at least 2^-250 times the node span; closer points may
+ *    give non-finite results, as they do in binary64 arithmetic by the
+ *    definition itself (w_k / (x - x_k) overflows).
+ *
+ * Precision
+ *  - FH_FP64: every step in binary64.
+ *  - FH_FP32_SPLIT: weights, the differences x - x_k and the final quotient
+ *    in binary64; the reciprocals and the O(m*n) sums in binary32, with
+ *    per-tile binary32 partial sums promoted into binary64 accumulators.  The
+ *    weights are scaled by an exact power of two 2^-e (e = exponent of
+ *    max|w_k|) before rounding to binary32, which changes neither r nor
+ *    Lambda (the paper's key idea of scaling by powers of the base, exact by
+ *    its rounding fact (rndA)).
+ */
+#ifndef FH_H
+#define FH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FH_OK = 0,
+  FH_E_ARG = 1,         /* bad size, NULL pointer, bad enum value               */
+  FH_E_DEGREE = 2,      /* d < 0 or d > n-1                                      */
+  FH_E_NODES = 3,       /* (device) nodes not strictly increasing               */
+  FH_E_NONFINITE = 4,   /* (device) a node is NaN or infinite                   */
+  FH_E_RANGE = 5,       /* (device) a weight product under/overflowed          */
+  FH_E_WORKSPACE = 6,   /* workspace NULL, too small or not 256-byte aligned    */
+  FH_E_HIP = 7,         /* a HIP runtime call failed                            */
+  FH_E_UNSUPPORTED = 8  /* combination not provided by this build               */
+} fh_status;
+
+typedef enum { FH_FP64 = 0, FH_FP32_SPLIT = 1 } fh_precision;
+
+/* Operation codes for fh_workspace_size. */
+typedef enum {
+  FH_OP_WEIGHTS = 0,
+  FH_OP_EVAL = 1,       /* also fh_lebesgue */
+  FH_OP_BACKWARD = 2
+} fh_op;
+
+/* Device status bits (fh_device_status). */
+#define FH_FLAG_NODES 0x1u     /* some x_k >= x_{k+1}                  */
+#define FH_FLAG_NONFINITE 0x2u /* some x_k is NaN or infinite          */
+#define FH_FLAG_RANGE 0x4u     /* a weight product is zero, subnormal or infinite */
+
+/* Bytes of workspace an operation needs (0 on bad arguments).  `m` is the
+ * number of evaluation points; for FH_OP_WEIGHTS it is ignored. */
+size_t fh_workspace_size(int32_t op, int64_t n, int64_t m, int32_t d, int32_t prec);
+
+/* Node weights w_k of the definition above (Floater & Hormann 2007, the
+ * barycentric form and its weights).  O(n d^2) work, one thread per node.
+ * Every product is formed in ascending j, inverted with one IEEE division,
+ * signed by (-1)^i and added in ascending i without FMA contraction, so the
+ * result is reproducible bit-for-bit.
+ *   nodes  [n]  strictly increasing abscissae x_k
+ *   d           blending degree, 0 <= d <= n-1
+ *   w_out  [n]  weights (unscaled)
+ *   ws          workspace (FH_OP_WEIGHTS): status word only            */
+fh_status fh_weights(const double* nodes, int64_t n, int32_t d, double* w_out, void* ws,
+                     size_t ws_bytes, void* stream);
+
+/* r(x_p) (and optionally Lambda(x_p)) at m points: the weight pass (unless
+ * `w` is given) followed by the fused second-form sum N = sum a_k f_k,
+ * D = sum a_k, L = sum |a_k| and the quotient, with the exact-hit branch.
+ *   nodes, values [n]   x_k and f_k
+ *   x          [m]      evaluation points (any order, any values)
+ *   r_out      [m]      r(x_p)
+ *   lambda_out [m]      Lambda(x_p), or NULL to skip the Lebesgue sum
+ *   w          [n]      weights from fh_weights, or NULL to compute them here
+ *   prec                FH_FP64 or FH_FP32_SPLIT
+ *   ws                  workspace of fh_workspace_size(FH_OP_EVAL, ...)   */
+fh_status fh_eval(const double* nodes, const double* values, int64_t n, int32_t d,
+                  const double* x, int64_t m, double* r_out, double* lambda_out, const double* w,
+                  int32_t prec, void* ws, size_t ws_bytes, void* stream);
+
+/* Two-phase form of fh_eval for evaluating one interpolant on many point
+ * batches.  fh_prepare runs the weight pass (unless `w` is given) and packs
+ * the node table (x_k, w_k, w_k f_k, f_k; binary32 copies for
+ * FH_FP32_SPLIT) into `ws`; fh_eval_prepared then runs only the evaluation
+ * kernel against that table.  `n` and `prec` must repeat the fh_prepare
+ * call, and the table must not be overwritten in between.  A table prepared
+ * with values == NULL supports lambda_out only (r_out must be NULL).
+ * fh_eval(...) is exactly fh_prepare(...) followed by fh_eval_prepared(...). */
+fh_status fh_prepare(const double* nodes, const double* values, int64_t n, int32_t d,
+                     const double* w, int32_t prec, void* ws, size_t ws_bytes, void* stream);
+fh_status fh_eval_prepared(void* ws, size_t ws_bytes, int64_t n, int32_t prec, const double* x,
+                           int64_t m, double* r_out, double* lambda_out, void* stream);
+
+/* Lambda(x_p) only (the Lebesgue function of the interpolation scheme,
+ * sum_k |b_k(x)| with cardinal functions b_k = a_k / sum_j a_j).  Arguments
+ * as in fh_eval; no values are needed. */
+fh_status fh_lebesgue(const double* nodes, int64_t n, int32_t d, const double* x, int64_t m,
+                      double* lambda_out, const double* w, int32_t prec, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* Adjoint of L = sum_p grad_r[p] * r(x_p) (any output may be NULL):
+ *   grad_values [n]  dL/df_k    = sum_p g_p a_pk / D_p
+ *   grad_x      [m]  dL/dx_p    = g_p sum_k a_pk (r_p - f_k) / ((x_p - x_k) D_p)
+ *   grad_nodes  [n]  dL/dx_k    = sum_p g_p a_pk (f_k - r_p) / ((x_p - x_k) D_p)
+ *                                 + sum_j dL/dw_j dw_j/dx_k   (total derivative)
+ * At a hit x_p == x_j: dL/df_j gets g_p, dL/dx_p = g_p r'(x_j) with the node
+ * formula r'(x_j) = sum_{k!=j} (w_k/w_j)(f_k - f_j)/(x_j - x_k) (Schneider &
+ * Werner 1986), dL/dx_j gets -g_p r'(x_j), and the weights get nothing.
+ * Per-node sums over points are reduced in a fixed order (deterministic).
+ *   ws  workspace of fh_workspace_size(FH_OP_BACKWARD, n, m, d, prec)      */
+fh_status fh_eval_backward(const double* nodes, const double* values, int64_t n, int32_t d,
+                           const double* x, int64_t m, const double* grad_r, double* grad_values,
+                           double* grad_x, double* grad_nodes, int32_t prec, void* ws,
+                           size_t ws_bytes, void* stream);
+
+/* Batched evaluation of `count` independent interpolants of uneven sizes in
+ * one captured HIP graph.  Instance i owns nodes/values
+ * [node_off[i], node_off[i+1]) and points/outputs [pt_off[i], pt_off[i+1])
+ * of the concatenated (CSR) device arrays, with node_off/pt_off the running
+ * sums of n_host/m_host.
+ *   fh_batch_create  validates the host arrays (n_i >= 1, 0 <= d_i <= n_i-1,
+ *                    m_i >= 0), builds the longest-first work list, allocates
+ *                    the batch's own device memory, and captures the weight
+ *                    pass and the persistent evaluation kernel into a graph.
+ *                    The device arrays are referenced, not copied: they must
+ *                    stay allocated and in place until fh_batch_destroy.
+ *   fh_eval_batched  launches the graph on `stream` (one hipGraphLaunch).
+ *   fh_batch_destroy frees the batch (after its launches have completed). */
+typedef struct fh_batch fh_batch;
+fh_status fh_batch_create(fh_batch** out, int32_t count, const int64_t* n_host,
+                          const int32_t* d_host, const int64_t* m_host, const double* nodes_cat,
+                          const double* values_cat, const double* x_cat, double* r_cat,
+                          double* lambda_cat, int32_t prec, void* stream);
+fh_status fh_eval_batched(fh_batch* b, void* stream);
+fh_status fh_batch_destroy(fh_batch* b);
+/* Sticky device status bits of a batch (synchronizes the stream, clears). */
+fh_status fh_batch_status(fh_batch* b, void* stream, uint32_t* bits_out);
+
+/* Synchronizes `stream`, reads the workspace status word into *bits_out,
+ * clears it, and returns the status of the most severe set bit, in the
+ * order FH_E_NONFINITE, FH_E_NODES, FH_E_RANGE (FH_OK if no bit is set). */
+fh_status fh_device_status(void* ws, void* stream, uint32_t* bits_out);
+
+/* Static, human-readable name of a status code. */
+const char* fh_status_string(int32_t s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FH_H */

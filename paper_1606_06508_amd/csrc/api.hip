@@ -1,0 +1,193 @@
+// C ABI of libfh: argument validation, workspace layout, kernel selection and
+// launch.  All device work is enqueued on the caller's stream; nothing here
+// allocates except fh_batch_create.
+#include <cstdlib>
+#include <cstring>
+
+#include "fh_internal.h"
+
+using namespace fhk;
+
+namespace {
+
+bool sync_check_enabled() {
+  static const bool on = [] {
+    const char* v = std::getenv("FH_SYNC_CHECK");
+    return v && v[0] == '1';
+  }();
+  return on;
+}
+
+fh_status check_problem(const double* nodes, int64_t n, int32_t d) {
+  if (n < 1 || nodes == nullptr) return FH_E_ARG;
+  if (d < 0 || (int64_t)d > n - 1) return FH_E_DEGREE;
+  return FH_OK;
+}
+
+fh_status check_ws(void* ws, size_t ws_bytes, size_t need) {
+  if (ws == nullptr || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0)
+    return FH_E_WORKSPACE;
+  return FH_OK;
+}
+
+__global__ void k_clear_word(uint32_t* p) { *p = 0u; }
+
+fh_status status_from_bits(uint32_t bits) {
+  if (bits & FH_FLAG_NONFINITE) return FH_E_NONFINITE;
+  if (bits & FH_FLAG_NODES) return FH_E_NODES;
+  if (bits & FH_FLAG_RANGE) return FH_E_RANGE;
+  return FH_OK;
+}
+
+fh_status finish(hipError_t e, void* ws, hipStream_t s) {
+  if (e != hipSuccess) return FH_E_HIP;
+  if (sync_check_enabled()) {
+    uint32_t bits = 0;
+    return fh_device_status(ws, s, &bits);
+  }
+  return FH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fh_status_string(int32_t s) {
+  switch (s) {
+    case FH_OK: return "ok";
+    case FH_E_ARG: return "invalid argument";
+    case FH_E_DEGREE: return "degree d outside 0..n-1";
+    case FH_E_NODES: return "nodes are not strictly increasing";
+    case FH_E_NONFINITE: return "a node is not finite";
+    case FH_E_RANGE: return "a weight product is not a normal binary64 number";
+    case FH_E_WORKSPACE: return "workspace missing, too small or misaligned";
+    case FH_E_HIP: return "HIP runtime error";
+    case FH_E_UNSUPPORTED: return "unsupported in this build";
+    default: return "unknown status";
+  }
+}
+
+size_t fh_workspace_size(int32_t op, int64_t n, int64_t m, int32_t d, int32_t prec) {
+  if (n < 1 || m < 0 || d < 0 || (int64_t)d > n - 1) return 0;
+  if (prec != FH_FP64 && prec != FH_FP32_SPLIT) return 0;
+  NodeTable t;
+  switch (op) {
+    case FH_OP_WEIGHTS: return kStatusBytes;
+    case FH_OP_EVAL: return layout_tables(nullptr, n, &t);
+    default: return 0;
+  }
+}
+
+fh_status fh_weights(const double* nodes, int64_t n, int32_t d, double* w_out, void* ws,
+                     size_t ws_bytes, void* stream) {
+  fh_status st = check_problem(nodes, n, d);
+  if (st != FH_OK) return st;
+  if (w_out == nullptr) return FH_E_ARG;
+  st = check_ws(ws, ws_bytes, kStatusBytes);
+  if (st != FH_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return finish(launch_weights(nodes, n, d, w_out, static_cast<uint32_t*>(ws), s), ws, s);
+}
+
+fh_status fh_prepare(const double* nodes, const double* values, int64_t n, int32_t d,
+                     const double* w, int32_t prec, void* ws, size_t ws_bytes, void* stream) {
+  fh_status st = check_problem(nodes, n, d);
+  if (st != FH_OK) return st;
+  if (prec != FH_FP64 && prec != FH_FP32_SPLIT) return FH_E_ARG;
+  st = check_ws(ws, ws_bytes, fh_workspace_size(FH_OP_EVAL, n, 0, d, prec));
+  if (st != FH_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  NodeTable t;
+  layout_tables(ws, n, &t);
+  return finish(launch_pack(nodes, values, w, n, d, t, prec == FH_FP32_SPLIT,
+                            static_cast<uint32_t*>(ws), s),
+                ws, s);
+}
+
+fh_status fh_eval_prepared(void* ws, size_t ws_bytes, int64_t n, int32_t prec, const double* x,
+                           int64_t m, double* r_out, double* lambda_out, void* stream) {
+  if (n < 1 || m < 0 || (m > 0 && x == nullptr)) return FH_E_ARG;
+  if (m > 0 && r_out == nullptr && lambda_out == nullptr) return FH_E_ARG;
+  if (prec != FH_FP64 && prec != FH_FP32_SPLIT) return FH_E_ARG;
+  fh_status st = check_ws(ws, ws_bytes, fh_workspace_size(FH_OP_EVAL, n, m, 0, prec));
+  if (st != FH_OK) return st;
+  if (m == 0) return FH_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  NodeTable t;
+  layout_tables(ws, n, &t);
+  const EvalConfig cfg =
+      choose_eval_config(prec, n, 0, m, r_out != nullptr, lambda_out != nullptr);
+  const hipError_t e = prec == FH_FP32_SPLIT
+                           ? launch_eval_split(x, m, t, n, r_out, lambda_out, cfg, s)
+                           : launch_eval_f64(x, m, t, n, r_out, lambda_out, cfg, s);
+  return finish(e, ws, s);
+}
+
+static fh_status eval_common(const double* nodes, const double* values, int64_t n, int32_t d,
+                             const double* x, int64_t m, double* r_out, double* lambda_out,
+                             const double* w, int32_t prec, void* ws, size_t ws_bytes,
+                             void* stream) {
+  fh_status st = check_problem(nodes, n, d);
+  if (st != FH_OK) return st;
+  if (m < 0 || (m > 0 && x == nullptr)) return FH_E_ARG;
+  if (m > 0 && r_out == nullptr && lambda_out == nullptr) return FH_E_ARG;
+  if (r_out != nullptr && values == nullptr) return FH_E_ARG;
+  if (prec != FH_FP64 && prec != FH_FP32_SPLIT) return FH_E_ARG;
+  st = check_ws(ws, ws_bytes, fh_workspace_size(FH_OP_EVAL, n, m, d, prec));
+  if (st != FH_OK) return st;
+  st = fh_prepare(nodes, values, n, d, w, prec, ws, ws_bytes, stream);
+  if (st != FH_OK) return st;
+  return fh_eval_prepared(ws, ws_bytes, n, prec, x, m, r_out, lambda_out, stream);
+}
+
+fh_status fh_eval(const double* nodes, const double* values, int64_t n, int32_t d,
+                  const double* x, int64_t m, double* r_out, double* lambda_out, const double* w,
+                  int32_t prec, void* ws, size_t ws_bytes, void* stream) {
+  if (m > 0 && r_out == nullptr) return FH_E_ARG;
+  if (values == nullptr) return FH_E_ARG;
+  return eval_common(nodes, values, n, d, x, m, r_out, lambda_out, w, prec, ws, ws_bytes, stream);
+}
+
+fh_status fh_lebesgue(const double* nodes, int64_t n, int32_t d, const double* x, int64_t m,
+                      double* lambda_out, const double* w, int32_t prec, void* ws,
+                      size_t ws_bytes, void* stream) {
+  if (m > 0 && lambda_out == nullptr) return FH_E_ARG;
+  return eval_common(nodes, nullptr, n, d, x, m, nullptr, lambda_out, w, prec, ws, ws_bytes,
+                     stream);
+}
+
+fh_status fh_eval_backward(const double*, const double*, int64_t, int32_t, const double*, int64_t,
+                           const double*, double*, double*, double*, int32_t, void*, size_t,
+                           void*) {
+  return FH_E_UNSUPPORTED;
+}
+
+fh_status fh_batch_create(fh_batch** out, int32_t, const int64_t*, const int32_t*,
+                          const int64_t*, const double*, const double*, const double*, double*,
+                          double*, int32_t, void*) {
+  if (out) *out = nullptr;
+  return FH_E_UNSUPPORTED;
+}
+fh_status fh_eval_batched(fh_batch*, void*) { return FH_E_UNSUPPORTED; }
+fh_status fh_batch_destroy(fh_batch*) { return FH_OK; }
+fh_status fh_batch_status(fh_batch*, void*, uint32_t* bits_out) {
+  if (bits_out) *bits_out = 0;
+  return FH_E_UNSUPPORTED;
+}
+
+fh_status fh_device_status(void* ws, void* stream, uint32_t* bits_out) {
+  if (ws == nullptr || bits_out == nullptr) return FH_E_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (hipStreamSynchronize(s) != hipSuccess) return FH_E_HIP;
+  uint32_t bits = 0;
+  if (hipMemcpy(&bits, ws, sizeof(bits), hipMemcpyDeviceToHost) != hipSuccess) return FH_E_HIP;
+  if (bits) {
+    k_clear_word<<<1, 1, 0, s>>>(static_cast<uint32_t*>(ws));
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+      return FH_E_HIP;
+  }
+  *bits_out = bits;
+  return status_from_bits(bits);
+}
+
+}  // extern "C"

@@ -1,0 +1,62 @@
+// Internal declarations of libfh (HIP, gfx950).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "fh.h"
+
+namespace fhk {
+
+// The first kStatusBytes of every workspace: word 0 = sticky status bits,
+// word 1 = binary32 scaling exponent e of the split form (max|w| = 2^e * m,
+// 1 <= m < 2), words 2.. reserved.
+constexpr size_t kStatusBytes = 256;
+// Node tables are padded to a multiple of this many records; padding
+// records repeat the last node with zero weight, so they add nothing.
+constexpr int64_t kNodePad = 64;
+constexpr size_t kAlign = 256;
+
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+inline size_t align_up(size_t a) { return (a + kAlign - 1) / kAlign * kAlign; }
+
+// Node table of one interpolant in structure-of-arrays form (device).
+struct NodeTable {
+  double* x;      // [n_pad] x_k
+  double* w;      // [n_pad] w_k
+  double* wf;     // [n_pad] w_k * f_k
+  double* f;      // [n_pad] f_k (exact-hit branch)
+  float* sx_hi;   // [n_pad] split form: binary32 head of x_k
+  float* sx_lo;   // [n_pad] split form: binary32 tail x_k - head
+  float* sw;      // [n_pad] split form: binary32 of w_k * 2^-e
+  float* swf;     // [n_pad] split form: binary32 of w_k f_k * 2^-e
+  int64_t n_pad;
+};
+
+// Workspace layout of FH_OP_EVAL / FH_OP_BACKWARD (node tables after the
+// status block).  Returns bytes used.
+size_t layout_tables(void* ws, int64_t n, NodeTable* t);
+
+// Launch configuration of the FP64 evaluation kernel, chosen per problem by
+// the tuner (tune.hip): points per lane and threads per block.
+struct EvalConfig {
+  int points_per_lane;  // 1, 2, 4
+  int block;            // 64, 128, 256
+};
+EvalConfig choose_eval_config(int32_t prec, int64_t n, int32_t d, int64_t m, bool want_r,
+                              bool want_l);
+
+// ---- launchers (each returns the launch error, hipSuccess on success) ----
+hipError_t launch_weights(const double* nodes, int64_t n, int32_t d, double* w_out,
+                          uint32_t* status, hipStream_t s);
+hipError_t launch_pack(const double* nodes, const double* values, const double* w_in, int64_t n,
+                       int32_t d, const NodeTable& t, bool split, uint32_t* status,
+                       hipStream_t s);
+hipError_t launch_eval_f64(const double* x, int64_t m, const NodeTable& t, int64_t n, double* r,
+                           double* lam, const EvalConfig& cfg, hipStream_t s);
+hipError_t launch_eval_split(const double* x, int64_t m, const NodeTable& t, int64_t n, double* r,
+                             double* lam, const EvalConfig& cfg, hipStream_t s);
+
+}  // namespace fhk

@@ -1,0 +1,159 @@
+// Weight pass and node-table packing (gfx950).
+//
+// Weights follow the barycentric form of Floater & Hormann (2007):
+//   w_k = sum_{i in J_k} (-1)^i / prod_{j=i..i+d, j!=k} (x_k - x_j),
+//   J_k = { max(0, k-d) <= i <= min(k, n-1-d) }.
+// One thread per node, O(d^2) work each.  The products run in ascending j,
+// each term is one IEEE division, and the terms are added in ascending i
+// with FMA contraction disabled, so the weights are reproducible bit-for-bit
+// on any IEEE machine that follows the same order.
+#include "fh_internal.h"
+
+namespace fhk {
+
+// Weight of node k; ORs FH_FLAG_* into *flags.
+__device__ inline double node_weight(const double* __restrict__ x, int64_t n, int32_t d, int64_t k,
+                                     uint32_t* flags) {
+#pragma clang fp contract(off)
+  const double xk = x[k];
+  const int64_t ilo = k - d > 0 ? k - d : 0;
+  const int64_t ihi = k < n - 1 - d ? k : n - 1 - d;
+  double s = 0.0;
+  for (int64_t i = ilo; i <= ihi; ++i) {
+    double prod = 1.0;
+    for (int64_t j = i; j <= i + d; ++j)
+      if (j != k) prod = prod * (xk - x[j]);
+    // a zero, subnormal, infinite or NaN product means the weight cannot be
+    // represented accurately
+    if (!__builtin_isnormal(prod)) *flags |= FH_FLAG_RANGE;
+    double term = 1.0 / prod;
+    if (i & 1) term = -term;
+    s = s + term;
+  }
+  return s;
+}
+
+__device__ inline uint32_t node_checks(const double* __restrict__ x, int64_t n, int64_t k) {
+  uint32_t f = 0;
+  const double xk = x[k];
+  if (!__builtin_isfinite(xk)) f |= FH_FLAG_NONFINITE;
+  if (k + 1 < n && !(xk < x[k + 1])) f |= FH_FLAG_NODES;
+  return f;
+}
+
+__global__ void __launch_bounds__(256) k_weights(const double* __restrict__ x, int64_t n, int32_t d,
+                                                 double* __restrict__ w, uint32_t* status) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  uint32_t flags = node_checks(x, n, k);
+  w[k] = node_weight(x, n, d, k, &flags);
+  if (flags) atomicOr(status, flags);
+}
+
+// FP64 node table: x_k, w_k, w_k f_k (one rounding), padded with zero-weight
+// copies of the last node.  w_in (if given) replaces the weight pass;
+// values may be NULL (Lebesgue only) and then w f is stored as 0.
+__global__ void __launch_bounds__(256) k_pack(const double* __restrict__ x,
+                                              const double* __restrict__ f,
+                                              const double* __restrict__ w_in, int64_t n,
+                                              int32_t d, int64_t n_pad, double* __restrict__ tx,
+                                              double* __restrict__ tw, double* __restrict__ twf,
+                                              double* __restrict__ tf, uint32_t* status) {
+#pragma clang fp contract(off)
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_pad) return;
+  if (k >= n) {
+    tx[k] = x[n - 1];
+    tw[k] = 0.0;
+    twf[k] = 0.0;
+    tf[k] = 0.0;
+    return;
+  }
+  uint32_t flags = node_checks(x, n, k);
+  double wk = w_in ? w_in[k] : node_weight(x, n, d, k, &flags);
+  tx[k] = x[k];
+  tw[k] = wk;
+  twf[k] = f ? wk * f[k] : 0.0;
+  tf[k] = f ? f[k] : 0.0;
+  if (flags) atomicOr(status, flags);
+}
+
+// Split (binary32) node table.  Every block first reduces max|w_k| over the
+// whole table (n is small next to the evaluation; doing it per block avoids
+// a second pass and any atomics), takes its binary exponent e, and stores
+// w_k 2^-e and w_k f_k 2^-e in binary32.  Multiplying by 2^-e is exact
+// (a power of two times a normal number), so the scaled sums differ from the
+// unscaled ones only by the final binary32 rounding; the common factor
+// cancels in r and in Lambda.  x_k is stored as a binary32 head and tail.
+__global__ void __launch_bounds__(256) k_pack_split(const double* __restrict__ tx,
+                                                    const double* __restrict__ tw,
+                                                    const double* __restrict__ twf, int64_t n_pad,
+                                                    float* __restrict__ sx_hi,
+                                                    float* __restrict__ sx_lo,
+                                                    float* __restrict__ sw,
+                                                    float* __restrict__ swf, int32_t* exp_out) {
+  __shared__ double red[256];
+  double mx = 0.0;
+  for (int64_t k = threadIdx.x; k < n_pad; k += blockDim.x) mx = fmax(mx, fabs(tw[k]));
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  int e = 0;
+  frexp(red[0], &e);  // max|w| = m 2^e, 1/2 <= m < 1
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *exp_out = e;
+  if (k >= n_pad) return;
+  const double xk = tx[k];
+  const float hi = (float)xk;
+  sx_hi[k] = hi;
+  sx_lo[k] = (float)(xk - (double)hi);
+  sw[k] = (float)ldexp(tw[k], -e);
+  swf[k] = (float)ldexp(twf[k], -e);
+}
+
+size_t layout_tables(void* ws, int64_t n, NodeTable* t) {
+  const int64_t n_pad = round_up(n, kNodePad);
+  char* base = static_cast<char*>(ws);
+  size_t off = kStatusBytes;
+  auto take = [&](size_t bytes) {
+    char* p = base ? base + off : nullptr;
+    off = align_up(off + bytes);
+    return p;
+  };
+  t->n_pad = n_pad;
+  t->x = reinterpret_cast<double*>(take(sizeof(double) * n_pad));
+  t->w = reinterpret_cast<double*>(take(sizeof(double) * n_pad));
+  t->wf = reinterpret_cast<double*>(take(sizeof(double) * n_pad));
+  t->f = reinterpret_cast<double*>(take(sizeof(double) * n_pad));
+  t->sx_hi = reinterpret_cast<float*>(take(sizeof(float) * n_pad));
+  t->sx_lo = reinterpret_cast<float*>(take(sizeof(float) * n_pad));
+  t->sw = reinterpret_cast<float*>(take(sizeof(float) * n_pad));
+  t->swf = reinterpret_cast<float*>(take(sizeof(float) * n_pad));
+  return off;
+}
+
+hipError_t launch_weights(const double* nodes, int64_t n, int32_t d, double* w_out,
+                          uint32_t* status, hipStream_t s) {
+  const int64_t blocks = (n + 255) / 256;
+  k_weights<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(nodes, n, d, w_out, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(const double* nodes, const double* values, const double* w_in, int64_t n,
+                       int32_t d, const NodeTable& t, bool split, uint32_t* status,
+                       hipStream_t s) {
+  const int64_t blocks = (t.n_pad + 255) / 256;
+  k_pack<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(nodes, values, w_in, n, d, t.n_pad, t.x, t.w,
+                                                      t.wf, t.f, status);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !split) return e;
+  k_pack_split<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(
+      t.x, t.w, t.wf, t.n_pad, t.sx_hi, t.sx_lo, t.sw, t.swf,
+      reinterpret_cast<int32_t*>(status) + 1);
+  return hipGetLastError();
+}
+
+}  // namespace fhk

@@ -1,0 +1,224 @@
+"""Thin ctypes binding of libfh.so (C ABI in include/fh.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libfh.so.  Tensors must be float64, contiguous and on a ROCm
+device; calls are enqueued on torch's current stream of that device.  If the
+library has not been built, every call raises FhError -- there is no CPU
+fallback.
+"""
+import ctypes
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfh.so")
+
+FH_OK, FH_E_ARG, FH_E_DEGREE, FH_E_NODES, FH_E_NONFINITE, FH_E_RANGE = 0, 1, 2, 3, 4, 5
+FH_E_WORKSPACE, FH_E_HIP, FH_E_UNSUPPORTED = 6, 7, 8
+FH_FP64, FH_FP32_SPLIT = 0, 1
+FH_OP_WEIGHTS, FH_OP_EVAL, FH_OP_BACKWARD = 0, 1, 2
+PRECISIONS = {"fp64": FH_FP64, "split": FH_FP32_SPLIT, "fp32_split": FH_FP32_SPLIT}
+
+_lib = None
+_lock = threading.Lock()
+
+
+class FhError(RuntimeError):
+    def __init__(self, code, where=""):
+        msg = status_string(code) if _lib is not None else f"status {code}"
+        super().__init__(f"{where}: {msg} (status {code})" if where else msg)
+        self.code = code
+
+
+def load():
+    """Opens libfh.so once; raises FhError if it is missing."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise FhError(FH_E_UNSUPPORTED,
+                          f"{LIB_PATH} is not built (python -m paper_1606_06508_amd.build)")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+        sig = {
+            "fh_workspace_size": ([i32, i64, i64, i32, i32], sz),
+            "fh_weights": ([vp, i64, i32, vp, vp, sz, vp], ctypes.c_int),
+            "fh_eval": ([vp, vp, i64, i32, vp, i64, vp, vp, vp, i32, vp, sz, vp], ctypes.c_int),
+            "fh_lebesgue": ([vp, i64, i32, vp, i64, vp, vp, i32, vp, sz, vp], ctypes.c_int),
+            "fh_prepare": ([vp, vp, i64, i32, vp, i32, vp, sz, vp], ctypes.c_int),
+            "fh_eval_prepared": ([vp, sz, i64, i32, vp, i64, vp, vp, vp], ctypes.c_int),
+            "fh_eval_backward": ([vp, vp, i64, i32, vp, i64, vp, vp, vp, vp, i32, vp, sz, vp],
+                                 ctypes.c_int),
+            "fh_batch_create": ([ctypes.POINTER(vp), i32, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp],
+                                ctypes.c_int),
+            "fh_eval_batched": ([vp, vp], ctypes.c_int),
+            "fh_batch_destroy": ([vp], ctypes.c_int),
+            "fh_batch_status": ([vp, vp, ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
+            "fh_device_status": ([vp, vp, ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
+            "fh_status_string": ([i32], ctypes.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+        return lib
+
+
+def status_string(code: int) -> str:
+    return load().fh_status_string(int(code)).decode()
+
+
+def _check(code, where):
+    if code != FH_OK:
+        raise FhError(code, where)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _f64(t, name):
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError(f"{name} must be a float64 tensor on a ROCm device")
+    if not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous")
+    return t
+
+
+def _stream(dev):
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _prec(precision):
+    if isinstance(precision, int):
+        return precision
+    try:
+        return PRECISIONS[precision]
+    except KeyError:
+        raise ValueError(f"precision must be one of {sorted(PRECISIONS)}") from None
+
+
+def workspace_size(op, n, m, d, precision="fp64"):
+    return int(load().fh_workspace_size(int(op), int(n), int(m), int(d), _prec(precision)))
+
+
+class Workspace:
+    """A zeroed, 256-byte aligned device workspace that grows on demand.
+
+    The first 256 bytes hold the device status word, so the buffer is
+    zero-filled when (re)allocated.  Calls that share a Workspace must be
+    ordered on one stream."""
+
+    def __init__(self, device=None, nbytes=0):
+        self.device = torch.device(device) if device is not None else torch.device("cuda")
+        self.buf = None
+        if nbytes:
+            self.reserve(nbytes)
+
+    def reserve(self, nbytes):
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = torch.zeros(max(int(nbytes), 256), dtype=torch.uint8, device=self.device)
+            assert self.buf.data_ptr() % 256 == 0
+        return self.buf
+
+    def status(self):
+        """Synchronizes, returns and clears the sticky device status bits."""
+        bits = ctypes.c_uint32(0)
+        code = load().fh_device_status(_ptr(self.buf), _stream(self.device), ctypes.byref(bits))
+        return code, bits.value
+
+
+_default_ws = {}
+
+
+def default_workspace(device) -> Workspace:
+    key = torch.device(device)
+    if key not in _default_ws:
+        _default_ws[key] = Workspace(key)
+    return _default_ws[key]
+
+
+def weights(nodes, d, *, out=None, ws=None):
+    """Floater-Hormann weights w_k (float64 tensor [n]) on nodes' device."""
+    lib = load()
+    x = _f64(nodes, "nodes")
+    n = x.numel()
+    w = torch.empty_like(x) if out is None else _f64(out, "out")
+    ws = ws or default_workspace(x.device)
+    buf = ws.reserve(workspace_size(FH_OP_WEIGHTS, n, 0, d))
+    _check(lib.fh_weights(_ptr(x), n, int(d), _ptr(w), _ptr(buf), buf.numel(), _stream(x.device)),
+           "fh_weights")
+    return w
+
+
+def evaluate(nodes, values, d, x, *, lebesgue=False, weights=None, precision="fp64", out=None,
+             lambda_out=None, ws=None):
+    """r(x) (and Lambda(x) if lebesgue=True) of the FH interpolant."""
+    lib = load()
+    xn, f, t = _f64(nodes, "nodes"), _f64(values, "values"), _f64(x, "x")
+    n, m = xn.numel(), t.numel()
+    if f.numel() != n:
+        raise ValueError("values must have as many entries as nodes")
+    if weights is not None and _f64(weights, "weights").numel() != n:
+        raise ValueError("weights must have as many entries as nodes")
+    prec = _prec(precision)
+    r = torch.empty_like(t) if out is None else _f64(out, "out")
+    lam = None
+    if lebesgue:
+        lam = torch.empty_like(t) if lambda_out is None else _f64(lambda_out, "lambda_out")
+    ws = ws or default_workspace(t.device)
+    buf = ws.reserve(workspace_size(FH_OP_EVAL, n, m, d, prec))
+    _check(lib.fh_eval(_ptr(xn), _ptr(f), n, int(d), _ptr(t), m, _ptr(r), _ptr(lam), _ptr(weights),
+                       prec, _ptr(buf), buf.numel(), _stream(t.device)), "fh_eval")
+    return (r, lam) if lebesgue else r
+
+
+def lebesgue(nodes, d, x, *, weights=None, precision="fp64", out=None, ws=None):
+    """Lebesgue function Lambda(x) of the FH scheme."""
+    lib = load()
+    xn, t = _f64(nodes, "nodes"), _f64(x, "x")
+    n, m = xn.numel(), t.numel()
+    prec = _prec(precision)
+    lam = torch.empty_like(t) if out is None else _f64(out, "out")
+    ws = ws or default_workspace(t.device)
+    buf = ws.reserve(workspace_size(FH_OP_EVAL, n, m, d, prec))
+    _check(lib.fh_lebesgue(_ptr(xn), n, int(d), _ptr(t), m, _ptr(lam), _ptr(weights), prec,
+                           _ptr(buf), buf.numel(), _stream(t.device)), "fh_lebesgue")
+    return lam
+
+
+class Prepared:
+    """An interpolant whose node table lives in its own workspace, for
+    evaluation on many point batches (fh_prepare + fh_eval_prepared)."""
+
+    def __init__(self, nodes, values, d, *, weights=None, precision="fp64", m_hint=0):
+        lib = load()
+        self.nodes = _f64(nodes, "nodes")
+        self.values = None if values is None else _f64(values, "values")
+        self.n, self.d, self.prec = self.nodes.numel(), int(d), _prec(precision)
+        self.device = self.nodes.device
+        self.ws = Workspace(self.device, workspace_size(FH_OP_EVAL, self.n, m_hint, d, self.prec))
+        buf = self.ws.buf
+        _check(lib.fh_prepare(_ptr(self.nodes), _ptr(self.values), self.n, self.d, _ptr(weights),
+                              self.prec, _ptr(buf), buf.numel(), _stream(self.device)),
+               "fh_prepare")
+
+    def __call__(self, x, *, want_r=True, lebesgue=False, out=None, lambda_out=None):
+        lib = load()
+        t = _f64(x, "x")
+        if want_r and self.values is None:
+            raise ValueError("prepared without values: only the Lebesgue function is available")
+        r = (torch.empty_like(t) if out is None else _f64(out, "out")) if want_r else None
+        lam = None
+        if lebesgue:
+            lam = torch.empty_like(t) if lambda_out is None else _f64(lambda_out, "lambda_out")
+        buf = self.ws.buf
+        _check(lib.fh_eval_prepared(_ptr(buf), buf.numel(), self.n, self.prec, _ptr(t), t.numel(),
+                                    _ptr(r), _ptr(lam), _stream(t.device)), "fh_eval_prepared")
+        if want_r and lebesgue:
+            return r, lam
+        return r if want_r else lam

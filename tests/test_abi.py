@@ -1,0 +1,91 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+declared in include/fh.h, and rejects bad host-side arguments with the
+documented status before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1606_06508_amd import fh
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fh.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fh_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_five_entry_points():
+    names = _declared()
+    for required in ("fh_weights", "fh_eval", "fh_lebesgue", "fh_eval_batched", "fh_eval_backward"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = fh.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings():
+    for code in range(9):
+        s = fh.status_string(code)
+        assert s and s != "unknown status"
+    assert fh.status_string(99) == "unknown status"
+
+
+def test_workspace_sizes():
+    lib = fh.load()
+    assert lib.fh_workspace_size(fh.FH_OP_WEIGHTS, 10, 0, 2, 0) == 256
+    a = lib.fh_workspace_size(fh.FH_OP_EVAL, 1001, 10 ** 6, 3, 0)
+    b = lib.fh_workspace_size(fh.FH_OP_EVAL, 4097, 10 ** 6, 3, 1)
+    assert 256 < a < b
+    assert a % 256 == 0
+    # invalid problems report 0
+    assert lib.fh_workspace_size(fh.FH_OP_EVAL, 0, 10, 0, 0) == 0
+    assert lib.fh_workspace_size(fh.FH_OP_EVAL, 5, 10, 5, 0) == 0
+    assert lib.fh_workspace_size(fh.FH_OP_EVAL, 5, -1, 1, 0) == 0
+    assert lib.fh_workspace_size(fh.FH_OP_EVAL, 5, 10, 1, 7) == 0
+
+
+# Fake, never-dereferenced device addresses: every call below must return
+# before any kernel launch or HIP call.
+P = ctypes.c_void_p(0x100000)
+P2 = ctypes.c_void_p(0x200000)
+
+
+@pytest.mark.parametrize("args,code", [
+    (dict(nodes=None), fh.FH_E_ARG),
+    (dict(n=0), fh.FH_E_ARG),
+    (dict(d=-1), fh.FH_E_DEGREE),
+    (dict(d=10), fh.FH_E_DEGREE),
+    (dict(m=-1), fh.FH_E_ARG),
+    (dict(x=None), fh.FH_E_ARG),
+    (dict(r=None), fh.FH_E_ARG),
+    (dict(values=None), fh.FH_E_ARG),
+    (dict(prec=5), fh.FH_E_ARG),
+    (dict(ws=None), fh.FH_E_WORKSPACE),
+    (dict(ws_bytes=100), fh.FH_E_WORKSPACE),
+    (dict(ws=ctypes.c_void_p(0x100008)), fh.FH_E_WORKSPACE),
+])
+def test_eval_host_validation(args, code):
+    lib = fh.load()
+    a = dict(nodes=P, values=P, n=10, d=3, x=P, m=100, r=P2, lam=None, w=None, prec=0, ws=P,
+             ws_bytes=1 << 30, stream=None)
+    a.update(args)
+    got = lib.fh_eval(a["nodes"], a["values"], a["n"], a["d"], a["x"], a["m"], a["r"], a["lam"],
+                      a["w"], a["prec"], a["ws"], a["ws_bytes"], a["stream"])
+    assert got == code
+
+
+def test_weights_and_lebesgue_host_validation():
+    lib = fh.load()
+    assert lib.fh_weights(P, 5, 5, P2, P, 256, None) == fh.FH_E_DEGREE
+    assert lib.fh_weights(P, 5, 1, None, P, 256, None) == fh.FH_E_ARG
+    assert lib.fh_weights(P, 5, 1, P2, None, 256, None) == fh.FH_E_WORKSPACE
+    assert lib.fh_lebesgue(P, 5, 1, P, 10, None, None, 0, P, 1 << 20, None) == fh.FH_E_ARG
+    assert lib.fh_lebesgue(P, 5, 7, P, 10, P2, None, 0, P, 1 << 20, None) == fh.FH_E_DEGREE
