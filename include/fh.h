@@ -183,6 +183,26 @@ fh_status fh_batch_destroy(fh_batch* b);
 /* Sticky device status bits of a batch (synchronizes the stream, clears). */
 fh_status fh_batch_status(fh_batch* b, void* stream, uint32_t* bits_out);
 
+/* Kernel-variant selection (the autotuner's interface).  Each evaluation
+ * kernel exists in several variants: points per lane, node group size of
+ * the shared reciprocal, and node split across the waves of a block.  The
+ * variant for a call is looked up by (prec, ceil(log2 of n rounded up to 64),
+ * ceil(log2 m)) in a per-process table; untuned shapes use a default chosen
+ * from the number of waves.  All variants compute the same quantities to the
+ * same error bound; they differ in speed and in summation order.
+ *   fh_variant_count / fh_variant_shape  enumerate the variants of `prec`;
+ *   fh_tune_set    records variant `id` for the shape bucket of (n, m)
+ *                  (id = -1 removes the entry);
+ *   fh_tune_force  pins variant `id` for every shape (-1 releases it);
+ *   fh_tune_get    the variant a call with (n, m) would use now.
+ * The table is process-wide and guarded by a mutex. */
+int32_t fh_variant_count(int32_t prec);
+fh_status fh_variant_shape(int32_t prec, int32_t id, int32_t* points_per_lane, int32_t* group,
+                           int32_t* node_split);
+fh_status fh_tune_set(int32_t prec, int64_t n, int64_t m, int32_t id);
+fh_status fh_tune_force(int32_t prec, int32_t id);
+int32_t fh_tune_get(int32_t prec, int64_t n, int64_t m);
+
 /* Synchronizes `stream`, reads the workspace status word into *bits_out,
  * clears it, and returns the status of the most severe set bit, in the
  * order FH_E_NONFINITE, FH_E_NODES, FH_E_RANGE (FH_OK if no bit is set). */

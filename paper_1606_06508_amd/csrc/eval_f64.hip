@@ -5,28 +5,32 @@
 // then r = N / D and Lambda = L / |D| (Floater & Hormann 2007, barycentric
 // form; Lambda is the Lebesgue function sum_k |a_k| / |sum_k a_k|).
 //
-// Mapping: each lane owns P points (strided by the block size so that the
-// point loads and result stores are coalesced); all lanes of a wave walk the
-// node table in the same order, so node records are wave-uniform and arrive
-// through scalar loads as SGPR operands of the vector instructions.
+// Mapping.  A block has S waves.  All S waves own the same 64*P points (each
+// lane P of them, strided by 64 so loads and stores coalesce); wave s walks
+// the s-th of S equal slices of the node table, and the S partial sums
+// (N, D, L) are added through LDS in wave order at the end, so the result
+// does not depend on timing.  S > 1 multiplies the number of waves for a
+// given point count (small point sets would otherwise leave SIMDs idle);
+// P > 1 gives each wave independent chains to hide latency.  Node records
+// are wave-uniform: they arrive through scalar loads as SGPR operands.
 //
-// Reciprocals: a division costs far more than a multiply (the paper's
+// Reciprocals.  A division costs far more than a multiply (the paper's
 // premise for preferring scaling to quotients).  On gfx950 v_rcp_f64 is a
 // quarter-rate estimate with about 25 correct bits.  Nodes are taken in
-// groups of four and their reciprocals are formed from one reciprocal of the
-// product (simultaneous inversion):
-//   q01 = d0 d1, q23 = d2 d3, q = q01 q23, y ~ 1/q (rcp + one Newton step),
-//   1/d0 = y q23 d1, 1/d1 = y q23 d0, 1/d2 = y q01 d3, 1/d3 = y q01 d2.
-// Each t then carries a relative error of a few units in the last place,
-// well inside the tolerance; the cost per pair drops from ~10 to ~7.75
-// issue slots.
+// groups of G (4 or 8) and their reciprocals come from one reciprocal of the
+// group product (simultaneous inversion): with a product tree
+// q_ab = d_a d_b, ..., Q = product of all, y ~ 1/Q (estimate plus one
+// Newton step), each 1/d_k is y times the product of the other deltas, read
+// off the same tree.  Cost per pair ~ 1 sub + 3 mul + 3 fma + (rcp + 3)/G
+// issue slots instead of ~10 with a refined reciprocal per pair; each t
+// keeps a relative error of a few units in the last place.
 //
-// Hits and range: q is zero exactly when some delta is zero (an exact hit),
-// NaN for a NaN point, and infinite or subnormal only for extreme
-// coordinates.  One v_cmp_class per group flags such lanes; after the node
-// loop a flagged lane recomputes its point with one IEEE division per pair
-// and the exact-hit branch (r = f_j bit-for-bit, Lambda = 1).  Unflagged
-// lanes never branch inside the loop.
+// Hits and range.  Q is zero exactly when some delta is zero (an exact hit),
+// NaN for a NaN point, infinite or subnormal only for extreme coordinates.
+// One v_cmp_class per group flags such lanes; after the node loop a flagged
+// lane recomputes its point with one IEEE division per pair and the
+// exact-hit branch (r = f_j bit-for-bit, Lambda = 1).  Unflagged lanes never
+// branch inside the loop.
 #include "fh_internal.h"
 
 namespace fhk {
@@ -41,6 +45,43 @@ __device__ __forceinline__ double rcp_refined(double q) {
   const double y = __builtin_amdgcn_rcp(q);
   const double e = __builtin_fma(-q, y, 1.0);
   return __builtin_fma(y, e, y);
+}
+
+// Reciprocals of G deltas via one reciprocal of their product.  Returns true
+// if the product is not a normal number (the lane must be recomputed).
+template <int G>
+__device__ __forceinline__ bool group_reciprocals(const double (&d)[G], double (&t)[G]);
+
+template <>
+__device__ __forceinline__ bool group_reciprocals<4>(const double (&d)[4], double (&t)[4]) {
+  const double q01 = d[0] * d[1], q23 = d[2] * d[3];
+  const double q = q01 * q23;
+  const double y = rcp_refined(q);
+  const double y01 = y * q23, y23 = y * q01;
+  t[0] = y01 * d[1];
+  t[1] = y01 * d[0];
+  t[2] = y23 * d[3];
+  t[3] = y23 * d[2];
+  return not_normal(q);
+}
+
+template <>
+__device__ __forceinline__ bool group_reciprocals<8>(const double (&d)[8], double (&t)[8]) {
+  const double q01 = d[0] * d[1], q23 = d[2] * d[3], q45 = d[4] * d[5], q67 = d[6] * d[7];
+  const double q03 = q01 * q23, q47 = q45 * q67;
+  const double q = q03 * q47;
+  const double y = rcp_refined(q);
+  const double y03 = y * q47, y47 = y * q03;
+  const double y01 = y03 * q23, y23 = y03 * q01, y45 = y47 * q67, y67 = y47 * q45;
+  t[0] = y01 * d[1];
+  t[1] = y01 * d[0];
+  t[2] = y23 * d[3];
+  t[3] = y23 * d[2];
+  t[4] = y45 * d[5];
+  t[5] = y45 * d[4];
+  t[6] = y67 * d[7];
+  t[7] = y67 * d[6];
+  return not_normal(q);
 }
 
 // Exact per-pair evaluation of one point (flagged lanes only).
@@ -66,68 +107,84 @@ __device__ __noinline__ void eval_point_exact(double t, const double* __restrict
   *l_out = A / fabs(D);
 }
 
-template <int P, bool R, bool L>
-__global__ void __launch_bounds__(256)
+template <int P, int G, int S, bool R, bool L>
+__global__ void __launch_bounds__(64 * S)
     k_eval_f64(const double* __restrict__ x, int64_t m, const double* __restrict__ tx,
                const double* __restrict__ tw, const double* __restrict__ twf, int64_t n_pad,
                const double* __restrict__ f, int64_t n, double* __restrict__ r,
                double* __restrict__ lam) {
-  const int64_t stride = blockDim.x;
-  const int64_t base = (int64_t)blockIdx.x * stride * P + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  // wave index, made provably wave-uniform so node loads stay scalar
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t base = (int64_t)blockIdx.x * 64 * P + lane;
   double xp[P], N[P], D[P], A[P];
   bool bad[P];
 #pragma unroll
   for (int j = 0; j < P; ++j) {
-    const int64_t idx = base + j * stride;
+    const int64_t idx = base + j * 64;
     xp[j] = x[idx < m ? idx : m - 1];
     N[j] = 0.0;
     D[j] = 0.0;
     A[j] = 0.0;
     bad[j] = false;
   }
+  // node slice of this wave (n_pad is a multiple of 64, hence of S * G)
+  const int64_t slice = n_pad / S;
+  const int64_t k_begin = wave * slice, k_end = k_begin + slice;
 
-#pragma unroll 2
-  for (int64_t k = 0; k < n_pad; k += 4) {
-    const double x0 = tx[k], x1 = tx[k + 1], x2 = tx[k + 2], x3 = tx[k + 3];
-    const double w0 = tw[k], w1 = tw[k + 1], w2 = tw[k + 2], w3 = tw[k + 3];
-    double v0 = 0, v1 = 0, v2 = 0, v3 = 0;
-    if (R) {
-      v0 = twf[k];
-      v1 = twf[k + 1];
-      v2 = twf[k + 2];
-      v3 = twf[k + 3];
+  for (int64_t k = k_begin; k < k_end; k += G) {
+    double xk[G], wk[G], vk[G];
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      xk[i] = tx[k + i];
+      wk[i] = tw[k + i];
+      vk[i] = R ? twf[k + i] : 0.0;
     }
 #pragma unroll
     for (int j = 0; j < P; ++j) {
-      const double d0 = xp[j] - x0, d1 = xp[j] - x1, d2 = xp[j] - x2, d3 = xp[j] - x3;
-      const double q01 = d0 * d1, q23 = d2 * d3;
-      const double q = q01 * q23;
-      bad[j] |= not_normal(q);
-      const double y = rcp_refined(q);
-      const double y01 = y * q23, y23 = y * q01;
-      const double t0 = y01 * d1, t1 = y01 * d0, t2 = y23 * d3, t3 = y23 * d2;
-      D[j] = __builtin_fma(w0, t0, D[j]);
-      D[j] = __builtin_fma(w1, t1, D[j]);
-      D[j] = __builtin_fma(w2, t2, D[j]);
-      D[j] = __builtin_fma(w3, t3, D[j]);
-      if (R) {
-        N[j] = __builtin_fma(v0, t0, N[j]);
-        N[j] = __builtin_fma(v1, t1, N[j]);
-        N[j] = __builtin_fma(v2, t2, N[j]);
-        N[j] = __builtin_fma(v3, t3, N[j]);
+      double dl[G], t[G];
+#pragma unroll
+      for (int i = 0; i < G; ++i) dl[i] = xp[j] - xk[i];
+      bad[j] |= group_reciprocals<G>(dl, t);
+#pragma unroll
+      for (int i = 0; i < G; ++i) {
+        D[j] = __builtin_fma(wk[i], t[i], D[j]);
+        if (R) N[j] = __builtin_fma(vk[i], t[i], N[j]);
+        if (L) A[j] = __builtin_fma(fabs(wk[i]), fabs(t[i]), A[j]);
       }
-      if (L) {
-        A[j] = __builtin_fma(fabs(w0), fabs(t0), A[j]);
-        A[j] = __builtin_fma(fabs(w1), fabs(t1), A[j]);
-        A[j] = __builtin_fma(fabs(w2), fabs(t2), A[j]);
-        A[j] = __builtin_fma(fabs(w3), fabs(t3), A[j]);
+    }
+  }
+
+  if constexpr (S > 1) {
+    // fixed-order reduction of the S partial sums through LDS
+    __shared__ double red[S - 1][3][64 * P];
+    __shared__ int redbad[S - 1][64 * P];
+    if (wave > 0) {
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        red[wave - 1][0][j * 64 + lane] = N[j];
+        red[wave - 1][1][j * 64 + lane] = D[j];
+        red[wave - 1][2][j * 64 + lane] = A[j];
+        redbad[wave - 1][j * 64 + lane] = bad[j];
+      }
+    }
+    __syncthreads();
+    if (wave > 0) return;
+#pragma unroll
+    for (int s = 0; s < S - 1; ++s) {
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        N[j] += red[s][0][j * 64 + lane];
+        D[j] += red[s][1][j * 64 + lane];
+        A[j] += red[s][2][j * 64 + lane];
+        bad[j] |= redbad[s][j * 64 + lane] != 0;
       }
     }
   }
 
 #pragma unroll
   for (int j = 0; j < P; ++j) {
-    const int64_t idx = base + j * stride;
+    const int64_t idx = base + j * 64;
     if (idx >= m) continue;
     double rv, lv;
     if (bad[j]) {
@@ -141,30 +198,58 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-template <int P>
-static hipError_t launch_p(const double* x, int64_t m, const NodeTable& t, int64_t n, double* r,
-                           double* lam, int block, hipStream_t s) {
-  const int64_t per = (int64_t)block * P;
-  const dim3 grid((unsigned)((m + per - 1) / per));
+template <int P, int G, int S>
+static hipError_t launch_v(const double* x, int64_t m, const NodeTable& t, int64_t n, double* r,
+                           double* lam, hipStream_t s) {
+  const int64_t per = 64LL * P;
+  const dim3 grid((unsigned)((m + per - 1) / per)), block(64 * S);
   if (r && lam)
-    k_eval_f64<P, true, true><<<grid, block, 0, s>>>(x, m, t.x, t.w, t.wf, t.n_pad, t.f, n, r,
-                                                     lam);
+    k_eval_f64<P, G, S, true, true><<<grid, block, 0, s>>>(x, m, t.x, t.w, t.wf, t.n_pad, t.f, n,
+                                                           r, lam);
   else if (r)
-    k_eval_f64<P, true, false><<<grid, block, 0, s>>>(x, m, t.x, t.w, t.wf, t.n_pad, t.f, n, r,
-                                                      lam);
+    k_eval_f64<P, G, S, true, false><<<grid, block, 0, s>>>(x, m, t.x, t.w, t.wf, t.n_pad, t.f, n,
+                                                            r, lam);
   else
-    k_eval_f64<P, false, true><<<grid, block, 0, s>>>(x, m, t.x, t.w, t.wf, t.n_pad, t.f, n, r,
-                                                      lam);
+    k_eval_f64<P, G, S, false, true><<<grid, block, 0, s>>>(x, m, t.x, t.w, t.wf, t.n_pad, t.f, n,
+                                                            r, lam);
   return hipGetLastError();
+}
+
+// Variant table: id -> (points per lane P, group size G, node split S).
+#define FH_F64_VARIANTS(X)                                                                    \
+  X(0, 1, 4, 1) X(1, 2, 4, 1) X(2, 4, 4, 1) X(3, 1, 8, 1) X(4, 2, 8, 1) X(5, 4, 8, 1)       \
+  X(6, 1, 4, 4) X(7, 2, 4, 4) X(8, 4, 4, 4) X(9, 1, 8, 4) X(10, 2, 8, 4) X(11, 4, 8, 4)     \
+  X(12, 1, 8, 2) X(13, 2, 8, 2) X(14, 4, 8, 2)
+
+int f64_variant_count() {
+#define FH_COUNT(id, p, g, s) +1
+  return 0 FH_F64_VARIANTS(FH_COUNT);
+#undef FH_COUNT
+}
+
+void f64_variant_shape(int id, int* p, int* g, int* s) {
+  switch (id) {
+#define FH_SHAPE(vid, vp, vg, vs) \
+  case vid:                       \
+    *p = vp;                      \
+    *g = vg;                      \
+    *s = vs;                      \
+    return;
+    FH_F64_VARIANTS(FH_SHAPE)
+#undef FH_SHAPE
+    default: *p = *g = *s = 0;
+  }
 }
 
 hipError_t launch_eval_f64(const double* x, int64_t m, const NodeTable& t, int64_t n, double* r,
                            double* lam, const EvalConfig& cfg, hipStream_t s) {
   if (m == 0) return hipSuccess;
-  switch (cfg.points_per_lane) {
-    case 1: return launch_p<1>(x, m, t, n, r, lam, cfg.block, s);
-    case 2: return launch_p<2>(x, m, t, n, r, lam, cfg.block, s);
-    default: return launch_p<4>(x, m, t, n, r, lam, cfg.block, s);
+  switch (cfg.variant) {
+#define FH_CASE(vid, vp, vg, vs) \
+  case vid: return launch_v<vp, vg, vs>(x, m, t, n, r, lam, s);
+    FH_F64_VARIANTS(FH_CASE)
+#undef FH_CASE
+    default: return hipErrorInvalidValue;
   }
 }
 

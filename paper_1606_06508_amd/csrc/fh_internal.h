@@ -28,10 +28,8 @@ struct NodeTable {
   double* w;      // [n_pad] w_k
   double* wf;     // [n_pad] w_k * f_k
   double* f;      // [n_pad] f_k (exact-hit branch)
-  float* sx_hi;   // [n_pad] split form: binary32 head of x_k
-  float* sx_lo;   // [n_pad] split form: binary32 tail x_k - head
-  float* sw;      // [n_pad] split form: binary32 of w_k * 2^-e
-  float* swf;     // [n_pad] split form: binary32 of w_k f_k * 2^-e
+  float4* s;      // [n_pad] split form: {binary32 head of x_k, binary32 tail
+                  // x_k - head, binary32 of w_k 2^-e, binary32 of w_k f_k 2^-e}
   int64_t n_pad;
 };
 
@@ -39,14 +37,18 @@ struct NodeTable {
 // status block).  Returns bytes used.
 size_t layout_tables(void* ws, int64_t n, NodeTable* t);
 
-// Launch configuration of the FP64 evaluation kernel, chosen per problem by
-// the tuner (tune.hip): points per lane and threads per block.
+// Launch configuration of an evaluation kernel: an index into the kernel's
+// variant table (points per lane, node group, node split), chosen per
+// problem shape by the tuner (tune.hip).
 struct EvalConfig {
-  int points_per_lane;  // 1, 2, 4
-  int block;            // 64, 128, 256
+  int variant;
 };
 EvalConfig choose_eval_config(int32_t prec, int64_t n, int32_t d, int64_t m, bool want_r,
                               bool want_l);
+int f64_variant_count();
+void f64_variant_shape(int id, int* p, int* g, int* s);
+int split_variant_count();
+void split_variant_shape(int id, int* p, int* g, int* s);
 
 // ---- launchers (each returns the launch error, hipSuccess on success) ----
 hipError_t launch_weights(const double* nodes, int64_t n, int32_t d, double* w_out,

@@ -88,10 +88,7 @@ __global__ void __launch_bounds__(256) k_pack(const double* __restrict__ x,
 __global__ void __launch_bounds__(256) k_pack_split(const double* __restrict__ tx,
                                                     const double* __restrict__ tw,
                                                     const double* __restrict__ twf, int64_t n_pad,
-                                                    float* __restrict__ sx_hi,
-                                                    float* __restrict__ sx_lo,
-                                                    float* __restrict__ sw,
-                                                    float* __restrict__ swf, int32_t* exp_out) {
+                                                    float4* __restrict__ s4, int32_t* exp_out) {
   __shared__ double red[256];
   double mx = 0.0;
   for (int64_t k = threadIdx.x; k < n_pad; k += blockDim.x) mx = fmax(mx, fabs(tw[k]));
@@ -108,10 +105,8 @@ __global__ void __launch_bounds__(256) k_pack_split(const double* __restrict__ t
   if (k >= n_pad) return;
   const double xk = tx[k];
   const float hi = (float)xk;
-  sx_hi[k] = hi;
-  sx_lo[k] = (float)(xk - (double)hi);
-  sw[k] = (float)ldexp(tw[k], -e);
-  swf[k] = (float)ldexp(twf[k], -e);
+  s4[k] = make_float4(hi, (float)(xk - (double)hi), (float)ldexp(tw[k], -e),
+                      (float)ldexp(twf[k], -e));
 }
 
 size_t layout_tables(void* ws, int64_t n, NodeTable* t) {
@@ -128,10 +123,7 @@ size_t layout_tables(void* ws, int64_t n, NodeTable* t) {
   t->w = reinterpret_cast<double*>(take(sizeof(double) * n_pad));
   t->wf = reinterpret_cast<double*>(take(sizeof(double) * n_pad));
   t->f = reinterpret_cast<double*>(take(sizeof(double) * n_pad));
-  t->sx_hi = reinterpret_cast<float*>(take(sizeof(float) * n_pad));
-  t->sx_lo = reinterpret_cast<float*>(take(sizeof(float) * n_pad));
-  t->sw = reinterpret_cast<float*>(take(sizeof(float) * n_pad));
-  t->swf = reinterpret_cast<float*>(take(sizeof(float) * n_pad));
+  t->s = reinterpret_cast<float4*>(take(sizeof(float4) * n_pad));
   return off;
 }
 
@@ -151,8 +143,7 @@ hipError_t launch_pack(const double* nodes, const double* values, const double* 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !split) return e;
   k_pack_split<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(
-      t.x, t.w, t.wf, t.n_pad, t.sx_hi, t.sx_lo, t.sw, t.swf,
-      reinterpret_cast<int32_t*>(status) + 1);
+      t.x, t.w, t.wf, t.n_pad, t.s, reinterpret_cast<int32_t*>(status) + 1);
   return hipGetLastError();
 }
 

@@ -59,6 +59,12 @@ def load():
             "fh_batch_status": ([vp, vp, ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
             "fh_device_status": ([vp, vp, ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
             "fh_status_string": ([i32], ctypes.c_char_p),
+            "fh_variant_count": ([i32], i32),
+            "fh_variant_shape": ([i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                  ctypes.POINTER(i32)], ctypes.c_int),
+            "fh_tune_set": ([i32, i64, i64, i32], ctypes.c_int),
+            "fh_tune_force": ([i32, i32], ctypes.c_int),
+            "fh_tune_get": ([i32, i64, i64], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -222,3 +228,28 @@ class Prepared:
         if want_r and lebesgue:
             return r, lam
         return r if want_r else lam
+
+
+def variants(precision="fp64"):
+    """[(id, points_per_lane, group, node_split)] of the evaluation kernel."""
+    lib = load()
+    prec = _prec(precision)
+    out = []
+    for i in range(lib.fh_variant_count(prec)):
+        p, g, s = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib.fh_variant_shape(prec, i, ctypes.byref(p), ctypes.byref(g), ctypes.byref(s)),
+               "fh_variant_shape")
+        out.append((i, p.value, g.value, s.value))
+    return out
+
+
+def tune_force(precision, variant):
+    _check(load().fh_tune_force(_prec(precision), int(variant)), "fh_tune_force")
+
+
+def tune_set(precision, n, m, variant):
+    _check(load().fh_tune_set(_prec(precision), int(n), int(m), int(variant)), "fh_tune_set")
+
+
+def tune_get(precision, n, m):
+    return int(load().fh_tune_get(_prec(precision), int(n), int(m)))

@@ -89,3 +89,30 @@ def test_weights_and_lebesgue_host_validation():
     assert lib.fh_weights(P, 5, 1, P2, None, 256, None) == fh.FH_E_WORKSPACE
     assert lib.fh_lebesgue(P, 5, 1, P, 10, None, None, 0, P, 1 << 20, None) == fh.FH_E_ARG
     assert lib.fh_lebesgue(P, 5, 7, P, 10, P2, None, 0, P, 1 << 20, None) == fh.FH_E_DEGREE
+
+
+def test_variant_tables_and_tuner_api():
+    """The tuner interface: enumerate variants, record / override / release
+    a choice, and reject bad arguments -- all host-side."""
+    for prec in ("fp64", "split"):
+        vs = fh.variants(prec)
+        assert len(vs) >= 4
+        assert len({v[0] for v in vs}) == len(vs)
+        for vid, p, g, s in vs:
+            assert p in (1, 2, 4, 8) and g in (1, 4, 8) and s in (1, 2, 4)
+        base = fh.tune_get(prec, 777, 123456)
+        assert 0 <= base < len(vs)
+        other = (base + 1) % len(vs)
+        fh.tune_set(prec, 777, 123456, other)
+        assert fh.tune_get(prec, 777, 123456) == other
+        assert fh.tune_get(prec, 777, 10 ** 8) != -1          # other bucket untouched
+        fh.tune_force(prec, base)
+        assert fh.tune_get(prec, 777, 123456) == base          # force wins
+        fh.tune_force(prec, -1)
+        fh.tune_set(prec, 777, 123456, -1)                      # remove entry
+        assert fh.tune_get(prec, 777, 123456) == base
+    lib = fh.load()
+    assert lib.fh_tune_force(0, 999) == fh.FH_E_ARG
+    assert lib.fh_tune_set(0, 0, 10, 1) == fh.FH_E_ARG
+    assert lib.fh_tune_set(5, 10, 10, 1) == fh.FH_E_ARG
+    assert lib.fh_variant_count(7) == 0
