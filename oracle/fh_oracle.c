@@ -215,6 +215,8 @@ int fho_threads(int32_t nthreads) {
  *   dr/dx   = sum_k a_k (r - f_k) / (x - x_k) / D
  *   dr/dw_k = (f_k - r) / ((x - x_k) D)
  *   dr/dx_k |_w = a_k (f_k - r) / ((x - x_k) D)
+ * A NaN or infinite point has no derivative: dL/dx_p = NaN and the point
+ * contributes nothing to the other gradients.
  * At a hit x == x_j: r = f_j whatever the weights, so dr/df_j = 1, dr/dw = 0,
  * dr/dx_k|_w = 0 for k != j, dr/dx = r'(x_j) by [SW], and
  * dr/dx_j|_w = -r'(x_j) because r depends on the nodes only through x - x_k.
@@ -254,7 +256,9 @@ int fho_backward(const double* x, const double* f, int64_t n, int32_t d, const d
     csum* a_dx = a_dw + n;
     for (int64_t p = p0; p < p1; ++p) {
       double t = pts[p], gp = g[p];
-      if (isnan(t)) {
+      /* r is not differentiable at a non-finite point: dL/dx_p is NaN and
+         the point adds nothing to the node gradients */
+      if (!isfinite(t)) {
         if (dpt) dpt[p] = NAN;
         continue;
       }

@@ -74,6 +74,10 @@ size_t fh_workspace_size(int32_t op, int64_t n, int64_t m, int32_t d, int32_t pr
   switch (op) {
     case FH_OP_WEIGHTS: return kStatusBytes;
     case FH_OP_EVAL: return layout_tables(nullptr, n, &t);
+    case FH_OP_BACKWARD: {
+      BackwardBufs b;
+      return layout_backward(nullptr, n, m, &t, &b);
+    }
     default: return 0;
   }
 }
@@ -156,10 +160,27 @@ fh_status fh_lebesgue(const double* nodes, int64_t n, int32_t d, const double* x
                      stream);
 }
 
-fh_status fh_eval_backward(const double*, const double*, int64_t, int32_t, const double*, int64_t,
-                           const double*, double*, double*, double*, int32_t, void*, size_t,
-                           void*) {
-  return FH_E_UNSUPPORTED;
+fh_status fh_eval_backward(const double* nodes, const double* values, int64_t n, int32_t d,
+                           const double* x, int64_t m, const double* grad_r, double* grad_values,
+                           double* grad_x, double* grad_nodes, int32_t prec, void* ws,
+                           size_t ws_bytes, void* stream) {
+  fh_status st = check_problem(nodes, n, d);
+  if (st != FH_OK) return st;
+  if (values == nullptr || m < 0 || (m > 0 && (x == nullptr || grad_r == nullptr)))
+    return FH_E_ARG;
+  if (prec != FH_FP64 && prec != FH_FP32_SPLIT) return FH_E_ARG;
+  if (prec == FH_FP32_SPLIT) return FH_E_UNSUPPORTED;
+  st = check_ws(ws, ws_bytes, fh_workspace_size(FH_OP_BACKWARD, n, m, d, prec));
+  if (st != FH_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  NodeTable t;
+  BackwardBufs b;
+  layout_backward(ws, n, m, &t, &b);
+  hipError_t e = launch_pack(nodes, values, nullptr, n, d, t, false, static_cast<uint32_t*>(ws), s);
+  if (e == hipSuccess)
+    e = launch_backward(nodes, x, grad_r, n, d, m, t, b, grad_values, m > 0 ? grad_x : nullptr,
+                        grad_nodes, s);
+  return finish(e, ws, s);
 }
 
 fh_status fh_batch_create(fh_batch** out, int32_t, const int64_t*, const int32_t*,

@@ -1,0 +1,329 @@
+// Adjoint of L = sum_p g_p r(x_p) (gfx950, binary64).
+//
+// With a_pk = w_k t_pk, t_pk = 1/(x_p - x_k), D_p = sum_k a_pk, r_p = N_p/D_p
+// and c_p = g_p / D_p, the derivatives at non-hit points are
+//   dL/dx_p   = c_p (r_p E_p - F_p),       E_p = sum_k w_k t_pk^2,
+//                                          F_p = sum_k w_k f_k t_pk^2,
+//   dL/df_k   = w_k S1_k,                  S1_k = sum_p c_p t_pk,
+//   dL/dw_k   = f_k S1_k - S2_k,           S2_k = sum_p c_p r_p t_pk,
+//   dL/dx_k|w = w_k (f_k S3_k - S4_k),     S3_k = sum_p c_p t_pk^2,
+//                                          S4_k = sum_p c_p r_p t_pk^2,
+// (differentiating the barycentric form of Floater & Hormann 2007 with
+// respect to f_k, x_p, w_k and x_k).  At a hit x_p == x_j, r = f_j whatever
+// the weights, so dL/df_j gets g_p, dL/dx_p = g_p r'(x_j) with the node
+// formula r'(x_j) = sum_{k!=j} (w_k/w_j)(f_k - f_j)/(x_j - x_k) (Schneider &
+// Werner 1986), and dL/dx_j|w gets -g_p r'(x_j) (r depends on the nodes only
+// through x - x_k).  The total node gradient adds the chain through the
+// weights, dL/dx_l += sum_k dL/dw_k dw_k/dx_l.
+//
+// Passes (all on the caller's stream, no atomics, fixed reduction order):
+//   1. per point (lanes own points, nodes streamed as in the evaluation
+//      kernel): N, D, E, F -> dL/dx_p and a pass-2 record {x, c, c r,
+//      g at a hit, g r' at a hit}; non-finite points get a record far from
+//      every node with zero weights (they contribute nothing) and NaN dx_p;
+//   2. per node and chunk of points (lanes own nodes, points streamed as
+//      wave-uniform scalar loads): S1..S4 and the hit sums, with
+//      reciprocals taken four points at a time (simultaneous inversion); a
+//      group whose product is not normal (a hit, or extreme range) is redone
+//      pair by pair, where a zero difference adds the hit terms;
+//   3. per node: fixed-order sum of the chunk partials, then dL/df, dL/dw and
+//      the direct dL/dx_k;
+//   4. per node: the weight chain (O(d^3) per node), total dL/dx_k.
+#include "fh_internal.h"
+#include "pair_math.h"
+
+namespace fhk {
+
+constexpr int kRecFields = 5;   // pass-2 point record: x, c, c r, g_hit, g_hit r'
+constexpr int kPartFields = 6;  // S1, S2, S3, S4, H1 (sum g_hit), H2 (sum g_hit r')
+
+// ---------------------------------------------------------------- pass 1 --
+template <int P>
+__global__ void __launch_bounds__(256)
+    k_bwd_points(const double* __restrict__ x, const double* __restrict__ g, int64_t m,
+                 int64_t m_pad, const double* __restrict__ tx, const double* __restrict__ tw,
+                 const double* __restrict__ twf, const double* __restrict__ tf, int64_t n_pad,
+                 int64_t n, double* __restrict__ dx, double* __restrict__ rec) {
+  const int64_t base = (int64_t)blockIdx.x * blockDim.x * P + threadIdx.x;
+  // a point far outside the node range: its differences are all of the
+  // order of the span, never zero
+  const double span = tx[n - 1] - tx[0];
+  const double far = tx[n - 1] + span + 1.0;
+  double xp[P], N[P], D[P], E[P], F[P];
+  bool bad[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const int64_t idx = base + (int64_t)j * blockDim.x;
+    xp[j] = idx < m ? x[idx] : far;
+    N[j] = D[j] = E[j] = F[j] = 0.0;
+    bad[j] = false;
+  }
+  for (int64_t k = 0; k < n_pad; k += 8) {
+    double xk[8], wk[8], vk[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      xk[i] = tx[k + i];
+      wk[i] = tw[k + i];
+      vk[i] = twf[k + i];
+    }
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      double dl[8], t[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) dl[i] = xp[j] - xk[i];
+      bad[j] |= group_reciprocals<8>(dl, t);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        D[j] = __builtin_fma(wk[i], t[i], D[j]);
+        N[j] = __builtin_fma(vk[i], t[i], N[j]);
+        const double t2 = t[i] * t[i];
+        E[j] = __builtin_fma(wk[i], t2, E[j]);
+        F[j] = __builtin_fma(vk[i], t2, F[j]);
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const int64_t idx = base + (int64_t)j * blockDim.x;
+    if (idx >= m_pad) continue;
+    double* out = rec + idx * kRecFields;
+    if (idx >= m) {
+      out[0] = far; out[1] = 0.0; out[2] = 0.0; out[3] = 0.0; out[4] = 0.0;
+      continue;
+    }
+    const double gp = g[idx];
+    const double t = xp[j];
+    double dxp, c = 0.0, cr = 0.0, hg = 0.0, hgr = 0.0, xr = t;
+    if (!__builtin_isfinite(t)) {
+      dxp = __builtin_nan("");
+      xr = far;
+    } else if (!bad[j]) {
+      const double r = N[j] / D[j];
+      c = gp / D[j];
+      cr = c * r;
+      dxp = c * (r * E[j] - F[j]);
+    } else {
+      // pair-by-pair: exact hit or extreme range
+      int64_t hit = -1;
+      double n2 = 0.0, d2 = 0.0, e2 = 0.0, f2 = 0.0;
+      for (int64_t k = 0; k < n; ++k) {
+        const double del = t - tx[k];
+        if (del == 0.0) {
+          hit = k;
+          break;
+        }
+        const double a = tw[k] / del;
+        const double q = 1.0 / del;
+        d2 += a;
+        n2 = __builtin_fma(a, tf[k], n2);
+        e2 = __builtin_fma(a, q, e2);
+        f2 = __builtin_fma(a * tf[k], q, f2);
+      }
+      if (hit >= 0) {
+        const double wj = tw[hit], fj = tf[hit], xj = tx[hit];
+        double rp = 0.0;
+        for (int64_t k = 0; k < n; ++k)
+          if (k != hit) rp += (tw[k] / wj) * (tf[k] - fj) / (xj - tx[k]);
+        dxp = gp * rp;
+        hg = gp;
+        hgr = gp * rp;
+      } else {
+        const double r = n2 / d2;
+        c = gp / d2;
+        cr = c * r;
+        dxp = c * (r * e2 - f2);
+      }
+    }
+    if (dx) dx[idx] = dxp;
+    out[0] = xr; out[1] = c; out[2] = cr; out[3] = hg; out[4] = hgr;
+  }
+}
+
+// ---------------------------------------------------------------- pass 2 --
+// grid: x = node tiles of 64*Q nodes, y = chunks of `chunk` points.
+template <int Q>
+__global__ void __launch_bounds__(64)
+    k_bwd_nodes(const double* __restrict__ rec, int64_t chunk, const double* __restrict__ tx,
+                int64_t n_pad, double* __restrict__ part) {
+  const int lane = threadIdx.x;
+  const int64_t k0 = (int64_t)blockIdx.x * 64 * Q + lane;
+  const int64_t c = blockIdx.y;
+  const double* r0 = rec + c * chunk * kRecFields;
+  double xk[Q], S1[Q], S2[Q], S3[Q], S4[Q], H1[Q], H2[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int64_t k = k0 + q * 64;
+    xk[q] = tx[k < n_pad ? k : n_pad - 1];
+    S1[q] = S2[q] = S3[q] = S4[q] = H1[q] = H2[q] = 0.0;
+  }
+  for (int64_t p = 0; p < chunk; p += 4) {
+    const double* pr = r0 + p * kRecFields;
+    double px[4], pc[4], pcr[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      px[i] = pr[i * kRecFields + 0];
+      pc[i] = pr[i * kRecFields + 1];
+      pcr[i] = pr[i * kRecFields + 2];
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      double dl[4], t[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) dl[i] = px[i] - xk[q];
+      const bool bad = group_reciprocals<4>(dl, t);
+      if (!bad) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const double t2 = t[i] * t[i];
+          S1[q] = __builtin_fma(pc[i], t[i], S1[q]);
+          S2[q] = __builtin_fma(pcr[i], t[i], S2[q]);
+          S3[q] = __builtin_fma(pc[i], t2, S3[q]);
+          S4[q] = __builtin_fma(pcr[i], t2, S4[q]);
+        }
+      } else {
+        // pair by pair: a zero difference is a hit on this node
+        for (int i = 0; i < 4; ++i) {
+          if (dl[i] == 0.0) {
+            H1[q] += pr[i * kRecFields + 3];
+            H2[q] += pr[i * kRecFields + 4];
+          } else {
+            const double ti = 1.0 / dl[i];
+            const double t2 = ti * ti;
+            S1[q] = __builtin_fma(pc[i], ti, S1[q]);
+            S2[q] = __builtin_fma(pcr[i], ti, S2[q]);
+            S3[q] = __builtin_fma(pc[i], t2, S3[q]);
+            S4[q] = __builtin_fma(pcr[i], t2, S4[q]);
+          }
+        }
+      }
+    }
+  }
+  double* out = part + c * kPartFields * n_pad;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int64_t k = k0 + q * 64;
+    if (k >= n_pad) continue;
+    out[0 * n_pad + k] = S1[q];
+    out[1 * n_pad + k] = S2[q];
+    out[2 * n_pad + k] = S3[q];
+    out[3 * n_pad + k] = S4[q];
+    out[4 * n_pad + k] = H1[q];
+    out[5 * n_pad + k] = H2[q];
+  }
+}
+
+// ---------------------------------------------------------------- pass 3 --
+__global__ void __launch_bounds__(256)
+    k_bwd_reduce(const double* __restrict__ part, int64_t chunks, int64_t n_pad, int64_t n,
+                 const double* __restrict__ tw, const double* __restrict__ tf,
+                 double* __restrict__ df, double* __restrict__ dw, double* __restrict__ dxd) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double s[kPartFields] = {0, 0, 0, 0, 0, 0};
+  for (int64_t c = 0; c < chunks; ++c) {
+    const double* pc = part + c * kPartFields * n_pad;
+#pragma unroll
+    for (int v = 0; v < kPartFields; ++v) s[v] += pc[v * n_pad + k];
+  }
+  const double w = tw[k], f = tf[k];
+  if (df) df[k] = w * s[0] + s[4];
+  dw[k] = f * s[0] - s[1];
+  dxd[k] = w * (f * s[2] - s[3]) - s[5];
+}
+
+// ---------------------------------------------------------------- pass 4 --
+// dL/dx_l = direct term + sum over the weights that depend on x_l:
+// w_k = sum_{i in J_k} T_{k,i},  T_{k,i} = (-1)^i / prod_{j in [i,i+d], j!=k} (x_k - x_j),
+// dT/dx_l = T / (x_k - x_l) for l != k in the window, dT/dx_k = -T sum_{j!=k} 1/(x_k - x_j).
+__global__ void __launch_bounds__(256)
+    k_bwd_chain(const double* __restrict__ x, int64_t n, int32_t d, const double* __restrict__ dw,
+                const double* __restrict__ dxd, double* __restrict__ dxn) {
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= n) return;
+  double acc = dxd[l];
+  const int64_t klo = l - d > 0 ? l - d : 0;
+  const int64_t khi = l + d < n - 1 ? l + d : n - 1;
+  for (int64_t k = klo; k <= khi; ++k) {
+    const int64_t ilo = k - d > 0 ? k - d : 0;
+    const int64_t ihi = k < n - 1 - d ? k : n - 1 - d;
+    double sk = 0.0;  // d w_k / d x_l
+    for (int64_t i = ilo; i <= ihi; ++i) {
+      if (l < i || l > i + d) continue;  // x_l not in this window
+      double prod = 1.0;
+      for (int64_t j = i; j <= i + d; ++j)
+        if (j != k) prod *= (x[k] - x[j]);
+      double T = 1.0 / prod;
+      if (i & 1) T = -T;
+      if (l != k) {
+        sk += T / (x[k] - x[l]);
+      } else {
+        double inv = 0.0;
+        for (int64_t j = i; j <= i + d; ++j)
+          if (j != k) inv += 1.0 / (x[k] - x[j]);
+        sk -= T * inv;
+      }
+    }
+    acc = __builtin_fma(dw[k], sk, acc);
+  }
+  dxn[l] = acc;
+}
+
+// ------------------------------------------------------------- launcher --
+BackwardPlan plan_backward(int64_t n, int64_t m) {
+  BackwardPlan p;
+  p.n_pad = round_up(n, kNodePad);
+  p.q = 1;
+  const int64_t node_waves = (p.n_pad + 64 * p.q - 1) / (64 * p.q);
+  // enough (node tile, chunk) waves to fill the chip, chunks of >= 256 points
+  int64_t chunks = (8192 + node_waves - 1) / node_waves;
+  const int64_t max_chunks = (m + 255) / 256;
+  if (chunks > max_chunks) chunks = max_chunks;
+  if (chunks < 1) chunks = 1;
+  p.chunk = round_up((m + chunks - 1) / chunks, 4);
+  if (p.chunk < 4) p.chunk = 4;
+  p.chunks = (m + p.chunk - 1) / p.chunk;
+  if (p.chunks < 1) p.chunks = 1;
+  p.m_pad = p.chunks * p.chunk;
+  return p;
+}
+
+size_t layout_backward(void* ws, int64_t n, int64_t m, NodeTable* t, BackwardBufs* b) {
+  size_t off = layout_tables(ws, n, t);
+  const BackwardPlan p = plan_backward(n, m);
+  char* base = static_cast<char*>(ws);
+  auto take = [&](size_t bytes) {
+    char* q = base ? base + off : nullptr;
+    off = align_up(off + bytes);
+    return reinterpret_cast<double*>(q);
+  };
+  b->plan = p;
+  b->rec = take(sizeof(double) * kRecFields * p.m_pad);
+  b->part = take(sizeof(double) * kPartFields * p.n_pad * p.chunks);
+  b->dw = take(sizeof(double) * p.n_pad);
+  b->dxd = take(sizeof(double) * p.n_pad);
+  return off;
+}
+
+hipError_t launch_backward(const double* nodes, const double* x, const double* g, int64_t n,
+                           int32_t d, int64_t m, const NodeTable& t, const BackwardBufs& b,
+                           double* df, double* dx, double* dxn, hipStream_t s) {
+  const BackwardPlan& p = b.plan;
+  constexpr int P = 1;
+  const dim3 g1((unsigned)((p.m_pad + 256 * P - 1) / (256 * P)));
+  k_bwd_points<P><<<g1, 256, 0, s>>>(x, g, m, p.m_pad, t.x, t.w, t.wf, t.f, t.n_pad, n, dx, b.rec);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const dim3 g2((unsigned)((p.n_pad + 64 * p.q - 1) / (64 * p.q)), (unsigned)p.chunks);
+  k_bwd_nodes<1><<<g2, 64, 0, s>>>(b.rec, p.chunk, t.x, t.n_pad, b.part);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const dim3 g3((unsigned)((n + 255) / 256));
+  k_bwd_reduce<<<g3, 256, 0, s>>>(b.part, p.chunks, p.n_pad, n, t.w, t.f, df, b.dw, b.dxd);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (dxn) {
+    k_bwd_chain<<<g3, 256, 0, s>>>(nodes, n, d, b.dw, b.dxd, dxn);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+}  // namespace fhk

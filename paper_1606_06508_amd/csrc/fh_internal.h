@@ -50,6 +50,24 @@ void f64_variant_shape(int id, int* p, int* g, int* s);
 int split_variant_count();
 void split_variant_shape(int id, int* p, int* g, int* s);
 
+// Adjoint: points are processed in `chunks` chunks of `chunk` points
+// (m_pad = chunks * chunk, the tail padded with neutral records) so that the
+// per-node pass has enough (node tile, chunk) waves.
+struct BackwardPlan {
+  int64_t n_pad, chunk, chunks, m_pad;
+  int q;  // nodes per lane in the per-node pass
+};
+struct BackwardBufs {
+  BackwardPlan plan;
+  double* rec;   // [m_pad][5] per-point records of pass 1
+  double* part;  // [chunks][6][n_pad] per-chunk node sums
+  double* dw;    // [n_pad] dL/dw_k
+  double* dxd;   // [n_pad] direct dL/dx_k at fixed weights
+};
+BackwardPlan plan_backward(int64_t n, int64_t m);
+// Workspace layout of FH_OP_BACKWARD (node tables, then the buffers above).
+size_t layout_backward(void* ws, int64_t n, int64_t m, NodeTable* t, BackwardBufs* b);
+
 // ---- launchers (each returns the launch error, hipSuccess on success) ----
 hipError_t launch_weights(const double* nodes, int64_t n, int32_t d, double* w_out,
                           uint32_t* status, hipStream_t s);
@@ -58,6 +76,9 @@ hipError_t launch_pack(const double* nodes, const double* values, const double* 
                        hipStream_t s);
 hipError_t launch_eval_f64(const double* x, int64_t m, const NodeTable& t, int64_t n, double* r,
                            double* lam, const EvalConfig& cfg, hipStream_t s);
+hipError_t launch_backward(const double* nodes, const double* x, const double* g, int64_t n,
+                           int32_t d, int64_t m, const NodeTable& t, const BackwardBufs& b,
+                           double* df, double* dx, double* dxn, hipStream_t s);
 hipError_t launch_eval_split(const double* x, int64_t m, const NodeTable& t, int64_t n, double* r,
                              double* lam, const EvalConfig& cfg, hipStream_t s);
 

@@ -1,0 +1,57 @@
+// Binary64 pair arithmetic shared by the evaluation and adjoint kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace fhk {
+
+// true if v is +-0, subnormal, infinite or NaN (everything but normal)
+__device__ __forceinline__ bool not_normal(double v) {
+  return __builtin_amdgcn_class(v, 0x2F7);
+}
+
+// 1/q to ~2^-50 relative: hardware estimate plus one Newton step
+__device__ __forceinline__ double rcp_refined(double q) {
+  const double y = __builtin_amdgcn_rcp(q);
+  const double e = __builtin_fma(-q, y, 1.0);
+  return __builtin_fma(y, e, y);
+}
+
+// Reciprocals of G deltas via one reciprocal of their product.  Returns true
+// if the product is not a normal number (the lane must be recomputed).
+template <int G>
+__device__ __forceinline__ bool group_reciprocals(const double (&d)[G], double (&t)[G]);
+
+template <>
+__device__ __forceinline__ bool group_reciprocals<4>(const double (&d)[4], double (&t)[4]) {
+  const double q01 = d[0] * d[1], q23 = d[2] * d[3];
+  const double q = q01 * q23;
+  const double y = rcp_refined(q);
+  const double y01 = y * q23, y23 = y * q01;
+  t[0] = y01 * d[1];
+  t[1] = y01 * d[0];
+  t[2] = y23 * d[3];
+  t[3] = y23 * d[2];
+  return not_normal(q);
+}
+
+template <>
+__device__ __forceinline__ bool group_reciprocals<8>(const double (&d)[8], double (&t)[8]) {
+  const double q01 = d[0] * d[1], q23 = d[2] * d[3], q45 = d[4] * d[5], q67 = d[6] * d[7];
+  const double q03 = q01 * q23, q47 = q45 * q67;
+  const double q = q03 * q47;
+  const double y = rcp_refined(q);
+  const double y03 = y * q47, y47 = y * q03;
+  const double y01 = y03 * q23, y23 = y03 * q01, y45 = y47 * q67, y67 = y47 * q45;
+  t[0] = y01 * d[1];
+  t[1] = y01 * d[0];
+  t[2] = y23 * d[3];
+  t[3] = y23 * d[2];
+  t[4] = y45 * d[5];
+  t[5] = y45 * d[4];
+  t[6] = y67 * d[7];
+  t[7] = y67 * d[6];
+  return not_normal(q);
+}
+
+}  // namespace fhk

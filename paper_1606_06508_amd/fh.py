@@ -197,6 +197,28 @@ def lebesgue(nodes, d, x, *, weights=None, precision="fp64", out=None, ws=None):
     return lam
 
 
+def eval_backward(nodes, values, d, x, grad_r, *, need_values=True, need_x=True,
+                  need_nodes=True, precision="fp64", ws=None):
+    """Adjoint of L = sum_p grad_r[p] r(x_p): (dL/dvalues, dL/dx, dL/dnodes),
+    None for the ones not requested.  dL/dnodes is the total derivative
+    (through the weights as well)."""
+    lib = load()
+    xn, f, t, g = _f64(nodes, "nodes"), _f64(values, "values"), _f64(x, "x"), _f64(grad_r, "grad_r")
+    n, m = xn.numel(), t.numel()
+    if f.numel() != n or g.numel() != m:
+        raise ValueError("values must match nodes and grad_r must match x")
+    prec = _prec(precision)
+    gv = torch.empty_like(xn) if need_values else None
+    gx = torch.empty_like(t) if need_x else None
+    gn = torch.empty_like(xn) if need_nodes else None
+    ws = ws or default_workspace(t.device)
+    buf = ws.reserve(workspace_size(FH_OP_BACKWARD, n, m, d, prec))
+    _check(lib.fh_eval_backward(_ptr(xn), _ptr(f), n, int(d), _ptr(t), m, _ptr(g), _ptr(gv),
+                                _ptr(gx), _ptr(gn), prec, _ptr(buf), buf.numel(),
+                                _stream(t.device)), "fh_eval_backward")
+    return gv, gx, gn
+
+
 class Prepared:
     """An interpolant whose node table lives in its own workspace, for
     evaluation on many point batches (fh_prepare + fh_eval_prepared)."""

@@ -1,0 +1,229 @@
+"""Parity of the HIP adjoint (fh_eval_backward) with the FP64 oracle, the
+structural identities of the gradients at full size, central differences
+of the HIP forward pass, and the autograd front.
+
+Error scales.  Each gradient component is a sum of terms; its rounding error
+is bounded by a few u times the sum of the terms' absolute values (and by
+the number of terms in the worst case).  Every term carries c_p = g_p / D_p,
+and D_p = sum_k a_pk has condition number Lambda(x_p), so c_p itself is only
+known to about u (1 + Lambda(x_p)); each point's terms are weighted by that
+factor.  The tests compute those absolute sums independently with numpy and
+require |HIP - oracle| <= TOL * scale,
+TOL = 1e-12 (about 10^4 u: room for the plain, chunked sums of the kernel
+over up to 10^4 terms against the oracle's compensated ones).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle
+from paper_1606_06508_amd import fh, inputs
+from paper_1606_06508_amd.autograd import FhEval, interpolate
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+U = 2.0 ** -53
+TOL = 1e-12
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def _np(t):
+    return None if t is None else t.cpu().numpy()
+
+
+def _gpu_bwd(nodes, vals, d, pts, g):
+    gv, gx, gn = fh.eval_backward(_t(nodes), _t(vals), d, _t(pts), _t(g))
+    torch.cuda.synchronize()
+    return _np(gv), _np(gx), _np(gn)
+
+
+def _weight_derivative_abs(x, d):
+    """A[k, l] = sum over the terms of w_k of |d term / d x_l| (dense, small n)."""
+    n = x.size
+    A = np.zeros((n, n))
+    for k in range(n):
+        for i in range(max(0, k - d), min(k, n - 1 - d) + 1):
+            win = [j for j in range(i, i + d + 1) if j != k]
+            T = 1.0 / np.prod([x[k] - x[j] for j in win]) if win else 1.0
+            for l in win:
+                A[k, l] += abs(T / (x[k] - x[l]))
+            A[k, k] += abs(T) * sum(1.0 / abs(x[k] - x[j]) for j in win)
+    return A
+
+
+def _scales(nodes, vals, d, pts, g):
+    """Absolute-value sums of the terms of every gradient component."""
+    w = oracle.weights(nodes, d)
+    r, lam, _ = oracle.evaluate(nodes, vals, d, pts, scale=False)
+    ok = np.isfinite(pts) & ~np.isin(pts, nodes)
+    s_df = np.zeros(nodes.size)
+    s_dw = np.zeros(nodes.size)
+    s_dxd = np.zeros(nodes.size)
+    s_dx = np.zeros(pts.size)
+    idx = np.flatnonzero(ok)
+    for lo in range(0, idx.size, 2000):
+        sel = idx[lo:lo + 2000]
+        T = 1.0 / (pts[sel, None] - nodes[None, :])
+        D = (w[None, :] * T).sum(1)
+        c = np.abs(g[sel] / D) * (1.0 + lam[sel])
+        rr = np.abs(r[sel])
+        s_df += np.abs(w) * (c[:, None] * np.abs(T)).sum(0)
+        s_dw += (c[:, None] * np.abs(T) * (np.abs(vals)[None, :] + rr[:, None])).sum(0)
+        T2 = T * T
+        s_dxd += np.abs(w) * (c[:, None] * T2 * (np.abs(vals)[None, :] + rr[:, None])).sum(0)
+        s_dx[sel] = c * (np.abs(w)[None, :] * T2 * (rr[:, None] + np.abs(vals)[None, :])).sum(1)
+    # exact hits: dL/df_j gets g_p; dL/dx_p and dL/dx_j get +-g_p r'(x_j),
+    # r'(x_j) = sum_{k != j} (w_k / w_j)(f_k - f_j)/(x_j - x_k)
+    for p in np.flatnonzero(np.isin(pts, nodes)):
+        j = int(np.searchsorted(nodes, pts[p]))
+        others = np.arange(nodes.size) != j
+        rp_abs = np.sum(np.abs(w[others] / w[j]) * np.abs(vals[others] - vals[j])
+                        / np.abs(nodes[j] - nodes[others]))
+        s_df[j] += abs(g[p])
+        s_dx[p] = abs(g[p]) * rp_abs
+        s_dxd[j] += abs(g[p]) * rp_abs
+    return s_df, s_dx, s_dxd, s_dw
+
+
+def _check_against_oracle(nodes, vals, d, pts, g, dense_chain=True):
+    gv, gx, gn = _gpu_bwd(nodes, vals, d, pts, g)
+    o = oracle.backward(nodes, vals, d, pts, g)
+    s_df, s_dx, s_dxd, s_dw = _scales(nodes, vals, d, pts, g)
+    assert np.all(np.abs(gv - o["d_values"]) <= TOL * s_df + 1e-300)
+    fin = np.isfinite(o["d_points"])
+    assert np.array_equal(np.isfinite(gx), fin)
+    assert np.all(np.abs(gx[fin] - o["d_points"][fin]) <= TOL * s_dx[fin] + 1e-300)
+    if dense_chain:
+        chain = _weight_derivative_abs(nodes, d).T @ s_dw
+        s_dn = s_dxd + chain
+        assert np.all(np.abs(gn - o["d_nodes"]) <= TOL * s_dn + 1e-300)
+    return gv, gx, gn, o
+
+
+# ------------------------------------------------------------- parity --
+def test_grad_workload_reduced():
+    c = inputs.grad_workload(n=513, m=6007)
+    _check_against_oracle(c["nodes"], c["values"], c["d"], c["points"], c["grad"])
+
+
+@pytest.mark.parametrize("n,d", [(1, 0), (2, 1), (5, 0), (5, 4), (64, 3), (65, 7), (130, 10)])
+def test_shapes_with_hits_and_nan(n, d):
+    g = np.random.default_rng(100 + n + d)
+    nodes = inputs.equispaced(n) + (g.uniform(-0.2, 0.2, n) * (2.0 / max(n - 1, 1)) if n > 2 else 0)
+    nodes = np.sort(nodes)
+    vals = g.standard_normal(n)
+    pts = np.concatenate([g.uniform(-1.1, 1.1, size=1001), nodes[:: max(1, n // 5)], [np.nan]])
+    grad = g.standard_normal(pts.size)
+    gv, gx, gn, o = _check_against_oracle(nodes, vals, d, pts, grad)
+    assert np.isnan(gx[-1])
+
+
+def test_full_size_identities_and_sampled_points():
+    """The full 10^6-point workload: identities that hold at any size, and
+    dL/dx_p against the oracle on a seeded sample of points (each dL/dx_p
+    depends on its own point only)."""
+    c = inputs.grad_workload()
+    nodes, vals, d, pts, g = c["nodes"], c["values"], c["d"], c["points"], c["grad"]
+    gv, gx, gn = _gpu_bwd(nodes, vals, d, pts, g)
+    assert np.all(np.isfinite(gv)) and np.all(np.isfinite(gx)) and np.all(np.isfinite(gn))
+    # partition of unity: sum_k dL/df_k = sum_p g_p
+    assert abs(gv.sum() - g.sum()) <= 1e-11 * np.abs(g).sum()
+    # translation invariance and scale invariance
+    tot = gn.sum() + gx.sum()
+    assert abs(tot) <= 1e-10 * (np.abs(gn).sum() + np.abs(gx).sum())
+    tot = (nodes * gn).sum() + (pts * gx).sum()
+    assert abs(tot) <= 1e-10 * (np.abs(nodes * gn).sum() + np.abs(pts * gx).sum())
+    idx = np.random.default_rng(5).choice(pts.size, 1500, replace=False)
+    o = oracle.backward(nodes, vals, d, pts[idx], g[idx])
+    _, s_dx, _, _ = _scales(nodes, vals, d, pts[idx], g[idx])
+    assert np.all(np.abs(gx[idx] - o["d_points"]) <= TOL * s_dx)
+
+
+def test_polynomial_data():
+    """Data from a polynomial of degree <= d: dL/dx_p = g_p p'(x_p) and
+    dL/dx_k + p'(x_k) dL/df_k = 0."""
+    g = np.random.default_rng(3)
+    d = 4
+    nodes = inputs.equispaced(301)
+    poly = g.standard_normal(d + 1)
+    vals = np.polyval(poly, nodes)
+    pts = g.uniform(-1, 1, size=20000)
+    grad = g.standard_normal(pts.size)
+    gv, gx, gn = _gpu_bwd(nodes, vals, d, pts, grad)
+    dp = grad * np.polyval(np.polyder(poly), pts)
+    assert np.allclose(gx, dp, rtol=1e-9, atol=1e-9 * np.abs(dp).max())
+    moved = gn + np.polyval(np.polyder(poly), nodes) * gv
+    assert np.abs(moved).max() <= 1e-10 * (np.abs(gn).sum() + np.abs(gv).sum())
+
+
+def test_central_differences():
+    """Central differences (h = 1e-6) of the HIP forward pass (weights
+    recomputed) against the adjoint, within 10 (h^2 M3/6 + 2u sum|g r|/h),
+    M3 estimated from differences at 10h."""
+    c = inputs.grad_workload(n=257, m=4001)
+    nodes, vals, d, pts, g = c["nodes"], c["values"], c["d"], c["points"], c["grad"]
+    gv, gx, gn = _gpu_bwd(nodes, vals, d, pts, g)
+    xn, f, t, gt = _t(nodes), _t(vals), _t(pts), _t(g)
+
+    def L(nodes_=None, vals_=None, pts_=None):
+        r = fh.evaluate(nodes_ if nodes_ is not None else xn, vals_ if vals_ is not None else f,
+                        d, pts_ if pts_ is not None else t)
+        return float((r * gt).sum())
+
+    r0 = fh.evaluate(xn, f, d, t)
+    noise = 2 * U * float((r0 * gt).abs().sum())
+    h = 1e-6
+
+    def fd(kind, k, step):
+        e = torch.zeros(nodes.size if kind != "pt" else pts.size, dtype=torch.float64, device=DEV)
+        e[k] = step
+        if kind == "node":
+            return (L(nodes_=xn + e) - L(nodes_=xn - e)) / (2 * step)
+        if kind == "val":
+            return (L(vals_=f + e) - L(vals_=f - e)) / (2 * step)
+        return (L(pts_=t + e) - L(pts_=t - e)) / (2 * step)
+
+    for kind, ks, ref in (("node", (0, 1, 77, 128, 255, 256), gn), ("val", (0, 100, 256), gv),
+                          ("pt", (0, 17, 4000), gx)):
+        for k in ks:
+            a, b = fd(kind, k, h), fd(kind, k, 10 * h)
+            m3 = abs(b - a) * 6 / (99 * h * h)
+            tol = 10 * (h * h * m3 / 6 + noise / h) + 1e-12 * abs(ref[k])
+            assert abs(a - ref[k]) <= tol, (kind, k, a, ref[k], tol)
+
+
+def test_deterministic():
+    c = inputs.grad_workload(n=1025, m=100003)
+    a = _gpu_bwd(c["nodes"], c["values"], c["d"], c["points"], c["grad"])
+    b = _gpu_bwd(c["nodes"], c["values"], c["d"], c["points"], c["grad"])
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+
+
+def test_partial_outputs_match_full():
+    c = inputs.grad_workload(n=129, m=5000)
+    full = _gpu_bwd(c["nodes"], c["values"], c["d"], c["points"], c["grad"])
+    gv, gx, gn = fh.eval_backward(_t(c["nodes"]), _t(c["values"]), c["d"], _t(c["points"]),
+                                  _t(c["grad"]), need_values=False, need_x=False)
+    assert gv is None and gx is None
+    assert np.array_equal(_np(gn), full[2])
+
+
+# ------------------------------------------------------------ autograd --
+def test_autograd_function_and_gradcheck():
+    g = np.random.default_rng(8)
+    nodes = _t(np.sort(inputs.equispaced(12) + g.uniform(-0.03, 0.03, 12))).requires_grad_()
+    vals = _t(g.standard_normal(12)).requires_grad_()
+    x = _t(g.uniform(-1, 1, 25)).requires_grad_()
+    assert torch.autograd.gradcheck(lambda a, b, c: FhEval.apply(a, b, c, 3), (nodes, vals, x),
+                                    eps=1e-6, atol=1e-6, rtol=1e-5)
+    # backward of a loss equals fh_eval_backward
+    r = interpolate(nodes, vals, x, 3)
+    w = torch.linspace(-1, 1, 25, dtype=torch.float64, device=DEV)
+    (r * w).sum().backward()
+    gv, gx, gn = fh.eval_backward(nodes.detach(), vals.detach(), 3, x.detach(), w)
+    assert torch.equal(nodes.grad, gn) and torch.equal(vals.grad, gv) and torch.equal(x.grad, gx)
