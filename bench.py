@@ -15,8 +15,11 @@ Also reported in the same JSON line:
                 (78.6 TFLOP/s) with 7 algorithmic flops per pair;
   cpu_baseline  the FP64 oracle on the host cores, on a bounded sample;
   max_error     parity of the timed outputs against the oracle on the sample;
-  forms         the other forms of the path on their own workloads (FP64 vs
-                FP32-split on the 4097-node, 10^7-point clustered workload).
+  forms         the other forms of the path on their own workloads: FP64 vs
+                FP32-split on the 4097-node, 10^7-point clustered workload;
+                the batched graph launch over 4096 uneven interpolants vs a
+                per-instance fh_eval loop; the adjoint on 2049 nodes and
+                10^6 points.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -174,6 +177,82 @@ def run_split_forms(dev, reps, with_cpu):
     return out
 
 
+def _time_ms(fn, reps, stream=None):
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def run_batched_form(dev, reps, with_cpu):
+    """All 4096 interpolants in one graph launch (weights + evaluation of
+    every instance), against a loop of one fh_eval call per instance on the
+    same stream (same precision, same outputs)."""
+    c = inputs.batched_workload()
+    n, d, m = c["n"], c["d"], c["m"]
+    pairs = float((n * m).sum())
+    nodes, vals, x = _t(c["nodes"], dev), _t(c["values"], dev), _t(c["points"], dev)
+    out = {"workload": f"batched: {n.size} instances, n in [16,2048], d in [1,10], "
+                       f"sum m = {int(m.sum())}, pairs = {pairs:.3e}"}
+    r_loop = torch.empty_like(x)
+    for prec in ("fp64", "split"):
+        b = fh.Batch(n, d, m, nodes, vals, x, precision=prec)
+        ms = _time_ms(b, reps)
+        out[prec] = {"Gpair_s": pairs / (ms * 1e-3) / 1e9, "ms_per_launch": ms}
+        if with_cpu and prec == "fp64":
+            from oracle import metrics, oracle
+            g = np.random.default_rng(1)
+            worst = {}
+            for i in g.choice(n.size, 12, replace=False):
+                ns = slice(int(c["node_off"][i]), int(c["node_off"][i + 1]))
+                p0, p1 = int(c["pt_off"][i]), int(c["pt_off"][i + 1])
+                sel = np.arange(p0, p1)[g.choice(p1 - p0, min(1000, p1 - p0), replace=False)]
+                r_o, _, s_o = oracle.evaluate(c["nodes"][ns], c["values"][ns], int(d[i]),
+                                              c["points"][sel], lebesgue=True)
+                st = metrics.parity(b.r[torch.from_numpy(sel).to(dev)].cpu().numpy(), None, r_o,
+                                    None, s_o)
+                for k, v in st.items():
+                    if k.startswith("e_"):
+                        worst[k] = max(worst.get(k, 0.0), v)
+            out[prec]["max_error_12_instances"] = worst
+        b.close()
+    ws = fh.Workspace(dev, fh.workspace_size(fh.FH_OP_EVAL, int(n.max()), int(m.max()), 0))
+    no, po = c["node_off"], c["pt_off"]
+
+    def loop():
+        for i in range(n.size):
+            fh.evaluate(nodes[no[i]:no[i + 1]], vals[no[i]:no[i + 1]], int(d[i]),
+                        x[po[i]:po[i + 1]], out=r_loop[po[i]:po[i + 1]], ws=ws)
+
+    ms_loop = _time_ms(loop, 1)
+    out["per_instance_loop_fp64"] = {"Gpair_s": pairs / (ms_loop * 1e-3) / 1e9, "ms": ms_loop}
+    out["batched_speedup_vs_loop_fp64"] = ms_loop / out["fp64"]["ms_per_launch"]
+    out["split_batched_speedup_vs_fp64_batched"] = (out["fp64"]["ms_per_launch"]
+                                                    / out["split"]["ms_per_launch"])
+    return out
+
+
+def run_backward_form(dev, reps):
+    """Adjoint of sum_p g_p r(x_p) on the 2049-node, 10^6-point workload:
+    gradients with respect to values, points and nodes."""
+    c = inputs.grad_workload()
+    n, m = c["nodes"].size, c["points"].size
+    nodes, vals, x, g = (_t(c[k], dev) for k in ("nodes", "values", "points", "grad"))
+    ws = fh.Workspace(dev, fh.workspace_size(fh.FH_OP_BACKWARD, n, m, c["d"]))
+    ms_b = _time_ms(lambda: fh.eval_backward(nodes, vals, c["d"], x, g, ws=ws), reps)
+    ms_f = _time_ms(lambda: fh.evaluate(nodes, vals, c["d"], x, ws=ws), reps)
+    return {"workload": f"grad: n={n} equispaced, d={c['d']}, m={m}, g ~ N(0,1)",
+            "fp64": {"backward_ms": ms_b, "forward_ms": ms_f,
+                     "backward_Gpair_s": n * m / (ms_b * 1e-3) / 1e9,
+                     "forward_Gpair_s": n * m / (ms_f * 1e-3) / 1e9}}
+
+
 def copy_calibration():
     """Three copies of 2^27 float64 (1 GiB read + 1 GiB written each)."""
     dev = torch.device("cuda:0")
@@ -242,8 +321,13 @@ def main():
                              **{k: v for k, v in stats.items() if k.startswith("e_")}}
         print("[bench] cpu baseline done", file=sys.stderr, flush=True)
     if not args.no_forms:
-        line["forms"] = {"split_workload": run_split_forms(dev, 5, not args.no_cpu_baseline)}
-        print("[bench] forms done", file=sys.stderr, flush=True)
+        forms = {"split_workload": run_split_forms(dev, 5, not args.no_cpu_baseline)}
+        print("[bench] split form done", file=sys.stderr, flush=True)
+        forms["batched_workload"] = run_batched_form(dev, 3, not args.no_cpu_baseline)
+        print("[bench] batched form done", file=sys.stderr, flush=True)
+        forms["grad_workload"] = run_backward_form(dev, 5)
+        print("[bench] backward form done", file=sys.stderr, flush=True)
+        line["forms"] = forms
     print(json.dumps(line))
 
 

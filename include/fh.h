@@ -186,9 +186,13 @@ fh_status fh_batch_status(fh_batch* b, void* stream, uint32_t* bits_out);
 /* Kernel-variant selection (the autotuner's interface).  Each evaluation
  * kernel exists in several variants: points per lane, node group size of
  * the shared reciprocal, and node split across the waves of a block.  The
- * variant for a call is looked up by (prec, ceil(log2 of n rounded up to 64),
- * ceil(log2 m)) in a per-process table; untuned shapes use a default chosen
- * from the number of waves.  All variants compute the same quantities to the
+ * variant for a call is looked up by (kernel family, ceil(log2 of n rounded
+ * up to 64), ceil(log2 m)) in a per-process table; untuned shapes use a
+ * built-in table measured on MI355X or a size rule.  Kernel families: the
+ * precisions FH_FP64 and FH_FP32_SPLIT for fh_eval / fh_lebesgue, and
+ * FH_TUNE_BATCHED_FP64 / FH_TUNE_BATCHED_SPLIT for fh_batch_create (keyed
+ * by the mean n and the total number of points; read when a batch is
+ * created).  All variants compute the same quantities to the
  * same error bound; they differ in speed and in summation order.
  *   fh_variant_count / fh_variant_shape  enumerate the variants of `prec`;
  *   fh_tune_set    records variant `id` for the shape bucket of (n, m)
@@ -196,6 +200,7 @@ fh_status fh_batch_status(fh_batch* b, void* stream, uint32_t* bits_out);
  *   fh_tune_force  pins variant `id` for every shape (-1 releases it);
  *   fh_tune_get    the variant a call with (n, m) would use now.
  * The table is process-wide and guarded by a mutex. */
+enum { FH_TUNE_BATCHED_FP64 = 2, FH_TUNE_BATCHED_SPLIT = 3 };
 int32_t fh_variant_count(int32_t prec);
 fh_status fh_variant_shape(int32_t prec, int32_t id, int32_t* points_per_lane, int32_t* group,
                            int32_t* node_split);

@@ -1,6 +1,7 @@
 // C ABI of libfh: argument validation, workspace layout, kernel selection and
 // launch.  All device work is enqueued on the caller's stream; nothing here
-// allocates except fh_batch_create.
+// allocates (the batched entry points, which own device memory, are in
+// batched.hip).
 #include <cstdlib>
 #include <cstring>
 
@@ -181,19 +182,6 @@ fh_status fh_eval_backward(const double* nodes, const double* values, int64_t n,
     e = launch_backward(nodes, x, grad_r, n, d, m, t, b, grad_values, m > 0 ? grad_x : nullptr,
                         grad_nodes, s);
   return finish(e, ws, s);
-}
-
-fh_status fh_batch_create(fh_batch** out, int32_t, const int64_t*, const int32_t*,
-                          const int64_t*, const double*, const double*, const double*, double*,
-                          double*, int32_t, void*) {
-  if (out) *out = nullptr;
-  return FH_E_UNSUPPORTED;
-}
-fh_status fh_eval_batched(fh_batch*, void*) { return FH_E_UNSUPPORTED; }
-fh_status fh_batch_destroy(fh_batch*) { return FH_OK; }
-fh_status fh_batch_status(fh_batch*, void*, uint32_t* bits_out) {
-  if (bits_out) *bits_out = 0;
-  return FH_E_UNSUPPORTED;
 }
 
 fh_status fh_device_status(void* ws, void* stream, uint32_t* bits_out) {

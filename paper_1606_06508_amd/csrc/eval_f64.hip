@@ -36,29 +36,6 @@
 
 namespace fhk {
 
-// Exact per-pair evaluation of one point (flagged lanes only).
-template <bool R, bool L>
-__device__ __noinline__ void eval_point_exact(double t, const double* __restrict__ tx,
-                                              const double* __restrict__ tw,
-                                              const double* __restrict__ f, int64_t n,
-                                              double* r_out, double* l_out) {
-  double N = 0.0, D = 0.0, A = 0.0;
-  for (int64_t k = 0; k < n; ++k) {
-    const double del = t - tx[k];
-    if (del == 0.0) {
-      *r_out = R ? f[k] : 0.0;
-      *l_out = 1.0;
-      return;
-    }
-    const double a = tw[k] / del;
-    if (R) N = __builtin_fma(a, f[k], N);
-    D = D + a;
-    if (L) A = A + fabs(a);
-  }
-  *r_out = N / D;
-  *l_out = A / fabs(D);
-}
-
 template <int P, int G, int S, bool R, bool L>
 __global__ void __launch_bounds__(64 * S)
     k_eval_f64(const double* __restrict__ x, int64_t m, const double* __restrict__ tx,
@@ -84,28 +61,7 @@ __global__ void __launch_bounds__(64 * S)
   const int64_t slice = n_pad / S;
   const int64_t k_begin = wave * slice, k_end = k_begin + slice;
 
-  for (int64_t k = k_begin; k < k_end; k += G) {
-    double xk[G], wk[G], vk[G];
-#pragma unroll
-    for (int i = 0; i < G; ++i) {
-      xk[i] = tx[k + i];
-      wk[i] = tw[k + i];
-      vk[i] = R ? twf[k + i] : 0.0;
-    }
-#pragma unroll
-    for (int j = 0; j < P; ++j) {
-      double dl[G], t[G];
-#pragma unroll
-      for (int i = 0; i < G; ++i) dl[i] = xp[j] - xk[i];
-      bad[j] |= group_reciprocals<G>(dl, t);
-#pragma unroll
-      for (int i = 0; i < G; ++i) {
-        D[j] = __builtin_fma(wk[i], t[i], D[j]);
-        if (R) N[j] = __builtin_fma(vk[i], t[i], N[j]);
-        if (L) A[j] = __builtin_fma(fabs(wk[i]), fabs(t[i]), A[j]);
-      }
-    }
-  }
+  accumulate_f64<P, G, R, L>(xp, tx, tw, twf, k_begin, k_end, N, D, A, bad);
 
   if constexpr (S > 1) {
     // fixed-order reduction of the S partial sums through LDS

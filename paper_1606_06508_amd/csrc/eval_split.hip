@@ -26,47 +26,11 @@
 // wave-uniform ds_read_b128 (a broadcast into VGPRs), and |t| and |w| for
 // the Lebesgue sum are taken with an integer and rather than an abs
 // modifier.  Every per-pair operation except the reciprocal is then VOP2.
-#include <cstdint>
-
 #include "fh_internal.h"
+#include "pair_math.h"
+#include "split_math.h"
 
 namespace fhk {
-
-constexpr int kTile = 32;     // binary32 partial-sum length (nodes)
-constexpr int kStage = 256;   // records per LDS stage (= threads per block)
-
-__device__ __forceinline__ bool not_finite32(float v) {
-  return __builtin_amdgcn_classf(v, 0x207);  // NaN or +-inf
-}
-
-// |v| by clearing the sign bit with a VOP2 v_and_b32 against a mask held in
-// a VGPR (an abs modifier, or an and with a known constant that the compiler
-// folds into one, would force the slower VOP3 encoding).
-__device__ __forceinline__ float abs_vop2(float v, uint32_t mask) {
-  return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, v) & mask);
-}
-
-template <bool R, bool L>
-__device__ __noinline__ void eval_point_exact_s(double t, const double* __restrict__ tx,
-                                                const double* __restrict__ tw,
-                                                const double* __restrict__ f, int64_t n,
-                                                double* r_out, double* l_out) {
-  double N = 0.0, D = 0.0, A = 0.0;
-  for (int64_t k = 0; k < n; ++k) {
-    const double del = t - tx[k];
-    if (del == 0.0) {
-      *r_out = R ? f[k] : 0.0;
-      *l_out = 1.0;
-      return;
-    }
-    const double a = tw[k] / del;
-    if (R) N = __builtin_fma(a, f[k], N);
-    D = D + a;
-    if (L) A = A + fabs(a);
-  }
-  *r_out = N / D;
-  *l_out = A / fabs(D);
-}
 
 template <int P, bool R, bool L>
 __global__ void __launch_bounds__(kStage)
@@ -82,7 +46,7 @@ __global__ void __launch_bounds__(kStage)
   const uint32_t mask =
       0x7fffffffu ^ (__builtin_amdgcn_mbcnt_lo(~0u, 0u) & (uint32_t)(n_pad >> 62));
   double xp[P], N[P], D[P], A[P];
-  float xh[P], xl[P], Nt[P], Dt[P], At[P];
+  float xh[P], xl[P];
   bool bad[P];
 #pragma unroll
   for (int j = 0; j < P; ++j) {
@@ -91,70 +55,10 @@ __global__ void __launch_bounds__(kStage)
     xh[j] = (float)xp[j];
     xl[j] = (float)(xp[j] - (double)xh[j]);
     N[j] = D[j] = A[j] = 0.0;
-    Nt[j] = Dt[j] = At[j] = 0.0f;
     bad[j] = false;
   }
 
-  if (tid < n_pad) stage[0][tid] = s4[tid];
-  __syncthreads();
-  int buf = 0;
-  for (int64_t k0 = 0; k0 < n_pad; k0 += kStage) {
-    // prefetch the next stage into the other buffer (last read two stages
-    // ago, released by the barrier that ended the previous stage)
-    const int64_t kn = k0 + kStage + tid;
-    if (kn < n_pad) stage[buf ^ 1][tid] = s4[kn];
-    const int cnt = (int)(n_pad - k0 < kStage ? n_pad - k0 : kStage);  // multiple of 64
-    for (int i0 = 0; i0 < cnt; i0 += kTile) {
-      for (int i = i0; i < i0 + kTile; i += 4) {
-        // four nodes at a time, all their P x 4 pairs independent
-        float4 rc[4];
-        float t[4][P];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) rc[q] = stage[buf][i + q];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-          for (int j = 0; j < P; ++j) t[q][j] = (xh[j] - rc[q].x) + (xl[j] - rc[q].y);
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-          for (int j = 0; j < P; ++j) t[q][j] = __builtin_amdgcn_rcpf(t[q][j]);
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-          for (int j = 0; j < P; ++j) {
-            Dt[j] = __builtin_fmaf(rc[q].z, t[q][j], Dt[j]);
-            if (R) Nt[j] = __builtin_fmaf(rc[q].w, t[q][j], Nt[j]);
-          }
-        if (L) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const float aw = abs_vop2(rc[q].z, mask);
-#pragma unroll
-            for (int j = 0; j < P; ++j) At[j] = __builtin_fmaf(aw, abs_vop2(t[q][j], mask), At[j]);
-          }
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < P; ++j) {
-        bad[j] |= not_finite32(Dt[j]);
-        D[j] += (double)Dt[j];
-        Dt[j] = 0.0f;
-        if (R) {
-          bad[j] |= not_finite32(Nt[j]);
-          N[j] += (double)Nt[j];
-          Nt[j] = 0.0f;
-        }
-        if (L) {
-          bad[j] |= not_finite32(At[j]);
-          A[j] += (double)At[j];
-          At[j] = 0.0f;
-        }
-      }
-    }
-    __syncthreads();
-    buf ^= 1;
-  }
+  split_block_sums<P, R, L>(stage, s4, n_pad, mask, xh, xl, N, D, A, bad);
 
 #pragma unroll
   for (int j = 0; j < P; ++j) {
@@ -162,7 +66,7 @@ __global__ void __launch_bounds__(kStage)
     if (idx >= m) continue;
     double rv, lv;
     if (bad[j]) {
-      eval_point_exact_s<R, L>(xp[j], tx, tw, f, n, &rv, &lv);
+      eval_point_exact<R, L>(xp[j], tx, tw, f, n, &rv, &lv);
     } else {
       rv = N[j] / D[j];
       lv = A[j] / fabs(D[j]);

@@ -49,6 +49,8 @@ int f64_variant_count();
 void f64_variant_shape(int id, int* p, int* g, int* s);
 int split_variant_count();
 void split_variant_shape(int id, int* p, int* g, int* s);
+int batched_variant_count();
+void batched_variant_shape(int id, int* p, int* g, int* s, bool split);
 
 // Adjoint: points are processed in `chunks` chunks of `chunk` points
 // (m_pad = chunks * chunk, the tail padded with neutral records) so that the

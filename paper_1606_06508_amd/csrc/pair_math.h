@@ -54,4 +54,60 @@ __device__ __forceinline__ bool group_reciprocals<8>(const double (&d)[8], doubl
   return not_normal(q);
 }
 
+// Exact per-pair evaluation of one point (flagged lanes only).
+template <bool R, bool L>
+__device__ __noinline__ void eval_point_exact(double t, const double* __restrict__ tx,
+                                              const double* __restrict__ tw,
+                                              const double* __restrict__ f, int64_t n,
+                                              double* r_out, double* l_out) {
+  double N = 0.0, D = 0.0, A = 0.0;
+  for (int64_t k = 0; k < n; ++k) {
+    const double del = t - tx[k];
+    if (del == 0.0) {
+      *r_out = R ? f[k] : 0.0;
+      *l_out = 1.0;
+      return;
+    }
+    const double a = tw[k] / del;
+    if (R) N = __builtin_fma(a, f[k], N);
+    D = D + a;
+    if (L) A = A + fabs(a);
+  }
+  *r_out = N / D;
+  *l_out = A / fabs(D);
+}
+
+// Fused sums of one wave over the node records [k_begin, k_end) (wave-
+// uniform range, a multiple of G): for each of the lane's P points,
+// D += w t, N += (w f) t, A += |w| |t|, with t from group_reciprocals<G>.
+template <int P, int G, bool R, bool L>
+__device__ __forceinline__ void accumulate_f64(const double (&xp)[P], const double* __restrict__ tx,
+                                               const double* __restrict__ tw,
+                                               const double* __restrict__ twf, int64_t k_begin,
+                                               int64_t k_end, double (&N)[P], double (&D)[P],
+                                               double (&A)[P], bool (&bad)[P]) {
+  for (int64_t k = k_begin; k < k_end; k += G) {
+    double xk[G], wk[G], vk[G];
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      xk[i] = tx[k + i];
+      wk[i] = tw[k + i];
+      vk[i] = R ? twf[k + i] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      double dl[G], t[G];
+#pragma unroll
+      for (int i = 0; i < G; ++i) dl[i] = xp[j] - xk[i];
+      bad[j] |= group_reciprocals<G>(dl, t);
+#pragma unroll
+      for (int i = 0; i < G; ++i) {
+        D[j] = __builtin_fma(wk[i], t[i], D[j]);
+        if (R) N[j] = __builtin_fma(vk[i], t[i], N[j]);
+        if (L) A[j] = __builtin_fma(fabs(wk[i]), fabs(t[i]), A[j]);
+      }
+    }
+  }
+}
+
 }  // namespace fhk

@@ -17,7 +17,7 @@ namespace fhk {
 namespace {
 
 std::mutex g_mu;
-int g_force[2] = {-1, -1};
+int g_force[4] = {-1, -1, -1, -1};
 std::unordered_map<int64_t, int> g_table;
 
 int ceil_log2(int64_t v) {
@@ -28,15 +28,22 @@ int ceil_log2(int64_t v) {
 
 int64_t key(int32_t prec, int nb, int mb) { return ((int64_t)prec << 16) | (nb << 8) | mb; }
 
-int variant_count(int32_t prec) {
-  return prec == FH_FP32_SPLIT ? split_variant_count() : f64_variant_count();
+bool valid_family(int32_t fam) { return fam >= FH_FP64 && fam <= FH_TUNE_BATCHED_SPLIT; }
+
+int variant_count(int32_t fam) {
+  switch (fam) {
+    case FH_FP64: return f64_variant_count();
+    case FH_FP32_SPLIT: return split_variant_count();
+    default: return batched_variant_count();
+  }
 }
 
-void shape(int32_t prec, int id, int* p, int* g, int* s) {
-  if (prec == FH_FP32_SPLIT)
-    split_variant_shape(id, p, g, s);
-  else
-    f64_variant_shape(id, p, g, s);
+void shape(int32_t fam, int id, int* p, int* g, int* s) {
+  switch (fam) {
+    case FH_FP64: f64_variant_shape(id, p, g, s); return;
+    case FH_FP32_SPLIT: split_variant_shape(id, p, g, s); return;
+    default: batched_variant_shape(id, p, g, s, fam == FH_TUNE_BATCHED_SPLIT);
+  }
 }
 
 // Built-in table: the autotuner's choices measured on MI355X (gfx950) for
@@ -58,6 +65,7 @@ constexpr Builtin kBuiltin[] = {
 int default_variant(int32_t prec, int nb, int mb) {
   for (const Builtin& b : kBuiltin)
     if (b.prec == prec && b.nb == nb && b.mb == mb) return b.variant;
+  if (prec == FH_TUNE_BATCHED_FP64 || prec == FH_TUNE_BATCHED_SPLIT) return 1;  // P = 2
   if (prec == FH_FP32_SPLIT) return mb <= 16 ? 2 : (mb <= 22 ? 0 : 1);
   return mb <= 16 ? 10 : (mb <= 22 ? 12 : 4);
 }
@@ -87,13 +95,13 @@ using namespace fhk;
 extern "C" {
 
 int32_t fh_variant_count(int32_t prec) {
-  if (prec != FH_FP64 && prec != FH_FP32_SPLIT) return 0;
+  if (!valid_family(prec)) return 0;
   return variant_count(prec);
 }
 
 fh_status fh_variant_shape(int32_t prec, int32_t id, int32_t* points_per_lane, int32_t* group,
                            int32_t* node_split) {
-  if (prec != FH_FP64 && prec != FH_FP32_SPLIT) return FH_E_ARG;
+  if (!valid_family(prec)) return FH_E_ARG;
   if (id < 0 || id >= variant_count(prec) || !points_per_lane || !group || !node_split)
     return FH_E_ARG;
   int p, g, s;
@@ -105,7 +113,7 @@ fh_status fh_variant_shape(int32_t prec, int32_t id, int32_t* points_per_lane, i
 }
 
 fh_status fh_tune_force(int32_t prec, int32_t id) {
-  if (prec != FH_FP64 && prec != FH_FP32_SPLIT) return FH_E_ARG;
+  if (!valid_family(prec)) return FH_E_ARG;
   if (id < -1 || id >= variant_count(prec)) return FH_E_ARG;
   std::lock_guard<std::mutex> lk(g_mu);
   g_force[prec] = id;
@@ -113,7 +121,7 @@ fh_status fh_tune_force(int32_t prec, int32_t id) {
 }
 
 fh_status fh_tune_set(int32_t prec, int64_t n, int64_t m, int32_t id) {
-  if (prec != FH_FP64 && prec != FH_FP32_SPLIT) return FH_E_ARG;
+  if (!valid_family(prec)) return FH_E_ARG;
   if (n < 1 || m < 1 || id < -1 || id >= variant_count(prec)) return FH_E_ARG;
   std::lock_guard<std::mutex> lk(g_mu);
   const int64_t k = key(prec, ceil_log2(round_up(n, kNodePad)), ceil_log2(m));
@@ -125,7 +133,7 @@ fh_status fh_tune_set(int32_t prec, int64_t n, int64_t m, int32_t id) {
 }
 
 int32_t fh_tune_get(int32_t prec, int64_t n, int64_t m) {
-  if (prec != FH_FP64 && prec != FH_FP32_SPLIT) return -1;
+  if (!valid_family(prec)) return -1;
   if (n < 1 || m < 1) return -1;
   return choose_eval_config(prec, n, 0, m, true, true).variant;
 }

@@ -1,0 +1,43 @@
+// Floater-Hormann weight of one node and the node-table checks, shared by
+// the single-interpolant and batched packing kernels.
+//   w_k = sum_{i in J_k} (-1)^i / prod_{j=i..i+d, j!=k} (x_k - x_j),
+//   J_k = { max(0, k-d) <= i <= min(k, n-1-d) }   (Floater & Hormann 2007).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fh.h"
+
+namespace fhk {
+
+// Weight of node k; ORs FH_FLAG_* into *flags.
+__device__ inline double node_weight(const double* __restrict__ x, int64_t n, int32_t d, int64_t k,
+                                     uint32_t* flags) {
+#pragma clang fp contract(off)
+  const double xk = x[k];
+  const int64_t ilo = k - d > 0 ? k - d : 0;
+  const int64_t ihi = k < n - 1 - d ? k : n - 1 - d;
+  double s = 0.0;
+  for (int64_t i = ilo; i <= ihi; ++i) {
+    double prod = 1.0;
+    for (int64_t j = i; j <= i + d; ++j)
+      if (j != k) prod = prod * (xk - x[j]);
+    // a zero, subnormal, infinite or NaN product means the weight cannot be
+    // represented accurately
+    if (!__builtin_isnormal(prod)) *flags |= FH_FLAG_RANGE;
+    double term = 1.0 / prod;
+    if (i & 1) term = -term;
+    s = s + term;
+  }
+  return s;
+}
+
+__device__ inline uint32_t node_checks(const double* __restrict__ x, int64_t n, int64_t k) {
+  uint32_t f = 0;
+  const double xk = x[k];
+  if (!__builtin_isfinite(xk)) f |= FH_FLAG_NONFINITE;
+  if (k + 1 < n && !(xk < x[k + 1])) f |= FH_FLAG_NODES;
+  return f;
+}
+
+}  // namespace fhk

@@ -20,6 +20,11 @@ FH_E_WORKSPACE, FH_E_HIP, FH_E_UNSUPPORTED = 6, 7, 8
 FH_FP64, FH_FP32_SPLIT = 0, 1
 FH_OP_WEIGHTS, FH_OP_EVAL, FH_OP_BACKWARD = 0, 1, 2
 PRECISIONS = {"fp64": FH_FP64, "split": FH_FP32_SPLIT, "fp32_split": FH_FP32_SPLIT}
+FH_TUNE_BATCHED_FP64, FH_TUNE_BATCHED_SPLIT = 2, 3
+# kernel families of the tuner: the two precisions of fh_eval and the two of
+# the batched kernel
+FAMILIES = {**PRECISIONS, "batched_fp64": FH_TUNE_BATCHED_FP64,
+            "batched_split": FH_TUNE_BATCHED_SPLIT}
 
 _lib = None
 _lock = threading.Lock()
@@ -52,8 +57,9 @@ def load():
             "fh_eval_prepared": ([vp, sz, i64, i32, vp, i64, vp, vp, vp], ctypes.c_int),
             "fh_eval_backward": ([vp, vp, i64, i32, vp, i64, vp, vp, vp, vp, i32, vp, sz, vp],
                                  ctypes.c_int),
-            "fh_batch_create": ([ctypes.POINTER(vp), i32, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp],
-                                ctypes.c_int),
+            "fh_batch_create": ([ctypes.POINTER(vp), i32, ctypes.POINTER(i64),
+                                 ctypes.POINTER(i32), ctypes.POINTER(i64), vp, vp, vp, vp, vp, i32,
+                                 vp], ctypes.c_int),
             "fh_eval_batched": ([vp, vp], ctypes.c_int),
             "fh_batch_destroy": ([vp], ctypes.c_int),
             "fh_batch_status": ([vp, vp, ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
@@ -252,10 +258,19 @@ class Prepared:
         return r if want_r else lam
 
 
+def _family(family):
+    if isinstance(family, int):
+        return family
+    try:
+        return FAMILIES[family]
+    except KeyError:
+        raise ValueError(f"kernel family must be one of {sorted(FAMILIES)}") from None
+
+
 def variants(precision="fp64"):
-    """[(id, points_per_lane, group, node_split)] of the evaluation kernel."""
+    """[(id, points_per_lane, group, node_split)] of a kernel family."""
     lib = load()
-    prec = _prec(precision)
+    prec = _family(precision)
     out = []
     for i in range(lib.fh_variant_count(prec)):
         p, g, s = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
@@ -266,12 +281,79 @@ def variants(precision="fp64"):
 
 
 def tune_force(precision, variant):
-    _check(load().fh_tune_force(_prec(precision), int(variant)), "fh_tune_force")
+    _check(load().fh_tune_force(_family(precision), int(variant)), "fh_tune_force")
 
 
 def tune_set(precision, n, m, variant):
-    _check(load().fh_tune_set(_prec(precision), int(n), int(m), int(variant)), "fh_tune_set")
+    _check(load().fh_tune_set(_family(precision), int(n), int(m), int(variant)), "fh_tune_set")
 
 
 def tune_get(precision, n, m):
-    return int(load().fh_tune_get(_prec(precision), int(n), int(m)))
+    return int(load().fh_tune_get(_family(precision), int(n), int(m)))
+
+
+class Batch:
+    """Many interpolants of uneven n and d evaluated by one graph launch
+    (fh_batch_create / fh_eval_batched).
+
+    n, d, m: host integer sequences (per instance); nodes_cat, values_cat,
+    x_cat: device float64 tensors concatenated in instance order (CSR).
+    The output tensors are allocated here unless given; the batch keeps
+    references to every tensor it was created with, which must not be
+    resized or moved while the batch lives."""
+
+    def __init__(self, n, d, m, nodes_cat, values_cat, x_cat, *, lebesgue=False,
+                 want_r=True, precision="fp64", r_out=None, lambda_out=None, stream=None):
+        import numpy as np
+        lib = load()
+        self._n = np.ascontiguousarray(np.asarray(n, dtype=np.int64))
+        self._d = np.ascontiguousarray(np.asarray(d, dtype=np.int32))
+        self._m = np.ascontiguousarray(np.asarray(m, dtype=np.int64))
+        if not (self._n.size == self._d.size == self._m.size):
+            raise ValueError("n, d and m must have one entry per instance")
+        self.nodes, self.values = _f64(nodes_cat, "nodes_cat"), _f64(values_cat, "values_cat")
+        self.x = _f64(x_cat, "x_cat")
+        if self.nodes.numel() != int(self._n.sum()) or self.values.numel() != self.nodes.numel():
+            raise ValueError("nodes_cat / values_cat must hold sum(n) entries")
+        if self.x.numel() != int(self._m.sum()):
+            raise ValueError("x_cat must hold sum(m) entries")
+        self.device = self.x.device
+        self.r = None
+        if want_r:
+            self.r = torch.empty_like(self.x) if r_out is None else _f64(r_out, "r_out")
+        self.lam = None
+        if lebesgue:
+            self.lam = torch.empty_like(self.x) if lambda_out is None else _f64(lambda_out,
+                                                                                 "lambda_out")
+        self._h = ctypes.c_void_p()
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        st = stream if stream is not None else _stream(self.device)
+        _check(lib.fh_batch_create(ctypes.byref(self._h), int(self._n.size),
+                                   self._n.ctypes.data_as(i64p), self._d.ctypes.data_as(i32p),
+                                   self._m.ctypes.data_as(i64p), _ptr(self.nodes),
+                                   _ptr(self.values), _ptr(self.x), _ptr(self.r), _ptr(self.lam),
+                                   _prec(precision), st), "fh_batch_create")
+
+    def __call__(self):
+        _check(load().fh_eval_batched(self._h, _stream(self.device)), "fh_eval_batched")
+        if self.r is not None and self.lam is not None:
+            return self.r, self.lam
+        return self.r if self.r is not None else self.lam
+
+    def status(self):
+        bits = ctypes.c_uint32(0)
+        code = load().fh_batch_status(self._h, _stream(self.device), ctypes.byref(bits))
+        return code, bits.value
+
+    def close(self):
+        if self._h:
+            torch.cuda.synchronize(self.device)
+            load().fh_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

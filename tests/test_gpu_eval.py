@@ -12,9 +12,6 @@ from paper_1606_06508_amd import fh, inputs
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
-# stated bound of the FP32-split form (binary32 terms, tiles of 32 nodes):
-# e_cond(r) and e_rel(Lambda) against the FP64 oracle
-SPLIT_TOL = 4e-6
 
 
 def _t(a):
@@ -118,7 +115,10 @@ def test_node_counts(n):
     nodes = inputs.equispaced(n)
     vals = g.standard_normal(n)
     pts = np.concatenate([g.uniform(-1.2, 1.2, size=3001), nodes])
-    for d in sorted({0, min(2, n - 1), n - 1}):
+    # d = n-1 on many equispaced nodes is polynomial interpolation with a
+    # Lebesgue constant near 2^n: beyond the oracle's own precision (its
+    # compensated D is good to about u|D| + n u^2 L), so the degree is capped
+    for d in sorted({0, min(2, n - 1), min(n - 1, 12)}):
         _check_case(nodes, vals, d, pts, lam_metric="cond")
 
 
@@ -237,7 +237,7 @@ def test_every_kernel_variant(precision):
             if precision == "fp64":
                 metrics.check_fp64(st)
             else:
-                assert st["e_cond_max"] <= SPLIT_TOL and st["e_rel_lam_max"] <= SPLIT_TOL, (vid, st)
+                metrics.check_split(st)
             hit = np.isin(pts, nodes)
             assert np.array_equal(r[hit], vals[np.searchsorted(nodes, pts[hit])]), vid
             assert np.all(lam[hit] == 1.0), vid
