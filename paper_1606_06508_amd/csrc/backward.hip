@@ -140,14 +140,16 @@ __global__ void __launch_bounds__(256)
 }
 
 // ---------------------------------------------------------------- pass 2 --
-// grid: x = node tiles of 64*Q nodes, y = chunks of `chunk` points.
+// grid: x = node tiles of 64*Q nodes, y = groups of four chunks of `chunk`
+// points; wave w of the block takes chunk 4*blockIdx.y + w.
 template <int Q>
-__global__ void __launch_bounds__(64)
-    k_bwd_nodes(const double* __restrict__ rec, int64_t chunk, const double* __restrict__ tx,
-                int64_t n_pad, double* __restrict__ part) {
-  const int lane = threadIdx.x;
+__global__ void __launch_bounds__(256)
+    k_bwd_nodes(const double* __restrict__ rec, int64_t chunk, int64_t chunks,
+                const double* __restrict__ tx, int64_t n_pad, double* __restrict__ part) {
+  const int lane = threadIdx.x & 63;
+  const int64_t c = (int64_t)blockIdx.y * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (c >= chunks) return;
   const int64_t k0 = (int64_t)blockIdx.x * 64 * Q + lane;
-  const int64_t c = blockIdx.y;
   const double* r0 = rec + c * chunk * kRecFields;
   double xk[Q], S1[Q], S2[Q], S3[Q], S4[Q], H1[Q], H2[Q];
 #pragma unroll
@@ -313,8 +315,8 @@ hipError_t launch_backward(const double* nodes, const double* x, const double* g
   k_bwd_points<P><<<g1, 256, 0, s>>>(x, g, m, p.m_pad, t.x, t.w, t.wf, t.f, t.n_pad, n, dx, b.rec);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const dim3 g2((unsigned)((p.n_pad + 64 * p.q - 1) / (64 * p.q)), (unsigned)p.chunks);
-  k_bwd_nodes<1><<<g2, 64, 0, s>>>(b.rec, p.chunk, t.x, t.n_pad, b.part);
+  const dim3 g2((unsigned)((p.n_pad + 64 * p.q - 1) / (64 * p.q)), (unsigned)((p.chunks + 3) / 4));
+  k_bwd_nodes<1><<<g2, 256, 0, s>>>(b.rec, p.chunk, p.chunks, t.x, t.n_pad, b.part);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const dim3 g3((unsigned)((n + 255) / 256));
   k_bwd_reduce<<<g3, 256, 0, s>>>(b.part, p.chunks, p.n_pad, n, t.w, t.f, df, b.dw, b.dxd);

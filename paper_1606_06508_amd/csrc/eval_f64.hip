@@ -5,14 +5,17 @@
 // then r = N / D and Lambda = L / |D| (Floater & Hormann 2007, barycentric
 // form; Lambda is the Lebesgue function sum_k |a_k| / |sum_k a_k|).
 //
-// Mapping.  A block has S waves.  All S waves own the same 64*P points (each
-// lane P of them, strided by 64 so loads and stores coalesce); wave s walks
-// the s-th of S equal slices of the node table, and the S partial sums
-// (N, D, L) are added through LDS in wave order at the end, so the result
-// does not depend on timing.  S > 1 multiplies the number of waves for a
-// given point count (small point sets would otherwise leave SIMDs idle);
-// P > 1 gives each wave independent chains to hide latency.  Node records
-// are wave-uniform: they arrive through scalar loads as SGPR operands.
+// Mapping.  A block has four waves, in 4/S groups of S waves.  The S waves
+// of a group own the same 64*P points (each lane P of them, strided by 64
+// so loads and stores coalesce); wave s of the group walks the s-th of S
+// equal slices of the node table, and the S partial sums (N, D, L) are
+// added through LDS in wave order at the end, so the result does not depend
+// on timing.  S > 1 multiplies the number of waves for a given point count
+// (small point sets would otherwise leave SIMDs idle); P > 1 gives each wave
+// independent chains to hide latency.  Blocks are always 256 threads: with
+// one-wave blocks the per-CU workgroup limit, not registers, would cap the
+// resident waves.  Node records are wave-uniform: they arrive through
+// scalar loads as SGPR operands.
 //
 // Reciprocals.  A division costs far more than a multiply (the paper's
 // premise for preferring scaling to quotients).  On gfx950 v_rcp_f64 is a
@@ -37,15 +40,17 @@
 namespace fhk {
 
 template <int P, int G, int S, bool R, bool L>
-__global__ void __launch_bounds__(64 * S)
+__global__ void __launch_bounds__(256)
     k_eval_f64(const double* __restrict__ x, int64_t m, const double* __restrict__ tx,
                const double* __restrict__ tw, const double* __restrict__ twf, int64_t n_pad,
                const double* __restrict__ f, int64_t n, double* __restrict__ r,
                double* __restrict__ lam) {
+  constexpr int PG = 4 / S;  // point groups per block
   const int lane = threadIdx.x & 63;
   // wave index, made provably wave-uniform so node loads stay scalar
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t base = (int64_t)blockIdx.x * 64 * P + lane;
+  const int slice = wave % S, pg = wave / S;
+  const int64_t base = ((int64_t)blockIdx.x * PG + pg) * 64 * P + lane;
   double xp[P], N[P], D[P], A[P];
   bool bad[P];
 #pragma unroll
@@ -58,34 +63,34 @@ __global__ void __launch_bounds__(64 * S)
     bad[j] = false;
   }
   // node slice of this wave (n_pad is a multiple of 64, hence of S * G)
-  const int64_t slice = n_pad / S;
-  const int64_t k_begin = wave * slice, k_end = k_begin + slice;
+  const int64_t slice_len = n_pad / S;
+  const int64_t k_begin = slice * slice_len, k_end = k_begin + slice_len;
 
   accumulate_f64<P, G, R, L>(xp, tx, tw, twf, k_begin, k_end, N, D, A, bad);
 
   if constexpr (S > 1) {
-    // fixed-order reduction of the S partial sums through LDS
-    __shared__ double red[S - 1][3][64 * P];
-    __shared__ int redbad[S - 1][64 * P];
-    if (wave > 0) {
+    // fixed-order reduction of the S partial sums of each group through LDS
+    __shared__ double red[PG][S - 1][3][64 * P];
+    __shared__ int redbad[PG][S - 1][64 * P];
+    if (slice > 0) {
 #pragma unroll
       for (int j = 0; j < P; ++j) {
-        red[wave - 1][0][j * 64 + lane] = N[j];
-        red[wave - 1][1][j * 64 + lane] = D[j];
-        red[wave - 1][2][j * 64 + lane] = A[j];
-        redbad[wave - 1][j * 64 + lane] = bad[j];
+        red[pg][slice - 1][0][j * 64 + lane] = N[j];
+        red[pg][slice - 1][1][j * 64 + lane] = D[j];
+        red[pg][slice - 1][2][j * 64 + lane] = A[j];
+        redbad[pg][slice - 1][j * 64 + lane] = bad[j];
       }
     }
     __syncthreads();
-    if (wave > 0) return;
+    if (slice > 0) return;
 #pragma unroll
     for (int s = 0; s < S - 1; ++s) {
 #pragma unroll
       for (int j = 0; j < P; ++j) {
-        N[j] += red[s][0][j * 64 + lane];
-        D[j] += red[s][1][j * 64 + lane];
-        A[j] += red[s][2][j * 64 + lane];
-        bad[j] |= redbad[s][j * 64 + lane] != 0;
+        N[j] += red[pg][s][0][j * 64 + lane];
+        D[j] += red[pg][s][1][j * 64 + lane];
+        A[j] += red[pg][s][2][j * 64 + lane];
+        bad[j] |= redbad[pg][s][j * 64 + lane] != 0;
       }
     }
   }
@@ -109,8 +114,8 @@ __global__ void __launch_bounds__(64 * S)
 template <int P, int G, int S>
 static hipError_t launch_v(const double* x, int64_t m, const NodeTable& t, int64_t n, double* r,
                            double* lam, hipStream_t s) {
-  const int64_t per = 64LL * P;
-  const dim3 grid((unsigned)((m + per - 1) / per)), block(64 * S);
+  const int64_t per = 64LL * P * (4 / S);  // points per block
+  const dim3 grid((unsigned)((m + per - 1) / per)), block(256);
   if (r && lam)
     k_eval_f64<P, G, S, true, true><<<grid, block, 0, s>>>(x, m, t.x, t.w, t.wf, t.n_pad, t.f, n,
                                                            r, lam);

@@ -54,9 +54,9 @@ struct Builtin {
   int variant;
 };
 constexpr Builtin kBuiltin[] = {
-    {FH_FP64, 6, 14, 7},   {FH_FP64, 10, 20, 12},  {FH_FP64, 12, 20, 9},  {FH_FP64, 13, 24, 4},
-    {FH_FP32_SPLIT, 6, 14, 2}, {FH_FP32_SPLIT, 10, 20, 0}, {FH_FP32_SPLIT, 12, 20, 1},
-    {FH_FP32_SPLIT, 13, 24, 1},
+    {FH_FP64, 6, 14, 7},       {FH_FP64, 10, 20, 12},      {FH_FP64, 12, 20, 10},
+    {FH_FP64, 13, 24, 4},      {FH_FP32_SPLIT, 6, 14, 1},  {FH_FP32_SPLIT, 10, 20, 0},
+    {FH_FP32_SPLIT, 12, 20, 0}, {FH_FP32_SPLIT, 13, 24, 1},
 };
 
 // Untuned shapes: small point sets split the node range over the waves of a
