@@ -41,16 +41,20 @@ from paper_1606_06508_amd import fh, inputs  # noqa: E402
 FP64_PEAK_TFLOPS = 78.6       # MI355X FP64 vector, published
 FLOPS_PER_PAIR_RL = 7         # sub, div, mul+add (N), add (D), add (L)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_eval_f64_sines.json")
-EVAL_SRC = os.path.join(ROOT, "paper_1606_06508_amd", "csrc", "eval_f64.hip")
+EVAL_SRC = [os.path.join(ROOT, "paper_1606_06508_amd", "csrc", f)
+            for f in ("eval_f64.hip", "pair_math.h")]
 
 
 def _t(a, dev):
     return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
 
 
-def _src_hash(path):
-    with open(path, "rb") as fh_:
-        return hashlib.sha256(fh_.read()).hexdigest()[:16]
+def _src_hash(paths):
+    h = hashlib.sha256()
+    for path in paths:
+        with open(path, "rb") as fh_:
+            h.update(fh_.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(n_launch_pairs):
@@ -61,7 +65,7 @@ def measured_traffic(n_launch_pairs):
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("eval_f64_src_sha256_16") != _src_hash(EVAL_SRC):
+    if rec.get("src_sha256_16") != _src_hash(EVAL_SRC):
         return None
     return rec.get("hbm_bytes_per_launch")
 
