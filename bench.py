@@ -175,8 +175,11 @@ def run_split_forms(dev, reps, with_cpu):
         r_o, lam_o, s_o = oracle.evaluate(c["nodes"], c["values"], c["d"], c["points"][idx])
         for prec in ("fp64", "split"):
             r, lam = res[prec]
-            st = metrics.parity(r.cpu().numpy()[idx], lam.cpu().numpy()[idx], r_o, lam_o, s_o)
-            out[prec]["max_error_sample4000"] = {k: v for k, v in st.items() if k.startswith("e_")}
+            st = metrics.parity(r.cpu().numpy()[idx], lam.cpu().numpy()[idx], r_o, lam_o, s_o,
+                                metrics.FP64_LAMBDA_MAX if prec == "fp64"
+                                else metrics.SPLIT_LAMBDA_MAX)
+            out[prec]["max_error_sample4000"] = {k: v for k, v in st.items()
+                                                 if k.startswith(("e_", "n_beyond"))}
     out["workload"] = f"split: n={n} jittered, d={c['d']}, m={m} (10% within 1e-8 of a node)"
     return out
 
@@ -217,13 +220,15 @@ def run_batched_form(dev, reps, with_cpu):
                 ns = slice(int(c["node_off"][i]), int(c["node_off"][i + 1]))
                 p0, p1 = int(c["pt_off"][i]), int(c["pt_off"][i + 1])
                 sel = np.arange(p0, p1)[g.choice(p1 - p0, min(1000, p1 - p0), replace=False)]
-                r_o, _, s_o = oracle.evaluate(c["nodes"][ns], c["values"][ns], int(d[i]),
-                                              c["points"][sel], lebesgue=True)
+                r_o, lam_o, s_o = oracle.evaluate(c["nodes"][ns], c["values"][ns], int(d[i]),
+                                                  c["points"][sel], lebesgue=True)
                 st = metrics.parity(b.r[torch.from_numpy(sel).to(dev)].cpu().numpy(), None, r_o,
-                                    None, s_o)
+                                    lam_o, s_o)
                 for k, v in st.items():
                     if k.startswith("e_"):
                         worst[k] = max(worst.get(k, 0.0), v)
+                    elif k == "n_beyond_lam_max":
+                        worst[k] = worst.get(k, 0) + v
             out[prec]["max_error_12_instances"] = worst
         b.close()
     ws = fh.Workspace(dev, fh.workspace_size(fh.FH_OP_EVAL, int(n.max()), int(m.max()), 0))
@@ -242,19 +247,37 @@ def run_batched_form(dev, reps, with_cpu):
     return out
 
 
-def run_backward_form(dev, reps):
+def run_backward_form(dev, reps, with_cpu):
     """Adjoint of sum_p g_p r(x_p) on the 2049-node, 10^6-point workload:
-    gradients with respect to values, points and nodes."""
+    gradients with respect to values, points and nodes, binary64 and
+    FP32-split; with_cpu adds the max scaled error of every output against
+    the oracle's adjoint (|path - oracle| / sum of |terms|, see the oracle's
+    error scales)."""
     c = inputs.grad_workload()
     n, m = c["nodes"].size, c["points"].size
     nodes, vals, x, g = (_t(c[k], dev) for k in ("nodes", "values", "points", "grad"))
-    ws = fh.Workspace(dev, fh.workspace_size(fh.FH_OP_BACKWARD, n, m, c["d"]))
-    ms_b = _time_ms(lambda: fh.eval_backward(nodes, vals, c["d"], x, g, ws=ws), reps)
-    ms_f = _time_ms(lambda: fh.evaluate(nodes, vals, c["d"], x, ws=ws), reps)
-    return {"workload": f"grad: n={n} equispaced, d={c['d']}, m={m}, g ~ N(0,1)",
-            "fp64": {"backward_ms": ms_b, "forward_ms": ms_f,
+    out = {"workload": f"grad: n={n} equispaced, d={c['d']}, m={m}, g ~ N(0,1)"}
+    ref = None
+    if with_cpu:
+        from oracle import oracle
+        o = oracle.backward(c["nodes"], c["values"], c["d"], c["points"], c["grad"])
+        sc = oracle.grad_scales(c["nodes"], c["values"], c["d"], c["points"], c["grad"])
+        ref = ((o["d_values"], sc[0]), (o["d_points"], sc[1]), (o["d_nodes"], sc[2]))
+    for prec in ("fp64", "split"):
+        ws = fh.Workspace(dev, fh.workspace_size(fh.FH_OP_BACKWARD, n, m, c["d"], prec))
+        ms_b = _time_ms(lambda: fh.eval_backward(nodes, vals, c["d"], x, g, precision=prec,
+                                                 ws=ws), reps)
+        ms_f = _time_ms(lambda: fh.evaluate(nodes, vals, c["d"], x, precision=prec, ws=ws), reps)
+        out[prec] = {"backward_ms": ms_b, "forward_ms": ms_f,
                      "backward_Gpair_s": n * m / (ms_b * 1e-3) / 1e9,
-                     "forward_Gpair_s": n * m / (ms_f * 1e-3) / 1e9}}
+                     "forward_Gpair_s": n * m / (ms_f * 1e-3) / 1e9}
+        if ref is not None:
+            got = fh.eval_backward(nodes, vals, c["d"], x, g, precision=prec, ws=ws)
+            out[prec]["max_scaled_error"] = {
+                name: float(np.max(np.abs(t.cpu().numpy() - r) / np.maximum(s, 1e-300)))
+                for name, t, (r, s) in zip(("dvalues", "dpoints", "dnodes"), got, ref)}
+    out["split_backward_speedup_vs_fp64"] = out["fp64"]["backward_ms"] / out["split"]["backward_ms"]
+    return out
 
 
 def copy_calibration():
@@ -329,7 +352,7 @@ def main():
         print("[bench] split form done", file=sys.stderr, flush=True)
         forms["batched_workload"] = run_batched_form(dev, 3, not args.no_cpu_baseline)
         print("[bench] batched form done", file=sys.stderr, flush=True)
-        forms["grad_workload"] = run_backward_form(dev, 5)
+        forms["grad_workload"] = run_backward_form(dev, 5, not args.no_cpu_baseline)
         print("[bench] backward form done", file=sys.stderr, flush=True)
         line["forms"] = forms
     print(json.dumps(line))

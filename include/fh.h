@@ -154,6 +154,14 @@ fh_status fh_lebesgue(const double* nodes, int64_t n, int32_t d, const double* x
  * formula r'(x_j) = sum_{k!=j} (w_k/w_j)(f_k - f_j)/(x_j - x_k) (Schneider &
  * Werner 1986), dL/dx_j gets -g_p r'(x_j), and the weights get nothing.
  * Per-node sums over points are reduced in a fixed order (deterministic).
+ * prec = FH_FP32_SPLIT runs the pair terms in binary32 as fh_eval does (node
+ * and point coordinates as binary32 head/tail pairs, weights and the point
+ * factors g_p / D_p scaled by the same power of two, binary32 partial sums
+ * over 32 terms added into binary64); data that leave the binary32 range
+ * (node span outside [2^-20, 2^20], points more than one span outside the
+ * nodes, g_p / D_p beyond 2^+-50 after scaling) take binary64 per-pair
+ * paths, so the split gradients stay within about 2^-17 of the binary64
+ * ones relative to the sums of their terms' magnitudes.
  *   ws  workspace of fh_workspace_size(FH_OP_BACKWARD, n, m, d, prec)      */
 fh_status fh_eval_backward(const double* nodes, const double* values, int64_t n, int32_t d,
                            const double* x, int64_t m, const double* grad_r, double* grad_values,

@@ -348,3 +348,110 @@ int fho_backward(const double* x, const double* f, int64_t n, int32_t d, const d
   free(w);
   return FHO_OK;
 }
+
+/* Error scales of the adjoint: for every gradient component, the sum of
+   the absolute values of its terms, each point's terms weighted by
+   (1 + Lambda(x_p)) (c_p = g_p / D_p is only known to about u (1 + Lambda),
+   D_p having condition number Lambda).  s_df[n], s_dx[m], and s_dn[n] for
+   the total node gradient: the direct terms plus the chain through the
+   weights, sum_k s_dw[k] sum_{i in J_k} |d T_{k,i} / d x_l|.  Plain sums:
+   these are tolerances, not results.  At a hit x_p == x_j: |g_p| goes to
+   s_df[j], and |g_p| sum_{k!=j} |w_k / w_j| |f_k - f_j| / |x_j - x_k| to
+   s_dx[p] and to the direct part of s_dn[j]. */
+int fho_grad_scales(const double* x, const double* f, int64_t n, int32_t d, const double* pts,
+                    int64_t m, const double* g, double* s_df, double* s_dx, double* s_dn,
+                    int32_t nthreads) {
+  int st = check_problem(x, n, d);
+  if (st != FHO_OK) return st;
+  if (f == NULL || m < 0 || (m > 0 && (pts == NULL || g == NULL))) return FHO_E_ARG;
+  double* w = (double*)malloc(sizeof(double) * (size_t)n);
+  if (!w) return FHO_E_ARG;
+  st = fho_weights(x, n, d, w);
+  if (st != FHO_OK) { free(w); return st; }
+  size_t per = (size_t)n * 3;
+  double* acc = (double*)calloc((size_t)FHO_CHUNKS * per, sizeof(double));
+  if (!acc) { free(w); return FHO_E_ARG; }
+
+#ifdef _OPENMP
+  int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+#pragma omp parallel for schedule(static) num_threads(nt)
+#endif
+  for (int c = 0; c < FHO_CHUNKS; ++c) {
+    int64_t p0 = m * c / FHO_CHUNKS, p1 = m * (c + 1) / FHO_CHUNKS;
+    double* a_df = acc + (size_t)c * per;
+    double* a_dw = a_df + n;
+    double* a_dx = a_dw + n;
+    for (int64_t p = p0; p < p1; ++p) {
+      double t = pts[p], gp = fabs(g[p]);
+      if (s_dx) s_dx[p] = 0.0;
+      if (!isfinite(t)) continue;
+      int64_t j = find_hit(x, n, t);
+      if (j >= 0) {
+        double rp = 0.0;
+        for (int64_t k = 0; k < n; ++k)
+          if (k != j) rp += fabs(w[k] / w[j]) * fabs(f[k] - f[j]) / fabs(x[j] - x[k]);
+        a_df[j] += gp;
+        a_dx[j] += gp * rp;
+        if (s_dx) s_dx[p] = gp * rp;
+        continue;
+      }
+      double N = 0.0, D = 0.0, L = 0.0;
+      for (int64_t k = 0; k < n; ++k) {
+        double a = w[k] / (t - x[k]);
+        N += a * f[k];
+        D += a;
+        L += fabs(a);
+      }
+      double rr = fabs(N / D);
+      double cp = gp / fabs(D) * (1.0 + L / fabs(D));
+      double sx = 0.0;
+      for (int64_t k = 0; k < n; ++k) {
+        double q = 1.0 / fabs(t - x[k]);
+        double q2 = q * q;
+        double fr = fabs(f[k]) + rr;
+        a_df[k] += fabs(w[k]) * cp * q;
+        a_dw[k] += cp * q * fr;
+        a_dx[k] += fabs(w[k]) * cp * q2 * fr;
+        sx += fabs(w[k]) * q2 * fr;
+      }
+      if (s_dx) s_dx[p] = cp * sx;
+    }
+  }
+
+  double* sw = (double*)calloc((size_t)n, sizeof(double));
+  if (!sw) { free(acc); free(w); return FHO_E_ARG; }
+  for (int64_t k = 0; k < n; ++k) {
+    double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+    for (int c = 0; c < FHO_CHUNKS; ++c) {
+      const double* b = acc + (size_t)c * per;
+      t0 += b[k];
+      t1 += b[n + k];
+      t2 += b[2 * n + k];
+    }
+    if (s_df) s_df[k] = t0;
+    sw[k] = t1;
+    if (s_dn) s_dn[k] = t2;
+  }
+  free(acc);
+  if (s_dn) {
+    for (int64_t k = 0; k < n; ++k) {
+      int64_t ilo = k - d > 0 ? k - d : 0;
+      int64_t ihi = k < n - 1 - d ? k : n - 1 - d;
+      for (int64_t i = ilo; i <= ihi; ++i) {
+        double prod = 1.0;
+        for (int64_t j = i; j <= i + d; ++j)
+          if (j != k) prod = prod * fabs(x[k] - x[j]);
+        double T = 1.0 / prod, inv = 0.0;
+        for (int64_t l = i; l <= i + d; ++l) {
+          if (l == k) continue;
+          s_dn[l] += sw[k] * T / fabs(x[k] - x[l]);
+          inv += 1.0 / fabs(x[k] - x[l]);
+        }
+        s_dn[k] += sw[k] * T * inv;
+      }
+    }
+  }
+  free(sw);
+  free(w);
+  return FHO_OK;
+}

@@ -18,11 +18,18 @@ Definitions (r_o, Lambda_o, S_o from the oracle; r, Lambda from the path):
                 where Lambda grows like 2^n).
 Exact hits are compared bit-for-bit.
 
-The oracle's own accuracy bounds what any comparison can show: its
-compensated D = sum a_k is good to about u |D| + n u^2 L (L = sum |a_k|), so
-points whose Lambda = L/|D| approaches 1/(n u^2) have no correct digits on
-either side; such shapes (d = n-1 on many equispaced nodes) are not used as
-parity cases.
+Conditioning limit.  Every term a_k = w_k / (x - x_k) carries a rounding
+error of order u |a_k| in any evaluation (the oracle's included; its
+compensation only removes the summation error), so a computed D is off by
+about u L (L = sum |a_k|), i.e. by a relative u Lambda.  The errors above
+are first-order statements: they hold while u Lambda is small, and where
+u Lambda approaches 1 the computed D (and with it r and Lambda) has no
+correct digits on any side.  FH interpolants on strongly non-uniform nodes
+reach that (Chebyshev nodes: Lambda ~ 3e7 at n = 300, d = 6 and up to
+~1e20 at n = 2048, d = 10).  So the bars apply at points whose oracle
+Lambda is at most lam_max: 2^40 for binary64 (u Lambda <= 2^-13) and 2^14
+for the binary32 terms of the split form (about 40 u32 Lambda <= 0.04);
+points beyond it are counted (n_beyond_lam_max), not compared.
 """
 import numpy as np
 
@@ -34,16 +41,30 @@ KAPPA_MAX = 100.0
 # reciprocal and the scaled weight: about 40 u32 = 2.4e-6; the stated bound
 # leaves a factor of about three, 2^-17 (~134 u32).
 SPLIT_TOL = 2.0 ** -17
+FP64_LAMBDA_MAX = 2.0 ** 40
+SPLIT_LAMBDA_MAX = 2.0 ** 14
+# Gradients (adjoint), measured against the sums of the absolute values of
+# each component's terms (grad_scales): binary64 1e-12 (about 10^4 u, room
+# for the plain chunked sums of the kernels against the oracle's compensated
+# ones); FP32-split 2^-17, as for the values (binary32 tile sums of 32 terms).
+GRAD_TOL = 1e-12
+SPLIT_GRAD_TOL = 2.0 ** -17
 
 
-def parity(r, lam, r_o, lam_o, s_o):
-    """Returns a dict of max errors (NaN-consistent points excluded from the
-    maxima; NaN mismatches are counted separately)."""
-    out = {}
+def parity(r, lam, r_o, lam_o, s_o, lam_max=FP64_LAMBDA_MAX):
+    """Returns a dict of max errors over the points whose oracle Lambda is at
+    most lam_max (all points when lam_o is None); NaN-consistent points are
+    excluded from the maxima and NaN mismatches counted separately (over all
+    points)."""
+    out = {"lam_max": float(lam_max)}
+    keep = np.ones(np.shape(r_o if r_o is not None else lam_o), dtype=bool)
+    if lam_o is not None:
+        keep = ~(lam_o > lam_max)            # NaN Lambda is kept (NaN checks)
+        out["n_beyond_lam_max"] = int(np.count_nonzero(~keep))
     if r is not None:
         nan_o, nan_g = np.isnan(r_o), np.isnan(r)
         out["nan_mismatch_r"] = int(np.count_nonzero(nan_o != nan_g))
-        ok = ~nan_o & ~nan_g
+        ok = ~nan_o & ~nan_g & keep
         err = np.abs(r[ok] - r_o[ok])
         s = s_o[ok]
         with np.errstate(divide="ignore", invalid="ignore"):
@@ -58,7 +79,7 @@ def parity(r, lam, r_o, lam_o, s_o):
     if lam is not None:
         nan_o, nan_g = np.isnan(lam_o), np.isnan(lam)
         out["nan_mismatch_lam"] = int(np.count_nonzero(nan_o != nan_g))
-        ok = ~nan_o & ~nan_g
+        ok = ~nan_o & ~nan_g & keep
         el = np.abs(lam[ok] - lam_o[ok]) / lam_o[ok]
         out["e_rel_lam_max"] = float(el.max()) if el.size else 0.0
         ec = el / (1.0 + lam_o[ok])
@@ -67,7 +88,9 @@ def parity(r, lam, r_o, lam_o, s_o):
 
 
 def check_split(stats, tol=SPLIT_TOL):
-    """Asserts the FP32-split bar on a parity() dict."""
+    """Asserts the FP32-split bar on a parity() dict computed with
+    lam_max <= SPLIT_LAMBDA_MAX."""
+    assert stats["lam_max"] <= SPLIT_LAMBDA_MAX, stats
     assert stats["nan_mismatch_r"] == 0 and stats["nan_mismatch_lam"] == 0, stats
     assert stats["e_cond_max"] <= tol, stats
     assert stats["e_cond_lam_max"] <= tol, stats
@@ -84,3 +107,87 @@ def check_fp64(stats, tol=FP64_TOL, lam_metric="rel"):
         assert stats["nan_mismatch_lam"] == 0, stats
         key = "e_rel_lam_max" if lam_metric == "rel" else "e_cond_lam_max"
         assert stats[key] <= tol, stats
+
+
+# ------------------------------------------------------------ gradients --
+def weight_derivative_abs(x, d):
+    """A[k, l] = sum over the terms of w_k of |d term / d x_l| (dense, small
+    n): the scale of the chain dL/dx_l += sum_k dL/dw_k dw_k/dx_l."""
+    n = x.size
+    A = np.zeros((n, n))
+    for k in range(n):
+        for i in range(max(0, k - d), min(k, n - 1 - d) + 1):
+            win = [j for j in range(i, i + d + 1) if j != k]
+            T = 1.0 / np.prod([x[k] - x[j] for j in win]) if win else 1.0
+            for l in win:
+                A[k, l] += abs(T / (x[k] - x[l]))
+            A[k, k] += abs(T) * sum(1.0 / abs(x[k] - x[j]) for j in win)
+    return A
+
+
+def grad_scales(nodes, vals, d, pts, g):
+    """Sums of the absolute values of the terms of every gradient component
+    (s_df[n], s_dx[m], s_dxd[n] for dL/dx_k at fixed weights, s_dw[n]).
+
+    Every term carries c_p = g_p / D_p, and D_p = sum_k a_pk has condition
+    number Lambda(x_p), so c_p is only known to about u (1 + Lambda(x_p)):
+    each point's terms are weighted by that factor.  Exact hits contribute
+    |g_p| to dL/df_j and |g_p| sum_k |w_k/w_j| |f_k - f_j| / |x_j - x_k| to
+    dL/dx_p and dL/dx_j."""
+    from . import oracle
+    w = oracle.weights(nodes, d)
+    r, lam, _ = oracle.evaluate(nodes, vals, d, pts, scale=False)
+    ok = np.isfinite(pts) & ~np.isin(pts, nodes)
+    s_df = np.zeros(nodes.size)
+    s_dw = np.zeros(nodes.size)
+    s_dxd = np.zeros(nodes.size)
+    s_dx = np.zeros(pts.size)
+    idx = np.flatnonzero(ok)
+    for lo in range(0, idx.size, 2000):
+        sel = idx[lo:lo + 2000]
+        T = 1.0 / (pts[sel, None] - nodes[None, :])
+        D = (w[None, :] * T).sum(1)
+        c = np.abs(g[sel] / D) * (1.0 + lam[sel])
+        rr = np.abs(r[sel])
+        s_df += np.abs(w) * (c[:, None] * np.abs(T)).sum(0)
+        s_dw += (c[:, None] * np.abs(T) * (np.abs(vals)[None, :] + rr[:, None])).sum(0)
+        T2 = T * T
+        s_dxd += np.abs(w) * (c[:, None] * T2 * (np.abs(vals)[None, :] + rr[:, None])).sum(0)
+        s_dx[sel] = c * (np.abs(w)[None, :] * T2 * (rr[:, None] + np.abs(vals)[None, :])).sum(1)
+    for p in np.flatnonzero(np.isin(pts, nodes)):
+        j = int(np.searchsorted(nodes, pts[p]))
+        others = np.arange(nodes.size) != j
+        rp_abs = np.sum(np.abs(w[others] / w[j]) * np.abs(vals[others] - vals[j])
+                        / np.abs(nodes[j] - nodes[others]))
+        s_df[j] += abs(g[p])
+        s_dx[p] = abs(g[p]) * rp_abs
+        s_dxd[j] += abs(g[p]) * rp_abs
+    return s_df, s_dx, s_dxd, s_dw
+
+
+def grad_errors(gv, gx, gn, o, scales, nodes=None, d=None):
+    """Max of |path - oracle| / scale per gradient (the node gradient only
+    when nodes and d are given: its scale adds the dense weight chain).
+    NaN patterns of dL/dx must agree (counted in nan_mismatch_dx)."""
+    s_df, s_dx, s_dxd, s_dw = scales
+    tiny = 1e-300
+    out = {}
+    if gv is not None:
+        out["dvalues"] = float(np.max(np.abs(gv - o["d_values"]) / (s_df + tiny)))
+    if gx is not None:
+        fin = np.isfinite(o["d_points"])
+        out["nan_mismatch_dx"] = int(np.count_nonzero(np.isfinite(gx) != fin))
+        out["dpoints"] = float(np.max(np.abs(gx[fin] - o["d_points"][fin]) / (s_dx[fin] + tiny))
+                               if np.any(fin) else 0.0)
+    if gn is not None and nodes is not None:
+        s_dn = s_dxd + weight_derivative_abs(nodes, d).T @ s_dw
+        out["dnodes"] = float(np.max(np.abs(gn - o["d_nodes"]) / (s_dn + tiny)))
+    return out
+
+
+def check_grad(errors, tol=GRAD_TOL):
+    """Asserts a grad_errors() dict against tol."""
+    assert errors.get("nan_mismatch_dx", 0) == 0, errors
+    for k in ("dvalues", "dpoints", "dnodes"):
+        if k in errors:
+            assert errors[k] <= tol, errors

@@ -42,8 +42,10 @@ def _load():
         lib.fho_weights.argtypes = [dp, i64, i32, dp]
         lib.fho_eval.argtypes = [dp, dp, i64, i32, dp, dp, i64, dp, dp, dp, i32, i32]
         lib.fho_backward.argtypes = [dp, dp, i64, i32, dp, i64, dp, dp, dp, dp, dp, i32]
+        lib.fho_grad_scales.argtypes = [dp, dp, i64, i32, dp, i64, dp, dp, dp, dp, i32]
         lib.fho_threads.argtypes = [i32]
-        for fn in (lib.fho_weights, lib.fho_eval, lib.fho_backward, lib.fho_threads):
+        for fn in (lib.fho_weights, lib.fho_eval, lib.fho_backward, lib.fho_grad_scales,
+                   lib.fho_threads):
             fn.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -99,6 +101,17 @@ def backward(nodes, values, d, pts, grad, nthreads=0):
     if st:
         raise OracleError(st)
     return {"d_values": df, "d_points": dp, "d_weights": dw, "d_nodes": dx}
+
+
+def grad_scales(nodes, values, d, pts, grad, nthreads=0):
+    """Error scales of the adjoint (fho_grad_scales): (s_df, s_dx, s_dn)."""
+    x, f, t, g = _f64(nodes), _f64(values), _f64(pts), _f64(grad)
+    s_df, s_dn, s_dx = np.empty_like(x), np.empty_like(x), np.empty_like(t)
+    st = _load().fho_grad_scales(_p(x), _p(f), x.size, int(d), _p(t), t.size, _p(g), _p(s_df),
+                                 _p(s_dx), _p(s_dn), int(nthreads))
+    if st:
+        raise OracleError(st)
+    return s_df, s_dx, s_dn
 
 
 def threads(nthreads=0):

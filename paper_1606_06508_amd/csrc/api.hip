@@ -77,7 +77,7 @@ size_t fh_workspace_size(int32_t op, int64_t n, int64_t m, int32_t d, int32_t pr
     case FH_OP_EVAL: return layout_tables(nullptr, n, &t);
     case FH_OP_BACKWARD: {
       BackwardBufs b;
-      return layout_backward(nullptr, n, m, &t, &b);
+      return layout_backward(nullptr, n, m, prec == FH_FP32_SPLIT, &t, &b);
     }
     default: return 0;
   }
@@ -123,7 +123,8 @@ fh_status fh_eval_prepared(void* ws, size_t ws_bytes, int64_t n, int32_t prec, c
   const EvalConfig cfg =
       choose_eval_config(prec, n, 0, m, r_out != nullptr, lambda_out != nullptr);
   const hipError_t e = prec == FH_FP32_SPLIT
-                           ? launch_eval_split(x, m, t, n, r_out, lambda_out, cfg, s)
+                           ? launch_eval_split(x, m, t, n, static_cast<int32_t*>(ws) + 1,
+                                               r_out, lambda_out, cfg, s)
                            : launch_eval_f64(x, m, t, n, r_out, lambda_out, cfg, s);
   return finish(e, ws, s);
 }
@@ -170,17 +171,18 @@ fh_status fh_eval_backward(const double* nodes, const double* values, int64_t n,
   if (values == nullptr || m < 0 || (m > 0 && (x == nullptr || grad_r == nullptr)))
     return FH_E_ARG;
   if (prec != FH_FP64 && prec != FH_FP32_SPLIT) return FH_E_ARG;
-  if (prec == FH_FP32_SPLIT) return FH_E_UNSUPPORTED;
   st = check_ws(ws, ws_bytes, fh_workspace_size(FH_OP_BACKWARD, n, m, d, prec));
   if (st != FH_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   NodeTable t;
   BackwardBufs b;
-  layout_backward(ws, n, m, &t, &b);
-  hipError_t e = launch_pack(nodes, values, nullptr, n, d, t, false, static_cast<uint32_t*>(ws), s);
+  const bool split = prec == FH_FP32_SPLIT;
+  layout_backward(ws, n, m, split, &t, &b);
+  uint32_t* status = static_cast<uint32_t*>(ws);
+  hipError_t e = launch_pack(nodes, values, nullptr, n, d, t, split, status, s);
   if (e == hipSuccess)
-    e = launch_backward(nodes, x, grad_r, n, d, m, t, b, grad_values, m > 0 ? grad_x : nullptr,
-                        grad_nodes, s);
+    e = launch_backward(nodes, x, grad_r, n, d, m, t, b, reinterpret_cast<int32_t*>(status) + 1,
+                        grad_values, m > 0 ? grad_x : nullptr, grad_nodes, s);
   return finish(e, ws, s);
 }
 

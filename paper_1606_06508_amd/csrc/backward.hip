@@ -29,13 +29,12 @@
 //   3. per node: fixed-order sum of the chunk partials, then dL/df, dL/dw and
 //      the direct dL/dx_k;
 //   4. per node: the weight chain (O(d^3) per node), total dL/dx_k.
+#include "bwd_math.h"
 #include "fh_internal.h"
 #include "pair_math.h"
+#include "split_math.h"
 
 namespace fhk {
-
-constexpr int kRecFields = 5;   // pass-2 point record: x, c, c r, g_hit, g_hit r'
-constexpr int kPartFields = 6;  // S1, S2, S3, S4, H1 (sum g_hit), H2 (sum g_hit r')
 
 // ---------------------------------------------------------------- pass 1 --
 template <int P>
@@ -104,35 +103,7 @@ __global__ void __launch_bounds__(256)
       dxp = c * (r * E[j] - F[j]);
     } else {
       // pair-by-pair: exact hit or extreme range
-      int64_t hit = -1;
-      double n2 = 0.0, d2 = 0.0, e2 = 0.0, f2 = 0.0;
-      for (int64_t k = 0; k < n; ++k) {
-        const double del = t - tx[k];
-        if (del == 0.0) {
-          hit = k;
-          break;
-        }
-        const double a = tw[k] / del;
-        const double q = 1.0 / del;
-        d2 += a;
-        n2 = __builtin_fma(a, tf[k], n2);
-        e2 = __builtin_fma(a, q, e2);
-        f2 = __builtin_fma(a * tf[k], q, f2);
-      }
-      if (hit >= 0) {
-        const double wj = tw[hit], fj = tf[hit], xj = tx[hit];
-        double rp = 0.0;
-        for (int64_t k = 0; k < n; ++k)
-          if (k != hit) rp += (tw[k] / wj) * (tf[k] - fj) / (xj - tx[k]);
-        dxp = gp * rp;
-        hg = gp;
-        hgr = gp * rp;
-      } else {
-        const double r = n2 / d2;
-        c = gp / d2;
-        cr = c * r;
-        dxp = c * (r * e2 - f2);
-      }
+      bwd_point_exact(t, gp, tx, tw, tf, n, &dxp, &c, &cr, &hg, &hgr);
     }
     if (dx) dx[idx] = dxp;
     out[0] = xr; out[1] = c; out[2] = cr; out[3] = hg; out[4] = hgr;
@@ -184,19 +155,8 @@ __global__ void __launch_bounds__(256)
         }
       } else {
         // pair by pair: a zero difference is a hit on this node
-        for (int i = 0; i < 4; ++i) {
-          if (dl[i] == 0.0) {
-            H1[q] += pr[i * kRecFields + 3];
-            H2[q] += pr[i * kRecFields + 4];
-          } else {
-            const double ti = 1.0 / dl[i];
-            const double t2 = ti * ti;
-            S1[q] = __builtin_fma(pc[i], ti, S1[q]);
-            S2[q] = __builtin_fma(pcr[i], ti, S2[q]);
-            S3[q] = __builtin_fma(pc[i], t2, S3[q]);
-            S4[q] = __builtin_fma(pcr[i], t2, S4[q]);
-          }
-        }
+        for (int i = 0; i < 4; ++i)
+          bwd_pair_exact(pr + i * kRecFields, xk[q], S1[q], S2[q], S3[q], S4[q], H1[q], H2[q]);
       }
     }
   }
@@ -215,21 +175,27 @@ __global__ void __launch_bounds__(256)
 }
 
 // ---------------------------------------------------------------- pass 3 --
+// The S sums may carry a common factor 2^e (the precision-split passes run
+// with c_p scaled by the weight scale 2^e, see backward_split.hip; e = 0
+// when scale_exp is null): dL/df = w 2^-e S1 + H1, dL/dw = 2^-e (f S1 - S2),
+// dL/dx_k|w = w 2^-e (f S3 - S4) - H2.  Scaling by a power of two is exact.
 __global__ void __launch_bounds__(256)
     k_bwd_reduce(const double* __restrict__ part, int64_t chunks, int64_t n_pad, int64_t n,
                  const double* __restrict__ tw, const double* __restrict__ tf,
-                 double* __restrict__ df, double* __restrict__ dw, double* __restrict__ dxd) {
+                 const int32_t* __restrict__ scale_exp, double* __restrict__ df,
+                 double* __restrict__ dw, double* __restrict__ dxd) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
+  const int e = scale_exp ? *scale_exp : 0;
   double s[kPartFields] = {0, 0, 0, 0, 0, 0};
   for (int64_t c = 0; c < chunks; ++c) {
     const double* pc = part + c * kPartFields * n_pad;
 #pragma unroll
     for (int v = 0; v < kPartFields; ++v) s[v] += pc[v * n_pad + k];
   }
-  const double w = tw[k], f = tf[k];
+  const double w = ldexp(tw[k], -e), f = tf[k];
   if (df) df[k] = w * s[0] + s[4];
-  dw[k] = f * s[0] - s[1];
+  dw[k] = ldexp(f * s[0] - s[1], -e);
   dxd[k] = w * (f * s[2] - s[3]) - s[5];
 }
 
@@ -271,55 +237,71 @@ __global__ void __launch_bounds__(256)
 }
 
 // ------------------------------------------------------------- launcher --
-BackwardPlan plan_backward(int64_t n, int64_t m) {
+BackwardPlan plan_backward(int64_t n, int64_t m, bool split) {
   BackwardPlan p;
   p.n_pad = round_up(n, kNodePad);
-  p.q = 1;
-  const int64_t node_waves = (p.n_pad + 64 * p.q - 1) / (64 * p.q);
+  p.split = split;
+  // binary64: waves of 64 nodes x one chunk; split: blocks of 256 q nodes
+  // sharing one chunk staged in LDS
+  p.q = split && p.n_pad >= 4096 ? 2 : 1;
+  const int64_t node_waves = split ? 4 * ((p.n_pad + 256 * p.q - 1) / (256 * p.q))
+                                   : (p.n_pad + 64 * p.q - 1) / (64 * p.q);
+  const int64_t align = split ? kTile : 4;
   // enough (node tile, chunk) waves to fill the chip, chunks of >= 256 points
   int64_t chunks = (8192 + node_waves - 1) / node_waves;
   const int64_t max_chunks = (m + 255) / 256;
   if (chunks > max_chunks) chunks = max_chunks;
   if (chunks < 1) chunks = 1;
-  p.chunk = round_up((m + chunks - 1) / chunks, 4);
-  if (p.chunk < 4) p.chunk = 4;
+  p.chunk = round_up((m + chunks - 1) / chunks, align);
+  if (p.chunk < align) p.chunk = align;
   p.chunks = (m + p.chunk - 1) / p.chunk;
   if (p.chunks < 1) p.chunks = 1;
   p.m_pad = p.chunks * p.chunk;
   return p;
 }
 
-size_t layout_backward(void* ws, int64_t n, int64_t m, NodeTable* t, BackwardBufs* b) {
+size_t layout_backward(void* ws, int64_t n, int64_t m, bool split, NodeTable* t,
+                       BackwardBufs* b) {
   size_t off = layout_tables(ws, n, t);
-  const BackwardPlan p = plan_backward(n, m);
+  const BackwardPlan p = plan_backward(n, m, split);
   char* base = static_cast<char*>(ws);
   auto take = [&](size_t bytes) {
     char* q = base ? base + off : nullptr;
     off = align_up(off + bytes);
-    return reinterpret_cast<double*>(q);
+    return q;
   };
   b->plan = p;
-  b->rec = take(sizeof(double) * kRecFields * p.m_pad);
-  b->part = take(sizeof(double) * kPartFields * p.n_pad * p.chunks);
-  b->dw = take(sizeof(double) * p.n_pad);
-  b->dxd = take(sizeof(double) * p.n_pad);
+  b->rec = reinterpret_cast<double*>(take(sizeof(double) * kRecFields * p.m_pad));
+  b->rec32 = split ? reinterpret_cast<float4*>(take(sizeof(float4) * p.m_pad)) : nullptr;
+  b->part = reinterpret_cast<double*>(take(sizeof(double) * kPartFields * p.n_pad * p.chunks));
+  b->dw = reinterpret_cast<double*>(take(sizeof(double) * p.n_pad));
+  b->dxd = reinterpret_cast<double*>(take(sizeof(double) * p.n_pad));
   return off;
 }
 
 hipError_t launch_backward(const double* nodes, const double* x, const double* g, int64_t n,
                            int32_t d, int64_t m, const NodeTable& t, const BackwardBufs& b,
-                           double* df, double* dx, double* dxn, hipStream_t s) {
+                           const int32_t* scale_exp, double* df, double* dx, double* dxn,
+                           hipStream_t s) {
   const BackwardPlan& p = b.plan;
-  constexpr int P = 1;
-  const dim3 g1((unsigned)((p.m_pad + 256 * P - 1) / (256 * P)));
-  k_bwd_points<P><<<g1, 256, 0, s>>>(x, g, m, p.m_pad, t.x, t.w, t.wf, t.f, t.n_pad, n, dx, b.rec);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const dim3 g2((unsigned)((p.n_pad + 64 * p.q - 1) / (64 * p.q)), (unsigned)((p.chunks + 3) / 4));
-  k_bwd_nodes<1><<<g2, 256, 0, s>>>(b.rec, p.chunk, p.chunks, t.x, t.n_pad, b.part);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipError_t e;
+  if (p.split) {
+    e = launch_backward_split_passes(x, g, n, m, t, b, scale_exp, dx, s);
+    if (e != hipSuccess) return e;
+  } else {
+    constexpr int P = 1;
+    const dim3 g1((unsigned)((p.m_pad + 256 * P - 1) / (256 * P)));
+    k_bwd_points<P><<<g1, 256, 0, s>>>(x, g, m, p.m_pad, t.x, t.w, t.wf, t.f, t.n_pad, n, dx,
+                                       b.rec);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const dim3 g2((unsigned)((p.n_pad + 64 * p.q - 1) / (64 * p.q)),
+                  (unsigned)((p.chunks + 3) / 4));
+    k_bwd_nodes<1><<<g2, 256, 0, s>>>(b.rec, p.chunk, p.chunks, t.x, t.n_pad, b.part);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   const dim3 g3((unsigned)((n + 255) / 256));
-  k_bwd_reduce<<<g3, 256, 0, s>>>(b.part, p.chunks, p.n_pad, n, t.w, t.f, df, b.dw, b.dxd);
+  k_bwd_reduce<<<g3, 256, 0, s>>>(b.part, p.chunks, p.n_pad, n, t.w, t.f,
+                                  p.split ? scale_exp : nullptr, df, b.dw, b.dxd);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (dxn) {
     k_bwd_chain<<<g3, 256, 0, s>>>(nodes, n, d, b.dw, b.dxd, dxn);

@@ -38,6 +38,7 @@ namespace fhk {
 struct InstDesc {
   int64_t noff, n, toff, n_pad, poff, m;
   int32_t d, strips;
+  int32_t shift, pad;  // split: ef - e of the instance's table (written by its packing)
 };
 
 constexpr int64_t kBatchPad = 8;
@@ -83,28 +84,17 @@ __global__ void __launch_bounds__(256)
 // one block per instance: exponent of max|w| of that instance, then its
 // binary32 records (see k_pack_split for the scaling argument)
 __global__ void __launch_bounds__(256)
-    k_batch_pack_split(const InstDesc* __restrict__ inst, const double* __restrict__ tx,
+    k_batch_pack_split(InstDesc* __restrict__ inst, const double* __restrict__ tx,
                        const double* __restrict__ tw, const double* __restrict__ twf,
                        float4* __restrict__ s4) {
-  __shared__ double red[256];
+  __shared__ double red[4][256];
   const InstDesc ds = inst[blockIdx.x];
-  double mx = 0.0;
-  for (int64_t k = threadIdx.x; k < ds.n_pad; k += blockDim.x)
-    mx = fmax(mx, fabs(tw[ds.toff + k]));
-  red[threadIdx.x] = mx;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
-    __syncthreads();
-  }
-  int ex = 0;
-  frexp(red[0], &ex);
+  const SplitScale sc =
+      split_table_scale(tx + ds.toff, tw + ds.toff, twf + ds.toff, ds.n, ds.n_pad, red);
+  if (threadIdx.x == 0) inst[blockIdx.x].shift = sc.shift;
   for (int64_t k = threadIdx.x; k < ds.n_pad; k += blockDim.x) {
     const int64_t e = ds.toff + k;
-    const double xk = tx[e];
-    const float hi = (float)xk;
-    s4[e] = make_float4(hi, (float)(xk - (double)hi), (float)ldexp(tw[e], -ex),
-                        (float)ldexp(twf[e], -ex));
+    s4[e] = split_record(tx[e], tw[e], twf[e], sc);
   }
 }
 
@@ -157,7 +147,7 @@ __global__ void __launch_bounds__(256)
       if (bad[j]) {
         eval_point_exact<R, L>(xp[j], tx + ds.toff, tw + ds.toff, tf + ds.toff, ds.n, &rv, &lv);
       } else {
-        rv = N[j] / D[j];
+        rv = ldexp(N[j] / D[j], ds.shift);
         lv = A[j] / fabs(D[j]);
       }
       if (R) r[ds.poff + idx] = rv;
@@ -186,6 +176,7 @@ __global__ void __launch_bounds__(kStage)
     const int64_t strip = __builtin_amdgcn_readfirstlane(it.y);
     const double* px = x + ds.poff;
     const int64_t base = strip * kStage * P + tid;
+    const double x_first = tx[ds.toff], x_last = tx[ds.toff + ds.n - 1];
     double xp[P], N[P], D[P], A[P];
     float xh[P], xl[P];
     bool bad[P];
@@ -196,7 +187,7 @@ __global__ void __launch_bounds__(kStage)
       xh[j] = (float)xp[j];
       xl[j] = (float)(xp[j] - (double)xh[j]);
       N[j] = D[j] = A[j] = 0.0;
-      bad[j] = false;
+      bad[j] = !in_split_domain(xp[j], x_first, x_last);
     }
     split_block_sums<P, R, L>(stage, s4 + ds.toff, ds.n_pad, mask, xh, xl, N, D, A, bad);
 #pragma unroll
@@ -207,7 +198,7 @@ __global__ void __launch_bounds__(kStage)
       if (bad[j]) {
         eval_point_exact<R, L>(xp[j], tx + ds.toff, tw + ds.toff, tf + ds.toff, ds.n, &rv, &lv);
       } else {
-        rv = N[j] / D[j];
+        rv = ldexp(N[j] / D[j], ds.shift);
         lv = A[j] / fabs(D[j]);
       }
       if (R) r[ds.poff + idx] = rv;
@@ -354,6 +345,8 @@ fh_status fh_batch_create(fh_batch** out, int32_t count, const int64_t* n_host,
     ds.poff = poff;
     ds.m = m_host[i];
     ds.strips = (int32_t)((ds.m + strip_pts - 1) / strip_pts);
+    ds.shift = 0;
+    ds.pad = 0;
     toff[i] = total_pad;
     noff += ds.n;
     poff += ds.m;

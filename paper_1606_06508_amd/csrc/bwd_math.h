@@ -1,0 +1,78 @@
+// Binary64 pieces of the adjoint shared by the binary64 and precision-split
+// kernels: the pair-by-pair treatment of one point (exact hits, extreme
+// range) and of one (point, node) pair in the per-node pass.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace fhk {
+
+constexpr int kRecFields = 5;   // pass-2 point record: x, c, c r, g_hit, g_hit r'
+constexpr int kPartFields = 6;  // S1, S2, S3, S4, H1 (sum g_hit), H2 (sum g_hit r')
+
+// Point x (finite) with loss weight gp, nodes tx/tw/tf[0, n), by one IEEE
+// division per pair.  At a hit x == x_j: r = f_j whatever the weights, so
+// the point's weight goes to the hit sums (hg = g, hgr = g r'(x_j), node
+// derivative of Schneider & Werner 1986) and c = c r = 0.  Otherwise
+// c = g / D, c r and dx = c (r E - F) from the plain sums.
+__device__ inline void bwd_point_exact(double x, double gp, const double* __restrict__ tx,
+                                       const double* __restrict__ tw,
+                                       const double* __restrict__ tf, int64_t n, double* dxp,
+                                       double* c, double* cr, double* hg, double* hgr) {
+  int64_t hit = -1;
+  double n2 = 0.0, d2 = 0.0, e2 = 0.0, f2 = 0.0;
+  for (int64_t k = 0; k < n; ++k) {
+    const double del = x - tx[k];
+    if (del == 0.0) {
+      hit = k;
+      break;
+    }
+    const double a = tw[k] / del;
+    const double q = 1.0 / del;
+    d2 += a;
+    n2 = __builtin_fma(a, tf[k], n2);
+    e2 = __builtin_fma(a, q, e2);
+    f2 = __builtin_fma(a * tf[k], q, f2);
+  }
+  if (hit >= 0) {
+    const double wj = tw[hit], fj = tf[hit], xj = tx[hit];
+    double rp = 0.0;
+    for (int64_t k = 0; k < n; ++k)
+      if (k != hit) rp += (tw[k] / wj) * (tf[k] - fj) / (xj - tx[k]);
+    *dxp = gp * rp;
+    *c = 0.0;
+    *cr = 0.0;
+    *hg = gp;
+    *hgr = gp * rp;
+  } else {
+    const double r = n2 / d2;
+    *c = gp / d2;
+    *cr = *c * r;
+    *dxp = *c * (r * e2 - f2);
+    *hg = 0.0;
+    *hgr = 0.0;
+  }
+}
+
+// One (point record pr, node xk) pair of the per-node pass by IEEE
+// division; a zero difference is a hit of the point on this node.
+__device__ inline void bwd_pair_exact(const double* __restrict__ pr, double xk, double& S1,
+                                      double& S2, double& S3, double& S4, double& H1,
+                                      double& H2) {
+  const double dl = pr[0] - xk;
+  if (dl == 0.0) {
+    H1 += pr[3];
+    H2 += pr[4];
+  } else {
+    const double ti = 1.0 / dl;
+    const double t2 = ti * ti;
+    S1 = __builtin_fma(pr[1], ti, S1);
+    S2 = __builtin_fma(pr[2], ti, S2);
+    S3 = __builtin_fma(pr[1], t2, S3);
+    S4 = __builtin_fma(pr[2], t2, S4);
+  }
+}
+
+}  // namespace fhk

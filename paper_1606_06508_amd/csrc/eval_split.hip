@@ -7,15 +7,17 @@
 //    node still get an accurate difference; a plain binary32 difference
 //    would round such points onto the node.
 //  - t = 1/delta with v_rcp_f32 (within one ulp on gfx950, no refinement).
-//  - Weights are the binary64 weights scaled by an exact power of two and
-//    rounded to binary32 (packing kernel); the scale cancels in r and
-//    Lambda.
+//  - Weights w_k and weighted values w_k f_k are the binary64 ones scaled
+//    by exact powers of two 2^-e and 2^-ef and rounded to binary32 (packing
+//    kernel); r = 2^(ef - e) N / D and Lambda = L / |D| restore them exactly.
 //  - Terms and per-tile partial sums (kTile nodes) are binary32; each tile's
 //    partials are added into binary64 accumulators, so the binary32
 //    rounding error grows with the tile length, not with n.
 //  - The quotient r = N / D and Lambda = L / |D| are binary64.
 // A lane whose tile sums are not finite (an exact hit gives t = inf, a NaN
-// point gives NaN, extreme data may overflow binary32) recomputes its point
+// point gives NaN, extreme data may overflow binary32), or whose point lies
+// outside the binary32 domain (more than one node span outside the nodes;
+// a table outside the domain carries NaN weights), recomputes its point
 // with the binary64 per-pair division path and the exact-hit branch.
 //
 // Issue rate.  On gfx950 binary32 add/sub/fmac issue at twice the binary64
@@ -36,9 +38,10 @@ template <int P, bool R, bool L>
 __global__ void __launch_bounds__(kStage)
     k_eval_split(const double* __restrict__ x, int64_t m, const float4* __restrict__ s4,
                  int64_t n_pad, const double* __restrict__ tx, const double* __restrict__ tw,
-                 const double* __restrict__ f, int64_t n, double* __restrict__ r,
-                 double* __restrict__ lam) {
+                 const double* __restrict__ f, int64_t n, const int32_t* __restrict__ scale,
+                 double* __restrict__ r, double* __restrict__ lam) {
   __shared__ float4 stage[2][kStage];
+  const double x_first = tx[0], x_last = tx[n - 1];
   const int tid = threadIdx.x;
   const int64_t base = (int64_t)blockIdx.x * kStage * P + tid;
   // 0x7fffffff in a VGPR, opaque to constant folding: the lane id ANDed with
@@ -55,10 +58,11 @@ __global__ void __launch_bounds__(kStage)
     xh[j] = (float)xp[j];
     xl[j] = (float)(xp[j] - (double)xh[j]);
     N[j] = D[j] = A[j] = 0.0;
-    bad[j] = false;
+    bad[j] = !in_split_domain(xp[j], x_first, x_last);
   }
 
   split_block_sums<P, R, L>(stage, s4, n_pad, mask, xh, xl, N, D, A, bad);
+  const int shift = scale[1];
 
 #pragma unroll
   for (int j = 0; j < P; ++j) {
@@ -68,7 +72,7 @@ __global__ void __launch_bounds__(kStage)
     if (bad[j]) {
       eval_point_exact<R, L>(xp[j], tx, tw, f, n, &rv, &lv);
     } else {
-      rv = N[j] / D[j];
+      rv = ldexp(N[j] / D[j], shift);
       lv = A[j] / fabs(D[j]);
     }
     if (R) r[idx] = rv;
@@ -77,19 +81,19 @@ __global__ void __launch_bounds__(kStage)
 }
 
 template <int P>
-static hipError_t launch_v(const double* x, int64_t m, const NodeTable& t, int64_t n, double* r,
-                           double* lam, hipStream_t s) {
+static hipError_t launch_v(const double* x, int64_t m, const NodeTable& t, int64_t n,
+                           const int32_t* sc, double* r, double* lam, hipStream_t s) {
   const int64_t per = (int64_t)kStage * P;
   const dim3 grid((unsigned)((m + per - 1) / per)), block(kStage);
   if (r && lam)
-    k_eval_split<P, true, true><<<grid, block, 0, s>>>(x, m, t.s, t.n_pad, t.x, t.w, t.f, n, r,
-                                                       lam);
+    k_eval_split<P, true, true><<<grid, block, 0, s>>>(x, m, t.s, t.n_pad, t.x, t.w, t.f, n, sc,
+                                                       r, lam);
   else if (r)
-    k_eval_split<P, true, false><<<grid, block, 0, s>>>(x, m, t.s, t.n_pad, t.x, t.w, t.f, n, r,
-                                                        lam);
+    k_eval_split<P, true, false><<<grid, block, 0, s>>>(x, m, t.s, t.n_pad, t.x, t.w, t.f, n, sc,
+                                                        r, lam);
   else
-    k_eval_split<P, false, true><<<grid, block, 0, s>>>(x, m, t.s, t.n_pad, t.x, t.w, t.f, n, r,
-                                                        lam);
+    k_eval_split<P, false, true><<<grid, block, 0, s>>>(x, m, t.s, t.n_pad, t.x, t.w, t.f, n, sc,
+                                                        r, lam);
   return hipGetLastError();
 }
 
@@ -117,12 +121,13 @@ void split_variant_shape(int id, int* p, int* g, int* s) {
   }
 }
 
-hipError_t launch_eval_split(const double* x, int64_t m, const NodeTable& t, int64_t n, double* r,
-                             double* lam, const EvalConfig& cfg, hipStream_t s) {
+hipError_t launch_eval_split(const double* x, int64_t m, const NodeTable& t, int64_t n,
+                             const int32_t* scale, double* r, double* lam, const EvalConfig& cfg,
+                             hipStream_t s) {
   if (m == 0) return hipSuccess;
   switch (cfg.variant) {
 #define FH_CASE(vid, vp) \
-  case vid: return launch_v<vp>(x, m, t, n, r, lam, s);
+  case vid: return launch_v<vp>(x, m, t, n, scale, r, lam, s);
     FH_SPLIT_VARIANTS(FH_CASE)
 #undef FH_CASE
     default: return hipErrorInvalidValue;

@@ -11,8 +11,9 @@
 namespace fhk {
 
 // The first kStatusBytes of every workspace: word 0 = sticky status bits,
-// word 1 = binary32 scaling exponent e of the split form (max|w| = 2^e * m,
-// 1 <= m < 2), words 2.. reserved.
+// word 1 = binary32 weight scaling exponent e of the split form
+// (max|w| = m 2^e, 1/2 <= m < 1), word 2 = ef - e with 2^ef the scale of
+// the weighted values w f (split_table_scale), words 3.. reserved.
 constexpr size_t kStatusBytes = 256;
 // Node tables are padded to a multiple of this many records; padding
 // records repeat the last node with zero weight, so they add nothing.
@@ -29,7 +30,7 @@ struct NodeTable {
   double* wf;     // [n_pad] w_k * f_k
   double* f;      // [n_pad] f_k (exact-hit branch)
   float4* s;      // [n_pad] split form: {binary32 head of x_k, binary32 tail
-                  // x_k - head, binary32 of w_k 2^-e, binary32 of w_k f_k 2^-e}
+                  // x_k - head, binary32 of w_k 2^-e, binary32 of w_k f_k 2^-ef}
   int64_t n_pad;
 };
 
@@ -57,18 +58,21 @@ void batched_variant_shape(int id, int* p, int* g, int* s, bool split);
 // per-node pass has enough (node tile, chunk) waves.
 struct BackwardPlan {
   int64_t n_pad, chunk, chunks, m_pad;
-  int q;  // nodes per lane in the per-node pass
+  int q;       // nodes per lane in the per-node pass
+  bool split;  // precision-split passes 1 and 2
 };
 struct BackwardBufs {
   BackwardPlan plan;
-  double* rec;   // [m_pad][5] per-point records of pass 1
-  double* part;  // [chunks][6][n_pad] per-chunk node sums
-  double* dw;    // [n_pad] dL/dw_k
-  double* dxd;   // [n_pad] direct dL/dx_k at fixed weights
+  double* rec;    // [m_pad][5] per-point records of pass 1
+  float4* rec32;  // [m_pad] binary32 point records (split only, else null)
+  double* part;   // [chunks][6][n_pad] per-chunk node sums
+  double* dw;     // [n_pad] dL/dw_k
+  double* dxd;    // [n_pad] direct dL/dx_k at fixed weights
 };
-BackwardPlan plan_backward(int64_t n, int64_t m);
+BackwardPlan plan_backward(int64_t n, int64_t m, bool split);
 // Workspace layout of FH_OP_BACKWARD (node tables, then the buffers above).
-size_t layout_backward(void* ws, int64_t n, int64_t m, NodeTable* t, BackwardBufs* b);
+size_t layout_backward(void* ws, int64_t n, int64_t m, bool split, NodeTable* t,
+                       BackwardBufs* b);
 
 // ---- launchers (each returns the launch error, hipSuccess on success) ----
 hipError_t launch_weights(const double* nodes, int64_t n, int32_t d, double* w_out,
@@ -78,10 +82,17 @@ hipError_t launch_pack(const double* nodes, const double* values, const double* 
                        hipStream_t s);
 hipError_t launch_eval_f64(const double* x, int64_t m, const NodeTable& t, int64_t n, double* r,
                            double* lam, const EvalConfig& cfg, hipStream_t s);
+// scale_exp: the split scaling exponent (status word 1) when b.plan.split.
 hipError_t launch_backward(const double* nodes, const double* x, const double* g, int64_t n,
                            int32_t d, int64_t m, const NodeTable& t, const BackwardBufs& b,
-                           double* df, double* dx, double* dxn, hipStream_t s);
-hipError_t launch_eval_split(const double* x, int64_t m, const NodeTable& t, int64_t n, double* r,
-                             double* lam, const EvalConfig& cfg, hipStream_t s);
+                           const int32_t* scale_exp, double* df, double* dx, double* dxn,
+                           hipStream_t s);
+hipError_t launch_backward_split_passes(const double* x, const double* g, int64_t n, int64_t m,
+                                        const NodeTable& t, const BackwardBufs& b,
+                                        const int32_t* scale_exp, double* dx, hipStream_t s);
+// scale: status words 1.. of the workspace (e, ef - e) written by the packing.
+hipError_t launch_eval_split(const double* x, int64_t m, const NodeTable& t, int64_t n,
+                             const int32_t* scale, double* r, double* lam, const EvalConfig& cfg,
+                             hipStream_t s);
 
 }  // namespace fhk

@@ -101,4 +101,123 @@ __device__ __forceinline__ void split_block_sums(float4 (&stage)[2][kStage],
 
 }
 
+// Streams the records src[0, count) (count a multiple of 4) through the
+// block's double-buffered LDS stage, as split_block_sums does: quad(rc) is
+// called for every four consecutive records (rc[4], the same for all lanes:
+// wave-uniform LDS reads), and flush(begin, end) after every kTile records
+// and after the last one, with the record range of that tile.  Must be
+// called by all kStage threads of the block.
+template <class Quad, class Flush>
+__device__ __forceinline__ void staged_tiles(float4 (&stage)[2][kStage],
+                                             const float4* __restrict__ src, int64_t count,
+                                             Quad&& quad, Flush&& flush) {
+  const int tid = threadIdx.x;
+  if (tid < count) stage[0][tid] = src[tid];
+  __syncthreads();
+  int buf = 0;
+  for (int64_t k0 = 0; k0 < count; k0 += kStage) {
+    const int64_t kn = k0 + kStage + tid;
+    if (kn < count) stage[buf ^ 1][tid] = src[kn];
+    const int cnt = (int)(count - k0 < kStage ? count - k0 : kStage);
+    for (int i0 = 0; i0 < cnt; i0 += kTile) {
+      const int iend = i0 + kTile < cnt ? i0 + kTile : cnt;
+      for (int i = i0; i < iend; i += 4) {
+        float4 rc[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rc[q] = stage[buf][i + q];
+        quad(rc);
+      }
+      flush(k0 + i0, k0 + iend);
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+}
+
+// ------------------------------------------------------- binary32 domain --
+// The split node table of one interpolant: {binary32 head of x_k, binary32
+// tail x_k - head, w_k 2^-e, w_k f_k 2^-ef} with 2^e and 2^ef the binary
+// exponents of max|w_k| and max|w_k f_k| (multiplying by a power of two is
+// exact).  The weighted values get their own scale so that the table does
+// not depend on the magnitude of f; the kernels restore it as
+// r = 2^(ef - e) N / D, exactly.
+//
+// The binary32 terms are trusted only inside a domain where every term
+// that matters is a normal binary32 number: node span in [2^-20, 2^20],
+// nonzero |w_k| >= 2^(e - 100) and nonzero finite |w_k f_k| >= 2^(ef - 100)
+// (table), and points no further than one span outside the nodes (point,
+// tested by the kernels), so that |t| >= 2^-21 / 2.  A table outside the
+// domain is written with NaN weights: every point then takes the binary64
+// per-pair path.  Terms of tiny weight that still underflow inside the
+// domain are below 2^-100 of the largest term of their sum.
+constexpr double kSpanMin = 0x1p-20, kSpanMax = 0x1p20;
+constexpr int kWeightRange = 100;
+
+struct SplitScale {
+  int e;      // max|w| = m 2^e, 1/2 <= m < 1
+  int shift;  // ef - e
+  bool ok;    // table inside the binary32 domain
+};
+
+// Block-wide (all threads, blockDim.x == 256) reduction over one table of
+// n real nodes in [0, n_pad); red is a 4 x 256 LDS scratch.
+__device__ inline SplitScale split_table_scale(const double* __restrict__ tx,
+                                               const double* __restrict__ tw,
+                                               const double* __restrict__ twf, int64_t n,
+                                               int64_t n_pad, double (*red)[256]) {
+  const int tid = threadIdx.x;
+  double mxw = 0.0, mxf = 0.0, mnw = __builtin_inf(), mnf = __builtin_inf();
+  for (int64_t k = tid; k < n_pad; k += blockDim.x) {
+    const double aw = fabs(tw[k]), af = fabs(twf[k]);
+    mxw = fmax(mxw, aw);
+    if (aw != 0.0) mnw = fmin(mnw, aw);
+    if (__builtin_isfinite(af)) {
+      mxf = fmax(mxf, af);
+      if (af != 0.0) mnf = fmin(mnf, af);
+    }
+  }
+  red[0][tid] = mxw;
+  red[1][tid] = mxf;
+  red[2][tid] = mnw;
+  red[3][tid] = mnf;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+      red[0][tid] = fmax(red[0][tid], red[0][tid + s]);
+      red[1][tid] = fmax(red[1][tid], red[1][tid + s]);
+      red[2][tid] = fmin(red[2][tid], red[2][tid + s]);
+      red[3][tid] = fmin(red[3][tid], red[3][tid + s]);
+    }
+    __syncthreads();
+  }
+  SplitScale sc;
+  int ef = 0;
+  frexp(red[0][0], &sc.e);
+  frexp(red[1][0], &ef);
+  sc.shift = ef - sc.e;
+  const double span = tx[n - 1] - tx[0];
+  sc.ok = n >= 2 && span >= kSpanMin && span <= kSpanMax &&
+          red[2][0] >= ldexp(1.0, sc.e - kWeightRange) &&
+          red[3][0] >= ldexp(1.0, ef - kWeightRange);
+  __syncthreads();  // red may be reused by the caller
+  return sc;
+}
+
+__device__ inline float4 split_record(double xk, double w, double wf, const SplitScale& sc) {
+  const float hi = (float)xk;
+  const float lo = (float)(xk - (double)hi);
+  if (!sc.ok) {
+    const float nan = __builtin_nanf("");
+    return make_float4(hi, lo, nan, nan);
+  }
+  return make_float4(hi, lo, (float)ldexp(w, -sc.e), (float)ldexp(wf, -(sc.e + sc.shift)));
+}
+
+// A point whose binary32 terms are trusted (also false for NaN): within one
+// node span of [x_first, x_last].
+__device__ __forceinline__ bool in_split_domain(double x, double x_first, double x_last) {
+  const double span = x_last - x_first;
+  return x >= x_first - span && x <= x_last + span;
+}
+
 }  // namespace fhk

@@ -8,6 +8,7 @@
 // with FMA contraction disabled, so the weights are reproducible bit-for-bit
 // on any IEEE machine that follows the same order.
 #include "fh_internal.h"
+#include "split_math.h"
 #include "weight_math.h"
 
 namespace fhk {
@@ -49,35 +50,24 @@ __global__ void __launch_bounds__(256) k_pack(const double* __restrict__ x,
   if (flags) atomicOr(status, flags);
 }
 
-// Split (binary32) node table.  Every block first reduces max|w_k| over the
-// whole table (n is small next to the evaluation; doing it per block avoids
-// a second pass and any atomics), takes its binary exponent e, and stores
-// w_k 2^-e and w_k f_k 2^-e in binary32.  Multiplying by 2^-e is exact
-// (a power of two times a normal number), so the scaled sums differ from the
-// unscaled ones only by the final binary32 rounding; the common factor
-// cancels in r and in Lambda.  x_k is stored as a binary32 head and tail.
+// Split (binary32) node table (split_table_scale / split_record).  Every
+// block reduces the whole table itself (n is small next to the evaluation;
+// doing it per block avoids a second pass and any atomics); block 0 stores
+// e and ef - e in status words 1 and 2.
 __global__ void __launch_bounds__(256) k_pack_split(const double* __restrict__ tx,
                                                     const double* __restrict__ tw,
-                                                    const double* __restrict__ twf, int64_t n_pad,
-                                                    float4* __restrict__ s4, int32_t* exp_out) {
-  __shared__ double red[256];
-  double mx = 0.0;
-  for (int64_t k = threadIdx.x; k < n_pad; k += blockDim.x) mx = fmax(mx, fabs(tw[k]));
-  red[threadIdx.x] = mx;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
-    __syncthreads();
-  }
-  int e = 0;
-  frexp(red[0], &e);  // max|w| = m 2^e, 1/2 <= m < 1
+                                                    const double* __restrict__ twf, int64_t n,
+                                                    int64_t n_pad, float4* __restrict__ s4,
+                                                    int32_t* scale_out) {
+  __shared__ double red[4][256];
+  const SplitScale sc = split_table_scale(tx, tw, twf, n, n_pad, red);
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *exp_out = e;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    scale_out[0] = sc.e;
+    scale_out[1] = sc.shift;
+  }
   if (k >= n_pad) return;
-  const double xk = tx[k];
-  const float hi = (float)xk;
-  s4[k] = make_float4(hi, (float)(xk - (double)hi), (float)ldexp(tw[k], -e),
-                      (float)ldexp(twf[k], -e));
+  s4[k] = split_record(tx[k], tw[k], twf[k], sc);
 }
 
 size_t layout_tables(void* ws, int64_t n, NodeTable* t) {
@@ -114,7 +104,7 @@ hipError_t launch_pack(const double* nodes, const double* values, const double* 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !split) return e;
   k_pack_split<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(
-      t.x, t.w, t.wf, t.n_pad, t.s, reinterpret_cast<int32_t*>(status) + 1);
+      t.x, t.w, t.wf, n, t.n_pad, t.s, reinterpret_cast<int32_t*>(status) + 1);
   return hipGetLastError();
 }
 

@@ -8,15 +8,15 @@ the number of terms in the worst case).  Every term carries c_p = g_p / D_p,
 and D_p = sum_k a_pk has condition number Lambda(x_p), so c_p itself is only
 known to about u (1 + Lambda(x_p)); each point's terms are weighted by that
 factor.  The tests compute those absolute sums independently with numpy and
-require |HIP - oracle| <= TOL * scale,
-TOL = 1e-12 (about 10^4 u: room for the plain, chunked sums of the kernel
-over up to 10^4 terms against the oracle's compensated ones).
+require |HIP - oracle| <= TOL * scale, TOL = 1e-12 (about 10^4 u: room for
+the plain, chunked sums of the kernel over up to 10^4 terms against the
+oracle's compensated ones); the scales are metrics.grad_scales.
 """
 import numpy as np
 import pytest
 import torch
 
-from oracle import oracle
+from oracle import metrics, oracle
 from paper_1606_06508_amd import fh, inputs
 from paper_1606_06508_amd.autograd import FhEval, interpolate
 
@@ -24,7 +24,7 @@ pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
 U = 2.0 ** -53
-TOL = 1e-12
+TOL = metrics.GRAD_TOL
 
 
 def _t(a):
@@ -41,66 +41,12 @@ def _gpu_bwd(nodes, vals, d, pts, g):
     return _np(gv), _np(gx), _np(gn)
 
 
-def _weight_derivative_abs(x, d):
-    """A[k, l] = sum over the terms of w_k of |d term / d x_l| (dense, small n)."""
-    n = x.size
-    A = np.zeros((n, n))
-    for k in range(n):
-        for i in range(max(0, k - d), min(k, n - 1 - d) + 1):
-            win = [j for j in range(i, i + d + 1) if j != k]
-            T = 1.0 / np.prod([x[k] - x[j] for j in win]) if win else 1.0
-            for l in win:
-                A[k, l] += abs(T / (x[k] - x[l]))
-            A[k, k] += abs(T) * sum(1.0 / abs(x[k] - x[j]) for j in win)
-    return A
-
-
-def _scales(nodes, vals, d, pts, g):
-    """Absolute-value sums of the terms of every gradient component."""
-    w = oracle.weights(nodes, d)
-    r, lam, _ = oracle.evaluate(nodes, vals, d, pts, scale=False)
-    ok = np.isfinite(pts) & ~np.isin(pts, nodes)
-    s_df = np.zeros(nodes.size)
-    s_dw = np.zeros(nodes.size)
-    s_dxd = np.zeros(nodes.size)
-    s_dx = np.zeros(pts.size)
-    idx = np.flatnonzero(ok)
-    for lo in range(0, idx.size, 2000):
-        sel = idx[lo:lo + 2000]
-        T = 1.0 / (pts[sel, None] - nodes[None, :])
-        D = (w[None, :] * T).sum(1)
-        c = np.abs(g[sel] / D) * (1.0 + lam[sel])
-        rr = np.abs(r[sel])
-        s_df += np.abs(w) * (c[:, None] * np.abs(T)).sum(0)
-        s_dw += (c[:, None] * np.abs(T) * (np.abs(vals)[None, :] + rr[:, None])).sum(0)
-        T2 = T * T
-        s_dxd += np.abs(w) * (c[:, None] * T2 * (np.abs(vals)[None, :] + rr[:, None])).sum(0)
-        s_dx[sel] = c * (np.abs(w)[None, :] * T2 * (rr[:, None] + np.abs(vals)[None, :])).sum(1)
-    # exact hits: dL/df_j gets g_p; dL/dx_p and dL/dx_j get +-g_p r'(x_j),
-    # r'(x_j) = sum_{k != j} (w_k / w_j)(f_k - f_j)/(x_j - x_k)
-    for p in np.flatnonzero(np.isin(pts, nodes)):
-        j = int(np.searchsorted(nodes, pts[p]))
-        others = np.arange(nodes.size) != j
-        rp_abs = np.sum(np.abs(w[others] / w[j]) * np.abs(vals[others] - vals[j])
-                        / np.abs(nodes[j] - nodes[others]))
-        s_df[j] += abs(g[p])
-        s_dx[p] = abs(g[p]) * rp_abs
-        s_dxd[j] += abs(g[p]) * rp_abs
-    return s_df, s_dx, s_dxd, s_dw
-
-
 def _check_against_oracle(nodes, vals, d, pts, g, dense_chain=True):
     gv, gx, gn = _gpu_bwd(nodes, vals, d, pts, g)
     o = oracle.backward(nodes, vals, d, pts, g)
-    s_df, s_dx, s_dxd, s_dw = _scales(nodes, vals, d, pts, g)
-    assert np.all(np.abs(gv - o["d_values"]) <= TOL * s_df + 1e-300)
-    fin = np.isfinite(o["d_points"])
-    assert np.array_equal(np.isfinite(gx), fin)
-    assert np.all(np.abs(gx[fin] - o["d_points"][fin]) <= TOL * s_dx[fin] + 1e-300)
-    if dense_chain:
-        chain = _weight_derivative_abs(nodes, d).T @ s_dw
-        s_dn = s_dxd + chain
-        assert np.all(np.abs(gn - o["d_nodes"]) <= TOL * s_dn + 1e-300)
+    scales = metrics.grad_scales(nodes, vals, d, pts, g)
+    err = metrics.grad_errors(gv, gx, gn, o, scales, *((nodes, d) if dense_chain else ()))
+    metrics.check_grad(err, TOL)
     return gv, gx, gn, o
 
 
@@ -139,8 +85,8 @@ def test_full_size_identities_and_sampled_points():
     assert abs(tot) <= 1e-10 * (np.abs(nodes * gn).sum() + np.abs(pts * gx).sum())
     idx = np.random.default_rng(5).choice(pts.size, 1500, replace=False)
     o = oracle.backward(nodes, vals, d, pts[idx], g[idx])
-    _, s_dx, _, _ = _scales(nodes, vals, d, pts[idx], g[idx])
-    assert np.all(np.abs(gx[idx] - o["d_points"]) <= TOL * s_dx)
+    scales = metrics.grad_scales(nodes, vals, d, pts[idx], g[idx])
+    metrics.check_grad(metrics.grad_errors(None, gx[idx], None, o, scales), TOL)
 
 
 def test_polynomial_data():

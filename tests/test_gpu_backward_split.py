@@ -1,0 +1,138 @@
+"""The FP32-split adjoint (fh_eval_backward with FH_FP32_SPLIT) against the
+FP64 oracle, and the full-size gradient workload in both precisions against
+the oracle at every point and node.
+
+Error measure: |path - oracle| / scale per gradient component, the scale
+being the sum of the absolute values of the component's terms with each
+point weighted by 1 + Lambda(x_p) (metrics.grad_scales, or the oracle's
+C version at full size).  Bars: metrics.GRAD_TOL (binary64) and
+metrics.SPLIT_GRAD_TOL = 2^-17 (binary32 tile sums of 32 terms, as for the
+split evaluation).  The range cases push the data outside what the binary32
+terms can carry (node span, far points, extreme loss weights), where the
+kernels must switch to their binary64 per-pair paths and stay within the
+same bar.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import metrics, oracle
+from paper_1606_06508_amd import fh, inputs
+from paper_1606_06508_amd.autograd import interpolate
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+TOLS = {"fp64": metrics.GRAD_TOL, "split": metrics.SPLIT_GRAD_TOL}
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def _np(t):
+    return None if t is None else t.cpu().numpy()
+
+
+def _gpu_bwd(nodes, vals, d, pts, g, precision="split"):
+    gv, gx, gn = fh.eval_backward(_t(nodes), _t(vals), d, _t(pts), _t(g), precision=precision)
+    torch.cuda.synchronize()
+    return _np(gv), _np(gx), _np(gn)
+
+
+def _check(nodes, vals, d, pts, g, precision="split"):
+    gv, gx, gn = _gpu_bwd(nodes, vals, d, pts, g, precision)
+    o = oracle.backward(nodes, vals, d, pts, g)
+    err = metrics.grad_errors(gv, gx, gn, o, metrics.grad_scales(nodes, vals, d, pts, g), nodes, d)
+    metrics.check_grad(err, TOLS[precision])
+    return err
+
+
+def test_reduced_workload():
+    c = inputs.grad_workload(n=513, m=6007)
+    err = _check(c["nodes"], c["values"], c["d"], c["points"], c["grad"])
+    # binary32 terms: the split gradients are not binary64-accurate
+    assert max(err["dvalues"], err["dpoints"], err["dnodes"]) > metrics.GRAD_TOL
+
+
+@pytest.mark.parametrize("n,d", [(1, 0), (2, 1), (5, 0), (5, 4), (64, 3), (65, 7), (130, 10),
+                                 (300, 2)])
+def test_shapes_with_hits_and_nan(n, d):
+    g = np.random.default_rng(200 + n + d)
+    nodes = inputs.equispaced(n) + (g.uniform(-0.2, 0.2, n) * (2.0 / max(n - 1, 1)) if n > 2 else 0)
+    nodes = np.sort(nodes)
+    vals = g.standard_normal(n)
+    pts = np.concatenate([g.uniform(-1.1, 1.1, size=1001), nodes[:: max(1, n // 5)], [np.nan],
+                          nodes[-1:] + 1e-15])
+    grad = g.standard_normal(pts.size)
+    _check(nodes, vals, d, pts, grad)
+    gv, gx, gn = _gpu_bwd(nodes, vals, d, pts, grad)
+    assert np.isnan(gx[-2]) and np.all(np.isfinite(gv)) and np.all(np.isfinite(gn))
+
+
+@pytest.mark.parametrize("case", ["tiny_span", "huge_span", "far_points", "huge_g", "tiny_g"])
+def test_range_fallbacks(case):
+    g = np.random.default_rng(7)
+    n, d = 97, 4
+    nodes = inputs.equispaced(n)
+    vals = g.standard_normal(n)
+    pts = g.uniform(-1, 1, size=3000)
+    grad = g.standard_normal(pts.size)
+    if case == "tiny_span":
+        nodes, pts = nodes * 1e-7, pts * 1e-7
+    elif case == "huge_span":
+        nodes, pts = nodes * 1e7, pts * 1e7
+    elif case == "far_points":
+        # beyond one span outside the nodes, where D is still well conditioned
+        pts[::3] = np.sign(pts[::3]) * (3.5 + 2.5 * np.abs(pts[::3]))
+    elif case == "huge_g":
+        grad[::2] *= 1e60
+    elif case == "tiny_g":
+        grad *= 1e-60
+    _check(nodes, vals, d, pts, grad)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "split"])
+def test_full_workload_every_output(precision):
+    """n = 2049, d = 4, 10^6 points: every gradient entry against the oracle
+    (C oracle adjoint and C error scales)."""
+    c = inputs.grad_workload()
+    nodes, vals, d, pts, g = c["nodes"], c["values"], c["d"], c["points"], c["grad"]
+    gv, gx, gn = _gpu_bwd(nodes, vals, d, pts, g, precision)
+    o = oracle.backward(nodes, vals, d, pts, g)
+    s_df, s_dx, s_dn = oracle.grad_scales(nodes, vals, d, pts, g)
+    tol = TOLS[precision]
+    assert np.all(np.abs(gv - o["d_values"]) <= tol * s_df)
+    assert np.all(np.abs(gx - o["d_points"]) <= tol * s_dx)
+    assert np.all(np.abs(gn - o["d_nodes"]) <= tol * s_dn)
+
+
+def test_deterministic():
+    c = inputs.grad_workload(n=1025, m=100003)
+    a = _gpu_bwd(c["nodes"], c["values"], c["d"], c["points"], c["grad"])
+    b = _gpu_bwd(c["nodes"], c["values"], c["d"], c["points"], c["grad"])
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+
+
+def test_partial_outputs_match_full():
+    c = inputs.grad_workload(n=129, m=5000)
+    full = _gpu_bwd(c["nodes"], c["values"], c["d"], c["points"], c["grad"])
+    gv, gx, gn = fh.eval_backward(_t(c["nodes"]), _t(c["values"]), c["d"], _t(c["points"]),
+                                  _t(c["grad"]), need_values=False, need_x=False,
+                                  precision="split")
+    assert gv is None and gx is None
+    assert np.array_equal(_np(gn), full[2])
+
+
+def test_autograd_split():
+    g = np.random.default_rng(9)
+    nodes = _t(inputs.equispaced(40)).requires_grad_()
+    vals = _t(g.standard_normal(40)).requires_grad_()
+    x = _t(g.uniform(-1, 1, 300)).requires_grad_()
+    r = interpolate(nodes, vals, x, 3, precision="split")
+    w = _t(g.standard_normal(300))
+    (r * w).sum().backward()
+    gv, gx, gn = fh.eval_backward(nodes.detach(), vals.detach(), 3, x.detach(), w,
+                                  precision="split")
+    assert torch.equal(nodes.grad, gn) and torch.equal(vals.grad, gv) and torch.equal(x.grad, gx)

@@ -45,11 +45,11 @@ def test_instances_against_oracle(precision):
         ns, ps = _slices(c, i)
         r_o, lam_o, s_o = oracle.evaluate(c["nodes"][ns], c["values"][ns], int(c["d"][i]),
                                           c["points"][ps])
-        st = metrics.parity(r[ps], lam[ps], r_o, lam_o, s_o)
         if precision == "fp64":
-            metrics.check_fp64(st, lam_metric="cond")
+            metrics.check_fp64(metrics.parity(r[ps], lam[ps], r_o, lam_o, s_o), lam_metric="cond")
         else:
-            metrics.check_split(st)
+            metrics.check_split(metrics.parity(r[ps], lam[ps], r_o, lam_o, s_o,
+                                               metrics.SPLIT_LAMBDA_MAX))
     b.close()
 
 
@@ -107,6 +107,40 @@ def test_edge_instances():
         metrics.check_fp64(metrics.parity(r[ps], lam[ps], r_o, lam_o, s_o), lam_metric="cond")
         hit = np.isin(c["points"][ps], c["nodes"][ns])
         assert np.array_equal(r[ps][hit], r_o[hit]) and np.all(lam[ps][hit] == 1.0)
+    b.close()
+
+
+def test_split_instances_outside_binary32_domain():
+    """Instances whose data leave the binary32 domain (values spanning more
+    than 2^100, points beyond one span outside the nodes) next to ordinary
+    ones and to tiny values that only need their own scale: every instance
+    within the split bar, the out-of-domain ones at binary64 accuracy."""
+    g = np.random.default_rng(21)
+    specs = []   # (nodes, values, d, points, binary64 expected)
+    x = inputs.equispaced(200)
+    specs.append((x, g.standard_normal(200), 3, g.uniform(-1, 1, 900), False))
+    specs.append((x, np.exp(-400.0 * x ** 2), 3, g.uniform(-1, 1, 800), True))
+    specs.append((x, 1e-35 * g.standard_normal(200), 3, g.uniform(-1, 1, 600), False))
+    specs.append((x, g.standard_normal(200), 3, 3.5 + g.uniform(0, 2.5, 500), True))
+    n = np.array([s[0].size for s in specs])
+    c = {"n": n, "d": np.array([s[2] for s in specs], dtype=np.int32),
+         "m": np.array([s[3].size for s in specs]),
+         "nodes": np.concatenate([s[0] for s in specs]),
+         "values": np.concatenate([s[1] for s in specs]),
+         "points": np.concatenate([s[3] for s in specs])}
+    c["node_off"] = np.concatenate([[0], np.cumsum(c["n"])])
+    c["pt_off"] = np.concatenate([[0], np.cumsum(c["m"])])
+    b, (r, lam) = _batch(c, "split")
+    r, lam = r.cpu().numpy(), lam.cpu().numpy()
+    for i, s in enumerate(specs):
+        ns, ps = _slices(c, i)
+        r_o, lam_o, s_o = oracle.evaluate(s[0], s[1], s[2], s[3])
+        st = metrics.parity(r[ps], lam[ps], r_o, lam_o, s_o, metrics.SPLIT_LAMBDA_MAX)
+        metrics.check_split(st)
+        if s[4]:
+            assert st["e_cond_max"] <= metrics.FP64_TOL, (i, st)
+        else:
+            assert st["e_cond_max"] > metrics.FP64_TOL, (i, st)
     b.close()
 
 

@@ -233,11 +233,11 @@ def test_every_kernel_variant(precision):
         for vid, p, grp, s in fh.variants(precision):
             fh.tune_force(precision, vid)
             r, lam = _run(nodes, vals, 5, pts, precision)
-            st = metrics.parity(r, lam, r_o, lam_o, s_o)
             if precision == "fp64":
-                metrics.check_fp64(st)
+                metrics.check_fp64(metrics.parity(r, lam, r_o, lam_o, s_o))
             else:
-                metrics.check_split(st)
+                metrics.check_split(metrics.parity(r, lam, r_o, lam_o, s_o,
+                                                   metrics.SPLIT_LAMBDA_MAX))
             hit = np.isin(pts, nodes)
             assert np.array_equal(r[hit], vals[np.searchsorted(nodes, pts[hit])]), vid
             assert np.all(lam[hit] == 1.0), vid

@@ -1,0 +1,165 @@
+"""The FP32-split evaluation (fh_eval with FH_FP32_SPLIT) against the FP64
+oracle: the clustered 4097-node workload at reduced and full size (sampled),
+node counts and degrees, special points, the pins that hold bit for bit in
+split mode (exact hits, power-of-two weight scaling), and the binary32
+domain: data that leave it (far points, extreme weight or value ranges, node
+spans) must be routed to the binary64 per-pair path, which shows as
+binary64 accuracy, while data inside it stay on the binary32 path.
+
+Bar: metrics.check_split (e_cond(r) and e_cond(Lambda) <= 2^-17)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import metrics, oracle
+from paper_1606_06508_amd import fh, inputs
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def _split(nodes, values, d, pts, weights=None):
+    r, lam = fh.evaluate(_t(nodes), _t(values), d, _t(pts), lebesgue=True, precision="split",
+                         weights=None if weights is None else _t(weights))
+    torch.cuda.synchronize()
+    return r.cpu().numpy(), lam.cpu().numpy()
+
+
+def _check(nodes, values, d, pts):
+    r, lam = _split(nodes, values, d, pts)
+    r_o, lam_o, s_o = oracle.evaluate(nodes, values, d, pts)
+    st = metrics.parity(r, lam, r_o, lam_o, s_o, metrics.SPLIT_LAMBDA_MAX)
+    metrics.check_split(st)
+    hit = np.isin(pts, nodes)
+    if np.any(hit):
+        idx = np.searchsorted(nodes, pts[hit])
+        assert np.array_equal(r[hit].view(np.int64), np.asarray(values)[idx].view(np.int64))
+        assert np.all(lam[hit] == 1.0)
+    return st
+
+
+def test_split_workload_reduced():
+    c = inputs.split_workload(m=30011)
+    st = _check(c["nodes"], c["values"], c["d"], c["points"])
+    assert st["e_cond_max"] > metrics.FP64_TOL  # the binary32 path ran
+
+
+def test_split_workload_full_size_sampled():
+    c = inputs.split_workload()
+    r, lam = fh.evaluate(_t(c["nodes"]), _t(c["values"]), c["d"], _t(c["points"]),
+                         lebesgue=True, precision="split")
+    idx = np.random.default_rng(11).choice(c["points"].size, 4000, replace=False)
+    sel = torch.from_numpy(idx).to(DEV)
+    r_o, lam_o, s_o = oracle.evaluate(c["nodes"], c["values"], c["d"], c["points"][idx])
+    metrics.check_split(metrics.parity(r[sel].cpu().numpy(), lam[sel].cpu().numpy(), r_o, lam_o,
+                                       s_o, metrics.SPLIT_LAMBDA_MAX))
+
+
+@pytest.mark.parametrize("d", [0, 3, 8])
+def test_sines_reduced(d):
+    c = inputs.sines_workload(m=20011)
+    _check(c["nodes"], c["values"], d, c["points"])
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 63, 64, 65, 129, 300])
+def test_node_counts(n):
+    g = np.random.default_rng(300 + n)
+    nodes = inputs.cheb2(n) if n > 2 else inputs.equispaced(n)
+    vals = g.standard_normal(n)
+    pts = np.concatenate([g.uniform(-1, 1, 3001), nodes])
+    for d in sorted({0, 1, min(n - 1, 5), min(n - 1, 12)}):
+        _check(nodes, vals, d, pts)
+
+
+def test_special_points():
+    c = inputs.split_workload(n=257, m=2000)
+    nodes, vals, d = c["nodes"], c["values"], c["d"]
+    pts = np.concatenate([c["points"], nodes[::16], [np.nan, np.inf, -np.inf],
+                          nodes[5:6] + 1e-15, nodes[5:6] - 1e-300, [1.5, -3.0, -4.5]])
+    r, lam = _split(nodes, vals, d, pts)
+    r_o, lam_o, s_o = oracle.evaluate(nodes, vals, d, pts)
+    nan = ~np.isfinite(pts)
+    assert np.all(np.isnan(r[nan])) and np.all(np.isnan(lam[nan]))
+    fin = ~nan
+    metrics.check_split(metrics.parity(r[fin], lam[fin], r_o[fin], lam_o[fin], s_o[fin],
+                                       metrics.SPLIT_LAMBDA_MAX))
+
+
+def test_one_node():
+    """One node: outside the binary32 domain (no span), so the binary64
+    per-pair path: the hit exactly, elsewhere (w f t) / (w t) within an ulp."""
+    r, lam = _split(np.array([0.25]), np.array([3.5]), 0, np.array([0.25, -1.0, 7.0]))
+    assert r[0] == 3.5 and lam[0] == 1.0
+    assert np.allclose(r, 3.5, rtol=2 ** -52, atol=0) and np.allclose(lam, 1.0, rtol=2 ** -52)
+
+
+def test_power_of_two_weight_scaling_bitwise():
+    """Scaling every weight by 2^k leaves the split table, hence r and
+    Lambda, bit for bit unchanged."""
+    c = inputs.split_workload(n=513, m=5000)
+    w = oracle.weights(c["nodes"], c["d"])
+    a = _split(c["nodes"], c["values"], c["d"], c["points"], weights=w)
+    for k in (-300, -7, 40, 500):
+        b = _split(c["nodes"], c["values"], c["d"], c["points"], weights=np.ldexp(w, k))
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), k
+
+
+@pytest.mark.parametrize("case", ["inside", "tiny_values", "huge_values", "far_points",
+                                  "value_range", "weight_range", "tiny_span", "huge_span"])
+def test_binary32_domain(case):
+    g = np.random.default_rng(17)
+    nodes, d = inputs.equispaced(257), 4
+    vals = g.standard_normal(nodes.size)
+    pts = g.uniform(-1, 1, 4000)
+    w = None
+    fallback = True  # every point on the binary64 per-pair path
+    if case == "inside":
+        fallback = False
+    elif case == "tiny_values":
+        vals, fallback = vals * 1e-35, False
+    elif case == "huge_values":
+        vals, fallback = vals * 1e35, False
+    elif case == "far_points":
+        # beyond one span outside the nodes, where D is still well conditioned
+        pts = np.sign(pts) * (3.5 + 2.5 * np.abs(pts))
+    elif case == "value_range":
+        vals = np.exp(-400.0 * nodes ** 2)       # |w f| spans more than 2^100
+    elif case == "weight_range":
+        # explicit weights of alternating sign spanning 2^110 (a well
+        # conditioned interpolant: Lambda stays below a few thousand; FH
+        # weights that span as much, e.g. d = 20 on 1000 Chebyshev nodes,
+        # come with Lambda beyond 1/u)
+        w = (-1.0) ** np.arange(nodes.size) * np.exp2(110.0 * np.arange(nodes.size) / 256)
+    elif case == "tiny_span":
+        nodes, pts = nodes * 1e-7, pts * 1e-7
+    elif case == "huge_span":
+        nodes, pts = nodes * 1e7, pts * 1e7
+    r, lam = _split(nodes, vals, d, pts, weights=w)
+    r_o, lam_o, s_o = oracle.evaluate(nodes, vals, d, pts, w=w)
+    st = metrics.parity(r, lam, r_o, lam_o, s_o, metrics.SPLIT_LAMBDA_MAX)
+    metrics.check_split(st)
+    if fallback:
+        assert st["e_cond_max"] <= metrics.FP64_TOL, st
+    else:
+        assert st["e_cond_max"] > metrics.FP64_TOL, st
+
+
+def test_prepared_matches_evaluate():
+    c = inputs.split_workload(n=1025, m=40000)
+    r1, l1 = _split(c["nodes"], c["values"], c["d"], c["points"])
+    prep = fh.Prepared(_t(c["nodes"]), _t(c["values"]), c["d"], precision="split")
+    r2, l2 = prep(_t(c["points"]), lebesgue=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(r1, r2.cpu().numpy()) and np.array_equal(l1, l2.cpu().numpy())
+
+
+def test_deterministic():
+    c = inputs.split_workload(m=200003)
+    a = _split(c["nodes"], c["values"], c["d"], c["points"])
+    b = _split(c["nodes"], c["values"], c["d"], c["points"])
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])

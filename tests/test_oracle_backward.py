@@ -15,7 +15,7 @@ from fractions import Fraction
 import numpy as np
 import pytest
 
-from oracle import exact, oracle
+from oracle import exact, metrics, oracle
 from paper_1606_06508_amd import inputs
 
 U = 2.0 ** -53
@@ -173,3 +173,23 @@ def test_central_differences_double():
         m3 = abs(b - a) * 6 / (99 * h * h) if b != a else 0.0
         tol = 10 * (h * h * m3 / 6 + noise / h)
         assert abs(a - out["d_nodes"][k]) <= tol, (k, a, out["d_nodes"][k], tol)
+
+
+@pytest.mark.parametrize("n,d", [(1, 0), (2, 1), (33, 3), (257, 4)])
+def test_grad_scales_c_matches_numpy(n, d):
+    """The C error scales of the adjoint (fho_grad_scales, used at full
+    sizes) against the independent numpy sums (metrics.grad_scales plus the
+    dense weight-derivative matrix), with hits and a NaN point.  The two
+    weight each point by 1 + Lambda from differently rounded sums of
+    D (plain here, compensated in the numpy path), which differ by about
+    u Lambda at extrapolated points: rtol 1e-6 for a tolerance scale."""
+    rng = np.random.default_rng(40 + n)
+    x = inputs.equispaced(n) if n > 1 else np.array([0.25])
+    f = rng.standard_normal(n)
+    pts = np.concatenate([rng.uniform(-1.2, 1.2, 500), x[:: max(1, n // 4)], [np.nan]])
+    g = rng.standard_normal(pts.size)
+    s_df, s_dx, s_dxd, s_dw = metrics.grad_scales(x, f, d, pts, g)
+    s_dn = s_dxd + metrics.weight_derivative_abs(x, d).T @ s_dw
+    c_df, c_dx, c_dn = oracle.grad_scales(x, f, d, pts, g)
+    for a, b in ((s_df, c_df), (s_dx, c_dx), (s_dn, c_dn)):
+        assert np.allclose(a, b, rtol=1e-6, atol=0.0)
