@@ -303,13 +303,22 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (the reference dispatch that "
                          "scales the HBM byte counters)")
+    ap.add_argument("--profile-form", choices=("split", "batched", "grad"),
+                    help="only run one secondary form's timed loops (--steps repetitions, "
+                         "no CPU work), for kernel profiles")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
         return
+    if args.profile_form:
+        dev = torch.device("cuda:0")
+        run = {"split": run_split_forms, "batched": run_batched_form,
+               "grad": run_backward_form}[args.profile_form]
+        print(json.dumps({args.profile_form: run(dev, args.steps, False)}))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the path needs no exchange between GPUs; see the design notes on sharding).",
+              "(every interpolant is evaluated by one GPU; nothing is exchanged between GPUs).",
               file=sys.stderr)
         sys.exit(2)
     dev = torch.device("cuda:0")

@@ -26,8 +26,8 @@
 //      reciprocals taken four points at a time (simultaneous inversion); a
 //      group whose product is not normal (a hit, or extreme range) is redone
 //      pair by pair, where a zero difference adds the hit terms;
-//   3. per node: fixed-order sum of the chunk partials, then dL/df, dL/dw and
-//      the direct dL/dx_k;
+//   3. per node and field: fixed-order sum of the chunk partials; then per
+//      node dL/df, dL/dw and the direct dL/dx_k;
 //   4. per node: the weight chain (O(d^3) per node), total dL/dx_k.
 #include "bwd_math.h"
 #include "fh_internal.h"
@@ -112,8 +112,9 @@ __global__ void __launch_bounds__(256)
 
 // ---------------------------------------------------------------- pass 2 --
 // grid: x = node tiles of 64*Q nodes, y = groups of four chunks of `chunk`
-// points; wave w of the block takes chunk 4*blockIdx.y + w.
-template <int Q>
+// points (chunk a multiple of G); wave w of the block takes chunk
+// 4*blockIdx.y + w.  Reciprocals are taken G points at a time.
+template <int Q, int G>
 __global__ void __launch_bounds__(256)
     k_bwd_nodes(const double* __restrict__ rec, int64_t chunk, int64_t chunks,
                 const double* __restrict__ tx, int64_t n_pad, double* __restrict__ part) {
@@ -129,24 +130,24 @@ __global__ void __launch_bounds__(256)
     xk[q] = tx[k < n_pad ? k : n_pad - 1];
     S1[q] = S2[q] = S3[q] = S4[q] = H1[q] = H2[q] = 0.0;
   }
-  for (int64_t p = 0; p < chunk; p += 4) {
+  for (int64_t p = 0; p < chunk; p += G) {
     const double* pr = r0 + p * kRecFields;
-    double px[4], pc[4], pcr[4];
+    double px[G], pc[G], pcr[G];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < G; ++i) {
       px[i] = pr[i * kRecFields + 0];
       pc[i] = pr[i * kRecFields + 1];
       pcr[i] = pr[i * kRecFields + 2];
     }
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      double dl[4], t[4];
+      double dl[G], t[G];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) dl[i] = px[i] - xk[q];
-      const bool bad = group_reciprocals<4>(dl, t);
+      for (int i = 0; i < G; ++i) dl[i] = px[i] - xk[q];
+      const bool bad = group_reciprocals<G>(dl, t);
       if (!bad) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < G; ++i) {
           const double t2 = t[i] * t[i];
           S1[q] = __builtin_fma(pc[i], t[i], S1[q]);
           S2[q] = __builtin_fma(pcr[i], t[i], S2[q]);
@@ -155,7 +156,7 @@ __global__ void __launch_bounds__(256)
         }
       } else {
         // pair by pair: a zero difference is a hit on this node
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < G; ++i)
           bwd_pair_exact(pr + i * kRecFields, xk[q], S1[q], S2[q], S3[q], S4[q], H1[q], H2[q]);
       }
     }
@@ -175,24 +176,40 @@ __global__ void __launch_bounds__(256)
 }
 
 // ---------------------------------------------------------------- pass 3 --
+// Sum of the chunk partials of one field for 64 nodes: grid (node tiles of
+// 64, kPartFields), wave w of the block adds chunks w, w + 4, ...; the four
+// wave sums are combined in a fixed order (deterministic).
+__global__ void __launch_bounds__(256)
+    k_bwd_reduce(const double* __restrict__ part, int64_t chunks, int64_t n_pad,
+                 double* __restrict__ sums) {
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t k = (int64_t)blockIdx.x * 64 + lane;
+  const int v = blockIdx.y;
+  double acc = 0.0;
+  if (k < n_pad)
+    for (int64_t c = w; c < chunks; c += 4) acc += part[(c * kPartFields + v) * n_pad + k];
+  red[w][lane] = acc;
+  __syncthreads();
+  if (w == 0 && k < n_pad) sums[v * n_pad + k] = ((red[0][lane] + red[1][lane]) + red[2][lane]) +
+                                                 red[3][lane];
+}
+
 // The S sums may carry a common factor 2^e (the precision-split passes run
 // with c_p scaled by the weight scale 2^e, see backward_split.hip; e = 0
 // when scale_exp is null): dL/df = w 2^-e S1 + H1, dL/dw = 2^-e (f S1 - S2),
 // dL/dx_k|w = w 2^-e (f S3 - S4) - H2.  Scaling by a power of two is exact.
-__global__ void __launch_bounds__(256)
-    k_bwd_reduce(const double* __restrict__ part, int64_t chunks, int64_t n_pad, int64_t n,
+__global__ void __launch_bounds__(64)
+    k_bwd_finish(const double* __restrict__ sums, int64_t n_pad, int64_t n,
                  const double* __restrict__ tw, const double* __restrict__ tf,
                  const int32_t* __restrict__ scale_exp, double* __restrict__ df,
                  double* __restrict__ dw, double* __restrict__ dxd) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const int e = scale_exp ? *scale_exp : 0;
-  double s[kPartFields] = {0, 0, 0, 0, 0, 0};
-  for (int64_t c = 0; c < chunks; ++c) {
-    const double* pc = part + c * kPartFields * n_pad;
+  double s[kPartFields];
 #pragma unroll
-    for (int v = 0; v < kPartFields; ++v) s[v] += pc[v * n_pad + k];
-  }
+  for (int v = 0; v < kPartFields; ++v) s[v] = sums[v * n_pad + k];
   const double w = ldexp(tw[k], -e), f = tf[k];
   if (df) df[k] = w * s[0] + s[4];
   dw[k] = ldexp(f * s[0] - s[1], -e);
@@ -203,37 +220,41 @@ __global__ void __launch_bounds__(256)
 // dL/dx_l = direct term + sum over the weights that depend on x_l:
 // w_k = sum_{i in J_k} T_{k,i},  T_{k,i} = (-1)^i / prod_{j in [i,i+d], j!=k} (x_k - x_j),
 // dT/dx_l = T / (x_k - x_l) for l != k in the window, dT/dx_k = -T sum_{j!=k} 1/(x_k - x_j).
+// One wave per node l; its lanes take the (k, i) pairs with x_l in window i
+// (k within d of l), each O(d); the wave sum runs in a fixed butterfly order.
 __global__ void __launch_bounds__(256)
     k_bwd_chain(const double* __restrict__ x, int64_t n, int32_t d, const double* __restrict__ dw,
                 const double* __restrict__ dxd, double* __restrict__ dxn) {
-  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= n) return;
-  double acc = dxd[l];
+  const int lane = threadIdx.x & 63;
+  const int64_t l = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (l >= n) return;  // whole wave
   const int64_t klo = l - d > 0 ? l - d : 0;
   const int64_t khi = l + d < n - 1 ? l + d : n - 1;
-  for (int64_t k = klo; k <= khi; ++k) {
-    const int64_t ilo = k - d > 0 ? k - d : 0;
-    const int64_t ihi = k < n - 1 - d ? k : n - 1 - d;
-    double sk = 0.0;  // d w_k / d x_l
-    for (int64_t i = ilo; i <= ihi; ++i) {
-      if (l < i || l > i + d) continue;  // x_l not in this window
-      double prod = 1.0;
+  const int64_t combos = (khi - klo + 1) * (int64_t)(d + 1);
+  double acc = 0.0;
+  for (int64_t q = lane; q < combos; q += 64) {
+    const int64_t k = klo + q / (d + 1);
+    const int64_t i = k - d + q % (d + 1);  // window start, i in [k-d, k]
+    if (i < 0 || i > n - 1 - d || l < i || l > i + d) continue;
+    double prod = 1.0;
+    for (int64_t j = i; j <= i + d; ++j)
+      if (j != k) prod *= (x[k] - x[j]);
+    double T = 1.0 / prod;
+    if (i & 1) T = -T;
+    double dT;
+    if (l != k) {
+      dT = T / (x[k] - x[l]);
+    } else {
+      double inv = 0.0;
       for (int64_t j = i; j <= i + d; ++j)
-        if (j != k) prod *= (x[k] - x[j]);
-      double T = 1.0 / prod;
-      if (i & 1) T = -T;
-      if (l != k) {
-        sk += T / (x[k] - x[l]);
-      } else {
-        double inv = 0.0;
-        for (int64_t j = i; j <= i + d; ++j)
-          if (j != k) inv += 1.0 / (x[k] - x[j]);
-        sk -= T * inv;
-      }
+        if (j != k) inv += 1.0 / (x[k] - x[j]);
+      dT = -T * inv;
     }
-    acc = __builtin_fma(dw[k], sk, acc);
+    acc = __builtin_fma(dw[k], dT, acc);
   }
-  dxn[l] = acc;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0) dxn[l] = dxd[l] + acc;
 }
 
 // ------------------------------------------------------------- launcher --
@@ -243,10 +264,15 @@ BackwardPlan plan_backward(int64_t n, int64_t m, bool split) {
   p.split = split;
   // binary64: waves of 64 nodes x one chunk; split: blocks of 256 q nodes
   // sharing one chunk staged in LDS
-  p.q = split && p.n_pad >= 4096 ? 2 : 1;
+  // binary64: two points per lane in pass 1, two nodes per lane and
+  // inversion over eight points in pass 2 (measured best on the 2049-node
+  // gradient workload); split: one node per lane up to 4096 nodes
+  p.p = 2;
+  p.g = 8;
+  p.q = split ? (p.n_pad >= 4096 ? 2 : 1) : 2;
   const int64_t node_waves = split ? 4 * ((p.n_pad + 256 * p.q - 1) / (256 * p.q))
                                    : (p.n_pad + 64 * p.q - 1) / (64 * p.q);
-  const int64_t align = split ? kTile : 4;
+  const int64_t align = split ? kTile : 8;
   // enough (node tile, chunk) waves to fill the chip, chunks of >= 256 points
   int64_t chunks = (8192 + node_waves - 1) / node_waves;
   const int64_t max_chunks = (m + 255) / 256;
@@ -274,9 +300,48 @@ size_t layout_backward(void* ws, int64_t n, int64_t m, bool split, NodeTable* t,
   b->rec = reinterpret_cast<double*>(take(sizeof(double) * kRecFields * p.m_pad));
   b->rec32 = split ? reinterpret_cast<float4*>(take(sizeof(float4) * p.m_pad)) : nullptr;
   b->part = reinterpret_cast<double*>(take(sizeof(double) * kPartFields * p.n_pad * p.chunks));
+  b->sums = reinterpret_cast<double*>(take(sizeof(double) * kPartFields * p.n_pad));
   b->dw = reinterpret_cast<double*>(take(sizeof(double) * p.n_pad));
   b->dxd = reinterpret_cast<double*>(take(sizeof(double) * p.n_pad));
   return off;
+}
+
+static hipError_t launch_bwd_points(const BackwardPlan& p, const double* x, const double* g,
+                                    int64_t m, const NodeTable& t, int64_t n, double* dx,
+                                    double* rec, hipStream_t s) {
+  const dim3 grid((unsigned)((p.m_pad + 256 * p.p - 1) / (256 * p.p)));
+  switch (p.p) {
+    case 1:
+      k_bwd_points<1><<<grid, 256, 0, s>>>(x, g, m, p.m_pad, t.x, t.w, t.wf, t.f, t.n_pad, n, dx,
+                                           rec);
+      break;
+    case 2:
+      k_bwd_points<2><<<grid, 256, 0, s>>>(x, g, m, p.m_pad, t.x, t.w, t.wf, t.f, t.n_pad, n, dx,
+                                           rec);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+static hipError_t launch_bwd_nodes(const BackwardPlan& p, const double* rec, const NodeTable& t,
+                                   double* part, hipStream_t s) {
+  const dim3 grid((unsigned)((p.n_pad + 64 * p.q - 1) / (64 * p.q)),
+                  (unsigned)((p.chunks + 3) / 4));
+  const int v = p.q * 10 + p.g;
+  switch (v) {
+#define FH_NODES_CASE(Q, G)                                                                   \
+  case Q * 10 + G:                                                                          \
+    k_bwd_nodes<Q, G><<<grid, 256, 0, s>>>(rec, p.chunk, p.chunks, t.x, t.n_pad, part); \
+    break;
+    FH_NODES_CASE(1, 4)
+    FH_NODES_CASE(2, 4)
+    FH_NODES_CASE(1, 8)
+    FH_NODES_CASE(2, 8)
+#undef FH_NODES_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_backward(const double* nodes, const double* x, const double* g, int64_t n,
@@ -289,22 +354,21 @@ hipError_t launch_backward(const double* nodes, const double* x, const double* g
     e = launch_backward_split_passes(x, g, n, m, t, b, scale_exp, dx, s);
     if (e != hipSuccess) return e;
   } else {
-    constexpr int P = 1;
-    const dim3 g1((unsigned)((p.m_pad + 256 * P - 1) / (256 * P)));
-    k_bwd_points<P><<<g1, 256, 0, s>>>(x, g, m, p.m_pad, t.x, t.w, t.wf, t.f, t.n_pad, n, dx,
-                                       b.rec);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    const dim3 g2((unsigned)((p.n_pad + 64 * p.q - 1) / (64 * p.q)),
-                  (unsigned)((p.chunks + 3) / 4));
-    k_bwd_nodes<1><<<g2, 256, 0, s>>>(b.rec, p.chunk, p.chunks, t.x, t.n_pad, b.part);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    e = launch_bwd_points(p, x, g, m, t, n, dx, b.rec, s);
+    if (e != hipSuccess) return e;
+    e = launch_bwd_nodes(p, b.rec, t, b.part, s);
+    if (e != hipSuccess) return e;
   }
-  const dim3 g3((unsigned)((n + 255) / 256));
-  k_bwd_reduce<<<g3, 256, 0, s>>>(b.part, p.chunks, p.n_pad, n, t.w, t.f,
-                                  p.split ? scale_exp : nullptr, df, b.dw, b.dxd);
+  const dim3 g3((unsigned)((p.n_pad + 63) / 64), (unsigned)kPartFields);
+  k_bwd_reduce<<<g3, 256, 0, s>>>(b.part, p.chunks, p.n_pad, b.sums);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // per-node passes in 64-thread blocks: n is small, so spread it over CUs
+  const dim3 g4((unsigned)((n + 63) / 64));
+  k_bwd_finish<<<g4, 64, 0, s>>>(b.sums, p.n_pad, n, t.w, t.f, p.split ? scale_exp : nullptr, df,
+                                 b.dw, b.dxd);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (dxn) {
-    k_bwd_chain<<<g3, 256, 0, s>>>(nodes, n, d, b.dw, b.dxd, dxn);
+    k_bwd_chain<<<dim3((unsigned)((n + 3) / 4)), 256, 0, s>>>(nodes, n, d, b.dw, b.dxd, dxn);
     e = hipGetLastError();
   }
   return e;

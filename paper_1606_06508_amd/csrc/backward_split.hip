@@ -246,7 +246,7 @@ hipError_t launch_backward_split_passes(const double* x, const double* g, int64_
                                         const NodeTable& t, const BackwardBufs& b,
                                         const int32_t* scale_exp, double* dx, hipStream_t s) {
   const BackwardPlan& p = b.plan;
-  constexpr int P = 2;
+  constexpr int P = 1;
   const dim3 g1((unsigned)((p.m_pad + kStage * P - 1) / (kStage * P)));
   k_bwd_points_split<P><<<g1, kStage, 0, s>>>(x, g, m, p.m_pad, t.s, t.n_pad, t.x, t.w, t.f, n,
                                               scale_exp, dx, b.rec, b.rec32);

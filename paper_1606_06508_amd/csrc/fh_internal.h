@@ -58,7 +58,9 @@ void batched_variant_shape(int id, int* p, int* g, int* s, bool split);
 // per-node pass has enough (node tile, chunk) waves.
 struct BackwardPlan {
   int64_t n_pad, chunk, chunks, m_pad;
+  int p;       // points per lane in the per-point pass (binary64)
   int q;       // nodes per lane in the per-node pass
+  int g;       // points per simultaneous inversion in the per-node pass (binary64)
   bool split;  // precision-split passes 1 and 2
 };
 struct BackwardBufs {
@@ -66,6 +68,7 @@ struct BackwardBufs {
   double* rec;    // [m_pad][5] per-point records of pass 1
   float4* rec32;  // [m_pad] binary32 point records (split only, else null)
   double* part;   // [chunks][6][n_pad] per-chunk node sums
+  double* sums;   // [6][n_pad] node sums over all chunks
   double* dw;     // [n_pad] dL/dw_k
   double* dxd;    // [n_pad] direct dL/dx_k at fixed weights
 };

@@ -45,10 +45,11 @@ def test_workspace_sizes():
     b = lib.fh_workspace_size(fh.FH_OP_EVAL, 4097, 10 ** 6, 3, 1)
     assert 256 < a < b
     assert a % 256 == 0
-    # the split adjoint adds a 16-byte binary32 record per point
+    # the adjoint holds a 40-byte binary64 record per point, and the split
+    # adjoint a 16-byte binary32 record besides
     bw64 = lib.fh_workspace_size(fh.FH_OP_BACKWARD, 2049, 10 ** 6, 4, 0)
     bw32 = lib.fh_workspace_size(fh.FH_OP_BACKWARD, 2049, 10 ** 6, 4, 1)
-    assert bw64 > 40 * 10 ** 6 and bw32 > bw64 + 10 * 10 ** 6
+    assert bw64 > 40 * 10 ** 6 and bw32 > 56 * 10 ** 6
     # invalid problems report 0
     assert lib.fh_workspace_size(fh.FH_OP_EVAL, 0, 10, 0, 0) == 0
     assert lib.fh_workspace_size(fh.FH_OP_EVAL, 5, 10, 5, 0) == 0
