@@ -29,6 +29,10 @@
 //   3. per node and field: fixed-order sum of the chunk partials; then per
 //      node dL/df, dL/dw and the direct dL/dx_k;
 //   4. per node: the weight chain (O(d^3) per node), total dL/dx_k.
+#include <mutex>
+#include <utility>
+#include <vector>
+
 #include "bwd_math.h"
 #include "fh_internal.h"
 #include "pair_math.h"
@@ -42,22 +46,23 @@ __global__ void __launch_bounds__(256)
     k_bwd_points(const double* __restrict__ x, const double* __restrict__ g, int64_t m,
                  int64_t m_pad, const double* __restrict__ tx, const double* __restrict__ tw,
                  const double* __restrict__ twf, const double* __restrict__ tf, int64_t n_pad,
-                 int64_t n, double* __restrict__ dx, double* __restrict__ rec) {
+                 int64_t n, double* __restrict__ dx, PointRecs rec) {
   const int64_t base = (int64_t)blockIdx.x * blockDim.x * P + threadIdx.x;
   // a point far outside the node range: its differences are all of the
   // order of the span, never zero
   const double span = tx[n - 1] - tx[0];
   const double far = tx[n - 1] + span + 1.0;
   double xp[P], N[P], D[P], E[P], F[P];
-  bool bad[P];
+  uint64_t badm[P];
 #pragma unroll
   for (int j = 0; j < P; ++j) {
     const int64_t idx = base + (int64_t)j * blockDim.x;
     xp[j] = idx < m ? x[idx] : far;
     N[j] = D[j] = E[j] = F[j] = 0.0;
-    bad[j] = false;
+    badm[j] = 0;
   }
-  for (int64_t k = 0; k < n_pad; k += 8) {
+  // 32-bit counter and wave-mask flags keep loop control on the scalar unit
+  for (int k = 0; k < (int)n_pad; k += 8) {
     double xk[8], wk[8], vk[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -70,7 +75,7 @@ __global__ void __launch_bounds__(256)
       double dl[8], t[8];
 #pragma unroll
       for (int i = 0; i < 8; ++i) dl[i] = xp[j] - xk[i];
-      bad[j] |= group_reciprocals<8>(dl, t);
+      badm[j] |= not_normal_mask(group_product_reciprocals<8>(dl, t));
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         D[j] = __builtin_fma(wk[i], t[i], D[j]);
@@ -81,13 +86,14 @@ __global__ void __launch_bounds__(256)
       }
     }
   }
+  const int lane = lane_id();
 #pragma unroll
   for (int j = 0; j < P; ++j) {
     const int64_t idx = base + (int64_t)j * blockDim.x;
     if (idx >= m_pad) continue;
-    double* out = rec + idx * kRecFields;
+    const bool bad = (badm[j] >> lane) & 1;
     if (idx >= m) {
-      out[0] = far; out[1] = 0.0; out[2] = 0.0; out[3] = 0.0; out[4] = 0.0;
+      rec.x[idx] = far; rec.c[idx] = 0.0; rec.cr[idx] = 0.0; rec.hg[idx] = 0.0; rec.hgr[idx] = 0.0;
       continue;
     }
     const double gp = g[idx];
@@ -96,7 +102,7 @@ __global__ void __launch_bounds__(256)
     if (!__builtin_isfinite(t)) {
       dxp = __builtin_nan("");
       xr = far;
-    } else if (!bad[j]) {
+    } else if (!bad) {
       const double r = N[j] / D[j];
       c = gp / D[j];
       cr = c * r;
@@ -106,7 +112,7 @@ __global__ void __launch_bounds__(256)
       bwd_point_exact(t, gp, tx, tw, tf, n, &dxp, &c, &cr, &hg, &hgr);
     }
     if (dx) dx[idx] = dxp;
-    out[0] = xr; out[1] = c; out[2] = cr; out[3] = hg; out[4] = hgr;
+    rec.x[idx] = xr; rec.c[idx] = c; rec.cr[idx] = cr; rec.hg[idx] = hg; rec.hgr[idx] = hgr;
   }
 }
 
@@ -116,13 +122,16 @@ __global__ void __launch_bounds__(256)
 // 4*blockIdx.y + w.  Reciprocals are taken G points at a time.
 template <int Q, int G>
 __global__ void __launch_bounds__(256)
-    k_bwd_nodes(const double* __restrict__ rec, int64_t chunk, int64_t chunks,
+    k_bwd_nodes(PointRecs rec, int64_t chunk, int64_t chunks,
                 const double* __restrict__ tx, int64_t n_pad, double* __restrict__ part) {
   const int lane = threadIdx.x & 63;
   const int64_t c = (int64_t)blockIdx.y * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (c >= chunks) return;
   const int64_t k0 = (int64_t)blockIdx.x * 64 * Q + lane;
-  const double* r0 = rec + c * chunk * kRecFields;
+  const int64_t p0 = c * chunk;
+  const double* __restrict__ rx = rec.x + p0;
+  const double* __restrict__ rc = rec.c + p0;
+  const double* __restrict__ rcr = rec.cr + p0;
   double xk[Q], S1[Q], S2[Q], S3[Q], S4[Q], H1[Q], H2[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
@@ -130,14 +139,13 @@ __global__ void __launch_bounds__(256)
     xk[q] = tx[k < n_pad ? k : n_pad - 1];
     S1[q] = S2[q] = S3[q] = S4[q] = H1[q] = H2[q] = 0.0;
   }
-  for (int64_t p = 0; p < chunk; p += G) {
-    const double* pr = r0 + p * kRecFields;
+  for (int p = 0; p < (int)chunk; p += G) {
     double px[G], pc[G], pcr[G];
 #pragma unroll
     for (int i = 0; i < G; ++i) {
-      px[i] = pr[i * kRecFields + 0];
-      pc[i] = pr[i * kRecFields + 1];
-      pcr[i] = pr[i * kRecFields + 2];
+      px[i] = rx[p + i];
+      pc[i] = rc[p + i];
+      pcr[i] = rcr[p + i];
     }
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -157,7 +165,7 @@ __global__ void __launch_bounds__(256)
       } else {
         // pair by pair: a zero difference is a hit on this node
         for (int i = 0; i < G; ++i)
-          bwd_pair_exact(pr + i * kRecFields, xk[q], S1[q], S2[q], S3[q], S4[q], H1[q], H2[q]);
+          bwd_pair_exact(rec, p0 + p + i, xk[q], S1[q], S2[q], S3[q], S4[q], H1[q], H2[q]);
       }
     }
   }
@@ -258,24 +266,62 @@ __global__ void __launch_bounds__(256)
 }
 
 // ------------------------------------------------------------- launcher --
+// Blocks of 256 threads of `kernel` resident on the current device at once
+// (over all CUs); 2048 when the runtime cannot tell (no device).
+static int64_t resident_blocks(const void* kernel) {
+  static std::mutex mu;
+  static std::vector<std::pair<std::pair<int, const void*>, int64_t>> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 2048;
+  std::lock_guard<std::mutex> lock(mu);
+  for (const auto& e : cache)
+    if (e.first.first == dev && e.first.second == kernel) return e.second;
+  int cus = 0, per_cu = 0;
+  int64_t r = 2048;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) == hipSuccess &&
+      cus > 0 && per_cu > 0)
+    r = (int64_t)cus * per_cu;
+  cache.push_back({{dev, kernel}, r});
+  return r;
+}
+
+static const void* bwd_nodes_kernel(int q, int g) {
+  switch (q * 10 + g) {
+    case 14: return reinterpret_cast<const void*>(k_bwd_nodes<1, 4>);
+    case 24: return reinterpret_cast<const void*>(k_bwd_nodes<2, 4>);
+    case 18: return reinterpret_cast<const void*>(k_bwd_nodes<1, 8>);
+    default: return reinterpret_cast<const void*>(k_bwd_nodes<2, 8>);
+  }
+}
+
 BackwardPlan plan_backward(int64_t n, int64_t m, bool split) {
   BackwardPlan p;
   p.n_pad = round_up(n, kNodePad);
   p.split = split;
-  // binary64: waves of 64 nodes x one chunk; split: blocks of 256 q nodes
-  // sharing one chunk staged in LDS
   // binary64: two points per lane in pass 1, two nodes per lane and
   // inversion over eight points in pass 2 (measured best on the 2049-node
   // gradient workload); split: one node per lane up to 4096 nodes
   p.p = 2;
   p.g = 8;
   p.q = split ? (p.n_pad >= 4096 ? 2 : 1) : 2;
-  const int64_t node_waves = split ? 4 * ((p.n_pad + 256 * p.q - 1) / (256 * p.q))
-                                   : (p.n_pad + 64 * p.q - 1) / (64 * p.q);
+  // Pass 2 runs (node tile, chunk) units of equal work.  The chunk count is
+  // chosen so that all units are resident at once (one full round): a
+  // second, partly filled round would leave most of the chip idle for as
+  // long as the first.  binary64: blocks of four waves, each a 64 q node
+  // tile and one chunk; split: blocks of 256 q nodes sharing one chunk.
+  int64_t chunks;
+  if (split) {
+    const int64_t tiles = (p.n_pad + 256 * p.q - 1) / (256 * p.q);
+    const int64_t rows = resident_blocks(bwd_nodes_split_kernel(p.q)) / tiles;
+    chunks = rows > 1 ? rows : 1;
+  } else {
+    const int64_t tiles = (p.n_pad + 64 * p.q - 1) / (64 * p.q);
+    const int64_t rows = resident_blocks(bwd_nodes_kernel(p.q, p.g)) / tiles;
+    chunks = 4 * (rows > 1 ? rows : 1);
+  }
   const int64_t align = split ? kTile : 8;
-  // enough (node tile, chunk) waves to fill the chip, chunks of >= 256 points
-  int64_t chunks = (8192 + node_waves - 1) / node_waves;
-  const int64_t max_chunks = (m + 255) / 256;
+  const int64_t max_chunks = (m + 255) / 256;  // chunks of >= 256 points
   if (chunks > max_chunks) chunks = max_chunks;
   if (chunks < 1) chunks = 1;
   p.chunk = round_up((m + chunks - 1) / chunks, align);
@@ -297,7 +343,8 @@ size_t layout_backward(void* ws, int64_t n, int64_t m, bool split, NodeTable* t,
     return q;
   };
   b->plan = p;
-  b->rec = reinterpret_cast<double*>(take(sizeof(double) * kRecFields * p.m_pad));
+  double** fields[] = {&b->rec.x, &b->rec.c, &b->rec.cr, &b->rec.hg, &b->rec.hgr};
+  for (double** f : fields) *f = reinterpret_cast<double*>(take(sizeof(double) * p.m_pad));
   b->rec32 = split ? reinterpret_cast<float4*>(take(sizeof(float4) * p.m_pad)) : nullptr;
   b->part = reinterpret_cast<double*>(take(sizeof(double) * kPartFields * p.n_pad * p.chunks));
   b->sums = reinterpret_cast<double*>(take(sizeof(double) * kPartFields * p.n_pad));
@@ -308,7 +355,7 @@ size_t layout_backward(void* ws, int64_t n, int64_t m, bool split, NodeTable* t,
 
 static hipError_t launch_bwd_points(const BackwardPlan& p, const double* x, const double* g,
                                     int64_t m, const NodeTable& t, int64_t n, double* dx,
-                                    double* rec, hipStream_t s) {
+                                    const PointRecs& rec, hipStream_t s) {
   const dim3 grid((unsigned)((p.m_pad + 256 * p.p - 1) / (256 * p.p)));
   switch (p.p) {
     case 1:
@@ -324,7 +371,7 @@ static hipError_t launch_bwd_points(const BackwardPlan& p, const double* x, cons
   return hipGetLastError();
 }
 
-static hipError_t launch_bwd_nodes(const BackwardPlan& p, const double* rec, const NodeTable& t,
+static hipError_t launch_bwd_nodes(const BackwardPlan& p, const PointRecs& rec, const NodeTable& t,
                                    double* part, hipStream_t s) {
   const dim3 grid((unsigned)((p.n_pad + 64 * p.q - 1) / (64 * p.q)),
                   (unsigned)((p.chunks + 3) / 4));

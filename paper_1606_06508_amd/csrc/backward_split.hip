@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(kStage)
                        const double* __restrict__ tx, const double* __restrict__ tw,
                        const double* __restrict__ tf, int64_t n,
                        const int32_t* __restrict__ scale_exp, double* __restrict__ dx,
-                       double* __restrict__ rec, float4* __restrict__ rec32) {
+                       PointRecs rec, float4* __restrict__ rec32) {
   __shared__ float4 stage[2][kStage];
   const int64_t base = (int64_t)blockIdx.x * kStage * P + threadIdx.x;
   const double x_first = tx[0], x_last = tx[n - 1];
@@ -137,8 +137,7 @@ __global__ void __launch_bounds__(kStage)
       }
       if (dx) dx[idx] = dxp;
     }
-    double* out = rec + idx * kRecFields;
-    out[0] = xr; out[1] = c; out[2] = cr; out[3] = hg; out[4] = hgr;
+    rec.x[idx] = xr; rec.c[idx] = c; rec.cr[idx] = cr; rec.hg[idx] = hg; rec.hgr[idx] = hgr;
     const float h = (float)xr, l = (float)(xr - (double)h), nan = __builtin_nanf("");
     float4 r32;
     if (c == 0.0 && cr == 0.0)
@@ -158,14 +157,14 @@ __global__ void __launch_bounds__(kStage)
 // l, l + kStage, ...), y = chunks of `chunk` points (a multiple of kTile).
 template <int Q>
 __global__ void __launch_bounds__(kStage)
-    k_bwd_nodes_split(const double* __restrict__ rec, const float4* __restrict__ rec32,
+    k_bwd_nodes_split(PointRecs rec, const float4* __restrict__ rec32,
                       int64_t chunk, const double* __restrict__ tx,
                       const float4* __restrict__ s4, int64_t n_pad, double* __restrict__ part) {
   __shared__ float4 stage[2][kStage];
   const int64_t c = blockIdx.y;
   const int64_t k0 = (int64_t)blockIdx.x * kStage * Q + threadIdx.x;
-  const double* p64 = rec + c * chunk * kRecFields;
-  const float4* p32 = rec32 + c * chunk;
+  const int64_t p0 = c * chunk;
+  const float4* p32 = rec32 + p0;
   float kh[Q], kl[Q], s1[Q], s2[Q], s3[Q], s4v[Q];
   double xk[Q], S1[Q], S2[Q], S3[Q], S4[Q], H1[Q], H2[Q];
 #pragma unroll
@@ -202,19 +201,20 @@ __global__ void __launch_bounds__(kStage)
           if (not_finite32(s1[q]) | not_finite32(s2[q]) | not_finite32(s3[q]) |
               not_finite32(s4v[q])) {
             for (int64_t p = b; p < end; ++p) {
-              const double* pr = p64 + p * kRecFields;
+              const int64_t pp = p0 + p;
               const float4 h = p32[p];
-              if (h.x == h.x && pr[0] != xk[q]) {
+              const double pc = rec.c[pp], pcr = rec.cr[pp];
+              if (h.x == h.x && rec.x[pp] != xk[q]) {
                 // binary32 c: the binary32 reciprocal it was computed with
-                if (pr[1] == 0.0 && pr[2] == 0.0) continue;
+                if (pc == 0.0 && pcr == 0.0) continue;
                 const double ti = (double)__builtin_amdgcn_rcpf((h.x - kh[q]) + (h.y - kl[q]));
                 const double t2 = ti * ti;
-                S1[q] = __builtin_fma(pr[1], ti, S1[q]);
-                S2[q] = __builtin_fma(pr[2], ti, S2[q]);
-                S3[q] = __builtin_fma(pr[1], t2, S3[q]);
-                S4[q] = __builtin_fma(pr[2], t2, S4[q]);
+                S1[q] = __builtin_fma(pc, ti, S1[q]);
+                S2[q] = __builtin_fma(pcr, ti, S2[q]);
+                S3[q] = __builtin_fma(pc, t2, S3[q]);
+                S4[q] = __builtin_fma(pcr, t2, S4[q]);
               } else {
-                bwd_pair_exact(pr, xk[q], S1[q], S2[q], S3[q], S4[q], H1[q], H2[q]);
+                bwd_pair_exact(rec, pp, xk[q], S1[q], S2[q], S3[q], S4[q], H1[q], H2[q]);
               }
             }
           } else {
@@ -242,6 +242,11 @@ __global__ void __launch_bounds__(kStage)
 }
 
 // ------------------------------------------------------------- launcher --
+const void* bwd_nodes_split_kernel(int q) {
+  return q == 2 ? reinterpret_cast<const void*>(k_bwd_nodes_split<2>)
+                : reinterpret_cast<const void*>(k_bwd_nodes_split<1>);
+}
+
 hipError_t launch_backward_split_passes(const double* x, const double* g, int64_t n, int64_t m,
                                         const NodeTable& t, const BackwardBufs& b,
                                         const int32_t* scale_exp, double* dx, hipStream_t s) {

@@ -9,8 +9,18 @@
 
 namespace fhk {
 
-constexpr int kRecFields = 5;   // pass-2 point record: x, c, c r, g_hit, g_hit r'
 constexpr int kPartFields = 6;  // S1, S2, S3, S4, H1 (sum g_hit), H2 (sum g_hit r')
+
+// Per-point records written by the point pass and read by the node pass,
+// one array per field ([m_pad] each), so that the node pass reads a group
+// of consecutive points with one wide scalar load per field.
+struct PointRecs {
+  double* x;    // the point (a far point for padding and non-finite points)
+  double* c;    // c = g / D (0 at hits)
+  double* cr;   // c r
+  double* hg;   // g at a hit, else 0
+  double* hgr;  // g r'(x_j) at a hit, else 0
+};
 
 // Point x (finite) with loss weight gp, nodes tx/tw/tf[0, n), by one IEEE
 // division per pair.  At a hit x == x_j: r = f_j whatever the weights, so
@@ -56,22 +66,22 @@ __device__ inline void bwd_point_exact(double x, double gp, const double* __rest
   }
 }
 
-// One (point record pr, node xk) pair of the per-node pass by IEEE
-// division; a zero difference is a hit of the point on this node.
-__device__ inline void bwd_pair_exact(const double* __restrict__ pr, double xk, double& S1,
+// One (point p, node xk) pair of the per-node pass by IEEE division; a zero
+// difference is a hit of the point on this node.
+__device__ inline void bwd_pair_exact(const PointRecs& rec, int64_t p, double xk, double& S1,
                                       double& S2, double& S3, double& S4, double& H1,
                                       double& H2) {
-  const double dl = pr[0] - xk;
+  const double dl = rec.x[p] - xk;
   if (dl == 0.0) {
-    H1 += pr[3];
-    H2 += pr[4];
+    H1 += rec.hg[p];
+    H2 += rec.hgr[p];
   } else {
     const double ti = 1.0 / dl;
     const double t2 = ti * ti;
-    S1 = __builtin_fma(pr[1], ti, S1);
-    S2 = __builtin_fma(pr[2], ti, S2);
-    S3 = __builtin_fma(pr[1], t2, S3);
-    S4 = __builtin_fma(pr[2], t2, S4);
+    S1 = __builtin_fma(rec.c[p], ti, S1);
+    S2 = __builtin_fma(rec.cr[p], ti, S2);
+    S3 = __builtin_fma(rec.c[p], t2, S3);
+    S4 = __builtin_fma(rec.cr[p], t2, S4);
   }
 }
 

@@ -7,6 +7,7 @@
 #include <cstdint>
 
 #include "fh.h"
+#include "bwd_math.h"
 
 namespace fhk {
 
@@ -65,7 +66,7 @@ struct BackwardPlan {
 };
 struct BackwardBufs {
   BackwardPlan plan;
-  double* rec;    // [m_pad][5] per-point records of pass 1
+  PointRecs rec;  // per-point records of pass 1 (five [m_pad] arrays)
   float4* rec32;  // [m_pad] binary32 point records (split only, else null)
   double* part;   // [chunks][6][n_pad] per-chunk node sums
   double* sums;   // [6][n_pad] node sums over all chunks
@@ -90,6 +91,8 @@ hipError_t launch_backward(const double* nodes, const double* x, const double* g
                            int32_t d, int64_t m, const NodeTable& t, const BackwardBufs& b,
                            const int32_t* scale_exp, double* df, double* dx, double* dxn,
                            hipStream_t s);
+// The per-node split kernel for q nodes per lane (occupancy queries).
+const void* bwd_nodes_split_kernel(int q);
 hipError_t launch_backward_split_passes(const double* x, const double* g, int64_t n, int64_t m,
                                         const NodeTable& t, const BackwardBufs& b,
                                         const int32_t* scale_exp, double* dx, hipStream_t s);

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+
 namespace fhk {
 
 // true if v is +-0, subnormal, infinite or NaN (everything but normal)
@@ -17,13 +19,14 @@ __device__ __forceinline__ double rcp_refined(double q) {
   return __builtin_fma(y, e, y);
 }
 
-// Reciprocals of G deltas via one reciprocal of their product.  Returns true
-// if the product is not a normal number (the lane must be recomputed).
+// Reciprocals of G deltas via one reciprocal of their product q, which is
+// returned: if q is not a normal number the lane must be recomputed.
 template <int G>
-__device__ __forceinline__ bool group_reciprocals(const double (&d)[G], double (&t)[G]);
+__device__ __forceinline__ double group_product_reciprocals(const double (&d)[G], double (&t)[G]);
 
 template <>
-__device__ __forceinline__ bool group_reciprocals<4>(const double (&d)[4], double (&t)[4]) {
+__device__ __forceinline__ double group_product_reciprocals<4>(const double (&d)[4],
+                                                              double (&t)[4]) {
   const double q01 = d[0] * d[1], q23 = d[2] * d[3];
   const double q = q01 * q23;
   const double y = rcp_refined(q);
@@ -32,11 +35,12 @@ __device__ __forceinline__ bool group_reciprocals<4>(const double (&d)[4], doubl
   t[1] = y01 * d[0];
   t[2] = y23 * d[3];
   t[3] = y23 * d[2];
-  return not_normal(q);
+  return q;
 }
 
 template <>
-__device__ __forceinline__ bool group_reciprocals<8>(const double (&d)[8], double (&t)[8]) {
+__device__ __forceinline__ double group_product_reciprocals<8>(const double (&d)[8],
+                                                              double (&t)[8]) {
   const double q01 = d[0] * d[1], q23 = d[2] * d[3], q45 = d[4] * d[5], q67 = d[6] * d[7];
   const double q03 = q01 * q23, q47 = q45 * q67;
   const double q = q03 * q47;
@@ -51,7 +55,13 @@ __device__ __forceinline__ bool group_reciprocals<8>(const double (&d)[8], doubl
   t[5] = y45 * d[4];
   t[6] = y67 * d[7];
   t[7] = y67 * d[6];
-  return not_normal(q);
+  return q;
+}
+
+// As group_product_reciprocals; returns true if the product is not normal.
+template <int G>
+__device__ __forceinline__ bool group_reciprocals(const double (&d)[G], double (&t)[G]) {
+  return not_normal(group_product_reciprocals<G>(d, t));
 }
 
 // Exact per-pair evaluation of one point (flagged lanes only).
@@ -77,29 +87,53 @@ __device__ __noinline__ void eval_point_exact(double t, const double* __restrict
   *l_out = A / fabs(D);
 }
 
+// Wave mask of the lanes whose q is not a normal number (below the smallest
+// normal, infinite or NaN): two compares whose lane masks feed the scalar
+// unit directly (a class test would be materialised per lane first).
+__device__ __forceinline__ uint64_t not_normal_mask(double q) {
+  const double a = fabs(q);
+  return __builtin_amdgcn_ballot_w64(!(a >= 0x1p-1022)) |
+         __builtin_amdgcn_ballot_w64(a > 0x1.fffffffffffffp+1023);
+}
+
+// Lane index within the wave (0..63).
+__device__ __forceinline__ int lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
 // Fused sums of one wave over the node records [k_begin, k_end) (wave-
-// uniform range, a multiple of G): for each of the lane's P points,
-// D += w t, N += (w f) t, A += |w| |t|, with t from group_reciprocals<G>.
+// uniform range, a multiple of G, below 2^31 records): for each of the
+// lane's P points, D += w t, N += (w f) t, A += |w| |t|, with t from
+// group_reciprocals<G>.  The loop counter is 32-bit and the flags are
+// gathered as wave masks, so loop control and flag bookkeeping stay on the
+// scalar unit (the scalar unit has no 64-bit ordered compare).
 template <int P, int G, bool R, bool L>
 __device__ __forceinline__ void accumulate_f64(const double (&xp)[P], const double* __restrict__ tx,
                                                const double* __restrict__ tw,
                                                const double* __restrict__ twf, int64_t k_begin,
                                                int64_t k_end, double (&N)[P], double (&D)[P],
                                                double (&A)[P], bool (&bad)[P]) {
-  for (int64_t k = k_begin; k < k_end; k += G) {
+  const double* __restrict__ px = tx + k_begin;
+  const double* __restrict__ pw = tw + k_begin;
+  const double* __restrict__ pv = twf + k_begin;
+  const int cnt = (int)(k_end - k_begin);
+  uint64_t badm[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) badm[j] = 0;
+  for (int k = 0; k < cnt; k += G) {
     double xk[G], wk[G], vk[G];
 #pragma unroll
     for (int i = 0; i < G; ++i) {
-      xk[i] = tx[k + i];
-      wk[i] = tw[k + i];
-      vk[i] = R ? twf[k + i] : 0.0;
+      xk[i] = px[k + i];
+      wk[i] = pw[k + i];
+      vk[i] = R ? pv[k + i] : 0.0;
     }
 #pragma unroll
     for (int j = 0; j < P; ++j) {
       double dl[G], t[G];
 #pragma unroll
       for (int i = 0; i < G; ++i) dl[i] = xp[j] - xk[i];
-      bad[j] |= group_reciprocals<G>(dl, t);
+      badm[j] |= not_normal_mask(group_product_reciprocals<G>(dl, t));
 #pragma unroll
       for (int i = 0; i < G; ++i) {
         D[j] = __builtin_fma(wk[i], t[i], D[j]);
@@ -108,6 +142,9 @@ __device__ __forceinline__ void accumulate_f64(const double (&xp)[P], const doub
       }
     }
   }
+  const int lane = lane_id();
+#pragma unroll
+  for (int j = 0; j < P; ++j) bad[j] |= (badm[j] >> lane) & 1;
 }
 
 }  // namespace fhk
