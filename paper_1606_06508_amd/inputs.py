@@ -19,6 +19,16 @@ Workloads (the shapes of the evaluation study this library is measured on):
            m ~ U{1000..100000} uniform points each; CSR-concatenated.
   grad     n=2049 equispaced, d=4, f = sines, 10^6 uniform points,
            upstream gradient g ~ N(0,1).
+  vectors  n vectors in R^2, R^3 or R^4 (binary32 or binary64) for the
+           normalization of the paper: random signs and mantissas; half the
+           vectors draw each component's binary exponent uniformly over the
+           whole range of the format (subnormals included), the other half
+           draw one exponent per vector and lower each component's by 0..3,
+           so both lopsided and balanced vectors appear at every scale, up to
+           the largest finite values; 1e-3 of the vectors are zero and 1e-3
+           carry one NaN component.
+  quats    near-unit quaternions: a uniform random unit quaternion (Shoemake's
+           parametrisation by three uniforms) times 1 + U[-1e-3, 1e-3].
 
 Every generator takes the sizes as arguments, so tests draw the same recipe
 at reduced sizes.
@@ -27,7 +37,7 @@ import numpy as np
 
 SEED_BASE = 1606065080
 
-WORKLOADS = ("runge", "sines", "split", "batched", "grad")
+WORKLOADS = ("runge", "sines", "split", "batched", "grad", "vectors", "quats")
 
 
 def rng(workload: str, salt: int = 0) -> np.random.Generator:
@@ -150,3 +160,76 @@ def grad_workload(n: int = 2049, m: int = 1_000_000, d: int = 4, salt: int = 0):
     pts = g.uniform(-1.0, 1.0, size=m)
     grad = g.standard_normal(m)
     return {"nodes": x, "values": f, "d": d, "points": pts, "grad": grad}
+
+
+# ------------------------------------------------------------ vectors --
+def _format(dtype):
+    """(lowest, highest binary exponent of a value m 2^e with m in [1, 2),
+    mantissa bits) of binary32 / binary64; 2^lowest is the smallest
+    subnormal."""
+    return (-149, 127, 23) if np.dtype(dtype) == np.float32 else (-1074, 1023, 52)
+
+
+def nrm_vectors(n: int, dim: int, dtype=np.float64, salt: int = 0, zero_frac: float = 1e-3,
+                nan_frac: float = 1e-3) -> np.ndarray:
+    """The vectors recipe (see the module docstring) as an (n, dim) array."""
+    g = rng("vectors", salt + 100 * dim + (0 if np.dtype(dtype) == np.float64 else 50))
+    lo, hi, mbits = _format(dtype)
+    # mantissas exactly representable in the target format, so that
+    # m 2^hi never rounds up to infinity
+    mant = 1.0 + np.floor(g.random((n, dim)) * 2.0 ** mbits) / 2.0 ** mbits
+    sign = np.where(g.random((n, dim)) < 0.5, -1.0, 1.0)
+    balanced = g.random(n) < 0.5
+    e_ind = g.integers(lo, hi + 1, size=(n, dim))
+    e_com = np.clip(g.integers(lo, hi + 1, size=(n, 1)) - g.integers(0, 4, size=(n, dim)), lo, hi)
+    e = np.where(balanced[:, None], e_com, e_ind)
+    x = np.ldexp(sign * mant, e).astype(dtype)
+    zero = g.random(n) < zero_frac
+    x[zero] = 0
+    nan = g.random(n) < nan_frac
+    x[np.flatnonzero(nan), g.integers(0, dim, size=int(nan.sum()))] = np.nan
+    return np.ascontiguousarray(x)
+
+
+def near_unit_quaternions(n: int, dtype=np.float64, salt: int = 0, rel: float = 1e-3):
+    """The quats recipe: unit quaternions of Shoemake's parametrisation
+    (u1, u2, u3 uniform) times 1 + U[-rel, rel]."""
+    g = rng("quats", salt)
+    u1, u2, u3 = g.random(n), g.random(n), g.random(n)
+    a, b = np.sqrt(1.0 - u1), np.sqrt(u1)
+    q = np.stack([a * np.sin(2 * np.pi * u2), a * np.cos(2 * np.pi * u2),
+                  b * np.sin(2 * np.pi * u3), b * np.cos(2 * np.pi * u3)], axis=1)
+    q *= (1.0 + g.uniform(-rel, rel, size=n))[:, None]
+    return np.ascontiguousarray(q.astype(dtype))
+
+
+def nrm_vectors_device(n: int, dim: int, dtype: str, device, salt: int = 0,
+                       zero_frac: float = 1e-3, nan_frac: float = 1e-3):
+    """The vectors recipe drawn on a torch device (for sizes the host would
+    take seconds to draw): the same distribution as nrm_vectors, from
+    torch's generator seeded like the host recipe (different streams)."""
+    import torch
+    np_dtype = np.float32 if dtype in ("f32", "float32") else np.float64
+    t_dtype = torch.float32 if np_dtype == np.float32 else torch.float64
+    lo, hi, mbits = _format(np_dtype)
+    g = torch.Generator(device=device)
+    g.manual_seed(SEED_BASE + WORKLOADS.index("vectors") + 1 + 1000 * (salt + 100 * dim))
+    f64 = dict(generator=g, device=device, dtype=torch.float64)
+    mant = 1.0 + torch.floor(torch.rand((n, dim), **f64) * 2.0 ** mbits) / 2.0 ** mbits
+    mant = torch.where(torch.rand((n, dim), **f64) < 0.5, -mant, mant)
+    balanced = torch.rand(n, **f64) < 0.5
+    i64 = dict(generator=g, device=device, dtype=torch.int64)
+    e = torch.randint(lo, hi + 1, (n, dim), **i64)
+    e_com = (torch.randint(lo, hi + 1, (n, 1), **i64) - torch.randint(0, 4, (n, dim), **i64))
+    e = torch.where(balanced[:, None], e_com.clamp(lo, hi), e)
+    # m 2^e as (m 2^(e - e//2)) 2^(e//2): both factors stay normal, so the
+    # only rounding is the final one (into the subnormals)
+    half = torch.div(e, 2, rounding_mode="floor")
+    x = (mant * torch.pow(2.0, (e - half).to(torch.float64))) * torch.pow(2.0, half.to(torch.float64))
+    x = x.to(t_dtype)
+    x[torch.rand(n, **f64) < zero_frac] = 0
+    nan_rows = torch.nonzero(torch.rand(n, **f64) < nan_frac).flatten()
+    cols = torch.randint(0, dim, (nan_rows.numel(),), **i64)
+    x[nan_rows, cols] = float("nan")
+    del mant, e, e_com, half, balanced
+    return x.contiguous()
