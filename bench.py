@@ -280,6 +280,84 @@ def run_backward_form(dev, reps, with_cpu):
     return out
 
 
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def run_normalize_form(dev, reps, with_cpu):
+    """Batched normalization (the paper's method): 10^8 vectors per kind
+    (2D, 3D, quaternion; binary32 and binary64), array-of-structs, drawn on
+    the device by the vectors recipe.  Per kind: vectors/s and HBM GB/s of
+    the scaling algorithm (algorithmic bytes: dim entries in, dim + 1 out),
+    the struct-of-arrays layout, the quotient algorithms and the naive
+    formula, with the time ratios of the paper's Tables 3 and 4; the
+    near-unit quaternion workload; with_cpu adds the sampled bit-for-bit
+    check against the oracle and the oracle's own rate on the host."""
+    from paper_1606_06508_amd.normalize import normalize
+    n = 10 ** 8
+    out = {"workload": f"normalize: n={n} vectors per kind, exponents over the whole range, "
+                       "1e-3 zero and 1e-3 NaN vectors; plus near-unit quaternions"}
+    for sfx in ("f32", "f64"):
+        for dim in (2, 3, 4):
+            x = inputs.nrm_vectors_device(n, dim, sfx, dev)
+            esize = x.element_size()
+            nbytes = n * (2 * dim + 1) * esize
+            r = torch.empty(n, dtype=x.dtype, device=dev)
+            xh = torch.empty_like(x)
+            rec = {}
+            methods = ["scaling", "quotient", "naive"] + (["quotient_pivot"] if dim == 3 else [])
+            for method in methods:
+                ms = _time_ms(lambda: normalize(x, method=method, r_out=r, dir_out=xh), reps)
+                rec[method] = {"ms": ms, "Gvec_s": n / (ms * 1e-3) / 1e9}
+            ms_s = rec["scaling"]["ms"]
+            rec["scaling"]["GB_s"] = nbytes / (ms_s * 1e-3) / 1e9
+            rec["scaling"]["hbm_frac"] = rec["scaling"]["GB_s"] / HBM_PEAK_GBS
+            xs = x.t().contiguous()
+            hs = torch.empty_like(xs)
+            ms_soa = _time_ms(lambda: normalize(xs, layout="soa", r_out=r, dir_out=hs), reps)
+            rec["scaling_soa"] = {"ms": ms_soa, "Gvec_s": n / (ms_soa * 1e-3) / 1e9,
+                                  "GB_s": nbytes / (ms_soa * 1e-3) / 1e9}
+            del xs, hs
+            rec["table3_quotient_over_scaling"] = rec["quotient"]["ms"] / ms_s
+            if dim == 3:
+                rec["table3_pivot_over_scaling"] = rec["quotient_pivot"]["ms"] / ms_s
+            rec["table4_scaling_over_naive"] = ms_s / rec["naive"]["ms"]
+            if with_cpu:
+                from oracle import nrm
+                normalize(x, r_out=r, dir_out=xh)
+                idx = torch.from_numpy(np.random.default_rng(dim).choice(n, 20000, replace=False)).to(dev)
+                r_o, xh_o = nrm.normalize(x[idx].cpu().numpy(), "scaling")
+                got_r, got_x = r[idx].cpu().numpy(), xh[idx].cpu().numpy()
+                bad = 0
+                for a, b in ((got_r, r_o), (got_x, xh_o)):
+                    na, nb = np.isnan(a), np.isnan(b)
+                    bad += int(np.count_nonzero(na != nb))
+                    both = ~na & ~nb
+                    bad += int(np.count_nonzero(a[both].view(np.uint8).reshape(-1, esize)
+                                                != b[both].view(np.uint8).reshape(-1, esize)))
+                rec["bitwise_mismatches_20000_sampled"] = bad
+            out[f"{dim}d_{sfx}"] = rec
+            del x, r, xh
+            torch.cuda.empty_cache()
+    for sfx, dt in (("f32", np.float32), ("f64", np.float64)):
+        q = torch.from_numpy(inputs.near_unit_quaternions(10 ** 7, dt)).to(dev)
+        r = torch.empty(q.shape[0], dtype=q.dtype, device=dev)
+        qh = torch.empty_like(q)
+        ms_s = _time_ms(lambda: normalize(q, r_out=r, dir_out=qh), reps)
+        ms_n = _time_ms(lambda: normalize(q, method="naive", r_out=r, dir_out=qh), reps)
+        out[f"near_unit_quaternions_{sfx}"] = {"n": q.shape[0], "scaling_ms": ms_s,
+                                               "naive_ms": ms_n,
+                                               "table4_scaling_over_naive": ms_s / ms_n}
+    if with_cpu:
+        from oracle import nrm
+        xc = inputs.nrm_vectors(2 * 10 ** 6, 3, np.float64)
+        t0 = time.perf_counter()
+        nrm.normalize(xc, "scaling")
+        dt_c = time.perf_counter() - t0
+        out["cpu_oracle_3d_f64"] = {"Gvec_s": xc.shape[0] / dt_c / 1e9, "cores": 1,
+                                    "sample": "2e6 vectors of the vectors recipe, scaling"}
+    return out
+
+
 def copy_calibration():
     """Three copies of 2^27 float64 (1 GiB read + 1 GiB written each)."""
     dev = torch.device("cuda:0")
@@ -303,7 +381,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (the reference dispatch that "
                          "scales the HBM byte counters)")
-    ap.add_argument("--profile-form", choices=("split", "batched", "grad"),
+    ap.add_argument("--profile-form", choices=("split", "batched", "grad", "normalize"),
                     help="only run one secondary form's timed loops (--steps repetitions, "
                          "no CPU work), for kernel profiles")
     args = ap.parse_args()
@@ -313,7 +391,7 @@ def main():
     if args.profile_form:
         dev = torch.device("cuda:0")
         run = {"split": run_split_forms, "batched": run_batched_form,
-               "grad": run_backward_form}[args.profile_form]
+               "grad": run_backward_form, "normalize": run_normalize_form}[args.profile_form]
         print(json.dumps({args.profile_form: run(dev, args.steps, False)}))
         return
     if args.gpus != 1:
@@ -363,6 +441,8 @@ def main():
         print("[bench] batched form done", file=sys.stderr, flush=True)
         forms["grad_workload"] = run_backward_form(dev, 5, not args.no_cpu_baseline)
         print("[bench] backward form done", file=sys.stderr, flush=True)
+        forms["normalize"] = run_normalize_form(dev, 5, not args.no_cpu_baseline)
+        print("[bench] normalize form done", file=sys.stderr, flush=True)
         line["forms"] = forms
     print(json.dumps(line))
 

@@ -72,6 +72,9 @@ def load():
             "fh_tune_force": ([i32, i32], ctypes.c_int),
             "fh_tune_get": ([i32, i64, i64], i32),
         }
+        for dim in (2, 3, 4):
+            for sfx in ("f32", "f64"):
+                sig[f"nrm_normalize{dim}_{sfx}"] = ([vp, i64, vp, vp, i32, i32, vp], ctypes.c_int)
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
             fn.argtypes = args

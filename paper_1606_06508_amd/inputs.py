@@ -215,17 +215,26 @@ def nrm_vectors_device(n: int, dim: int, dtype: str, device, salt: int = 0,
     g = torch.Generator(device=device)
     g.manual_seed(SEED_BASE + WORKLOADS.index("vectors") + 1 + 1000 * (salt + 100 * dim))
     f64 = dict(generator=g, device=device, dtype=torch.float64)
-    mant = 1.0 + torch.floor(torch.rand((n, dim), **f64) * 2.0 ** mbits) / 2.0 ** mbits
+    # the fraction is clamped: a device uniform may return exactly 1.0, and a
+    # mantissa of 2 at the largest exponent would overflow
+    frac = torch.floor(torch.rand((n, dim), **f64) * 2.0 ** mbits).clamp_(max=2.0 ** mbits - 1)
+    mant = 1.0 + frac / 2.0 ** mbits
+    del frac
     mant = torch.where(torch.rand((n, dim), **f64) < 0.5, -mant, mant)
     balanced = torch.rand(n, **f64) < 0.5
     i64 = dict(generator=g, device=device, dtype=torch.int64)
     e = torch.randint(lo, hi + 1, (n, dim), **i64)
     e_com = (torch.randint(lo, hi + 1, (n, 1), **i64) - torch.randint(0, 4, (n, dim), **i64))
     e = torch.where(balanced[:, None], e_com.clamp(lo, hi), e)
-    # m 2^e as (m 2^(e - e//2)) 2^(e//2): both factors stay normal, so the
-    # only rounding is the final one (into the subnormals)
+    # m 2^e as (m 2^(e - e//2)) 2^(e//2): both powers of two are normal and
+    # built from their bit patterns (exact), so the only rounding is the
+    # final one (into the subnormals)
     half = torch.div(e, 2, rounding_mode="floor")
-    x = (mant * torch.pow(2.0, (e - half).to(torch.float64))) * torch.pow(2.0, half.to(torch.float64))
+
+    def pow2(k):
+        return ((k + 1023) << 52).view(torch.float64)
+
+    x = (mant * pow2(e - half)) * pow2(half)
     x = x.to(t_dtype)
     x[torch.rand(n, **f64) < zero_frac] = 0
     nan_rows = torch.nonzero(torch.rand(n, **f64) < nan_frac).flatten()

@@ -1,5 +1,5 @@
 """C ABI checks that need no GPU: the library loads, exports every function
-declared in include/fh.h, and rejects bad host-side arguments with the
+declared in include/*.h, and rejects bad host-side arguments with the
 documented status before touching the device."""
 import ctypes
 import os
@@ -10,13 +10,15 @@ import pytest
 from paper_1606_06508_amd import fh
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "fh.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("fh.h", "nrm.h")]
 
 
 def _declared():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(fh_[a-z_]+)\s*\(", text)))
+    names = set()
+    for header in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(header).read(), flags=re.S)
+        names |= set(re.findall(r"\b((?:fh|nrm)_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declares_the_five_entry_points():
@@ -121,3 +123,24 @@ def test_variant_tables_and_tuner_api():
     assert lib.fh_tune_set(0, 0, 10, 1) == fh.FH_E_ARG
     assert lib.fh_tune_set(5, 10, 10, 1) == fh.FH_E_ARG
     assert lib.fh_variant_count(7) == 0
+
+
+def test_normalize_entry_points_and_host_validation():
+    """The six normalization entry points are declared and reject bad
+    arguments before any launch."""
+    lib = fh.load()
+    names = _declared()
+    dummy = ctypes.c_void_p(256)  # never dereferenced: every call below fails validation
+    for dim in (2, 3, 4):
+        for sfx in ("f32", "f64"):
+            name = f"nrm_normalize{dim}_{sfx}"
+            assert name in names
+            fn = getattr(lib, name)
+            assert fn(None, 0, None, None, 0, 0, None) == fh.FH_OK          # nothing to do
+            assert fn(None, -1, None, None, 0, 0, None) == fh.FH_E_ARG
+            assert fn(None, 4, dummy, dummy, 0, 0, None) == fh.FH_E_ARG     # no input
+            assert fn(dummy, 4, None, None, 0, 0, None) == fh.FH_E_ARG     # no output
+            assert fn(dummy, 4, dummy, dummy, 2, 0, None) == fh.FH_E_ARG   # layout
+            assert fn(dummy, 4, dummy, dummy, 0, 4, None) == fh.FH_E_ARG   # method
+            pivot = fn(dummy, 4, dummy, dummy, 0, 2, None) if dim != 3 else None
+            assert dim == 3 or pivot == fh.FH_E_ARG                         # Algorithm 2 is 3D
