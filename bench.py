@@ -317,6 +317,10 @@ def run_normalize_form(dev, reps, with_cpu):
             rec["scaling_soa"] = {"ms": ms_soa, "Gvec_s": n / (ms_soa * 1e-3) / 1e9,
                                   "GB_s": nbytes / (ms_soa * 1e-3) / 1e9}
             del xs, hs
+            # practical ceiling: a plain device copy of the input array
+            ms_c = _time_ms(lambda: xh.copy_(x), reps)
+            rec["copy_reference"] = {"ms": ms_c,
+                                     "GB_s": 2 * n * dim * esize / (ms_c * 1e-3) / 1e9}
             rec["table3_quotient_over_scaling"] = rec["quotient"]["ms"] / ms_s
             if dim == 3:
                 rec["table3_pivot_over_scaling"] = rec["quotient_pivot"]["ms"] / ms_s

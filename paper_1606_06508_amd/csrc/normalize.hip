@@ -3,13 +3,15 @@
 // and quaternions" (Scale2D / Scale3D of Section 2, Normalize2D /
 // Normalize3D of Section 3, Normalize4D of Section 4, parameters of
 // Table 2), the two quotient algorithms of the Introduction and the naive
-// formula, one vector per lane.
+// formula.
 //
 // The work per vector is a handful of compares, one scaling multiply, a
-// sum of squares, one square root and one division, against 16 to 72 bytes
+// sum of squares, one square root and one division, against 20 to 72 bytes
 // of HBM traffic: the kernels are bound by HBM bandwidth.  Lanes take
-// consecutive vectors (grid-stride), so array-of-structs loads of a wave
-// cover one contiguous span and struct-of-arrays loads are unit stride.
+// consecutive vectors (grid-stride), so the loads of a wave cover one
+// contiguous span (array-of-structs) or are unit stride (struct-of-arrays);
+// aligned array-of-structs data move in 16-byte loads and stores, several
+// vectors per lane where one vector is not a whole number of 16 bytes.
 //
 // Scaling is branch-free: the largest magnitude m comes from each
 // procedure's comparison tree, then every entry is multiplied by
@@ -200,6 +202,20 @@ __device__ __forceinline__ void naive(const T (&x)[N], T* r, T (&xh)[N]) {
   for (int k = 0; k < N; ++k) xh[k] = h * x[k];
 }
 
+template <typename T, int N, int METHOD>
+__device__ __forceinline__ void normalize_one(const T (&v)[N], T* len, T (&o)[N]) {
+  if constexpr (METHOD == NRM_SCALING) {
+    scaling(v, len, o);
+  } else if constexpr (METHOD == NRM_QUOTIENT) {
+    quotient(v, len, o);
+  } else if constexpr (METHOD == NRM_QUOTIENT_PIVOT) {
+    if constexpr (N == 3) quotient_pivot(v, len, o);
+  } else {
+    naive(v, len, o);
+  }
+}
+
+// One vector per lane and step; any alignment.
 template <typename T, int N, int LAYOUT, int METHOD>
 __global__ void __launch_bounds__(256)
     k_normalize(const T* __restrict__ x, int64_t n, T* __restrict__ r, T* __restrict__ xh) {
@@ -208,15 +224,7 @@ __global__ void __launch_bounds__(256)
     T v[N], o[N], len;
 #pragma unroll
     for (int k = 0; k < N; ++k) v[k] = LAYOUT == NRM_AOS ? x[i * N + k] : x[k * n + i];
-    if constexpr (METHOD == NRM_SCALING) {
-      scaling(v, &len, o);
-    } else if constexpr (METHOD == NRM_QUOTIENT) {
-      quotient(v, &len, o);
-    } else if constexpr (METHOD == NRM_QUOTIENT_PIVOT) {
-      if constexpr (N == 3) quotient_pivot(v, &len, o);
-    } else {
-      naive(v, &len, o);
-    }
+    normalize_one<T, N, METHOD>(v, &len, o);
     if (r) r[i] = len;
     if (xh) {
 #pragma unroll
@@ -230,26 +238,103 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// Array-of-structs with 16-byte aligned arrays: each lane takes V
+// consecutive vectors, V N sizeof(T) a multiple of 16 bytes, and moves them
+// with 16-byte loads and stores (the lengths with V-wide stores when
+// V sizeof(T) is 8 or 16 bytes).  The lanes of a wave cover one contiguous
+// span per step.  The tail (n mod V vectors) is left to k_normalize.
+template <typename T, int N, int METHOD, int V>
+__global__ void __launch_bounds__(256)
+    k_normalize_aos_vec(const T* __restrict__ x, int64_t groups, T* __restrict__ r,
+                        T* __restrict__ xh) {
+  constexpr int kChunks = V * N * (int)sizeof(T) / 16;
+  static_assert(V * N * sizeof(T) % 16 == 0, "whole 16-byte chunks");
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gi < groups; gi += stride) {
+    union {
+      uint4 c[kChunks];
+      T e[V * N];
+    } in, out;
+    const uint4* src = reinterpret_cast<const uint4*>(x) + gi * kChunks;
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c) in.c[c] = src[c];
+    T len[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      T v[N], o[N];
+#pragma unroll
+      for (int k = 0; k < N; ++k) v[k] = in.e[j * N + k];
+      normalize_one<T, N, METHOD>(v, &len[j], o);
+#pragma unroll
+      for (int k = 0; k < N; ++k) out.e[j * N + k] = o[k];
+    }
+    if (xh) {
+      uint4* dst = reinterpret_cast<uint4*>(xh) + gi * kChunks;
+#pragma unroll
+      for (int c = 0; c < kChunks; ++c) dst[c] = out.c[c];
+    }
+    if (r) {
+#pragma unroll
+      for (int j = 0; j < V; ++j) r[gi * V + j] = len[j];
+    }
+  }
+}
+
+static int64_t grid_for(int64_t items) {
+  int64_t blocks = (items + 255) / 256;
+  return blocks > 65536 ? 65536 : (blocks < 1 ? 1 : blocks);  // grid-stride beyond
+}
+
+// Vectors per lane of the 16-byte path: the least V with V N sizeof(T) a
+// multiple of 16.
+template <typename T, int N>
+constexpr int vec_group() {
+  return (N * sizeof(T)) % 16 == 0 ? 1 : ((2 * N * sizeof(T)) % 16 == 0 ? 2 : 4);
+}
+
+template <typename T, int N, int LAYOUT, int METHOD>
+static void launch_method(const T* x, int64_t n, T* r, T* xh, bool aligned, hipStream_t s) {
+  const dim3 block(256);
+  int64_t done = 0;
+  if constexpr (LAYOUT == NRM_AOS) {
+    constexpr int V = vec_group<T, N>();
+    const int64_t groups = n / V;
+    if (aligned && groups > 0) {
+      k_normalize_aos_vec<T, N, METHOD, V>
+          <<<dim3((unsigned)grid_for(groups)), block, 0, s>>>(x, groups, r, xh);
+      done = groups * V;
+    }
+  }
+  if (done < n) {
+    // the remaining vectors (all of them on the generic path)
+    const int64_t rest = n - done;
+    if (LAYOUT == NRM_AOS)
+      k_normalize<T, N, LAYOUT, METHOD><<<dim3((unsigned)grid_for(rest)), block, 0, s>>>(
+          x + done * N, rest, r ? r + done : nullptr, xh ? xh + done * N : nullptr);
+    else
+      k_normalize<T, N, LAYOUT, METHOD><<<dim3((unsigned)grid_for(n)), block, 0, s>>>(x, n, r,
+                                                                                      xh);
+  }
+}
+
 template <typename T, int N, int LAYOUT>
-static hipError_t launch_layout(const T* x, int64_t n, T* r, T* xh, int method, hipStream_t s) {
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > 65536) blocks = 65536;  // grid-stride beyond
-  const dim3 grid((unsigned)blocks), block(256);
+static hipError_t launch_layout(const T* x, int64_t n, T* r, T* xh, int method, bool aligned,
+                                hipStream_t s) {
   switch (method) {
     case NRM_SCALING:
-      k_normalize<T, N, LAYOUT, NRM_SCALING><<<grid, block, 0, s>>>(x, n, r, xh);
+      launch_method<T, N, LAYOUT, NRM_SCALING>(x, n, r, xh, aligned, s);
       break;
     case NRM_QUOTIENT:
-      k_normalize<T, N, LAYOUT, NRM_QUOTIENT><<<grid, block, 0, s>>>(x, n, r, xh);
+      launch_method<T, N, LAYOUT, NRM_QUOTIENT>(x, n, r, xh, aligned, s);
       break;
     case NRM_QUOTIENT_PIVOT:
       if constexpr (N == 3) {
-        k_normalize<T, N, LAYOUT, NRM_QUOTIENT_PIVOT><<<grid, block, 0, s>>>(x, n, r, xh);
+        launch_method<T, N, LAYOUT, NRM_QUOTIENT_PIVOT>(x, n, r, xh, aligned, s);
         break;
       }
       return hipErrorInvalidValue;
     default:
-      k_normalize<T, N, LAYOUT, NRM_NAIVE><<<grid, block, 0, s>>>(x, n, r, xh);
+      launch_method<T, N, LAYOUT, NRM_NAIVE>(x, n, r, xh, aligned, s);
       break;
   }
   return hipGetLastError();
@@ -264,8 +349,13 @@ static fh_status normalize(const T* x, int64_t n, T* r, T* xh, int32_t layout, i
   if (n == 0) return FH_OK;
   if (x == nullptr || (r == nullptr && xh == nullptr)) return FH_E_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const hipError_t e = layout == NRM_AOS ? launch_layout<T, N, NRM_AOS>(x, n, r, xh, method, s)
-                                         : launch_layout<T, N, NRM_SOA>(x, n, r, xh, method, s);
+  // the 16-byte path needs x and x_hat 16-byte aligned, and r aligned to
+  // the width of its V-wide stores
+  auto al = [](const void* p, uintptr_t a) { return p == nullptr || (uintptr_t)p % a == 0; };
+  const bool aligned = al(x, 16) && al(xh, 16) && al(r, sizeof(T));
+  const hipError_t e =
+      layout == NRM_AOS ? launch_layout<T, N, NRM_AOS>(x, n, r, xh, method, aligned, s)
+                        : launch_layout<T, N, NRM_SOA>(x, n, r, xh, method, aligned, s);
   return e == hipSuccess ? FH_OK : FH_E_HIP;
 }
 
