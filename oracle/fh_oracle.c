@@ -194,6 +194,96 @@ int fho_eval(const double* x, const double* f, int64_t n, int32_t d, const doubl
   return FHO_OK;
 }
 
+/* ---------------------------------------------------------- derivative -- */
+/* r(x) and r'(x).  Away from the nodes r = N / D with N = sum a_k f_k,
+   D = sum a_k (a_k = w_k / (x - x_k)); differentiating, N' = -F and D' = -E
+   with F = sum a_k f_k / (x - x_k), E = sum a_k / (x - x_k), so
+   r' = (N'D - N D') / D^2 = (r E - F) / D.  At a hit x == x_j the node
+   formula of [SW]: r'(x_j) = sum_{k != j} (w_k / w_j)(f_k - f_j)/(x_j - x_k).
+   A NaN or infinite point gives NaN for both.  The scale of the rounding
+   error of r' (any evaluation of these sums) is
+     S' = ((|r| + S) sum|a_k / (x - x_k)| + sum|a_k f_k / (x - x_k)|) / |D|
+          + |r'| Lambda,
+   with S = sum|a_k f_k| / |D| + |r| Lambda the scale of r; at a hit,
+   S' = sum_{k != j} |w_k / w_j| |f_k - f_j| / |x_j - x_k|. */
+static void deriv_point(const double* x, const double* f, const double* w, int64_t n, double t,
+                        double* r, double* dr, double* scale) {
+  if (!isfinite(t)) {
+    *r = NAN; *dr = NAN; *scale = NAN;
+    return;
+  }
+  int64_t j = find_hit(x, n, t);
+  if (j >= 0) {
+    csum s = {0, 0}, sa = {0, 0};
+    for (int64_t k = 0; k < n; ++k) {
+      if (k == j) continue;
+      double term = (w[k] / w[j]) * (f[k] - f[j]) / (x[j] - x[k]);
+      cs_add(&s, term);
+      cs_add(&sa, fabs(term));
+    }
+    *r = f[j];
+    *dr = cs_val(&s);
+    *scale = cs_val(&sa);
+    return;
+  }
+  csum N = {0, 0}, D = {0, 0}, E = {0, 0}, F = {0, 0};
+  csum L = {0, 0}, A = {0, 0}, LQ = {0, 0}, FQ = {0, 0};
+  for (int64_t k = 0; k < n; ++k) {
+    double del = t - x[k];
+    double a = w[k] / del;
+    double q = 1.0 / del;
+    double af = a * f[k];
+    cs_add(&N, af);
+    cs_add(&D, a);
+    cs_add(&E, a * q);
+    cs_add(&F, af * q);
+    cs_add(&L, fabs(a));
+    cs_add(&A, fabs(af));
+    cs_add(&LQ, fabs(a * q));
+    cs_add(&FQ, fabs(af * q));
+  }
+  double dd = cs_val(&D);
+  double rr = cs_val(&N) / dd;
+  double der = (rr * cs_val(&E) - cs_val(&F)) / dd;
+  double lam = cs_val(&L) / fabs(dd);
+  double sr = cs_val(&A) / fabs(dd) + fabs(rr) * lam;
+  *r = rr;
+  *dr = der;
+  *scale = ((fabs(rr) + sr) * cs_val(&LQ) + cs_val(&FQ)) / fabs(dd) + fabs(der) * lam;
+}
+
+/* r and r' at m points (scale may be NULL); w may be NULL (computed here). */
+int fho_eval_deriv(const double* x, const double* f, int64_t n, int32_t d, const double* w_in,
+                   const double* pts, int64_t m, double* r, double* dr, double* scale,
+                   int32_t nthreads) {
+  int st = check_problem(x, n, d);
+  if (st != FHO_OK) return st;
+  if (f == NULL || m < 0 || (m > 0 && (pts == NULL || r == NULL || dr == NULL))) return FHO_E_ARG;
+  double* wbuf = NULL;
+  const double* w = w_in;
+  if (w == NULL) {
+    wbuf = (double*)malloc(sizeof(double) * (size_t)n);
+    if (!wbuf) return FHO_E_ARG;
+    st = fho_weights(x, n, d, wbuf);
+    if (st != FHO_OK) { free(wbuf); return st; }
+    w = wbuf;
+  }
+#ifdef _OPENMP
+  int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+#pragma omp parallel for schedule(static) num_threads(nt)
+#endif
+  for (int64_t p = 0; p < m; ++p) {
+    double rr, dd, ss;
+    deriv_point(x, f, w, n, pts[p], &rr, &dd, &ss);
+    r[p] = rr;
+    dr[p] = dd;
+    if (scale) scale[p] = ss;
+  }
+  (void)nthreads;
+  free(wbuf);
+  return FHO_OK;
+}
+
 /* Number of threads fho_eval would use for a given request. */
 int fho_threads(int32_t nthreads) {
 #ifdef _OPENMP

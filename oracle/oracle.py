@@ -43,9 +43,10 @@ def _load():
         lib.fho_eval.argtypes = [dp, dp, i64, i32, dp, dp, i64, dp, dp, dp, i32, i32]
         lib.fho_backward.argtypes = [dp, dp, i64, i32, dp, i64, dp, dp, dp, dp, dp, i32]
         lib.fho_grad_scales.argtypes = [dp, dp, i64, i32, dp, i64, dp, dp, dp, dp, i32]
+        lib.fho_eval_deriv.argtypes = [dp, dp, i64, i32, dp, dp, i64, dp, dp, dp, i32]
         lib.fho_threads.argtypes = [i32]
         for fn in (lib.fho_weights, lib.fho_eval, lib.fho_backward, lib.fho_grad_scales,
-                   lib.fho_threads):
+                   lib.fho_eval_deriv, lib.fho_threads):
             fn.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -101,6 +102,19 @@ def backward(nodes, values, d, pts, grad, nthreads=0):
     if st:
         raise OracleError(st)
     return {"d_values": df, "d_points": dp, "d_weights": dw, "d_nodes": dx}
+
+
+def eval_deriv(nodes, values, d, pts, w=None, nthreads=0):
+    """(r, r', S') at the points: values, derivatives (node formula at
+    hits) and the scale of the derivative's rounding error."""
+    x, f, t = _f64(nodes), _f64(values), _f64(pts)
+    wp = None if w is None else _f64(w)
+    r, dr, sc = np.empty_like(t), np.empty_like(t), np.empty_like(t)
+    st = _load().fho_eval_deriv(_p(x), _p(f), x.size, int(d), None if wp is None else _p(wp),
+                                _p(t), t.size, _p(r), _p(dr), _p(sc), int(nthreads))
+    if st:
+        raise OracleError(st)
+    return r, dr, sc
 
 
 def grad_scales(nodes, values, d, pts, grad, nthreads=0):
