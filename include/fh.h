@@ -145,6 +145,19 @@ fh_status fh_lebesgue(const double* nodes, int64_t n, int32_t d, const double* x
                       double* lambda_out, const double* w, int32_t prec, void* ws,
                       size_t ws_bytes, void* stream);
 
+/* Derivative of the interpolant: r(x_p) (r_out, may be NULL) and r'(x_p)
+ * (dr_out) at m points.  Away from the nodes r' = (r E - F) / D with
+ * D = sum a_k, E = sum a_k / (x - x_k), F = sum a_k f_k / (x - x_k)
+ * (a_k = w_k / (x - x_k)), the derivative of N / D; at an exact hit
+ * x_p == x_j the node formula r'(x_j) = sum_{k!=j} (w_k/w_j)(f_k - f_j) /
+ * (x_j - x_k) (Schneider & Werner 1986).  NaN and infinite points give NaN.
+ * w, prec, ws (fh_workspace_size(FH_OP_EVAL, ...)) and the status block
+ * behave as in fh_eval; FH_FP32_SPLIT runs the sums with binary32 terms as
+ * the split evaluation does. */
+fh_status fh_eval_deriv(const double* nodes, const double* values, int64_t n, int32_t d,
+                        const double* x, int64_t m, double* r_out, double* dr_out,
+                        const double* w, int32_t prec, void* ws, size_t ws_bytes, void* stream);
+
 /* Adjoint of L = sum_p grad_r[p] * r(x_p) (any output may be NULL):
  *   grad_values [n]  dL/df_k    = sum_p g_p a_pk / D_p
  *   grad_x      [m]  dL/dx_p    = g_p sum_k a_pk (r_p - f_k) / ((x_p - x_k) D_p)

@@ -162,6 +162,28 @@ fh_status fh_lebesgue(const double* nodes, int64_t n, int32_t d, const double* x
                      stream);
 }
 
+fh_status fh_eval_deriv(const double* nodes, const double* values, int64_t n, int32_t d,
+                        const double* x, int64_t m, double* r_out, double* dr_out,
+                        const double* w, int32_t prec, void* ws, size_t ws_bytes, void* stream) {
+  fh_status st = check_problem(nodes, n, d);
+  if (st != FH_OK) return st;
+  if (values == nullptr || m < 0 || (m > 0 && (x == nullptr || dr_out == nullptr)))
+    return FH_E_ARG;
+  if (prec != FH_FP64 && prec != FH_FP32_SPLIT) return FH_E_ARG;
+  st = check_ws(ws, ws_bytes, fh_workspace_size(FH_OP_EVAL, n, m, d, prec));
+  if (st != FH_OK) return st;
+  st = fh_prepare(nodes, values, n, d, w, prec, ws, ws_bytes, stream);
+  if (st != FH_OK || m == 0) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  NodeTable t;
+  layout_tables(ws, n, &t);
+  const hipError_t e =
+      prec == FH_FP32_SPLIT
+          ? launch_eval_deriv_split(x, m, t, n, static_cast<int32_t*>(ws) + 1, r_out, dr_out, s)
+          : launch_eval_deriv(x, m, t, n, r_out, dr_out, s);
+  return finish(e, ws, s);
+}
+
 fh_status fh_eval_backward(const double* nodes, const double* values, int64_t n, int32_t d,
                            const double* x, int64_t m, const double* grad_r, double* grad_values,
                            double* grad_x, double* grad_nodes, int32_t prec, void* ws,

@@ -41,12 +41,15 @@
 namespace fhk {
 
 // ---------------------------------------------------------------- pass 1 --
-template <int P>
+// DERIV: the derivative r'(x) = (r E - F) / D of the interpolant (dL/dx_p
+// with g_p = 1; the node formula at hits) is written to dx and r to r_out;
+// g, the records and the padding are not used (m_pad = m).
+template <int P, bool DERIV>
 __global__ void __launch_bounds__(256)
     k_bwd_points(const double* __restrict__ x, const double* __restrict__ g, int64_t m,
                  int64_t m_pad, const double* __restrict__ tx, const double* __restrict__ tw,
                  const double* __restrict__ twf, const double* __restrict__ tf, int64_t n_pad,
-                 int64_t n, double* __restrict__ dx, PointRecs rec) {
+                 int64_t n, double* __restrict__ dx, PointRecs rec, double* __restrict__ r_out) {
   const int64_t base = (int64_t)blockIdx.x * blockDim.x * P + threadIdx.x;
   // a point far outside the node range: its differences are all of the
   // order of the span, never zero
@@ -93,26 +96,33 @@ __global__ void __launch_bounds__(256)
     if (idx >= m_pad) continue;
     const bool bad = (badm[j] >> lane) & 1;
     if (idx >= m) {
-      rec.x[idx] = far; rec.c[idx] = 0.0; rec.cr[idx] = 0.0; rec.hg[idx] = 0.0; rec.hgr[idx] = 0.0;
+      if (!DERIV) {
+        rec.x[idx] = far; rec.c[idx] = 0.0; rec.cr[idx] = 0.0; rec.hg[idx] = 0.0;
+        rec.hgr[idx] = 0.0;
+      }
       continue;
     }
-    const double gp = g[idx];
+    const double gp = DERIV ? 1.0 : g[idx];
     const double t = xp[j];
-    double dxp, c = 0.0, cr = 0.0, hg = 0.0, hgr = 0.0, xr = t;
+    double dxp, rv, c = 0.0, cr = 0.0, hg = 0.0, hgr = 0.0, xr = t;
     if (!__builtin_isfinite(t)) {
-      dxp = __builtin_nan("");
+      dxp = rv = __builtin_nan("");
       xr = far;
     } else if (!bad) {
-      const double r = N[j] / D[j];
+      rv = N[j] / D[j];
       c = gp / D[j];
-      cr = c * r;
-      dxp = c * (r * E[j] - F[j]);
+      cr = c * rv;
+      dxp = c * (rv * E[j] - F[j]);
     } else {
       // pair-by-pair: exact hit or extreme range
-      bwd_point_exact(t, gp, tx, tw, tf, n, &dxp, &c, &cr, &hg, &hgr);
+      bwd_point_exact(t, gp, tx, tw, tf, n, &dxp, &c, &cr, &hg, &hgr, &rv);
     }
     if (dx) dx[idx] = dxp;
-    rec.x[idx] = xr; rec.c[idx] = c; rec.cr[idx] = cr; rec.hg[idx] = hg; rec.hgr[idx] = hgr;
+    if (DERIV) {
+      if (r_out) r_out[idx] = rv;
+    } else {
+      rec.x[idx] = xr; rec.c[idx] = c; rec.cr[idx] = cr; rec.hg[idx] = hg; rec.hgr[idx] = hgr;
+    }
   }
 }
 
@@ -359,12 +369,12 @@ static hipError_t launch_bwd_points(const BackwardPlan& p, const double* x, cons
   const dim3 grid((unsigned)((p.m_pad + 256 * p.p - 1) / (256 * p.p)));
   switch (p.p) {
     case 1:
-      k_bwd_points<1><<<grid, 256, 0, s>>>(x, g, m, p.m_pad, t.x, t.w, t.wf, t.f, t.n_pad, n, dx,
-                                           rec);
+      k_bwd_points<1, false><<<grid, 256, 0, s>>>(x, g, m, p.m_pad, t.x, t.w, t.wf, t.f, t.n_pad,
+                                                  n, dx, rec, nullptr);
       break;
     case 2:
-      k_bwd_points<2><<<grid, 256, 0, s>>>(x, g, m, p.m_pad, t.x, t.w, t.wf, t.f, t.n_pad, n, dx,
-                                           rec);
+      k_bwd_points<2, false><<<grid, 256, 0, s>>>(x, g, m, p.m_pad, t.x, t.w, t.wf, t.f, t.n_pad,
+                                                  n, dx, rec, nullptr);
       break;
     default: return hipErrorInvalidValue;
   }
@@ -419,6 +429,17 @@ hipError_t launch_backward(const double* nodes, const double* x, const double* g
     e = hipGetLastError();
   }
   return e;
+}
+
+// ---------------------------------------------------------- derivative --
+hipError_t launch_eval_deriv(const double* x, int64_t m, const NodeTable& t, int64_t n, double* r,
+                             double* dr, hipStream_t s) {
+  if (m == 0) return hipSuccess;
+  constexpr int P = 2;
+  const dim3 grid((unsigned)((m + 256 * P - 1) / (256 * P)));
+  k_bwd_points<P, true><<<grid, 256, 0, s>>>(x, nullptr, m, m, t.x, t.w, t.wf, t.f, t.n_pad, n,
+                                             dr, PointRecs{}, r);
+  return hipGetLastError();
 }
 
 }  // namespace fhk

@@ -49,14 +49,16 @@ __device__ __forceinline__ bool in_binary32_range(double v) {
 }
 
 // ---------------------------------------------------------------- pass 1 --
-template <int P>
+// DERIV: write r (r_out) and the derivative r' (dx) only, as if g_p = 1;
+// no records (m_pad = m).
+template <int P, bool DERIV>
 __global__ void __launch_bounds__(kStage)
     k_bwd_points_split(const double* __restrict__ x, const double* __restrict__ g, int64_t m,
                        int64_t m_pad, const float4* __restrict__ s4, int64_t n_pad,
                        const double* __restrict__ tx, const double* __restrict__ tw,
                        const double* __restrict__ tf, int64_t n,
                        const int32_t* __restrict__ scale_exp, double* __restrict__ dx,
-                       PointRecs rec, float4* __restrict__ rec32) {
+                       PointRecs rec, float4* __restrict__ rec32, double* __restrict__ r_out) {
   __shared__ float4 stage[2][kStage];
   const int64_t base = (int64_t)blockIdx.x * kStage * P + threadIdx.x;
   const double x_first = tx[0], x_last = tx[n - 1];
@@ -120,23 +122,25 @@ __global__ void __launch_bounds__(kStage)
     if (idx >= m_pad) continue;
     double xr = xp[j], c = 0.0, cr = 0.0, hg = 0.0, hgr = 0.0;
     if (idx < m) {
-      const double gp = g[idx];
-      double dxp;
+      const double gp = DERIV ? 1.0 : g[idx];
+      double dxp, rv;
       if (!__builtin_isfinite(xp[j])) {
-        dxp = __builtin_nan("");
+        dxp = rv = __builtin_nan("");
         xr = far;
       } else if (!bad[j]) {
-        const double r = ldexp(N[j] / D[j], shift);
+        rv = ldexp(N[j] / D[j], shift);
         c = gp / D[j];  // = 2^e g / D_p
-        cr = c * r;
-        dxp = c * (r * E[j] - ldexp(F[j], shift));
+        cr = c * rv;
+        dxp = c * (rv * E[j] - ldexp(F[j], shift));
       } else {
-        bwd_point_exact(xp[j], gp, tx, tw, tf, n, &dxp, &c, &cr, &hg, &hgr);
+        bwd_point_exact(xp[j], gp, tx, tw, tf, n, &dxp, &c, &cr, &hg, &hgr, &rv);
         c = ldexp(c, e);
         cr = ldexp(cr, e);
       }
       if (dx) dx[idx] = dxp;
+      if (DERIV && r_out) r_out[idx] = rv;
     }
+    if (DERIV) continue;
     rec.x[idx] = xr; rec.c[idx] = c; rec.cr[idx] = cr; rec.hg[idx] = hg; rec.hgr[idx] = hgr;
     const float h = (float)xr, l = (float)(xr - (double)h), nan = __builtin_nanf("");
     float4 r32;
@@ -253,8 +257,9 @@ hipError_t launch_backward_split_passes(const double* x, const double* g, int64_
   const BackwardPlan& p = b.plan;
   constexpr int P = 1;
   const dim3 g1((unsigned)((p.m_pad + kStage * P - 1) / (kStage * P)));
-  k_bwd_points_split<P><<<g1, kStage, 0, s>>>(x, g, m, p.m_pad, t.s, t.n_pad, t.x, t.w, t.f, n,
-                                              scale_exp, dx, b.rec, b.rec32);
+  k_bwd_points_split<P, false><<<g1, kStage, 0, s>>>(x, g, m, p.m_pad, t.s, t.n_pad, t.x, t.w,
+                                                     t.f, n, scale_exp, dx, b.rec, b.rec32,
+                                                     nullptr);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const dim3 g2((unsigned)((p.n_pad + kStage * p.q - 1) / (kStage * p.q)), (unsigned)p.chunks);
@@ -262,6 +267,16 @@ hipError_t launch_backward_split_passes(const double* x, const double* g, int64_
     k_bwd_nodes_split<2><<<g2, kStage, 0, s>>>(b.rec, b.rec32, p.chunk, t.x, t.s, t.n_pad, b.part);
   else
     k_bwd_nodes_split<1><<<g2, kStage, 0, s>>>(b.rec, b.rec32, p.chunk, t.x, t.s, t.n_pad, b.part);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_deriv_split(const double* x, int64_t m, const NodeTable& t, int64_t n,
+                                   const int32_t* scale, double* r, double* dr, hipStream_t s) {
+  if (m == 0) return hipSuccess;
+  constexpr int P = 1;
+  const dim3 grid((unsigned)((m + kStage * P - 1) / (kStage * P)));
+  k_bwd_points_split<P, true><<<grid, kStage, 0, s>>>(x, nullptr, m, m, t.s, t.n_pad, t.x, t.w,
+                                                      t.f, n, scale, dr, PointRecs{}, nullptr, r);
   return hipGetLastError();
 }
 

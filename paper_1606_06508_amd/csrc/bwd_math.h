@@ -26,11 +26,13 @@ struct PointRecs {
 // division per pair.  At a hit x == x_j: r = f_j whatever the weights, so
 // the point's weight goes to the hit sums (hg = g, hgr = g r'(x_j), node
 // derivative of Schneider & Werner 1986) and c = c r = 0.  Otherwise
-// c = g / D, c r and dx = c (r E - F) from the plain sums.
+// c = g / D, c r and dx = c (r E - F) from the plain sums.  *r_val (if
+// given) receives r.
 __device__ inline void bwd_point_exact(double x, double gp, const double* __restrict__ tx,
                                        const double* __restrict__ tw,
                                        const double* __restrict__ tf, int64_t n, double* dxp,
-                                       double* c, double* cr, double* hg, double* hgr) {
+                                       double* c, double* cr, double* hg, double* hgr,
+                                       double* r_val = nullptr) {
   int64_t hit = -1;
   double n2 = 0.0, d2 = 0.0, e2 = 0.0, f2 = 0.0;
   for (int64_t k = 0; k < n; ++k) {
@@ -56,8 +58,10 @@ __device__ inline void bwd_point_exact(double x, double gp, const double* __rest
     *cr = 0.0;
     *hg = gp;
     *hgr = gp * rp;
+    if (r_val) *r_val = fj;
   } else {
     const double r = n2 / d2;
+    if (r_val) *r_val = r;
     *c = gp / d2;
     *cr = *c * r;
     *dxp = *c * (r * e2 - f2);

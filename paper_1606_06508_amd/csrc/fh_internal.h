@@ -97,6 +97,11 @@ hipError_t launch_backward_split_passes(const double* x, const double* g, int64_
                                         const NodeTable& t, const BackwardBufs& b,
                                         const int32_t* scale_exp, double* dx, hipStream_t s);
 // scale: status words 1.. of the workspace (e, ef - e) written by the packing.
+// r and r' at m points from a packed node table (binary64 / split).
+hipError_t launch_eval_deriv(const double* x, int64_t m, const NodeTable& t, int64_t n, double* r,
+                             double* dr, hipStream_t s);
+hipError_t launch_eval_deriv_split(const double* x, int64_t m, const NodeTable& t, int64_t n,
+                                   const int32_t* scale, double* r, double* dr, hipStream_t s);
 hipError_t launch_eval_split(const double* x, int64_t m, const NodeTable& t, int64_t n,
                              const int32_t* scale, double* r, double* lam, const EvalConfig& cfg,
                              hipStream_t s);

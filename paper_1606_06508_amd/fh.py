@@ -57,6 +57,8 @@ def load():
             "fh_eval_prepared": ([vp, sz, i64, i32, vp, i64, vp, vp, vp], ctypes.c_int),
             "fh_eval_backward": ([vp, vp, i64, i32, vp, i64, vp, vp, vp, vp, i32, vp, sz, vp],
                                  ctypes.c_int),
+            "fh_eval_deriv": ([vp, vp, i64, i32, vp, i64, vp, vp, vp, i32, vp, sz, vp],
+                              ctypes.c_int),
             "fh_batch_create": ([ctypes.POINTER(vp), i32, ctypes.POINTER(i64),
                                  ctypes.POINTER(i32), ctypes.POINTER(i64), vp, vp, vp, vp, vp, i32,
                                  vp], ctypes.c_int),
@@ -204,6 +206,27 @@ def lebesgue(nodes, d, x, *, weights=None, precision="fp64", out=None, ws=None):
     _check(lib.fh_lebesgue(_ptr(xn), n, int(d), _ptr(t), m, _ptr(lam), _ptr(weights), prec,
                            _ptr(buf), buf.numel(), _stream(t.device)), "fh_lebesgue")
     return lam
+
+
+def eval_deriv(nodes, values, d, x, *, want_r=True, weights=None, precision="fp64", ws=None):
+    """(r, r') at the points x: the interpolant and its derivative (node
+    formula at exact hits); r is None when want_r is False."""
+    lib = load()
+    xn, f, t = _f64(nodes, "nodes"), _f64(values, "values"), _f64(x, "x")
+    n, m = xn.numel(), t.numel()
+    if f.numel() != n:
+        raise ValueError("values must match nodes")
+    if weights is not None:
+        weights = _f64(weights, "weights")
+    prec = _prec(precision)
+    r = torch.empty_like(t) if want_r else None
+    dr = torch.empty_like(t)
+    ws = ws or default_workspace(t.device)
+    buf = ws.reserve(workspace_size(FH_OP_EVAL, n, m, d, prec))
+    _check(lib.fh_eval_deriv(_ptr(xn), _ptr(f), n, int(d), _ptr(t), m, _ptr(r), _ptr(dr),
+                             _ptr(weights), prec, _ptr(buf), buf.numel(), _stream(t.device)),
+           "fh_eval_deriv")
+    return r, dr
 
 
 def eval_backward(nodes, values, d, x, grad_r, *, need_values=True, need_x=True,
