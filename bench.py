@@ -18,8 +18,8 @@ Also reported in the same JSON line:
   forms         the other forms of the path on their own workloads: FP64 vs
                 FP32-split on the 4097-node, 10^7-point clustered workload;
                 the batched graph launch over 4096 uneven interpolants vs a
-                per-instance fh_eval loop; the adjoint on 2049 nodes and
-                10^6 points.
+                per-instance fh_eval loop; the adjoint and the derivative
+                r' on 2049 nodes and 10^6 points.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -250,9 +250,10 @@ def run_batched_form(dev, reps, with_cpu):
 def run_backward_form(dev, reps, with_cpu):
     """Adjoint of sum_p g_p r(x_p) on the 2049-node, 10^6-point workload:
     gradients with respect to values, points and nodes, binary64 and
-    FP32-split; with_cpu adds the max scaled error of every output against
-    the oracle's adjoint (|path - oracle| / sum of |terms|, see the oracle's
-    error scales)."""
+    FP32-split, and the forward derivative r'(x_p) with r(x_p); with_cpu adds
+    the max scaled error of every output against the oracle's adjoint and
+    derivative (|path - oracle| / sum of |terms|, see the oracle's error
+    scales)."""
     c = inputs.grad_workload()
     n, m = c["nodes"].size, c["points"].size
     nodes, vals, x, g = (_t(c[k], dev) for k in ("nodes", "values", "points", "grad"))
@@ -263,19 +264,26 @@ def run_backward_form(dev, reps, with_cpu):
         o = oracle.backward(c["nodes"], c["values"], c["d"], c["points"], c["grad"])
         sc = oracle.grad_scales(c["nodes"], c["values"], c["d"], c["points"], c["grad"])
         ref = ((o["d_values"], sc[0]), (o["d_points"], sc[1]), (o["d_nodes"], sc[2]))
+        _, dr_o, s_o = oracle.eval_deriv(c["nodes"], c["values"], c["d"], c["points"])
     for prec in ("fp64", "split"):
         ws = fh.Workspace(dev, fh.workspace_size(fh.FH_OP_BACKWARD, n, m, c["d"], prec))
         ms_b = _time_ms(lambda: fh.eval_backward(nodes, vals, c["d"], x, g, precision=prec,
                                                  ws=ws), reps)
         ms_f = _time_ms(lambda: fh.evaluate(nodes, vals, c["d"], x, precision=prec, ws=ws), reps)
-        out[prec] = {"backward_ms": ms_b, "forward_ms": ms_f,
+        ms_d = _time_ms(lambda: fh.eval_deriv(nodes, vals, c["d"], x, precision=prec, ws=ws),
+                        reps)
+        out[prec] = {"backward_ms": ms_b, "forward_ms": ms_f, "deriv_ms": ms_d,
                      "backward_Gpair_s": n * m / (ms_b * 1e-3) / 1e9,
-                     "forward_Gpair_s": n * m / (ms_f * 1e-3) / 1e9}
+                     "forward_Gpair_s": n * m / (ms_f * 1e-3) / 1e9,
+                     "deriv_Gpair_s": n * m / (ms_d * 1e-3) / 1e9}
         if ref is not None:
             got = fh.eval_backward(nodes, vals, c["d"], x, g, precision=prec, ws=ws)
             out[prec]["max_scaled_error"] = {
                 name: float(np.max(np.abs(t.cpu().numpy() - r) / np.maximum(s, 1e-300)))
                 for name, t, (r, s) in zip(("dvalues", "dpoints", "dnodes"), got, ref)}
+            _, dr = fh.eval_deriv(nodes, vals, c["d"], x, precision=prec, ws=ws)
+            out[prec]["max_scaled_error"]["deriv"] = float(
+                np.max(np.abs(dr.cpu().numpy() - dr_o) / np.maximum(s_o, 1e-300)))
     out["split_backward_speedup_vs_fp64"] = out["fp64"]["backward_ms"] / out["split"]["backward_ms"]
     return out
 

@@ -22,6 +22,9 @@
  *         interpolation", Math. Comp. 47 (1986): derivative of a barycentric
  *         rational at a node, r'(x_j) = sum_{k!=j} (w_k/w_j)(f_k - f_j)/(x_j - x_k).
  *   [NEU] A. Neumaier (1974): compensated summation (improved Kahan-Babuska).
+ *   [LC]  The Lebesgue constant max_x Lambda(x) of an interpolation scheme,
+ *         the quantity reported for FH by Bos, De Marchi, Hormann and Klein
+ *         (Numer. Math. 2012); the search for it is a plain grid zoom.
  *   Paper (vector normalization, Mascarenhas): NaN propagation convention
  *         (Section 2, scaling algorithms propagate NaNs) and the IEEE rounding
  *         facts of the proofs appendix, in particular (rndA): multiplying a
@@ -278,6 +281,83 @@ int fho_eval_deriv(const double* x, const double* f, int64_t n, int32_t d, const
     r[p] = rr;
     dr[p] = dd;
     if (scale) scale[p] = ss;
+  }
+  (void)nthreads;
+  free(wbuf);
+  return FHO_OK;
+}
+
+/* ---------------------------------------------------- Lebesgue constant -- */
+/* Lambda(t) alone, summed as in eval_point (1 at a hit, NaN at a NaN point). */
+static double lam_point(const double* x, const double* w, int64_t n, double t) {
+  if (isnan(t)) return NAN;
+  if (find_hit(x, n, t) >= 0) return 1.0;
+  csum D = {0, 0}, L = {0, 0};
+  for (int64_t k = 0; k < n; ++k) {
+    double a = w[k] / (t - x[k]);
+    cs_add(&D, a);
+    cs_add(&L, fabs(a));
+  }
+  return cs_val(&L) / fabs(cs_val(&D));
+}
+
+/* [LC] The Lebesgue constant of the scheme is the largest value of its
+ * Lebesgue function on [x_0, x_{n-1}]; Lambda = 1 at the nodes, so it is
+ * the largest of the maxima over the n-1 intervals [x_k, x_{k+1}].  Each
+ * interval's maximum is searched for by sampling and zooming in:
+ *   a round samples S interior points of the current bracket [lo, hi],
+ *     h = (hi - lo) / (S + 1),  t_i = lo + (i + 1) h,  i = 0..S-1
+ *   (the product (i + 1) h and the sum rounded separately);
+ *   i* is the first index of the largest sampled Lambda (NaN never counts;
+ *   if every sample is NaN the search of this interval stops);
+ *   the next round's bracket is [t_{i*-1}, t_{i*+1}] with t_{-1} = lo and
+ *   t_S = hi; the first round's bracket is the interval itself.
+ * After R rounds lam_out[k] is the largest Lambda seen in any round (the
+ * first seen on ties) and x_out[k] the sample where it was seen (NaN, NaN
+ * if none was a number).  The search converges to the interval's maximum
+ * when Lambda has one local maximum there (true of the FH node families
+ * this is used with); each round divides the bracket by (S + 1) / 2. */
+int fho_lebesgue_max(const double* x, int64_t n, int32_t d, const double* w_in, int32_t samples,
+                     int32_t rounds, double* lam_out, double* x_out, int32_t nthreads) {
+  int st = check_problem(x, n, d);
+  if (st != FHO_OK) return st;
+  if (samples < 1 || rounds < 1 || (n > 1 && (lam_out == NULL || x_out == NULL)))
+    return FHO_E_ARG;
+  double* wbuf = NULL;
+  const double* w = w_in;
+  if (w == NULL) {
+    wbuf = (double*)malloc(sizeof(double) * (size_t)n);
+    if (!wbuf) return FHO_E_ARG;
+    st = fho_weights(x, n, d, wbuf);
+    if (st != FHO_OK) { free(wbuf); return st; }
+    w = wbuf;
+  }
+#ifdef _OPENMP
+  int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
+#endif
+  for (int64_t k = 0; k < n - 1; ++k) {
+    double lo = x[k], hi = x[k + 1];
+    double best = -INFINITY, best_x = NAN;
+    for (int32_t r = 0; r < rounds; ++r) {
+      double h = (hi - lo) / (double)(samples + 1);
+      int32_t bi = -1;
+      double bv = -INFINITY;
+      for (int32_t i = 0; i < samples; ++i) {
+        double t = lo + (double)(i + 1) * h;
+        double v = lam_point(x, w, n, t);
+        if (v > bv) { bv = v; bi = i; }
+      }
+      if (bi < 0) break;
+      double t_best = lo + (double)(bi + 1) * h;
+      if (bv > best) { best = bv; best_x = t_best; }
+      double nlo = bi > 0 ? lo + (double)bi * h : lo;
+      double nhi = bi < samples - 1 ? lo + (double)(bi + 2) * h : hi;
+      lo = nlo;
+      hi = nhi;
+    }
+    lam_out[k] = best == -INFINITY ? NAN : best;
+    x_out[k] = best == -INFINITY ? NAN : best_x;
   }
   (void)nthreads;
   free(wbuf);

@@ -44,9 +44,10 @@ def _load():
         lib.fho_backward.argtypes = [dp, dp, i64, i32, dp, i64, dp, dp, dp, dp, dp, i32]
         lib.fho_grad_scales.argtypes = [dp, dp, i64, i32, dp, i64, dp, dp, dp, dp, i32]
         lib.fho_eval_deriv.argtypes = [dp, dp, i64, i32, dp, dp, i64, dp, dp, dp, i32]
+        lib.fho_lebesgue_max.argtypes = [dp, i64, i32, dp, i32, i32, dp, dp, i32]
         lib.fho_threads.argtypes = [i32]
         for fn in (lib.fho_weights, lib.fho_eval, lib.fho_backward, lib.fho_grad_scales,
-                   lib.fho_eval_deriv, lib.fho_threads):
+                   lib.fho_eval_deriv, lib.fho_lebesgue_max, lib.fho_threads):
             fn.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -115,6 +116,32 @@ def eval_deriv(nodes, values, d, pts, w=None, nthreads=0):
     if st:
         raise OracleError(st)
     return r, dr, sc
+
+
+def lebesgue_max(nodes, d, samples=256, rounds=5, w=None, nthreads=0):
+    """Largest Lebesgue function value on every interval [x_k, x_{k+1}] by
+    the grid zoom of fho_lebesgue_max, and the Lebesgue constant.
+
+    Returns (lam[n-1], x[n-1], (Lambda_max, x_max)); the constant is the
+    first largest interval value (NaN values never count); a single node
+    gives (1, x_0)."""
+    x = _f64(nodes)
+    wp = None if w is None else _f64(w)
+    k = max(x.size - 1, 0)
+    lam, loc = np.empty(k), np.empty(k)
+    st = _load().fho_lebesgue_max(_p(x), x.size, int(d), None if wp is None else _p(wp),
+                                  int(samples), int(rounds), _p(lam), _p(loc), int(nthreads))
+    if st:
+        raise OracleError(st)
+    if x.size == 1:
+        return lam, loc, (1.0, float(x[0]))
+    best, at = -np.inf, np.nan
+    for v, t in zip(lam, loc):
+        if v > best:
+            best, at = float(v), float(t)
+    if best == -np.inf:
+        best = np.nan
+    return lam, loc, (best, at)
 
 
 def grad_scales(nodes, values, d, pts, grad, nthreads=0):
