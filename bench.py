@@ -19,7 +19,8 @@ Also reported in the same JSON line:
                 FP32-split on the 4097-node, 10^7-point clustered workload;
                 the batched graph launch over 4096 uneven interpolants vs a
                 per-instance fh_eval loop; the adjoint and the derivative
-                r' on 2049 nodes and 10^6 points.
+                r' on 2049 nodes and 10^6 points; normalization of 10^8
+                vectors; Lebesgue constants of a node-family table.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -288,6 +289,62 @@ def run_backward_form(dev, reps, with_cpu):
     return out
 
 
+FLOPS_PER_PAIR_L = 5  # sub, div, mul (a = w t), add (D), add (L)
+
+
+def run_lebesgue_form(dev, reps, with_cpu):
+    """Lebesgue constants of the node-family table (fh_lebesgue_max, 256
+    samples per round, 5 rounds): equispaced and jittered nodes for
+    n in {65, 257, 1025, 4097} and d = 0..10, Chebyshev second-kind nodes
+    for d <= 3.  A step computes all 104 constants (weights, per-interval
+    searches, the maximum) one call after another on one stream; the
+    largest configuration is also timed alone.  with_cpu adds the oracle's
+    rate on sampled intervals of that configuration and the max scaled
+    difference (|GPU - oracle| / (1e-13 Lambda (1 + Lambda))) on them."""
+    table = inputs.lebesgue_workload()
+    S, R = 256, 5
+    nodes = [_t(c["nodes"], dev) for c in table]
+    ws = fh.Workspace(dev, max(fh.workspace_size(fh.FH_OP_LEBESGUE_MAX, c["n"], 0, c["d"])
+                               for c in table))
+    pairs = float(sum((c["n"] - 1) * c["n"] for c in table)) * S * R
+    res = [None] * len(table)
+
+    def step():
+        for i, c in enumerate(table):
+            res[i] = fh.lebesgue_max(nodes[i], c["d"], samples=S, rounds=R, ws=ws)
+
+    ms = _time_ms(step, reps)
+    out = {"workload": f"lebesgue: {len(table)} (family, n, d) node sets, n in 65..4097, "
+                       f"d in 0..10, {S} samples x {R} rounds per interval",
+           "ms_per_table": ms, "Gpair_s": pairs / (ms * 1e-3) / 1e9, "pairs": pairs}
+    big = max(range(len(table)), key=lambda i: (table[i]["n"], table[i]["d"] == 3))
+    cb = table[big]
+    pb = float((cb["n"] - 1) * cb["n"]) * S * R
+    ms_b = _time_ms(lambda: fh.lebesgue_max(nodes[big], cb["d"], samples=S, rounds=R, ws=ws),
+                    reps)
+    out["largest"] = {"config": f"{cb['family']} n={cb['n']} d={cb['d']}", "ms": ms_b,
+                      "Gpair_s": pb / (ms_b * 1e-3) / 1e9,
+                      "TFLOP_s": FLOPS_PER_PAIR_L * pb / (ms_b * 1e-3) / 1e12}
+    step()
+    torch.cuda.synchronize()
+    consts = {}
+    for c, (_, _, best) in zip(table, res):
+        consts.setdefault(f"{c['family']} n={c['n']}", []).append(round(float(best[0]), 6))
+    out["constants_by_d"] = consts
+    if with_cpu:
+        from oracle import oracle
+        ks = np.random.default_rng(0).choice(cb["n"] - 1, 128, replace=False)
+        t0 = time.perf_counter()
+        lam_o, _, _ = oracle.lebesgue_max(cb["nodes"], cb["d"], S, R, intervals=ks)
+        dt = time.perf_counter() - t0
+        lam_g = res[big][0].cpu().numpy()[ks]
+        out["cpu_oracle"] = {"Gpair_s": ks.size * cb["n"] * S * R / dt / 1e9,
+                             "cores": oracle.threads(), "sample": f"128 intervals of {out['largest']['config']}"}
+        out["max_scaled_diff_vs_oracle"] = float(np.max(
+            np.abs(lam_g - lam_o) / (1e-13 * lam_o * (1 + lam_o))))
+    return out
+
+
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
@@ -393,7 +450,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (the reference dispatch that "
                          "scales the HBM byte counters)")
-    ap.add_argument("--profile-form", choices=("split", "batched", "grad", "normalize"),
+    ap.add_argument("--profile-form", choices=("split", "batched", "grad", "normalize",
+                                               "lebesgue"),
                     help="only run one secondary form's timed loops (--steps repetitions, "
                          "no CPU work), for kernel profiles")
     args = ap.parse_args()
@@ -403,7 +461,8 @@ def main():
     if args.profile_form:
         dev = torch.device("cuda:0")
         run = {"split": run_split_forms, "batched": run_batched_form,
-               "grad": run_backward_form, "normalize": run_normalize_form}[args.profile_form]
+               "grad": run_backward_form, "normalize": run_normalize_form,
+               "lebesgue": run_lebesgue_form}[args.profile_form]
         print(json.dumps({args.profile_form: run(dev, args.steps, False)}))
         return
     if args.gpus != 1:
@@ -455,6 +514,8 @@ def main():
         print("[bench] backward form done", file=sys.stderr, flush=True)
         forms["normalize"] = run_normalize_form(dev, 5, not args.no_cpu_baseline)
         print("[bench] normalize form done", file=sys.stderr, flush=True)
+        forms["lebesgue"] = run_lebesgue_form(dev, 3, not args.no_cpu_baseline)
+        print("[bench] lebesgue form done", file=sys.stderr, flush=True)
         line["forms"] = forms
     print(json.dumps(line))
 

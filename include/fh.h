@@ -87,7 +87,8 @@ typedef enum { FH_FP64 = 0, FH_FP32_SPLIT = 1 } fh_precision;
 typedef enum {
   FH_OP_WEIGHTS = 0,
   FH_OP_EVAL = 1,       /* also fh_lebesgue */
-  FH_OP_BACKWARD = 2
+  FH_OP_BACKWARD = 2,
+  FH_OP_LEBESGUE_MAX = 3 /* fh_lebesgue_max (m ignored) */
 } fh_op;
 
 /* Device status bits (fh_device_status). */
@@ -144,6 +145,33 @@ fh_status fh_eval_prepared(void* ws, size_t ws_bytes, int64_t n, int32_t prec, c
 fh_status fh_lebesgue(const double* nodes, int64_t n, int32_t d, const double* x, int64_t m,
                       double* lambda_out, const double* w, int32_t prec, void* ws,
                       size_t ws_bytes, void* stream);
+
+/* Lebesgue constant: the largest value of the Lebesgue function Lambda
+ * (see fh_lebesgue) on [x_0, x_{n-1}], the quantity the FH literature
+ * reports per node family, n and d (Bos, De Marchi, Hormann and Klein,
+ * Numer. Math. 2012).  Lambda = 1 at the nodes, so it is the largest of the
+ * maxima over the n - 1 intervals [x_k, x_{k+1}]; each is searched for by a
+ * grid zoom: `rounds` rounds, each sampling `samples` interior points
+ * t_i = lo + (i + 1) h, h = (hi - lo) / (samples + 1), of the bracket
+ * [lo, hi] (first the interval itself; the product and the sum rounded
+ * separately), the next bracket being the two neighbours of the first
+ * largest sample.  The search finds the maximum when Lambda has one local
+ * maximum per interval; each round divides the bracket by (samples + 1)/2.
+ *   nodes, n, d, w   as in fh_lebesgue (w may be NULL)
+ *   samples          1..512 per round;  rounds 1..64
+ *   lam_out          [n-1] per-interval maxima (the largest Lambda seen, first
+ *                    seen on ties; NaN if no sample was a number), or NULL
+ *   x_out            [n-1] where each was seen, or NULL
+ *   best_out         [2] = {Lebesgue constant, its location}: the first
+ *                    largest interval maximum (n = 1 gives {1, x_0}), or NULL
+ *   prec             FH_FP64 (FH_FP32_SPLIT: FH_E_UNSUPPORTED; the zoom
+ *                    compares values that differ in late digits)
+ *   ws               fh_workspace_size(FH_OP_LEBESGUE_MAX, n, 0, d, prec)
+ * All outputs are device arrays; at least one must be given.  Errors as in
+ * fh_eval (node-order and weight-range problems set status bits). */
+fh_status fh_lebesgue_max(const double* nodes, int64_t n, int32_t d, const double* w,
+                          int32_t samples, int32_t rounds, double* lam_out, double* x_out,
+                          double* best_out, int32_t prec, void* ws, size_t ws_bytes, void* stream);
 
 /* Derivative of the interpolant: r(x_p) (r_out, may be NULL) and r'(x_p)
  * (dr_out) at m points.  Away from the nodes r' = (r E - F) / D with

@@ -318,11 +318,17 @@ static double lam_point(const double* x, const double* w, int64_t n, double t) {
  * when Lambda has one local maximum there (true of the FH node families
  * this is used with); each round divides the bracket by (S + 1) / 2. */
 int fho_lebesgue_max(const double* x, int64_t n, int32_t d, const double* w_in, int32_t samples,
-                     int32_t rounds, double* lam_out, double* x_out, int32_t nthreads) {
+                     int32_t rounds, const int64_t* ks, int64_t nk, double* lam_out,
+                     double* x_out, int32_t nthreads) {
+  /* ks: the intervals to search (nk of them, outputs in that order), or
+     NULL for all n - 1 */
   int st = check_problem(x, n, d);
   if (st != FHO_OK) return st;
-  if (samples < 1 || rounds < 1 || (n > 1 && (lam_out == NULL || x_out == NULL)))
+  if (ks == NULL) nk = n - 1;
+  if (samples < 1 || rounds < 1 || nk < 0 || (nk > 0 && (lam_out == NULL || x_out == NULL)))
     return FHO_E_ARG;
+  for (int64_t q = 0; ks != NULL && q < nk; ++q)
+    if (ks[q] < 0 || ks[q] >= n - 1) return FHO_E_ARG;
   double* wbuf = NULL;
   const double* w = w_in;
   if (w == NULL) {
@@ -336,7 +342,8 @@ int fho_lebesgue_max(const double* x, int64_t n, int32_t d, const double* w_in, 
   int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
 #endif
-  for (int64_t k = 0; k < n - 1; ++k) {
+  for (int64_t q = 0; q < nk; ++q) {
+    int64_t k = ks != NULL ? ks[q] : q;
     double lo = x[k], hi = x[k + 1];
     double best = -INFINITY, best_x = NAN;
     for (int32_t r = 0; r < rounds; ++r) {
@@ -356,8 +363,8 @@ int fho_lebesgue_max(const double* x, int64_t n, int32_t d, const double* w_in, 
       lo = nlo;
       hi = nhi;
     }
-    lam_out[k] = best == -INFINITY ? NAN : best;
-    x_out[k] = best == -INFINITY ? NAN : best_x;
+    lam_out[q] = best == -INFINITY ? NAN : best;
+    x_out[q] = best == -INFINITY ? NAN : best_x;
   }
   (void)nthreads;
   free(wbuf);

@@ -44,7 +44,8 @@ def _load():
         lib.fho_backward.argtypes = [dp, dp, i64, i32, dp, i64, dp, dp, dp, dp, dp, i32]
         lib.fho_grad_scales.argtypes = [dp, dp, i64, i32, dp, i64, dp, dp, dp, dp, i32]
         lib.fho_eval_deriv.argtypes = [dp, dp, i64, i32, dp, dp, i64, dp, dp, dp, i32]
-        lib.fho_lebesgue_max.argtypes = [dp, i64, i32, dp, i32, i32, dp, dp, i32]
+        lib.fho_lebesgue_max.argtypes = [dp, i64, i32, dp, i32, i32,
+                                         ctypes.POINTER(ctypes.c_int64), i64, dp, dp, i32]
         lib.fho_threads.argtypes = [i32]
         for fn in (lib.fho_weights, lib.fho_eval, lib.fho_backward, lib.fho_grad_scales,
                    lib.fho_eval_deriv, lib.fho_lebesgue_max, lib.fho_threads):
@@ -118,19 +119,25 @@ def eval_deriv(nodes, values, d, pts, w=None, nthreads=0):
     return r, dr, sc
 
 
-def lebesgue_max(nodes, d, samples=256, rounds=5, w=None, nthreads=0):
+def lebesgue_max(nodes, d, samples=256, rounds=5, w=None, intervals=None, nthreads=0):
     """Largest Lebesgue function value on every interval [x_k, x_{k+1}] by
     the grid zoom of fho_lebesgue_max, and the Lebesgue constant.
 
     Returns (lam[n-1], x[n-1], (Lambda_max, x_max)); the constant is the
     first largest interval value (NaN values never count); a single node
-    gives (1, x_0)."""
+    gives (1, x_0).  With `intervals` (indices k) only those are searched,
+    in that order, and the constant is taken over them."""
     x = _f64(nodes)
     wp = None if w is None else _f64(w)
-    k = max(x.size - 1, 0)
+    ks = None
+    if intervals is not None:
+        ks = np.ascontiguousarray(np.asarray(intervals, dtype=np.int64))
+    k = ks.size if ks is not None else max(x.size - 1, 0)
     lam, loc = np.empty(k), np.empty(k)
-    st = _load().fho_lebesgue_max(_p(x), x.size, int(d), None if wp is None else _p(wp),
-                                  int(samples), int(rounds), _p(lam), _p(loc), int(nthreads))
+    st = _load().fho_lebesgue_max(
+        _p(x), x.size, int(d), None if wp is None else _p(wp), int(samples), int(rounds),
+        None if ks is None else ks.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), k,
+        _p(lam), _p(loc), int(nthreads))
     if st:
         raise OracleError(st)
     if x.size == 1:

@@ -79,6 +79,10 @@ size_t fh_workspace_size(int32_t op, int64_t n, int64_t m, int32_t d, int32_t pr
       BackwardBufs b;
       return layout_backward(nullptr, n, m, prec == FH_FP32_SPLIT, &t, &b);
     }
+    case FH_OP_LEBESGUE_MAX: {
+      double *lam, *xk;
+      return layout_lebesgue_max(nullptr, n, &t, &lam, &xk);
+    }
     default: return 0;
   }
 }
@@ -160,6 +164,29 @@ fh_status fh_lebesgue(const double* nodes, int64_t n, int32_t d, const double* x
   if (m > 0 && lambda_out == nullptr) return FH_E_ARG;
   return eval_common(nodes, nullptr, n, d, x, m, nullptr, lambda_out, w, prec, ws, ws_bytes,
                      stream);
+}
+
+fh_status fh_lebesgue_max(const double* nodes, int64_t n, int32_t d, const double* w,
+                          int32_t samples, int32_t rounds, double* lam_out, double* x_out,
+                          double* best_out, int32_t prec, void* ws, size_t ws_bytes,
+                          void* stream) {
+  fh_status st = check_problem(nodes, n, d);
+  if (st != FH_OK) return st;
+  if (samples < 1 || samples > 512 || rounds < 1 || rounds > 64) return FH_E_ARG;
+  if (lam_out == nullptr && x_out == nullptr && best_out == nullptr) return FH_E_ARG;
+  if (prec == FH_FP32_SPLIT) return FH_E_UNSUPPORTED;
+  if (prec != FH_FP64) return FH_E_ARG;
+  st = check_ws(ws, ws_bytes, fh_workspace_size(FH_OP_LEBESGUE_MAX, n, 0, d, prec));
+  if (st != FH_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  NodeTable t;
+  double *lam, *xk;
+  layout_lebesgue_max(ws, n, &t, &lam, &xk);
+  hipError_t e = launch_pack(nodes, nullptr, w, n, d, t, false, static_cast<uint32_t*>(ws), s);
+  if (e == hipSuccess)
+    e = launch_lebesgue_max(t, n, samples, rounds, lam_out ? lam_out : lam, x_out ? x_out : xk,
+                            best_out, s);
+  return finish(e, ws, s);
 }
 
 fh_status fh_eval_deriv(const double* nodes, const double* values, int64_t n, int32_t d,

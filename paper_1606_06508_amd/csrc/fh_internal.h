@@ -102,6 +102,14 @@ hipError_t launch_eval_deriv(const double* x, int64_t m, const NodeTable& t, int
                              double* dr, hipStream_t s);
 hipError_t launch_eval_deriv_split(const double* x, int64_t m, const NodeTable& t, int64_t n,
                                    const int32_t* scale, double* r, double* dr, hipStream_t s);
+// Workspace layout of FH_OP_LEBESGUE_MAX: node tables, then per-interval
+// maxima and their locations ([n-1] each).  Returns bytes used.
+size_t layout_lebesgue_max(void* ws, int64_t n, NodeTable* t, double** lam, double** xk);
+// Per-interval maxima of Lambda (lam, xk: [n-1], not null) by the grid zoom
+// of `rounds` rounds of `samples` samples; best (if not null) = {the
+// constant, its location}.
+hipError_t launch_lebesgue_max(const NodeTable& t, int64_t n, int32_t samples, int32_t rounds,
+                               double* lam, double* xk, double* best, hipStream_t s);
 hipError_t launch_eval_split(const double* x, int64_t m, const NodeTable& t, int64_t n,
                              const int32_t* scale, double* r, double* lam, const EvalConfig& cfg,
                              hipStream_t s);

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libfh.so")
 FH_OK, FH_E_ARG, FH_E_DEGREE, FH_E_NODES, FH_E_NONFINITE, FH_E_RANGE = 0, 1, 2, 3, 4, 5
 FH_E_WORKSPACE, FH_E_HIP, FH_E_UNSUPPORTED = 6, 7, 8
 FH_FP64, FH_FP32_SPLIT = 0, 1
-FH_OP_WEIGHTS, FH_OP_EVAL, FH_OP_BACKWARD = 0, 1, 2
+FH_OP_WEIGHTS, FH_OP_EVAL, FH_OP_BACKWARD, FH_OP_LEBESGUE_MAX = 0, 1, 2, 3
 PRECISIONS = {"fp64": FH_FP64, "split": FH_FP32_SPLIT, "fp32_split": FH_FP32_SPLIT}
 FH_TUNE_BATCHED_FP64, FH_TUNE_BATCHED_SPLIT = 2, 3
 # kernel families of the tuner: the two precisions of fh_eval and the two of
@@ -59,6 +59,8 @@ def load():
                                  ctypes.c_int),
             "fh_eval_deriv": ([vp, vp, i64, i32, vp, i64, vp, vp, vp, i32, vp, sz, vp],
                               ctypes.c_int),
+            "fh_lebesgue_max": ([vp, i64, i32, vp, i32, i32, vp, vp, vp, i32, vp, sz, vp],
+                                ctypes.c_int),
             "fh_batch_create": ([ctypes.POINTER(vp), i32, ctypes.POINTER(i64),
                                  ctypes.POINTER(i32), ctypes.POINTER(i64), vp, vp, vp, vp, vp, i32,
                                  vp], ctypes.c_int),
@@ -227,6 +229,28 @@ def eval_deriv(nodes, values, d, x, *, want_r=True, weights=None, precision="fp6
                              _ptr(weights), prec, _ptr(buf), buf.numel(), _stream(t.device)),
            "fh_eval_deriv")
     return r, dr
+
+
+def lebesgue_max(nodes, d, *, samples=256, rounds=5, weights=None, per_interval=True, ws=None):
+    """Lebesgue constant by the grid zoom of fh_lebesgue_max: returns
+    (lam[n-1], loc[n-1], best[2]) with the per-interval maxima and their
+    locations (None, None when per_interval is False) and best = {the
+    constant, its location}, all on the nodes' device."""
+    lib = load()
+    xn = _f64(nodes, "nodes")
+    n = xn.numel()
+    if weights is not None:
+        weights = _f64(weights, "weights")
+    k = max(n - 1, 0)
+    lam = torch.empty(k, dtype=torch.float64, device=xn.device) if per_interval else None
+    loc = torch.empty(k, dtype=torch.float64, device=xn.device) if per_interval else None
+    best = torch.empty(2, dtype=torch.float64, device=xn.device)
+    ws = ws or default_workspace(xn.device)
+    buf = ws.reserve(workspace_size(FH_OP_LEBESGUE_MAX, n, 0, d, FH_FP64))
+    _check(lib.fh_lebesgue_max(_ptr(xn), n, int(d), _ptr(weights), int(samples), int(rounds),
+                               _ptr(lam), _ptr(loc), _ptr(best), FH_FP64, _ptr(buf), buf.numel(),
+                               _stream(xn.device)), "fh_lebesgue_max")
+    return lam, loc, best
 
 
 def eval_backward(nodes, values, d, x, grad_r, *, need_values=True, need_x=True,

@@ -29,6 +29,11 @@ Workloads (the shapes of the evaluation study this library is measured on):
            carry one NaN component.
   quats    near-unit quaternions: a uniform random unit quaternion (Shoemake's
            parametrisation by three uniforms) times 1 + U[-1e-3, 1e-3].
+  lebesgue a table of node sets for Lebesgue constants: for n in
+           {65, 257, 1025, 4097} and d = 0..10, equispaced nodes and
+           jittered equispaced nodes (interior nodes moved by 0.3 of the
+           spacing times U[-1,1]); Chebyshev second-kind nodes for d <= 3
+           (larger d on these nodes has Lebesgue constants beyond 1/u).
 
 Every generator takes the sizes as arguments, so tests draw the same recipe
 at reduced sizes.
@@ -37,7 +42,7 @@ import numpy as np
 
 SEED_BASE = 1606065080
 
-WORKLOADS = ("runge", "sines", "split", "batched", "grad", "vectors", "quats")
+WORKLOADS = ("runge", "sines", "split", "batched", "grad", "vectors", "quats", "lebesgue")
 
 
 def rng(workload: str, salt: int = 0) -> np.random.Generator:
@@ -242,3 +247,20 @@ def nrm_vectors_device(n: int, dim: int, dtype: str, device, salt: int = 0,
     x[nan_rows, cols] = float("nan")
     del mant, e, e_com, half, balanced
     return x.contiguous()
+
+
+def lebesgue_workload(ns=(65, 257, 1025, 4097), ds=tuple(range(11)), rel: float = 0.3,
+                      cheb_dmax: int = 3, salt: int = 0):
+    """List of {"family", "n", "d", "nodes"} (see the module docstring)."""
+    g = rng("lebesgue", salt)
+    out = []
+    for n in ns:
+        jit = jittered_nodes(n, g, rel)
+        for d in ds:
+            if d > n - 1:
+                continue
+            out.append({"family": "equispaced", "n": n, "d": d, "nodes": equispaced(n)})
+            out.append({"family": "jittered", "n": n, "d": d, "nodes": jit})
+            if d <= cheb_dmax:
+                out.append({"family": "cheb2", "n": n, "d": d, "nodes": cheb2(n)})
+    return out

@@ -98,6 +98,31 @@ def test_weights_and_lebesgue_host_validation():
     assert lib.fh_lebesgue(P, 5, 7, P, 10, P2, None, 0, P, 1 << 20, None) == fh.FH_E_DEGREE
 
 
+def test_lebesgue_max_host_validation_and_workspace():
+    lib = fh.load()
+    a = lib.fh_workspace_size(fh.FH_OP_EVAL, 1001, 0, 3, 0)
+    b = lib.fh_workspace_size(fh.FH_OP_LEBESGUE_MAX, 1001, 0, 3, 0)
+    assert b >= a + 2 * 8 * 1000 and b % 256 == 0
+    assert lib.fh_workspace_size(fh.FH_OP_LEBESGUE_MAX, 1, 0, 0, 0) > 0
+
+    def call(**kw):
+        a = dict(nodes=P, n=10, d=3, w=None, samples=256, rounds=5, lam=P2, loc=None, best=None,
+                 prec=0, ws=P, ws_bytes=1 << 30)
+        a.update(kw)
+        return lib.fh_lebesgue_max(a["nodes"], a["n"], a["d"], a["w"], a["samples"], a["rounds"],
+                                   a["lam"], a["loc"], a["best"], a["prec"], a["ws"],
+                                   a["ws_bytes"], None)
+
+    assert call(nodes=None) == fh.FH_E_ARG
+    assert call(d=10) == fh.FH_E_DEGREE
+    for bad in (dict(samples=0), dict(samples=513), dict(rounds=0), dict(rounds=65),
+                dict(lam=None), dict(prec=4)):
+        assert call(**bad) == fh.FH_E_ARG, bad
+    assert call(prec=1) == fh.FH_E_UNSUPPORTED
+    assert call(ws=None) == fh.FH_E_WORKSPACE
+    assert call(ws_bytes=300) == fh.FH_E_WORKSPACE
+
+
 def test_variant_tables_and_tuner_api():
     """The tuner interface: enumerate variants, record / override / release
     a choice, and reject bad arguments -- all host-side."""

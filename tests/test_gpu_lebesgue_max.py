@@ -1,0 +1,116 @@
+"""The Lebesgue constant (fh_lebesgue_max) against the oracle's grid zoom.
+
+Both sides sample the same points in the first round (same formula, same
+rounding), so with one round the maxima agree to the evaluation tolerance
+of Lambda and the locations agree exactly wherever the best sample is not
+a near-tie.  With more rounds the two searches may zoom into neighbouring
+brackets after a near-tie, so the maxima are compared to the evaluation
+tolerance (the final grid spacing is far below its resolution) and every
+GPU location is checked to be valid: the oracle's Lambda there reaches the
+oracle's maximum within the same tolerance.  The full-size table of the
+benchmark is checked on sampled intervals."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle
+from paper_1606_06508_amd import fh, inputs
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def _tol(lam):
+    """e_cond bar of Lambda: 1e-13 Lambda (1 + Lambda)."""
+    return 1e-13 * lam * (1.0 + lam)
+
+
+def _gpu(nodes, d, samples, rounds):
+    lam, loc, best = fh.lebesgue_max(_t(nodes), d, samples=samples, rounds=rounds)
+    torch.cuda.synchronize()
+    return lam.cpu().numpy(), loc.cpu().numpy(), best.cpu().numpy()
+
+
+def _check(nodes, d, samples, rounds, ks=None):
+    lam, loc, best = _gpu(nodes, d, samples, rounds)
+    lam_o, loc_o, (best_o, _) = oracle.lebesgue_max(nodes, d, samples, rounds, intervals=ks)
+    if ks is not None:
+        lam, loc = lam[ks], loc[ks]
+    assert np.all(np.isfinite(lam)) and np.all(np.isfinite(loc))
+    assert np.all(np.abs(lam - lam_o) <= _tol(lam_o)), np.max(np.abs(lam - lam_o) / _tol(lam_o))
+    k = np.arange(nodes.size - 1) if ks is None else np.asarray(ks)
+    assert np.all((loc > nodes[k]) & (loc < nodes[k + 1]))
+    _, lam_at, _ = oracle.evaluate(nodes, np.zeros_like(nodes), d, loc)
+    assert np.all(lam_at >= lam_o - 2 * _tol(lam_o))
+    if ks is None:
+        assert abs(best[0] - best_o) <= _tol(best_o)
+        assert best[0] == lam.max() and best[1] == loc[int(np.argmax(lam))]
+    if rounds == 1 and k.size >= 20:
+        # identical samples: the same sample wins except at near-ties
+        assert np.mean(loc == loc_o) >= 0.9
+    return lam, loc
+
+
+@pytest.mark.parametrize("rounds", [1, 5])
+@pytest.mark.parametrize("samples", [1, 64, 100, 256, 512])
+def test_equispaced_against_oracle(samples, rounds):
+    for n, d in ((2, 1), (3, 2), (17, 0), (101, 3), (301, 8)):
+        _check(inputs.equispaced(n), d, samples, rounds)
+
+
+@pytest.mark.parametrize("family,n,d", [("cheb2", 200, 3), ("jittered", 513, 5),
+                                        ("jittered", 64, 10), ("cheb2", 9, 8)])
+def test_node_families_against_oracle(family, n, d):
+    nodes = inputs.cheb2(n) if family == "cheb2" else \
+        inputs.jittered_nodes(n, np.random.default_rng(n + d), rel=0.3)
+    for samples, rounds in ((256, 5), (65, 1), (33, 6)):
+        _check(nodes, d, samples, rounds)
+
+
+@pytest.mark.parametrize("n", [2050, 2600, 4098, 4600])
+def test_node_split_variants(n):
+    """Interval counts on both sides of the node-split thresholds (2048 and
+    4096 intervals), on sampled intervals."""
+    nodes = inputs.jittered_nodes(n, np.random.default_rng(n), rel=0.3)
+    ks = np.unique(np.concatenate([[0, 1, n - 3, n - 2],
+                                   np.random.default_rng(1).choice(n - 1, 60, replace=False)]))
+    _check(nodes, 4, 128, 1, ks)
+    _check(nodes, 4, 128, 5, ks)
+
+
+def test_single_and_two_nodes():
+    lam, loc, best = fh.lebesgue_max(_t(np.array([0.375])), 0)
+    torch.cuda.synchronize()
+    assert lam.numel() == 0 and best.cpu().tolist() == [1.0, 0.375]
+    for d in (0, 1):
+        lam, loc, best = _gpu(np.array([-0.75, 2.5]), d, 33, 3)
+        assert abs(lam[0] - 1.0) <= 4 * 2.0 ** -53 and -0.75 < loc[0] < 2.5
+
+
+def test_given_weights_and_best_only():
+    nodes = inputs.equispaced(129)
+    w = oracle.weights(nodes, 3)
+    lam, loc, best = _gpu(nodes, 3, 128, 4)
+    lam2, loc2, best2 = fh.lebesgue_max(_t(nodes), 3, samples=128, rounds=4,
+                                        weights=_t(np.ldexp(w, 9)))
+    _, _, best3 = fh.lebesgue_max(_t(nodes), 3, samples=128, rounds=4, per_interval=False)
+    torch.cuda.synchronize()
+    # a power-of-two weight scale changes no bit
+    assert np.array_equal(lam, lam2.cpu().numpy()) and np.array_equal(loc, loc2.cpu().numpy())
+    assert np.array_equal(best, best3.cpu().numpy())
+
+
+def test_full_table_sampled():
+    """The benchmark's table (256 samples, 5 rounds): every configuration
+    with n <= 257 in full, the larger ones on 24 sampled intervals."""
+    g = np.random.default_rng(4)
+    for c in inputs.lebesgue_workload():
+        n = c["n"]
+        ks = None if n <= 257 else np.unique(np.concatenate(
+            [[0, n - 2], g.choice(n - 1, 22, replace=False)]))
+        _check(c["nodes"], c["d"], 256, 5, ks)

@@ -177,3 +177,14 @@ def test_errors():
             oracle.lebesgue_max(nodes, 2, **kw)
     with pytest.raises(oracle.OracleError):
         oracle.lebesgue_max(nodes, 5)
+
+
+def test_interval_subset_gives_the_same_values():
+    nodes = inputs.jittered_nodes(300, np.random.default_rng(3), rel=0.3)
+    lam, loc, _ = oracle.lebesgue_max(nodes, 4, samples=64, rounds=3)
+    ks = np.array([298, 0, 17, 150, 17])
+    lam2, loc2, (best, at) = oracle.lebesgue_max(nodes, 4, samples=64, rounds=3, intervals=ks)
+    assert np.array_equal(lam2, lam[ks]) and np.array_equal(loc2, loc[ks])
+    assert best == lam[ks].max()
+    with pytest.raises(oracle.OracleError):
+        oracle.lebesgue_max(nodes, 4, intervals=[299])
