@@ -189,7 +189,7 @@ __global__ void __launch_bounds__(kStage)
       N[j] = D[j] = A[j] = 0.0;
       bad[j] = !in_split_domain(xp[j], x_first, x_last);
     }
-    split_block_sums<P, R, L>(stage, s4 + ds.toff, ds.n_pad, mask, xh, xl, N, D, A, bad);
+    split_block_sums<P, R, L, 4>(stage, s4 + ds.toff, ds.n_pad, mask, xh, xl, N, D, A, bad);
 #pragma unroll
     for (int j = 0; j < P; ++j) {
       const int64_t idx = base + j * kStage;
@@ -212,7 +212,7 @@ int batched_variant_count() { return 3; }
 void batched_variant_shape(int id, int* p, int* g, int* s, bool split) {
   static const int P[3] = {1, 2, 4};
   *p = (id >= 0 && id < 3) ? P[id] : 0;
-  *g = split ? 1 : 8;
+  *g = split ? 4 : 8;  // split: binary32 simultaneous inversion of node quads
   *s = 1;
 }
 

@@ -6,7 +6,11 @@
 //    the head difference is exact (Sterbenz), so points that sit next to a
 //    node still get an accurate difference; a plain binary32 difference
 //    would round such points onto the node.
-//  - t = 1/delta with v_rcp_f32 (within one ulp on gfx950, no refinement).
+//  - t = 1/delta with v_rcp_f32 (within one ulp on gfx950, no refinement),
+//    per difference (G = 1) or by simultaneous inversion of the four
+//    differences of a node quad (G = 4: one v_rcp_f32 of their product and
+//    nine multiplications, about six binary32 roundings per t; a product
+//    that is not a normal number flags the lane).
 //  - Weights w_k and weighted values w_k f_k are the binary64 ones scaled
 //    by exact powers of two 2^-e and 2^-ef and rounded to binary32 (packing
 //    kernel); r = 2^(ef - e) N / D and Lambda = L / |D| restore them exactly.
@@ -34,7 +38,7 @@
 
 namespace fhk {
 
-template <int P, bool R, bool L>
+template <int P, int G, bool R, bool L>
 __global__ void __launch_bounds__(kStage)
     k_eval_split(const double* __restrict__ x, int64_t m, const float4* __restrict__ s4,
                  int64_t n_pad, const double* __restrict__ tx, const double* __restrict__ tw,
@@ -61,7 +65,7 @@ __global__ void __launch_bounds__(kStage)
     bad[j] = !in_split_domain(xp[j], x_first, x_last);
   }
 
-  split_block_sums<P, R, L>(stage, s4, n_pad, mask, xh, xl, N, D, A, bad);
+  split_block_sums<P, R, L, G>(stage, s4, n_pad, mask, xh, xl, N, D, A, bad);
   const int shift = scale[1];
 
 #pragma unroll
@@ -80,44 +84,45 @@ __global__ void __launch_bounds__(kStage)
   }
 }
 
-template <int P>
+template <int P, int G>
 static hipError_t launch_v(const double* x, int64_t m, const NodeTable& t, int64_t n,
                            const int32_t* sc, double* r, double* lam, hipStream_t s) {
   const int64_t per = (int64_t)kStage * P;
   const dim3 grid((unsigned)((m + per - 1) / per)), block(kStage);
   if (r && lam)
-    k_eval_split<P, true, true><<<grid, block, 0, s>>>(x, m, t.s, t.n_pad, t.x, t.w, t.f, n, sc,
-                                                       r, lam);
+    k_eval_split<P, G, true, true><<<grid, block, 0, s>>>(x, m, t.s, t.n_pad, t.x, t.w, t.f, n,
+                                                          sc, r, lam);
   else if (r)
-    k_eval_split<P, true, false><<<grid, block, 0, s>>>(x, m, t.s, t.n_pad, t.x, t.w, t.f, n, sc,
-                                                        r, lam);
+    k_eval_split<P, G, true, false><<<grid, block, 0, s>>>(x, m, t.s, t.n_pad, t.x, t.w, t.f, n,
+                                                           sc, r, lam);
   else
-    k_eval_split<P, false, true><<<grid, block, 0, s>>>(x, m, t.s, t.n_pad, t.x, t.w, t.f, n, sc,
-                                                        r, lam);
+    k_eval_split<P, G, false, true><<<grid, block, 0, s>>>(x, m, t.s, t.n_pad, t.x, t.w, t.f, n,
+                                                           sc, r, lam);
   return hipGetLastError();
 }
 
-// Variant table: id -> points per lane P (node split is always 1 here:
-// all waves of a block share the staged node tile).
-#define FH_SPLIT_VARIANTS(X) X(0, 1) X(1, 2) X(2, 4) X(3, 8)
+// Variant table: id -> (points per lane P, reciprocal group G); the node
+// split is always 1 here (all waves of a block share the staged node tile).
+#define FH_SPLIT_VARIANTS(X) \
+  X(0, 1, 1) X(1, 2, 1) X(2, 4, 1) X(3, 8, 1) X(4, 1, 4) X(5, 2, 4) X(6, 4, 4) X(7, 8, 4)
 
 int split_variant_count() {
-#define FH_COUNT(id, p) +1
+#define FH_COUNT(id, p, g) +1
   return 0 FH_SPLIT_VARIANTS(FH_COUNT);
 #undef FH_COUNT
 }
 
 void split_variant_shape(int id, int* p, int* g, int* s) {
-  *g = 1;
   *s = 1;
   switch (id) {
-#define FH_SHAPE(vid, vp) \
-  case vid:               \
-    *p = vp;              \
+#define FH_SHAPE(vid, vp, vg) \
+  case vid:                   \
+    *p = vp;                  \
+    *g = vg;                  \
     return;
     FH_SPLIT_VARIANTS(FH_SHAPE)
 #undef FH_SHAPE
-    default: *p = 0;
+    default: *p = *g = 0;
   }
 }
 
@@ -126,8 +131,8 @@ hipError_t launch_eval_split(const double* x, int64_t m, const NodeTable& t, int
                              hipStream_t s) {
   if (m == 0) return hipSuccess;
   switch (cfg.variant) {
-#define FH_CASE(vid, vp) \
-  case vid: return launch_v<vp>(x, m, t, n, scale, r, lam, s);
+#define FH_CASE(vid, vp, vg) \
+  case vid: return launch_v<vp, vg>(x, m, t, n, scale, r, lam, s);
     FH_SPLIT_VARIANTS(FH_CASE)
 #undef FH_CASE
     default: return hipErrorInvalidValue;

@@ -55,8 +55,8 @@ struct Builtin {
 };
 constexpr Builtin kBuiltin[] = {
     {FH_FP64, 6, 14, 7},       {FH_FP64, 10, 20, 12},      {FH_FP64, 12, 20, 10},
-    {FH_FP64, 13, 24, 4},      {FH_FP32_SPLIT, 6, 14, 1},  {FH_FP32_SPLIT, 10, 20, 0},
-    {FH_FP32_SPLIT, 12, 20, 0}, {FH_FP32_SPLIT, 13, 24, 1},
+    {FH_FP64, 13, 24, 4},      {FH_FP32_SPLIT, 6, 14, 5},  {FH_FP32_SPLIT, 10, 20, 5},
+    {FH_FP32_SPLIT, 12, 20, 5}, {FH_FP32_SPLIT, 13, 24, 5},
 };
 
 // Untuned shapes: small point sets split the node range over the waves of a
@@ -66,7 +66,7 @@ int default_variant(int32_t prec, int nb, int mb) {
   for (const Builtin& b : kBuiltin)
     if (b.prec == prec && b.nb == nb && b.mb == mb) return b.variant;
   if (prec == FH_TUNE_BATCHED_FP64 || prec == FH_TUNE_BATCHED_SPLIT) return 1;  // P = 2
-  if (prec == FH_FP32_SPLIT) return mb <= 16 ? 2 : (mb <= 22 ? 0 : 1);
+  if (prec == FH_FP32_SPLIT) return mb <= 16 ? 6 : 5;  // P = 4 / 2, quads inverted together
   return mb <= 16 ? 10 : (mb <= 22 ? 12 : 4);
 }
 

@@ -53,7 +53,7 @@ def test_instances_against_oracle(precision):
     b.close()
 
 
-@pytest.mark.parametrize("precision,single_variant", [("fp64", 4), ("split", 1)])
+@pytest.mark.parametrize("precision,single_variant", [("fp64", 4), ("split", 5)])
 def test_bitwise_equal_to_single_kernel(precision, single_variant):
     """The batched kernel (2 points per lane) runs, per point, exactly the
     operations of the single-interpolant variant with 2 points per lane and
