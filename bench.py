@@ -443,7 +443,9 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    # 25 untimed steps (~60 ms): the kernel time settles only after ~30 ms
+    # of back-to-back work (clock ramp), 290 us -> 225 us per launch
+    ap.add_argument("--warmup", type=int, default=25)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")

@@ -72,15 +72,16 @@ def test_node_families_against_oracle(family, n, d):
         _check(nodes, d, samples, rounds)
 
 
-@pytest.mark.parametrize("n", [2050, 2600, 4098, 4600])
-def test_node_split_variants(n):
+@pytest.mark.parametrize("n,samples", [(2050, 128), (2600, 33), (4098, 128), (4600, 512),
+                                       (3000, 512), (700, 300)])
+def test_node_split_variants(n, samples):
     """Interval counts on both sides of the node-split thresholds (2048 and
-    4096 intervals), on sampled intervals."""
+    4096 intervals) and every samples-per-lane shape, on sampled intervals."""
     nodes = inputs.jittered_nodes(n, np.random.default_rng(n), rel=0.3)
     ks = np.unique(np.concatenate([[0, 1, n - 3, n - 2],
                                    np.random.default_rng(1).choice(n - 1, 60, replace=False)]))
-    _check(nodes, 4, 128, 1, ks)
-    _check(nodes, 4, 128, 5, ks)
+    _check(nodes, 4, samples, 1, ks)
+    _check(nodes, 4, samples, 5, ks)
 
 
 def test_single_and_two_nodes():
