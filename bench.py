@@ -58,15 +58,18 @@ def _src_hash(paths):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(n_launch_pairs):
+def measured_traffic(n, m):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when it is missing or was taken on a different kernel source."""
+    None when it is missing or was taken on a different kernel source or
+    launch variant than the one this run uses."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
     if rec.get("src_sha256_16") != _src_hash(EVAL_SRC):
+        return None
+    if rec.get("variant") != fh.tune_get("fp64", n, m):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -492,7 +495,7 @@ def main():
                    "n": n, "m": m, "degrees": "0..8", "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": measured_traffic(n * m),
+                     "traffic": measured_traffic(n, m),
                      "kernel": "k_eval_f64 (fused r + Lebesgue, FP64)",
                      "kernel_ms_avg": k_ms,
                      "kernel_Gpair_s": n * m / (k_ms * 1e-3) / 1e9,

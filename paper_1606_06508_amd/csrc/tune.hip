@@ -54,7 +54,7 @@ struct Builtin {
   int variant;
 };
 constexpr Builtin kBuiltin[] = {
-    {FH_FP64, 6, 14, 7},       {FH_FP64, 10, 20, 12},      {FH_FP64, 12, 20, 10},
+    {FH_FP64, 6, 14, 7},       {FH_FP64, 10, 20, 10},      {FH_FP64, 12, 20, 10},
     {FH_FP64, 13, 24, 4},      {FH_FP32_SPLIT, 6, 14, 5},  {FH_FP32_SPLIT, 10, 20, 5},
     {FH_FP32_SPLIT, 12, 20, 5}, {FH_FP32_SPLIT, 13, 24, 5},
 };
