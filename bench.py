@@ -141,11 +141,62 @@ def cpu_baseline(case, gpu_r, gpu_lam, target_s):
     el = time.perf_counter() - t
     pairs = 9 * n * m_s
     stats = metrics.parity(gpu_r[:m_s], gpu_lam[:m_s], r_o, lam_o, s_o)
+    # one thread on a small sample (d = 4)
+    one = pts[:max(1000, min(m_s, int(1.5 / (per_point * oracle.threads()))))]
+    t = time.perf_counter()
+    oracle.evaluate(nodes, vals, 4, one, nthreads=1)
+    el1 = time.perf_counter() - t
     base = {"value": pairs / el / 1e9, "unit": "Gpair/s", "cores": oracle.threads(),
             "kind": "oracle",
             "sample": f"first {m_s} of the 10^6 points, all 9 degrees, n={n} "
-                      f"(compensated FP64, {el:.1f} s)"}
+                      f"(compensated FP64, {el:.1f} s)",
+            "single_core_value": n * one.size / el1 / 1e9,
+            "single_core_sample": f"first {one.size} points, d=4, one thread",
+            **host_cpu()}
     return base, stats
+
+
+def host_cpu():
+    """CPU model and logical/physical counts of this host (/proc/cpuinfo)."""
+    model, logical, cores = None, 0, set()
+    phys = core = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                key, _, val = line.partition(":")
+                key, val = key.strip(), val.strip()
+                if key == "model name":
+                    model = model or val
+                    logical += 1
+                elif key == "physical id":
+                    phys = val
+                elif key == "core id":
+                    core = val
+                    cores.add((phys, core))
+    except OSError:
+        pass
+    return {"cpu_model": model, "host_logical_cpus": logical,
+            "host_physical_cores": len(cores) or None}
+
+
+def launch_overheads(dev, reps=200):
+    """Time of an (almost) empty kernel launch and of an empty one-kernel
+    graph replay on this machine: the launch cost that the per-launch figures
+    contain (the analogue of subtracting an empty loop)."""
+    t = torch.zeros(1, dtype=torch.float64, device=dev)
+    ms_k = _time_ms(lambda: t.add_(0.0), reps)
+    side = torch.cuda.Stream(dev)
+    side.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(side):
+        t.add_(0.0)
+    torch.cuda.current_stream(dev).wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        t.add_(0.0)
+    ms_g = _time_ms(g.replay, reps)
+    return {"empty_kernel_us": ms_k * 1e3, "empty_graph_us": ms_g * 1e3,
+            "how": "1-element add_ launched, and replayed as a captured graph, "
+                   f"{reps} times back to back; mean per launch"}
 
 
 def run_split_forms(dev, reps, with_cpu):
@@ -510,6 +561,7 @@ def main():
         line["max_error"] = {"vs": "FP64 oracle on the CPU-baseline sample, d=8",
                              **{k: v for k, v in stats.items() if k.startswith("e_")}}
         print("[bench] cpu baseline done", file=sys.stderr, flush=True)
+    line["launch_overheads"] = launch_overheads(dev)
     if not args.no_forms:
         forms = {"split_workload": run_split_forms(dev, 5, not args.no_cpu_baseline)}
         print("[bench] split form done", file=sys.stderr, flush=True)
