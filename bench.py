@@ -20,7 +20,8 @@ Also reported in the same JSON line:
                 the batched graph launch over 4096 uneven interpolants vs a
                 per-instance fh_eval loop; the adjoint and the derivative
                 r' on 2049 nodes and 10^6 points; normalization of 10^8
-                vectors; Lebesgue constants of a node-family table.
+                vectors; Lebesgue constants of a node-family table; several
+                interpolants on the same nodes and points in one launch.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -343,6 +344,51 @@ def run_backward_form(dev, reps, with_cpu):
     return out
 
 
+def run_multi_form(dev, reps, with_cpu):
+    """Several interpolants on the same nodes and points in one launch
+    (fh_eval_multi), against one fh_eval per interpolant on the same stream:
+    the headline's sweep over d = 0..8 (separate weights, r and Lambda), and
+    vector-valued data (16 value columns, d = 4, shared weights).  Both
+    sides produce the same bits (the multi kernel runs the per-pair
+    operations of single-kernel variant 3), which with_cpu checks."""
+    c = inputs.sines_workload()
+    n, m = c["nodes"].size, c["points"].size
+    nodes, x = _t(c["nodes"], dev), _t(c["points"], dev)
+    out = {"workload": f"multi: sines nodes n={n}, m={m} points"}
+    g = np.random.default_rng(7)
+    cases = {"degree_sweep_0_8": (np.tile(c["values"], (9, 1)), list(range(9)), True),
+             "vector_valued_16_d4": (g.standard_normal((16, n)), [4] * 16, False)}
+    for name, (vals, degs, lebesgue) in cases.items():
+        K = len(degs)
+        v = _t(vals, dev)
+        ws = fh.Workspace(dev, fh.multi_workspace_size(n, K))
+        ms = _time_ms(lambda: fh.eval_multi(nodes, v, degs, x, lebesgue=lebesgue, ws=ws), reps)
+        ws1 = fh.Workspace(dev, fh.workspace_size(fh.FH_OP_EVAL, n, m, max(degs)))
+        outs = [torch.empty_like(x) for _ in range(K)]
+        lams = [torch.empty_like(x) for _ in range(K)] if lebesgue else [None] * K
+
+        def loop():
+            for k in range(K):
+                fh.evaluate(nodes, v[k], degs[k], x, lebesgue=lebesgue, ws=ws1, out=outs[k],
+                            lambda_out=lams[k])
+
+        ms_loop = _time_ms(loop, reps)
+        pairs = K * n * m
+        out[name] = {"K": K, "lebesgue": lebesgue, "ms": ms, "Gpair_s": pairs / (ms * 1e-3) / 1e9,
+                     "one_call_per_interpolant_ms": ms_loop,
+                     "one_call_per_interpolant_Gpair_s": pairs / (ms_loop * 1e-3) / 1e9,
+                     "speedup": ms_loop / ms}
+        if with_cpu:
+            r, lam = fh.eval_multi(nodes, v, degs, x, lebesgue=lebesgue, ws=ws)
+            fh.tune_force("fp64", 3)
+            try:
+                same = all(torch.equal(r[k], fh.evaluate(nodes, v[k], degs[k], x)) for k in (0, K - 1))
+            finally:
+                fh.tune_force("fp64", -1)
+            out[name]["bitwise_equal_to_single_variant_3"] = bool(same)
+    return out
+
+
 FLOPS_PER_PAIR_L = 5  # sub, div, mul (a = w t), add (D), add (L)
 
 
@@ -507,7 +553,7 @@ def main():
                     help="only run a plain 1 GiB device copy (the reference dispatch that "
                          "scales the HBM byte counters)")
     ap.add_argument("--profile-form", choices=("split", "batched", "grad", "normalize",
-                                               "lebesgue"),
+                                               "lebesgue", "multi"),
                     help="only run one secondary form's timed loops (--steps repetitions, "
                          "no CPU work), for kernel profiles")
     args = ap.parse_args()
@@ -518,7 +564,7 @@ def main():
         dev = torch.device("cuda:0")
         run = {"split": run_split_forms, "batched": run_batched_form,
                "grad": run_backward_form, "normalize": run_normalize_form,
-               "lebesgue": run_lebesgue_form}[args.profile_form]
+               "lebesgue": run_lebesgue_form, "multi": run_multi_form}[args.profile_form]
         print(json.dumps({args.profile_form: run(dev, args.steps, False)}))
         return
     if args.gpus != 1:
@@ -573,6 +619,8 @@ def main():
         print("[bench] normalize form done", file=sys.stderr, flush=True)
         forms["lebesgue"] = run_lebesgue_form(dev, 3, not args.no_cpu_baseline)
         print("[bench] lebesgue form done", file=sys.stderr, flush=True)
+        forms["multi"] = run_multi_form(dev, 5, not args.no_cpu_baseline)
+        print("[bench] multi form done", file=sys.stderr, flush=True)
         line["forms"] = forms
     print(json.dumps(line))
 

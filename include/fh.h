@@ -173,6 +173,24 @@ fh_status fh_lebesgue_max(const double* nodes, int64_t n, int32_t d, const doubl
                           int32_t samples, int32_t rounds, double* lam_out, double* x_out,
                           double* best_out, int32_t prec, void* ws, size_t ws_bytes, void* stream);
 
+/* Several interpolants on the same nodes and points in one call: column c
+ * (0 <= c < K) has degree d_host[c] and values values[c * n .. c * n + n - 1];
+ * r_out[c * m + p] = r_c(x_p) and, if lambda_out is not NULL,
+ * lambda_out[c * m + p] = Lambda_c(x_p).  The reciprocals 1 / (x_p - x_k)
+ * are computed once for all columns (a sweep over d, or vector-valued data:
+ * when all degrees are equal the weights, D and Lambda are shared too).
+ * Every column's results are those of fh_eval (FH_FP64) bit for bit with
+ * one point per lane, groups of eight and no node split (launch variant 3).
+ *   K        1..64;  d_host: host array of K degrees, each in 0..n-1
+ *   values   device [K][n];  r_out, lambda_out: device [K][m]
+ *   ws       fh_multi_workspace_size(n, K) bytes (status block as in fh_eval)
+ * Errors as in fh_eval (FH_E_DEGREE for a degree out of range). */
+size_t fh_multi_workspace_size(int64_t n, int32_t K);
+fh_status fh_eval_multi(const double* nodes, const double* values, int64_t n,
+                        const int32_t* d_host, int32_t K, const double* x, int64_t m,
+                        double* r_out, double* lambda_out, void* ws, size_t ws_bytes,
+                        void* stream);
+
 /* Derivative of the interpolant: r(x_p) (r_out, may be NULL) and r'(x_p)
  * (dr_out) at m points.  Away from the nodes r' = (r E - F) / D with
  * D = sum a_k, E = sum a_k / (x - x_k), F = sum a_k f_k / (x - x_k)

@@ -189,6 +189,36 @@ fh_status fh_lebesgue_max(const double* nodes, int64_t n, int32_t d, const doubl
   return finish(e, ws, s);
 }
 
+size_t fh_multi_workspace_size(int64_t n, int32_t K) {
+  if (n < 1 || K < 1 || K > kMultiMax) return 0;
+  MultiTable t;
+  return layout_multi(nullptr, n, K, &t);
+}
+
+fh_status fh_eval_multi(const double* nodes, const double* values, int64_t n,
+                        const int32_t* d_host, int32_t K, const double* x, int64_t m,
+                        double* r_out, double* lambda_out, void* ws, size_t ws_bytes,
+                        void* stream) {
+  if (n < 1 || nodes == nullptr || values == nullptr || d_host == nullptr) return FH_E_ARG;
+  if (K < 1 || K > kMultiMax) return FH_E_ARG;
+  if (m < 0 || (m > 0 && (x == nullptr || r_out == nullptr))) return FH_E_ARG;
+  MultiDegrees deg;
+  bool shared = true;
+  for (int32_t c = 0; c < K; ++c) {
+    if (d_host[c] < 0 || (int64_t)d_host[c] > n - 1) return FH_E_DEGREE;
+    deg.d[c] = d_host[c];
+    shared = shared && d_host[c] == d_host[0];
+  }
+  fh_status st = check_ws(ws, ws_bytes, fh_multi_workspace_size(n, K));
+  if (st != FH_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  MultiTable t;
+  layout_multi(ws, n, K, &t);
+  return finish(launch_multi(nodes, values, n, deg, K, shared, x, m, t, r_out, lambda_out,
+                             static_cast<uint32_t*>(ws), s),
+                ws, s);
+}
+
 fh_status fh_eval_deriv(const double* nodes, const double* values, int64_t n, int32_t d,
                         const double* x, int64_t m, double* r_out, double* dr_out,
                         const double* w, int32_t prec, void* ws, size_t ws_bytes, void* stream) {

@@ -78,6 +78,29 @@ BackwardPlan plan_backward(int64_t n, int64_t m, bool split);
 size_t layout_backward(void* ws, int64_t n, int64_t m, bool split, NodeTable* t,
                        BackwardBufs* b);
 
+// Several interpolants on the same nodes and points (fh_eval_multi).
+constexpr int kMultiMax = 64;
+struct MultiDegrees {
+  int32_t d[kMultiMax];
+};
+// Node tables of K columns (plus zero padding): x[n_pad] shared;
+// w[.][n_pad] (only row 0 used when every column has the same degree),
+// wf[.][n_pad] = w f, f[.][n_pad].
+struct MultiTable {
+  double *x, *w, *wf, *f;
+  int64_t n_pad;
+};
+size_t layout_multi(void* ws, int64_t n, int32_t K, MultiTable* t);
+// Columns the tables hold: K plus zero padding up to a whole number of
+// launch chunks.
+int64_t multi_padded_columns(int32_t K);
+// Packs the K tables, then evaluates r (and Lambda if lam) of every column:
+// r[c * m + p], lam[c * m + p].
+hipError_t launch_multi(const double* nodes, const double* values, int64_t n,
+                        const MultiDegrees& deg, int32_t K, bool shared, const double* x,
+                        int64_t m, const MultiTable& t, double* r, double* lam, uint32_t* status,
+                        hipStream_t s);
+
 // ---- launchers (each returns the launch error, hipSuccess on success) ----
 hipError_t launch_weights(const double* nodes, int64_t n, int32_t d, double* w_out,
                           uint32_t* status, hipStream_t s);

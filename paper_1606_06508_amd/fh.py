@@ -61,6 +61,9 @@ def load():
                               ctypes.c_int),
             "fh_lebesgue_max": ([vp, i64, i32, vp, i32, i32, vp, vp, vp, i32, vp, sz, vp],
                                 ctypes.c_int),
+            "fh_multi_workspace_size": ([i64, i32], sz),
+            "fh_eval_multi": ([vp, vp, i64, ctypes.POINTER(i32), i32, vp, i64, vp, vp, vp, sz,
+                               vp], ctypes.c_int),
             "fh_batch_create": ([ctypes.POINTER(vp), i32, ctypes.POINTER(i64),
                                  ctypes.POINTER(i32), ctypes.POINTER(i64), vp, vp, vp, vp, vp, i32,
                                  vp], ctypes.c_int),
@@ -229,6 +232,31 @@ def eval_deriv(nodes, values, d, x, *, want_r=True, weights=None, precision="fp6
                              _ptr(weights), prec, _ptr(buf), buf.numel(), _stream(t.device)),
            "fh_eval_deriv")
     return r, dr
+
+
+def multi_workspace_size(n, K):
+    return int(load().fh_multi_workspace_size(int(n), int(K)))
+
+
+def eval_multi(nodes, values, degrees, x, *, lebesgue=False, ws=None):
+    """K interpolants on the same nodes and points (fh_eval_multi): values is
+    a (K, n) tensor, degrees K ints; returns (r, Lambda or None), each (K, m)."""
+    lib = load()
+    xn, t = _f64(nodes, "nodes"), _f64(x, "x")
+    f = _f64(values, "values")
+    n, m = xn.numel(), t.numel()
+    degs = [int(v) for v in degrees]
+    K = len(degs)
+    if f.dim() != 2 or f.shape[0] != K or f.shape[1] != n:
+        raise ValueError("values must be (len(degrees), n)")
+    r = torch.empty((K, m), dtype=torch.float64, device=t.device)
+    lam = torch.empty((K, m), dtype=torch.float64, device=t.device) if lebesgue else None
+    ws = ws or default_workspace(t.device)
+    buf = ws.reserve(multi_workspace_size(n, K))
+    d_arr = (ctypes.c_int32 * K)(*degs)
+    _check(lib.fh_eval_multi(_ptr(xn), _ptr(f), n, d_arr, K, _ptr(t), m, _ptr(r), _ptr(lam),
+                             _ptr(buf), buf.numel(), _stream(t.device)), "fh_eval_multi")
+    return r, lam
 
 
 def lebesgue_max(nodes, d, *, samples=256, rounds=5, weights=None, per_interval=True, ws=None):

@@ -169,3 +169,26 @@ def test_normalize_entry_points_and_host_validation():
             assert fn(dummy, 4, dummy, dummy, 0, 4, None) == fh.FH_E_ARG   # method
             pivot = fn(dummy, 4, dummy, dummy, 0, 2, None) if dim != 3 else None
             assert dim == 3 or pivot == fh.FH_E_ARG                         # Algorithm 2 is 3D
+
+
+def test_multi_host_validation_and_workspace():
+    lib = fh.load()
+    one = lib.fh_workspace_size(fh.FH_OP_EVAL, 1001, 0, 3, 0)
+    assert lib.fh_multi_workspace_size(1001, 9) > one
+    assert lib.fh_multi_workspace_size(1001, 0) == 0 and lib.fh_multi_workspace_size(1001, 65) == 0
+    assert lib.fh_multi_workspace_size(0, 4) == 0
+
+    def call(K=3, degs=(1, 2, 3), n=10, **kw):
+        a = dict(nodes=P, values=P, x=P, m=100, r=P2, lam=None, ws=P, ws_bytes=1 << 30)
+        a.update(kw)
+        d = (ctypes.c_int32 * max(len(degs), 1))(*degs)
+        return lib.fh_eval_multi(a["nodes"], a["values"], n, d, K, a["x"], a["m"], a["r"],
+                                 a["lam"], a["ws"], a["ws_bytes"], None)
+
+    assert call(K=0, degs=()) == fh.FH_E_ARG
+    assert call(K=65, degs=tuple([1] * 65)) == fh.FH_E_ARG
+    assert call(degs=(1, 10, 3)) == fh.FH_E_DEGREE
+    assert call(degs=(1, -1, 3)) == fh.FH_E_DEGREE
+    assert call(nodes=None) == fh.FH_E_ARG and call(values=None) == fh.FH_E_ARG
+    assert call(r=None) == fh.FH_E_ARG and call(m=-1) == fh.FH_E_ARG
+    assert call(ws=None) == fh.FH_E_WORKSPACE and call(ws_bytes=512) == fh.FH_E_WORKSPACE
