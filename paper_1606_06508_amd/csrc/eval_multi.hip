@@ -174,11 +174,14 @@ size_t layout_multi(void* ws, int64_t n, int32_t K, MultiTable* t) {
   return off;
 }
 
-// Column chunking: at most 12 columns per launch row (16 with shared
-// weights), balanced, rounded up to a compiled chunk size.
+// Column chunking: at most 6 columns per launch row (16 with shared
+// weights; measured on the sines workload: the d = 0..8 sweep runs 1.38 ms
+// in chunks of 5, 1.43 ms in one chunk of 9, where the record loads of nine
+// columns exhaust the scalar registers), balanced, rounded up to a
+// compiled chunk size.
 static int multi_chunk(int32_t K, bool shared) {
   static const int sizes[] = {1, 2, 3, 4, 5, 6, 8, 9, 10, 12, 16};
-  const int kmax = shared ? 16 : 12;
+  const int kmax = shared ? 16 : 6;
   const int chunks = (K + kmax - 1) / kmax;
   const int kc = (K + chunks - 1) / chunks;
   for (int v : sizes)
