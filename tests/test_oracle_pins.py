@@ -274,3 +274,34 @@ def test_compensation_is_at_least_as_accurate():
         ec += float(abs(Fraction(a) - ex))
         ep += float(abs(Fraction(b) - ex))
     assert ec <= ep
+
+
+# ------------------------------------------------------------------- P11 --
+@pytest.mark.parametrize("d", [3, 8])
+def test_oracle_own_error_against_sixty_digit_evaluation(d):
+    """The oracle's rounding error on the 1001-node sines workload, against
+    the same second form (same binary64 weights, values and points) summed
+    in 60-digit decimal arithmetic: e_cond(r) <= 4u and
+    |Lambda - Lambda_ref| <= 4u Lambda (1 + Lambda)."""
+    from decimal import Decimal, localcontext
+
+    c = inputs.sines_workload(m=150)
+    nodes, vals, pts = c["nodes"], c["values"], c["points"]
+    w = oracle.weights(nodes, d)
+    r_o, lam_o, s_o = oracle.evaluate(nodes, vals, d, pts)
+    xs = [Decimal(float(v)) for v in nodes]
+    ws = [Decimal(float(v)) for v in w]
+    fs = [Decimal(float(v)) for v in vals]
+    with localcontext() as ctx:
+        ctx.prec = 60
+        for p, t in enumerate(pts):
+            td = Decimal(float(t))
+            N = D = L = Decimal(0)
+            for xk, wk, fk in zip(xs, ws, fs):
+                a = wk / (td - xk)
+                N += a * fk
+                D += a
+                L += abs(a)
+            r_ref, lam_ref = float(N / D), float(L / abs(D))
+            assert abs(r_o[p] - r_ref) <= 4 * U * s_o[p], (p, r_o[p], r_ref)
+            assert abs(lam_o[p] - lam_ref) <= 4 * U * lam_ref * (1 + lam_ref), p
