@@ -78,7 +78,7 @@ typedef enum {
   FH_E_RANGE = 5,       /* (device) a weight product under/overflowed          */
   FH_E_WORKSPACE = 6,   /* workspace NULL, too small or not 256-byte aligned    */
   FH_E_HIP = 7,         /* a HIP runtime call failed                            */
-  FH_E_UNSUPPORTED = 8  /* combination not provided by this build               */
+  FH_E_UNSUPPORTED = 8  /* combination the library does not provide              */
 } fh_status;
 
 typedef enum { FH_FP64 = 0, FH_FP32_SPLIT = 1 } fh_precision;

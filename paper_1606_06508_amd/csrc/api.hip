@@ -63,7 +63,7 @@ const char* fh_status_string(int32_t s) {
     case FH_E_RANGE: return "a weight product is not a normal binary64 number";
     case FH_E_WORKSPACE: return "workspace missing, too small or misaligned";
     case FH_E_HIP: return "HIP runtime error";
-    case FH_E_UNSUPPORTED: return "unsupported in this build";
+    case FH_E_UNSUPPORTED: return "combination not supported by the library";
     default: return "unknown status";
   }
 }
