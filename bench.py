@@ -6,8 +6,8 @@ Workload of the headline line ("sines"): n = 1001 equispaced nodes on
 [-1,1], f = sum of 8 seeded sines, 10^6 uniform points, blending degree d
 swept 0..8.  One step = for every d: the weight pass and node-table packing
 (fh_prepare) and the fused r + Lebesgue evaluation (fh_eval_prepared) of all
-10^6 points.  value = 9 * n * m pairs per step / step time.  Inputs are
-resident in HBM before timing starts.
+10^6 points into that degree's own output arrays.  value = 9 * n * m pairs
+per step / step time.  Inputs are resident in HBM before timing starts.
 
 Also reported in the same JSON line:
   roofline      the evaluation kernel (the dominant kernel), timed live with
@@ -76,11 +76,17 @@ def measured_traffic(n, m):
 
 
 def run_sines(dev, steps, warmup):
+    """The headline step: for every d the weight pass with node-table packing
+    (fh_prepare) and the fused r + Lambda evaluation (fh_eval_prepared) of
+    all points, each degree into its own output arrays, on one stream.
+    (Packing the next degree on a second stream, overlapped with the current
+    evaluation, was measured slower: the cross-stream event waits cost more
+    than the ~6 us packing they hide.)"""
     c = inputs.sines_workload()
     n, m, degrees = c["nodes"].size, c["points"].size, c["degrees"]
     nodes, vals, x = _t(c["nodes"], dev), _t(c["values"], dev), _t(c["points"], dev)
-    r = torch.empty(m, dtype=torch.float64, device=dev)
-    lam = torch.empty(m, dtype=torch.float64, device=dev)
+    r = torch.empty((len(degrees), m), dtype=torch.float64, device=dev)
+    lam = torch.empty((len(degrees), m), dtype=torch.float64, device=dev)
     ws = fh.Workspace(dev, fh.workspace_size(fh.FH_OP_EVAL, n, m, 8))
     lib = fh.load()
     buf = ws.buf
@@ -89,13 +95,13 @@ def run_sines(dev, steps, warmup):
     P = fh._ptr
 
     def step(evs=None):
-        for d in degrees:
+        for i, d in enumerate(degrees):
             st = lib.fh_prepare(P(nodes), P(vals), n, d, None, fh.FH_FP64, P(buf), buf.numel(), sptr)
             if evs is not None:
                 evs.append(torch.cuda.Event(enable_timing=True))
                 evs[-1].record(stream)
-            st |= lib.fh_eval_prepared(P(buf), buf.numel(), n, fh.FH_FP64, P(x), m, P(r), P(lam),
-                                       sptr)
+            st |= lib.fh_eval_prepared(P(buf), buf.numel(), n, fh.FH_FP64, P(x), m, P(r[i]),
+                                       P(lam[i]), sptr)
             if evs is not None:
                 evs.append(torch.cuda.Event(enable_timing=True))
                 evs[-1].record(stream)
@@ -116,10 +122,10 @@ def run_sines(dev, steps, warmup):
     total_ms = t0.elapsed_time(t1)
     kern_ms = [evs[i].elapsed_time(evs[i + 1]) for i in range(0, len(evs), 2)]
     per_d = {d: float(np.mean(kern_ms[i::len(degrees)])) for i, d in enumerate(degrees)}
-    # outputs of the last timed launch (d = 8) for the parity sample
+    # outputs of the last degree (d = 8) for the parity sample
     return {
         "n": n, "m": m, "degrees": degrees, "total_ms": total_ms, "kernel_ms": kern_ms,
-        "per_d_ms": per_d, "r_last": r, "lam_last": lam, "case": c,
+        "per_d_ms": per_d, "r_last": r[-1], "lam_last": lam[-1], "case": c,
     }
 
 
