@@ -35,26 +35,48 @@ def _problem(n, m, device, seed=0):
     return t(nodes), t(vals), t(pts)
 
 
-def time_variants(n, m, precision="fp64", d=4, reps=5, lebesgue=True, device="cuda:0"):
-    """{variant id: mean ms of one evaluation-kernel launch}."""
+def _warm(fn, min_ms=60.0):
+    """Runs fn back to back for at least min_ms of GPU time: the clock needs
+    tens of milliseconds of steady work before launch times settle."""
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    done, k = 0.0, 1
+    while done < min_ms and k <= 4096:
+        e0.record()
+        for _ in range(k):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        done += e0.elapsed_time(e1)
+        k *= 2
+
+
+def time_variants(n, m, precision="fp64", d=4, reps=5, lebesgue=True, device="cuda:0",
+                  passes=2):
+    """{variant id: ms of one evaluation-kernel launch}: after a warm-up,
+    `passes` rounds over all variants of `reps` launches each; the best
+    round's mean per variant (rounds interleave the variants, so a drifting
+    clock does not favour one of them)."""
     nodes, vals, pts = _problem(n, m, device)
     prep = fh.Prepared(nodes, vals, min(d, n - 1), precision=precision, m_hint=m)
     r = torch.empty(m, dtype=torch.float64, device=device)
     lam = torch.empty(m, dtype=torch.float64, device=device) if lebesgue else None
     out = {}
     try:
-        for vid, *_ in fh.variants(precision):
-            fh.tune_force(precision, vid)
-            prep(pts, lebesgue=lebesgue, out=r, lambda_out=lam)
-            torch.cuda.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(reps):
+        _warm(lambda: prep(pts, lebesgue=lebesgue, out=r, lambda_out=lam))
+        for _ in range(passes):
+            for vid, *_ in fh.variants(precision):
+                fh.tune_force(precision, vid)
                 prep(pts, lebesgue=lebesgue, out=r, lambda_out=lam)
-            e1.record()
-            torch.cuda.synchronize()
-            out[vid] = e0.elapsed_time(e1) / reps
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(reps):
+                    prep(pts, lebesgue=lebesgue, out=r, lambda_out=lam)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / reps
+                out[vid] = min(out.get(vid, ms), ms)
     finally:
         fh.tune_force(precision, -1)
     return out

@@ -55,19 +55,19 @@ struct Builtin {
 };
 constexpr Builtin kBuiltin[] = {
     {FH_FP64, 6, 14, 7},       {FH_FP64, 10, 20, 10},      {FH_FP64, 12, 20, 10},
-    {FH_FP64, 13, 24, 4},      {FH_FP32_SPLIT, 6, 14, 5},  {FH_FP32_SPLIT, 10, 20, 5},
+    {FH_FP64, 13, 24, 10},     {FH_FP32_SPLIT, 6, 14, 4},  {FH_FP32_SPLIT, 10, 20, 5},
     {FH_FP32_SPLIT, 12, 20, 5}, {FH_FP32_SPLIT, 13, 24, 5},
 };
 
-// Untuned shapes: small point sets split the node range over the waves of a
-// block (S = 4 or 2) so that enough waves exist and the last round of waves
-// on each SIMD is short; large point sets give each lane two points.
+// Untuned shapes: two points per lane with the node range split over the
+// four waves of a block (the tuner's choice for every large shape measured),
+// four points per lane for the split form's small point sets.
 int default_variant(int32_t prec, int nb, int mb) {
   for (const Builtin& b : kBuiltin)
     if (b.prec == prec && b.nb == nb && b.mb == mb) return b.variant;
   if (prec == FH_TUNE_BATCHED_FP64 || prec == FH_TUNE_BATCHED_SPLIT) return 1;  // P = 2
   if (prec == FH_FP32_SPLIT) return mb <= 16 ? 6 : 5;  // P = 4 / 2, quads inverted together
-  return mb <= 16 ? 10 : (mb <= 22 ? 12 : 4);
+  return 10;                                            // P = 2, G = 8, S = 4
 }
 
 }  // namespace
