@@ -92,9 +92,10 @@ __global__ void __launch_bounds__(256)
   const SplitScale sc =
       split_table_scale(tx + ds.toff, tw + ds.toff, twf + ds.toff, ds.n, ds.n_pad, red);
   if (threadIdx.x == 0) inst[blockIdx.x].shift = sc.shift;
+  const double pad = split_pad_x(tx[ds.toff], tx[ds.toff + ds.n - 1]);
   for (int64_t k = threadIdx.x; k < ds.n_pad; k += blockDim.x) {
     const int64_t e = ds.toff + k;
-    s4[e] = split_record(tx[e], tw[e], twf[e], sc);
+    s4[e] = split_record(k < ds.n ? tx[e] : pad, tw[e], twf[e], sc);
   }
 }
 

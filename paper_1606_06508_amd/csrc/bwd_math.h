@@ -7,6 +7,8 @@
 
 #include <cstdint>
 
+#include "pair_math.h"
+
 namespace fhk {
 
 constexpr int kPartFields = 6;  // S1, S2, S3, S4, H1 (sum g_hit), H2 (sum g_hit r')
@@ -33,14 +35,13 @@ __device__ inline void bwd_point_exact(double x, double gp, const double* __rest
                                        const double* __restrict__ tf, int64_t n, double* dxp,
                                        double* c, double* cr, double* hg, double* hgr,
                                        double* r_val = nullptr) {
-  int64_t hit = -1;
+  // the hit by binary search, then loops without early exits (their loads
+  // pipeline; a flagged lane holds its whole wave)
+  const int64_t hit = find_node(x, tx, n);
   double n2 = 0.0, d2 = 0.0, e2 = 0.0, f2 = 0.0;
-  for (int64_t k = 0; k < n; ++k) {
+#pragma unroll 4
+  for (int64_t k = 0; hit < 0 && k < n; ++k) {
     const double del = x - tx[k];
-    if (del == 0.0) {
-      hit = k;
-      break;
-    }
     const double a = tw[k] / del;
     const double q = 1.0 / del;
     d2 += a;
@@ -51,6 +52,7 @@ __device__ inline void bwd_point_exact(double x, double gp, const double* __rest
   if (hit >= 0) {
     const double wj = tw[hit], fj = tf[hit], xj = tx[hit];
     double rp = 0.0;
+#pragma unroll 4
     for (int64_t k = 0; k < n; ++k)
       if (k != hit) rp += (tw[k] / wj) * (tf[k] - fj) / (xj - tx[k]);
     *dxp = gp * rp;

@@ -64,20 +64,49 @@ __device__ __forceinline__ bool group_reciprocals(const double (&d)[G], double (
   return not_normal(group_product_reciprocals<G>(d, t));
 }
 
-// Exact per-pair evaluation of one point (flagged lanes only).
+// Index j with tx[j] == t among the strictly increasing tx[0, n), or -1
+// (binary search; NaN never matches).
+__device__ __forceinline__ int64_t find_node(double t, const double* __restrict__ tx, int64_t n) {
+  int64_t lo = 0, hi = n - 1;
+  if (t != t) return -1;
+  while (lo <= hi) {
+    const int64_t mid = lo + ((hi - lo) >> 1);
+    const double v = tx[mid];
+    if (v == t) return mid;
+    if (v < t)
+      lo = mid + 1;
+    else
+      hi = mid - 1;
+  }
+  return -1;
+}
+
+// Exact per-pair evaluation of one point (flagged lanes only).  A NaN or
+// infinite point gives NaN (every a_k is NaN or 0: r = Lambda = NaN); an
+// exact hit is looked up by binary search (r = f_j, Lambda = 1); anything
+// else -- products that leave the binary64 range -- takes one IEEE division
+// per pair in a loop without early exits, so its loads pipeline (a flagged
+// lane holds its whole wave).
 template <bool R, bool L>
 __device__ __noinline__ void eval_point_exact(double t, const double* __restrict__ tx,
                                               const double* __restrict__ tw,
                                               const double* __restrict__ f, int64_t n,
                                               double* r_out, double* l_out) {
+  if (!__builtin_isfinite(t)) {
+    *r_out = __builtin_nan("");
+    *l_out = __builtin_nan("");
+    return;
+  }
+  const int64_t j = find_node(t, tx, n);
+  if (j >= 0) {
+    *r_out = R ? f[j] : 0.0;
+    *l_out = 1.0;
+    return;
+  }
   double N = 0.0, D = 0.0, A = 0.0;
+#pragma unroll 4
   for (int64_t k = 0; k < n; ++k) {
     const double del = t - tx[k];
-    if (del == 0.0) {
-      *r_out = R ? f[k] : 0.0;
-      *l_out = 1.0;
-      return;
-    }
     const double a = tw[k] / del;
     if (R) N = __builtin_fma(a, f[k], N);
     D = D + a;

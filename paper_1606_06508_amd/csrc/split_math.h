@@ -262,6 +262,15 @@ __device__ inline float4 split_record(double xk, double w, double wf, const Spli
   return make_float4(hi, lo, (float)ldexp(w, -sc.e), (float)ldexp(wf, -(sc.e + sc.shift)));
 }
 
+// Position of the zero-weight padding records of a split table: two node
+// spans beyond the last node, out of reach of every point in the binary32
+// domain.  (Copies of the last node would give a point next to it the
+// product (x - x_last)^4 of a padding quad, which leaves the binary32 range
+// below |x - x_last| ~ 3e-10 and sends the lane to the per-pair path.)
+__device__ __forceinline__ double split_pad_x(double x_first, double x_last) {
+  return x_last + 2.0 * (x_last - x_first);
+}
+
 // A point whose binary32 terms are trusted (also false for NaN): within one
 // node span of [x_first, x_last].
 __device__ __forceinline__ bool in_split_domain(double x, double x_first, double x_last) {

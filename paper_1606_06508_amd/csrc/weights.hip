@@ -67,7 +67,7 @@ __global__ void __launch_bounds__(256) k_pack_split(const double* __restrict__ t
     scale_out[1] = sc.shift;
   }
   if (k >= n_pad) return;
-  s4[k] = split_record(tx[k], tw[k], twf[k], sc);
+  s4[k] = split_record(k < n ? tx[k] : split_pad_x(tx[0], tx[n - 1]), tw[k], twf[k], sc);
 }
 
 size_t layout_tables(void* ws, int64_t n, NodeTable* t) {
