@@ -163,3 +163,30 @@ def test_deterministic():
     a = _split(c["nodes"], c["values"], c["d"], c["points"])
     b = _split(c["nodes"], c["values"], c["d"], c["points"])
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_hits_and_close_points_at_both_ends():
+    """Exact hits on the first and last node and points within 1e-8 ... 1e-14
+    of them, for every split launch variant: hits give f_j and Lambda = 1 bit
+    for bit, the rest meet the split bar (the zero-weight padding of the
+    table lies beyond the domain, so points next to the last node keep their
+    binary32 terms)."""
+    g = np.random.default_rng(17)
+    nodes = inputs.jittered_nodes(4097, g)
+    vals = np.sin(7 * nodes)
+    close = np.concatenate([[nodes[0] + s * 10.0 ** -e, nodes[-1] - s * 10.0 ** -e]
+                            for e in (8, 10, 12, 14) for s in (1.0, 0.37)])
+    pts = np.concatenate([[nodes[0], nodes[-1], nodes[2048]], close, g.uniform(-1, 1, 3000)])
+    r_o, lam_o, s_o = oracle.evaluate(nodes, vals, 6, pts)
+    try:
+        for vid, p, grp, s in fh.variants("split"):
+            fh.tune_force("split", vid)
+            r, lam = fh.evaluate(_t(nodes), _t(vals), 6, _t(pts), lebesgue=True,
+                                 precision="split")
+            torch.cuda.synchronize()
+            r, lam = r.cpu().numpy(), lam.cpu().numpy()
+            assert r[0] == vals[0] and r[1] == vals[-1] and r[2] == vals[2048], vid
+            assert np.all(lam[:3] == 1.0), vid
+            metrics.check_split(metrics.parity(r, lam, r_o, lam_o, s_o, metrics.SPLIT_LAMBDA_MAX))
+    finally:
+        fh.tune_force("split", -1)
