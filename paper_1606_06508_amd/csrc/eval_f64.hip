@@ -19,7 +19,7 @@
 //
 // Reciprocals.  A division costs far more than a multiply (the paper's
 // premise for preferring scaling to quotients).  On gfx950 v_rcp_f64 is a
-// quarter-rate estimate with about 25 correct bits.  Nodes are taken in
+// quarter-rate estimate with about 24.4 correct bits.  Nodes are taken in
 // groups of G (4 or 8) and their reciprocals come from one reciprocal of the
 // group product (simultaneous inversion): with a product tree
 // q_ab = d_a d_b, ..., Q = product of all, y ~ 1/Q (estimate plus one
