@@ -31,9 +31,9 @@
  *    workspace (allocate it zeroed).  Calls that share a workspace must be
  *    ordered (same stream); concurrent calls need separate workspaces.
  *  - Host-checkable errors are returned synchronously and no work is
- *    enqueued: FH_E_ARG (n < 1, m < 0, a NULL pointer that is needed -- point
- *    and output arrays are needed only when m > 0 -- a bad precision or op
- *    code), FH_E_DEGREE (d < 0 or d > n-1), FH_E_WORKSPACE
+ *    enqueued: FH_E_ARG (n < 1 or n > FH_MAX_NODES, m < 0, a NULL pointer
+ *    that is needed -- point and output arrays are needed only when m > 0 --
+ *    a bad precision or op code), FH_E_DEGREE (d < 0 or d > n-1), FH_E_WORKSPACE
  *    (workspace missing, too small or misaligned).
  *  - Properties of the node VALUES (strictly increasing, finite, weights
  *    representable) are checked on the device.  A violation sets bits in the
@@ -64,6 +64,10 @@
 
 #include <stddef.h>
 #include <stdint.h>
+
+/* Largest node count of one interpolant (2^28): node tables and node loops
+ * index with 32-bit integers, and a larger n is refused with FH_E_ARG. */
+#define FH_MAX_NODES (1LL << 28)
 
 #ifdef __cplusplus
 extern "C" {

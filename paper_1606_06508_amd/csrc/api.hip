@@ -20,7 +20,7 @@ bool sync_check_enabled() {
 }
 
 fh_status check_problem(const double* nodes, int64_t n, int32_t d) {
-  if (n < 1 || nodes == nullptr) return FH_E_ARG;
+  if (n < 1 || n > FH_MAX_NODES || nodes == nullptr) return FH_E_ARG;
   if (d < 0 || (int64_t)d > n - 1) return FH_E_DEGREE;
   return FH_OK;
 }
@@ -69,7 +69,7 @@ const char* fh_status_string(int32_t s) {
 }
 
 size_t fh_workspace_size(int32_t op, int64_t n, int64_t m, int32_t d, int32_t prec) {
-  if (n < 1 || m < 0 || d < 0 || (int64_t)d > n - 1) return 0;
+  if (n < 1 || n > FH_MAX_NODES || m < 0 || d < 0 || (int64_t)d > n - 1) return 0;
   if (prec != FH_FP64 && prec != FH_FP32_SPLIT) return 0;
   NodeTable t;
   switch (op) {
@@ -115,7 +115,7 @@ fh_status fh_prepare(const double* nodes, const double* values, int64_t n, int32
 
 fh_status fh_eval_prepared(void* ws, size_t ws_bytes, int64_t n, int32_t prec, const double* x,
                            int64_t m, double* r_out, double* lambda_out, void* stream) {
-  if (n < 1 || m < 0 || (m > 0 && x == nullptr)) return FH_E_ARG;
+  if (n < 1 || n > FH_MAX_NODES || m < 0 || (m > 0 && x == nullptr)) return FH_E_ARG;
   if (m > 0 && r_out == nullptr && lambda_out == nullptr) return FH_E_ARG;
   if (prec != FH_FP64 && prec != FH_FP32_SPLIT) return FH_E_ARG;
   fh_status st = check_ws(ws, ws_bytes, fh_workspace_size(FH_OP_EVAL, n, m, 0, prec));
@@ -190,7 +190,7 @@ fh_status fh_lebesgue_max(const double* nodes, int64_t n, int32_t d, const doubl
 }
 
 size_t fh_multi_workspace_size(int64_t n, int32_t K) {
-  if (n < 1 || K < 1 || K > kMultiMax) return 0;
+  if (n < 1 || n > FH_MAX_NODES || K < 1 || K > kMultiMax) return 0;
   MultiTable t;
   return layout_multi(nullptr, n, K, &t);
 }
@@ -199,7 +199,8 @@ fh_status fh_eval_multi(const double* nodes, const double* values, int64_t n,
                         const int32_t* d_host, int32_t K, const double* x, int64_t m,
                         double* r_out, double* lambda_out, void* ws, size_t ws_bytes,
                         void* stream) {
-  if (n < 1 || nodes == nullptr || values == nullptr || d_host == nullptr) return FH_E_ARG;
+  if (n < 1 || n > FH_MAX_NODES || nodes == nullptr || values == nullptr || d_host == nullptr)
+    return FH_E_ARG;
   if (K < 1 || K > kMultiMax) return FH_E_ARG;
   if (m < 0 || (m > 0 && (x == nullptr || r_out == nullptr))) return FH_E_ARG;
   MultiDegrees deg;

@@ -316,7 +316,7 @@ fh_status fh_batch_create(fh_batch** out, int32_t count, const int64_t* n_host,
   for (int32_t i = 0; i < count; ++i) {
     const int64_t n = n_host[i], m = m_host[i];
     const int32_t d = d_host[i];
-    if (n < 1 || m < 0) return FH_E_ARG;
+    if (n < 1 || n > FH_MAX_NODES || m < 0) return FH_E_ARG;
     if (d < 0 || (int64_t)d > n - 1) return FH_E_DEGREE;
     total_m += m;
   }

@@ -19,6 +19,7 @@ FH_OK, FH_E_ARG, FH_E_DEGREE, FH_E_NODES, FH_E_NONFINITE, FH_E_RANGE = 0, 1, 2, 
 FH_E_WORKSPACE, FH_E_HIP, FH_E_UNSUPPORTED = 6, 7, 8
 FH_FP64, FH_FP32_SPLIT = 0, 1
 FH_OP_WEIGHTS, FH_OP_EVAL, FH_OP_BACKWARD, FH_OP_LEBESGUE_MAX = 0, 1, 2, 3
+FH_MAX_NODES = 1 << 28  # largest node count of one interpolant
 PRECISIONS = {"fp64": FH_FP64, "split": FH_FP32_SPLIT, "fp32_split": FH_FP32_SPLIT}
 FH_TUNE_BATCHED_FP64, FH_TUNE_BATCHED_SPLIT = 2, 3
 # kernel families of the tuner: the two precisions of fh_eval and the two of

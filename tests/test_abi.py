@@ -192,3 +192,35 @@ def test_multi_host_validation_and_workspace():
     assert call(nodes=None) == fh.FH_E_ARG and call(values=None) == fh.FH_E_ARG
     assert call(r=None) == fh.FH_E_ARG and call(m=-1) == fh.FH_E_ARG
     assert call(ws=None) == fh.FH_E_WORKSPACE and call(ws_bytes=512) == fh.FH_E_WORKSPACE
+
+
+def test_node_count_limit():
+    """n above FH_MAX_NODES (node loops index with 32-bit integers) is refused
+    on the host by every entry point that takes a node count."""
+    lib = fh.load()
+    hdr = open(HEADERS[0]).read()
+    assert re.search(r"#define FH_MAX_NODES \(1LL << 28\)", hdr) and fh.FH_MAX_NODES == 1 << 28
+    big = fh.FH_MAX_NODES + 1
+    assert lib.fh_workspace_size(fh.FH_OP_EVAL, fh.FH_MAX_NODES, 10, 3, 0) > 0
+    for op in (fh.FH_OP_WEIGHTS, fh.FH_OP_EVAL, fh.FH_OP_BACKWARD, fh.FH_OP_LEBESGUE_MAX):
+        assert lib.fh_workspace_size(op, big, 10, 3, 0) == 0, op
+    assert lib.fh_multi_workspace_size(big, 2) == 0
+    assert lib.fh_weights(P, big, 3, P2, P, 1 << 62, None) == fh.FH_E_ARG
+    assert lib.fh_eval(P, P, big, 3, P, 100, P2, None, None, 0, P, 1 << 62, None) == fh.FH_E_ARG
+    assert lib.fh_lebesgue(P, big, 3, P, 100, P2, None, 0, P, 1 << 62, None) == fh.FH_E_ARG
+    assert lib.fh_eval_prepared(P, 1 << 62, big, 0, P, 100, P2, None, None) == fh.FH_E_ARG
+    assert lib.fh_eval_deriv(P, P, big, 3, P, 100, None, P2, None, 0, P, 1 << 62,
+                             None) == fh.FH_E_ARG
+    assert lib.fh_eval_backward(P, P, big, 3, P, 100, P2, P2, P2, P2, 0, P, 1 << 62,
+                                None) == fh.FH_E_ARG
+    assert lib.fh_lebesgue_max(P, big, 3, None, 256, 5, P2, None, None, 0, P, 1 << 62,
+                               None) == fh.FH_E_ARG
+    d = (ctypes.c_int32 * 2)(3, 3)
+    assert lib.fh_eval_multi(P, P, big, d, 2, P, 100, P2, None, P, 1 << 62, None) == fh.FH_E_ARG
+    h = ctypes.c_void_p()
+    n_host = (ctypes.c_int64 * 2)(5, big)
+    d_host = (ctypes.c_int32 * 2)(1, 1)
+    m_host = (ctypes.c_int64 * 2)(10, 10)
+    assert lib.fh_batch_create(ctypes.byref(h), 2, n_host, d_host, m_host, P, P, P, P2, None, 0,
+                               None) == fh.FH_E_ARG
+    assert h.value is None
