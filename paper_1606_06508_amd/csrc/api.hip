@@ -203,7 +203,7 @@ fh_status fh_eval_multi(const double* nodes, const double* values, int64_t n,
     return FH_E_ARG;
   if (K < 1 || K > kMultiMax) return FH_E_ARG;
   if (m < 0 || (m > 0 && (x == nullptr || r_out == nullptr))) return FH_E_ARG;
-  MultiDegrees deg;
+  MultiDegrees deg{};
   bool shared = true;
   for (int32_t c = 0; c < K; ++c) {
     if (d_host[c] < 0 || (int64_t)d_host[c] > n - 1) return FH_E_DEGREE;

@@ -32,14 +32,21 @@ constexpr int kMultiG = 8;
 
 // Weight table of K columns: tw[cw][n_pad] (cw = c, or 0 when shared),
 // twf[c][n_pad] = w^(c) f^(c), tf[c][n_pad] = f^(c); tx[n_pad] shared.
+// LDS: each block first stages its column's node window (degree at most
+// kWeightLdsMaxD, LDS sized for the largest degree of the launch).
+template <bool LDS>
 __global__ void __launch_bounds__(256)
     k_pack_multi(const double* __restrict__ x, const double* __restrict__ f, int64_t n,
                  MultiDegrees deg, int32_t K, bool shared, int64_t n_pad,
                  double* __restrict__ tx, double* __restrict__ tw, double* __restrict__ twf,
                  double* __restrict__ tf, uint32_t* status) {
 #pragma clang fp contract(off)
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  extern __shared__ double xs[];
+  const int64_t base = (int64_t)blockIdx.x * blockDim.x;
+  const int64_t k = base + threadIdx.x;
   const int c = blockIdx.y;  // 0 .. K_pad - 1; columns from K on are zero padding
+  const int32_t dc = c < K ? deg.d[shared ? 0 : c] : 0;
+  if constexpr (LDS) stage_weight_window(x, n, dc, base, xs);
   if (k >= n_pad) return;
   double* w_c = tw + (shared ? 0 : (int64_t)c * n_pad);
   if (k >= n || c >= K) {
@@ -51,13 +58,12 @@ __global__ void __launch_bounds__(256)
   }
   uint32_t flags = 0;
   double wk;
-  if (shared) {
-    wk = node_weight(x, n, deg.d[0], k, &flags);  // each column recomputes it: O(d^2)
-    if (c == 0) w_c[k] = wk;
-  } else {
-    wk = node_weight(x, n, deg.d[c], k, &flags);
-    w_c[k] = wk;
-  }
+  // with shared weights each column recomputes them (O(d^2) per node)
+  if constexpr (LDS)
+    wk = node_weight_of([&](int64_t j) { return xs[j - base + dc]; }, n, dc, k, &flags);
+  else
+    wk = node_weight(x, n, dc, k, &flags);
+  if (c == 0 || !shared) w_c[k] = wk;
   if (c == 0) {
     flags |= node_checks(x, n, k);
     tx[k] = x[k];
@@ -198,8 +204,14 @@ hipError_t launch_multi(const double* nodes, const double* values, int64_t n,
   const int kc = multi_chunk(K, shared);
   const int rows = (K + kc - 1) / kc;
   const dim3 pg((unsigned)((t.n_pad + 255) / 256), (unsigned)(rows * kc));
-  k_pack_multi<<<pg, 256, 0, s>>>(nodes, values, n, deg, K, shared, t.n_pad, t.x, t.w, t.wf, t.f,
-                                  status);
+  int32_t dmax = 0;
+  for (int32_t c = 0; c < K; ++c) dmax = deg.d[c] > dmax ? deg.d[c] : dmax;
+  if (dmax <= kWeightLdsMaxD)
+    k_pack_multi<true><<<pg, 256, weight_window_bytes(dmax, 256), s>>>(
+        nodes, values, n, deg, K, shared, t.n_pad, t.x, t.w, t.wf, t.f, status);
+  else
+    k_pack_multi<false><<<pg, 256, 0, s>>>(nodes, values, n, deg, K, shared, t.n_pad, t.x, t.w,
+                                           t.wf, t.f, status);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || m == 0) return e;
   switch (kc * 2 + (shared ? 1 : 0)) {

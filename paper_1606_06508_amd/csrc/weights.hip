@@ -3,28 +3,38 @@
 // Weights follow the barycentric form of Floater & Hormann (2007):
 //   w_k = sum_{i in J_k} (-1)^i / prod_{j=i..i+d, j!=k} (x_k - x_j),
 //   J_k = { max(0, k-d) <= i <= min(k, n-1-d) }.
-// One thread per node, O(d^2) work each.  The products run in ascending j,
-// each term is one IEEE division, and the terms are added in ascending i
-// with FMA contraction disabled, so the weights are reproducible bit-for-bit
-// on any IEEE machine that follows the same order.
+// One thread per node, O(d^2) work each, reading the block's node window
+// from LDS.  The products run in ascending j, each term is one IEEE
+// division, and the terms are added in ascending i with FMA contraction
+// disabled, so the weights are reproducible bit-for-bit on any IEEE machine
+// that follows the same order.
 #include "fh_internal.h"
 #include "split_math.h"
 #include "weight_math.h"
 
 namespace fhk {
 
+// LDS: the block's node window is staged in LDS first (d <= kWeightLdsMaxD).
+template <bool LDS>
 __global__ void __launch_bounds__(256) k_weights(const double* __restrict__ x, int64_t n, int32_t d,
                                                  double* __restrict__ w, uint32_t* status) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  extern __shared__ double xs[];
+  const int64_t base = (int64_t)blockIdx.x * blockDim.x;
+  const int64_t k = base + threadIdx.x;
+  if constexpr (LDS) stage_weight_window(x, n, d, base, xs);
   if (k >= n) return;
   uint32_t flags = node_checks(x, n, k);
-  w[k] = node_weight(x, n, d, k, &flags);
+  if constexpr (LDS)
+    w[k] = node_weight_of([&](int64_t j) { return xs[j - base + d]; }, n, d, k, &flags);
+  else
+    w[k] = node_weight(x, n, d, k, &flags);
   if (flags) atomicOr(status, flags);
 }
 
 // FP64 node table: x_k, w_k, w_k f_k (one rounding), padded with zero-weight
 // copies of the last node.  w_in (if given) replaces the weight pass;
 // values may be NULL (Lebesgue only) and then w f is stored as 0.
+template <bool LDS>
 __global__ void __launch_bounds__(256) k_pack(const double* __restrict__ x,
                                               const double* __restrict__ f,
                                               const double* __restrict__ w_in, int64_t n,
@@ -32,7 +42,10 @@ __global__ void __launch_bounds__(256) k_pack(const double* __restrict__ x,
                                               double* __restrict__ tw, double* __restrict__ twf,
                                               double* __restrict__ tf, uint32_t* status) {
 #pragma clang fp contract(off)
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  extern __shared__ double xs[];
+  const int64_t base = (int64_t)blockIdx.x * blockDim.x;
+  const int64_t k = base + threadIdx.x;
+  if constexpr (LDS) stage_weight_window(x, n, d, base, xs);
   if (k >= n_pad) return;
   if (k >= n) {
     tx[k] = x[n - 1];
@@ -42,7 +55,11 @@ __global__ void __launch_bounds__(256) k_pack(const double* __restrict__ x,
     return;
   }
   uint32_t flags = node_checks(x, n, k);
-  double wk = w_in ? w_in[k] : node_weight(x, n, d, k, &flags);
+  double wk;
+  if constexpr (LDS)
+    wk = node_weight_of([&](int64_t j) { return xs[j - base + d]; }, n, d, k, &flags);
+  else
+    wk = w_in ? w_in[k] : node_weight(x, n, d, k, &flags);
   tx[k] = x[k];
   tw[k] = wk;
   twf[k] = f ? wk * f[k] : 0.0;
@@ -91,7 +108,11 @@ size_t layout_tables(void* ws, int64_t n, NodeTable* t) {
 hipError_t launch_weights(const double* nodes, int64_t n, int32_t d, double* w_out,
                           uint32_t* status, hipStream_t s) {
   const int64_t blocks = (n + 255) / 256;
-  k_weights<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(nodes, n, d, w_out, status);
+  if (d <= kWeightLdsMaxD)
+    k_weights<true><<<dim3((unsigned)blocks), dim3(256), weight_window_bytes(d, 256), s>>>(
+        nodes, n, d, w_out, status);
+  else
+    k_weights<false><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(nodes, n, d, w_out, status);
   return hipGetLastError();
 }
 
@@ -99,8 +120,12 @@ hipError_t launch_pack(const double* nodes, const double* values, const double* 
                        int32_t d, const NodeTable& t, bool split, uint32_t* status,
                        hipStream_t s) {
   const int64_t blocks = (t.n_pad + 255) / 256;
-  k_pack<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(nodes, values, w_in, n, d, t.n_pad, t.x, t.w,
-                                                      t.wf, t.f, status);
+  if (w_in == nullptr && d <= kWeightLdsMaxD)
+    k_pack<true><<<dim3((unsigned)blocks), dim3(256), weight_window_bytes(d, 256), s>>>(
+        nodes, values, w_in, n, d, t.n_pad, t.x, t.w, t.wf, t.f, status);
+  else
+    k_pack<false><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(nodes, values, w_in, n, d, t.n_pad,
+                                                               t.x, t.w, t.wf, t.f, status);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !split) return e;
   k_pack_split<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(
