@@ -56,15 +56,15 @@ __global__ void __launch_bounds__(256)
   const double span = tx[n - 1] - tx[0];
   const double far = tx[n - 1] + span + 1.0;
   double xp[P], N[P], D[P], E[P], F[P];
-  uint64_t badm[P];
 #pragma unroll
   for (int j = 0; j < P; ++j) {
     const int64_t idx = base + (int64_t)j * blockDim.x;
     xp[j] = idx < m ? x[idx] : far;
     N[j] = D[j] = E[j] = F[j] = 0.0;
-    badm[j] = 0;
   }
-  // 32-bit counter and wave-mask flags keep loop control on the scalar unit
+  // 32-bit counter keeps loop control on the scalar unit; no range test in
+  // the loop: a zero, infinite or NaN group product makes every t of its
+  // group NaN, and with it D (tested once per point below)
   for (int k = 0; k < (int)n_pad; k += 8) {
     double xk[8], wk[8], vk[8];
 #pragma unroll
@@ -78,7 +78,7 @@ __global__ void __launch_bounds__(256)
       double dl[8], t[8];
 #pragma unroll
       for (int i = 0; i < 8; ++i) dl[i] = xp[j] - xk[i];
-      badm[j] |= not_normal_mask(group_product_reciprocals<8>(dl, t));
+      group_product_reciprocals<8>(dl, t);
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         D[j] = __builtin_fma(wk[i], t[i], D[j]);
@@ -89,12 +89,11 @@ __global__ void __launch_bounds__(256)
       }
     }
   }
-  const int lane = lane_id();
 #pragma unroll
   for (int j = 0; j < P; ++j) {
     const int64_t idx = base + (int64_t)j * blockDim.x;
     if (idx >= m_pad) continue;
-    const bool bad = (badm[j] >> lane) & 1;
+    const bool bad = !(fabs(D[j]) <= 0x1.fffffffffffffp+1023);
     if (idx >= m) {
       if (!DERIV) {
         rec.x[idx] = far; rec.c[idx] = 0.0; rec.cr[idx] = 0.0; rec.hg[idx] = 0.0;

@@ -30,10 +30,10 @@
 //
 // Hits and range.  Q is zero exactly when some delta is zero (an exact hit),
 // NaN for a NaN point, infinite or subnormal only for extreme coordinates.
-// One v_cmp_class per group flags such lanes; after the node loop a flagged
-// lane recomputes its point with one IEEE division per pair and the
-// exact-hit branch (r = f_j bit-for-bit, Lambda = 1).  Unflagged lanes never
-// branch inside the loop.
+// Such a Q makes the refined reciprocal NaN, hence D; a lane whose D is not
+// finite after the node loop is flagged and recomputes its point with the
+// exact-hit branch (r = f_j bit-for-bit, Lambda = 1) or one IEEE division
+// per pair.  The loop itself holds no test and no branch.
 #include "fh_internal.h"
 #include "pair_math.h"
 

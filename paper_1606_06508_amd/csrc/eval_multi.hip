@@ -95,13 +95,12 @@ __global__ void __launch_bounds__(256)
   for (int c = 0; c < KC; ++c) N[c] = 0.0;
 #pragma unroll
   for (int c = 0; c < KD; ++c) D[c] = A[c] = 0.0;
-  uint64_t badm = 0;
   const int cnt = (int)n_pad;
   for (int k = 0; k < cnt; k += kMultiG) {
     double dl[kMultiG], t[kMultiG];
 #pragma unroll
     for (int i = 0; i < kMultiG; ++i) dl[i] = xp - tx[k + i];
-    badm |= not_normal_mask(group_product_reciprocals<kMultiG>(dl, t));
+    group_product_reciprocals<kMultiG>(dl, t);
     if constexpr (SH) {
 #pragma unroll
       for (int i = 0; i < kMultiG; ++i) {
@@ -128,14 +127,15 @@ __global__ void __launch_bounds__(256)
     }
   }
   if (idx >= m) return;
-  const bool bad = (badm >> lane) & 1;
+  // a column's lane is flagged as in k_eval_f64: D not finite (a zero,
+  // infinite or NaN group product makes every t NaN)
 #pragma unroll
   for (int c = 0; c < KC; ++c) {
     if (c >= kc) break;
     const int cd = SH ? 0 : c;
     const int64_t col = c0 + c;
     double rv, lv;
-    if (bad) {
+    if (!(fabs(D[cd]) <= 0x1.fffffffffffffp+1023)) {
       eval_point_exact<true, L>(xp, tx, tw + (SH ? 0 : col * n_pad), tf + col * n_pad, n, &rv,
                                 &lv);
     } else {
@@ -180,22 +180,25 @@ size_t layout_multi(void* ws, int64_t n, int32_t K, MultiTable* t) {
   return off;
 }
 
-// Column chunking: at most 6 columns per launch row (16 with shared
-// weights; measured on the sines workload: the d = 0..8 sweep runs 1.38 ms
-// in chunks of 5, 1.43 ms in one chunk of 9, where the record loads of nine
-// columns exhaust the scalar registers), balanced, rounded up to a
-// compiled chunk size.
+// Column chunking: at most 6 columns per launch row (8 with shared
+// weights), balanced, rounded up to a compiled chunk size.  Measured on the
+// sines workload: the d = 0..8 sweep runs 1.38 ms in chunks of 5 and
+// 1.43 ms in one chunk of 9, where the record loads of nine columns exhaust
+// the scalar registers; 16 value columns with shared weights take 0.83 ms
+// in chunks of 8, 1.06 ms in chunks of 6 or 1.10 ms in one chunk of 16
+// (whose scalar loads are then waited for in small batches).
 static int multi_chunk(int32_t K, bool shared) {
-  static const int sizes[] = {1, 2, 3, 4, 5, 6, 8, 9, 10, 12, 16};
-  const int kmax = shared ? 16 : 6;
+  static const int sizes[] = {1, 2, 3, 4, 5, 6, 8};
+  const int kmax = shared ? 8 : 6;
   const int chunks = (K + kmax - 1) / kmax;
   const int kc = (K + chunks - 1) / chunks;
   for (int v : sizes)
     if (v >= kc) return v;
-  return 16;
+  return 8;
 }
 
-int64_t multi_padded_columns(int32_t K) { return (int64_t)K + 16; }
+// the chunks cover rows * kc < K + 8 columns
+int64_t multi_padded_columns(int32_t K) { return (int64_t)K + 8; }
 
 hipError_t launch_multi(const double* nodes, const double* values, int64_t n,
                         const MultiDegrees& deg, int32_t K, bool shared, const double* x,
@@ -219,8 +222,7 @@ hipError_t launch_multi(const double* nodes, const double* values, int64_t n,
   case KC * 2: return launch_multi_kc<KC, false>(x, m, t, n, K, r, lam, s);          \
   case KC * 2 + 1: return launch_multi_kc<KC, true>(x, m, t, n, K, r, lam, s);
     FH_MULTI_CASE(1) FH_MULTI_CASE(2) FH_MULTI_CASE(3) FH_MULTI_CASE(4) FH_MULTI_CASE(5)
-    FH_MULTI_CASE(6) FH_MULTI_CASE(8) FH_MULTI_CASE(9) FH_MULTI_CASE(10) FH_MULTI_CASE(12)
-    FH_MULTI_CASE(16)
+    FH_MULTI_CASE(6) FH_MULTI_CASE(8)
 #undef FH_MULTI_CASE
     default: return hipErrorInvalidValue;
   }

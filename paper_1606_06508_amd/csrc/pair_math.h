@@ -117,26 +117,20 @@ __device__ __noinline__ void eval_point_exact(double t, const double* __restrict
   *l_out = A / fabs(D);
 }
 
-// Wave mask of the lanes whose q is not a normal number (below the smallest
-// normal, infinite or NaN): two compares whose lane masks feed the scalar
-// unit directly (a class test would be materialised per lane first).
-__device__ __forceinline__ uint64_t not_normal_mask(double q) {
-  const double a = fabs(q);
-  return __builtin_amdgcn_ballot_w64(!(a >= 0x1p-1022)) |
-         __builtin_amdgcn_ballot_w64(a > 0x1.fffffffffffffp+1023);
-}
-
-// Lane index within the wave (0..63).
-__device__ __forceinline__ int lane_id() {
-  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
-}
-
 // Fused sums of one wave over the node records [k_begin, k_end) (wave-
 // uniform range, a multiple of G, below 2^31 records): for each of the
 // lane's P points, D += w t, N += (w f) t, A += |w| |t|, with t from
-// group_reciprocals<G>.  The loop counter is 32-bit and the flags are
-// gathered as wave masks, so loop control and flag bookkeeping stay on the
-// scalar unit (the scalar unit has no 64-bit ordered compare).
+// group_product_reciprocals<G>.  The loop counter is 32-bit, so loop control
+// stays on the scalar unit.
+//
+// No range test inside the loop.  A group product q that is zero (an exact
+// hit), infinite or NaN makes the refined reciprocal NaN (its Newton step
+// forms 0 * inf or inf * 0), and so does a subnormal q whose estimate
+// overflows; a NaN y makes every t of the group NaN and with it D, whatever
+// the weights (w t is NaN even for w = 0).  One test of D per point after
+// the loop therefore flags every lane that a test of each q would flag,
+// except a subnormal q in (2^-1024, 2^-1022) whose reciprocal is finite: its
+// terms stay correct to within 2^-51 of q's rounding instead of 2^-53.
 template <int P, int G, bool R, bool L>
 __device__ __forceinline__ void accumulate_f64(const double (&xp)[P], const double* __restrict__ tx,
                                                const double* __restrict__ tw,
@@ -147,9 +141,6 @@ __device__ __forceinline__ void accumulate_f64(const double (&xp)[P], const doub
   const double* __restrict__ pw = tw + k_begin;
   const double* __restrict__ pv = twf + k_begin;
   const int cnt = (int)(k_end - k_begin);
-  uint64_t badm[P];
-#pragma unroll
-  for (int j = 0; j < P; ++j) badm[j] = 0;
   for (int k = 0; k < cnt; k += G) {
     double xk[G], wk[G], vk[G];
 #pragma unroll
@@ -163,7 +154,7 @@ __device__ __forceinline__ void accumulate_f64(const double (&xp)[P], const doub
       double dl[G], t[G];
 #pragma unroll
       for (int i = 0; i < G; ++i) dl[i] = xp[j] - xk[i];
-      badm[j] |= not_normal_mask(group_product_reciprocals<G>(dl, t));
+      group_product_reciprocals<G>(dl, t);
 #pragma unroll
       for (int i = 0; i < G; ++i) {
         D[j] = __builtin_fma(wk[i], t[i], D[j]);
@@ -172,9 +163,8 @@ __device__ __forceinline__ void accumulate_f64(const double (&xp)[P], const doub
       }
     }
   }
-  const int lane = lane_id();
 #pragma unroll
-  for (int j = 0; j < P; ++j) bad[j] |= (badm[j] >> lane) & 1;
+  for (int j = 0; j < P; ++j) bad[j] |= !(fabs(D[j]) <= 0x1.fffffffffffffp+1023);
 }
 
 }  // namespace fhk
