@@ -218,16 +218,7 @@ def run_split_forms(dev, reps, with_cpu):
         prep = fh.Prepared(nodes, vals, c["d"], precision=prec, m_hint=m)
         r = torch.empty(m, dtype=torch.float64, device=dev)
         lam = torch.empty(m, dtype=torch.float64, device=dev)
-        prep(x, lebesgue=True, out=r, lambda_out=lam)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            prep(x, lebesgue=True, out=r, lambda_out=lam)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
+        ms = _time_ms(lambda: prep(x, lebesgue=True, out=r, lambda_out=lam), reps)
         out[prec] = {"Gpair_s": n * m / (ms * 1e-3) / 1e9, "ms": ms}
         res[prec] = (r, lam)
     out["split_speedup_vs_fp64"] = out["split"]["Gpair_s"] / out["fp64"]["Gpair_s"]
@@ -246,9 +237,21 @@ def run_split_forms(dev, reps, with_cpu):
     return out
 
 
-def _time_ms(fn, reps, stream=None):
+def _warm(fn, ms=50.0):
+    """Back-to-back calls of fn for about `ms` milliseconds: the clock needs
+    tens of milliseconds of steady work to ramp up (more after an idle
+    phase such as the host-side oracle)."""
+    t0 = time.perf_counter()
     fn()
     torch.cuda.synchronize()
+    one = max(time.perf_counter() - t0, 1e-6)
+    for _ in range(min(int(ms * 1e-3 / one), 20000)):
+        fn()
+    torch.cuda.synchronize()
+
+
+def _time_ms(fn, reps, stream=None):
+    _warm(fn)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
