@@ -22,24 +22,20 @@ __device__ __forceinline__ float abs_vop2(float v, uint32_t mask) {
   return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, v) & mask);
 }
 
-// Wave mask of the lanes whose binary32 q is zero, subnormal or NaN: one
-// compare that feeds the scalar unit directly.  (An infinite q cannot occur
-// inside the binary32 domain: differences are at most twice the node span,
-// 2^21, so a product of four stays below 2^84.)
-__device__ __forceinline__ uint64_t tiny_mask32(float q) {
-  return __builtin_amdgcn_ballot_w64(!(__builtin_fabsf(q) >= 0x1p-126f));
-}
-
 // Reciprocals of four binary32 differences d[0..3] in place by simultaneous
 // inversion: one v_rcp_f32 of the product q = (d0 d1)(d2 d3), then
 // 1/d0 = y q23 d1 and so on (y ~ 1/q).  Nine multiplications and one
 // quarter-rate reciprocal replace four reciprocals; each result carries
 // about six binary32 roundings (three for q, the reciprocal's ulp, two on
-// the way back) instead of one.  Valid while q is a normal number; returns
-// the wave mask of the lanes where q is zero, subnormal or NaN (their
-// results must be recomputed).
-__device__ __forceinline__ uint64_t group4_reciprocals32(float& d0, float& d1, float& d2,
-                                                         float& d3) {
+// the way back) instead of one.  A zero or NaN q (a point on a node, a NaN
+// point) makes the results infinite or NaN, and so does a subnormal q whose
+// reciprocal overflows; the caller's test of its tile sums catches them, as
+// it catches the infinite reciprocal of a zero difference with G = 1.  (An
+// infinite q cannot occur inside the binary32 domain: differences are at
+// most twice the node span, 2^21, so a product of four stays below 2^84.)
+// The one unflagged case, a subnormal q in [2^-128, 2^-126) with a finite
+// reciprocal, rounds q to 2^-22 relative instead of 2^-24.
+__device__ __forceinline__ void group4_reciprocals32(float& d0, float& d1, float& d2, float& d3) {
   const float q01 = d0 * d1, q23 = d2 * d3;
   const float q = q01 * q23;
   const float y = __builtin_amdgcn_rcpf(q);
@@ -49,7 +45,6 @@ __device__ __forceinline__ uint64_t group4_reciprocals32(float& d0, float& d1, f
   d1 = t1;
   d2 = t2;
   d3 = t3;
-  return tiny_mask32(q);
 }
 
 // Sums of one block over the split node table s4[0, n_pad) (n_pad a multiple
@@ -58,9 +53,9 @@ __device__ __forceinline__ uint64_t group4_reciprocals32(float& d0, float& d1, f
 // lane accumulates its P points in binary32 tile sums promoted to binary64
 // every kTile nodes.  G = 1 takes one v_rcp_f32 per difference; G = 4 the
 // simultaneous inversion of the four differences of each node quad
-// (group4_reciprocals32; lanes with a product that is not normal -- a point
-// on or extremely close to a node -- are flagged for the exact path).  Must
-// be called by all threads of the block.
+// (group4_reciprocals32).  A tile sum that is not finite -- a point on or
+// extremely close to a node, a NaN point -- flags the lane for the exact
+// path.  Must be called by all threads of the block.
 template <int P, bool R, bool L, int G = 1>
 __device__ __forceinline__ void split_block_sums(float4 (&stage)[2][kStage],
                                                  const float4* __restrict__ s4, int64_t n_pad,
@@ -70,12 +65,8 @@ __device__ __forceinline__ void split_block_sums(float4 (&stage)[2][kStage],
   static_assert(G == 1 || G == 4, "group size 1 or 4");
   const int tid = threadIdx.x;
   float Nt[P], Dt[P], At[P];
-  uint64_t badm[P];
 #pragma unroll
-  for (int j = 0; j < P; ++j) {
-    Nt[j] = Dt[j] = At[j] = 0.0f;
-    badm[j] = 0;
-  }
+  for (int j = 0; j < P; ++j) Nt[j] = Dt[j] = At[j] = 0.0f;
   if (tid < n_pad) stage[0][tid] = s4[tid];
   __syncthreads();
   int buf = 0;
@@ -104,8 +95,7 @@ __device__ __forceinline__ void split_block_sums(float4 (&stage)[2][kStage],
             for (int j = 0; j < P; ++j) t[q][j] = __builtin_amdgcn_rcpf(t[q][j]);
         } else {
 #pragma unroll
-          for (int j = 0; j < P; ++j)
-            badm[j] |= group4_reciprocals32(t[0][j], t[1][j], t[2][j], t[3][j]);
+          for (int j = 0; j < P; ++j) group4_reciprocals32(t[0][j], t[1][j], t[2][j], t[3][j]);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q)
@@ -142,11 +132,6 @@ __device__ __forceinline__ void split_block_sums(float4 (&stage)[2][kStage],
     }
     __syncthreads();
     buf ^= 1;
-  }
-  if constexpr (G == 4) {
-    const int lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
-#pragma unroll
-    for (int j = 0; j < P; ++j) bad[j] |= (badm[j] >> lane) & 1;
   }
 }
 
