@@ -266,6 +266,15 @@ fh_status fh_batch_status(fh_batch* b, void* stream, uint32_t* bits_out);
  * created).  All variants compute the same quantities to the
  * same error bound; they differ in speed and in summation order.
  *   fh_variant_count / fh_variant_shape  enumerate the variants of `prec`;
+ *   fh_variant_lebesgue_block  the node block length U of a variant whose
+ *                  Lebesgue sum is taken by blocks (binary64 variants that
+ *                  use the alternating signs of the weights: one multiply-
+ *                  add per pair serves both sum_k a_k and sum_k |a_k|), 0
+ *                  for plain sums, -1 for a bad family or id.  Such a
+ *                  variant runs plain sums when caller weights do not
+ *                  alternate strictly in sign (w_k w_{k+1} < 0 for every k;
+ *                  Floater-Hormann weights always do); r does not depend on
+ *                  whether Lambda is requested;
  *   fh_tune_set    records variant `id` for the shape bucket of (n, m)
  *                  (id = -1 removes the entry);
  *   fh_tune_force  pins variant `id` for every shape (-1 releases it);
@@ -275,6 +284,7 @@ enum { FH_TUNE_BATCHED_FP64 = 2, FH_TUNE_BATCHED_SPLIT = 3 };
 int32_t fh_variant_count(int32_t prec);
 fh_status fh_variant_shape(int32_t prec, int32_t id, int32_t* points_per_lane, int32_t* group,
                            int32_t* node_split);
+int32_t fh_variant_lebesgue_block(int32_t prec, int32_t id);
 fh_status fh_tune_set(int32_t prec, int64_t n, int64_t m, int32_t id);
 fh_status fh_tune_force(int32_t prec, int32_t id);
 int32_t fh_tune_get(int32_t prec, int64_t n, int64_t m);

@@ -98,7 +98,8 @@ def tune(shapes=None, precisions=("fp64", "split"), reps=5, device="cuda:0", ver
                                      "all_ms": {str(k): v for k, v in times.items()}})
             if verbose:
                 shape = dict((v[0], v[1:]) for v in fh.variants(prec))[best]
-                print(f"[tune] {prec} n={n} m={m}: variant {best} (P,G,S)={shape} "
+                shape += (fh.variant_lebesgue_block(prec, best),)
+                print(f"[tune] {prec} n={n} m={m}: variant {best} (P,G,S,U)={shape} "
                       f"{times[best]:.4f} ms; worst {max(times.values()):.4f} ms",
                       file=sys.stderr, flush=True)
     return table

@@ -39,12 +39,15 @@
 
 namespace fhk {
 
-template <int P, int G, int S, bool R, bool L>
+// U > 0: the sums are taken by blocks of U nodes (accumulate_f64_blocks)
+// when the table's weights alternate in sign, which *alt says (written by
+// the packing); D, hence r, is then the same with and without Lambda.
+template <int P, int G, int S, bool R, bool L, int U>
 __global__ void __launch_bounds__(256)
     k_eval_f64(const double* __restrict__ x, int64_t m, const double* __restrict__ tx,
                const double* __restrict__ tw, const double* __restrict__ twf, int64_t n_pad,
-               const double* __restrict__ f, int64_t n, double* __restrict__ r,
-               double* __restrict__ lam) {
+               const double* __restrict__ f, int64_t n, const uint32_t* __restrict__ alt,
+               double* __restrict__ r, double* __restrict__ lam) {
   constexpr int PG = 4 / S;  // point groups per block
   const int lane = threadIdx.x & 63;
   // wave index, made provably wave-uniform so node loads stay scalar
@@ -66,7 +69,13 @@ __global__ void __launch_bounds__(256)
   const int64_t slice_len = n_pad / S;
   const int64_t k_begin = slice * slice_len, k_end = k_begin + slice_len;
 
-  accumulate_f64<P, G, R, L>(xp, tx, tw, twf, k_begin, k_end, N, D, A, bad);
+  bool blocks = false;
+  if constexpr (U > 0) {
+    blocks = __builtin_amdgcn_readfirstlane(*alt) != 0;
+    if (blocks)
+      accumulate_f64_blocks<P, G, U, R, L>(xp, tx, tw, twf, k_begin, k_end, N, D, A, bad);
+  }
+  if (!blocks) accumulate_f64<P, G, R, L>(xp, tx, tw, twf, k_begin, k_end, N, D, A, bad);
 
   if constexpr (S > 1) {
     // fixed-order reduction of the S partial sums of each group through LDS
@@ -103,50 +112,55 @@ __global__ void __launch_bounds__(256)
     if (bad[j]) {
       eval_point_exact<R, L>(xp[j], tx, tw, f, n, &rv, &lv);
     } else {
+      double a = A[j];
+      if constexpr (L && U > 0)
+        if (blocks) a = lebesgue_block_fix<G, U>(xp[j], tx, tw, n, a);
       rv = N[j] / D[j];
-      lv = A[j] / fabs(D[j]);
+      lv = a / fabs(D[j]);
     }
     if (R) r[idx] = rv;
     if (L) lam[idx] = lv;
   }
 }
 
-template <int P, int G, int S>
-static hipError_t launch_v(const double* x, int64_t m, const NodeTable& t, int64_t n, double* r,
-                           double* lam, hipStream_t s) {
+template <int P, int G, int S, int U>
+static hipError_t launch_v(const double* x, int64_t m, const NodeTable& t, int64_t n,
+                           const uint32_t* alt, double* r, double* lam, hipStream_t s) {
   const int64_t per = 64LL * P * (4 / S);  // points per block
   const dim3 grid((unsigned)((m + per - 1) / per)), block(256);
   if (r && lam)
-    k_eval_f64<P, G, S, true, true><<<grid, block, 0, s>>>(x, m, t.x, t.w, t.wf, t.n_pad, t.f, n,
-                                                           r, lam);
+    k_eval_f64<P, G, S, true, true, U><<<grid, block, 0, s>>>(x, m, t.x, t.w, t.wf, t.n_pad, t.f,
+                                                              n, alt, r, lam);
   else if (r)
-    k_eval_f64<P, G, S, true, false><<<grid, block, 0, s>>>(x, m, t.x, t.w, t.wf, t.n_pad, t.f, n,
-                                                            r, lam);
+    k_eval_f64<P, G, S, true, false, U><<<grid, block, 0, s>>>(x, m, t.x, t.w, t.wf, t.n_pad,
+                                                               t.f, n, alt, r, lam);
   else
-    k_eval_f64<P, G, S, false, true><<<grid, block, 0, s>>>(x, m, t.x, t.w, t.wf, t.n_pad, t.f, n,
-                                                            r, lam);
+    k_eval_f64<P, G, S, false, true, U><<<grid, block, 0, s>>>(x, m, t.x, t.w, t.wf, t.n_pad,
+                                                               t.f, n, alt, r, lam);
   return hipGetLastError();
 }
 
-// Variant table: id -> (points per lane P, group size G, node split S).
+// Variant table: id -> (points per lane P, group size G, node split S,
+// Lebesgue block U; U = 0: plain sums).
 #define FH_F64_VARIANTS(X)                                                                    \
-  X(0, 1, 4, 1) X(1, 2, 4, 1) X(2, 4, 4, 1) X(3, 1, 8, 1) X(4, 2, 8, 1) X(5, 4, 8, 1)       \
-  X(6, 1, 4, 4) X(7, 2, 4, 4) X(8, 4, 4, 4) X(9, 1, 8, 4) X(10, 2, 8, 4) X(11, 4, 8, 4)     \
-  X(12, 1, 8, 2) X(13, 2, 8, 2) X(14, 4, 8, 2)
+  X(0, 1, 4, 1, 0) X(1, 2, 4, 1, 0) X(2, 4, 4, 1, 0) X(3, 1, 8, 1, 0) X(4, 2, 8, 1, 0)        \
+  X(5, 4, 8, 1, 0) X(6, 1, 4, 4, 0) X(7, 2, 4, 4, 0) X(8, 4, 4, 4, 0) X(9, 1, 8, 4, 0)        \
+  X(10, 2, 8, 4, 0) X(11, 4, 8, 4, 0) X(12, 1, 8, 2, 0) X(13, 2, 8, 2, 0) X(14, 4, 8, 2, 0)   \
+  X(15, 1, 8, 4, 16) X(16, 2, 8, 4, 16) X(17, 1, 8, 2, 16) X(18, 2, 8, 2, 16)
 
 int f64_variant_count() {
-#define FH_COUNT(id, p, g, s) +1
+#define FH_COUNT(id, p, g, s, u) +1
   return 0 FH_F64_VARIANTS(FH_COUNT);
 #undef FH_COUNT
 }
 
 void f64_variant_shape(int id, int* p, int* g, int* s) {
   switch (id) {
-#define FH_SHAPE(vid, vp, vg, vs) \
-  case vid:                       \
-    *p = vp;                      \
-    *g = vg;                      \
-    *s = vs;                      \
+#define FH_SHAPE(vid, vp, vg, vs, vu) \
+  case vid:                           \
+    *p = vp;                          \
+    *g = vg;                          \
+    *s = vs;                          \
     return;
     FH_F64_VARIANTS(FH_SHAPE)
 #undef FH_SHAPE
@@ -154,12 +168,23 @@ void f64_variant_shape(int id, int* p, int* g, int* s) {
   }
 }
 
-hipError_t launch_eval_f64(const double* x, int64_t m, const NodeTable& t, int64_t n, double* r,
-                           double* lam, const EvalConfig& cfg, hipStream_t s) {
+int f64_variant_block(int id) {
+  switch (id) {
+#define FH_BLOCK(vid, vp, vg, vs, vu) \
+  case vid: return vu;
+    FH_F64_VARIANTS(FH_BLOCK)
+#undef FH_BLOCK
+    default: return 0;
+  }
+}
+
+hipError_t launch_eval_f64(const double* x, int64_t m, const NodeTable& t, int64_t n,
+                           const uint32_t* alt, double* r, double* lam, const EvalConfig& cfg,
+                           hipStream_t s) {
   if (m == 0) return hipSuccess;
   switch (cfg.variant) {
-#define FH_CASE(vid, vp, vg, vs) \
-  case vid: return launch_v<vp, vg, vs>(x, m, t, n, r, lam, s);
+#define FH_CASE(vid, vp, vg, vs, vu) \
+  case vid: return launch_v<vp, vg, vs, vu>(x, m, t, n, alt, r, lam, s);
     FH_F64_VARIANTS(FH_CASE)
 #undef FH_CASE
     default: return hipErrorInvalidValue;

@@ -14,7 +14,10 @@ namespace fhk {
 // The first kStatusBytes of every workspace: word 0 = sticky status bits,
 // word 1 = binary32 weight scaling exponent e of the split form
 // (max|w| = m 2^e, 1/2 <= m < 1), word 2 = ef - e with 2^ef the scale of
-// the weighted values w f (split_table_scale), words 3.. reserved.
+// the weighted values w f (split_table_scale), word 3 = 1 if the node
+// table's weights alternate strictly in sign (always for the library's
+// weights; caller weights are checked pair by pair), written by every
+// packing; words 4.. reserved.
 constexpr size_t kStatusBytes = 256;
 // Node tables are padded to a multiple of this many records; padding
 // records repeat the last node with zero weight, so they add nothing.
@@ -49,6 +52,7 @@ EvalConfig choose_eval_config(int32_t prec, int64_t n, int32_t d, int64_t m, boo
                               bool want_l);
 int f64_variant_count();
 void f64_variant_shape(int id, int* p, int* g, int* s);
+int f64_variant_block(int id);  // Lebesgue block length U, 0 for plain sums
 int split_variant_count();
 void split_variant_shape(int id, int* p, int* g, int* s);
 int batched_variant_count();
@@ -107,8 +111,11 @@ hipError_t launch_weights(const double* nodes, int64_t n, int32_t d, double* w_o
 hipError_t launch_pack(const double* nodes, const double* values, const double* w_in, int64_t n,
                        int32_t d, const NodeTable& t, bool split, uint32_t* status,
                        hipStream_t s);
-hipError_t launch_eval_f64(const double* x, int64_t m, const NodeTable& t, int64_t n, double* r,
-                           double* lam, const EvalConfig& cfg, hipStream_t s);
+// alt: status word 3 of the workspace (1 if the table's weights alternate
+// in sign, written by launch_pack), read by the Lebesgue-block variants.
+hipError_t launch_eval_f64(const double* x, int64_t m, const NodeTable& t, int64_t n,
+                           const uint32_t* alt, double* r, double* lam, const EvalConfig& cfg,
+                           hipStream_t s);
 // scale_exp: the split scaling exponent (status word 1) when b.plan.split.
 hipError_t launch_backward(const double* nodes, const double* x, const double* g, int64_t n,
                            int32_t d, int64_t m, const NodeTable& t, const BackwardBufs& b,

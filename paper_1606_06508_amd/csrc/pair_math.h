@@ -167,4 +167,117 @@ __device__ __forceinline__ void accumulate_f64(const double (&xp)[P], const doub
   for (int j = 0; j < P; ++j) bad[j] |= !(fabs(D[j]) <= 0x1.fffffffffffffp+1023);
 }
 
+// Number of nodes tx[0, n) below v (v finite; tx strictly increasing).
+__device__ __forceinline__ int64_t nodes_below(double v, const double* __restrict__ tx, int64_t n) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (tx[mid] < v)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Fused sums with the Lebesgue sum taken by blocks of U nodes, for weights
+// that alternate in sign (Floater-Hormann weights do: every term of w_k has
+// the sign (-1)^(k-d)).  On a block that lies on one side of the point all
+// t_k share a sign, so |w_k t_k| alternates like w_k: the block's
+// sum_k |w_k t_k| is |E - O| and its sum_k w_k t_k is E + O.  Each pair
+// costs one multiply-add for both sums (two with the plain scheme), each
+// block four additions.  The one block that contains the point (if any)
+// gets its exact sum_k |w_k t_k| from lebesgue_block_fix after the loop.
+// Without L the block sums still form D, so r does not depend on whether
+// Lambda is requested.  Lane flags as in accumulate_f64 (D not finite).
+template <int P, int G, int U, bool R, bool L>
+__device__ __forceinline__ void accumulate_f64_blocks(const double (&xp)[P],
+                                                      const double* __restrict__ tx,
+                                                      const double* __restrict__ tw,
+                                                      const double* __restrict__ twf,
+                                                      int64_t k_begin, int64_t k_end,
+                                                      double (&N)[P], double (&D)[P],
+                                                      double (&A)[P], bool (&bad)[P]) {
+  static_assert(U % G == 0, "blocks of whole node groups");
+  const double* __restrict__ px = tx + k_begin;
+  const double* __restrict__ pw = tw + k_begin;
+  const double* __restrict__ pv = twf + k_begin;
+  const int cnt = (int)(k_end - k_begin);
+  for (int k = 0; k < cnt; k += U) {
+    // E = sum of w_k t_k over the block's even records, O over its odd ones
+    // (lebesgue_block_fix repeats these operations in this order)
+    double E[P], O[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) E[j] = O[j] = 0.0;
+#pragma unroll
+    for (int h = 0; h < U; h += G) {
+      double xk[G], wk[G], vk[G];
+#pragma unroll
+      for (int i = 0; i < G; ++i) {
+        xk[i] = px[k + h + i];
+        wk[i] = pw[k + h + i];
+        vk[i] = R ? pv[k + h + i] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        double dl[G], t[G];
+#pragma unroll
+        for (int i = 0; i < G; ++i) dl[i] = xp[j] - xk[i];
+        group_product_reciprocals<G>(dl, t);
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+          if (R) N[j] = __builtin_fma(vk[i], t[i], N[j]);
+          if (i & 1)
+            O[j] = __builtin_fma(wk[i], t[i], O[j]);
+          else
+            E[j] = __builtin_fma(wk[i], t[i], E[j]);
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      D[j] += E[j] + O[j];
+      if (L) A[j] += fabs(E[j] - O[j]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < P; ++j) bad[j] |= !(fabs(D[j]) <= 0x1.fffffffffffffp+1023);
+}
+
+// The Lebesgue sum A of accumulate_f64_blocks over the whole table with its
+// one wrong term replaced: if the point v (finite, not a node) lies strictly
+// inside block b (nodes x_{bU} .. x_{bU+U-1} on both sides of it), A holds
+// |E_b - O_b| for that block; it gets sum_k |w_k t_k| instead, recomputed
+// with the same operations.  tx/tw are the padded tables (length a multiple
+// of U), n the node count.
+template <int G, int U>
+__device__ __forceinline__ double lebesgue_block_fix(double v, const double* __restrict__ tx,
+                                                     const double* __restrict__ tw, int64_t n,
+                                                     double A) {
+  const int64_t j = nodes_below(v, tx, n);
+  if (j == 0 || j >= n || j % U == 0) return A;
+  const int64_t b = j - j % U;
+  double E = 0.0, O = 0.0, exact = 0.0;
+  // one group at a time (once per point: few registers matter more here)
+#pragma unroll 1
+  for (int h = 0; h < U; h += G) {
+    double dl[G], t[G], wk[G];
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      dl[i] = v - tx[b + h + i];
+      wk[i] = tw[b + h + i];
+    }
+    group_product_reciprocals<G>(dl, t);
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      if (i & 1)
+        O = __builtin_fma(wk[i], t[i], O);
+      else
+        E = __builtin_fma(wk[i], t[i], E);
+      exact = __builtin_fma(fabs(wk[i]), fabs(t[i]), exact);
+    }
+  }
+  return (A - fabs(E - O)) + exact;
+}
+
 }  // namespace fhk

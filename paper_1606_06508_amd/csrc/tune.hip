@@ -54,20 +54,22 @@ struct Builtin {
   int variant;
 };
 constexpr Builtin kBuiltin[] = {
-    {FH_FP64, 6, 14, 7},       {FH_FP64, 10, 20, 10},      {FH_FP64, 12, 20, 10},
-    {FH_FP64, 13, 24, 10},     {FH_FP32_SPLIT, 6, 14, 4},  {FH_FP32_SPLIT, 10, 20, 5},
+    {FH_FP64, 6, 14, 7},       {FH_FP64, 10, 20, 15},      {FH_FP64, 12, 20, 15},
+    {FH_FP64, 13, 20, 16},     {FH_FP64, 13, 24, 16},      {FH_FP32_SPLIT, 6, 14, 4},
+    {FH_FP32_SPLIT, 10, 20, 5},
     {FH_FP32_SPLIT, 12, 20, 5}, {FH_FP32_SPLIT, 13, 24, 5},
 };
 
 // Untuned shapes: two points per lane with the node range split over the
-// four waves of a block (the tuner's choice for every large shape measured),
-// four points per lane for the split form's small point sets.
+// four waves of a block and the Lebesgue sum taken by node blocks (the
+// tuner's choice for every large shape measured), four points per lane for
+// the split form's small point sets.
 int default_variant(int32_t prec, int nb, int mb) {
   for (const Builtin& b : kBuiltin)
     if (b.prec == prec && b.nb == nb && b.mb == mb) return b.variant;
   if (prec == FH_TUNE_BATCHED_FP64 || prec == FH_TUNE_BATCHED_SPLIT) return 1;  // P = 2
   if (prec == FH_FP32_SPLIT) return mb <= 16 ? 6 : 5;  // P = 4 / 2, quads inverted together
-  return 10;                                            // P = 2, G = 8, S = 4
+  return 16;                                            // P = 2, G = 8, S = 4, U = 16
 }
 
 }  // namespace
@@ -110,6 +112,11 @@ fh_status fh_variant_shape(int32_t prec, int32_t id, int32_t* points_per_lane, i
   *group = g;
   *node_split = s;
   return FH_OK;
+}
+
+int32_t fh_variant_lebesgue_block(int32_t prec, int32_t id) {
+  if (!valid_family(prec) || id < 0 || id >= variant_count(prec)) return -1;
+  return prec == FH_FP64 ? f64_variant_block(id) : 0;
 }
 
 fh_status fh_tune_force(int32_t prec, int32_t id) {

@@ -31,6 +31,8 @@ __global__ void __launch_bounds__(256) k_weights(const double* __restrict__ x, i
   if (flags) atomicOr(status, flags);
 }
 
+__global__ void k_set_word(uint32_t* p, uint32_t v) { *p = v; }
+
 // FP64 node table: x_k, w_k, w_k f_k (one rounding), padded with zero-weight
 // copies of the last node.  w_in (if given) replaces the weight pass;
 // values may be NULL (Lebesgue only) and then w f is stored as 0.
@@ -45,6 +47,11 @@ __global__ void __launch_bounds__(256) k_pack(const double* __restrict__ x,
   extern __shared__ double xs[];
   const int64_t base = (int64_t)blockIdx.x * blockDim.x;
   const int64_t k = base + threadIdx.x;
+  // status word 3 = 1 while the weights alternate in sign: always for the
+  // library's weights (every term of w_k has the sign (-1)^(k-d)); caller
+  // weights start at 1 (k_set_word, launched before) and any pair that does
+  // not alternate strictly clears it
+  if (k == 0 && w_in == nullptr) status[3] = 1u;
   if constexpr (LDS) stage_weight_window(x, n, d, base, xs);
   if (k >= n_pad) return;
   if (k >= n) {
@@ -56,10 +63,14 @@ __global__ void __launch_bounds__(256) k_pack(const double* __restrict__ x,
   }
   uint32_t flags = node_checks(x, n, k);
   double wk;
-  if constexpr (LDS)
+  if constexpr (LDS) {
     wk = node_weight_of([&](int64_t j) { return xs[j - base + d]; }, n, d, k, &flags);
-  else
-    wk = w_in ? w_in[k] : node_weight(x, n, d, k, &flags);
+  } else if (w_in) {
+    wk = w_in[k];
+    if (k + 1 < n && !(wk * w_in[k + 1] < 0.0)) status[3] = 0u;
+  } else {
+    wk = node_weight(x, n, d, k, &flags);
+  }
   tx[k] = x[k];
   tw[k] = wk;
   twf[k] = f ? wk * f[k] : 0.0;
@@ -120,6 +131,11 @@ hipError_t launch_pack(const double* nodes, const double* values, const double* 
                        int32_t d, const NodeTable& t, bool split, uint32_t* status,
                        hipStream_t s) {
   const int64_t blocks = (t.n_pad + 255) / 256;
+  if (w_in) {
+    k_set_word<<<1, 1, 0, s>>>(status + 3, 1u);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   if (w_in == nullptr && d <= kWeightLdsMaxD)
     k_pack<true><<<dim3((unsigned)blocks), dim3(256), weight_window_bytes(d, 256), s>>>(
         nodes, values, w_in, n, d, t.n_pad, t.x, t.w, t.wf, t.f, status);

@@ -76,6 +76,7 @@ def load():
             "fh_variant_count": ([i32], i32),
             "fh_variant_shape": ([i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                   ctypes.POINTER(i32)], ctypes.c_int),
+            "fh_variant_lebesgue_block": ([i32, i32], i32),
             "fh_tune_set": ([i32, i64, i64, i32], ctypes.c_int),
             "fh_tune_force": ([i32, i32], ctypes.c_int),
             "fh_tune_get": ([i32, i64, i64], i32),
@@ -357,6 +358,15 @@ def variants(precision="fp64"):
                "fh_variant_shape")
         out.append((i, p.value, g.value, s.value))
     return out
+
+
+def variant_lebesgue_block(precision, variant):
+    """Node block length of a variant whose Lebesgue sum is taken by blocks
+    (0: plain sums)."""
+    u = load().fh_variant_lebesgue_block(_family(precision), int(variant))
+    if u < 0:
+        raise FhError(FH_E_ARG, "fh_variant_lebesgue_block")
+    return u
 
 
 def tune_force(precision, variant):

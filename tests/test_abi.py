@@ -150,6 +150,26 @@ def test_variant_tables_and_tuner_api():
     assert lib.fh_variant_count(7) == 0
 
 
+def test_lebesgue_block_variants():
+    """Binary64 variants 15..18 take the Lebesgue sum by blocks of 16 nodes
+    (the block counterparts of plain shapes); every other variant, and every
+    split and batched variant, uses plain sums."""
+    blocks = {vid: fh.variant_lebesgue_block("fp64", vid) for vid, *_ in fh.variants("fp64")}
+    assert {vid for vid, u in blocks.items() if u} == {15, 16, 17, 18}
+    assert set(blocks.values()) == {0, 16}
+    shapes = {vid: (p, g, s) for vid, p, g, s in fh.variants("fp64")}
+    for vid in (15, 16, 17, 18):
+        assert shapes[vid] in [shapes[v] for v, u in blocks.items() if u == 0]
+    for fam in ("split", 2, 3):
+        for vid, *_ in fh.variants(fam):
+            assert fh.variant_lebesgue_block(fam, vid) == 0
+    lib = fh.load()
+    assert lib.fh_variant_lebesgue_block(0, 99) == -1
+    assert lib.fh_variant_lebesgue_block(7, 0) == -1
+    with pytest.raises(fh.FhError):
+        fh.variant_lebesgue_block("fp64", -1)
+
+
 def test_normalize_entry_points_and_host_validation():
     """The six normalization entry points are declared and reject bad
     arguments before any launch."""
