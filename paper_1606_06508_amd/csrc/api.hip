@@ -185,8 +185,8 @@ fh_status fh_lebesgue_max(const double* nodes, int64_t n, int32_t d, const doubl
   layout_lebesgue_max(ws, n, &t, &lam, &xk);
   hipError_t e = launch_pack(nodes, nullptr, w, n, d, t, false, static_cast<uint32_t*>(ws), s);
   if (e == hipSuccess)
-    e = launch_lebesgue_max(t, n, samples, rounds, lam_out ? lam_out : lam, x_out ? x_out : xk,
-                            best_out, s);
+    e = launch_lebesgue_max(t, n, samples, rounds, static_cast<uint32_t*>(ws) + 3,
+                            lam_out ? lam_out : lam, x_out ? x_out : xk, best_out, s);
   return finish(e, ws, s);
 }
 

@@ -137,9 +137,10 @@ hipError_t launch_eval_deriv_split(const double* x, int64_t m, const NodeTable& 
 size_t layout_lebesgue_max(void* ws, int64_t n, NodeTable* t, double** lam, double** xk);
 // Per-interval maxima of Lambda (lam, xk: [n-1], not null) by the grid zoom
 // of `rounds` rounds of `samples` samples; best (if not null) = {the
-// constant, its location}.
+// constant, its location}; alt: status word 3 (weights alternate in sign).
 hipError_t launch_lebesgue_max(const NodeTable& t, int64_t n, int32_t samples, int32_t rounds,
-                               double* lam, double* xk, double* best, hipStream_t s);
+                               const uint32_t* alt, double* lam, double* xk, double* best,
+                               hipStream_t s);
 hipError_t launch_eval_split(const double* x, int64_t m, const NodeTable& t, int64_t n,
                              const int32_t* scale, double* r, double* lam, const EvalConfig& cfg,
                              hipStream_t s);

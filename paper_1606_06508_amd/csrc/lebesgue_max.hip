@@ -28,7 +28,11 @@
 // no LDS and no barrier.
 //
 // Sums use the simultaneous inversion of the evaluation kernels (group
-// products of 8 differences, one reciprocal each); a flagged sample (a hit
+// products of 8 differences, one reciprocal each), with the Lebesgue sum
+// taken by blocks of 16 nodes when the weights alternate in sign (one
+// multiply-add per pair for both sums; the block around the interval, the
+// same for every sample of the wave, takes plain sums); a flagged
+// sample (a hit
 // on a node, which the zoom produces only once the bracket is below the
 // spacing of binary64 numbers, or an extreme product) is recomputed with one
 // division per pair and Lambda = 1 at a hit.
@@ -41,7 +45,8 @@ namespace fhk {
 
 namespace {
 
-constexpr int kLmG = 8;  // nodes per simultaneous inversion
+constexpr int kLmG = 8;   // nodes per simultaneous inversion
+constexpr int kLmU = 16;  // node block of the Lebesgue sums
 
 // t_i = lo + (i + 1) h, product and sum rounded separately
 __device__ __forceinline__ double sample_at(double lo, double h, int i) {
@@ -58,8 +63,8 @@ __device__ __forceinline__ bool better(double v, int i, double bv, int bi) {
 template <int P, int NS>
 __global__ void __launch_bounds__(256)
     k_lebesgue_max(const double* __restrict__ tx, const double* __restrict__ tw, int64_t n_pad,
-                   int64_t n, int32_t samples, int32_t rounds, double* __restrict__ lam_out,
-                   double* __restrict__ x_out) {
+                   int64_t n, int32_t samples, int32_t rounds, const uint32_t* __restrict__ alt,
+                   double* __restrict__ lam_out, double* __restrict__ x_out) {
   constexpr int IG = 4 / NS;  // intervals per block
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -77,6 +82,12 @@ __global__ void __launch_bounds__(256)
 
   const int64_t slice_len = n_pad / NS;
   const int64_t k_begin = part * slice_len, k_end = k_begin + slice_len;
+  // Lebesgue sums by node blocks when the weights alternate in sign; every
+  // sample of the wave lies in interval k, so the one block that can hold
+  // nodes on both sides of it is known: the block of x_k and x_{k+1}, if
+  // they share one (that block gets plain sums)
+  const bool blocks = __builtin_amdgcn_readfirstlane(*alt) != 0;
+  const int64_t split_block = (k + 1) % kLmU != 0 ? k - k % kLmU : -1;
 
   double lo = tx[k], hi = tx[k + 1];
   double best = -INFINITY, best_x = NAN;
@@ -93,7 +104,11 @@ __global__ void __launch_bounds__(256)
       A[j] = 0.0;
       bad[j] = false;
     }
-    accumulate_f64<P, kLmG, false, true>(xp, tx, tw, nullptr, k_begin, k_end, N, D, A, bad);
+    if (blocks)
+      accumulate_f64_blocks<P, kLmG, kLmU, false, true, true>(xp, tx, tw, nullptr, k_begin, k_end,
+                                                               N, D, A, bad, split_block);
+    else
+      accumulate_f64<P, kLmG, false, true>(xp, tx, tw, nullptr, k_begin, k_end, N, D, A, bad);
 
     if constexpr (NS > 1) {
       if (part > 0) {
@@ -230,23 +245,23 @@ __global__ void __launch_bounds__(256)
 }
 
 template <int P, int NS>
-hipError_t launch_lm(const NodeTable& t, int64_t n, int32_t samples, int32_t rounds, double* lam,
-                     double* xk, hipStream_t s) {
+hipError_t launch_lm(const NodeTable& t, int64_t n, int32_t samples, int32_t rounds,
+                     const uint32_t* alt, double* lam, double* xk, hipStream_t s) {
   constexpr int IG = 4 / NS;
   const int64_t blocks = (n - 1 + IG - 1) / IG;
   k_lebesgue_max<P, NS><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(t.x, t.w, t.n_pad, n, samples,
-                                                                     rounds, lam, xk);
+                                                                     rounds, alt, lam, xk);
   return hipGetLastError();
 }
 
 template <int P>
-hipError_t launch_lm_p(const NodeTable& t, int64_t n, int32_t samples, int32_t rounds, double* lam,
-                       double* xk, hipStream_t s) {
+hipError_t launch_lm_p(const NodeTable& t, int64_t n, int32_t samples, int32_t rounds,
+                       const uint32_t* alt, double* lam, double* xk, hipStream_t s) {
   const int64_t intervals = n - 1;
   // enough waves for the chip: about 4 per SIMD (1024 SIMDs)
-  if (intervals >= 4096) return launch_lm<P, 1>(t, n, samples, rounds, lam, xk, s);
-  if (intervals >= 2048) return launch_lm<P, 2>(t, n, samples, rounds, lam, xk, s);
-  return launch_lm<P, 4>(t, n, samples, rounds, lam, xk, s);
+  if (intervals >= 4096) return launch_lm<P, 1>(t, n, samples, rounds, alt, lam, xk, s);
+  if (intervals >= 2048) return launch_lm<P, 2>(t, n, samples, rounds, alt, lam, xk, s);
+  return launch_lm<P, 4>(t, n, samples, rounds, alt, lam, xk, s);
 }
 
 }  // namespace
@@ -263,18 +278,19 @@ size_t layout_lebesgue_max(void* ws, int64_t n, NodeTable* t, double** lam, doub
 }
 
 hipError_t launch_lebesgue_max(const NodeTable& t, int64_t n, int32_t samples, int32_t rounds,
-                               double* lam, double* xk, double* best, hipStream_t s) {
+                               const uint32_t* alt, double* lam, double* xk, double* best,
+                               hipStream_t s) {
   hipError_t e = hipSuccess;
   if (n > 1) {
     const int p = (samples + 63) / 64;
     if (p <= 1)
-      e = launch_lm_p<1>(t, n, samples, rounds, lam, xk, s);
+      e = launch_lm_p<1>(t, n, samples, rounds, alt, lam, xk, s);
     else if (p <= 2)
-      e = launch_lm_p<2>(t, n, samples, rounds, lam, xk, s);
+      e = launch_lm_p<2>(t, n, samples, rounds, alt, lam, xk, s);
     else if (p <= 4)
-      e = launch_lm_p<4>(t, n, samples, rounds, lam, xk, s);
+      e = launch_lm_p<4>(t, n, samples, rounds, alt, lam, xk, s);
     else
-      e = launch_lm_p<8>(t, n, samples, rounds, lam, xk, s);
+      e = launch_lm_p<8>(t, n, samples, rounds, alt, lam, xk, s);
   }
   if (e != hipSuccess || best == nullptr) return e;
   k_lebesgue_best<<<dim3(1), dim3(256), 0, s>>>(lam, xk, n - 1, t.x, best);

@@ -184,32 +184,66 @@ __device__ __forceinline__ int64_t nodes_below(double v, const double* __restric
 // that alternate in sign (Floater-Hormann weights do: every term of w_k has
 // the sign (-1)^(k-d)).  On a block that lies on one side of the point all
 // t_k share a sign, so |w_k t_k| alternates like w_k: the block's
-// sum_k |w_k t_k| is |E - O| and its sum_k w_k t_k is E + O.  Each pair
+// sum_k |w_k t_k| is |E - O| and its sum_k w_k t_k is E + O, with E and O
+// the sums of w_k t_k over the block's even and odd records.  Each pair
 // costs one multiply-add for both sums (two with the plain scheme), each
-// block four additions.  The one block that contains the point (if any)
-// gets its exact sum_k |w_k t_k| from lebesgue_block_fix after the loop.
-// Without L the block sums still form D, so r does not depend on whether
-// Lambda is requested.  Lane flags as in accumulate_f64 (D not finite).
-template <int P, int G, int U, bool R, bool L>
+// block four additions.  Without L the block sums still form D, so r does
+// not depend on whether Lambda is requested.  The one block that holds
+// nodes on both sides of the point is wrong in A: either the caller
+// replaces its term afterwards (lebesgue_block_fix), or, when that block is
+// the same for all points of the wave (SPLIT: block split_block), the loop
+// takes plain sums on it.  Lane flags as in accumulate_f64 (D not finite).
+template <int P, int G, int U, bool R, bool L, bool SPLIT = false>
 __device__ __forceinline__ void accumulate_f64_blocks(const double (&xp)[P],
                                                       const double* __restrict__ tx,
                                                       const double* __restrict__ tw,
                                                       const double* __restrict__ twf,
                                                       int64_t k_begin, int64_t k_end,
                                                       double (&N)[P], double (&D)[P],
-                                                      double (&A)[P], bool (&bad)[P]) {
+                                                      double (&A)[P], bool (&bad)[P],
+                                                      int64_t split_block = -1) {
   static_assert(U % G == 0, "blocks of whole node groups");
   const double* __restrict__ px = tx + k_begin;
   const double* __restrict__ pw = tw + k_begin;
   const double* __restrict__ pv = twf + k_begin;
   const int cnt = (int)(k_end - k_begin);
   for (int k = 0; k < cnt; k += U) {
+    if (SPLIT && k_begin + k == split_block) {
+      // the block around the points: plain sums, right on any block
+#pragma unroll 1
+      for (int h = 0; h < U; h += G) {
+        double xk[G], wk[G], vk[G];
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+          xk[i] = px[k + h + i];
+          wk[i] = pw[k + h + i];
+          vk[i] = R ? pv[k + h + i] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+          double dl[G], t[G];
+#pragma unroll
+          for (int i = 0; i < G; ++i) dl[i] = xp[j] - xk[i];
+          group_product_reciprocals<G>(dl, t);
+#pragma unroll
+          for (int i = 0; i < G; ++i) {
+            if (R) N[j] = __builtin_fma(vk[i], t[i], N[j]);
+            D[j] = __builtin_fma(wk[i], t[i], D[j]);
+            if (L) A[j] = __builtin_fma(fabs(wk[i]), fabs(t[i]), A[j]);
+          }
+        }
+      }
+      continue;
+    }
     // E = sum of w_k t_k over the block's even records, O over its odd ones
-    // (lebesgue_block_fix repeats these operations in this order)
+    // (lebesgue_block_replace repeats these operations in this order)
     double E[P], O[P];
 #pragma unroll
     for (int j = 0; j < P; ++j) E[j] = O[j] = 0.0;
-#pragma unroll
+    // one node group per iteration, as in accumulate_f64: unrolling the
+    // block's groups lets the scheduler overlap them for all P points, at
+    // several times the registers
+#pragma unroll 1
     for (int h = 0; h < U; h += G) {
       double xk[G], wk[G], vk[G];
 #pragma unroll
@@ -244,12 +278,40 @@ __device__ __forceinline__ void accumulate_f64_blocks(const double (&xp)[P],
   for (int j = 0; j < P; ++j) bad[j] |= !(fabs(D[j]) <= 0x1.fffffffffffffp+1023);
 }
 
-// The Lebesgue sum A of accumulate_f64_blocks over the whole table with its
-// one wrong term replaced: if the point v (finite, not a node) lies strictly
-// inside block b (nodes x_{bU} .. x_{bU+U-1} on both sides of it), A holds
-// |E_b - O_b| for that block; it gets sum_k |w_k t_k| instead, recomputed
-// with the same operations.  tx/tw are the padded tables (length a multiple
-// of U), n the node count.
+// The Lebesgue sum A of accumulate_f64_blocks with the term of the block
+// at px/pw (U node records) replaced: A holds |E - O| for that block, which
+// is right only if the block lies on one side of the point v; it gets
+// sum_k |w_k t_k| instead, with E and O recomputed by the same operations.
+template <int G, int U>
+__device__ __forceinline__ double lebesgue_block_replace(double v, const double* __restrict__ px,
+                                                         const double* __restrict__ pw,
+                                                         double A) {
+  double E = 0.0, O = 0.0, exact = 0.0;
+  // one group at a time (once per point: few registers matter more here)
+#pragma unroll 1
+  for (int h = 0; h < U; h += G) {
+    double dl[G], t[G];
+#pragma unroll
+    for (int i = 0; i < G; ++i) dl[i] = v - px[h + i];
+    group_product_reciprocals<G>(dl, t);
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      const double wk = pw[h + i];
+      if (i & 1)
+        O = __builtin_fma(wk, t[i], O);
+      else
+        E = __builtin_fma(wk, t[i], E);
+      exact = __builtin_fma(fabs(wk), fabs(t[i]), exact);
+    }
+  }
+  return (A - fabs(E - O)) + exact;
+}
+
+// A of accumulate_f64_blocks over the whole table, corrected: if the point v
+// (finite, not a node) lies strictly inside block b (nodes x_{bU} ..
+// x_{bU+U-1} on both sides of it, found by binary search), that block's
+// term is replaced.  tx/tw are the padded tables (length a multiple of U),
+// n the node count.
 template <int G, int U>
 __device__ __forceinline__ double lebesgue_block_fix(double v, const double* __restrict__ tx,
                                                      const double* __restrict__ tw, int64_t n,
@@ -257,27 +319,7 @@ __device__ __forceinline__ double lebesgue_block_fix(double v, const double* __r
   const int64_t j = nodes_below(v, tx, n);
   if (j == 0 || j >= n || j % U == 0) return A;
   const int64_t b = j - j % U;
-  double E = 0.0, O = 0.0, exact = 0.0;
-  // one group at a time (once per point: few registers matter more here)
-#pragma unroll 1
-  for (int h = 0; h < U; h += G) {
-    double dl[G], t[G], wk[G];
-#pragma unroll
-    for (int i = 0; i < G; ++i) {
-      dl[i] = v - tx[b + h + i];
-      wk[i] = tw[b + h + i];
-    }
-    group_product_reciprocals<G>(dl, t);
-#pragma unroll
-    for (int i = 0; i < G; ++i) {
-      if (i & 1)
-        O = __builtin_fma(wk[i], t[i], O);
-      else
-        E = __builtin_fma(wk[i], t[i], E);
-      exact = __builtin_fma(fabs(wk[i]), fabs(t[i]), exact);
-    }
-  }
-  return (A - fabs(E - O)) + exact;
+  return lebesgue_block_replace<G, U>(v, tx + b, tw + b, A);
 }
 
 }  // namespace fhk
