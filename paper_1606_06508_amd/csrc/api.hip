@@ -128,7 +128,8 @@ fh_status fh_eval_prepared(void* ws, size_t ws_bytes, int64_t n, int32_t prec, c
       choose_eval_config(prec, n, 0, m, r_out != nullptr, lambda_out != nullptr);
   const hipError_t e = prec == FH_FP32_SPLIT
                            ? launch_eval_split(x, m, t, n, static_cast<int32_t*>(ws) + 1,
-                                               r_out, lambda_out, cfg, s)
+                                               static_cast<uint32_t*>(ws) + 3, r_out,
+                                               lambda_out, cfg, s)
                            : launch_eval_f64(x, m, t, n, static_cast<uint32_t*>(ws) + 3, r_out,
                                              lambda_out, cfg, s);
   return finish(e, ws, s);

@@ -38,12 +38,16 @@
 
 namespace fhk {
 
-template <int P, int G, bool R, bool L>
+// B: the sums are taken by node tiles (split_block_sums<..., B>) when the
+// table's weights alternate in sign, which *alt says (written by the
+// packing); D, hence r, is then the same with and without Lambda.
+template <int P, int G, bool R, bool L, bool B>
 __global__ void __launch_bounds__(kStage)
     k_eval_split(const double* __restrict__ x, int64_t m, const float4* __restrict__ s4,
                  int64_t n_pad, const double* __restrict__ tx, const double* __restrict__ tw,
                  const double* __restrict__ f, int64_t n, const int32_t* __restrict__ scale,
-                 double* __restrict__ r, double* __restrict__ lam) {
+                 const uint32_t* __restrict__ alt, double* __restrict__ r,
+                 double* __restrict__ lam) {
   __shared__ float4 stage[2][kStage];
   const double x_first = tx[0], x_last = tx[n - 1];
   const int tid = threadIdx.x;
@@ -65,7 +69,12 @@ __global__ void __launch_bounds__(kStage)
     bad[j] = !in_split_domain(xp[j], x_first, x_last);
   }
 
-  split_block_sums<P, R, L, G>(stage, s4, n_pad, mask, xh, xl, N, D, A, bad);
+  bool blocks = false;
+  if constexpr (B) {
+    blocks = __builtin_amdgcn_readfirstlane(*alt) != 0;
+    if (blocks) split_block_sums<P, R, L, G, true>(stage, s4, n_pad, mask, xh, xl, N, D, A, bad);
+  }
+  if (!blocks) split_block_sums<P, R, L, G>(stage, s4, n_pad, mask, xh, xl, N, D, A, bad);
   const int shift = scale[1];
 
 #pragma unroll
@@ -76,38 +85,44 @@ __global__ void __launch_bounds__(kStage)
     if (bad[j]) {
       eval_point_exact<R, L>(xp[j], tx, tw, f, n, &rv, &lv);
     } else {
+      double a = A[j];
+      if constexpr (B && L)
+        if (blocks) a = split_tile_fix<G>(xp[j], xh[j], xl[j], tx, n, s4, mask, a);
       rv = ldexp(N[j] / D[j], shift);
-      lv = A[j] / fabs(D[j]);
+      lv = a / fabs(D[j]);
     }
     if (R) r[idx] = rv;
     if (L) lam[idx] = lv;
   }
 }
 
-template <int P, int G>
+template <int P, int G, bool B>
 static hipError_t launch_v(const double* x, int64_t m, const NodeTable& t, int64_t n,
-                           const int32_t* sc, double* r, double* lam, hipStream_t s) {
+                           const int32_t* sc, const uint32_t* alt, double* r, double* lam,
+                           hipStream_t s) {
   const int64_t per = (int64_t)kStage * P;
   const dim3 grid((unsigned)((m + per - 1) / per)), block(kStage);
   if (r && lam)
-    k_eval_split<P, G, true, true><<<grid, block, 0, s>>>(x, m, t.s, t.n_pad, t.x, t.w, t.f, n,
-                                                          sc, r, lam);
+    k_eval_split<P, G, true, true, B><<<grid, block, 0, s>>>(x, m, t.s, t.n_pad, t.x, t.w, t.f,
+                                                             n, sc, alt, r, lam);
   else if (r)
-    k_eval_split<P, G, true, false><<<grid, block, 0, s>>>(x, m, t.s, t.n_pad, t.x, t.w, t.f, n,
-                                                           sc, r, lam);
+    k_eval_split<P, G, true, false, B><<<grid, block, 0, s>>>(x, m, t.s, t.n_pad, t.x, t.w, t.f,
+                                                              n, sc, alt, r, lam);
   else
-    k_eval_split<P, G, false, true><<<grid, block, 0, s>>>(x, m, t.s, t.n_pad, t.x, t.w, t.f, n,
-                                                           sc, r, lam);
+    k_eval_split<P, G, false, true, B><<<grid, block, 0, s>>>(x, m, t.s, t.n_pad, t.x, t.w, t.f,
+                                                              n, sc, alt, r, lam);
   return hipGetLastError();
 }
 
-// Variant table: id -> (points per lane P, reciprocal group G); the node
-// split is always 1 here (all waves of a block share the staged node tile).
-#define FH_SPLIT_VARIANTS(X) \
-  X(0, 1, 1) X(1, 2, 1) X(2, 4, 1) X(3, 8, 1) X(4, 1, 4) X(5, 2, 4) X(6, 4, 4) X(7, 8, 4)
+// Variant table: id -> (points per lane P, reciprocal group G, sums by node
+// tiles B); the node split is always 1 here (all waves of a block share the
+// staged node tile).
+#define FH_SPLIT_VARIANTS(X)                                                               \
+  X(0, 1, 1, 0) X(1, 2, 1, 0) X(2, 4, 1, 0) X(3, 8, 1, 0) X(4, 1, 4, 0) X(5, 2, 4, 0)      \
+  X(6, 4, 4, 0) X(7, 8, 4, 0) X(8, 1, 4, 1) X(9, 2, 4, 1) X(10, 4, 4, 1) X(11, 8, 4, 1)
 
 int split_variant_count() {
-#define FH_COUNT(id, p, g) +1
+#define FH_COUNT(id, p, g, b) +1
   return 0 FH_SPLIT_VARIANTS(FH_COUNT);
 #undef FH_COUNT
 }
@@ -115,10 +130,10 @@ int split_variant_count() {
 void split_variant_shape(int id, int* p, int* g, int* s) {
   *s = 1;
   switch (id) {
-#define FH_SHAPE(vid, vp, vg) \
-  case vid:                   \
-    *p = vp;                  \
-    *g = vg;                  \
+#define FH_SHAPE(vid, vp, vg, vb) \
+  case vid:                       \
+    *p = vp;                      \
+    *g = vg;                      \
     return;
     FH_SPLIT_VARIANTS(FH_SHAPE)
 #undef FH_SHAPE
@@ -126,13 +141,23 @@ void split_variant_shape(int id, int* p, int* g, int* s) {
   }
 }
 
+int split_variant_block(int id) {
+  switch (id) {
+#define FH_BLOCK(vid, vp, vg, vb) \
+  case vid: return vb ? kTile : 0;
+    FH_SPLIT_VARIANTS(FH_BLOCK)
+#undef FH_BLOCK
+    default: return 0;
+  }
+}
+
 hipError_t launch_eval_split(const double* x, int64_t m, const NodeTable& t, int64_t n,
-                             const int32_t* scale, double* r, double* lam, const EvalConfig& cfg,
-                             hipStream_t s) {
+                             const int32_t* scale, const uint32_t* alt, double* r, double* lam,
+                             const EvalConfig& cfg, hipStream_t s) {
   if (m == 0) return hipSuccess;
   switch (cfg.variant) {
-#define FH_CASE(vid, vp, vg) \
-  case vid: return launch_v<vp, vg>(x, m, t, n, scale, r, lam, s);
+#define FH_CASE(vid, vp, vg, vb) \
+  case vid: return launch_v<vp, vg, vb != 0>(x, m, t, n, scale, alt, r, lam, s);
     FH_SPLIT_VARIANTS(FH_CASE)
 #undef FH_CASE
     default: return hipErrorInvalidValue;

@@ -55,6 +55,7 @@ void f64_variant_shape(int id, int* p, int* g, int* s);
 int f64_variant_block(int id);  // Lebesgue block length U, 0 for plain sums
 int split_variant_count();
 void split_variant_shape(int id, int* p, int* g, int* s);
+int split_variant_block(int id);  // node tile of the block sums, 0 for plain sums
 int batched_variant_count();
 void batched_variant_shape(int id, int* p, int* g, int* s, bool split);
 
@@ -142,7 +143,7 @@ hipError_t launch_lebesgue_max(const NodeTable& t, int64_t n, int32_t samples, i
                                const uint32_t* alt, double* lam, double* xk, double* best,
                                hipStream_t s);
 hipError_t launch_eval_split(const double* x, int64_t m, const NodeTable& t, int64_t n,
-                             const int32_t* scale, double* r, double* lam, const EvalConfig& cfg,
-                             hipStream_t s);
+                             const int32_t* scale, const uint32_t* alt, double* r, double* lam,
+                             const EvalConfig& cfg, hipStream_t s);
 
 }  // namespace fhk

@@ -6,6 +6,8 @@
 
 #include <cstdint>
 
+#include "pair_math.h"
+
 namespace fhk {
 
 constexpr int kTile = 32;     // binary32 partial-sum length (nodes)
@@ -55,8 +57,12 @@ __device__ __forceinline__ void group4_reciprocals32(float& d0, float& d1, float
 // simultaneous inversion of the four differences of each node quad
 // (group4_reciprocals32).  A tile sum that is not finite -- a point on or
 // extremely close to a node, a NaN point -- flags the lane for the exact
-// path.  Must be called by all threads of the block.
-template <int P, bool R, bool L, int G = 1>
+// path.  B (weights that alternate in sign, see accumulate_f64_blocks): each
+// tile is a block, its sums E (first and third record of every quad) and O
+// (second and fourth) give D += E + O and A += |E - O| with one multiply-
+// add per pair; the tile around the point is corrected afterwards
+// (split_tile_fix).  Must be called by all threads of the block.
+template <int P, bool R, bool L, int G = 1, bool B = false>
 __device__ __forceinline__ void split_block_sums(float4 (&stage)[2][kStage],
                                                  const float4* __restrict__ s4, int64_t n_pad,
                                                  uint32_t mask, const float (&xh)[P],
@@ -64,6 +70,7 @@ __device__ __forceinline__ void split_block_sums(float4 (&stage)[2][kStage],
                                                  double (&D)[P], double (&A)[P], bool (&bad)[P]) {
   static_assert(G == 1 || G == 4, "group size 1 or 4");
   const int tid = threadIdx.x;
+  // B: Dt and At hold the tile's E and O
   float Nt[P], Dt[P], At[P];
 #pragma unroll
   for (int j = 0; j < P; ++j) Nt[j] = Dt[j] = At[j] = 0.0f;
@@ -97,6 +104,19 @@ __device__ __forceinline__ void split_block_sums(float4 (&stage)[2][kStage],
 #pragma unroll
           for (int j = 0; j < P; ++j) group4_reciprocals32(t[0][j], t[1][j], t[2][j], t[3][j]);
         }
+        if constexpr (B) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int j = 0; j < P; ++j) {
+              if (q & 1)
+                At[j] = __builtin_fmaf(rc[q].z, t[q][j], At[j]);
+              else
+                Dt[j] = __builtin_fmaf(rc[q].z, t[q][j], Dt[j]);
+              if (R) Nt[j] = __builtin_fmaf(rc[q].w, t[q][j], Nt[j]);
+            }
+          continue;
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -112,6 +132,22 @@ __device__ __forceinline__ void split_block_sums(float4 (&stage)[2][kStage],
             for (int j = 0; j < P; ++j) At[j] = __builtin_fmaf(aw, abs_vop2(t[q][j], mask), At[j]);
           }
         }
+      }
+      if constexpr (B) {
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+          bad[j] |= not_finite32(Dt[j]) | not_finite32(At[j]);
+          const double e = (double)Dt[j], o = (double)At[j];
+          D[j] += e + o;
+          if (L) A[j] += fabs(e - o);
+          Dt[j] = At[j] = 0.0f;
+          if (R) {
+            bad[j] |= not_finite32(Nt[j]);
+            N[j] += (double)Nt[j];
+            Nt[j] = 0.0f;
+          }
+        }
+        continue;
       }
 #pragma unroll
       for (int j = 0; j < P; ++j) {
@@ -133,6 +169,47 @@ __device__ __forceinline__ void split_block_sums(float4 (&stage)[2][kStage],
     __syncthreads();
     buf ^= 1;
   }
+}
+
+// The Lebesgue sum A of split_block_sums<..., B = true> corrected for the
+// tile (kTile records) that holds nodes on both sides of the point xv (found
+// by binary search in the binary64 nodes tx[0, n)): its |E - O|, recomputed
+// from the split records s4 with the loop's operations, is replaced by
+// sum_k |w_k t_k|.  xv finite and not a node.
+template <int G>
+__device__ __forceinline__ double split_tile_fix(double xv, float xh, float xl,
+                                                 const double* __restrict__ tx, int64_t n,
+                                                 const float4* __restrict__ s4, uint32_t mask,
+                                                 double A) {
+  const int64_t j = nodes_below(xv, tx, n);
+  if (j == 0 || j >= n || j % kTile == 0) return A;
+  const int64_t b = j - j % kTile;
+  float E = 0.0f, O = 0.0f, exact = 0.0f;
+#pragma unroll 1
+  for (int i = 0; i < kTile; i += 4) {
+    float4 rc[4];
+    float t[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      rc[q] = s4[b + i + q];
+      t[q] = (xh - rc[q].x) + (xl - rc[q].y);
+    }
+    if constexpr (G == 1) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) t[q] = __builtin_amdgcn_rcpf(t[q]);
+    } else {
+      group4_reciprocals32(t[0], t[1], t[2], t[3]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (q & 1)
+        O = __builtin_fmaf(rc[q].z, t[q], O);
+      else
+        E = __builtin_fmaf(rc[q].z, t[q], E);
+      exact = __builtin_fmaf(abs_vop2(rc[q].z, mask), abs_vop2(t[q], mask), exact);
+    }
+  }
+  return (A - fabs((double)E - (double)O)) + (double)exact;
 }
 
 // Streams the records src[0, count) (count a multiple of 4) through the

@@ -56,8 +56,8 @@ struct Builtin {
 constexpr Builtin kBuiltin[] = {
     {FH_FP64, 6, 14, 7},       {FH_FP64, 10, 20, 17},      {FH_FP64, 12, 20, 16},
     {FH_FP64, 13, 20, 16},     {FH_FP64, 13, 24, 18},      {FH_FP32_SPLIT, 6, 14, 4},
-    {FH_FP32_SPLIT, 10, 20, 5},
-    {FH_FP32_SPLIT, 12, 20, 5}, {FH_FP32_SPLIT, 13, 24, 5},
+    {FH_FP32_SPLIT, 10, 20, 9}, {FH_FP32_SPLIT, 12, 20, 9}, {FH_FP32_SPLIT, 13, 20, 9},
+    {FH_FP32_SPLIT, 13, 24, 9},
 };
 
 // Untuned shapes: two points per lane with the node range split over the
@@ -68,7 +68,7 @@ int default_variant(int32_t prec, int nb, int mb) {
   for (const Builtin& b : kBuiltin)
     if (b.prec == prec && b.nb == nb && b.mb == mb) return b.variant;
   if (prec == FH_TUNE_BATCHED_FP64 || prec == FH_TUNE_BATCHED_SPLIT) return 1;  // P = 2
-  if (prec == FH_FP32_SPLIT) return mb <= 16 ? 6 : 5;  // P = 4 / 2, quads inverted together
+  if (prec == FH_FP32_SPLIT) return mb <= 16 ? 10 : 9;  // P = 4 / 2, quads, tile sums
   return 16;                                            // P = 2, G = 8, S = 4, U = 16
 }
 
@@ -116,7 +116,8 @@ fh_status fh_variant_shape(int32_t prec, int32_t id, int32_t* points_per_lane, i
 
 int32_t fh_variant_lebesgue_block(int32_t prec, int32_t id) {
   if (!valid_family(prec) || id < 0 || id >= variant_count(prec)) return -1;
-  return prec == FH_FP64 ? f64_variant_block(id) : 0;
+  if (prec == FH_FP64) return f64_variant_block(id);
+  return prec == FH_FP32_SPLIT ? split_variant_block(id) : 0;
 }
 
 fh_status fh_tune_force(int32_t prec, int32_t id) {

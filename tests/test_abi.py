@@ -151,16 +151,22 @@ def test_variant_tables_and_tuner_api():
 
 
 def test_lebesgue_block_variants():
-    """Binary64 variants 15..18 take the Lebesgue sum by blocks of 16 nodes
-    (the block counterparts of plain shapes); every other variant, and every
-    split and batched variant, uses plain sums."""
+    """Binary64 variants 15..18 take the Lebesgue sum by blocks of 16 nodes,
+    split variants 8..11 by tiles of 32 (the block counterparts of plain
+    shapes); every other variant, and every batched variant, uses plain
+    sums."""
     blocks = {vid: fh.variant_lebesgue_block("fp64", vid) for vid, *_ in fh.variants("fp64")}
     assert {vid for vid, u in blocks.items() if u} == {15, 16, 17, 18}
     assert set(blocks.values()) == {0, 16}
     shapes = {vid: (p, g, s) for vid, p, g, s in fh.variants("fp64")}
     for vid in (15, 16, 17, 18):
         assert shapes[vid] in [shapes[v] for v, u in blocks.items() if u == 0]
-    for fam in ("split", 2, 3):
+    sb = {vid: fh.variant_lebesgue_block("split", vid) for vid, *_ in fh.variants("split")}
+    assert {vid for vid, u in sb.items() if u} == {8, 9, 10, 11} and set(sb.values()) == {0, 32}
+    sshapes = {vid: (p, g, s) for vid, p, g, s in fh.variants("split")}
+    for vid in (8, 9, 10, 11):
+        assert sshapes[vid] in [sshapes[v] for v, u in sb.items() if u == 0]
+    for fam in (2, 3):
         for vid, *_ in fh.variants(fam):
             assert fh.variant_lebesgue_block(fam, vid) == 0
     lib = fh.load()
