@@ -3,7 +3,7 @@
 // f^(c).  Every interpolant's sums need the same reciprocals
 // t_k = 1 / (x - x_k) of the point-node pairs; computing them once for all
 // columns divides their cost (a difference, the simultaneous inversion of
-// eight differences per v_rcp_f64, the flag compares) by the number of
+// eight differences per v_rcp_f64) by the number of
 // columns, leaving the three fused multiply-adds per pair and column
 // (N += (w f) t, D += w t, L += |w| |t|).  When every column has the same
 // degree the weights are shared and so are D and L: one fused multiply-add
