@@ -305,3 +305,39 @@ def test_oracle_own_error_against_sixty_digit_evaluation(d):
             r_ref, lam_ref = float(N / D), float(L / abs(D))
             assert abs(r_o[p] - r_ref) <= 4 * U * s_o[p], (p, r_o[p], r_ref)
             assert abs(lam_o[p] - lam_ref) <= 4 * U * lam_ref * (1 + lam_ref), p
+
+
+@pytest.mark.parametrize("family", ["equispaced", "cheb2", "jittered", "random"])
+def test_weights_alternate_strictly_in_sign(family):
+    """Floater-Hormann weights alternate strictly in sign: every term of the
+    sum that defines w_k has the sign (-1)^(k-d) (the no-poles argument of
+    Floater & Hormann 2007), so w_k w_{k+1} < 0 for every k.  The block sums
+    of the evaluation kernels rely on it.  Checked on the oracle's weights
+    for random node sets, n = 2..120 and every degree up to 10 (and in exact
+    rationals on a small set)."""
+    g = np.random.default_rng({"equispaced": 1, "cheb2": 2, "jittered": 3, "random": 4}[family])
+    for n in list(range(2, 20)) + [37, 64, 120]:
+        if family == "equispaced":
+            nodes = inputs.equispaced(n)
+        elif family == "cheb2":
+            nodes = inputs.cheb2(n)
+        elif family == "jittered":
+            nodes = inputs.jittered_nodes(n, g, rel=0.3) if n > 2 else inputs.equispaced(n)
+        else:  # gaps spanning six orders of magnitude
+            nodes = np.cumsum(10.0 ** g.uniform(-6, 0, n))
+        for d in range(0, min(n - 1, 10) + 1):
+            w = oracle.weights(nodes, d)
+            assert np.all(w[:-1] * w[1:] < 0), (n, d)
+            assert np.all(np.sign(w) == (-1.0) ** (np.arange(n) - d)), (n, d)
+    # exact rationals: the sign pattern is a property of the formula, not of rounding
+    xs = [Fraction(0), Fraction(1, 7), Fraction(1, 3), Fraction(1, 2), Fraction(5, 6), Fraction(1)]
+    for d in range(len(xs)):
+        for k in range(len(xs)):
+            terms = []
+            for i in range(max(0, k - d), min(k, len(xs) - 1 - d) + 1):
+                prod = Fraction(1)
+                for j in range(i, i + d + 1):
+                    if j != k:
+                        prod *= xs[k] - xs[j]
+                terms.append(Fraction((-1) ** i) / prod)
+            assert all((t > 0) == ((k - d) % 2 == 0) for t in terms), (d, k)
