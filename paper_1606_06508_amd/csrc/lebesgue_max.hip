@@ -87,7 +87,7 @@ __global__ void __launch_bounds__(256)
   // nodes on both sides of it is known: the block of x_k and x_{k+1}, if
   // they share one (that block gets plain sums)
   const bool blocks = __builtin_amdgcn_readfirstlane(*alt) != 0;
-  const int64_t split_block = (k + 1) % kLmU != 0 ? k - k % kLmU : -1;
+  const int64_t plain_block = (k + 1) % kLmU != 0 ? k - k % kLmU : -1;
 
   double lo = tx[k], hi = tx[k + 1];
   double best = -INFINITY, best_x = NAN;
@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(256)
     }
     if (blocks)
       accumulate_f64_blocks<P, kLmG, kLmU, false, true, true>(xp, tx, tw, nullptr, k_begin, k_end,
-                                                               N, D, A, bad, split_block);
+                                                               N, D, A, bad, plain_block);
     else
       accumulate_f64<P, kLmG, false, true>(xp, tx, tw, nullptr, k_begin, k_end, N, D, A, bad);
 

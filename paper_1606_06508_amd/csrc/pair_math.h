@@ -191,9 +191,10 @@ __device__ __forceinline__ int64_t nodes_below(double v, const double* __restric
 // not depend on whether Lambda is requested.  The one block that holds
 // nodes on both sides of the point is wrong in A: either the caller
 // replaces its term afterwards (lebesgue_block_fix), or, when that block is
-// the same for all points of the wave (SPLIT: block split_block), the loop
-// takes plain sums on it.  Lane flags as in accumulate_f64 (D not finite).
-template <int P, int G, int U, bool R, bool L, bool SPLIT = false>
+// the same for all points of the wave (KNOWN_BLOCK: the block starting at
+// record plain_block), the loop takes plain sums on it.  Lane flags as in
+// accumulate_f64 (D not finite).
+template <int P, int G, int U, bool R, bool L, bool KNOWN_BLOCK = false>
 __device__ __forceinline__ void accumulate_f64_blocks(const double (&xp)[P],
                                                       const double* __restrict__ tx,
                                                       const double* __restrict__ tw,
@@ -201,14 +202,14 @@ __device__ __forceinline__ void accumulate_f64_blocks(const double (&xp)[P],
                                                       int64_t k_begin, int64_t k_end,
                                                       double (&N)[P], double (&D)[P],
                                                       double (&A)[P], bool (&bad)[P],
-                                                      int64_t split_block = -1) {
+                                                      int64_t plain_block = -1) {
   static_assert(U % G == 0, "blocks of whole node groups");
   const double* __restrict__ px = tx + k_begin;
   const double* __restrict__ pw = tw + k_begin;
   const double* __restrict__ pv = twf + k_begin;
   const int cnt = (int)(k_end - k_begin);
   for (int k = 0; k < cnt; k += U) {
-    if (SPLIT && k_begin + k == split_block) {
+    if (KNOWN_BLOCK && k_begin + k == plain_block) {
       // the block around the points: plain sums, right on any block
 #pragma unroll 1
       for (int h = 0; h < U; h += G) {
