@@ -4,10 +4,12 @@ pairs per second (Gpair/s), at a stated max error against the FP64 oracle.
 
 Workload of the headline line ("sines"): n = 1001 equispaced nodes on
 [-1,1], f = sum of 8 seeded sines, 10^6 uniform points, blending degree d
-swept 0..8.  One step = for every d: the weight pass and node-table packing
-(fh_prepare) and the fused r + Lebesgue evaluation (fh_eval_prepared) of all
-10^6 points into that degree's own output arrays.  value = 9 * n * m pairs
-per step / step time.  Inputs are resident in HBM before timing starts.
+swept 0..8.  One step = the weight pass and node-table packing of all nine
+degrees (fh_prepare_many, one launch, each degree into its own workspace)
+and, for every d, the fused r + Lebesgue evaluation (fh_eval_prepared) of
+all 10^6 points into that degree's own output arrays.  value = 9 * n * m
+pairs per step / step time.  Inputs are resident in HBM before timing
+starts.
 
 Also reported in the same JSON line:
   roofline      the evaluation kernel (the dominant kernel), timed live with
@@ -26,6 +28,7 @@ Also reported in the same JSON line:
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -76,27 +79,33 @@ def measured_traffic(n, m):
 
 
 def run_sines(dev, steps, warmup):
-    """The headline step: for every d the weight pass with node-table packing
-    (fh_prepare) and the fused r + Lambda evaluation (fh_eval_prepared) of
-    all points, each degree into its own output arrays, on one stream.
-    (Packing the next degree on a second stream, overlapped with the current
-    evaluation, was measured slower: the cross-stream event waits cost more
-    than the ~6 us packing they hide.)"""
+    """The headline step: the node tables of all nine degrees (weights and
+    packing, fh_prepare_many: one launch) and the fused r + Lambda evaluation
+    of all points for each degree (fh_eval_prepared), each degree into its
+    own workspace and output arrays, on one stream.  (Packing each degree
+    with fh_prepare just before its evaluation costs a launch and two
+    dependent-launch gaps per degree, ~8 us; packing the next degree on a
+    second stream, overlapped with the current evaluation, was measured
+    slower: the cross-stream event waits cost more than they hide.)"""
     c = inputs.sines_workload()
     n, m, degrees = c["nodes"].size, c["points"].size, c["degrees"]
     nodes, vals, x = _t(c["nodes"], dev), _t(c["values"], dev), _t(c["points"], dev)
     r = torch.empty((len(degrees), m), dtype=torch.float64, device=dev)
     lam = torch.empty((len(degrees), m), dtype=torch.float64, device=dev)
-    ws = fh.Workspace(dev, fh.workspace_size(fh.FH_OP_EVAL, n, m, 8))
+    ws_bytes = fh.workspace_size(fh.FH_OP_EVAL, n, m, max(degrees))
+    wss = [fh.Workspace(dev, ws_bytes) for _ in degrees]
+    K = len(degrees)
+    d_arr = (ctypes.c_int32 * K)(*degrees)
+    ws_arr = (ctypes.c_void_p * K)(*[w.buf.data_ptr() for w in wss])
     lib = fh.load()
-    buf = ws.buf
     stream = torch.cuda.current_stream(dev)
     sptr = fh._stream(dev)
     P = fh._ptr
 
     def step(evs=None):
+        st = lib.fh_prepare_many(P(nodes), P(vals), n, d_arr, K, fh.FH_FP64, ws_arr, ws_bytes, sptr)
         for i, d in enumerate(degrees):
-            st = lib.fh_prepare(P(nodes), P(vals), n, d, None, fh.FH_FP64, P(buf), buf.numel(), sptr)
+            buf = wss[i].buf
             if evs is not None:
                 evs.append(torch.cuda.Event(enable_timing=True))
                 evs[-1].record(stream)
@@ -105,8 +114,8 @@ def run_sines(dev, steps, warmup):
             if evs is not None:
                 evs.append(torch.cuda.Event(enable_timing=True))
                 evs[-1].record(stream)
-            if st:
-                raise fh.FhError(st, "bench step")
+        if st:
+            raise fh.FhError(st, "bench step")
 
     for _ in range(warmup):
         step()

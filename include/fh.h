@@ -143,6 +143,22 @@ fh_status fh_prepare(const double* nodes, const double* values, int64_t n, int32
 fh_status fh_eval_prepared(void* ws, size_t ws_bytes, int64_t n, int32_t prec, const double* x,
                            int64_t m, double* r_out, double* lambda_out, void* stream);
 
+/* fh_prepare for K degrees of one interpolant at once (a sweep over d), in
+ * one launch: workspace ws_host[c] gets the table of degree d_host[c], the
+ * same bits fh_prepare(nodes, values, n, d_host[c], NULL, prec, ws_host[c],
+ * ...) writes; each is then evaluated with fh_eval_prepared.
+ *   d_host   host array of K degrees, each in 0..n-1;  1 <= K <= 16
+ *   ws_host  host array of K distinct device workspaces, each of at least
+ *            fh_workspace_size(FH_OP_EVAL, n, m, d_host[c], prec) <= ws_bytes
+ *            bytes (the same ws_bytes is checked for all)
+ *   prec     FH_FP64 (FH_FP32_SPLIT tables: FH_E_UNSUPPORTED; use fh_prepare)
+ *   values   may be NULL (tables for Lambda only, as with fh_prepare)
+ * Errors as in fh_prepare; FH_E_ARG also for K out of range or a workspace
+ * listed twice.  The library's weights are computed, never caller weights. */
+fh_status fh_prepare_many(const double* nodes, const double* values, int64_t n,
+                          const int32_t* d_host, int32_t K, int32_t prec, void* const* ws_host,
+                          size_t ws_bytes, void* stream);
+
 /* Lambda(x_p) only (the Lebesgue function of the interpolation scheme,
  * sum_k |b_k(x)| with cardinal functions b_k = a_k / sum_j a_j).  Arguments
  * as in fh_eval; no values are needed. */

@@ -113,6 +113,43 @@ fh_status fh_prepare(const double* nodes, const double* values, int64_t n, int32
                 ws, s);
 }
 
+fh_status fh_prepare_many(const double* nodes, const double* values, int64_t n,
+                          const int32_t* d_host, int32_t K, int32_t prec, void* const* ws_host,
+                          size_t ws_bytes, void* stream) {
+  if (n < 1 || n > FH_MAX_NODES || nodes == nullptr || d_host == nullptr || ws_host == nullptr)
+    return FH_E_ARG;
+  if (K < 1 || K > kPackMany) return FH_E_ARG;
+  if (prec == FH_FP32_SPLIT) return FH_E_UNSUPPORTED;
+  if (prec != FH_FP64) return FH_E_ARG;
+  PackMany a{};
+  for (int32_t c = 0; c < K; ++c) {
+    const int32_t d = d_host[c];
+    if (d < 0 || (int64_t)d > n - 1) return FH_E_DEGREE;
+    fh_status st = check_ws(ws_host[c], ws_bytes, fh_workspace_size(FH_OP_EVAL, n, 0, d, prec));
+    if (st != FH_OK) return st;
+    for (int32_t e = 0; e < c; ++e)
+      if (ws_host[e] == ws_host[c]) return FH_E_ARG;  // one table per workspace
+    NodeTable t;
+    layout_tables(ws_host[c], n, &t);
+    a.x[c] = t.x;
+    a.w[c] = t.w;
+    a.wf[c] = t.wf;
+    a.f[c] = t.f;
+    a.status[c] = static_cast<uint32_t*>(ws_host[c]);
+    a.d[c] = d;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (launch_pack_many(nodes, values, n, a, K, s) != hipSuccess) return FH_E_HIP;
+  if (sync_check_enabled()) {
+    for (int32_t c = 0; c < K; ++c) {
+      uint32_t bits = 0;
+      const fh_status st = fh_device_status(ws_host[c], s, &bits);
+      if (st != FH_OK) return st;
+    }
+  }
+  return FH_OK;
+}
+
 fh_status fh_eval_prepared(void* ws, size_t ws_bytes, int64_t n, int32_t prec, const double* x,
                            int64_t m, double* r_out, double* lambda_out, void* stream) {
   if (n < 1 || n > FH_MAX_NODES || m < 0 || (m > 0 && x == nullptr)) return FH_E_ARG;

@@ -109,6 +109,18 @@ hipError_t launch_multi(const double* nodes, const double* values, int64_t n,
 // ---- launchers (each returns the launch error, hipSuccess on success) ----
 hipError_t launch_weights(const double* nodes, int64_t n, int32_t d, double* w_out,
                           uint32_t* status, hipStream_t s);
+// Tables of up to kPackMany degrees of one interpolant (FP64), one launch.
+constexpr int kPackMany = 16;
+struct PackMany {
+  double* x[kPackMany];
+  double* w[kPackMany];
+  double* wf[kPackMany];
+  double* f[kPackMany];
+  uint32_t* status[kPackMany];
+  int32_t d[kPackMany];
+};
+hipError_t launch_pack_many(const double* nodes, const double* values, int64_t n,
+                            const PackMany& a, int32_t K, hipStream_t s);
 hipError_t launch_pack(const double* nodes, const double* values, const double* w_in, int64_t n,
                        int32_t d, const NodeTable& t, bool split, uint32_t* status,
                        hipStream_t s);

@@ -78,6 +78,46 @@ __global__ void __launch_bounds__(256) k_pack(const double* __restrict__ x,
   if (flags) atomicOr(status, flags);
 }
 
+// The FP64 node tables of K degrees of one interpolant in one launch
+// (blockIdx.y = c packs degree a.d[c] into the tables of workspace c), with
+// the per-node arithmetic of k_pack: the same tables, bit for bit.
+template <bool LDS>
+__global__ void __launch_bounds__(256) k_pack_many(const double* __restrict__ x,
+                                                   const double* __restrict__ f, int64_t n,
+                                                   int64_t n_pad, PackMany a) {
+#pragma clang fp contract(off)
+  extern __shared__ double xs[];
+  const int c = blockIdx.y;
+  const int32_t d = a.d[c];
+  const int64_t base = (int64_t)blockIdx.x * blockDim.x;
+  const int64_t k = base + threadIdx.x;
+  if (k == 0) a.status[c][3] = 1u;  // the library's weights alternate in sign
+  if constexpr (LDS) stage_weight_window(x, n, d, base, xs);
+  if (k >= n_pad) return;
+  double* __restrict__ tx = a.x[c];
+  double* __restrict__ tw = a.w[c];
+  double* __restrict__ twf = a.wf[c];
+  double* __restrict__ tf = a.f[c];
+  if (k >= n) {
+    tx[k] = x[n - 1];
+    tw[k] = 0.0;
+    twf[k] = 0.0;
+    tf[k] = 0.0;
+    return;
+  }
+  uint32_t flags = node_checks(x, n, k);
+  double wk;
+  if constexpr (LDS)
+    wk = node_weight_of([&](int64_t j) { return xs[j - base + d]; }, n, d, k, &flags);
+  else
+    wk = node_weight(x, n, d, k, &flags);
+  tx[k] = x[k];
+  tw[k] = wk;
+  twf[k] = f ? wk * f[k] : 0.0;
+  tf[k] = f ? f[k] : 0.0;
+  if (flags) atomicOr(a.status[c], flags);
+}
+
 // Split (binary32) node table (split_table_scale / split_record).  Every
 // block reduces the whole table itself (n is small next to the evaluation;
 // doing it per block avoids a second pass and any atomics); block 0 stores
@@ -146,6 +186,20 @@ hipError_t launch_pack(const double* nodes, const double* values, const double* 
   if (e != hipSuccess || !split) return e;
   k_pack_split<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(
       t.x, t.w, t.wf, n, t.n_pad, t.s, reinterpret_cast<int32_t*>(status) + 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_many(const double* nodes, const double* values, int64_t n,
+                            const PackMany& a, int32_t K, hipStream_t s) {
+  const int64_t n_pad = round_up(n, kNodePad);
+  const dim3 grid((unsigned)((n_pad + 255) / 256), (unsigned)K);
+  int32_t dmax = 0;
+  for (int32_t c = 0; c < K; ++c) dmax = a.d[c] > dmax ? a.d[c] : dmax;
+  if (dmax <= kWeightLdsMaxD)
+    k_pack_many<true><<<grid, dim3(256), weight_window_bytes(dmax, 256), s>>>(nodes, values, n,
+                                                                             n_pad, a);
+  else
+    k_pack_many<false><<<grid, dim3(256), 0, s>>>(nodes, values, n, n_pad, a);
   return hipGetLastError();
 }
 

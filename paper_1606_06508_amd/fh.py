@@ -55,6 +55,8 @@ def load():
             "fh_eval": ([vp, vp, i64, i32, vp, i64, vp, vp, vp, i32, vp, sz, vp], ctypes.c_int),
             "fh_lebesgue": ([vp, i64, i32, vp, i64, vp, vp, i32, vp, sz, vp], ctypes.c_int),
             "fh_prepare": ([vp, vp, i64, i32, vp, i32, vp, sz, vp], ctypes.c_int),
+            "fh_prepare_many": ([vp, vp, i64, ctypes.POINTER(i32), i32, i32,
+                                 ctypes.POINTER(vp), sz, vp], ctypes.c_int),
             "fh_eval_prepared": ([vp, sz, i64, i32, vp, i64, vp, vp, vp], ctypes.c_int),
             "fh_eval_backward": ([vp, vp, i64, i32, vp, i64, vp, vp, vp, vp, i32, vp, sz, vp],
                                  ctypes.c_int),
@@ -309,13 +311,16 @@ class Prepared:
     """An interpolant whose node table lives in its own workspace, for
     evaluation on many point batches (fh_prepare + fh_eval_prepared)."""
 
-    def __init__(self, nodes, values, d, *, weights=None, precision="fp64", m_hint=0):
+    def __init__(self, nodes, values, d, *, weights=None, precision="fp64", m_hint=0,
+                 _pack=True):
         lib = load()
         self.nodes = _f64(nodes, "nodes")
         self.values = None if values is None else _f64(values, "values")
         self.n, self.d, self.prec = self.nodes.numel(), int(d), _prec(precision)
         self.device = self.nodes.device
         self.ws = Workspace(self.device, workspace_size(FH_OP_EVAL, self.n, m_hint, d, self.prec))
+        if not _pack:  # filled by prepare_many
+            return
         buf = self.ws.buf
         _check(lib.fh_prepare(_ptr(self.nodes), _ptr(self.values), self.n, self.d, _ptr(weights),
                               self.prec, _ptr(buf), buf.numel(), _stream(self.device)),
@@ -336,6 +341,25 @@ class Prepared:
         if want_r and lebesgue:
             return r, lam
         return r if want_r else lam
+
+
+def prepare_many(nodes, values, degrees, *, m_hint=0):
+    """Prepared interpolants of several degrees on the same nodes and values
+    (binary64), their tables packed in one launch (fh_prepare_many): the
+    same tables as Prepared(nodes, values, d) for each d."""
+    lib = load()
+    degrees = [int(d) for d in degrees]
+    preps = [Prepared(nodes, values, d, m_hint=m_hint, _pack=False) for d in degrees]
+    size = max(p.ws.buf.numel() for p in preps)
+    for p in preps:
+        p.ws.reserve(size)
+    K = len(preps)
+    ds = (ctypes.c_int32 * K)(*degrees)
+    wss = (ctypes.c_void_p * K)(*[p.ws.buf.data_ptr() for p in preps])
+    xn = preps[0].nodes
+    _check(lib.fh_prepare_many(_ptr(xn), _ptr(preps[0].values), xn.numel(), ds, K, FH_FP64, wss,
+                               size, _stream(xn.device)), "fh_prepare_many")
+    return preps
 
 
 def _family(family):

@@ -250,3 +250,24 @@ def test_node_count_limit():
     assert lib.fh_batch_create(ctypes.byref(h), 2, n_host, d_host, m_host, P, P, P, P2, None, 0,
                                None) == fh.FH_E_ARG
     assert h.value is None
+
+
+def test_prepare_many_host_validation():
+    lib = fh.load()
+    ws = (ctypes.c_void_p * 3)(0x100000, 0x200000, 0x300000)
+
+    def call(K=3, degs=(1, 2, 3), n=10, prec=0, wss=ws, ws_bytes=1 << 30, nodes=P):
+        d = (ctypes.c_int32 * max(len(degs), 1))(*degs)
+        return lib.fh_prepare_many(nodes, P, n, d, K, prec, wss, ws_bytes, None)
+
+    assert call(K=0, degs=()) == fh.FH_E_ARG
+    assert call(K=17, degs=tuple([1] * 17),
+                wss=(ctypes.c_void_p * 17)(*[0x100000 * (i + 1) for i in range(17)])) == fh.FH_E_ARG
+    assert call(n=0) == fh.FH_E_ARG and call(nodes=None) == fh.FH_E_ARG
+    assert call(prec=1) == fh.FH_E_UNSUPPORTED and call(prec=3) == fh.FH_E_ARG
+    assert call(degs=(1, 10, 3)) == fh.FH_E_DEGREE
+    assert call(ws_bytes=300) == fh.FH_E_WORKSPACE
+    assert call(wss=(ctypes.c_void_p * 3)(0x100000, None, 0x300000)) == fh.FH_E_WORKSPACE
+    assert call(wss=(ctypes.c_void_p * 3)(0x100000, 0x200008, 0x300000)) == fh.FH_E_WORKSPACE
+    assert call(wss=(ctypes.c_void_p * 3)(0x100000, 0x200000, 0x100000)) == fh.FH_E_ARG
+    assert lib.fh_prepare_many(P, P, 10, None, 3, 0, ws, 1 << 30, None) == fh.FH_E_ARG
