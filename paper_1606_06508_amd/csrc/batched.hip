@@ -146,7 +146,10 @@ __global__ void __launch_bounds__(256)
       if (idx >= ds.m) continue;
       double rv, lv;
       if (bad[j]) {
-        eval_point_exact<R, L>(xp[j], tx + ds.toff, tw + ds.toff, tf + ds.toff, ds.n, &rv, &lv);
+        const PointRL e =
+            eval_point_exact<R, L>(xp[j], tx + ds.toff, tw + ds.toff, tf + ds.toff, ds.n);
+        rv = e.r;
+        lv = e.l;
       } else {
         rv = ldexp(N[j] / D[j], ds.shift);
         lv = A[j] / fabs(D[j]);
@@ -197,7 +200,10 @@ __global__ void __launch_bounds__(kStage)
       if (idx >= ds.m) continue;
       double rv, lv;
       if (bad[j]) {
-        eval_point_exact<R, L>(xp[j], tx + ds.toff, tw + ds.toff, tf + ds.toff, ds.n, &rv, &lv);
+        const PointRL e =
+            eval_point_exact<R, L>(xp[j], tx + ds.toff, tw + ds.toff, tf + ds.toff, ds.n);
+        rv = e.r;
+        lv = e.l;
       } else {
         rv = ldexp(N[j] / D[j], ds.shift);
         lv = A[j] / fabs(D[j]);
@@ -289,9 +295,9 @@ int resident_grid(fh_batch* b, bool r, bool l) {
 
 void free_batch(fh_batch* b) {
   if (!b) return;
-  if (b->exec) hipGraphExecDestroy(b->exec);
-  if (b->graph) hipGraphDestroy(b->graph);
-  if (b->mem) hipFree(b->mem);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->mem) (void)hipFree(b->mem);
   delete b;
 }
 
@@ -442,9 +448,9 @@ fh_status fh_batch_create(fh_batch** out, int32_t count, const int64_t* n_host,
       k_batch_pack_split<<<(unsigned)count, 256, 0, cs>>>(b->inst, b->tx, b->tw, b->twf, b->s4);
     if (items > 0) {
       switch (b->points_per_lane) {
-        case 1: enqueue_eval<1>(b, x_cat, r_cat, lambda_cat, grid, cs); break;
-        case 2: enqueue_eval<2>(b, x_cat, r_cat, lambda_cat, grid, cs); break;
-        default: enqueue_eval<4>(b, x_cat, r_cat, lambda_cat, grid, cs); break;
+        case 1: e = enqueue_eval<1>(b, x_cat, r_cat, lambda_cat, grid, cs); break;
+        case 2: e = enqueue_eval<2>(b, x_cat, r_cat, lambda_cat, grid, cs); break;
+        default: e = enqueue_eval<4>(b, x_cat, r_cat, lambda_cat, grid, cs); break;
       }
     }
     hipError_t e2 = hipStreamEndCapture(cs, &b->graph);
@@ -452,7 +458,7 @@ fh_status fh_batch_create(fh_batch** out, int32_t count, const int64_t* n_host,
     if (e == hipSuccess) e = e2;
   }
   if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
-  hipStreamDestroy(cs);
+  (void)hipStreamDestroy(cs);
   if (e != hipSuccess) {
     free_batch(b);
     return FH_E_HIP;

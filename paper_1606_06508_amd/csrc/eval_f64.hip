@@ -110,7 +110,9 @@ __global__ void __launch_bounds__(256)
     if (idx >= m) continue;
     double rv, lv;
     if (bad[j]) {
-      eval_point_exact<R, L>(xp[j], tx, tw, f, n, &rv, &lv);
+      const PointRL e = eval_point_exact<R, L>(xp[j], tx, tw, f, n);
+      rv = e.r;
+      lv = e.l;
     } else {
       double a = A[j];
       if constexpr (L && U > 0)

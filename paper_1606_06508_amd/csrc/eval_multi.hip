@@ -136,8 +136,10 @@ __global__ void __launch_bounds__(256)
     const int64_t col = c0 + c;
     double rv, lv;
     if (!(fabs(D[cd]) <= 0x1.fffffffffffffp+1023)) {
-      eval_point_exact<true, L>(xp, tx, tw + (SH ? 0 : col * n_pad), tf + col * n_pad, n, &rv,
-                                &lv);
+      const PointRL e =
+          eval_point_exact<true, L>(xp, tx, tw + (SH ? 0 : col * n_pad), tf + col * n_pad, n);
+      rv = e.r;
+      lv = e.l;
     } else {
       rv = N[c] / D[cd];
       lv = A[cd] / fabs(D[cd]);

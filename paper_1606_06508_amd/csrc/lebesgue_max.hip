@@ -142,8 +142,7 @@ __global__ void __launch_bounds__(256)
         const int i = j * 64 + lane;
         double v;
         if (bad[j]) {
-          double rv;
-          eval_point_exact<false, true>(xp[j], tx, tw, nullptr, n, &rv, &v);
+          v = eval_point_exact<false, true>(xp[j], tx, tw, nullptr, n).l;
         } else {
           v = A[j] / fabs(D[j]);
         }

@@ -82,6 +82,12 @@ __device__ __forceinline__ int64_t find_node(double t, const double* __restrict_
   return -1;
 }
 
+// r and Lambda of one point, as eval_point_exact returns them (in registers:
+// the out-of-line call then needs no private memory).
+struct PointRL {
+  double r, l;
+};
+
 // Exact per-pair evaluation of one point (flagged lanes only).  A NaN or
 // infinite point gives NaN (every a_k is NaN or 0: r = Lambda = NaN); an
 // exact hit is looked up by binary search (r = f_j, Lambda = 1); anything
@@ -89,21 +95,12 @@ __device__ __forceinline__ int64_t find_node(double t, const double* __restrict_
 // per pair in a loop without early exits, so its loads pipeline (a flagged
 // lane holds its whole wave).
 template <bool R, bool L>
-__device__ __noinline__ void eval_point_exact(double t, const double* __restrict__ tx,
-                                              const double* __restrict__ tw,
-                                              const double* __restrict__ f, int64_t n,
-                                              double* r_out, double* l_out) {
-  if (!__builtin_isfinite(t)) {
-    *r_out = __builtin_nan("");
-    *l_out = __builtin_nan("");
-    return;
-  }
+__device__ __noinline__ PointRL eval_point_exact(double t, const double* __restrict__ tx,
+                                                 const double* __restrict__ tw,
+                                                 const double* __restrict__ f, int64_t n) {
+  if (!__builtin_isfinite(t)) return {__builtin_nan(""), __builtin_nan("")};
   const int64_t j = find_node(t, tx, n);
-  if (j >= 0) {
-    *r_out = R ? f[j] : 0.0;
-    *l_out = 1.0;
-    return;
-  }
+  if (j >= 0) return {R ? f[j] : 0.0, 1.0};
   double N = 0.0, D = 0.0, A = 0.0;
 #pragma unroll 4
   for (int64_t k = 0; k < n; ++k) {
@@ -113,8 +110,7 @@ __device__ __noinline__ void eval_point_exact(double t, const double* __restrict
     D = D + a;
     if (L) A = A + fabs(a);
   }
-  *r_out = N / D;
-  *l_out = A / fabs(D);
+  return {N / D, A / fabs(D)};
 }
 
 // Fused sums of one wave over the node records [k_begin, k_end) (wave-
@@ -167,11 +163,13 @@ __device__ __forceinline__ void accumulate_f64(const double (&xp)[P], const doub
   for (int j = 0; j < P; ++j) bad[j] |= !(fabs(D[j]) <= 0x1.fffffffffffffp+1023);
 }
 
-// Number of nodes tx[0, n) below v (v finite; tx strictly increasing).
+// Number of nodes tx[0, n) below v (v finite; tx strictly increasing;
+// n <= FH_MAX_NODES, so 32-bit indices: half the instructions of 64-bit
+// ones on the vector unit).
 __device__ __forceinline__ int64_t nodes_below(double v, const double* __restrict__ tx, int64_t n) {
-  int64_t lo = 0, hi = n;
+  int32_t lo = 0, hi = (int32_t)n;
   while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
+    const int32_t mid = (int32_t)((uint32_t)(lo + hi) >> 1);
     if (tx[mid] < v)
       lo = mid + 1;
     else
@@ -282,7 +280,10 @@ __device__ __forceinline__ void accumulate_f64_blocks(const double (&xp)[P],
 // The Lebesgue sum A of accumulate_f64_blocks with the term of the block
 // at px/pw (U node records) replaced: A holds |E - O| for that block, which
 // is right only if the block lies on one side of the point v; it gets
-// sum_k |w_k t_k| instead, with E and O recomputed by the same operations.
+// sum_k |w_k t_k| instead, with E and O recomputed by the loop's operations
+// (so the term removed is the term added).  (One refined reciprocal per
+// pair instead of the group inversion needs fewer registers but more issue
+// slots, and measured slower.)
 template <int G, int U>
 __device__ __forceinline__ double lebesgue_block_replace(double v, const double* __restrict__ px,
                                                          const double* __restrict__ pw,
