@@ -305,6 +305,11 @@ def run_batched_form(dev, reps, with_cpu):
                         worst[k] = worst.get(k, 0) + v
             out[prec]["max_error_12_instances"] = worst
         b.close()
+        # the same batch with the Lebesgue function as well
+        b = fh.Batch(n, d, m, nodes, vals, x, precision=prec, lebesgue=True)
+        ms = _time_ms(b, reps)
+        out[prec]["with_lebesgue"] = {"Gpair_s": pairs / (ms * 1e-3) / 1e9, "ms_per_launch": ms}
+        b.close()
     ws = fh.Workspace(dev, fh.workspace_size(fh.FH_OP_EVAL, int(n.max()), int(m.max()), 0))
     no, po = c["node_off"], c["pt_off"]
 

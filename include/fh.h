@@ -290,7 +290,9 @@ fh_status fh_batch_status(fh_batch* b, void* stream, uint32_t* bits_out);
  *                  variant runs plain sums when caller weights do not
  *                  alternate strictly in sign (w_k w_{k+1} < 0 for every k;
  *                  Floater-Hormann weights always do); r does not depend on
- *                  whether Lambda is requested;
+ *                  whether Lambda is requested.  Batched split variants
+ *                  (weights always the library's) take tiles of 32;
+ *                  batched binary64 variants plain sums;
  *   fh_tune_set    records variant `id` for the shape bucket of (n, m)
  *                  (id = -1 removes the entry);
  *   fh_tune_force  pins variant `id` for every shape (-1 releases it);

@@ -89,7 +89,7 @@ __global__ void __launch_bounds__(kStage)
     } else {
       double a = A[j];
       if constexpr (B && L)
-        if (blocks) a = split_tile_fix<G>(xp[j], xh[j], xl[j], tx, n, s4, mask, a);
+        if (blocks) a = split_tile_fix<G>(xp[j], xh[j], xl[j], tx, n, s4, n_pad, mask, a);
       rv = ldexp(N[j] / D[j], shift);
       lv = a / fabs(D[j]);
     }

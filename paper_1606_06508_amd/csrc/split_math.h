@@ -175,18 +175,20 @@ __device__ __forceinline__ void split_block_sums(float4 (&stage)[2][kStage],
 // tile (kTile records) that holds nodes on both sides of the point xv (found
 // by binary search in the binary64 nodes tx[0, n)): its |E - O|, recomputed
 // from the split records s4 with the loop's operations, is replaced by
-// sum_k |w_k t_k|.  xv finite and not a node.
+// sum_k |w_k t_k|.  xv finite and not a node; n_pad (a multiple of 4) ends
+// the records, so a table's last tile may be partial, as in the loop.
 template <int G>
 __device__ __forceinline__ double split_tile_fix(double xv, float xh, float xl,
                                                  const double* __restrict__ tx, int64_t n,
-                                                 const float4* __restrict__ s4, uint32_t mask,
-                                                 double A) {
+                                                 const float4* __restrict__ s4, int64_t n_pad,
+                                                 uint32_t mask, double A) {
   const int64_t j = nodes_below(xv, tx, n);
   if (j == 0 || j >= n || j % kTile == 0) return A;
   const int64_t b = j - j % kTile;
+  const int len = (int)(n_pad - b < kTile ? n_pad - b : kTile);
   float E = 0.0f, O = 0.0f, exact = 0.0f;
 #pragma unroll 1
-  for (int i = 0; i < kTile; i += 4) {
+  for (int i = 0; i < len; i += 4) {
     float4 rc[4];
     float t[4];
 #pragma unroll

@@ -117,7 +117,9 @@ fh_status fh_variant_shape(int32_t prec, int32_t id, int32_t* points_per_lane, i
 int32_t fh_variant_lebesgue_block(int32_t prec, int32_t id) {
   if (!valid_family(prec) || id < 0 || id >= variant_count(prec)) return -1;
   if (prec == FH_FP64) return f64_variant_block(id);
-  return prec == FH_FP32_SPLIT ? split_variant_block(id) : 0;
+  if (prec == FH_FP32_SPLIT) return split_variant_block(id);
+  // batches: split by tiles (library weights), binary64 plain
+  return prec == FH_TUNE_BATCHED_FP64 ? 0 : 32;
 }
 
 fh_status fh_tune_force(int32_t prec, int32_t id) {

@@ -153,8 +153,8 @@ def test_variant_tables_and_tuner_api():
 def test_lebesgue_block_variants():
     """Binary64 variants 15..18 take the Lebesgue sum by blocks of 16 nodes,
     split variants 8..11 by tiles of 32 (the block counterparts of plain
-    shapes); every other variant, and every batched variant, uses plain
-    sums."""
+    shapes); every other single variant uses plain sums.  Batched split
+    variants take tiles of 32, batched binary64 ones plain sums."""
     blocks = {vid: fh.variant_lebesgue_block("fp64", vid) for vid, *_ in fh.variants("fp64")}
     assert {vid for vid, u in blocks.items() if u} == {15, 16, 17, 18}
     assert set(blocks.values()) == {0, 16}
@@ -166,9 +166,9 @@ def test_lebesgue_block_variants():
     sshapes = {vid: (p, g, s) for vid, p, g, s in fh.variants("split")}
     for vid in (8, 9, 10, 11):
         assert sshapes[vid] in [sshapes[v] for v, u in sb.items() if u == 0]
-    for fam in (2, 3):
+    for fam, u in ((2, 0), (3, 32)):
         for vid, *_ in fh.variants(fam):
-            assert fh.variant_lebesgue_block(fam, vid) == 0
+            assert fh.variant_lebesgue_block(fam, vid) == u
     lib = fh.load()
     assert lib.fh_variant_lebesgue_block(0, 99) == -1
     assert lib.fh_variant_lebesgue_block(7, 0) == -1
