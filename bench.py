@@ -6,15 +6,17 @@ Workload of the headline line ("sines"): n = 1001 equispaced nodes on
 [-1,1], f = sum of 8 seeded sines, 10^6 uniform points, blending degree d
 swept 0..8.  One step = the weight pass and node-table packing of all nine
 degrees (fh_prepare_many, one launch, each degree into its own workspace)
-and, for every d, the fused r + Lebesgue evaluation (fh_eval_prepared) of
-all 10^6 points into that degree's own output arrays.  value = 9 * n * m
-pairs per step / step time.  Inputs are resident in HBM before timing
+and the fused r + Lebesgue evaluation of all 10^6 points for every d, each
+degree into its own output arrays, in one launch (fh_eval_prepared_many:
+the bits of one fh_eval_prepared call per degree).  value = 9 * n * m pairs
+per step / step time.  Inputs are resident in HBM before timing
 starts.
 
 Also reported in the same JSON line:
-  roofline      the evaluation kernel (the dominant kernel), timed live with
-                HIP events on its launch stream, against the FP64 vector peak
-                (78.6 TFLOP/s) with 7 algorithmic flops per pair;
+  roofline      the evaluation kernel (the dominant kernel; one launch covers
+                the nine degrees), timed live with HIP events on its launch
+                stream, against the FP64 vector peak (78.6 TFLOP/s) with 7
+                algorithmic flops per pair;
   cpu_baseline  the FP64 oracle on the host cores, on a bounded sample;
   max_error     parity of the timed outputs against the oracle on the sample;
   forms         the other forms of the path on their own workloads: FP64 vs
@@ -81,11 +83,13 @@ def measured_traffic(n, m):
 def run_sines(dev, steps, warmup):
     """The headline step: the node tables of all nine degrees (weights and
     packing, fh_prepare_many: one launch) and the fused r + Lambda evaluation
-    of all points for each degree (fh_eval_prepared), each degree into its
-    own workspace and output arrays, on one stream.  (Packing each degree
-    with fh_prepare just before its evaluation costs a launch and two
-    dependent-launch gaps per degree, ~8 us; packing the next degree on a
-    second stream, overlapped with the current evaluation, was measured
+    of all points for every degree (fh_eval_prepared_many: one launch), each
+    degree into its own workspace and output arrays, on one stream.  (One
+    fh_eval_prepared launch per degree gives the same bits and took 5 %
+    longer: each launch drains its last blocks before the next starts.
+    Packing each degree with fh_prepare just before its evaluation costs a
+    launch and two dependent-launch gaps per degree; packing the next degree
+    on a second stream, overlapped with the current evaluation, was measured
     slower: the cross-stream event waits cost more than they hide.)"""
     c = inputs.sines_workload()
     n, m, degrees = c["nodes"].size, c["points"].size, c["degrees"]
@@ -97,6 +101,8 @@ def run_sines(dev, steps, warmup):
     K = len(degrees)
     d_arr = (ctypes.c_int32 * K)(*degrees)
     ws_arr = (ctypes.c_void_p * K)(*[w.buf.data_ptr() for w in wss])
+    r_arr = (ctypes.c_void_p * K)(*[r[i].data_ptr() for i in range(K)])
+    l_arr = (ctypes.c_void_p * K)(*[lam[i].data_ptr() for i in range(K)])
     lib = fh.load()
     stream = torch.cuda.current_stream(dev)
     sptr = fh._stream(dev)
@@ -104,16 +110,14 @@ def run_sines(dev, steps, warmup):
 
     def step(evs=None):
         st = lib.fh_prepare_many(P(nodes), P(vals), n, d_arr, K, fh.FH_FP64, ws_arr, ws_bytes, sptr)
-        for i, d in enumerate(degrees):
-            buf = wss[i].buf
-            if evs is not None:
-                evs.append(torch.cuda.Event(enable_timing=True))
-                evs[-1].record(stream)
-            st |= lib.fh_eval_prepared(P(buf), buf.numel(), n, fh.FH_FP64, P(x), m, P(r[i]),
-                                       P(lam[i]), sptr)
-            if evs is not None:
-                evs.append(torch.cuda.Event(enable_timing=True))
-                evs[-1].record(stream)
+        if evs is not None:
+            evs.append(torch.cuda.Event(enable_timing=True))
+            evs[-1].record(stream)
+        st |= lib.fh_eval_prepared_many(ws_arr, ws_bytes, K, n, fh.FH_FP64, P(x), m, r_arr, l_arr,
+                                        sptr)
+        if evs is not None:
+            evs.append(torch.cuda.Event(enable_timing=True))
+            evs[-1].record(stream)
         if st:
             raise fh.FhError(st, "bench step")
 
@@ -130,11 +134,10 @@ def run_sines(dev, steps, warmup):
     torch.cuda.synchronize()
     total_ms = t0.elapsed_time(t1)
     kern_ms = [evs[i].elapsed_time(evs[i + 1]) for i in range(0, len(evs), 2)]
-    per_d = {d: float(np.mean(kern_ms[i::len(degrees)])) for i, d in enumerate(degrees)}
     # outputs of the last degree (d = 8) for the parity sample
     return {
         "n": n, "m": m, "degrees": degrees, "total_ms": total_ms, "kernel_ms": kern_ms,
-        "per_d_ms": per_d, "r_last": r[-1], "lam_last": lam[-1], "case": c,
+        "r_last": r[-1], "lam_last": lam[-1], "case": c,
     }
 
 
@@ -603,8 +606,8 @@ def main():
     pairs_step = len(res["degrees"]) * n * m
     ms_step = res["total_ms"] / args.steps
     value = pairs_step / (ms_step * 1e-3) / 1e9
-    k_ms = float(np.mean(res["kernel_ms"]))
-    achieved = FLOPS_PER_PAIR_RL * n * m / (k_ms * 1e-3) / 1e12
+    k_ms = float(np.mean(res["kernel_ms"]))  # one launch: all nine degrees
+    achieved = FLOPS_PER_PAIR_RL * pairs_step / (k_ms * 1e-3) / 1e12
     line = {
         "metric": "node-point pairs/sec (Gpair/s) FP64 vs FP32-split vs batched at stated max error",
         "value": value, "unit": "Gpair/s", "n_gpus": 1, "steps": args.steps,
@@ -616,10 +619,10 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": measured_traffic(n, m),
-                     "kernel": "k_eval_f64 (fused r + Lebesgue, FP64)",
+                     "kernel": "k_eval_f64_many (fused r + Lebesgue, FP64, nine degrees "
+                               "per launch)",
                      "kernel_ms_avg": k_ms,
-                     "kernel_Gpair_s": n * m / (k_ms * 1e-3) / 1e9,
-                     "per_d_kernel_ms": res["per_d_ms"]},
+                     "kernel_Gpair_s": pairs_step / (k_ms * 1e-3) / 1e9},
     }
     print(f"[bench] sines done: {value:.1f} Gpair/s, kernel {k_ms:.3f} ms", file=sys.stderr,
           flush=True)

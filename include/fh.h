@@ -159,6 +159,26 @@ fh_status fh_prepare_many(const double* nodes, const double* values, int64_t n,
                           const int32_t* d_host, int32_t K, int32_t prec, void* const* ws_host,
                           size_t ws_bytes, void* stream);
 
+/* fh_eval_prepared for K prepared tables with the same node count n on the
+ * same points, in one launch (for instance the degrees of a sweep prepared
+ * by fh_prepare_many): table c writes r_host[c][0..m) and
+ * lambda_host[c][0..m), the same bits fh_eval_prepared(ws_host[c], ...)
+ * writes.  One launch instead of K saves, per table, the drain of the
+ * launch's last blocks and the gap before the next launch.
+ *   ws_host      host array of K device workspaces prepared in binary64
+ *                with n nodes (fh_prepare or fh_prepare_many), each of at
+ *                least fh_workspace_size(FH_OP_EVAL, n, m, 0, prec) <=
+ *                ws_bytes bytes;  1 <= K <= 16
+ *   r_host       host array of K device output pointers (m doubles each),
+ *                or NULL for no r; lambda_host likewise for Lambda; not
+ *                both NULL, and no NULL entry in an array that is given
+ *   prec         FH_FP64 (FH_FP32_SPLIT: FH_E_UNSUPPORTED)
+ * Outputs of different tables must not overlap.  Errors as in
+ * fh_eval_prepared; FH_E_ARG also for K out of range. */
+fh_status fh_eval_prepared_many(void* const* ws_host, size_t ws_bytes, int32_t K, int64_t n,
+                                int32_t prec, const double* x, int64_t m, double* const* r_host,
+                                double* const* lambda_host, void* stream);
+
 /* Lambda(x_p) only (the Lebesgue function of the interpolation scheme,
  * sum_k |b_k(x)| with cardinal functions b_k = a_k / sum_j a_j).  Arguments
  * as in fh_eval; no values are needed. */

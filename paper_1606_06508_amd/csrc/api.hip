@@ -150,6 +150,49 @@ fh_status fh_prepare_many(const double* nodes, const double* values, int64_t n,
   return FH_OK;
 }
 
+fh_status fh_eval_prepared_many(void* const* ws_host, size_t ws_bytes, int32_t K, int64_t n,
+                                int32_t prec, const double* x, int64_t m, double* const* r_host,
+                                double* const* lambda_host, void* stream) {
+  if (n < 1 || n > FH_MAX_NODES || m < 0 || (m > 0 && x == nullptr) || ws_host == nullptr)
+    return FH_E_ARG;
+  if (K < 1 || K > kEvalMany) return FH_E_ARG;
+  if (r_host == nullptr && lambda_host == nullptr) return FH_E_ARG;
+  if (prec == FH_FP32_SPLIT) return FH_E_UNSUPPORTED;
+  if (prec != FH_FP64) return FH_E_ARG;
+  EvalMany a{};
+  int64_t n_pad = 0;
+  for (int32_t c = 0; c < K; ++c) {
+    fh_status st = check_ws(ws_host[c], ws_bytes, fh_workspace_size(FH_OP_EVAL, n, m, 0, prec));
+    if (st != FH_OK) return st;
+    if ((r_host && r_host[c] == nullptr) || (lambda_host && lambda_host[c] == nullptr))
+      return FH_E_ARG;
+    NodeTable t;
+    layout_tables(ws_host[c], n, &t);
+    n_pad = t.n_pad;
+    a.x[c] = t.x;
+    a.w[c] = t.w;
+    a.wf[c] = t.wf;
+    a.f[c] = t.f;
+    a.alt[c] = static_cast<uint32_t*>(ws_host[c]) + 3;
+    a.r[c] = r_host ? r_host[c] : nullptr;
+    a.lam[c] = lambda_host ? lambda_host[c] : nullptr;
+  }
+  if (m == 0) return FH_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const EvalConfig cfg = choose_eval_config(prec, n, 0, m, r_host != nullptr, lambda_host != nullptr);
+  if (launch_eval_f64_many(x, m, n, n_pad, a, K, r_host != nullptr, lambda_host != nullptr, cfg,
+                           s) != hipSuccess)
+    return FH_E_HIP;
+  if (sync_check_enabled()) {
+    for (int32_t c = 0; c < K; ++c) {
+      uint32_t bits = 0;
+      const fh_status st = fh_device_status(ws_host[c], s, &bits);
+      if (st != FH_OK) return st;
+    }
+  }
+  return FH_OK;
+}
+
 fh_status fh_eval_prepared(void* ws, size_t ws_bytes, int64_t n, int32_t prec, const double* x,
                            int64_t m, double* r_out, double* lambda_out, void* stream) {
   if (n < 1 || n > FH_MAX_NODES || m < 0 || (m > 0 && x == nullptr)) return FH_E_ARG;

@@ -43,11 +43,13 @@ namespace fhk {
 // when the table's weights alternate in sign, which *alt says (written by
 // the packing); D, hence r, is then the same with and without Lambda.
 template <int P, int G, int S, bool R, bool L, int U>
-__global__ void __launch_bounds__(256)
-    k_eval_f64(const double* __restrict__ x, int64_t m, const double* __restrict__ tx,
-               const double* __restrict__ tw, const double* __restrict__ twf, int64_t n_pad,
-               const double* __restrict__ f, int64_t n, const uint32_t* __restrict__ alt,
-               double* __restrict__ r, double* __restrict__ lam) {
+__device__ __forceinline__ void eval_f64_points(const double* __restrict__ x, int64_t m,
+                                                const double* __restrict__ tx,
+                                                const double* __restrict__ tw,
+                                                const double* __restrict__ twf, int64_t n_pad,
+                                                const double* __restrict__ f, int64_t n,
+                                                const uint32_t* __restrict__ alt,
+                                                double* __restrict__ r, double* __restrict__ lam) {
   constexpr int PG = 4 / S;  // point groups per block
   const int lane = threadIdx.x & 63;
   // wave index, made provably wave-uniform so node loads stay scalar
@@ -125,6 +127,41 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+template <int P, int G, int S, bool R, bool L, int U>
+__global__ void __launch_bounds__(256)
+    k_eval_f64(const double* __restrict__ x, int64_t m, const double* __restrict__ tx,
+               const double* __restrict__ tw, const double* __restrict__ twf, int64_t n_pad,
+               const double* __restrict__ f, int64_t n, const uint32_t* __restrict__ alt,
+               double* __restrict__ r, double* __restrict__ lam) {
+  eval_f64_points<P, G, S, R, L, U>(x, m, tx, tw, twf, n_pad, f, n, alt, r, lam);
+}
+
+// Several tables on the same points: table blockIdx.y, the points of
+// blockIdx.x as in k_eval_f64.  One launch instead of one per table saves
+// the drain of each launch's last blocks and the gap before the next.
+template <int P, int G, int S, bool R, bool L, int U>
+__global__ void __launch_bounds__(256)
+    k_eval_f64_many(const double* __restrict__ x, int64_t m, int64_t n_pad, int64_t n,
+                    EvalMany a) {
+  const int i = blockIdx.y;
+  eval_f64_points<P, G, S, R, L, U>(x, m, a.x[i], a.w[i], a.wf[i], n_pad, a.f[i], n, a.alt[i],
+                                    a.r[i], a.lam[i]);
+}
+
+template <int P, int G, int S, int U>
+static hipError_t launch_many_v(const double* x, int64_t m, int64_t n, int64_t n_pad,
+                                const EvalMany& a, int32_t K, bool r, bool lam, hipStream_t s) {
+  const int64_t per = 64LL * P * (4 / S);  // points per block
+  const dim3 grid((unsigned)((m + per - 1) / per), (unsigned)K), block(256);
+  if (r && lam)
+    k_eval_f64_many<P, G, S, true, true, U><<<grid, block, 0, s>>>(x, m, n_pad, n, a);
+  else if (r)
+    k_eval_f64_many<P, G, S, true, false, U><<<grid, block, 0, s>>>(x, m, n_pad, n, a);
+  else
+    k_eval_f64_many<P, G, S, false, true, U><<<grid, block, 0, s>>>(x, m, n_pad, n, a);
+  return hipGetLastError();
+}
+
 template <int P, int G, int S, int U>
 static hipError_t launch_v(const double* x, int64_t m, const NodeTable& t, int64_t n,
                            const uint32_t* alt, double* r, double* lam, hipStream_t s) {
@@ -187,6 +224,19 @@ hipError_t launch_eval_f64(const double* x, int64_t m, const NodeTable& t, int64
   switch (cfg.variant) {
 #define FH_CASE(vid, vp, vg, vs, vu) \
   case vid: return launch_v<vp, vg, vs, vu>(x, m, t, n, alt, r, lam, s);
+    FH_F64_VARIANTS(FH_CASE)
+#undef FH_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_eval_f64_many(const double* x, int64_t m, int64_t n, int64_t n_pad,
+                                const EvalMany& a, int32_t K, bool r, bool lam,
+                                const EvalConfig& cfg, hipStream_t s) {
+  if (m == 0 || K == 0) return hipSuccess;
+  switch (cfg.variant) {
+#define FH_CASE(vid, vp, vg, vs, vu) \
+  case vid: return launch_many_v<vp, vg, vs, vu>(x, m, n, n_pad, a, K, r, lam, s);
     FH_F64_VARIANTS(FH_CASE)
 #undef FH_CASE
     default: return hipErrorInvalidValue;

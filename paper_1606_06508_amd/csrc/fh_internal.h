@@ -124,6 +124,22 @@ hipError_t launch_pack_many(const double* nodes, const double* values, int64_t n
 hipError_t launch_pack(const double* nodes, const double* values, const double* w_in, int64_t n,
                        int32_t d, const NodeTable& t, bool split, uint32_t* status,
                        hipStream_t s);
+// Up to kEvalMany prepared binary64 tables with the same node count,
+// evaluated on the same points in one launch (grid.y = table).
+constexpr int kEvalMany = 16;
+struct EvalMany {
+  const double* x[kEvalMany];
+  const double* w[kEvalMany];
+  const double* wf[kEvalMany];
+  const double* f[kEvalMany];
+  const uint32_t* alt[kEvalMany];
+  double* r[kEvalMany];
+  double* lam[kEvalMany];
+};
+// r / lam: whether every table's r / Lambda is written.
+hipError_t launch_eval_f64_many(const double* x, int64_t m, int64_t n, int64_t n_pad,
+                                const EvalMany& a, int32_t K, bool r, bool lam,
+                                const EvalConfig& cfg, hipStream_t s);
 // alt: status word 3 of the workspace (1 if the table's weights alternate
 // in sign, written by launch_pack), read by the Lebesgue-block variants.
 hipError_t launch_eval_f64(const double* x, int64_t m, const NodeTable& t, int64_t n,

@@ -58,6 +58,8 @@ def load():
             "fh_prepare_many": ([vp, vp, i64, ctypes.POINTER(i32), i32, i32,
                                  ctypes.POINTER(vp), sz, vp], ctypes.c_int),
             "fh_eval_prepared": ([vp, sz, i64, i32, vp, i64, vp, vp, vp], ctypes.c_int),
+            "fh_eval_prepared_many": ([ctypes.POINTER(vp), sz, i32, i64, i32, vp, i64,
+                                       ctypes.POINTER(vp), ctypes.POINTER(vp), vp], ctypes.c_int),
             "fh_eval_backward": ([vp, vp, i64, i32, vp, i64, vp, vp, vp, vp, i32, vp, sz, vp],
                                  ctypes.c_int),
             "fh_eval_deriv": ([vp, vp, i64, i32, vp, i64, vp, vp, vp, i32, vp, sz, vp],
@@ -360,6 +362,45 @@ def prepare_many(nodes, values, degrees, *, m_hint=0):
     _check(lib.fh_prepare_many(_ptr(xn), _ptr(preps[0].values), xn.numel(), ds, K, FH_FP64, wss,
                                size, _stream(xn.device)), "fh_prepare_many")
     return preps
+
+
+def eval_many(preps, x, *, want_r=True, lebesgue=False, out=None, lambda_out=None):
+    """Evaluate several prepared binary64 interpolants with the same node
+    count on the same points in one launch (fh_eval_prepared_many): row c of
+    the (K, m) results has the bits of preps[c](x, ...)."""
+    lib = load()
+    preps = list(preps)
+    K = len(preps)
+    if K == 0:
+        raise ValueError("no prepared interpolants")
+    n = preps[0].n
+    if any(p.n != n or p.prec != FH_FP64 for p in preps):
+        raise ValueError("eval_many takes binary64 tables with one node count")
+    if want_r and any(p.values is None for p in preps):
+        raise ValueError("a table prepared without values has no r")
+    t = _f64(x, "x")
+    m = t.numel()
+
+    def rows(o, name):
+        if o is None:
+            return torch.empty((K, m), dtype=torch.float64, device=t.device)
+        o = _f64(o, name)
+        if o.shape != (K, m):
+            raise ValueError(f"{name} must have shape (K, m)")
+        return o
+
+    r = rows(out, "out") if want_r else None
+    lam = rows(lambda_out, "lambda_out") if lebesgue else None
+    wss = (ctypes.c_void_p * K)(*[p.ws.buf.data_ptr() for p in preps])
+    rp = None if r is None else (ctypes.c_void_p * K)(*[r[c].data_ptr() for c in range(K)])
+    lp = None if lam is None else (ctypes.c_void_p * K)(*[lam[c].data_ptr() for c in range(K)])
+    # every workspace holds at least the smallest one's bytes
+    _check(lib.fh_eval_prepared_many(wss, min(p.ws.buf.numel() for p in preps), K, n, FH_FP64,
+                                     _ptr(t), m, rp, lp, _stream(t.device)),
+           "fh_eval_prepared_many")
+    if want_r and lebesgue:
+        return r, lam
+    return r if want_r else lam
 
 
 def _family(family):

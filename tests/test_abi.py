@@ -271,3 +271,31 @@ def test_prepare_many_host_validation():
     assert call(wss=(ctypes.c_void_p * 3)(0x100000, 0x200008, 0x300000)) == fh.FH_E_WORKSPACE
     assert call(wss=(ctypes.c_void_p * 3)(0x100000, 0x200000, 0x100000)) == fh.FH_E_ARG
     assert lib.fh_prepare_many(P, P, 10, None, 3, 0, ws, 1 << 30, None) == fh.FH_E_ARG
+
+
+def test_eval_prepared_many_host_validation():
+    """Host-checkable errors of fh_eval_prepared_many return before any
+    launch (fake device addresses: none is dereferenced)."""
+    lib = fh.load()
+    VP = ctypes.c_void_p
+    ws = (VP * 3)(0x100000, 0x200000, 0x300000)
+    outs = (VP * 3)(0x400000, 0x500000, 0x600000)
+
+    def call(K=3, n=10, prec=0, wss=ws, ws_bytes=1 << 30, x=P, m=100, r=outs, lam=outs):
+        return lib.fh_eval_prepared_many(wss, ws_bytes, K, n, prec, x, m, r, lam, None)
+
+    assert call(K=0) == fh.FH_E_ARG
+    assert call(K=17, wss=(VP * 17)(*[0x100000 * (i + 1) for i in range(17)]),
+                r=None, lam=(VP * 17)(*[0x100000 * (i + 40) for i in range(17)])) == fh.FH_E_ARG
+    assert call(n=0) == fh.FH_E_ARG and call(n=fh.FH_MAX_NODES + 1) == fh.FH_E_ARG
+    assert call(m=-1) == fh.FH_E_ARG and call(x=None) == fh.FH_E_ARG
+    assert call(r=None, lam=None) == fh.FH_E_ARG
+    assert call(wss=None) == fh.FH_E_ARG
+    assert call(prec=1) == fh.FH_E_UNSUPPORTED and call(prec=3) == fh.FH_E_ARG
+    assert call(ws_bytes=300) == fh.FH_E_WORKSPACE
+    assert call(wss=(VP * 3)(0x100000, None, 0x300000)) == fh.FH_E_WORKSPACE
+    assert call(wss=(VP * 3)(0x100000, 0x200008, 0x300000)) == fh.FH_E_WORKSPACE
+    assert call(r=(VP * 3)(0x400000, None, 0x600000)) == fh.FH_E_ARG
+    assert call(lam=(VP * 3)(0x400000, 0x500000, None)) == fh.FH_E_ARG
+    # m = 0: validated, nothing launched
+    assert call(m=0, x=None) == fh.FH_OK

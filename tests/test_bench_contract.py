@@ -29,8 +29,9 @@ def test_committed_traffic_record_is_current():
     assert rec["src_sha256_16"] == bench._src_hash(bench.EVAL_SRC)
     assert rec["variant"] == fh.tune_get("fp64", 1001, 10 ** 6)
     assert bench.measured_traffic(1001, 10 ** 6) == pytest.approx(rec["hbm_bytes_per_launch"])
-    # algorithmic bytes: 8 B in, 16 B out per point; the counters may add a little
-    assert 24e6 <= rec["hbm_bytes_per_launch"] <= 1.1 * 24e6
+    # algorithmic bytes per launch (nine degrees): per degree 8 B in, 16 B
+    # out per point; the counters may add a little
+    assert 9 * 24e6 <= rec["hbm_bytes_per_launch"] <= 1.1 * 9 * 24e6
 
 
 @pytest.mark.parametrize("change", ["variant", "source"])
