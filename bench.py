@@ -75,7 +75,7 @@ def measured_traffic(n, m):
         return None
     if rec.get("src_sha256_16") != _src_hash(EVAL_SRC):
         return None
-    if rec.get("variant") != fh.tune_get("fp64", n, m):
+    if rec.get("variant") != fh.tune_get("fp64", n, m):  # m: points per launch
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -618,7 +618,7 @@ def main():
                    "n": n, "m": m, "degrees": "0..8", "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": measured_traffic(n, m),
+                     "traffic": measured_traffic(n, len(res["degrees"]) * m),
                      "kernel": "k_eval_f64_many (fused r + Lebesgue, FP64, nine degrees "
                                "per launch)",
                      "kernel_ms_avg": k_ms,

@@ -173,6 +173,7 @@ fh_status fh_prepare_many(const double* nodes, const double* values, int64_t n,
  *                or NULL for no r; lambda_host likewise for Lambda; not
  *                both NULL, and no NULL entry in an array that is given
  *   prec         FH_FP64 (FH_FP32_SPLIT: FH_E_UNSUPPORTED)
+ * The launch variant is the one tuned for n nodes and K * m points.
  * Outputs of different tables must not overlap.  Errors as in
  * fh_eval_prepared; FH_E_ARG also for K out of range. */
 fh_status fh_eval_prepared_many(void* const* ws_host, size_t ws_bytes, int32_t K, int64_t n,

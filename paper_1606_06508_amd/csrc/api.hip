@@ -179,7 +179,9 @@ fh_status fh_eval_prepared_many(void* const* ws_host, size_t ws_bytes, int32_t K
   }
   if (m == 0) return FH_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const EvalConfig cfg = choose_eval_config(prec, n, 0, m, r_host != nullptr, lambda_host != nullptr);
+  // the launch's shape: K * m points over n nodes
+  const EvalConfig cfg =
+      choose_eval_config(prec, n, 0, m * K, r_host != nullptr, lambda_host != nullptr);
   if (launch_eval_f64_many(x, m, n, n_pad, a, K, r_host != nullptr, lambda_host != nullptr, cfg,
                            s) != hipSuccess)
     return FH_E_HIP;

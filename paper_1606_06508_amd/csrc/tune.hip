@@ -54,7 +54,8 @@ struct Builtin {
   int variant;
 };
 constexpr Builtin kBuiltin[] = {
-    {FH_FP64, 6, 14, 7},       {FH_FP64, 10, 20, 17},      {FH_FP64, 12, 20, 16},
+    {FH_FP64, 6, 14, 7},       {FH_FP64, 10, 20, 17},      {FH_FP64, 10, 24, 18},
+    {FH_FP64, 12, 20, 16},
     {FH_FP64, 13, 20, 16},     {FH_FP64, 13, 24, 18},      {FH_FP32_SPLIT, 6, 14, 4},
     {FH_FP32_SPLIT, 10, 20, 9}, {FH_FP32_SPLIT, 12, 20, 9}, {FH_FP32_SPLIT, 13, 20, 9},
     {FH_FP32_SPLIT, 13, 24, 9},

@@ -27,8 +27,9 @@ def test_committed_traffic_record_is_current():
     with open(bench.TRAFFIC_FILE) as f:
         rec = json.load(f)
     assert rec["src_sha256_16"] == bench._src_hash(bench.EVAL_SRC)
-    assert rec["variant"] == fh.tune_get("fp64", 1001, 10 ** 6)
-    assert bench.measured_traffic(1001, 10 ** 6) == pytest.approx(rec["hbm_bytes_per_launch"])
+    # one launch: nine degrees of 10^6 points
+    assert rec["variant"] == fh.tune_get("fp64", 1001, 9 * 10 ** 6)
+    assert bench.measured_traffic(1001, 9 * 10 ** 6) == pytest.approx(rec["hbm_bytes_per_launch"])
     # algorithmic bytes per launch (nine degrees): per degree 8 B in, 16 B
     # out per point; the counters may add a little
     assert 9 * 24e6 <= rec["hbm_bytes_per_launch"] <= 1.1 * 9 * 24e6
@@ -45,7 +46,7 @@ def test_stale_traffic_record_gives_none(tmp_path, monkeypatch, change):
     path = tmp_path / "traffic.json"
     path.write_text(json.dumps(rec))
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(path))
-    assert bench.measured_traffic(1001, 10 ** 6) is None
+    assert bench.measured_traffic(1001, 9 * 10 ** 6) is None
 
 
 def test_host_cpu_fields():
