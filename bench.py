@@ -8,7 +8,8 @@ swept 0..8.  One step = the weight pass and node-table packing of all nine
 degrees (fh_prepare_many, one launch, each degree into its own workspace)
 and the fused r + Lebesgue evaluation of all 10^6 points for every d, each
 degree into its own output arrays, in one launch (fh_eval_prepared_many:
-the bits of one fh_eval_prepared call per degree).  value = 9 * n * m pairs
+per degree the bits of an fh_eval_prepared call with the same launch
+variant).  value = 9 * n * m pairs
 per step / step time.  Inputs are resident in HBM before timing
 starts.
 
@@ -85,8 +86,9 @@ def run_sines(dev, steps, warmup):
     packing, fh_prepare_many: one launch) and the fused r + Lambda evaluation
     of all points for every degree (fh_eval_prepared_many: one launch), each
     degree into its own workspace and output arrays, on one stream.  (One
-    fh_eval_prepared launch per degree gives the same bits and took 5 %
-    longer: each launch drains its last blocks before the next starts.
+    fh_eval_prepared launch per degree, with the same launch variant, gives
+    the same bits and took 5 % longer: each launch drains its last blocks
+    before the next starts.
     Packing each degree with fh_prepare just before its evaluation costs a
     launch and two dependent-launch gaps per degree; packing the next degree
     on a second stream, overlapped with the current evaluation, was measured

@@ -162,9 +162,11 @@ fh_status fh_prepare_many(const double* nodes, const double* values, int64_t n,
 /* fh_eval_prepared for K prepared tables with the same node count n on the
  * same points, in one launch (for instance the degrees of a sweep prepared
  * by fh_prepare_many): table c writes r_host[c][0..m) and
- * lambda_host[c][0..m), the same bits fh_eval_prepared(ws_host[c], ...)
- * writes.  One launch instead of K saves, per table, the drain of the
- * launch's last blocks and the gap before the next launch.
+ * lambda_host[c][0..m), the bits fh_eval_prepared(ws_host[c], ...) writes
+ * with the same launch variant (each call picks the variant tuned for its
+ * own point count: K * m here, m there; fh_tune_force makes them one).  One
+ * launch instead of K saves, per table, the drain of the launch's last
+ * blocks and the gap before the next launch.
  *   ws_host      host array of K device workspaces prepared in binary64
  *                with n nodes (fh_prepare or fh_prepare_many), each of at
  *                least fh_workspace_size(FH_OP_EVAL, n, m, 0, prec) <=
@@ -173,7 +175,6 @@ fh_status fh_prepare_many(const double* nodes, const double* values, int64_t n,
  *                or NULL for no r; lambda_host likewise for Lambda; not
  *                both NULL, and no NULL entry in an array that is given
  *   prec         FH_FP64 (FH_FP32_SPLIT: FH_E_UNSUPPORTED)
- * The launch variant is the one tuned for n nodes and K * m points.
  * Outputs of different tables must not overlap.  Errors as in
  * fh_eval_prepared; FH_E_ARG also for K out of range. */
 fh_status fh_eval_prepared_many(void* const* ws_host, size_t ws_bytes, int32_t K, int64_t n,

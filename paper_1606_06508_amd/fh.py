@@ -367,7 +367,9 @@ def prepare_many(nodes, values, degrees, *, m_hint=0):
 def eval_many(preps, x, *, want_r=True, lebesgue=False, out=None, lambda_out=None):
     """Evaluate several prepared binary64 interpolants with the same node
     count on the same points in one launch (fh_eval_prepared_many): row c of
-    the (K, m) results has the bits of preps[c](x, ...)."""
+    the (K, m) results has the bits of preps[c](x, ...) run with the same
+    launch variant (the launch tunes for K * m points, a single call for
+    m; tune_force makes them one)."""
     lib = load()
     preps = list(preps)
     K = len(preps)
