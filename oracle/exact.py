@@ -115,3 +115,44 @@ def central_difference(fun, t, h=Fraction(1, 10 ** 30)) -> Fraction:
 def to_float(q: Fraction) -> float:
     """Correctly rounded binary64 value of an exact rational."""
     return float(q)
+
+
+def cardinal_derivatives(nodes, d: int, t, h=Fraction(1, 10 ** 30)) -> List[Fraction]:
+    """b_k'(t) of the blend cardinals by exact central differences (also at a
+    node, where the cardinals are smooth; truncation O(h^2))."""
+    t = F(t)
+    bp = blend_cardinals(nodes, d, t + h)
+    bm = blend_cardinals(nodes, d, t - h)
+    return [(p - m) / (2 * h) for p, m in zip(bp, bm)]
+
+
+EPS = Fraction(1, 2 ** 100)
+
+
+def term_sensitivities(fun, groups, eps=EPS):
+    """First-order worst-case sensitivity of a computation to relative
+    errors in its terms, by experiment: `groups` is a list of lists of exact
+    terms, `fun(groups)` returns the result (a Fraction or a list of them).
+    Every term is perturbed alone by the relative amount eps and the changes
+    of the result are added in absolute value (per component for a list):
+    sum over terms of |fun(term * (1 + eps)) - fun()| / eps.  No formula for
+    the sensitivity is used; for eps -> 0 this is sum |d fun / d term * term|,
+    the largest first-order change when every term carries its own relative
+    error of at most one unit."""
+    base = fun(groups)
+    single = not isinstance(base, list)
+    base_l = [base] if single else base
+    tot = [Fraction(0)] * len(base_l)
+    for gi, grp in enumerate(groups):
+        for k, v in enumerate(grp):
+            if v == 0:
+                continue
+            pert = list(groups)
+            pert[gi] = list(grp)
+            pert[gi][k] = v * (1 + eps)
+            out = fun(pert)
+            out_l = [out] if single else out
+            for c, (o, b) in enumerate(zip(out_l, base_l)):
+                tot[c] += abs(o - b)
+    res = [s / eps for s in tot]
+    return res[0] if single else res

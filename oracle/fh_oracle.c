@@ -128,9 +128,14 @@ static int64_t find_hit(const double* x, int64_t n, double t) {
 }
 
 /* ------------------------------------------------------------ one point -- */
-/* r(t), Lambda(t) and the error scale S(t) = sum|a_k f_k|/|D| + |r| Lambda
- * (the quantity that bounds the rounding error of any evaluation of the
- * second form; used by the parity metric).  compensated=0 gives the plain
+/* r(t), Lambda(t) and the error scale S(t) = sum|a_k f_k|/|D| + |r| Lambda,
+ * used by the parity metric.  S is the largest first-order change of
+ * r = N / D per unit relative error when every term of N = sum a_k f_k and of
+ * D = sum a_k carries a relative error of its own (rounding of the terms and
+ * of their sums, in any evaluation): with the cardinal functions
+ * b_k = a_k / D, d r / d(N term k) = b_k f_k and d r / d(D term k) = -b_k r,
+ * so S = sum|b_k f_k| + |r| sum|b_k|.  At a hit r = f_j is exact and S = |f_j|
+ * only serves as a positive denominator.  compensated=0 gives the plain
  * ascending sum, reported only to show what compensation buys. */
 static void eval_point(const double* x, const double* f, const double* w, int64_t n,
                        double t, int compensated, double* r, double* lam, double* scale) {
@@ -204,11 +209,15 @@ int fho_eval(const double* x, const double* f, int64_t n, int32_t d, const doubl
    r' = (N'D - N D') / D^2 = (r E - F) / D.  At a hit x == x_j the node
    formula of [SW]: r'(x_j) = sum_{k != j} (w_k / w_j)(f_k - f_j)/(x_j - x_k).
    A NaN or infinite point gives NaN for both.  The scale of the rounding
-   error of r' (any evaluation of these sums) is
-     S' = ((|r| + S) sum|a_k / (x - x_k)| + sum|a_k f_k / (x - x_k)|) / |D|
-          + |r'| Lambda,
-   with S = sum|a_k f_k| / |D| + |r| Lambda the scale of r; at a hit,
-   S' = sum_{k != j} |w_k / w_j| |f_k - f_j| / |x_j - x_k|. */
+   error of r' is S', the largest first-order change of r' per unit relative
+   error when every term of each of the four sums N, D, E, F carries a
+   relative error of its own: with b_k = a_k / D, q_k = 1 / (x - x_k) and
+   e = E / D = sum b_k q_k,
+     d r' / d(N term k) = b_k f_k e,        d r' / d(D term k) = -b_k (r e + r'),
+     d r' / d(E term k) = r b_k q_k,        d r' / d(F term k) = -b_k f_k q_k,
+   so S' = |e| sum|b_k f_k| + |r e + r'| Lambda + sum|b_k q_k| (|r| + |f_k|).
+   At a hit, S' = sum_{k != j} |w_k / w_j| |f_k - f_j| / |x_j - x_k|, the sum
+   of the absolute values of the node formula's terms. */
 static void deriv_point(const double* x, const double* f, const double* w, int64_t n, double t,
                         double* r, double* dr, double* scale) {
   if (!isfinite(t)) {
@@ -249,10 +258,11 @@ static void deriv_point(const double* x, const double* f, const double* w, int64
   double rr = cs_val(&N) / dd;
   double der = (rr * cs_val(&E) - cs_val(&F)) / dd;
   double lam = cs_val(&L) / fabs(dd);
-  double sr = cs_val(&A) / fabs(dd) + fabs(rr) * lam;
+  double e = cs_val(&E) / dd;
   *r = rr;
   *dr = der;
-  *scale = ((fabs(rr) + sr) * cs_val(&LQ) + cs_val(&FQ)) / fabs(dd) + fabs(der) * lam;
+  *scale = fabs(e) * (cs_val(&A) / fabs(dd)) + fabs(rr * e + der) * lam +
+           (fabs(rr) * cs_val(&LQ) + cs_val(&FQ)) / fabs(dd);
 }
 
 /* r and r' at m points (scale may be NULL); w may be NULL (computed here). */
@@ -526,18 +536,27 @@ int fho_backward(const double* x, const double* f, int64_t n, int32_t d, const d
   return FHO_OK;
 }
 
-/* Error scales of the adjoint: for every gradient component, the sum of
-   the absolute values of its terms, each point's terms weighted by
-   (1 + Lambda(x_p)) (c_p = g_p / D_p is only known to about u (1 + Lambda),
-   D_p having condition number Lambda).  s_df[n], s_dx[m], and s_dn[n] for
-   the total node gradient: the direct terms plus the chain through the
-   weights, sum_k s_dw[k] sum_{i in J_k} |d T_{k,i} / d x_l|.  Plain sums:
-   these are tolerances, not results.  At a hit x_p == x_j: |g_p| goes to
-   s_df[j], and |g_p| sum_{k!=j} |w_k / w_j| |f_k - f_j| / |x_j - x_k| to
-   s_dx[p] and to the direct part of s_dn[j]. */
+/* Error scales of the adjoint: for every gradient component, the largest
+   first-order change per unit relative error when every term that an
+   evaluation of the adjoint forms carries a relative error of its own:
+   per point the terms of N_p = sum a_pk f_k and D_p = sum a_pk (through
+   r_p = N_p / D_p and c_p = g_p / D_p), and per node the terms of the
+   node sums over points, c_p a_pk (dL/df_k), c_p f_k t_pk and c_p r_p t_pk
+   (dL/dw_k), c_p a_pk f_k t_pk and c_p a_pk r_p t_pk (dL/dx_k at fixed
+   weights), t_pk = 1 / (x_p - x_k).  With b_k = a_pk / D_p, Lambda_p and
+   B_pk = |f_k| + |r_p| + Lambda_p |2 r_p - f_k| + sum_j |b_j f_j|:
+     s_df[k] = sum_p |g_p b_k| (1 + Lambda_p),
+     s_dw[k] = sum_p |c_p t_pk| B_pk,    s_dxd[k] = sum_p |g_p b_k t_pk| B_pk,
+     s_dx[p] = |g_p| S'(x_p) (S' the derivative's scale; dL/dx_p = g_p r'),
+   and s_dn[l] = s_dxd[l] + sum_k s_dw[k] sum_{i in J_k} |d T_{k,i} / d x_l|
+   for the total node gradient (the chain through the weights).  At a hit
+   x_p == x_j: |g_p| goes to s_df[j], |g_p| S'(x_j) to s_dx[p] and to s_dxd[j].
+   A non-finite point adds nothing (s_dx = 0).  Plain sums over points:
+   these are tolerances, not results.  s_dw and s_dxd (may be NULL) return
+   the two parts of s_dn. */
 int fho_grad_scales(const double* x, const double* f, int64_t n, int32_t d, const double* pts,
                     int64_t m, const double* g, double* s_df, double* s_dx, double* s_dn,
-                    int32_t nthreads) {
+                    double* s_dw, double* s_dxd, int32_t nthreads) {
   int st = check_problem(x, n, d);
   if (st != FHO_OK) return st;
   if (f == NULL || m < 0 || (m > 0 && (pts == NULL || g == NULL))) return FHO_E_ARG;
@@ -562,36 +581,31 @@ int fho_grad_scales(const double* x, const double* f, int64_t n, int32_t d, cons
       double t = pts[p], gp = fabs(g[p]);
       if (s_dx) s_dx[p] = 0.0;
       if (!isfinite(t)) continue;
+      double rr, der, sd;
+      deriv_point(x, f, w, n, t, &rr, &der, &sd);
+      if (s_dx) s_dx[p] = gp * sd;
       int64_t j = find_hit(x, n, t);
       if (j >= 0) {
-        double rp = 0.0;
-        for (int64_t k = 0; k < n; ++k)
-          if (k != j) rp += fabs(w[k] / w[j]) * fabs(f[k] - f[j]) / fabs(x[j] - x[k]);
         a_df[j] += gp;
-        a_dx[j] += gp * rp;
-        if (s_dx) s_dx[p] = gp * rp;
+        a_dx[j] += gp * sd;
         continue;
       }
-      double N = 0.0, D = 0.0, L = 0.0;
+      csum D = {0, 0}, L = {0, 0}, A = {0, 0};
       for (int64_t k = 0; k < n; ++k) {
         double a = w[k] / (t - x[k]);
-        N += a * f[k];
-        D += a;
-        L += fabs(a);
+        cs_add(&D, a);
+        cs_add(&L, fabs(a));
+        cs_add(&A, fabs(a * f[k]));
       }
-      double rr = fabs(N / D);
-      double cp = gp / fabs(D) * (1.0 + L / fabs(D));
-      double sx = 0.0;
+      double dd = fabs(cs_val(&D));
+      double lam = cs_val(&L) / dd, sbf = cs_val(&A) / dd, cp = gp / dd;
       for (int64_t k = 0; k < n; ++k) {
         double q = 1.0 / fabs(t - x[k]);
-        double q2 = q * q;
-        double fr = fabs(f[k]) + rr;
-        a_df[k] += fabs(w[k]) * cp * q;
-        a_dw[k] += cp * q * fr;
-        a_dx[k] += fabs(w[k]) * cp * q2 * fr;
-        sx += fabs(w[k]) * q2 * fr;
+        double bk = fabs(f[k]) + fabs(rr) + lam * fabs(2.0 * rr - f[k]) + sbf;
+        a_df[k] += fabs(w[k]) * cp * q * (1.0 + lam);
+        a_dw[k] += cp * q * bk;
+        a_dx[k] += fabs(w[k]) * cp * q * q * bk;
       }
-      if (s_dx) s_dx[p] = cp * sx;
     }
   }
 
@@ -607,6 +621,8 @@ int fho_grad_scales(const double* x, const double* f, int64_t n, int32_t d, cons
     }
     if (s_df) s_df[k] = t0;
     sw[k] = t1;
+    if (s_dw) s_dw[k] = t1;
+    if (s_dxd) s_dxd[k] = t2;
     if (s_dn) s_dn[k] = t2;
   }
   free(acc);

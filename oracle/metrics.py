@@ -51,6 +51,15 @@ GRAD_TOL = 1e-12
 SPLIT_GRAD_TOL = 2.0 ** -17
 
 
+def lambda_scale(lam):
+    """Scale of the rounding error of Lambda = L / |D|: Lambda (1 + Lambda),
+    the largest first-order change of Lambda per unit relative error when
+    every term of L = sum |a_k| and of D = sum a_k carries an error of its
+    own (d Lambda / d(L term k) = |b_k|, d Lambda / d(D term k) =
+    -Lambda b_k)."""
+    return lam * (1.0 + lam)
+
+
 def parity(r, lam, r_o, lam_o, s_o, lam_max=FP64_LAMBDA_MAX):
     """Returns a dict of max errors over the points whose oracle Lambda is at
     most lam_max (all points when lam_o is None); NaN-consistent points are
@@ -80,9 +89,10 @@ def parity(r, lam, r_o, lam_o, s_o, lam_max=FP64_LAMBDA_MAX):
         nan_o, nan_g = np.isnan(lam_o), np.isnan(lam)
         out["nan_mismatch_lam"] = int(np.count_nonzero(nan_o != nan_g))
         ok = ~nan_o & ~nan_g & keep
-        el = np.abs(lam[ok] - lam_o[ok]) / lam_o[ok]
+        dl = np.abs(lam[ok] - lam_o[ok])
+        el = dl / lam_o[ok]
         out["e_rel_lam_max"] = float(el.max()) if el.size else 0.0
-        ec = el / (1.0 + lam_o[ok])
+        ec = dl / lambda_scale(lam_o[ok])
         out["e_cond_lam_max"] = float(ec.max()) if ec.size else 0.0
     return out
 
@@ -126,34 +136,52 @@ def weight_derivative_abs(x, d):
 
 
 def grad_scales(nodes, vals, d, pts, g):
-    """Sums of the absolute values of the terms of every gradient component
-    (s_df[n], s_dx[m], s_dxd[n] for dL/dx_k at fixed weights, s_dw[n]).
-
-    Every term carries c_p = g_p / D_p, and D_p = sum_k a_pk has condition
-    number Lambda(x_p), so c_p is only known to about u (1 + Lambda(x_p)):
-    each point's terms are weighted by that factor.  Exact hits contribute
-    |g_p| to dL/df_j and |g_p| sum_k |w_k/w_j| |f_k - f_j| / |x_j - x_k| to
-    dL/dx_p and dL/dx_j."""
+    """The adjoint's error scales (s_df[n], s_dx[m], s_dxd[n] for dL/dx_k at
+    fixed weights, s_dw[n]) in numpy, by the definition of fho_grad_scales:
+    each is the largest first-order change of its gradient component per
+    unit relative error when every term an evaluation of the adjoint forms
+    carries an error of its own -- the terms of N_p and D_p (which reach the
+    gradients through r_p = N_p / D_p and c_p = g_p / D_p) and the terms of
+    the node sums over points.  With b_k = a_pk / D_p, t_pk = 1/(x_p - x_k)
+    and B_pk = |f_k| + |r_p| + Lambda_p |2 r_p - f_k| + sum_j |b_j f_j|:
+      s_df[k] = sum_p |g_p b_k| (1 + Lambda_p),
+      s_dw[k] = sum_p |g_p / D_p| |t_pk| B_pk,
+      s_dxd[k] = sum_p |g_p b_k t_pk| B_pk,
+      s_dx[p] = |g_p| S'(x_p), S' the derivative's scale (dL/dx_p = g_p r'):
+        |e| sum|b_k f_k| + |r e + r'| Lambda + sum|b_k t_k| (|r| + |f_k|),
+        e = sum_k b_k t_k.
+    Exact hits x_p == x_j contribute |g_p| to s_df[j] and |g_p| times the
+    sum of |terms| of the node formula to s_dx[p] and s_dxd[j]."""
     from . import oracle
     w = oracle.weights(nodes, d)
-    r, lam, _ = oracle.evaluate(nodes, vals, d, pts, scale=False)
     ok = np.isfinite(pts) & ~np.isin(pts, nodes)
     s_df = np.zeros(nodes.size)
     s_dw = np.zeros(nodes.size)
     s_dxd = np.zeros(nodes.size)
     s_dx = np.zeros(pts.size)
+    af_abs = np.abs(vals)
     idx = np.flatnonzero(ok)
     for lo in range(0, idx.size, 2000):
         sel = idx[lo:lo + 2000]
         T = 1.0 / (pts[sel, None] - nodes[None, :])
-        D = (w[None, :] * T).sum(1)
-        c = np.abs(g[sel] / D) * (1.0 + lam[sel])
-        rr = np.abs(r[sel])
-        s_df += np.abs(w) * (c[:, None] * np.abs(T)).sum(0)
-        s_dw += (c[:, None] * np.abs(T) * (np.abs(vals)[None, :] + rr[:, None])).sum(0)
-        T2 = T * T
-        s_dxd += np.abs(w) * (c[:, None] * T2 * (np.abs(vals)[None, :] + rr[:, None])).sum(0)
-        s_dx[sel] = c * (np.abs(w)[None, :] * T2 * (rr[:, None] + np.abs(vals)[None, :])).sum(1)
+        a = w[None, :] * T
+        af = a * vals[None, :]
+        D = a.sum(1)
+        r = af.sum(1) / D
+        lam = np.abs(a).sum(1) / np.abs(D)
+        sbf = np.abs(af).sum(1) / np.abs(D)
+        e = (a * T).sum(1) / D
+        dr = (r * (a * T).sum(1) - (af * T).sum(1)) / D
+        b = np.abs(a) / np.abs(D)[:, None]
+        s_dx[sel] = np.abs(g[sel]) * (
+            np.abs(e) * sbf + np.abs(r * e + dr) * lam
+            + (b * np.abs(T) * (np.abs(r)[:, None] + af_abs[None, :])).sum(1))
+        B = (af_abs[None, :] + np.abs(r)[:, None]
+             + lam[:, None] * np.abs(2.0 * r[:, None] - vals[None, :]) + sbf[:, None])
+        gb = np.abs(g[sel])[:, None] * b
+        s_df += (gb * (1.0 + lam)[:, None]).sum(0)
+        s_dw += (np.abs(g[sel] / D)[:, None] * np.abs(T) * B).sum(0)
+        s_dxd += (gb * np.abs(T) * B).sum(0)
     for p in np.flatnonzero(np.isin(pts, nodes)):
         j = int(np.searchsorted(nodes, pts[p]))
         others = np.arange(nodes.size) != j

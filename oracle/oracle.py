@@ -42,7 +42,7 @@ def _load():
         lib.fho_weights.argtypes = [dp, i64, i32, dp]
         lib.fho_eval.argtypes = [dp, dp, i64, i32, dp, dp, i64, dp, dp, dp, i32, i32]
         lib.fho_backward.argtypes = [dp, dp, i64, i32, dp, i64, dp, dp, dp, dp, dp, i32]
-        lib.fho_grad_scales.argtypes = [dp, dp, i64, i32, dp, i64, dp, dp, dp, dp, i32]
+        lib.fho_grad_scales.argtypes = [dp, dp, i64, i32, dp, i64, dp, dp, dp, dp, dp, dp, i32]
         lib.fho_eval_deriv.argtypes = [dp, dp, i64, i32, dp, dp, i64, dp, dp, dp, i32]
         lib.fho_lebesgue_max.argtypes = [dp, i64, i32, dp, i32, i32,
                                          ctypes.POINTER(ctypes.c_int64), i64, dp, dp, i32]
@@ -151,14 +151,18 @@ def lebesgue_max(nodes, d, samples=256, rounds=5, w=None, intervals=None, nthrea
     return lam, loc, (best, at)
 
 
-def grad_scales(nodes, values, d, pts, grad, nthreads=0):
-    """Error scales of the adjoint (fho_grad_scales): (s_df, s_dx, s_dn)."""
+def grad_scales(nodes, values, d, pts, grad, nthreads=0, parts=False):
+    """Error scales of the adjoint (fho_grad_scales): (s_df, s_dx, s_dn), and
+    with parts=True also (s_dw, s_dxd), the two parts of s_dn."""
     x, f, t, g = _f64(nodes), _f64(values), _f64(pts), _f64(grad)
     s_df, s_dn, s_dx = np.empty_like(x), np.empty_like(x), np.empty_like(t)
+    s_dw, s_dxd = np.empty_like(x), np.empty_like(x)
     st = _load().fho_grad_scales(_p(x), _p(f), x.size, int(d), _p(t), t.size, _p(g), _p(s_df),
-                                 _p(s_dx), _p(s_dn), int(nthreads))
+                                 _p(s_dx), _p(s_dn), _p(s_dw), _p(s_dxd), int(nthreads))
     if st:
         raise OracleError(st)
+    if parts:
+        return s_df, s_dx, s_dn, s_dw, s_dxd
     return s_df, s_dx, s_dn
 
 
