@@ -82,7 +82,8 @@ typedef enum {
   FH_E_RANGE = 5,       /* (device) a weight product under/overflowed          */
   FH_E_WORKSPACE = 6,   /* workspace NULL, too small or not 256-byte aligned    */
   FH_E_HIP = 7,         /* a HIP runtime call failed                            */
-  FH_E_UNSUPPORTED = 8  /* combination the library does not provide              */
+  FH_E_UNSUPPORTED = 8, /* combination the library does not provide              */
+  FH_E_TOO_LARGE = 9    /* problem exceeds the fixed scratch of fh_eval_noalloc */
 } fh_status;
 
 typedef enum { FH_FP64 = 0, FH_FP32_SPLIT = 1 } fh_precision;
@@ -129,6 +130,30 @@ fh_status fh_weights(const double* nodes, int64_t n, int32_t d, double* w_out, v
 fh_status fh_eval(const double* nodes, const double* values, int64_t n, int32_t d,
                   const double* x, int64_t m, double* r_out, double* lambda_out, const double* w,
                   int32_t prec, void* ws, size_t ws_bytes, void* stream);
+
+/* fh_eval for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Arguments, results and bits are those of fh_eval, but there is no `ws`:
+ * the node table lives in a fixed device array of FH_NOALLOC_SCRATCH_BYTES
+ * bytes inside the library, one per GPU, held until the process ends (its
+ * device address is resolved on the first call on each device).  Nothing
+ * is allocated, on the device or through any library, in any call.
+ *   n              at most FH_NOALLOC_MAX_NODES (the largest table the array
+ *                  holds); a larger n returns FH_E_TOO_LARGE, before any
+ *                  work is enqueued
+ *   other errors   as in fh_eval (FH_E_HIP if the array's address cannot be
+ *                  resolved)
+ * Every call on one GPU uses that GPU's one array, and the array keeps the
+ * last call's table: calls that overlap on one GPU (different streams or
+ * host threads without ordering) race and give undefined results; order
+ * them on one stream.  Each call clears the array's status block first, so
+ * device-side node checks report only under FH_SYNC_CHECK=1 (no workspace
+ * is exposed to read them back later). */
+#define FH_NOALLOC_SCRATCH_BYTES ((size_t)2 << 20)
+#define FH_NOALLOC_MAX_NODES 43648LL
+fh_status fh_eval_noalloc(const double* nodes, const double* values, int64_t n, int32_t d,
+                          const double* x, int64_t m, double* r_out, double* lambda_out,
+                          const double* w, int32_t prec, void* stream);
 
 /* Two-phase form of fh_eval for evaluating one interpolant on many point
  * batches.  fh_prepare runs the weight pass (unless `w` is given) and packs

@@ -64,6 +64,7 @@ const char* fh_status_string(int32_t s) {
     case FH_E_WORKSPACE: return "workspace missing, too small or misaligned";
     case FH_E_HIP: return "HIP runtime error";
     case FH_E_UNSUPPORTED: return "combination not supported by the library";
+    case FH_E_TOO_LARGE: return "problem exceeds the fixed scratch of fh_eval_noalloc";
     default: return "unknown status";
   }
 }

@@ -16,10 +16,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfh.so")
 
 FH_OK, FH_E_ARG, FH_E_DEGREE, FH_E_NODES, FH_E_NONFINITE, FH_E_RANGE = 0, 1, 2, 3, 4, 5
-FH_E_WORKSPACE, FH_E_HIP, FH_E_UNSUPPORTED = 6, 7, 8
+FH_E_WORKSPACE, FH_E_HIP, FH_E_UNSUPPORTED, FH_E_TOO_LARGE = 6, 7, 8, 9
 FH_FP64, FH_FP32_SPLIT = 0, 1
 FH_OP_WEIGHTS, FH_OP_EVAL, FH_OP_BACKWARD, FH_OP_LEBESGUE_MAX = 0, 1, 2, 3
 FH_MAX_NODES = 1 << 28  # largest node count of one interpolant
+FH_NOALLOC_MAX_NODES = 43648  # largest node count of fh_eval_noalloc
 PRECISIONS = {"fp64": FH_FP64, "split": FH_FP32_SPLIT, "fp32_split": FH_FP32_SPLIT}
 FH_TUNE_BATCHED_FP64, FH_TUNE_BATCHED_SPLIT = 2, 3
 # kernel families of the tuner: the two precisions of fh_eval and the two of
@@ -53,6 +54,7 @@ def load():
             "fh_workspace_size": ([i32, i64, i64, i32, i32], sz),
             "fh_weights": ([vp, i64, i32, vp, vp, sz, vp], ctypes.c_int),
             "fh_eval": ([vp, vp, i64, i32, vp, i64, vp, vp, vp, i32, vp, sz, vp], ctypes.c_int),
+            "fh_eval_noalloc": ([vp, vp, i64, i32, vp, i64, vp, vp, vp, i32, vp], ctypes.c_int),
             "fh_lebesgue": ([vp, i64, i32, vp, i64, vp, vp, i32, vp, sz, vp], ctypes.c_int),
             "fh_prepare": ([vp, vp, i64, i32, vp, i32, vp, sz, vp], ctypes.c_int),
             "fh_prepare_many": ([vp, vp, i64, ctypes.POINTER(i32), i32, i32,
@@ -203,6 +205,26 @@ def evaluate(nodes, values, d, x, *, lebesgue=False, weights=None, precision="fp
     _check(lib.fh_eval(_ptr(xn), _ptr(f), n, int(d), _ptr(t), m, _ptr(r), _ptr(lam), _ptr(weights),
                        prec, _ptr(buf), buf.numel(), _stream(t.device)), "fh_eval")
     return (r, lam) if lebesgue else r
+
+
+def evaluate_noalloc(nodes, values, d, x, out, *, lambda_out=None, weights=None,
+                     precision="fp64"):
+    """fh_eval_noalloc: r(x) into `out` (and Lambda(x) into `lambda_out` if
+    given) with the node table in the library's fixed device array; nothing
+    is allocated, here or in the library (n <= FH_NOALLOC_MAX_NODES)."""
+    lib = load()
+    xn, f, t = _f64(nodes, "nodes"), _f64(values, "values"), _f64(x, "x")
+    r = _f64(out, "out")
+    lam = None if lambda_out is None else _f64(lambda_out, "lambda_out")
+    if f.numel() != xn.numel() or r.numel() != t.numel() or \
+            (lam is not None and lam.numel() != t.numel()):
+        raise ValueError("values, out and lambda_out must match nodes and x in size")
+    if weights is not None and _f64(weights, "weights").numel() != xn.numel():
+        raise ValueError("weights must have as many entries as nodes")
+    _check(lib.fh_eval_noalloc(_ptr(xn), _ptr(f), xn.numel(), int(d), _ptr(t), t.numel(), _ptr(r),
+                               _ptr(lam), _ptr(weights), _prec(precision), _stream(t.device)),
+           "fh_eval_noalloc")
+    return r if lam is None else (r, lam)
 
 
 def lebesgue(nodes, d, x, *, weights=None, precision="fp64", out=None, ws=None):

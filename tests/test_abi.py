@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_status_strings():
-    for code in range(9):
+    for code in range(10):
         s = fh.status_string(code)
         assert s and s != "unknown status"
     assert fh.status_string(99) == "unknown status"
@@ -250,6 +250,36 @@ def test_node_count_limit():
     assert lib.fh_batch_create(ctypes.byref(h), 2, n_host, d_host, m_host, P, P, P, P2, None, 0,
                                None) == fh.FH_E_ARG
     assert h.value is None
+
+
+def test_noalloc_host_validation_and_limit():
+    """fh_eval_noalloc refuses bad arguments, and node counts whose table
+    does not fit its fixed device array, before any HIP call; the header's
+    limit is the largest node count whose table fits."""
+    lib = fh.load()
+    hdr = open(HEADERS[0]).read()
+    cap = int(re.search(r"#define FH_NOALLOC_SCRATCH_BYTES \(\(size_t\)2 << 20\)", hdr)
+              and 2 << 20)
+    top = int(re.search(r"#define FH_NOALLOC_MAX_NODES (\d+)LL", hdr).group(1))
+    assert top == fh.FH_NOALLOC_MAX_NODES
+    for prec in (0, 1):
+        assert lib.fh_workspace_size(fh.FH_OP_EVAL, top, 10, 3, prec) <= cap
+        assert lib.fh_workspace_size(fh.FH_OP_EVAL, top + 1, 10, 3, prec) > cap
+
+    def call(**kw):
+        a = dict(nodes=P, values=P, n=10, d=3, x=P, m=100, r=P2, lam=None, w=None, prec=0)
+        a.update(kw)
+        return lib.fh_eval_noalloc(a["nodes"], a["values"], a["n"], a["d"], a["x"], a["m"],
+                                   a["r"], a["lam"], a["w"], a["prec"], None)
+
+    assert call(n=top + 1) == fh.FH_E_TOO_LARGE
+    assert call(n=fh.FH_MAX_NODES + 1) == fh.FH_E_ARG
+    assert call(nodes=None) == fh.FH_E_ARG and call(values=None) == fh.FH_E_ARG
+    assert call(n=0) == fh.FH_E_ARG and call(m=-1) == fh.FH_E_ARG
+    assert call(x=None) == fh.FH_E_ARG and call(r=None) == fh.FH_E_ARG
+    assert call(d=10) == fh.FH_E_DEGREE and call(d=-1) == fh.FH_E_DEGREE
+    assert call(prec=2) == fh.FH_E_ARG
+    assert "noalloc" in fh.status_string(fh.FH_E_TOO_LARGE)
 
 
 def test_prepare_many_host_validation():
