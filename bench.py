@@ -47,7 +47,10 @@ sys.path.insert(0, ROOT)
 from paper_1606_06508_amd import fh, inputs  # noqa: E402
 
 FP64_PEAK_TFLOPS = 78.6       # MI355X FP64 vector, published
-FLOPS_PER_PAIR_RL = 7         # sub, div, mul+add (N), add (D), add (L)
+# algorithmic flops per pair with r and Lambda: sub (delta = x - x_k), div
+# (t = 1 / delta), mul (a = w t), multiply-add into N (2), add into D, add
+# into L (|a|); 6 without Lambda
+FLOPS_PER_PAIR_RL = 7
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_eval_f64_sines.json")
 EVAL_SRC = [os.path.join(ROOT, "paper_1606_06508_amd", "csrc", f)
             for f in ("eval_f64.hip", "pair_math.h")]
@@ -276,10 +279,13 @@ def _time_ms(fn, reps, stream=None):
     return e0.elapsed_time(e1) / reps
 
 
-def run_batched_form(dev, reps, with_cpu):
+def run_batched_form(dev, reps, with_cpu, tune=True):
     """All 4096 interpolants in one graph launch (weights + evaluation of
     every instance), against a loop of one fh_eval call per instance on the
-    same stream (same precision, same outputs)."""
+    same stream (same precision, same outputs).  With tune, the autotuner
+    first times every batched launch variant on this batch (one graph launch
+    each) and installs the fastest; the timed batches then run its choice."""
+    from paper_1606_06508_amd import autotune
     c = inputs.batched_workload()
     n, d, m = c["n"], c["d"], c["m"]
     pairs = float((n * m).sum())
@@ -288,9 +294,22 @@ def run_batched_form(dev, reps, with_cpu):
                        f"sum m = {int(m.sum())}, pairs = {pairs:.3e}"}
     r_loop = torch.empty_like(x)
     for prec in ("fp64", "split"):
+        family = "batched_" + prec
+        tuned = None
+        if tune:
+            (tuned,) = autotune.tune_batch(c, (prec,), reps=2, device=dev)["entries"]
         b = fh.Batch(n, d, m, nodes, vals, x, precision=prec)
         ms = _time_ms(b, reps)
-        out[prec] = {"Gpair_s": pairs / (ms * 1e-3) / 1e9, "ms_per_launch": ms}
+        shape = dict((v[0], v[1:]) for v in fh.variants(family))[b.variant]
+        out[prec] = {"Gpair_s": pairs / (ms * 1e-3) / 1e9, "ms_per_launch": ms,
+                     "variant": {"id": b.variant, "chosen_by": "autotuner, live" if tune
+                                 else "built-in table",
+                                 "points_per_lane": shape[0], "node_split": shape[2],
+                                 "lebesgue_block": fh.variant_lebesgue_block(family, b.variant),
+                                 "strip_points": b.strip_points}}
+        if tuned is not None:
+            out[prec]["variant"]["tuner_ms_by_variant"] = {
+                k: round(v, 3) for k, v in sorted(tuned["all_ms"].items(), key=lambda t: t[1])}
         if with_cpu and prec == "fp64":
             from oracle import metrics, oracle
             g = np.random.default_rng(1)
@@ -577,6 +596,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="batched form: run the built-in variant choice instead of tuning live")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (the reference dispatch that "
                          "scales the HBM byte counters)")
@@ -590,7 +611,8 @@ def main():
         return
     if args.profile_form:
         dev = torch.device("cuda:0")
-        run = {"split": run_split_forms, "batched": run_batched_form,
+        run = {"split": run_split_forms,
+               "batched": lambda dev, reps, cpu: run_batched_form(dev, reps, cpu, tune=False),
                "grad": run_backward_form, "normalize": run_normalize_form,
                "lebesgue": run_lebesgue_form, "multi": run_multi_form}[args.profile_form]
         print(json.dumps({args.profile_form: run(dev, args.steps, False)}))
@@ -639,7 +661,8 @@ def main():
     if not args.no_forms:
         forms = {"split_workload": run_split_forms(dev, 5, not args.no_cpu_baseline)}
         print("[bench] split form done", file=sys.stderr, flush=True)
-        forms["batched_workload"] = run_batched_form(dev, 3, not args.no_cpu_baseline)
+        forms["batched_workload"] = run_batched_form(dev, 3, not args.no_cpu_baseline,
+                                                     tune=not args.no_tune)
         print("[bench] batched form done", file=sys.stderr, flush=True)
         forms["grad_workload"] = run_backward_form(dev, 5, not args.no_cpu_baseline)
         print("[bench] backward form done", file=sys.stderr, flush=True)

@@ -188,10 +188,12 @@ fh_status fh_prepare_many(const double* nodes, const double* values, int64_t n,
  * same points, in one launch (for instance the degrees of a sweep prepared
  * by fh_prepare_many): table c writes r_host[c][0..m) and
  * lambda_host[c][0..m), the bits fh_eval_prepared(ws_host[c], ...) writes
- * with the same launch variant (each call picks the variant tuned for its
- * own point count: K * m here, m there; fh_tune_force makes them one).  One
- * launch instead of K saves, per table, the drain of the launch's last
- * blocks and the gap before the next launch.
+ * for the same m: the launch takes the variant tuned for its K * m points
+ * only when that variant sums in the same order as the one a single call
+ * with m points would take (they differ only in points per lane), and that
+ * single call's variant otherwise.  One launch instead of K saves, per
+ * table, the drain of the launch's last blocks and the gap before the next
+ * launch.
  *   ws_host      host array of K device workspaces prepared in binary64
  *                with n nodes (fh_prepare or fh_prepare_many), each of at
  *                least fh_workspace_size(FH_OP_EVAL, n, m, 0, prec) <=
@@ -318,41 +320,60 @@ fh_status fh_batch_destroy(fh_batch* b);
 fh_status fh_batch_status(fh_batch* b, void* stream, uint32_t* bits_out);
 
 /* Kernel-variant selection (the autotuner's interface).  Each evaluation
- * kernel exists in several variants: points per lane, node group size of
- * the shared reciprocal, and node split across the waves of a block.  The
+ * kernel exists in several launch variants: points per lane, node group size
+ * of the shared reciprocal, node split across the waves of a block, the node
+ * block of the Lebesgue sums, and (batches) the passes per work item.  The
  * variant for a call is looked up by (kernel family, ceil(log2 of n rounded
- * up to 64), ceil(log2 m)) in a per-process table; untuned shapes use a
- * built-in table measured on MI355X or a size rule.  Kernel families: the
- * precisions FH_FP64 and FH_FP32_SPLIT for fh_eval / fh_lebesgue, and
- * FH_TUNE_BATCHED_FP64 / FH_TUNE_BATCHED_SPLIT for fh_batch_create (keyed
- * by the mean n and the total number of points; read when a batch is
- * created).  All variants compute the same quantities to the
- * same error bound; they differ in speed and in summation order.
- *   fh_variant_count / fh_variant_shape  enumerate the variants of `prec`;
+ * up to 64), ceil(log2 m)) in a per-process table; shapes with no entry use
+ * a built-in table measured on MI355X, then a size rule.  Whether Lambda is
+ * requested does not enter the choice, so r has the same bits with and
+ * without it.  Kernel families: the precisions FH_FP64 and FH_FP32_SPLIT for
+ * fh_eval / fh_lebesgue / fh_eval_prepared, and FH_TUNE_BATCHED_FP64 /
+ * FH_TUNE_BATCHED_SPLIT for fh_batch_create (keyed by the mean n and the
+ * total number of points; read when a batch is created).  All variants
+ * compute the same quantities to the same error bound; they differ in speed
+ * and, where their summation order differs, in the last bits.
+ *   fh_variant_count / fh_variant_shape  enumerate the variants of a family
+ *                  (points per lane, group size, node split);
  *   fh_variant_lebesgue_block  the node block length U of a variant whose
- *                  Lebesgue sum is taken by blocks (binary64 variants that
- *                  use the alternating signs of the weights: one multiply-
- *                  add per pair serves both sum_k a_k and sum_k |a_k|), 0
- *                  for plain sums, -1 for a bad family or id.  Such a
- *                  variant runs plain sums when caller weights do not
- *                  alternate strictly in sign (w_k w_{k+1} < 0 for every k;
- *                  Floater-Hormann weights always do); r does not depend on
- *                  whether Lambda is requested.  Batched split variants
- *                  (weights always the library's) take tiles of 32;
- *                  batched binary64 variants plain sums;
- *   fh_tune_set    records variant `id` for the shape bucket of (n, m)
- *                  (id = -1 removes the entry);
- *   fh_tune_force  pins variant `id` for every shape (-1 releases it);
+ *                  sums are taken by blocks (they use the alternating signs
+ *                  of the weights: one multiply-add per pair serves both
+ *                  sum_k a_k and sum_k |a_k|), 0 for plain sums, -1 for a bad
+ *                  family or id.  Such a variant runs plain sums when caller
+ *                  weights do not alternate strictly in sign (w_k w_{k+1} < 0
+ *                  for every k; Floater-Hormann weights always do); r does not
+ *                  depend on whether Lambda is requested.  Batched split
+ *                  variants take tiles of 32, batched binary64 variants 16 or
+ *                  plain sums;
+ *   fh_variant_strip_points  points one block covers (single-interpolant
+ *                  families) or one work item (batched families), -1 for a
+ *                  bad family or id;
+ *   fh_tune_set    records variant `id` of family `prec` for the shape bucket
+ *                  of (n, m) (id = -1 removes the entry);
+ *   fh_tune_force  pins variant `id` of a family for every shape (-1
+ *                  releases it);
  *   fh_tune_get    the variant a call with (n, m) would use now.
- * The table is process-wide and guarded by a mutex. */
+ * The table is process-wide and guarded by a mutex.  With the environment
+ * variable FH_AUTOTUNE_CACHE naming a table saved by the autotuner
+ * (paper_1606_06508_amd/autotune.py: JSON with "arch" and "entries"), the
+ * library installs it on first use when its "arch" is the device's; FH_LOG=1
+ * reports on stderr every new (shape, variant) choice, where it came from
+ * (forced, tuned, built-in), and each batch's launch shape. */
 enum { FH_TUNE_BATCHED_FP64 = 2, FH_TUNE_BATCHED_SPLIT = 3 };
 int32_t fh_variant_count(int32_t prec);
 fh_status fh_variant_shape(int32_t prec, int32_t id, int32_t* points_per_lane, int32_t* group,
                            int32_t* node_split);
 int32_t fh_variant_lebesgue_block(int32_t prec, int32_t id);
+int64_t fh_variant_strip_points(int32_t prec, int32_t id);
 fh_status fh_tune_set(int32_t prec, int64_t n, int64_t m, int32_t id);
 fh_status fh_tune_force(int32_t prec, int32_t id);
 int32_t fh_tune_get(int32_t prec, int64_t n, int64_t m);
+
+/* The launch variant a batch runs (of family FH_TUNE_BATCHED_FP64 or
+ * FH_TUNE_BATCHED_SPLIT, chosen when it was created) and the points of one
+ * of its work items; -1 for NULL. */
+int32_t fh_batch_variant(const fh_batch* b);
+int64_t fh_batch_strip_points(const fh_batch* b);
 
 /* Synchronizes `stream`, reads the workspace status word into *bits_out,
  * clears it, and returns the status of the most severe set bit, in the

@@ -2,13 +2,21 @@
 
 Every evaluation kernel of libfh.so exists in several variants (points per
 lane, node-group size of the shared reciprocal, node split across the waves
-of a block; fh.variants() lists them).  tune() times every variant on
-synthetic problems of the requested shapes with HIP events, keeps the
-fastest per (precision, n bucket, m bucket) and records it in the library's
-per-process table (fh_tune_set).  save()/load() keep the table as JSON keyed
-by GPU architecture, so a tuned table can be reused without re-timing.
+of a block, node block of the Lebesgue sums, and for batches the passes per
+work item, i.e. the strip length; fh.variants() lists them).  tune() times
+every variant of the single-interpolant kernels on synthetic problems of
+the requested shapes, tune_batch() every variant of the batched kernel on a
+given batch (one graph launch each), both with HIP events; the fastest is
+recorded per (family, n bucket, m bucket) in the library's per-process
+table (fh_tune_set), which fh_eval and fh_batch_create read.  Each entry
+notes whether it was timed with Lambda ("lambda"); the choice serves calls
+with and without it, so r keeps the same bits either way.
+save()/load() keep the table as JSON keyed by GPU architecture, so a tuned
+table can be reused without re-timing -- from Python, or by the library
+itself through the environment variable FH_AUTOTUNE_CACHE.
 
     python -m paper_1606_06508_amd.autotune --out tune.json [--shapes 1001x1000000 ...]
+        [--batch]
 
 All variants compute the same quantities to the same error bound; the
 tuner only chooses among them by speed.
@@ -82,18 +90,23 @@ def time_variants(n, m, precision="fp64", d=4, reps=5, lebesgue=True, device="cu
     return out
 
 
-def tune(shapes=None, precisions=("fp64", "split"), reps=5, device="cuda:0", verbose=False):
-    """Times all variants per shape and installs the fastest.  Returns the
-    table as a JSON-ready dict."""
+def _arch(device):
+    return torch.cuda.get_device_properties(device).gcnArchName.split(":")[0]
+
+
+def tune(shapes=None, precisions=("fp64", "split"), reps=5, device="cuda:0", verbose=False,
+         lebesgue=True):
+    """Times all variants per shape (with or without Lambda) and installs the
+    fastest.  Returns the table as a JSON-ready dict."""
     shapes = shapes or DEFAULT_SHAPES
-    arch = torch.cuda.get_device_properties(device).gcnArchName.split(":")[0]
-    table = {"arch": arch, "entries": []}
+    table = {"arch": _arch(device), "entries": []}
     for prec in precisions:
         for n, m in shapes:
-            times = time_variants(n, m, prec, reps=reps, device=device)
+            times = time_variants(n, m, prec, reps=reps, device=device, lebesgue=lebesgue)
             best = min(times, key=times.get)
             fh.tune_set(prec, n, m, best)
-            table["entries"].append({"precision": prec, "n": n, "m": m, "variant": best,
+            table["entries"].append({"precision": prec, "n": n, "m": m,
+                                     "lambda": int(bool(lebesgue)), "variant": best,
                                      "ms": times[best],
                                      "all_ms": {str(k): v for k, v in times.items()}})
             if verbose:
@@ -102,6 +115,79 @@ def tune(shapes=None, precisions=("fp64", "split"), reps=5, device="cuda:0", ver
                 print(f"[tune] {prec} n={n} m={m}: variant {best} (P,G,S,U)={shape} "
                       f"{times[best]:.4f} ms; worst {max(times.values()):.4f} ms",
                       file=sys.stderr, flush=True)
+    return table
+
+
+def batch_key(n):
+    """(n, m) under which fh_batch_create looks a batch up: the mean node
+    count (rounded up) and the total number of points."""
+    n = np.asarray(n, dtype=np.int64)
+    return int(-(-int(n.sum()) // n.size))
+
+
+def time_batch_variants(c, precision="fp64", lebesgue=False, reps=3, passes=2,
+                        device="cuda:0"):
+    """{variant id: ms of one graph launch} of the batched kernel family
+    `precision` on the CSR batch c (inputs.batched_workload's dict): one batch
+    per variant (created with that variant forced), warmed up, then `passes`
+    rounds over all variants of `reps` launches each; the best round's mean
+    per variant (rounds interleave the variants)."""
+    family = "batched_" + precision
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(device)  # noqa
+    nodes, vals, pts = t(c["nodes"]), t(c["values"]), t(c["points"])
+    r = torch.empty_like(pts)
+    lam = torch.empty_like(pts) if lebesgue else None
+    batches, out = {}, {}
+    try:
+        for vid, *_ in fh.variants(family):
+            fh.tune_force(family, vid)
+            batches[vid] = fh.Batch(c["n"], c["d"], c["m"], nodes, vals, pts, lebesgue=lebesgue,
+                                    precision=precision, r_out=r, lambda_out=lam)
+        fh.tune_force(family, -1)
+        first = next(iter(batches.values()))
+        _warm(first)
+        for _ in range(passes):
+            for vid, b in batches.items():
+                b()
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(reps):
+                    b()
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / reps
+                out[vid] = min(out.get(vid, ms), ms)
+    finally:
+        fh.tune_force(family, -1)
+        for b in batches.values():
+            b.close()
+    return out
+
+
+def tune_batch(c, precisions=("fp64",), lebesgue=False, reps=3, device="cuda:0",
+               verbose=False):
+    """Times every batched variant on the batch c and installs the fastest for
+    that batch's shape (family, mean n, total m): a batch created afterwards
+    on the same shape runs it.  Returns the table."""
+    n_key, m_key = batch_key(c["n"]), int(np.asarray(c["m"]).sum())
+    table = {"arch": _arch(device), "entries": []}
+    for prec in precisions:
+        family = "batched_" + prec
+        times = time_batch_variants(c, prec, lebesgue=lebesgue, reps=reps, device=device)
+        best = min(times, key=times.get)
+        fh.tune_set(family, n_key, m_key, best)
+        table["entries"].append({"precision": family, "n": n_key, "m": m_key,
+                                 "lambda": int(bool(lebesgue)), "variant": best,
+                                 "ms": times[best],
+                                 "all_ms": {str(k): v for k, v in times.items()}})
+        if verbose:
+            shape = dict((v[0], v[1:]) for v in fh.variants(family))[best]
+            print(f"[tune] {family} {len(c['n'])} instances: variant {best} (P,G,S)={shape} "
+                  f"U={fh.variant_lebesgue_block(family, best)} "
+                  f"strip={fh.variant_strip_points(family, best)} {times[best]:.3f} ms; "
+                  f"worst {max(times.values()):.3f} ms", file=sys.stderr, flush=True)
     return table
 
 
@@ -115,8 +201,7 @@ def load(path, device="cuda:0"):
     Returns the number of entries installed."""
     with open(path) as f:
         table = json.load(f)
-    arch = torch.cuda.get_device_properties(device).gcnArchName.split(":")[0]
-    if table.get("arch") != arch:
+    if table.get("arch") != _arch(device):
         return 0
     for e in table["entries"]:
         fh.tune_set(e["precision"], e["n"], e["m"], e["variant"])
@@ -129,11 +214,17 @@ def main():
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--shapes", nargs="*", default=None, help="n x m, e.g. 1001x1000000")
     ap.add_argument("--precisions", nargs="*", default=["fp64", "split"])
+    ap.add_argument("--batch", action="store_true",
+                    help="also tune the batched kernels on the 4096-instance workload")
     args = ap.parse_args()
     shapes = None
     if args.shapes:
         shapes = [tuple(int(v) for v in s.lower().split("x")) for s in args.shapes]
     table = tune(shapes, args.precisions, args.reps, verbose=True)
+    if args.batch:
+        from . import inputs
+        table["entries"] += tune_batch(inputs.batched_workload(), args.precisions,
+                                       verbose=True)["entries"]
     if args.out:
         save(table, args.out)
     print(json.dumps(table))

@@ -180,9 +180,13 @@ fh_status fh_eval_prepared_many(void* const* ws_host, size_t ws_bytes, int32_t K
   }
   if (m == 0) return FH_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  // the launch's shape: K * m points over n nodes
-  const EvalConfig cfg =
-      choose_eval_config(prec, n, 0, m * K, r_host != nullptr, lambda_host != nullptr);
+  // the bits of each table are those of one fh_eval_prepared call with m
+  // points: the variant tuned for the launch's K * m points is taken only if
+  // it sums in the same order as that call's variant
+  const bool want_r = r_host != nullptr, want_l = lambda_host != nullptr;
+  const EvalConfig one = choose_eval_config(prec, n, 0, m, want_r, want_l);
+  EvalConfig cfg = choose_eval_config(prec, n, 0, m * K, want_r, want_l);
+  if (bit_class(prec, cfg.variant) != bit_class(prec, one.variant)) cfg = one;
   if (launch_eval_f64_many(x, m, n, n_pad, a, K, r_host != nullptr, lambda_host != nullptr, cfg,
                            s) != hipSuccess)
     return FH_E_HIP;

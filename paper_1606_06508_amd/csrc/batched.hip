@@ -7,21 +7,25 @@
 // binary32 split records), each instance padded to a multiple of 8 records
 // with zero-weight copies of its last node.
 //
-// Work.  A work item is one strip of 256 * P consecutive points of one
-// instance (one block's worth).  Items are ordered longest first (by the
-// instance's padded node count, i.e. the cost of a strip), and a persistent
-// grid sized to the resident capacity of the device pulls them from an
-// atomic counter: big strips start first, small ones fill the tail.  Inside
-// an item the block runs the same node loops as the single-interpolant
-// kernels (binary64: each wave streams the instance's node records through
-// scalar loads; split: the block stages them in LDS).  The batch's weights
-// are the library's, which alternate in sign, so the split kernel takes its
-// sums by node tiles (one binary32 multiply-add per pair into the tile's
-// even or odd sum serves D and the Lebesgue sum; the tile around each point
-// is corrected afterwards), with or without Lambda, so r does not depend on
-// it.  The binary64 kernel keeps plain sums: by blocks of 16 its r-only
-// form ran 4 % slower on the 4096-instance workload, with Lambda 2.5 %
-// faster.
+// Work.  A work item is one strip of consecutive points of one instance:
+// Q passes of the block, each pass 64 * P * (4 / S) points (P points per
+// lane, S waves splitting the node range of each group of 64 * P points).
+// Items are ordered longest first (by the instance's padded node count,
+// i.e. the cost of a strip), and a persistent grid sized to the resident
+// capacity of the device pulls them from an atomic counter: big strips
+// start first, small ones fill the tail.  Inside a pass the block runs the
+// node loops of the single-interpolant kernels (binary64: each wave streams
+// its slice of the instance's node records through scalar loads; split: the
+// block stages them in LDS).
+//
+// Launch variants (the autotuner's choice per batch shape): points per lane
+// P, node split S, the binary64 Lebesgue block U (0 = plain sums; 16 = sums
+// by node blocks, one multiply-add per pair for D and the Lebesgue sum, the
+// block around each point corrected afterwards; the batch's weights are the
+// library's, which alternate in sign) and passes per strip Q.  Binary64
+// variants with U = 16 pad each instance to a multiple of 16 records, the
+// others to 8.  The split kernel always takes its sums by node tiles (with
+// or without Lambda, so r does not depend on it); its variants are P and Q.
 //
 // Graph.  fh_batch_create captures, on a private stream: a one-thread kernel
 // that resets the item counter (a kernel rather than a memset node), the
@@ -29,6 +33,7 @@
 // and the persistent evaluation kernel.  fh_eval_batched is one
 // hipGraphLaunch.
 #include <algorithm>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -118,16 +123,23 @@ __device__ __forceinline__ int next_item(uint32_t* counter, int* s_item) {
   return item;
 }
 
-template <int P, bool R, bool L>
+// Binary64: wave (slice, pg) of the block owns the 64 * P points pg of the
+// pass and the node slice `slice` (whole node groups, or whole blocks of U
+// records); the S partial sums meet in LDS in wave order.
+template <int P, int G, int S, bool R, bool L, int U>
 __global__ void __launch_bounds__(256)
     k_batch_f64(const InstDesc* __restrict__ inst, const int2* __restrict__ items, int n_items,
-                uint32_t* counter, const double* __restrict__ x, double* __restrict__ r,
-                double* __restrict__ lam, const double* __restrict__ tx,
+                int32_t passes, uint32_t* counter, const double* __restrict__ x,
+                double* __restrict__ r, double* __restrict__ lam, const double* __restrict__ tx,
                 const double* __restrict__ tw, const double* __restrict__ twf,
                 const double* __restrict__ tf) {
-  constexpr int G = 8;
+  constexpr int PG = 4 / S;  // point groups per block
+  constexpr int64_t kPass = 64LL * P * PG;
+  constexpr int64_t kUnit = U > 0 ? U : G;
   __shared__ int s_item;
-  const int tid = threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int slice = wave % S, pg = wave / S;
   for (;;) {
     const int item = next_item(counter, &s_item);
     if (item >= n_items) break;
@@ -135,34 +147,77 @@ __global__ void __launch_bounds__(256)
     const InstDesc ds = inst[__builtin_amdgcn_readfirstlane(it.x)];
     const int64_t strip = __builtin_amdgcn_readfirstlane(it.y);
     const double* px = x + ds.poff;
-    const int64_t base = strip * 256 * P + tid;
-    double xp[P], N[P], D[P], A[P];
-    bool bad[P];
+    const double *ix = tx + ds.toff, *iw = tw + ds.toff, *iwf = twf + ds.toff, *iff = tf + ds.toff;
+    // node slice of this wave: whole units, the last slices possibly shorter
+    const int64_t units = ds.n_pad / kUnit;
+    const int64_t per_slice = (units + S - 1) / S;
+    const int64_t u0 = slice * per_slice < units ? slice * per_slice : units;
+    const int64_t u1 = (slice + 1) * per_slice < units ? (slice + 1) * per_slice : units;
+    const int64_t first = strip * passes * kPass;
+    for (int q = 0; q < passes; ++q) {
+      const int64_t pass0 = first + q * kPass;
+      if (pass0 >= ds.m) break;  // uniform over the block
+      const int64_t base = pass0 + pg * 64 * P + lane;
+      double xp[P], N[P], D[P], A[P];
+      bool bad[P];
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-      const int64_t idx = base + j * 256;
-      xp[j] = px[idx < ds.m ? idx : ds.m - 1];
-      N[j] = D[j] = A[j] = 0.0;
-      bad[j] = false;
-    }
-    accumulate_f64<P, G, R, L>(xp, tx + ds.toff, tw + ds.toff, twf + ds.toff, 0, ds.n_pad, N, D,
-                               A, bad);
-#pragma unroll
-    for (int j = 0; j < P; ++j) {
-      const int64_t idx = base + j * 256;
-      if (idx >= ds.m) continue;
-      double rv, lv;
-      if (bad[j]) {
-        const PointRL e =
-            eval_point_exact<R, L>(xp[j], tx + ds.toff, tw + ds.toff, tf + ds.toff, ds.n);
-        rv = e.r;
-        lv = e.l;
-      } else {
-        rv = ldexp(N[j] / D[j], ds.shift);
-        lv = A[j] / fabs(D[j]);
+      for (int j = 0; j < P; ++j) {
+        const int64_t idx = base + j * 64;
+        xp[j] = px[idx < ds.m ? idx : ds.m - 1];
+        N[j] = D[j] = A[j] = 0.0;
+        bad[j] = false;
       }
-      if (R) r[ds.poff + idx] = rv;
-      if (L) lam[ds.poff + idx] = lv;
+      if constexpr (U > 0)
+        accumulate_f64_blocks<P, G, U, R, L>(xp, ix, iw, iwf, u0 * kUnit, u1 * kUnit, N, D, A,
+                                             bad);
+      else
+        accumulate_f64<P, G, R, L>(xp, ix, iw, iwf, u0 * kUnit, u1 * kUnit, N, D, A, bad);
+      if constexpr (S > 1) {
+        __shared__ double red[PG][S - 1][3][64 * P];
+        __shared__ int redbad[PG][S - 1][64 * P];
+        if (slice > 0) {
+#pragma unroll
+          for (int j = 0; j < P; ++j) {
+            red[pg][slice - 1][0][j * 64 + lane] = N[j];
+            red[pg][slice - 1][1][j * 64 + lane] = D[j];
+            red[pg][slice - 1][2][j * 64 + lane] = A[j];
+            redbad[pg][slice - 1][j * 64 + lane] = bad[j];
+          }
+        }
+        __syncthreads();
+        if (slice == 0) {
+#pragma unroll
+          for (int h = 0; h < S - 1; ++h) {
+#pragma unroll
+            for (int j = 0; j < P; ++j) {
+              N[j] += red[pg][h][0][j * 64 + lane];
+              D[j] += red[pg][h][1][j * 64 + lane];
+              A[j] += red[pg][h][2][j * 64 + lane];
+              bad[j] |= redbad[pg][h][j * 64 + lane] != 0;
+            }
+          }
+        }
+        __syncthreads();  // the partial sums are read: the next pass may write
+        if (slice > 0) continue;
+      }
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        const int64_t idx = base + j * 64;
+        if (idx >= ds.m) continue;
+        double rv, lv;
+        if (bad[j]) {
+          const PointRL e = eval_point_exact<R, L>(xp[j], ix, iw, iff, ds.n);
+          rv = e.r;
+          lv = e.l;
+        } else {
+          double a = A[j];
+          if constexpr (L && U > 0) a = lebesgue_block_fix<G, U>(xp[j], ix, iw, ds.n, a);
+          rv = N[j] / D[j];
+          lv = a / fabs(D[j]);
+        }
+        if (R) r[ds.poff + idx] = rv;
+        if (L) lam[ds.poff + idx] = lv;
+      }
     }
   }
 }
@@ -170,10 +225,11 @@ __global__ void __launch_bounds__(256)
 template <int P, bool R, bool L>
 __global__ void __launch_bounds__(kStage)
     k_batch_split(const InstDesc* __restrict__ inst, const int2* __restrict__ items, int n_items,
-                  uint32_t* counter, const double* __restrict__ x, double* __restrict__ r,
-                  double* __restrict__ lam, const float4* __restrict__ s4,
+                  int32_t passes, uint32_t* counter, const double* __restrict__ x,
+                  double* __restrict__ r, double* __restrict__ lam, const float4* __restrict__ s4,
                   const double* __restrict__ tx, const double* __restrict__ tw,
                   const double* __restrict__ tf) {
+  constexpr int64_t kPass = (int64_t)kStage * P;
   __shared__ float4 stage[2][kStage];
   __shared__ int s_item;
   const int tid = threadIdx.x;
@@ -186,52 +242,105 @@ __global__ void __launch_bounds__(kStage)
     const InstDesc ds = inst[__builtin_amdgcn_readfirstlane(it.x)];
     const int64_t strip = __builtin_amdgcn_readfirstlane(it.y);
     const double* px = x + ds.poff;
-    const int64_t base = strip * kStage * P + tid;
     const double x_first = tx[ds.toff], x_last = tx[ds.toff + ds.n - 1];
-    double xp[P], N[P], D[P], A[P];
-    float xh[P], xl[P];
-    bool bad[P];
+    const int64_t first = strip * passes * kPass;
+    for (int q = 0; q < passes; ++q) {
+      const int64_t pass0 = first + q * kPass;
+      if (pass0 >= ds.m) break;  // uniform over the block
+      const int64_t base = pass0 + tid;
+      double xp[P], N[P], D[P], A[P];
+      float xh[P], xl[P];
+      bool bad[P];
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-      const int64_t idx = base + j * kStage;
-      xp[j] = px[idx < ds.m ? idx : ds.m - 1];
-      xh[j] = (float)xp[j];
-      xl[j] = (float)(xp[j] - (double)xh[j]);
-      N[j] = D[j] = A[j] = 0.0;
-      bad[j] = !in_split_domain(xp[j], x_first, x_last);
-    }
-    split_block_sums<P, R, L, 4, true>(stage, s4 + ds.toff, ds.n_pad, mask, xh, xl, N, D, A, bad);
-#pragma unroll
-    for (int j = 0; j < P; ++j) {
-      const int64_t idx = base + j * kStage;
-      if (idx >= ds.m) continue;
-      double rv, lv;
-      if (bad[j]) {
-        const PointRL e =
-            eval_point_exact<R, L>(xp[j], tx + ds.toff, tw + ds.toff, tf + ds.toff, ds.n);
-        rv = e.r;
-        lv = e.l;
-      } else {
-        double a = A[j];
-        if constexpr (L)
-          a = split_tile_fix<4>(xp[j], xh[j], xl[j], tx + ds.toff, ds.n, s4 + ds.toff, ds.n_pad,
-                                mask, a);
-        rv = ldexp(N[j] / D[j], ds.shift);
-        lv = a / fabs(D[j]);
+      for (int j = 0; j < P; ++j) {
+        const int64_t idx = base + j * kStage;
+        xp[j] = px[idx < ds.m ? idx : ds.m - 1];
+        xh[j] = (float)xp[j];
+        xl[j] = (float)(xp[j] - (double)xh[j]);
+        N[j] = D[j] = A[j] = 0.0;
+        bad[j] = !in_split_domain(xp[j], x_first, x_last);
       }
-      if (R) r[ds.poff + idx] = rv;
-      if (L) lam[ds.poff + idx] = lv;
+      split_block_sums<P, R, L, 4, true>(stage, s4 + ds.toff, ds.n_pad, mask, xh, xl, N, D, A,
+                                         bad);
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        const int64_t idx = base + j * kStage;
+        if (idx >= ds.m) continue;
+        double rv, lv;
+        if (bad[j]) {
+          const PointRL e =
+              eval_point_exact<R, L>(xp[j], tx + ds.toff, tw + ds.toff, tf + ds.toff, ds.n);
+          rv = e.r;
+          lv = e.l;
+        } else {
+          double a = A[j];
+          if constexpr (L)
+            a = split_tile_fix<4>(xp[j], xh[j], xl[j], tx + ds.toff, ds.n, s4 + ds.toff, ds.n_pad,
+                                  mask, a);
+          rv = ldexp(N[j] / D[j], ds.shift);
+          lv = a / fabs(D[j]);
+        }
+        if (R) r[ds.poff + idx] = rv;
+        if (L) lam[ds.poff + idx] = lv;
+      }
+      __syncthreads();  // the next pass's staging reuses the LDS buffers
     }
-    __syncthreads();  // the next item's staging reuses the LDS buffers
   }
 }
 
-int batched_variant_count() { return 3; }
+// Variant tables.  Binary64: id -> (points per lane P, group G, node split
+// S, Lebesgue block U, passes per strip Q).  Split: id -> (P, Q), with node
+// quads inverted together (G = 4) and sums by 32-node tiles.
+#define FH_BATCH_F64_VARIANTS(X)                                                               \
+  X(0, 1, 8, 1, 0, 1) X(1, 2, 8, 1, 0, 1) X(2, 4, 8, 1, 0, 1) X(3, 1, 8, 2, 0, 1)             \
+  X(4, 2, 8, 2, 0, 1) X(5, 4, 8, 2, 0, 1) X(6, 1, 8, 1, 16, 1) X(7, 2, 8, 1, 16, 1)           \
+  X(8, 4, 8, 1, 16, 1) X(9, 1, 8, 2, 16, 1) X(10, 2, 8, 2, 16, 1) X(11, 4, 8, 2, 16, 1)       \
+  X(12, 1, 8, 1, 0, 4) X(13, 2, 8, 1, 0, 4) X(14, 4, 8, 1, 0, 4) X(15, 2, 8, 2, 0, 4)         \
+  X(16, 2, 8, 1, 16, 4) X(17, 4, 8, 1, 16, 4)
+#define FH_BATCH_SPLIT_VARIANTS(X) \
+  X(0, 1, 1) X(1, 2, 1) X(2, 4, 1) X(3, 8, 1) X(4, 1, 4) X(5, 2, 4) X(6, 4, 4) X(7, 8, 4)
+
+struct BatchShape {
+  int p, g, s, u, q;
+};
+
+BatchShape batch_shape(int id, bool split) {
+  if (split) {
+    switch (id) {
+#define FH_SHAPE(vid, vp, vq) \
+  case vid: return {vp, 4, 1, kTile, vq};
+      FH_BATCH_SPLIT_VARIANTS(FH_SHAPE)
+#undef FH_SHAPE
+      default: return {0, 0, 0, 0, 0};
+    }
+  }
+  switch (id) {
+#define FH_SHAPE(vid, vp, vg, vs, vu, vq) \
+  case vid: return {vp, vg, vs, vu, vq};
+    FH_BATCH_F64_VARIANTS(FH_SHAPE)
+#undef FH_SHAPE
+    default: return {0, 0, 0, 0, 0};
+  }
+}
+
+int batched_variant_count(bool split) {
+#define FH_COUNT(...) +1
+  return split ? 0 FH_BATCH_SPLIT_VARIANTS(FH_COUNT) : 0 FH_BATCH_F64_VARIANTS(FH_COUNT);
+#undef FH_COUNT
+}
+
 void batched_variant_shape(int id, int* p, int* g, int* s, bool split) {
-  static const int P[3] = {1, 2, 4};
-  *p = (id >= 0 && id < 3) ? P[id] : 0;
-  *g = split ? 4 : 8;  // split: binary32 simultaneous inversion of node quads
-  *s = 1;
+  const BatchShape b = batch_shape(id, split);
+  *p = b.p;
+  *g = b.g;
+  *s = b.s;
+}
+
+int batched_variant_block(int id, bool split) { return batch_shape(id, split).u; }
+
+int64_t batched_variant_strip(int id, bool split) {
+  const BatchShape b = batch_shape(id, split);
+  return split ? (int64_t)kStage * b.p * b.q : 64LL * b.p * (4 / (b.s > 0 ? b.s : 1)) * b.q;
 }
 
 }  // namespace fhk
@@ -239,9 +348,9 @@ void batched_variant_shape(int id, int* p, int* g, int* s, bool split) {
 using namespace fhk;
 
 struct fh_batch {
-  int32_t count = 0, prec = 0, variant = 0, points_per_lane = 1;
+  int32_t count = 0, prec = 0, variant = 0, passes = 1;
   int device = 0;
-  int64_t total_pad = 0, n_items = 0;
+  int64_t total_pad = 0, n_items = 0, strip_pts = 0;
   void* mem = nullptr;
   InstDesc* inst = nullptr;
   int64_t* toff = nullptr;
@@ -255,51 +364,53 @@ struct fh_batch {
 
 namespace {
 
-template <int P>
-hipError_t enqueue_eval(fh_batch* b, const double* x, double* r, double* lam, int grid,
-                        hipStream_t s) {
-  const int n_items = (int)b->n_items;
-  if (b->prec == FH_FP32_SPLIT) {
-    if (r && lam)
-      k_batch_split<P, true, true><<<grid, kStage, 0, s>>>(b->inst, b->items, n_items, b->ctrl, x,
-                                                           r, lam, b->s4, b->tx, b->tw, b->tf);
-    else if (r)
-      k_batch_split<P, true, false><<<grid, kStage, 0, s>>>(b->inst, b->items, n_items, b->ctrl,
-                                                            x, r, lam, b->s4, b->tx, b->tw, b->tf);
-    else
-      k_batch_split<P, false, true><<<grid, kStage, 0, s>>>(b->inst, b->items, n_items, b->ctrl,
-                                                            x, r, lam, b->s4, b->tx, b->tw, b->tf);
-  } else {
-    if (r && lam)
-      k_batch_f64<P, true, true><<<grid, 256, 0, s>>>(b->inst, b->items, n_items, b->ctrl, x, r,
-                                                      lam, b->tx, b->tw, b->twf, b->tf);
-    else if (r)
-      k_batch_f64<P, true, false><<<grid, 256, 0, s>>>(b->inst, b->items, n_items, b->ctrl, x, r,
-                                                       lam, b->tx, b->tw, b->twf, b->tf);
-    else
-      k_batch_f64<P, false, true><<<grid, 256, 0, s>>>(b->inst, b->items, n_items, b->ctrl, x, r,
-                                                       lam, b->tx, b->tw, b->twf, b->tf);
+using F64Kernel = void (*)(const InstDesc*, const int2*, int, int32_t, uint32_t*, const double*,
+                           double*, double*, const double*, const double*, const double*,
+                           const double*);
+using SplitKernel = void (*)(const InstDesc*, const int2*, int, int32_t, uint32_t*,
+                             const double*, double*, double*, const float4*, const double*,
+                             const double*, const double*);
+
+template <int P, int G, int S, int U>
+F64Kernel f64_kernel(bool r, bool l) {
+  return r && l ? k_batch_f64<P, G, S, true, true, U>
+                : (r ? k_batch_f64<P, G, S, true, false, U> : k_batch_f64<P, G, S, false, true, U>);
+}
+
+F64Kernel pick_f64(int id, bool r, bool l) {
+  switch (id) {
+#define FH_CASE(vid, vp, vg, vs, vu, vq) \
+  case vid: return f64_kernel<vp, vg, vs, vu>(r, l);
+    FH_BATCH_F64_VARIANTS(FH_CASE)
+#undef FH_CASE
+    default: return nullptr;
   }
-  return hipGetLastError();
 }
 
 template <int P>
-int resident_grid(fh_batch* b, bool r, bool l) {
-  int per_cu = 0;
-  hipError_t e;
-  if (b->prec == FH_FP32_SPLIT) {
-    const void* k = r && l ? (const void*)k_batch_split<P, true, true>
-                           : (r ? (const void*)k_batch_split<P, true, false>
-                                : (const void*)k_batch_split<P, false, true>);
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kStage, 0);
-  } else {
-    const void* k = r && l ? (const void*)k_batch_f64<P, true, true>
-                           : (r ? (const void*)k_batch_f64<P, true, false>
-                                : (const void*)k_batch_f64<P, false, true>);
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, 0);
+SplitKernel split_kernel(bool r, bool l) {
+  return r && l ? k_batch_split<P, true, true>
+                : (r ? k_batch_split<P, true, false> : k_batch_split<P, false, true>);
+}
+
+SplitKernel pick_split(int id, bool r, bool l) {
+  switch (id) {
+#define FH_CASE(vid, vp, vq) \
+  case vid: return split_kernel<vp>(r, l);
+    FH_BATCH_SPLIT_VARIANTS(FH_CASE)
+#undef FH_CASE
+    default: return nullptr;
   }
+}
+
+// Resident blocks of the batch's kernel on the whole device (-1 on error).
+int resident_grid(fh_batch* b, const void* kernel, int block) {
+  int per_cu = 0;
   hipDeviceProp_t prop;
-  if (e != hipSuccess || hipGetDeviceProperties(&prop, b->device) != hipSuccess) return -1;
+  if (kernel == nullptr ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess ||
+      hipGetDeviceProperties(&prop, b->device) != hipSuccess)
+    return -1;
   if (per_cu < 1) per_cu = 1;
   return per_cu * prop.multiProcessorCount;
 }
@@ -346,19 +457,23 @@ fh_status fh_batch_create(fh_batch** out, int32_t count, const int64_t* n_host,
     int64_t avg_n = 0;
     for (int32_t i = 0; i < count; ++i) avg_n += n_host[i];
     avg_n = (avg_n + count - 1) / count;
-    b->variant = choose_eval_config(tune_family, avg_n, 0, total_m > 0 ? total_m : 1, true, true)
+    b->variant = choose_eval_config(tune_family, avg_n, 0, total_m > 0 ? total_m : 1,
+                                    r_cat != nullptr, lambda_cat != nullptr)
                      .variant;
-    int p, g, s;
-    batched_variant_shape(b->variant, &p, &g, &s, prec == FH_FP32_SPLIT);
-    b->points_per_lane = p;
   }
-  const int64_t strip_pts = 256LL * b->points_per_lane;
+  const bool split = prec == FH_FP32_SPLIT;
+  const BatchShape shape = batch_shape(b->variant, split);
+  b->passes = shape.q;
+  b->strip_pts = batched_variant_strip(b->variant, split);
+  const int64_t strip_pts = b->strip_pts;
+  // binary64 blocks of U records need whole blocks per instance
+  const int64_t pad = !split && shape.u > 0 ? shape.u : kBatchPad;
   for (int32_t i = 0; i < count; ++i) {
     InstDesc& ds = inst[i];
     ds.noff = noff;
     ds.n = n_host[i];
     ds.d = d_host[i];
-    ds.n_pad = round_up(ds.n, kBatchPad);
+    ds.n_pad = round_up(ds.n, pad);
     ds.toff = total_pad;
     ds.poff = poff;
     ds.m = m_host[i];
@@ -438,13 +553,19 @@ fh_status fh_batch_create(fh_batch** out, int32_t count, const int64_t* n_host,
   }
 
   // capture the whole evaluation into a graph on a private stream
-  int grid = -1;
   const bool want_r = r_cat != nullptr, want_l = lambda_cat != nullptr;
-  switch (b->points_per_lane) {
-    case 1: grid = resident_grid<1>(b, want_r, want_l); break;
-    case 2: grid = resident_grid<2>(b, want_r, want_l); break;
-    default: grid = resident_grid<4>(b, want_r, want_l); break;
-  }
+  const F64Kernel kf = split ? nullptr : pick_f64(b->variant, want_r, want_l);
+  const SplitKernel ks = split ? pick_split(b->variant, want_r, want_l) : nullptr;
+  const int block = split ? kStage : 256;
+  const int grid =
+      resident_grid(b, split ? reinterpret_cast<const void*>(ks) : reinterpret_cast<const void*>(kf),
+                    block);
+  if (log_enabled())
+    std::fprintf(stderr,
+                 "[fh] batch of %d instances (%s): variant %d, P %d, S %d, U %d, Q %d, strip %lld "
+                 "points, %lld items, grid %d\n",
+                 count, split ? "split" : "fp64", b->variant, shape.p, shape.s, shape.u, shape.q,
+                 (long long)b->strip_pts, (long long)b->n_items, grid);
   if (grid < 1 || hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
     free_batch(b);
     return FH_E_HIP;
@@ -458,11 +579,14 @@ fh_status fh_batch_create(fh_batch** out, int32_t count, const int64_t* n_host,
     if (prec == FH_FP32_SPLIT)
       k_batch_pack_split<<<(unsigned)count, 256, 0, cs>>>(b->inst, b->tx, b->tw, b->twf, b->s4);
     if (items > 0) {
-      switch (b->points_per_lane) {
-        case 1: e = enqueue_eval<1>(b, x_cat, r_cat, lambda_cat, grid, cs); break;
-        case 2: e = enqueue_eval<2>(b, x_cat, r_cat, lambda_cat, grid, cs); break;
-        default: e = enqueue_eval<4>(b, x_cat, r_cat, lambda_cat, grid, cs); break;
-      }
+      const int n_it = (int)b->n_items;
+      if (split)
+        ks<<<grid, block, 0, cs>>>(b->inst, b->items, n_it, b->passes, b->ctrl, x_cat, r_cat,
+                                   lambda_cat, b->s4, b->tx, b->tw, b->tf);
+      else
+        kf<<<grid, block, 0, cs>>>(b->inst, b->items, n_it, b->passes, b->ctrl, x_cat, r_cat,
+                                   lambda_cat, b->tx, b->tw, b->twf, b->tf);
+      e = hipGetLastError();
     }
     hipError_t e2 = hipStreamEndCapture(cs, &b->graph);
     if (e == hipSuccess) e = hipGetLastError();
@@ -483,6 +607,10 @@ fh_status fh_eval_batched(fh_batch* b, void* stream) {
   return hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)) == hipSuccess ? FH_OK
                                                                                   : FH_E_HIP;
 }
+
+int32_t fh_batch_variant(const fh_batch* b) { return b ? b->variant : -1; }
+
+int64_t fh_batch_strip_points(const fh_batch* b) { return b ? b->strip_pts : -1; }
 
 fh_status fh_batch_destroy(fh_batch* b) {
   free_batch(b);

@@ -56,8 +56,15 @@ int f64_variant_block(int id);  // Lebesgue block length U, 0 for plain sums
 int split_variant_count();
 void split_variant_shape(int id, int* p, int* g, int* s);
 int split_variant_block(int id);  // node tile of the block sums, 0 for plain sums
-int batched_variant_count();
+int batched_variant_count(bool split);
 void batched_variant_shape(int id, int* p, int* g, int* s, bool split);
+int batched_variant_block(int id, bool split);      // Lebesgue block / node tile, 0 for plain
+int64_t batched_variant_strip(int id, bool split);  // points of one work item
+// Variants of one family with the same bit class give the same bits for the
+// same point and table (they differ only in points per lane or strip length).
+int bit_class(int32_t prec, int id);
+// FH_LOG set (and not "0"): launch choices are reported on stderr.
+bool log_enabled();
 
 // Adjoint: points are processed in `chunks` chunks of `chunk` points
 // (m_pad = chunks * chunk, the tail padded with neutral records) so that the

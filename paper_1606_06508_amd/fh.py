@@ -83,6 +83,9 @@ def load():
             "fh_variant_shape": ([i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                   ctypes.POINTER(i32)], ctypes.c_int),
             "fh_variant_lebesgue_block": ([i32, i32], i32),
+            "fh_variant_strip_points": ([i32, i32], i64),
+            "fh_batch_variant": ([vp], i32),
+            "fh_batch_strip_points": ([vp], i64),
             "fh_tune_set": ([i32, i64, i64, i32], ctypes.c_int),
             "fh_tune_force": ([i32, i32], ctypes.c_int),
             "fh_tune_get": ([i32, i64, i64], i32),
@@ -389,9 +392,9 @@ def prepare_many(nodes, values, degrees, *, m_hint=0):
 def eval_many(preps, x, *, want_r=True, lebesgue=False, out=None, lambda_out=None):
     """Evaluate several prepared binary64 interpolants with the same node
     count on the same points in one launch (fh_eval_prepared_many): row c of
-    the (K, m) results has the bits of preps[c](x, ...) run with the same
-    launch variant (the launch tunes for K * m points, a single call for
-    m; tune_force makes them one)."""
+    the (K, m) results has the bits of preps[c](x, ...) (the launch takes the
+    variant tuned for its K * m points only where it sums in the same order
+    as the single call's)."""
     lib = load()
     preps = list(preps)
     K = len(preps)
@@ -458,11 +461,22 @@ def variant_lebesgue_block(precision, variant):
     return u
 
 
+def variant_strip_points(precision, variant):
+    """Points one block (single-interpolant families) or one work item
+    (batched families) of a variant covers."""
+    v = int(load().fh_variant_strip_points(_family(precision), int(variant)))
+    if v < 0:
+        raise FhError(FH_E_ARG, "fh_variant_strip_points")
+    return v
+
+
 def tune_force(precision, variant):
     _check(load().fh_tune_force(_family(precision), int(variant)), "fh_tune_force")
 
 
 def tune_set(precision, n, m, variant):
+    """Records `variant` of a kernel family for calls of shape (n, m)
+    (variant -1 removes the entry)."""
     _check(load().fh_tune_set(_family(precision), int(n), int(m), int(variant)), "fh_tune_set")
 
 
@@ -512,6 +526,16 @@ class Batch:
                                    self._m.ctypes.data_as(i64p), _ptr(self.nodes),
                                    _ptr(self.values), _ptr(self.x), _ptr(self.r), _ptr(self.lam),
                                    _prec(precision), st), "fh_batch_create")
+
+    @property
+    def variant(self):
+        """The launch variant the batch runs (chosen when it was created)."""
+        return int(load().fh_batch_variant(self._h))
+
+    @property
+    def strip_points(self):
+        """Points of one work item of the batch's launch variant."""
+        return int(load().fh_batch_strip_points(self._h))
 
     def __call__(self):
         _check(load().fh_eval_batched(self._h, _stream(self.device)), "fh_eval_batched")

@@ -150,6 +150,34 @@ def test_variant_tables_and_tuner_api():
     assert lib.fh_variant_count(7) == 0
 
 
+def test_batched_variant_tables():
+    """Batched variants: binary64 over points per lane, node split, Lebesgue
+    block and passes per strip; split over points per lane and passes.  The
+    strip (points of one work item) is 64 P (4 / S) Q, split 256 P Q; the
+    first three binary64 variants are the plain single-pass shapes with
+    P = 1, 2, 4."""
+    f64 = fh.variants("batched_fp64")
+    assert len(f64) >= 12 and [v[1:] for v in f64[:3]] == [(1, 8, 1), (2, 8, 1), (4, 8, 1)]
+    strips = set()
+    for vid, p, g, s in f64:
+        st = fh.variant_strip_points("batched_fp64", vid)
+        assert st % (64 * p * (4 // s)) == 0 and st // (64 * p * (4 // s)) in (1, 4)
+        strips.add(st)
+        assert fh.variant_lebesgue_block("batched_fp64", vid) in (0, 16)
+    assert len(strips) >= 4
+    sp = fh.variants("batched_split")
+    assert len(sp) >= 6
+    for vid, p, g, s in sp:
+        assert g == 4 and s == 1
+        st = fh.variant_strip_points("batched_split", vid)
+        assert st % (256 * p) == 0 and st // (256 * p) in (1, 4)
+    assert fh.variant_strip_points("fp64", 16) == 64 * 2 * 1   # P = 2, S = 4
+    assert fh.variant_strip_points("split", 9) == 256 * 2
+    lib = fh.load()
+    assert lib.fh_variant_strip_points(7, 0) == -1 and lib.fh_variant_strip_points(2, 999) == -1
+    assert lib.fh_batch_variant(None) == -1 and lib.fh_batch_strip_points(None) == -1
+
+
 def test_lebesgue_block_variants():
     """Binary64 variants 15..18 take the Lebesgue sum by blocks of 16 nodes,
     split variants 8..11 by tiles of 32 (the block counterparts of plain
@@ -166,9 +194,10 @@ def test_lebesgue_block_variants():
     sshapes = {vid: (p, g, s) for vid, p, g, s in fh.variants("split")}
     for vid in (8, 9, 10, 11):
         assert sshapes[vid] in [sshapes[v] for v, u in sb.items() if u == 0]
-    for fam, u in ((2, 0), (3, 32)):
-        for vid, *_ in fh.variants(fam):
-            assert fh.variant_lebesgue_block(fam, vid) == u
+    bb = {vid: fh.variant_lebesgue_block(2, vid) for vid, *_ in fh.variants(2)}
+    assert set(bb.values()) == {0, 16}
+    for vid, *_ in fh.variants(3):
+        assert fh.variant_lebesgue_block(3, vid) == 32
     lib = fh.load()
     assert lib.fh_variant_lebesgue_block(0, 99) == -1
     assert lib.fh_variant_lebesgue_block(7, 0) == -1

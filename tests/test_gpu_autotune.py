@@ -25,6 +25,7 @@ def test_tune_install_save_load(tmp_path):
         path = tmp_path / "tune.json"
         autotune.save(table, path)
         for e in table["entries"]:
+            assert e["lambda"] == 1
             fh.tune_set(e["precision"], n, m, -1)
         assert autotune.load(path, device=DEV) == len(table["entries"])
         for e in table["entries"]:
@@ -45,3 +46,40 @@ def test_tune_install_save_load(tmp_path):
     finally:
         for prec in ("fp64", "split"):
             fh.tune_set(prec, n, m, -1)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "split"])
+def test_tune_batch_installs_the_variant_a_new_batch_runs(precision):
+    """tune_batch times every batched variant on a batch (one graph launch
+    each) and installs the fastest for that batch's shape: a batch created
+    afterwards on the same shape runs it, within the oracle's bar."""
+    family = "batched_" + precision
+    c = inputs.batched_workload(count=64, n_range=(16, 400), m_range=(500, 6000), salt=11)
+    n_key, m_key = autotune.batch_key(c["n"]), int(c["m"].sum())
+    try:
+        table = autotune.tune_batch(c, (precision,), reps=1, device=DEV)
+        (e,) = table["entries"]
+        assert e["precision"] == family and e["n"] == n_key and e["m"] == m_key
+        assert set(e["all_ms"]) == {str(v[0]) for v in fh.variants(family)}
+        assert e["ms"] == min(e["all_ms"].values())
+        assert fh.tune_get(family, n_key, m_key) == e["variant"]
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)  # noqa: E731
+        b = fh.Batch(c["n"], c["d"], c["m"], t(c["nodes"]), t(c["values"]), t(c["points"]),
+                     precision=precision)
+        assert b.variant == e["variant"]
+        assert b.strip_points == fh.variant_strip_points(family, e["variant"])
+        r = b().cpu().numpy()
+        for i in range(0, c["n"].size, 8):
+            ns = slice(int(c["node_off"][i]), int(c["node_off"][i + 1]))
+            ps = slice(int(c["pt_off"][i]), int(c["pt_off"][i + 1]))
+            r_o, lam_o, s_o = oracle.evaluate(c["nodes"][ns], c["values"][ns], int(c["d"][i]),
+                                              c["points"][ps])
+            st = metrics.parity(r[ps], None, r_o, None, s_o)
+            tol = metrics.FP64_TOL if precision == "fp64" else metrics.SPLIT_TOL
+            keep = lam_o <= (metrics.FP64_LAMBDA_MAX if precision == "fp64" else
+                             metrics.SPLIT_LAMBDA_MAX)
+            err = np.abs(r[ps] - r_o)[keep] / s_o[keep]
+            assert st["nan_mismatch_r"] == 0 and np.all(err <= tol), (i, st)
+        b.close()
+    finally:
+        fh.tune_set(family, n_key, m_key, -1)

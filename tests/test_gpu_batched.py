@@ -84,7 +84,7 @@ def test_bitwise_equal_to_single_kernel(precision, single_variant, lebesgue):
     b.close()
 
 
-def test_edge_instances():
+def _edge_batch():
     g = np.random.default_rng(4)
     specs = [(1, 0, 5), (2, 1, 0), (16, 10, 1), (2048, 1, 700), (17, 3, 257), (300, 0, 513),
              (64, 63, 100), (5, 2, 0)]
@@ -104,6 +104,12 @@ def test_edge_instances():
          "points": np.concatenate(pts)}
     c["node_off"] = np.concatenate([[0], np.cumsum(n)])
     c["pt_off"] = np.concatenate([[0], np.cumsum(m)])
+    return c
+
+
+def test_edge_instances():
+    c = _edge_batch()
+    n, d, m = c["n"], c["d"], c["m"]
     b, (r, lam) = _batch(c)
     r, lam = r.cpu().numpy(), lam.cpu().numpy()
     for i in range(n.size):
@@ -116,6 +122,61 @@ def test_edge_instances():
         hit = np.isin(c["points"][ps], c["nodes"][ns])
         assert np.array_equal(r[ps][hit], r_o[hit]) and np.all(lam[ps][hit] == 1.0)
     b.close()
+
+
+def _bit_class(family, vid):
+    shape = {v[0]: v[1:] for v in fh.variants(family)}[vid]
+    return shape[1], shape[2], fh.variant_lebesgue_block(family, vid)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "split"])
+@pytest.mark.parametrize("lebesgue", [True, False])
+def test_every_batched_variant(precision, lebesgue):
+    """Every launch variant of the batched kernel (points per lane, node
+    split, Lebesgue block, passes per strip), forced one at a time, on edge
+    instances (n = 1, 2, 16, ..., m = 0, 1, ragged, exact hits) and a
+    seeded small batch: each instance within the oracle's bar, and variants
+    that sum in the same order (they differ in points per lane or strip
+    length only) give the same bits."""
+    family = "batched_" + precision
+    c = _edge_batch()
+    small = _small_batch(salt=7, count=24)
+    bits = {}
+    for vid, *_ in fh.variants(family):
+        fh.tune_force(family, vid)
+        try:
+            outs = [_batch(cc, precision, lebesgue=lebesgue) for cc in (c, small)]
+        finally:
+            fh.tune_force(family, -1)
+        for (b, out), cc in zip(outs, (c, small)):
+            assert b.variant == vid
+            r, lam = out if lebesgue else (out, None)
+            r_h = r.cpu().numpy()
+            lam_h = lam.cpu().numpy() if lebesgue else None
+            for i in range(cc["n"].size):
+                ns, ps = _slices(cc, i)
+                if ps.stop == ps.start:
+                    continue
+                r_o, lam_o, s_o = oracle.evaluate(cc["nodes"][ns], cc["values"][ns],
+                                                  int(cc["d"][i]), cc["points"][ps])
+                st = metrics.parity(r_h[ps], lam_h[ps] if lebesgue else None, r_o, lam_o, s_o,
+                                    metrics.FP64_LAMBDA_MAX if precision == "fp64" else
+                                    metrics.SPLIT_LAMBDA_MAX)
+                if precision == "fp64":
+                    metrics.check_fp64(st, lam_metric="cond")
+                else:
+                    assert st["nan_mismatch_r"] == 0 and st["e_cond_max"] <= metrics.SPLIT_TOL, st
+                    if lebesgue:
+                        assert st["e_cond_lam_max"] <= metrics.SPLIT_TOL, st
+                hit = np.isin(cc["points"][ps], cc["nodes"][ns])
+                assert np.array_equal(r_h[ps][hit], r_o[hit]), (vid, i)
+            b.close()
+        key = _bit_class(family, vid)
+        got = [o[1] if not lebesgue else torch.cat(o[1]) for o in outs]
+        if key in bits:
+            assert all(torch.equal(a, b_) for a, b_ in zip(got, bits[key])), (vid, key)
+        else:
+            bits[key] = got
 
 
 def test_split_instances_outside_binary32_domain():

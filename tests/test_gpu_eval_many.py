@@ -1,8 +1,8 @@
 """Several prepared tables evaluated in one launch (fh_eval_prepared_many):
 every table's r and Lambda have the bits of its own fh_eval_prepared call
-with the same launch variant (the per-point operations are the same; only
-the launch differs; each call tunes for its own point count, so the
-comparisons force one variant), for
+-- with the tuner's own choices (the launch takes the variant tuned for all
+its points only where that sums in the same order as the single call's),
+and with one launch variant forced -- for
 several launch variants (plain sums, Lebesgue blocks, node splits 2 and 4),
 ragged point counts, r alone, Lambda alone, up to 16 tables, tables packed
 by fh_prepare_many or one by one; and the oracle's bar on the sines
@@ -36,6 +36,21 @@ def _case(n, m, seed):
     pts = np.concatenate([g.uniform(nodes[0] - 0.1, nodes[-1] + 0.1, m), nodes[::5],
                           [np.nan, np.inf]])
     return nodes, vals, pts
+
+
+@pytest.mark.parametrize("n,m,K", [(21, 10021, 3), (1001, 20011, 9), (1001, 1_000_000, 9),
+                                   (257, 300_000, 16), (4097, 99_999, 2)])
+def test_bits_independent_of_call_shape(n, m, K):
+    """No variant forced: each table of one launch over K tables equals its
+    own fh_eval_prepared call with the same m, bit for bit."""
+    nodes, vals, pts = _case(n, m, 5)
+    degrees = [k % min(n, 9) for k in range(K)]
+    preps = fh.prepare_many(_t(nodes), _t(vals), degrees)
+    x = _t(pts)
+    many = fh.eval_many(preps, x, lebesgue=True)
+    for c, p in enumerate(preps):
+        r1, l1 = p(x, lebesgue=True)
+        assert _bits_equal(many[0][c], r1) and _bits_equal(many[1][c], l1), (n, m, K, c)
 
 
 @pytest.mark.parametrize("vid", [3, 10, 15, 17, 18])

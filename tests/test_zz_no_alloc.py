@@ -57,7 +57,7 @@ def test_noalloc_equals_fh_eval_on_consecutive_calls(precision, lebesgue):
         r_o, lam_o, s_o = oracle.evaluate(nodes, vals, d, pts[sel])
         idx = torch.from_numpy(sel).to(DEV)
         st = metrics.parity(r[idx].cpu().numpy(), lam[idx].cpu().numpy() if lebesgue else None,
-                            r_o, lam_o if lebesgue else None, s_o,
+                            r_o, lam_o, s_o,
                             metrics.FP64_LAMBDA_MAX if precision == "fp64" else
                             metrics.SPLIT_LAMBDA_MAX)
         if precision == "fp64":
