@@ -21,15 +21,22 @@ Exact hits are compared bit-for-bit.
 Conditioning limit.  Every term a_k = w_k / (x - x_k) carries a rounding
 error of order u |a_k| in any evaluation (the oracle's included; its
 compensation only removes the summation error), so a computed D is off by
-about u L (L = sum |a_k|), i.e. by a relative u Lambda.  The errors above
-are first-order statements: they hold while u Lambda is small, and where
-u Lambda approaches 1 the computed D (and with it r and Lambda) has no
-correct digits on any side.  FH interpolants on strongly non-uniform nodes
-reach that (Chebyshev nodes: Lambda ~ 3e7 at n = 300, d = 6 and up to
-~1e20 at n = 2048, d = 10).  So the bars apply at points whose oracle
-Lambda is at most lam_max: 2^40 for binary64 (u Lambda <= 2^-13) and 2^14
-for the binary32 terms of the split form (about 40 u32 Lambda <= 0.04);
-points beyond it are counted (n_beyond_lam_max), not compared.
+up to c u L (L = sum |a_k|), a relative eta = c u Lambda.  The errors above
+are first-order statements; to all orders, r^ - r = (dN / D - r dD / D) /
+(1 + dD / D), so e_cond(r) and e_cond(Lambda) grow by at most 1 / (1 - eta)
+and stay bounded while eta < 1.  FH interpolants on strongly non-uniform
+nodes reach large Lambda (Chebyshev nodes: Lambda ~ 3e7 at n = 300, d = 6
+and up to ~1e20 at n = 2048, d = 10).  Three bands, by the oracle's Lambda:
+  Lambda <= lam_max (2^40, u Lambda <= 2^-13): the first-order bars;
+  lam_max < Lambda <= lam_cap (2^48, u Lambda <= 2^-5): the same bars times
+    k = Lambda / lam_max (the "Lambda-scaled" bar): 1 / (1 - c u Lambda) <= k
+    holds for c <= 2^13 (k - 1) / k^2, i.e. for every c up to 31 over the
+    whole band (k <= 256) and for larger c lower in it;
+  Lambda > lam_cap: counted (n_beyond_lam_cap), not compared -- with
+    c ~ 10..30, eta approaches 1 there and no evaluation has correct digits.
+The FP32-split kernels recompute in binary64 every point whose binary32
+terms give a Lebesgue function above 2^14 (their conditioning guard), so
+the split bar applies on the same bands.
 """
 import numpy as np
 
@@ -42,7 +49,14 @@ KAPPA_MAX = 100.0
 # leaves a factor of about three, 2^-17 (~134 u32).
 SPLIT_TOL = 2.0 ** -17
 FP64_LAMBDA_MAX = 2.0 ** 40
-SPLIT_LAMBDA_MAX = 2.0 ** 14
+# the split value kernels send points beyond their guard (Lambda^ > 2^14) to
+# binary64, so their bar covers the binary64 bands
+SPLIT_LAMBDA_MAX = FP64_LAMBDA_MAX
+LAMBDA_CAP = 2.0 ** 48
+# first-order statement of the binary32 terms (error-statement tests) and
+# the split derivative and adjoint kernels, which have no guard: points with
+# Lambda up to 2^14 (about 40 u32 Lambda <= 0.04)
+SPLIT_TERMS_LAMBDA_MAX = 2.0 ** 14
 # Gradients (adjoint), measured against the sums of the absolute values of
 # each component's terms (grad_scales): binary64 1e-12 (about 10^4 u, room
 # for the plain chunked sums of the kernels against the oracle's compensated
@@ -60,16 +74,25 @@ def lambda_scale(lam):
     return lam * (1.0 + lam)
 
 
-def parity(r, lam, r_o, lam_o, s_o, lam_max=FP64_LAMBDA_MAX):
-    """Returns a dict of max errors over the points whose oracle Lambda is at
-    most lam_max (all points when lam_o is None); NaN-consistent points are
-    excluded from the maxima and NaN mismatches counted separately (over all
-    points)."""
-    out = {"lam_max": float(lam_max)}
-    keep = np.ones(np.shape(r_o if r_o is not None else lam_o), dtype=bool)
+def parity(r, lam, r_o, lam_o, s_o, lam_max=FP64_LAMBDA_MAX, lam_cap=LAMBDA_CAP):
+    """Returns a dict of max errors: the first-order bars over the points
+    whose oracle Lambda is at most lam_max (all points when lam_o is None),
+    the Lambda-scaled maxima (e_cond / (Lambda / lam_max)) over the points
+    in (lam_max, lam_cap], and the counts of each band; NaN-consistent
+    points are excluded from the maxima and NaN mismatches counted
+    separately (over all points)."""
+    out = {"lam_max": float(lam_max), "lam_cap": float(lam_cap)}
+    shape = np.shape(r_o if r_o is not None else lam_o)
+    keep = np.ones(shape, dtype=bool)
+    mid = np.zeros(shape, dtype=bool)
+    growth = np.ones(shape)
     if lam_o is not None:
         keep = ~(lam_o > lam_max)            # NaN Lambda is kept (NaN checks)
+        mid = (lam_o > lam_max) & (lam_o <= lam_cap)
+        growth = np.where(mid, lam_o / lam_max, 1.0)
         out["n_beyond_lam_max"] = int(np.count_nonzero(~keep))
+        out["n_lambda_scaled"] = int(np.count_nonzero(mid))
+        out["n_beyond_lam_cap"] = int(np.count_nonzero(lam_o > lam_cap))
     if r is not None:
         nan_o, nan_g = np.isnan(r_o), np.isnan(r)
         out["nan_mismatch_r"] = int(np.count_nonzero(nan_o != nan_g))
@@ -85,6 +108,11 @@ def parity(r, lam, r_o, lam_o, s_o, lam_max=FP64_LAMBDA_MAX):
         well = kappa <= KAPPA_MAX
         out["e_rel_max_well_conditioned"] = float(erel[well].max()) if np.any(well) else 0.0
         out["e_rel_p9999"] = float(np.quantile(erel, 0.9999)) if erel.size else 0.0
+        okm = ~nan_o & ~nan_g & mid
+        em = np.abs(r[okm] - r_o[okm])
+        with np.errstate(divide="ignore", invalid="ignore"):
+            ecm = np.where(s_o[okm] > 0, em / s_o[okm], np.where(em == 0, 0.0, np.inf))
+        out["e_cond_scaled_max"] = float((ecm / growth[okm]).max()) if ecm.size else 0.0
     if lam is not None:
         nan_o, nan_g = np.isnan(lam_o), np.isnan(lam)
         out["nan_mismatch_lam"] = int(np.count_nonzero(nan_o != nan_g))
@@ -94,16 +122,22 @@ def parity(r, lam, r_o, lam_o, s_o, lam_max=FP64_LAMBDA_MAX):
         out["e_rel_lam_max"] = float(el.max()) if el.size else 0.0
         ec = dl / lambda_scale(lam_o[ok])
         out["e_cond_lam_max"] = float(ec.max()) if ec.size else 0.0
+        okm = ~nan_o & ~nan_g & mid
+        ecm = np.abs(lam[okm] - lam_o[okm]) / lambda_scale(lam_o[okm])
+        out["e_cond_lam_scaled_max"] = float((ecm / growth[okm]).max()) if ecm.size else 0.0
     return out
 
 
 def check_split(stats, tol=SPLIT_TOL):
     """Asserts the FP32-split bar on a parity() dict computed with
-    lam_max <= SPLIT_LAMBDA_MAX."""
+    lam_max <= SPLIT_LAMBDA_MAX: the first-order band and the Lambda-scaled
+    band."""
     assert stats["lam_max"] <= SPLIT_LAMBDA_MAX, stats
     assert stats["nan_mismatch_r"] == 0 and stats["nan_mismatch_lam"] == 0, stats
     assert stats["e_cond_max"] <= tol, stats
     assert stats["e_cond_lam_max"] <= tol, stats
+    assert stats.get("e_cond_scaled_max", 0.0) <= tol, stats
+    assert stats.get("e_cond_lam_scaled_max", 0.0) <= tol, stats
 
 
 def check_fp64(stats, tol=FP64_TOL, lam_metric="rel"):
@@ -113,10 +147,12 @@ def check_fp64(stats, tol=FP64_TOL, lam_metric="rel"):
         assert stats["nan_mismatch_r"] == 0, stats
         assert stats["e_cond_max"] <= tol, stats
         assert stats["e_rel_max_well_conditioned"] <= tol, stats
+        assert stats.get("e_cond_scaled_max", 0.0) <= tol, stats
     if "e_rel_lam_max" in stats:
         assert stats["nan_mismatch_lam"] == 0, stats
         key = "e_rel_lam_max" if lam_metric == "rel" else "e_cond_lam_max"
         assert stats[key] <= tol, stats
+        assert stats.get("e_cond_lam_scaled_max", 0.0) <= tol, stats
 
 
 # ------------------------------------------------------------ gradients --

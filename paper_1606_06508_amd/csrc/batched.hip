@@ -50,7 +50,8 @@ namespace fhk {
 struct InstDesc {
   int64_t noff, n, toff, n_pad, poff, m;
   int32_t d, strips;
-  int32_t shift, pad;  // split: ef - e of the instance's table (written by its packing)
+  int32_t shift;  // split: ef - e of the instance's table (written by its packing)
+  int32_t wide;   // split: 1 if the instance takes binary64 terms (written by its packing)
 };
 
 constexpr int64_t kBatchPad = 8;
@@ -94,7 +95,11 @@ __global__ void __launch_bounds__(256)
 }
 
 // one block per instance: exponent of max|w| of that instance, then its
-// binary32 records (see k_pack_split for the scaling argument)
+// binary32 records (see k_pack_split for the scaling argument), then its
+// conditioning (split_table_wide): an instance too ill-conditioned for
+// binary32 terms, or outside the binary32 domain, is marked wide and every
+// point of it is evaluated with binary64 terms (the per-point guard would
+// send most of them there one lane at a time).
 __global__ void __launch_bounds__(256)
     k_batch_pack_split(InstDesc* __restrict__ inst, const double* __restrict__ tx,
                        const double* __restrict__ tw, const double* __restrict__ twf,
@@ -109,6 +114,8 @@ __global__ void __launch_bounds__(256)
     const int64_t e = ds.toff + k;
     s4[e] = split_record(k < ds.n ? tx[e] : pad, tw[e], twf[e], sc);
   }
+  const int wide = split_table_wide(tx + ds.toff, tw + ds.toff, ds.n, red) | !sc.ok;
+  if (threadIdx.x == 0) inst[blockIdx.x].wide = wide;
 }
 
 __global__ void k_batch_reset(uint32_t* counter) { *counter = 0u; }
@@ -228,7 +235,7 @@ __global__ void __launch_bounds__(kStage)
                   int32_t passes, uint32_t* counter, const double* __restrict__ x,
                   double* __restrict__ r, double* __restrict__ lam, const float4* __restrict__ s4,
                   const double* __restrict__ tx, const double* __restrict__ tw,
-                  const double* __restrict__ tf) {
+                  const double* __restrict__ twf, const double* __restrict__ tf) {
   constexpr int64_t kPass = (int64_t)kStage * P;
   __shared__ float4 stage[2][kStage];
   __shared__ int s_item;
@@ -250,7 +257,7 @@ __global__ void __launch_bounds__(kStage)
       const int64_t base = pass0 + tid;
       double xp[P], N[P], D[P], A[P];
       float xh[P], xl[P];
-      bool bad[P];
+      bool bad[P], wide64[P];
 #pragma unroll
       for (int j = 0; j < P; ++j) {
         const int64_t idx = base + j * kStage;
@@ -258,30 +265,61 @@ __global__ void __launch_bounds__(kStage)
         xh[j] = (float)xp[j];
         xl[j] = (float)(xp[j] - (double)xh[j]);
         N[j] = D[j] = A[j] = 0.0;
-        bad[j] = !in_split_domain(xp[j], x_first, x_last);
+        wide64[j] = !in_split_domain(xp[j], x_first, x_last);
+        bad[j] = wide64[j];
       }
-      split_block_sums<P, R, L, 4, true>(stage, s4 + ds.toff, ds.n_pad, mask, xh, xl, N, D, A,
-                                         bad);
+      const double *ix = tx + ds.toff, *iw = tw + ds.toff, *iwf = twf + ds.toff;
+      if (ds.wide) {
+        // an instance too ill-conditioned for binary32 terms: binary64 terms
+        // for all its points (the per-point operations of eval_point_f64)
+#pragma unroll
+        for (int j = 0; j < P; ++j) bad[j] = wide64[j] = false;
+        accumulate_f64<P, 4, R, L>(xp, ix, iw, iwf, 0, ds.n_pad, N, D, A, bad);
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+          const int64_t idx = base + j * kStage;
+          if (idx >= ds.m || bad[j]) continue;
+          if (R) r[ds.poff + idx] = N[j] / D[j];
+          if (L) lam[ds.poff + idx] = A[j] / fabs(D[j]);
+        }
+      } else {
+        // the Lebesgue sum is always accumulated: the conditioning guard
+        // needs it
+        split_block_sums<P, R, true, 4, true>(stage, s4 + ds.toff, ds.n_pad, mask, xh, xl, N, D,
+                                              A, bad);
+        // as in k_eval_split: points that pass the guard, then points for
+        // binary64 terms, then the exact branch for sums that are not finite
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+          const int64_t idx = base + j * kStage;
+          if (idx >= ds.m || bad[j]) continue;
+          const double a = split_tile_fix<4>(xp[j], xh[j], xl[j], ix, ds.n, s4 + ds.toff,
+                                             ds.n_pad, mask, A[j]);
+          if (!(a <= kSplitLambdaGuard * fabs(D[j]))) {
+            bad[j] = wide64[j] = true;
+            continue;
+          }
+          if (R) r[ds.poff + idx] = ldexp(N[j] / D[j], ds.shift);
+          if (L) lam[ds.poff + idx] = a / fabs(D[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+          const int64_t idx = base + j * kStage;
+          if (idx >= ds.m || !wide64[j]) continue;
+          const PointRLF e = eval_point_f64<R, L>(xp[j], ix, iw, iwf, ds.n_pad);
+          if (e.flagged) continue;
+          bad[j] = false;
+          if (R) r[ds.poff + idx] = e.r;
+          if (L) lam[ds.poff + idx] = e.l;
+        }
+      }
 #pragma unroll
       for (int j = 0; j < P; ++j) {
         const int64_t idx = base + j * kStage;
-        if (idx >= ds.m) continue;
-        double rv, lv;
-        if (bad[j]) {
-          const PointRL e =
-              eval_point_exact<R, L>(xp[j], tx + ds.toff, tw + ds.toff, tf + ds.toff, ds.n);
-          rv = e.r;
-          lv = e.l;
-        } else {
-          double a = A[j];
-          if constexpr (L)
-            a = split_tile_fix<4>(xp[j], xh[j], xl[j], tx + ds.toff, ds.n, s4 + ds.toff, ds.n_pad,
-                                  mask, a);
-          rv = ldexp(N[j] / D[j], ds.shift);
-          lv = a / fabs(D[j]);
-        }
-        if (R) r[ds.poff + idx] = rv;
-        if (L) lam[ds.poff + idx] = lv;
+        if (idx >= ds.m || !bad[j]) continue;
+        const PointRL ex = eval_point_exact<R, L>(xp[j], ix, iw, tf + ds.toff, ds.n);
+        if (R) r[ds.poff + idx] = ex.r;
+        if (L) lam[ds.poff + idx] = ex.l;
       }
       __syncthreads();  // the next pass's staging reuses the LDS buffers
     }
@@ -369,7 +407,7 @@ using F64Kernel = void (*)(const InstDesc*, const int2*, int, int32_t, uint32_t*
                            const double*);
 using SplitKernel = void (*)(const InstDesc*, const int2*, int, int32_t, uint32_t*,
                              const double*, double*, double*, const float4*, const double*,
-                             const double*, const double*);
+                             const double*, const double*, const double*);
 
 template <int P, int G, int S, int U>
 F64Kernel f64_kernel(bool r, bool l) {
@@ -479,7 +517,7 @@ fh_status fh_batch_create(fh_batch** out, int32_t count, const int64_t* n_host,
     ds.m = m_host[i];
     ds.strips = (int32_t)((ds.m + strip_pts - 1) / strip_pts);
     ds.shift = 0;
-    ds.pad = 0;
+    ds.wide = 0;
     toff[i] = total_pad;
     noff += ds.n;
     poff += ds.m;
@@ -582,7 +620,7 @@ fh_status fh_batch_create(fh_batch** out, int32_t count, const int64_t* n_host,
       const int n_it = (int)b->n_items;
       if (split)
         ks<<<grid, block, 0, cs>>>(b->inst, b->items, n_it, b->passes, b->ctrl, x_cat, r_cat,
-                                   lambda_cat, b->s4, b->tx, b->tw, b->tf);
+                                   lambda_cat, b->s4, b->tx, b->tw, b->twf, b->tf);
       else
         kf<<<grid, block, 0, cs>>>(b->inst, b->items, n_it, b->passes, b->ctrl, x_cat, r_cat,
                                    lambda_cat, b->tx, b->tw, b->twf, b->tf);

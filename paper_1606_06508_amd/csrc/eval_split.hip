@@ -19,10 +19,14 @@
 //    rounding error grows with the tile length, not with n.
 //  - The quotient r = N / D and Lambda = L / |D| are binary64.
 // A lane whose tile sums are not finite (an exact hit gives t = inf, a NaN
-// point gives NaN, extreme data may overflow binary32), or whose point lies
+// point gives NaN, extreme data may overflow binary32), whose point lies
 // outside the binary32 domain (more than one node span outside the nodes;
-// a table outside the domain carries NaN weights), recomputes its point
-// with the binary64 per-pair division path and the exact-hit branch.
+// a table outside the domain carries NaN weights), or whose point is too
+// ill-conditioned for binary32 terms (the Lebesgue sum, always accumulated,
+// exceeds kSplitLambdaGuard |D|), recomputes its point in binary64 with the
+// binary64 kernel's group reciprocals (eval_point_f64, groups of four), and
+// from there the exact-hit branch or the per-pair division path where that
+// flags.
 //
 // Issue rate.  On gfx950 binary32 add/sub/fmac issue at twice the binary64
 // rate only in the 32-bit VOP2 encoding with VGPR operands; an SGPR operand
@@ -36,6 +40,11 @@
 #include "pair_math.h"
 #include "split_math.h"
 
+// A table that the packing finds too ill-conditioned for binary32 terms
+// (split_table_wide: a Lebesgue function above 2^12 at one of 64 sampled
+// interval midpoints) is evaluated with binary64 terms at every point
+// instead (status word 4).
+
 namespace fhk {
 
 // B: the sums are taken by node tiles (split_block_sums<..., B>) when the
@@ -45,7 +54,8 @@ template <int P, int G, bool R, bool L, bool B>
 __global__ void __launch_bounds__(kStage)
     k_eval_split(const double* __restrict__ x, int64_t m, const float4* __restrict__ s4,
                  int64_t n_pad, const double* __restrict__ tx, const double* __restrict__ tw,
-                 const double* __restrict__ f, int64_t n, const int32_t* __restrict__ scale,
+                 const double* __restrict__ twf, const double* __restrict__ f, int64_t n,
+                 const int32_t* __restrict__ scale,
                  const uint32_t* __restrict__ alt, double* __restrict__ r,
                  double* __restrict__ lam) {
   __shared__ float4 stage[2][kStage];
@@ -58,7 +68,7 @@ __global__ void __launch_bounds__(kStage)
       0x7fffffffu ^ (__builtin_amdgcn_mbcnt_lo(~0u, 0u) & (uint32_t)(n_pad >> 62));
   double xp[P], N[P], D[P], A[P];
   float xh[P], xl[P];
-  bool bad[P];
+  bool bad[P], dom[P];
 #pragma unroll
   for (int j = 0; j < P; ++j) {
     const int64_t idx = base + j * kStage;
@@ -66,35 +76,79 @@ __global__ void __launch_bounds__(kStage)
     xh[j] = (float)xp[j];
     xl[j] = (float)(xp[j] - (double)xh[j]);
     N[j] = D[j] = A[j] = 0.0;
-    bad[j] = !in_split_domain(xp[j], x_first, x_last);
+    dom[j] = !in_split_domain(xp[j], x_first, x_last);
+    bad[j] = dom[j];
   }
 
+  if (__builtin_amdgcn_readfirstlane(scale[3]) != 0) {
+    // a table too ill-conditioned for binary32 terms (status word 4, written
+    // by the packing): binary64 terms for every point, block-uniformly
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      const int64_t idx = base + j * kStage;
+      if (idx >= m) continue;
+      PointRLF e = eval_point_f64<R, L>(xp[j], tx, tw, twf, n_pad);
+      if (e.flagged) {
+        const PointRL ex = eval_point_exact<R, L>(xp[j], tx, tw, f, n);
+        e.r = ex.r;
+        e.l = ex.l;
+      }
+      if (R) r[idx] = e.r;
+      if (L) lam[idx] = e.l;
+    }
+    return;
+  }
+
+  // the Lebesgue sum is always accumulated: the conditioning guard needs it
   bool blocks = false;
   if constexpr (B) {
     blocks = __builtin_amdgcn_readfirstlane(*alt) != 0;
-    if (blocks) split_block_sums<P, R, L, G, true>(stage, s4, n_pad, mask, xh, xl, N, D, A, bad);
+    if (blocks)
+      split_block_sums<P, R, true, G, true>(stage, s4, n_pad, mask, xh, xl, N, D, A, bad);
   }
-  if (!blocks) split_block_sums<P, R, L, G>(stage, s4, n_pad, mask, xh, xl, N, D, A, bad);
+  if (!blocks) split_block_sums<P, R, true, G>(stage, s4, n_pad, mask, xh, xl, N, D, A, bad);
   const int shift = scale[1];
 
+  // Three groups of points, in this order so that little stays live across
+  // the slower paths: points whose binary32 terms pass the guard; points
+  // for binary64 terms (outside the binary32 domain, or flagged by the
+  // guard); points whose binary32 sums are not finite (an exact hit, a NaN
+  // point, a difference too small for binary32) or that the binary64 sums
+  // flag too, which take the exact branch at once (its binary search finds
+  // a hit without a pass over the nodes).
+  bool wide64[P];
 #pragma unroll
   for (int j = 0; j < P; ++j) {
     const int64_t idx = base + j * kStage;
-    if (idx >= m) continue;
-    double rv, lv;
-    if (bad[j]) {
-      const PointRL e = eval_point_exact<R, L>(xp[j], tx, tw, f, n);
-      rv = e.r;
-      lv = e.l;
-    } else {
-      double a = A[j];
-      if constexpr (B && L)
-        if (blocks) a = split_tile_fix<G>(xp[j], xh[j], xl[j], tx, n, s4, n_pad, mask, a);
-      rv = ldexp(N[j] / D[j], shift);
-      lv = a / fabs(D[j]);
+    wide64[j] = dom[j];
+    if (idx >= m || bad[j]) continue;
+    double a = A[j];
+    if constexpr (B)
+      if (blocks) a = split_tile_fix<G>(xp[j], xh[j], xl[j], tx, n, s4, n_pad, mask, a);
+    if (!(a <= kSplitLambdaGuard * fabs(D[j]))) {
+      bad[j] = wide64[j] = true;
+      continue;
     }
-    if (R) r[idx] = rv;
-    if (L) lam[idx] = lv;
+    if (R) r[idx] = ldexp(N[j] / D[j], shift);
+    if (L) lam[idx] = a / fabs(D[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const int64_t idx = base + j * kStage;
+    if (idx >= m || !wide64[j]) continue;
+    const PointRLF e = eval_point_f64<R, L>(xp[j], tx, tw, twf, n_pad);
+    if (e.flagged) continue;
+    bad[j] = false;
+    if (R) r[idx] = e.r;
+    if (L) lam[idx] = e.l;
+  }
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const int64_t idx = base + j * kStage;
+    if (idx >= m || !bad[j]) continue;
+    const PointRL ex = eval_point_exact<R, L>(xp[j], tx, tw, f, n);
+    if (R) r[idx] = ex.r;
+    if (L) lam[idx] = ex.l;
   }
 }
 
@@ -105,14 +159,14 @@ static hipError_t launch_v(const double* x, int64_t m, const NodeTable& t, int64
   const int64_t per = (int64_t)kStage * P;
   const dim3 grid((unsigned)((m + per - 1) / per)), block(kStage);
   if (r && lam)
-    k_eval_split<P, G, true, true, B><<<grid, block, 0, s>>>(x, m, t.s, t.n_pad, t.x, t.w, t.f,
-                                                             n, sc, alt, r, lam);
+    k_eval_split<P, G, true, true, B><<<grid, block, 0, s>>>(x, m, t.s, t.n_pad, t.x, t.w, t.wf,
+                                                             t.f, n, sc, alt, r, lam);
   else if (r)
-    k_eval_split<P, G, true, false, B><<<grid, block, 0, s>>>(x, m, t.s, t.n_pad, t.x, t.w, t.f,
-                                                              n, sc, alt, r, lam);
+    k_eval_split<P, G, true, false, B><<<grid, block, 0, s>>>(x, m, t.s, t.n_pad, t.x, t.w, t.wf,
+                                                              t.f, n, sc, alt, r, lam);
   else
-    k_eval_split<P, G, false, true, B><<<grid, block, 0, s>>>(x, m, t.s, t.n_pad, t.x, t.w, t.f,
-                                                              n, sc, alt, r, lam);
+    k_eval_split<P, G, false, true, B><<<grid, block, 0, s>>>(x, m, t.s, t.n_pad, t.x, t.w, t.wf,
+                                                              t.f, n, sc, alt, r, lam);
   return hipGetLastError();
 }
 

@@ -17,7 +17,9 @@ namespace fhk {
 // the weighted values w f (split_table_scale), word 3 = 1 if the node
 // table's weights alternate strictly in sign (always for the library's
 // weights; caller weights are checked pair by pair), written by every
-// packing; words 4.. reserved.
+// packing; word 4 = 1 if a split table is too ill-conditioned for binary32
+// terms (split_table_wide, written by the split packing); words 5..
+// reserved.
 constexpr size_t kStatusBytes = 256;
 // Node tables are padded to a multiple of this many records; padding
 // records repeat the last node with zero weight, so they add nothing.

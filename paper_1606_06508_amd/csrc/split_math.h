@@ -12,6 +12,56 @@ namespace fhk {
 
 constexpr int kTile = 32;     // binary32 partial-sum length (nodes)
 constexpr int kStage = 256;   // records per LDS stage (= threads per block)
+// Conditioning guard of the split kernels: a point whose binary32-term
+// Lebesgue function L / |D| exceeds this is recomputed in binary64.  The
+// binary32 sums give |D^ - D| <= c u32 L with c <= 41 (first order), so an
+// unflagged point has a true Lebesgue constant below about 2^16 (where
+// c u32 Lambda <= 0.16 and the first-order split bound holds with a factor
+// of at most 1.2), and a flagged one gets binary64 accuracy.
+constexpr double kSplitLambdaGuard = 0x1p14;
+
+// A pointer argument made provably wave-uniform (it is the same in every
+// lane), so loads through it become scalar loads.
+template <class T>
+__device__ __forceinline__ const T* uniform_ptr(const T* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return reinterpret_cast<const T*>(((uint64_t)hi << 32) | lo);
+}
+
+// Binary64 evaluation of one point over a packed table (records [0, n_pad),
+// n_pad a multiple of 4): the fused sums with groups of four differences per
+// reciprocal and plain sums, the per-pair operations of the binary64 kernel
+// with groups of four, no node split and plain sums (so the same bits;
+// groups of eight would keep the split kernel from fitting eight waves per
+// SIMD).  For the points of the split kernels whose binary32 terms cannot
+// be trusted: all points of a table too ill-conditioned for them, and lanes
+// that their per-point guard flags.  Inline, so that it shares the
+// registers of the binary32 loop that ran before it (an out-of-line call
+// adds its registers to the kernel's); the table is the same for every
+// lane, so its records arrive through scalar loads.  `flagged` is set where
+// the binary64 sums flag too (an exact hit, a NaN or infinite point, a group
+// product out of range): the caller then takes eval_point_exact.
+struct PointRLF {
+  double r, l;
+  bool flagged;
+};
+
+template <bool R, bool L>
+__device__ __forceinline__ PointRLF eval_point_f64(double v, const double* __restrict__ tx,
+                                                   const double* __restrict__ tw,
+                                                   const double* __restrict__ twf,
+                                                   int64_t n_pad) {
+  tx = uniform_ptr(tx);
+  tw = uniform_ptr(tw);
+  twf = uniform_ptr(twf);
+  n_pad = __builtin_amdgcn_readfirstlane((int32_t)n_pad);  // n_pad < 2^31
+  double xp[1] = {v}, N[1] = {0.0}, D[1] = {0.0}, A[1] = {0.0};
+  bool bad[1] = {false};
+  accumulate_f64<1, 4, R, L>(xp, tx, tw, twf, 0, n_pad, N, D, A, bad);
+  return {N[0] / D[0], A[0] / fabs(D[0]), bad[0]};
+}
 
 __device__ __forceinline__ bool not_finite32(float v) {
   return __builtin_amdgcn_classf(v, 0x207);  // NaN or +-inf
@@ -314,6 +364,50 @@ __device__ inline SplitScale split_table_scale(const double* __restrict__ tx,
           red[3][0] >= ldexp(1.0, ef - kWeightRange);
   __syncthreads();  // red may be reused by the caller
   return sc;
+}
+
+// Conditioning of a split table, decided once at packing: Lebesgue function
+// above which a table takes binary64 terms for all its points.  It lies
+// below the per-point guard kSplitLambdaGuard, so that few points of a
+// table that passes are left to that guard.
+constexpr double kSplitWideGuard = 0x1p12;
+constexpr int kWideSamples = 64;
+
+// Block-wide (all threads, blockDim.x == 256, records tx/tw wave-uniform):
+// 1 in every thread if the Lebesgue function of the table of n nodes
+// exceeds kSplitWideGuard (or is not a number) at one of the midpoints of
+// kWideSamples intervals spread over it, else 0 (always 0 for n < 2).  The
+// samples are evaluated in binary64 with groups of four differences per
+// reciprocal; wave w sums the records [w q, (w + 1) q) (q = four-aligned
+// quarter of the table rounded up to 4) and the four partial sums are added
+// in wave order, so the decision depends only on the n real nodes (padding
+// records beyond them add exact zeros): the single and the batched split
+// kernels decide alike.  red: LDS scratch of the caller, free on entry.
+__device__ inline int split_table_wide(const double* __restrict__ tx,
+                                       const double* __restrict__ tw, int64_t n,
+                                       double (*red)[256]) {
+  if (n < 2) return 0;  // n is uniform over the block
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t nr = (n + 3) / 4 * 4, q = ((n + 3) / 4 + 3) / 4 * 4;
+  const int64_t k0 = wave * q < nr ? wave * q : nr, k1 = (wave + 1) * q < nr ? (wave + 1) * q : nr;
+  const int64_t i = ((int64_t)lane * (n - 1)) / kWideSamples;
+  double xp[1] = {tx[i] + 0.5 * (tx[i + 1] - tx[i])}, N[1] = {0.0}, D[1] = {0.0}, A[1] = {0.0};
+  bool bad[1] = {false};
+  accumulate_f64<1, 4, false, true>(xp, tx, tw, tw, k0, k1, N, D, A, bad);
+  red[0][threadIdx.x] = D[0];
+  red[1][threadIdx.x] = A[0];
+  __syncthreads();
+  int wide = 0;
+  if (wave == 0) {
+    double ds = red[0][lane], as = red[1][lane];
+    for (int w = 1; w < 4; ++w) {
+      ds += red[0][w * 64 + lane];
+      as += red[1][w * 64 + lane];
+    }
+    wide = !(as <= kSplitWideGuard * fabs(ds));
+  }
+  return __syncthreads_or(wide);
 }
 
 __device__ inline float4 split_record(double xk, double w, double wf, const SplitScale& sc) {

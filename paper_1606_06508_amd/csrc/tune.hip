@@ -68,7 +68,7 @@ constexpr Builtin kBuiltin[] = {
     {FH_FP32_SPLIT, 6, 14, 4},  {FH_FP32_SPLIT, 10, 20, 9}, {FH_FP32_SPLIT, 12, 20, 9},
     {FH_FP32_SPLIT, 13, 20, 9}, {FH_FP32_SPLIT, 13, 24, 9},
     // the 4096-instance batch (mean n 1041, 2.04e8 points)
-    {FH_TUNE_BATCHED_FP64, 11, 28, 2}, {FH_TUNE_BATCHED_SPLIT, 11, 28, 6},
+    {FH_TUNE_BATCHED_FP64, 11, 28, 2}, {FH_TUNE_BATCHED_SPLIT, 11, 28, 5},
 };
 
 // Untuned shapes: two points per lane with the node range split over the

@@ -121,7 +121,8 @@ __global__ void __launch_bounds__(256) k_pack_many(const double* __restrict__ x,
 // Split (binary32) node table (split_table_scale / split_record).  Every
 // block reduces the whole table itself (n is small next to the evaluation;
 // doing it per block avoids a second pass and any atomics); block 0 stores
-// e and ef - e in status words 1 and 2.
+// e and ef - e in status words 1 and 2 and the table's conditioning flag
+// (split_table_wide) in status word 4.
 __global__ void __launch_bounds__(256) k_pack_split(const double* __restrict__ tx,
                                                     const double* __restrict__ tw,
                                                     const double* __restrict__ twf, int64_t n,
@@ -130,12 +131,18 @@ __global__ void __launch_bounds__(256) k_pack_split(const double* __restrict__ t
   __shared__ double red[4][256];
   const SplitScale sc = split_table_scale(tx, tw, twf, n, n_pad, red);
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    scale_out[0] = sc.e;
-    scale_out[1] = sc.shift;
+  if (k < n_pad)
+    s4[k] = split_record(k < n ? tx[k] : split_pad_x(tx[0], tx[n - 1]), tw[k], twf[k], sc);
+  if (blockIdx.x == 0) {
+    // block 0 also decides whether the table is too ill-conditioned for
+    // binary32 terms (status word 4)
+    const int wide = split_table_wide(tx, tw, n, red);
+    if (threadIdx.x == 0) {
+      scale_out[0] = sc.e;
+      scale_out[1] = sc.shift;
+      scale_out[3] = wide;
+    }
   }
-  if (k >= n_pad) return;
-  s4[k] = split_record(k < n ? tx[k] : split_pad_x(tx[0], tx[n - 1]), tw[k], twf[k], sc);
 }
 
 size_t layout_tables(void* ws, int64_t n, NodeTable* t) {

@@ -265,12 +265,20 @@ def test_bad_batch_arguments():
         fh.Batch([5], [1], [10], _t(np.linspace(-1, 1, 4)), _t(np.zeros(4)), _t(np.zeros(10)))
 
 
-def test_full_workload_sampled():
-    """All 4096 instances (about 2e8 points) in one launch; 24 seeded
-    instances checked against the oracle on up to 1500 points each."""
+@pytest.mark.parametrize("precision", ["fp64", "split"])
+def test_full_workload_sampled(precision):
+    """All 4096 instances (about 2e8 points) in one launch, in the variant
+    the tuner's table gives that shape; 24 seeded instances checked against
+    the oracle on up to 1500 points each: the first-order bars up to
+    Lambda = 2^40, the Lambda-scaled bars up to 2^48, and how many sampled
+    points lie beyond 2^48 (no correct digits on either side) is bounded --
+    about 6.5 % of the workload's points, by a sample of 60 instances.  The
+    split kernel's conditioning guard sends every point it cannot trust to
+    binary64, so both precisions are held to the same bands."""
     c = inputs.batched_workload()
-    b, (r, lam) = _batch(c)
+    b, (r, lam) = _batch(c, precision)
     g = np.random.default_rng(9)
+    counts = {"n": 0, "n_beyond_lam_max": 0, "n_lambda_scaled": 0, "n_beyond_lam_cap": 0}
     for i in g.choice(c["n"].size, 24, replace=False):
         ns, ps = _slices(c, i)
         sel = np.arange(ps.start, ps.stop)
@@ -278,6 +286,57 @@ def test_full_workload_sampled():
         r_o, lam_o, s_o = oracle.evaluate(c["nodes"][ns], c["values"][ns], int(c["d"][i]),
                                           c["points"][sel])
         idx = torch.from_numpy(sel).to(DEV)
-        st = metrics.parity(r[idx].cpu().numpy(), lam[idx].cpu().numpy(), r_o, lam_o, s_o)
-        metrics.check_fp64(st, lam_metric="cond")
+        st = metrics.parity(r[idx].cpu().numpy(), lam[idx].cpu().numpy(), r_o, lam_o, s_o,
+                            metrics.FP64_LAMBDA_MAX if precision == "fp64" else
+                            metrics.SPLIT_LAMBDA_MAX)
+        if precision == "fp64":
+            metrics.check_fp64(st, lam_metric="cond")
+        else:
+            metrics.check_split(st)
+        counts["n"] += sel.size
+        for k in ("n_beyond_lam_max", "n_lambda_scaled", "n_beyond_lam_cap"):
+            counts[k] += st[k]
+    b.close()
+    assert counts["n_lambda_scaled"] > 0, counts          # the scaled band was exercised
+    assert counts["n_beyond_lam_cap"] <= 0.12 * counts["n"], counts
+
+
+@pytest.mark.parametrize("lebesgue", [True, False])
+def test_split_batch_ill_conditioned_instances(lebesgue):
+    """A split batch mixing instances too ill-conditioned for binary32 terms
+    (Chebyshev nodes with d = 8..10: Lebesgue functions up to 1e18) with
+    well-conditioned ones: the packing marks the former, whose points then
+    all take binary64 terms (the bits of binary64 launch variant 0), while
+    the others stay on the binary32 path; every instance within the split
+    bar's bands."""
+    g = np.random.default_rng(31)
+    specs = [(inputs.cheb2(600), 10), (inputs.equispaced(300), 3), (inputs.cheb2(1000), 8),
+             (inputs.jittered_nodes(513, g), 4), (inputs.cheb2(129), 9)]
+    vals = [g.standard_normal(x.size) for x, _ in specs]
+    pts = [g.uniform(-1, 1, 3000 + 17 * i) for i in range(len(specs))]
+    c = {"n": np.array([x.size for x, _ in specs]), "d": np.array([d for _, d in specs], np.int32),
+         "m": np.array([p.size for p in pts]), "nodes": np.concatenate([x for x, _ in specs]),
+         "values": np.concatenate(vals), "points": np.concatenate(pts)}
+    c["node_off"] = np.concatenate([[0], np.cumsum(c["n"])])
+    c["pt_off"] = np.concatenate([[0], np.cumsum(c["m"])])
+    b, out = _batch(c, "split", lebesgue=lebesgue)
+    r, lam = out if lebesgue else (out, None)
+    r = r.cpu().numpy()
+    fh.tune_force("fp64", 0)
+    try:
+        for i, (x, d) in enumerate(specs):
+            ns, ps = _slices(c, i)
+            o = fh.evaluate(_t(x), _t(vals[i]), d, _t(pts[i]), lebesgue=lebesgue)
+            r64 = (o[0] if lebesgue else o).cpu().numpy()
+            r_o, lam_o, s_o = oracle.evaluate(x, vals[i], d, pts[i])
+            st = metrics.parity(r[ps], lam[ps].cpu().numpy() if lebesgue else None, r_o, lam_o,
+                                s_o, metrics.SPLIT_LAMBDA_MAX)
+            assert st["nan_mismatch_r"] == 0 and st["e_cond_max"] <= metrics.SPLIT_TOL, (i, st)
+            assert st["e_cond_scaled_max"] <= metrics.SPLIT_TOL, (i, st)
+            if np.max(lam_o) > 2.0 ** 20:          # ill-conditioned: binary64 for all points
+                assert np.array_equal(r[ps].view(np.int64), r64.view(np.int64)), i
+            elif np.max(lam_o) < 2.0 ** 8:         # well-conditioned: binary32 terms
+                assert not np.array_equal(r[ps], r64), i
+    finally:
+        fh.tune_force("fp64", -1)
     b.close()

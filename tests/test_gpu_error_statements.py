@@ -76,6 +76,6 @@ def test_split_first_order_bound(n, d):
             r, lam = _run(nodes, vals, d, pts, "split")
         finally:
             fh.tune_force("split", -1)
-        st = metrics.parity(r, lam, r_o, lam_o, s_o, metrics.SPLIT_LAMBDA_MAX)
+        st = metrics.parity(r, lam, r_o, lam_o, s_o, metrics.SPLIT_TERMS_LAMBDA_MAX)
         bound = 44 * U32
         assert st["e_cond_max"] <= bound and st["e_cond_lam_max"] <= bound, (vid, grp, st)

@@ -60,8 +60,13 @@ def test_weights_bitwise(family, n, d):
 
 # ---------------------------------------------------------- workloads --
 def test_runge_full():
+    """The Runge workload in full: besides the bars, plain relative error
+    e_rel(r) <= 1e-13 at every point, without the conditioning filter (its
+    r = 1/(1+25x^2) stays away from zero)."""
     c = inputs.runge()
-    _check_case(c["nodes"], c["values"], c["d"], c["points"])
+    st = _check_case(c["nodes"], c["values"], c["d"], c["points"])
+    assert st["e_rel_max"] <= metrics.FP64_TOL, st
+    assert st["n_beyond_lam_max"] == 0 and st["nan_mismatch_r"] == 0, st
 
 
 @pytest.mark.parametrize("d", list(range(9)))

@@ -190,3 +190,84 @@ def test_hits_and_close_points_at_both_ends():
             metrics.check_split(metrics.parity(r, lam, r_o, lam_o, s_o, metrics.SPLIT_LAMBDA_MAX))
     finally:
         fh.tune_force("split", -1)
+
+
+def _split_and_f64(nodes, vals, d, pts, vid, lebesgue):
+    """Split outputs with split launch variant vid, and binary64 launch
+    variant 0 (one point per lane, groups of four, no node split, plain
+    sums: the operations the split kernels use wherever they take binary64
+    terms)."""
+    fh.tune_force("split", vid)
+    try:
+        out = fh.evaluate(_t(nodes), _t(vals), d, _t(pts), lebesgue=lebesgue, precision="split")
+    finally:
+        fh.tune_force("split", -1)
+    fh.tune_force("fp64", 0)
+    try:
+        out64 = fh.evaluate(_t(nodes), _t(vals), d, _t(pts), lebesgue=lebesgue)
+    finally:
+        fh.tune_force("fp64", -1)
+    torch.cuda.synchronize()
+    r, lam = out if lebesgue else (out, None)
+    r64, lam64 = out64 if lebesgue else (out64, None)
+    np_ = (lambda t: None if t is None else t.cpu().numpy())
+    return np_(r), np_(lam), np_(r64), np_(lam64)
+
+
+def _bands(r, lam, r_o, lam_o, s_o):
+    st = metrics.parity(r, lam, r_o, lam_o, s_o, metrics.SPLIT_LAMBDA_MAX)
+    assert st["nan_mismatch_r"] == 0, st
+    for k in ("e_cond_max", "e_cond_scaled_max", "e_cond_lam_max", "e_cond_lam_scaled_max"):
+        assert st.get(k, 0.0) <= metrics.SPLIT_TOL, (k, st)
+    return st
+
+
+@pytest.mark.parametrize("n,d,vid", [(600, 8, 9), (1200, 10, 9), (300, 6, 5), (257, 9, 10)])
+@pytest.mark.parametrize("lebesgue", [True, False])
+def test_ill_conditioned_table_takes_binary64_terms(n, d, vid, lebesgue):
+    """Chebyshev nodes with large d have Lebesgue functions far beyond what
+    binary32 terms resolve (up to 1e18 here).  The packing samples the
+    table's Lebesgue function and marks it: every point then takes binary64
+    terms, so every point meets the split bar's bands (first order to 2^40,
+    Lambda-scaled to 2^48) and carries the bits of binary64 launch variant 0,
+    with and without Lambda requested."""
+    g = np.random.default_rng(n + d)
+    nodes = inputs.cheb2(n)
+    vals = g.standard_normal(n)
+    pts = np.concatenate([g.uniform(-1, 1, 20000), -1 + 1e-4 * g.uniform(0, 1, 500),
+                          1 - 1e-4 * g.uniform(0, 1, 500), nodes[::7]])
+    r, lam, r64, lam64 = _split_and_f64(nodes, vals, d, pts, vid, lebesgue)
+    r_o, lam_o, s_o = oracle.evaluate(nodes, vals, d, pts)
+    assert np.max(lam_o) > 2.0 ** 20
+    _bands(r, lam, r_o, lam_o, s_o)
+    assert np.array_equal(r.view(np.int64), r64.view(np.int64))
+    if lebesgue:
+        assert np.array_equal(lam.view(np.int64), lam64.view(np.int64))
+
+
+@pytest.mark.parametrize("vid", [9, 5, 1])
+@pytest.mark.parametrize("lebesgue", [True, False])
+def test_per_point_conditioning_guard(vid, lebesgue):
+    """A table that passes the packing's sample (equispaced nodes, small d)
+    evaluated both inside its nodes and just outside them, where D cancels
+    and the Lebesgue function grows past 2^14 within one node span: the
+    points whose binary32 terms give Lambda above 2^14 are recomputed with
+    binary64 terms (those whose true Lambda is beyond 2^17, sure to be
+    flagged, carry the bits of binary64 launch variant 0), the others stay on
+    the binary32 path; every point within the split bar's bands."""
+    g = np.random.default_rng(vid)
+    n, d = 257, 4
+    nodes = inputs.equispaced(n)
+    vals = np.sin(3 * nodes) + 0.1 * g.standard_normal(n)
+    pts = np.concatenate([g.uniform(-1, 1, 8000), 1 + 2 * g.uniform(0, 1, 4000),
+                          -1 - 2 * g.uniform(0, 1, 4000)])
+    r, lam, r64, lam64 = _split_and_f64(nodes, vals, d, pts, vid, lebesgue)
+    r_o, lam_o, s_o = oracle.evaluate(nodes, vals, d, pts)
+    _bands(r, lam, r_o, lam_o, s_o)
+    sure = lam_o > 2.0 ** 17
+    assert np.count_nonzero(sure) > 100, np.count_nonzero(sure)   # the guard was exercised
+    assert np.array_equal(r[sure].view(np.int64), r64[sure].view(np.int64))
+    if lebesgue:
+        assert np.array_equal(lam[sure].view(np.int64), lam64[sure].view(np.int64))
+    calm = lam_o < 2.0 ** 8
+    assert np.max(np.abs(r[calm] - r_o[calm]) / s_o[calm]) > metrics.FP64_TOL
