@@ -20,13 +20,17 @@ Also reported in the same JSON line:
                 algorithmic flops per pair;
   cpu_baseline  the FP64 oracle on the host cores, on a bounded sample;
   max_error     parity of the timed outputs against the oracle on the sample;
-  forms         the other forms of the path on their own workloads: FP64 vs
-                FP32-split on the 4097-node, 10^7-point clustered workload;
-                the batched graph launch over 4096 uneven interpolants vs a
-                per-instance fh_eval loop; the adjoint and the derivative
+  forms         the other forms of the path on their own workloads: the
+                launch-bound 21-node Runge case; FP64 vs FP32-split on the
+                4097-node, 10^7-point clustered workload; the batched graph
+                launch over 4096 uneven interpolants (in the launch variant
+                the autotuner picks for it, live) vs a per-instance fh_eval
+                loop; the adjoint and the derivative
                 r' on 2049 nodes and 10^6 points; normalization of 10^8
                 vectors; Lebesgue constants of a node-family table; several
                 interpolants on the same nodes and points in one launch.
+                Each form with the CPU leg reports the oracle's rate on a
+                bounded sample beside its own.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -223,6 +227,35 @@ def launch_overheads(dev, reps=200):
                    f"{reps} times back to back; mean per launch"}
 
 
+def run_runge_form(dev, reps, with_cpu):
+    """The Runge workload (n = 21 equispaced nodes, d = 3, 10 021 points):
+    one fh_eval call (weights, packing and the fused r + Lambda evaluation)
+    is launch-bound -- a few microseconds of work behind two launches --
+    so it is reported per call next to the empty-launch time; with_cpu adds
+    the oracle's rate on the whole workload and its max error."""
+    c = inputs.runge()
+    n, m = c["nodes"].size, c["points"].size
+    nodes, vals, x = _t(c["nodes"], dev), _t(c["values"], dev), _t(c["points"], dev)
+    ws = fh.Workspace(dev, fh.workspace_size(fh.FH_OP_EVAL, n, m, c["d"]))
+    r = torch.empty_like(x)
+    lam = torch.empty_like(x)
+    ms = _time_ms(lambda: fh.evaluate(nodes, vals, c["d"], x, lebesgue=True, out=r,
+                                      lambda_out=lam, ws=ws), max(reps, 200))
+    out = {"workload": f"runge: n={n} equispaced, d={c['d']}, f=1/(1+25x^2), m={m}",
+           "us_per_call": ms * 1e3, "Gpair_s": n * m / (ms * 1e-3) / 1e9}
+    if with_cpu:
+        from oracle import metrics, oracle
+        t0 = time.perf_counter()
+        for _ in range(20):
+            r_o, lam_o, s_o = oracle.evaluate(c["nodes"], c["values"], c["d"], c["points"])
+        dt = (time.perf_counter() - t0) / 20
+        out["cpu_oracle"] = {"us_per_call": dt * 1e6, "Gpair_s": n * m / dt / 1e9,
+                             "cores": oracle.threads(), "sample": "the whole workload"}
+        st = metrics.parity(r.cpu().numpy(), lam.cpu().numpy(), r_o, lam_o, s_o)
+        out["max_error"] = {k: v for k, v in st.items() if k.startswith("e_")}
+    return out
+
+
 def run_split_forms(dev, reps, with_cpu):
     """FP64 vs FP32-split on the clustered 4097-node, 10^7-point workload
     (eval kernel only, node table prepared once)."""
@@ -242,14 +275,18 @@ def run_split_forms(dev, reps, with_cpu):
     if with_cpu:
         from oracle import metrics, oracle
         idx = np.random.default_rng(0).choice(m, 4000, replace=False)
+        t0 = time.perf_counter()
         r_o, lam_o, s_o = oracle.evaluate(c["nodes"], c["values"], c["d"], c["points"][idx])
+        dt = time.perf_counter() - t0
+        out["cpu_oracle"] = {"Gpair_s": n * idx.size / dt / 1e9, "cores": oracle.threads(),
+                             "sample": f"{idx.size} seeded points of the workload, r and Lambda"}
         for prec in ("fp64", "split"):
             r, lam = res[prec]
             st = metrics.parity(r.cpu().numpy()[idx], lam.cpu().numpy()[idx], r_o, lam_o, s_o,
                                 metrics.FP64_LAMBDA_MAX if prec == "fp64"
                                 else metrics.SPLIT_LAMBDA_MAX)
             out[prec]["max_error_sample4000"] = {k: v for k, v in st.items()
-                                                 if k.startswith(("e_", "n_beyond"))}
+                                                 if k.startswith(("e_", "n_"))}
     out["workload"] = f"split: n={n} jittered, d={c['d']}, m={m} (10% within 1e-8 of a node)"
     return out
 
@@ -310,24 +347,31 @@ def run_batched_form(dev, reps, with_cpu, tune=True):
         if tuned is not None:
             out[prec]["variant"]["tuner_ms_by_variant"] = {
                 k: round(v, 3) for k, v in sorted(tuned["all_ms"].items(), key=lambda t: t[1])}
-        if with_cpu and prec == "fp64":
+        if with_cpu:
             from oracle import metrics, oracle
             g = np.random.default_rng(1)
-            worst = {}
+            worst, pairs_o, secs_o = {}, 0.0, 0.0
             for i in g.choice(n.size, 12, replace=False):
                 ns = slice(int(c["node_off"][i]), int(c["node_off"][i + 1]))
                 p0, p1 = int(c["pt_off"][i]), int(c["pt_off"][i + 1])
                 sel = np.arange(p0, p1)[g.choice(p1 - p0, min(1000, p1 - p0), replace=False)]
+                t0 = time.perf_counter()
                 r_o, lam_o, s_o = oracle.evaluate(c["nodes"][ns], c["values"][ns], int(d[i]),
                                                   c["points"][sel], lebesgue=True)
+                secs_o += time.perf_counter() - t0
+                pairs_o += float(n[i]) * sel.size
                 st = metrics.parity(b.r[torch.from_numpy(sel).to(dev)].cpu().numpy(), None, r_o,
                                     lam_o, s_o)
                 for k, v in st.items():
                     if k.startswith("e_"):
                         worst[k] = max(worst.get(k, 0.0), v)
-                    elif k == "n_beyond_lam_max":
+                    elif k.startswith("n_"):
                         worst[k] = worst.get(k, 0) + v
+            worst["n_points"] = 12000 if n.size >= 12 else None
             out[prec]["max_error_12_instances"] = worst
+            if prec == "fp64":
+                out["cpu_oracle"] = {"Gpair_s": pairs_o / secs_o / 1e9, "cores": oracle.threads(),
+                                     "sample": "up to 1000 seeded points of 12 seeded instances"}
         b.close()
         # the same batch with the Lebesgue function as well
         b = fh.Batch(n, d, m, nodes, vals, x, precision=prec, lebesgue=True)
@@ -364,7 +408,11 @@ def run_backward_form(dev, reps, with_cpu):
     ref = None
     if with_cpu:
         from oracle import oracle
+        t0 = time.perf_counter()
         o = oracle.backward(c["nodes"], c["values"], c["d"], c["points"], c["grad"])
+        dt = time.perf_counter() - t0
+        out["cpu_oracle"] = {"backward_Gpair_s": n * m / dt / 1e9, "backward_s": dt,
+                             "cores": oracle.threads(), "sample": "the whole workload (all gradients)"}
         sc = oracle.grad_scales(c["nodes"], c["values"], c["d"], c["points"], c["grad"])
         ref = ((o["d_values"], sc[0]), (o["d_points"], sc[1]), (o["d_nodes"], sc[2]))
         _, dr_o, s_o = oracle.eval_deriv(c["nodes"], c["values"], c["d"], c["points"])
@@ -463,7 +511,8 @@ def run_lebesgue_form(dev, reps, with_cpu):
     ms = _time_ms(step, reps)
     out = {"workload": f"lebesgue: {len(table)} (family, n, d) node sets, n in 65..4097, "
                        f"d in 0..10, {S} samples x {R} rounds per interval",
-           "ms_per_table": ms, "Gpair_s": pairs / (ms * 1e-3) / 1e9, "pairs": pairs}
+           "ms_all_tables": ms, "ms_per_table_mean": ms / len(table),
+           "Gpair_s": pairs / (ms * 1e-3) / 1e9, "pairs": pairs}
     big = max(range(len(table)), key=lambda i: (table[i]["n"], table[i]["d"] == 3))
     cb = table[big]
     pb = float((cb["n"] - 1) * cb["n"]) * S * R
@@ -601,7 +650,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (the reference dispatch that "
                          "scales the HBM byte counters)")
-    ap.add_argument("--profile-form", choices=("split", "batched", "grad", "normalize",
+    ap.add_argument("--profile-form", choices=("runge", "split", "batched", "grad", "normalize",
                                                "lebesgue", "multi"),
                     help="only run one secondary form's timed loops (--steps repetitions, "
                          "no CPU work), for kernel profiles")
@@ -611,7 +660,7 @@ def main():
         return
     if args.profile_form:
         dev = torch.device("cuda:0")
-        run = {"split": run_split_forms,
+        run = {"runge": run_runge_form, "split": run_split_forms,
                "batched": lambda dev, reps, cpu: run_batched_form(dev, reps, cpu, tune=False),
                "grad": run_backward_form, "normalize": run_normalize_form,
                "lebesgue": run_lebesgue_form, "multi": run_multi_form}[args.profile_form]
@@ -659,7 +708,9 @@ def main():
         print("[bench] cpu baseline done", file=sys.stderr, flush=True)
     line["launch_overheads"] = launch_overheads(dev)
     if not args.no_forms:
-        forms = {"split_workload": run_split_forms(dev, 5, not args.no_cpu_baseline)}
+        forms = {"runge": run_runge_form(dev, 200, not args.no_cpu_baseline)}
+        print("[bench] runge form done", file=sys.stderr, flush=True)
+        forms["split_workload"] = run_split_forms(dev, 5, not args.no_cpu_baseline)
         print("[bench] split form done", file=sys.stderr, flush=True)
         forms["batched_workload"] = run_batched_form(dev, 3, not args.no_cpu_baseline,
                                                      tune=not args.no_tune)
