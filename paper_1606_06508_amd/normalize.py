@@ -34,12 +34,21 @@ def normalize(x, *, method="scaling", layout="aos", lengths=True, directions=Tru
     if dim not in (2, 3, 4):
         raise ValueError("vectors must have 2, 3 or 4 entries")
     x = x.contiguous()
+
+    def _out(t, shape, name):
+        if t.dtype != x.dtype or t.device != x.device or tuple(t.shape) != tuple(shape) or \
+                not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {x.dtype} tensor of shape "
+                             f"{tuple(shape)} on {x.device}")
+        return t
+
     r = None
     if lengths:
-        r = torch.empty(n, dtype=x.dtype, device=x.device) if r_out is None else r_out
+        r = torch.empty(n, dtype=x.dtype, device=x.device) if r_out is None else \
+            _out(r_out, (n,), "r_out")
     xh = None
     if directions:
-        xh = torch.empty_like(x) if dir_out is None else dir_out
+        xh = torch.empty_like(x) if dir_out is None else _out(dir_out, x.shape, "dir_out")
     sfx = "f32" if x.dtype == torch.float32 else "f64"
     fn = getattr(lib, f"nrm_normalize{dim}_{sfx}")
     st = fn(x.data_ptr(), n, 0 if r is None else r.data_ptr(), 0 if xh is None else xh.data_ptr(),
