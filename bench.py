@@ -420,10 +420,16 @@ def run_backward_form(dev, reps, with_cpu):
         ws = fh.Workspace(dev, fh.workspace_size(fh.FH_OP_BACKWARD, n, m, c["d"], prec))
         ms_b = _time_ms(lambda: fh.eval_backward(nodes, vals, c["d"], x, g, precision=prec,
                                                  ws=ws), reps)
+        # only some gradients: the passes and sums they need
+        ms_bv = _time_ms(lambda: fh.eval_backward(nodes, vals, c["d"], x, g, need_x=False,
+                                                  need_nodes=False, precision=prec, ws=ws), reps)
+        ms_bx = _time_ms(lambda: fh.eval_backward(nodes, vals, c["d"], x, g, need_values=False,
+                                                  need_nodes=False, precision=prec, ws=ws), reps)
         ms_f = _time_ms(lambda: fh.evaluate(nodes, vals, c["d"], x, precision=prec, ws=ws), reps)
         ms_d = _time_ms(lambda: fh.eval_deriv(nodes, vals, c["d"], x, precision=prec, ws=ws),
                         reps)
         out[prec] = {"backward_ms": ms_b, "forward_ms": ms_f, "deriv_ms": ms_d,
+                     "backward_values_only_ms": ms_bv, "backward_points_only_ms": ms_bx,
                      "backward_Gpair_s": n * m / (ms_b * 1e-3) / 1e9,
                      "forward_Gpair_s": n * m / (ms_f * 1e-3) / 1e9,
                      "deriv_Gpair_s": n * m / (ms_d * 1e-3) / 1e9}

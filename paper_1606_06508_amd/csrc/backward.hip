@@ -43,8 +43,9 @@ namespace fhk {
 // ---------------------------------------------------------------- pass 1 --
 // DERIV: the derivative r'(x) = (r E - F) / D of the interpolant (dL/dx_p
 // with g_p = 1; the node formula at hits) is written to dx and r to r_out;
-// g, the records and the padding are not used (m_pad = m).
-template <int P, bool DERIV>
+// g, the records and the padding are not used (m_pad = m).  EF: E and F are
+// summed (for dx; without them pass 1 writes only the records).
+template <int P, bool DERIV, bool EF>
 __global__ void __launch_bounds__(256)
     k_bwd_points(const double* __restrict__ x, const double* __restrict__ g, int64_t m,
                  int64_t m_pad, const double* __restrict__ tx, const double* __restrict__ tw,
@@ -83,9 +84,11 @@ __global__ void __launch_bounds__(256)
       for (int i = 0; i < 8; ++i) {
         D[j] = __builtin_fma(wk[i], t[i], D[j]);
         N[j] = __builtin_fma(vk[i], t[i], N[j]);
-        const double t2 = t[i] * t[i];
-        E[j] = __builtin_fma(wk[i], t2, E[j]);
-        F[j] = __builtin_fma(vk[i], t2, F[j]);
+        if constexpr (EF) {
+          const double t2 = t[i] * t[i];
+          E[j] = __builtin_fma(wk[i], t2, E[j]);
+          F[j] = __builtin_fma(vk[i], t2, F[j]);
+        }
       }
     }
   }
@@ -111,12 +114,12 @@ __global__ void __launch_bounds__(256)
       rv = N[j] / D[j];
       c = gp / D[j];
       cr = c * rv;
-      dxp = c * (rv * E[j] - F[j]);
+      dxp = EF ? c * (rv * E[j] - F[j]) : 0.0;
     } else {
       // pair-by-pair: exact hit or extreme range
       bwd_point_exact(t, gp, tx, tw, tf, n, &dxp, &c, &cr, &hg, &hgr, &rv);
     }
-    if (dx) dx[idx] = dxp;
+    if (EF && dx) dx[idx] = dxp;
     if (DERIV) {
       if (r_out) r_out[idx] = rv;
     } else {
@@ -128,8 +131,10 @@ __global__ void __launch_bounds__(256)
 // ---------------------------------------------------------------- pass 2 --
 // grid: x = node tiles of 64*Q nodes, y = groups of four chunks of `chunk`
 // points (chunk a multiple of G); wave w of the block takes chunk
-// 4*blockIdx.y + w.  Reciprocals are taken G points at a time.
-template <int Q, int G>
+// 4*blockIdx.y + w.  Reciprocals are taken G points at a time.  FULL: all
+// four sums and both hit sums (the node gradient needs them); otherwise S1
+// and H1 only (dL/df), the others written as zeros.
+template <int Q, int G, bool FULL>
 __global__ void __launch_bounds__(256)
     k_bwd_nodes(PointRecs rec, int64_t chunk, int64_t chunks,
                 const double* __restrict__ tx, int64_t n_pad, double* __restrict__ part) {
@@ -154,7 +159,7 @@ __global__ void __launch_bounds__(256)
     for (int i = 0; i < G; ++i) {
       px[i] = rx[p + i];
       pc[i] = rc[p + i];
-      pcr[i] = rcr[p + i];
+      pcr[i] = FULL ? rcr[p + i] : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -165,16 +170,19 @@ __global__ void __launch_bounds__(256)
       if (!bad) {
 #pragma unroll
         for (int i = 0; i < G; ++i) {
-          const double t2 = t[i] * t[i];
           S1[q] = __builtin_fma(pc[i], t[i], S1[q]);
-          S2[q] = __builtin_fma(pcr[i], t[i], S2[q]);
-          S3[q] = __builtin_fma(pc[i], t2, S3[q]);
-          S4[q] = __builtin_fma(pcr[i], t2, S4[q]);
+          if constexpr (FULL) {
+            const double t2 = t[i] * t[i];
+            S2[q] = __builtin_fma(pcr[i], t[i], S2[q]);
+            S3[q] = __builtin_fma(pc[i], t2, S3[q]);
+            S4[q] = __builtin_fma(pcr[i], t2, S4[q]);
+          }
         }
       } else {
         // pair by pair: a zero difference is a hit on this node
         for (int i = 0; i < G; ++i)
-          bwd_pair_exact(rec, p0 + p + i, xk[q], S1[q], S2[q], S3[q], S4[q], H1[q], H2[q]);
+          bwd_pair_exact<FULL>(rec, p0 + p + i, xk[q], S1[q], S2[q], S3[q], S4[q], H1[q],
+                               H2[q]);
       }
     }
   }
@@ -297,10 +305,10 @@ static int64_t resident_blocks(const void* kernel) {
 
 static const void* bwd_nodes_kernel(int q, int g) {
   switch (q * 10 + g) {
-    case 14: return reinterpret_cast<const void*>(k_bwd_nodes<1, 4>);
-    case 24: return reinterpret_cast<const void*>(k_bwd_nodes<2, 4>);
-    case 18: return reinterpret_cast<const void*>(k_bwd_nodes<1, 8>);
-    default: return reinterpret_cast<const void*>(k_bwd_nodes<2, 8>);
+    case 14: return reinterpret_cast<const void*>(k_bwd_nodes<1, 4, true>);
+    case 24: return reinterpret_cast<const void*>(k_bwd_nodes<2, 4, true>);
+    case 18: return reinterpret_cast<const void*>(k_bwd_nodes<1, 8, true>);
+    default: return reinterpret_cast<const void*>(k_bwd_nodes<2, 8, true>);
   }
 }
 
@@ -362,33 +370,46 @@ size_t layout_backward(void* ws, int64_t n, int64_t m, bool split, NodeTable* t,
   return off;
 }
 
+template <int P>
+static void launch_bwd_points_p(const BackwardPlan& p, const double* x, const double* g,
+                                int64_t m, const NodeTable& t, int64_t n, double* dx,
+                                const PointRecs& rec, hipStream_t s) {
+  const dim3 grid((unsigned)((p.m_pad + 256 * P - 1) / (256 * P)));
+  if (dx)
+    k_bwd_points<P, false, true><<<grid, 256, 0, s>>>(x, g, m, p.m_pad, t.x, t.w, t.wf, t.f,
+                                                      t.n_pad, n, dx, rec, nullptr);
+  else
+    k_bwd_points<P, false, false><<<grid, 256, 0, s>>>(x, g, m, p.m_pad, t.x, t.w, t.wf, t.f,
+                                                       t.n_pad, n, dx, rec, nullptr);
+}
+
+// dx null: E and F are not summed (the records are all pass 2 needs)
 static hipError_t launch_bwd_points(const BackwardPlan& p, const double* x, const double* g,
                                     int64_t m, const NodeTable& t, int64_t n, double* dx,
                                     const PointRecs& rec, hipStream_t s) {
-  const dim3 grid((unsigned)((p.m_pad + 256 * p.p - 1) / (256 * p.p)));
   switch (p.p) {
-    case 1:
-      k_bwd_points<1, false><<<grid, 256, 0, s>>>(x, g, m, p.m_pad, t.x, t.w, t.wf, t.f, t.n_pad,
-                                                  n, dx, rec, nullptr);
-      break;
-    case 2:
-      k_bwd_points<2, false><<<grid, 256, 0, s>>>(x, g, m, p.m_pad, t.x, t.w, t.wf, t.f, t.n_pad,
-                                                  n, dx, rec, nullptr);
-      break;
+    case 1: launch_bwd_points_p<1>(p, x, g, m, t, n, dx, rec, s); break;
+    case 2: launch_bwd_points_p<2>(p, x, g, m, t, n, dx, rec, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
+// full: all four sums (the node gradient is wanted), else S1 only
 static hipError_t launch_bwd_nodes(const BackwardPlan& p, const PointRecs& rec, const NodeTable& t,
-                                   double* part, hipStream_t s) {
+                                   double* part, bool full, hipStream_t s) {
   const dim3 grid((unsigned)((p.n_pad + 64 * p.q - 1) / (64 * p.q)),
                   (unsigned)((p.chunks + 3) / 4));
   const int v = p.q * 10 + p.g;
   switch (v) {
-#define FH_NODES_CASE(Q, G)                                                                   \
-  case Q * 10 + G:                                                                          \
-    k_bwd_nodes<Q, G><<<grid, 256, 0, s>>>(rec, p.chunk, p.chunks, t.x, t.n_pad, part); \
+#define FH_NODES_CASE(Q, G)                                                                  \
+  case Q * 10 + G:                                                                         \
+    if (full)                                                                              \
+      k_bwd_nodes<Q, G, true><<<grid, 256, 0, s>>>(rec, p.chunk, p.chunks, t.x, t.n_pad,   \
+                                                   part);                                  \
+    else                                                                                   \
+      k_bwd_nodes<Q, G, false><<<grid, 256, 0, s>>>(rec, p.chunk, p.chunks, t.x, t.n_pad,  \
+                                                    part);                                 \
     break;
     FH_NODES_CASE(1, 4)
     FH_NODES_CASE(2, 4)
@@ -406,15 +427,22 @@ hipError_t launch_backward(const double* nodes, const double* x, const double* g
                            hipStream_t s) {
   const BackwardPlan& p = b.plan;
   hipError_t e;
+  // only the passes and sums the requested gradients need: dL/dx_p comes
+  // from pass 1 alone; dL/df needs S1 (and the hit sums); the node gradient
+  // all four sums
+  const bool nodes_pass = df != nullptr || dxn != nullptr, full = dxn != nullptr;
   if (p.split) {
-    e = launch_backward_split_passes(x, g, n, m, t, b, scale_exp, dx, s);
+    e = launch_backward_split_passes(x, g, n, m, t, b, scale_exp, dx, nodes_pass, full, s);
     if (e != hipSuccess) return e;
   } else {
     e = launch_bwd_points(p, x, g, m, t, n, dx, b.rec, s);
     if (e != hipSuccess) return e;
-    e = launch_bwd_nodes(p, b.rec, t, b.part, s);
-    if (e != hipSuccess) return e;
+    if (nodes_pass) {
+      e = launch_bwd_nodes(p, b.rec, t, b.part, full, s);
+      if (e != hipSuccess) return e;
+    }
   }
+  if (!nodes_pass) return hipSuccess;
   const dim3 g3((unsigned)((p.n_pad + 63) / 64), (unsigned)kPartFields);
   k_bwd_reduce<<<g3, 256, 0, s>>>(b.part, p.chunks, p.n_pad, b.sums);
   if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -436,8 +464,8 @@ hipError_t launch_eval_deriv(const double* x, int64_t m, const NodeTable& t, int
   if (m == 0) return hipSuccess;
   constexpr int P = 2;
   const dim3 grid((unsigned)((m + 256 * P - 1) / (256 * P)));
-  k_bwd_points<P, true><<<grid, 256, 0, s>>>(x, nullptr, m, m, t.x, t.w, t.wf, t.f, t.n_pad, n,
-                                             dr, PointRecs{}, r);
+  k_bwd_points<P, true, true><<<grid, 256, 0, s>>>(x, nullptr, m, m, t.x, t.w, t.wf, t.f,
+                                                   t.n_pad, n, dr, PointRecs{}, r);
   return hipGetLastError();
 }
 

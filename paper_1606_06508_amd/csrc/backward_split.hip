@@ -50,8 +50,8 @@ __device__ __forceinline__ bool in_binary32_range(double v) {
 
 // ---------------------------------------------------------------- pass 1 --
 // DERIV: write r (r_out) and the derivative r' (dx) only, as if g_p = 1;
-// no records (m_pad = m).
-template <int P, bool DERIV>
+// no records (m_pad = m).  EF: E and F are summed (for dx).
+template <int P, bool DERIV, bool EF>
 __global__ void __launch_bounds__(kStage)
     k_bwd_points_split(const double* __restrict__ x, const double* __restrict__ g, int64_t m,
                        int64_t m_pad, const float4* __restrict__ s4, int64_t n_pad,
@@ -95,23 +95,28 @@ __global__ void __launch_bounds__(kStage)
         for (int q = 0; q < 4; ++q)
 #pragma unroll
           for (int j = 0; j < P; ++j) {
-            const float t2 = t[q][j] * t[q][j];
             Dt[j] = __builtin_fmaf(rc[q].z, t[q][j], Dt[j]);
             Nt[j] = __builtin_fmaf(rc[q].w, t[q][j], Nt[j]);
-            Et[j] = __builtin_fmaf(rc[q].z, t2, Et[j]);
-            Ft[j] = __builtin_fmaf(rc[q].w, t2, Ft[j]);
+            if constexpr (EF) {
+              const float t2 = t[q][j] * t[q][j];
+              Et[j] = __builtin_fmaf(rc[q].z, t2, Et[j]);
+              Ft[j] = __builtin_fmaf(rc[q].w, t2, Ft[j]);
+            }
           }
       },
       [&](int64_t, int64_t) {
 #pragma unroll
         for (int j = 0; j < P; ++j) {
-          bad[j] |= not_finite32(Dt[j]) | not_finite32(Nt[j]) | not_finite32(Et[j]) |
-                    not_finite32(Ft[j]);
+          bad[j] |= not_finite32(Dt[j]) | not_finite32(Nt[j]);
           D[j] += (double)Dt[j];
           N[j] += (double)Nt[j];
-          E[j] += (double)Et[j];
-          F[j] += (double)Ft[j];
-          Dt[j] = Nt[j] = Et[j] = Ft[j] = 0.0f;
+          Dt[j] = Nt[j] = 0.0f;
+          if constexpr (EF) {
+            bad[j] |= not_finite32(Et[j]) | not_finite32(Ft[j]);
+            E[j] += (double)Et[j];
+            F[j] += (double)Ft[j];
+            Et[j] = Ft[j] = 0.0f;
+          }
         }
       });
 
@@ -131,13 +136,13 @@ __global__ void __launch_bounds__(kStage)
         rv = ldexp(N[j] / D[j], shift);
         c = gp / D[j];  // = 2^e g / D_p
         cr = c * rv;
-        dxp = c * (rv * E[j] - ldexp(F[j], shift));
+        dxp = EF ? c * (rv * E[j] - ldexp(F[j], shift)) : 0.0;
       } else {
         bwd_point_exact(xp[j], gp, tx, tw, tf, n, &dxp, &c, &cr, &hg, &hgr, &rv);
         c = ldexp(c, e);
         cr = ldexp(cr, e);
       }
-      if (dx) dx[idx] = dxp;
+      if (EF && dx) dx[idx] = dxp;
       if (DERIV && r_out) r_out[idx] = rv;
     }
     if (DERIV) continue;
@@ -159,7 +164,9 @@ __global__ void __launch_bounds__(kStage)
 // ---------------------------------------------------------------- pass 2 --
 // grid: x = node tiles of kStage * Q nodes (lane l of the block owns nodes
 // l, l + kStage, ...), y = chunks of `chunk` points (a multiple of kTile).
-template <int Q>
+// FULL: all four sums and both hit sums (the node gradient needs them);
+// otherwise S1 and H1 only (dL/df), the others written as zeros.
+template <int Q, bool FULL>
 __global__ void __launch_bounds__(kStage)
     k_bwd_nodes_split(PointRecs rec, const float4* __restrict__ rec32,
                       int64_t chunk, const double* __restrict__ tx,
@@ -192,11 +199,13 @@ __global__ void __launch_bounds__(kStage)
           for (int q = 0; q < Q; ++q) {
             float t = (rc[i].x - kh[q]) + (rc[i].y - kl[q]);
             t = __builtin_amdgcn_rcpf(t);
-            const float t2 = t * t;
             s1[q] = __builtin_fmaf(rc[i].z, t, s1[q]);
-            s2[q] = __builtin_fmaf(rc[i].w, t, s2[q]);
-            s3[q] = __builtin_fmaf(rc[i].z, t2, s3[q]);
-            s4v[q] = __builtin_fmaf(rc[i].w, t2, s4v[q]);
+            if constexpr (FULL) {
+              const float t2 = t * t;
+              s2[q] = __builtin_fmaf(rc[i].w, t, s2[q]);
+              s3[q] = __builtin_fmaf(rc[i].z, t2, s3[q]);
+              s4v[q] = __builtin_fmaf(rc[i].w, t2, s4v[q]);
+            }
           }
       },
       [&](int64_t b, int64_t end) {
@@ -212,13 +221,15 @@ __global__ void __launch_bounds__(kStage)
                 // binary32 c: the binary32 reciprocal it was computed with
                 if (pc == 0.0 && pcr == 0.0) continue;
                 const double ti = (double)__builtin_amdgcn_rcpf((h.x - kh[q]) + (h.y - kl[q]));
-                const double t2 = ti * ti;
                 S1[q] = __builtin_fma(pc, ti, S1[q]);
-                S2[q] = __builtin_fma(pcr, ti, S2[q]);
-                S3[q] = __builtin_fma(pc, t2, S3[q]);
-                S4[q] = __builtin_fma(pcr, t2, S4[q]);
+                if (FULL) {
+                  const double t2 = ti * ti;
+                  S2[q] = __builtin_fma(pcr, ti, S2[q]);
+                  S3[q] = __builtin_fma(pc, t2, S3[q]);
+                  S4[q] = __builtin_fma(pcr, t2, S4[q]);
+                }
               } else {
-                bwd_pair_exact(rec, pp, xk[q], S1[q], S2[q], S3[q], S4[q], H1[q], H2[q]);
+                bwd_pair_exact<FULL>(rec, pp, xk[q], S1[q], S2[q], S3[q], S4[q], H1[q], H2[q]);
               }
             }
           } else {
@@ -247,26 +258,39 @@ __global__ void __launch_bounds__(kStage)
 
 // ------------------------------------------------------------- launcher --
 const void* bwd_nodes_split_kernel(int q) {
-  return q == 2 ? reinterpret_cast<const void*>(k_bwd_nodes_split<2>)
-                : reinterpret_cast<const void*>(k_bwd_nodes_split<1>);
+  return q == 2 ? reinterpret_cast<const void*>(k_bwd_nodes_split<2, true>)
+                : reinterpret_cast<const void*>(k_bwd_nodes_split<1, true>);
+}
+
+template <int Q, bool FULL>
+static void launch_nodes_split(const BackwardPlan& p, const NodeTable& t, const BackwardBufs& b,
+                               hipStream_t s) {
+  const dim3 g2((unsigned)((p.n_pad + kStage * Q - 1) / (kStage * Q)), (unsigned)p.chunks);
+  k_bwd_nodes_split<Q, FULL><<<g2, kStage, 0, s>>>(b.rec, b.rec32, p.chunk, t.x, t.s, t.n_pad,
+                                                   b.part);
 }
 
 hipError_t launch_backward_split_passes(const double* x, const double* g, int64_t n, int64_t m,
                                         const NodeTable& t, const BackwardBufs& b,
-                                        const int32_t* scale_exp, double* dx, hipStream_t s) {
+                                        const int32_t* scale_exp, double* dx, bool nodes_pass,
+                                        bool full, hipStream_t s) {
   const BackwardPlan& p = b.plan;
   constexpr int P = 1;
   const dim3 g1((unsigned)((p.m_pad + kStage * P - 1) / (kStage * P)));
-  k_bwd_points_split<P, false><<<g1, kStage, 0, s>>>(x, g, m, p.m_pad, t.s, t.n_pad, t.x, t.w,
-                                                     t.f, n, scale_exp, dx, b.rec, b.rec32,
-                                                     nullptr);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const dim3 g2((unsigned)((p.n_pad + kStage * p.q - 1) / (kStage * p.q)), (unsigned)p.chunks);
-  if (p.q == 2)
-    k_bwd_nodes_split<2><<<g2, kStage, 0, s>>>(b.rec, b.rec32, p.chunk, t.x, t.s, t.n_pad, b.part);
+  if (dx)
+    k_bwd_points_split<P, false, true><<<g1, kStage, 0, s>>>(x, g, m, p.m_pad, t.s, t.n_pad, t.x,
+                                                             t.w, t.f, n, scale_exp, dx, b.rec,
+                                                             b.rec32, nullptr);
   else
-    k_bwd_nodes_split<1><<<g2, kStage, 0, s>>>(b.rec, b.rec32, p.chunk, t.x, t.s, t.n_pad, b.part);
+    k_bwd_points_split<P, false, false><<<g1, kStage, 0, s>>>(x, g, m, p.m_pad, t.s, t.n_pad,
+                                                              t.x, t.w, t.f, n, scale_exp, dx,
+                                                              b.rec, b.rec32, nullptr);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !nodes_pass) return e;
+  if (p.q == 2)
+    full ? launch_nodes_split<2, true>(p, t, b, s) : launch_nodes_split<2, false>(p, t, b, s);
+  else
+    full ? launch_nodes_split<1, true>(p, t, b, s) : launch_nodes_split<1, false>(p, t, b, s);
   return hipGetLastError();
 }
 
@@ -275,8 +299,9 @@ hipError_t launch_eval_deriv_split(const double* x, int64_t m, const NodeTable& 
   if (m == 0) return hipSuccess;
   constexpr int P = 1;
   const dim3 grid((unsigned)((m + kStage * P - 1) / (kStage * P)));
-  k_bwd_points_split<P, true><<<grid, kStage, 0, s>>>(x, nullptr, m, m, t.s, t.n_pad, t.x, t.w,
-                                                      t.f, n, scale, dr, PointRecs{}, nullptr, r);
+  k_bwd_points_split<P, true, true><<<grid, kStage, 0, s>>>(x, nullptr, m, m, t.s, t.n_pad, t.x,
+                                                            t.w, t.f, n, scale, dr, PointRecs{},
+                                                            nullptr, r);
   return hipGetLastError();
 }
 

@@ -73,21 +73,25 @@ __device__ inline void bwd_point_exact(double x, double gp, const double* __rest
 }
 
 // One (point p, node xk) pair of the per-node pass by IEEE division; a zero
-// difference is a hit of the point on this node.
+// difference is a hit of the point on this node.  FULL: all sums, else S1
+// and H1 only (the node gradient is not wanted).
+template <bool FULL = true>
 __device__ inline void bwd_pair_exact(const PointRecs& rec, int64_t p, double xk, double& S1,
                                       double& S2, double& S3, double& S4, double& H1,
                                       double& H2) {
   const double dl = rec.x[p] - xk;
   if (dl == 0.0) {
     H1 += rec.hg[p];
-    H2 += rec.hgr[p];
+    if (FULL) H2 += rec.hgr[p];
   } else {
     const double ti = 1.0 / dl;
-    const double t2 = ti * ti;
     S1 = __builtin_fma(rec.c[p], ti, S1);
-    S2 = __builtin_fma(rec.cr[p], ti, S2);
-    S3 = __builtin_fma(rec.c[p], t2, S3);
-    S4 = __builtin_fma(rec.cr[p], t2, S4);
+    if (FULL) {
+      const double t2 = ti * ti;
+      S2 = __builtin_fma(rec.cr[p], ti, S2);
+      S3 = __builtin_fma(rec.c[p], t2, S3);
+      S4 = __builtin_fma(rec.cr[p], t2, S4);
+    }
   }
 }
 

@@ -161,9 +161,12 @@ hipError_t launch_backward(const double* nodes, const double* x, const double* g
                            hipStream_t s);
 // The per-node split kernel for q nodes per lane (occupancy queries).
 const void* bwd_nodes_split_kernel(int q);
+// nodes_pass: run the per-node pass (dL/df or the node gradient wanted);
+// full: all four sums there (the node gradient wanted), else S1 only.
 hipError_t launch_backward_split_passes(const double* x, const double* g, int64_t n, int64_t m,
                                         const NodeTable& t, const BackwardBufs& b,
-                                        const int32_t* scale_exp, double* dx, hipStream_t s);
+                                        const int32_t* scale_exp, double* dx, bool nodes_pass,
+                                        bool full, hipStream_t s);
 // scale: status words 1.. of the workspace (e, ef - e) written by the packing.
 // r and r' at m points from a packed node table (binary64 / split).
 hipError_t launch_eval_deriv(const double* x, int64_t m, const NodeTable& t, int64_t n, double* r,

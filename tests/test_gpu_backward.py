@@ -150,13 +150,26 @@ def test_deterministic():
         assert np.array_equal(u, v)
 
 
-def test_partial_outputs_match_full():
+@pytest.mark.parametrize("precision", ["fp64", "split"])
+@pytest.mark.parametrize("need", [(True, False, False), (False, True, False), (False, False, True),
+                                  (True, True, False), (True, False, True), (False, True, True)])
+def test_partial_outputs_match_full(precision, need):
+    """Only the requested gradients are computed -- dL/dx_p from the point
+    pass alone, dL/df with the first of the four node sums only, the node
+    gradient with all of them -- and each has the bits of the full call
+    (the same operations in the same order), hits included."""
     c = inputs.grad_workload(n=129, m=5000)
-    full = _gpu_bwd(c["nodes"], c["values"], c["d"], c["points"], c["grad"])
-    gv, gx, gn = fh.eval_backward(_t(c["nodes"]), _t(c["values"]), c["d"], _t(c["points"]),
-                                  _t(c["grad"]), need_values=False, need_x=False)
-    assert gv is None and gx is None
-    assert np.array_equal(_np(gn), full[2])
+    pts = c["points"].copy()
+    pts[:5] = c["nodes"][[0, 3, 64, 100, 128]]                       # exact hits
+    args = (_t(c["nodes"]), _t(c["values"]), c["d"], _t(pts), _t(c["grad"]))
+    full = fh.eval_backward(*args, precision=precision)
+    part = fh.eval_backward(*args, need_values=need[0], need_x=need[1], need_nodes=need[2],
+                            precision=precision)
+    for want, a, b in zip(need, part, full):
+        if want:
+            assert torch.equal(a, b)
+        else:
+            assert a is None
 
 
 # ------------------------------------------------------------ autograd --
