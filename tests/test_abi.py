@@ -358,3 +358,43 @@ def test_eval_prepared_many_host_validation():
     assert call(lam=(VP * 3)(0x400000, 0x500000, None)) == fh.FH_E_ARG
     # m = 0: validated, nothing launched
     assert call(m=0, x=None) == fh.FH_OK
+
+
+def _run_py(code, env_extra):
+    import subprocess
+    import sys
+    env = dict(os.environ, **env_extra)
+    return subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                          timeout=120, env=env, cwd=ROOT)
+
+
+def test_fh_log_reports_choices():
+    """FH_LOG=1: every new (shape, variant) choice is reported on stderr with
+    its source, once."""
+    code = ("from paper_1606_06508_amd import fh\n"
+            "fh.tune_get('fp64', 1001, 10**6); fh.tune_get('fp64', 1001, 10**6)\n"
+            "fh.tune_get('batched_split', 1041, 204421648)\n")
+    p = _run_py(code, {"FH_LOG": "1"})
+    assert p.returncode == 0, p.stderr
+    lines = [ln for ln in p.stderr.splitlines() if ln.startswith("[fh]")]
+    assert lines == ["[fh] fp64 n=1001 m=1000000: variant 17 (built-in)",
+                     "[fh] batched_split n=1041 m=204421648: variant 5 (built-in)"], p.stderr
+    q = _run_py(code, {"FH_LOG": "0"})
+    assert q.returncode == 0 and "[fh]" not in q.stderr
+
+
+def test_autotune_cache_for_another_architecture_is_ignored(tmp_path):
+    """A table saved for another architecture is not installed (and the
+    library says so under FH_LOG); a missing file is reported too."""
+    import json
+    path = tmp_path / "tune.json"
+    path.write_text(json.dumps({"arch": "gfx000", "entries": [
+        {"precision": "fp64", "n": 1001, "m": 1000000, "lambda": 1, "variant": 3,
+         "ms": 0.2, "all_ms": {"3": 0.2, "17": 0.3}}]}))
+    code = "from paper_1606_06508_amd import fh\nprint(fh.tune_get('fp64', 1001, 10**6))\n"
+    p = _run_py(code, {"FH_LOG": "1", "FH_AUTOTUNE_CACHE": str(path)})
+    assert p.returncode == 0, p.stderr
+    assert p.stdout.strip() == "17"
+    assert "made for 'gfx000'" in p.stderr and "ignored" in p.stderr
+    q = _run_py(code, {"FH_LOG": "1", "FH_AUTOTUNE_CACHE": str(tmp_path / "missing.json")})
+    assert q.stdout.strip() == "17" and "cannot open" in q.stderr

@@ -83,3 +83,28 @@ def test_tune_batch_installs_the_variant_a_new_batch_runs(precision):
         b.close()
     finally:
         fh.tune_set(family, n_key, m_key, -1)
+
+
+def test_library_loads_a_saved_table(tmp_path):
+    """FH_AUTOTUNE_CACHE: the library itself installs a table saved by the
+    autotuner on first use (same architecture), with no Python in between;
+    its calls then run the saved variants."""
+    import json
+    import os
+    import subprocess
+    import sys
+    arch = torch.cuda.get_device_properties(DEV).gcnArchName.split(":")[0]
+    path = tmp_path / "tune.json"
+    path.write_text(json.dumps({"arch": arch, "entries": [
+        {"precision": "fp64", "n": 1001, "m": 1000000, "lambda": 1, "variant": 3, "ms": 1.0},
+        {"precision": "batched_fp64", "n": 300, "m": 50000, "lambda": 0, "variant": 13,
+         "ms": 1.0}]}))
+    code = ("from paper_1606_06508_amd import fh\n"
+            "print(fh.tune_get('fp64', 1001, 10**6), fh.tune_get('batched_fp64', 300, 50000),"
+            " fh.tune_get('fp64', 4097, 10**7))\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120,
+                       cwd=root, env=dict(os.environ, FH_AUTOTUNE_CACHE=str(path), FH_LOG="1"))
+    assert p.returncode == 0, p.stderr
+    assert p.stdout.split() == ["3", "13", "18"], (p.stdout, p.stderr)
+    assert "2 entries installed" in p.stderr
