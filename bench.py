@@ -433,6 +433,22 @@ def run_backward_form(dev, reps, with_cpu):
                      "backward_Gpair_s": n * m / (ms_b * 1e-3) / 1e9,
                      "forward_Gpair_s": n * m / (ms_f * 1e-3) / 1e9,
                      "deriv_Gpair_s": n * m / (ms_d * 1e-3) / 1e9}
+        # saved-state adjoint (the autograd path): the forward keeps 1/D, r and
+        # the hit data; the backward forms each reciprocal once
+        wss = fh.Workspace(dev, fh.workspace_size(fh.FH_OP_BACKWARD_SAVED, n, m, c["d"], prec))
+        ms_fs = _time_ms(lambda: fh.eval_forward(nodes, vals, c["d"], x, precision=prec, ws=wss),
+                         reps)
+        _, st = fh.eval_forward(nodes, vals, c["d"], x, precision=prec, ws=wss)
+        ms_bs = _time_ms(lambda: fh.eval_backward_saved(st, g), reps)
+        ms_bsv = _time_ms(lambda: fh.eval_backward_saved(st, g, need_x=False, need_nodes=False),
+                          reps)
+        ms_bsx = _time_ms(lambda: fh.eval_backward_saved(st, g, need_values=False,
+                                                         need_nodes=False), reps)
+        out[prec]["saved_state"] = {
+            "forward_ms": ms_fs, "backward_ms": ms_bs, "backward_values_only_ms": ms_bsv,
+            "backward_points_only_ms": ms_bsx,
+            "backward_over_forward": ms_bs / ms_fs,
+            "step_ms": ms_fs + ms_bs, "step_ms_without_state": ms_f + ms_b}
         if ref is not None:
             got = fh.eval_backward(nodes, vals, c["d"], x, g, precision=prec, ws=ws)
             out[prec]["max_scaled_error"] = {
@@ -441,6 +457,10 @@ def run_backward_form(dev, reps, with_cpu):
             _, dr = fh.eval_deriv(nodes, vals, c["d"], x, precision=prec, ws=ws)
             out[prec]["max_scaled_error"]["deriv"] = float(
                 np.max(np.abs(dr.cpu().numpy() - dr_o) / np.maximum(s_o, 1e-300)))
+            got = fh.eval_backward_saved(st, g)
+            out[prec]["saved_state"]["max_scaled_error"] = {
+                name: float(np.max(np.abs(t.cpu().numpy() - r) / np.maximum(s, 1e-300)))
+                for name, t, (r, s) in zip(("dvalues", "dpoints", "dnodes"), got, ref)}
     out["split_backward_speedup_vs_fp64"] = out["fp64"]["backward_ms"] / out["split"]["backward_ms"]
     return out
 

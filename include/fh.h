@@ -93,7 +93,8 @@ typedef enum {
   FH_OP_WEIGHTS = 0,
   FH_OP_EVAL = 1,       /* also fh_lebesgue */
   FH_OP_BACKWARD = 2,
-  FH_OP_LEBESGUE_MAX = 3 /* fh_lebesgue_max (m ignored) */
+  FH_OP_LEBESGUE_MAX = 3, /* fh_lebesgue_max (m ignored) */
+  FH_OP_BACKWARD_SAVED = 4 /* fh_eval_forward + fh_eval_backward_saved */
 } fh_op;
 
 /* Device status bits (fh_device_status). */
@@ -295,6 +296,40 @@ fh_status fh_eval_backward(const double* nodes, const double* values, int64_t n,
                            const double* x, int64_t m, const double* grad_r, double* grad_values,
                            double* grad_x, double* grad_nodes, int32_t prec, void* ws,
                            size_t ws_bytes, void* stream);
+
+/* The adjoint in two steps that share their work, for callers that run a
+ * forward evaluation and later its adjoint (automatic differentiation).
+ *
+ * fh_eval_forward: r(x_p) into r_out [m] (as fh_eval, binary64 sums in
+ * groups of eight reciprocals) and, in ws, the node table and what the
+ * adjoint needs per point, for unit loss weights: 1/D_p, r_p, and at an exact
+ * hit x_p == x_j the flag and the node formula r'(x_j) (Schneider & Werner
+ * 1986).  NaN and infinite points give r = NaN.
+ *
+ * fh_eval_backward_saved: the gradients of fh_eval_backward (same
+ * definitions, hit rules, outputs and NULL conventions) from that state and
+ * the loss weights grad_r [m], without evaluating N_p and D_p again: one pass
+ * over the (point, node) pairs forms each reciprocal once and adds both the
+ * per-node sums S1..S4 (in a fixed order) and the per-point sums of
+ * dL/dx_p (across the lanes of a wave, then over node tile groups in a
+ * fixed order; deterministic).  The state is read, not changed: the backward
+ * may run any number of times on one forward.
+ *
+ * Both take ws of fh_workspace_size(FH_OP_BACKWARD_SAVED, n, m, d, prec) and
+ * must see the same nodes, n, d, x, m and prec; values are read by the
+ * forward only.  Between the two calls the workspace must not be used by
+ * another call.  prec = FH_FP32_SPLIT: the forward is the split evaluation
+ * of fh_eval and the backward runs the split fh_eval_backward on the node
+ * table the forward packed (no shared per-point state).  Errors as in
+ * fh_eval_backward; a backward on a workspace its forward did not fill
+ * gives unspecified values. */
+fh_status fh_eval_forward(const double* nodes, const double* values, int64_t n, int32_t d,
+                          const double* x, int64_t m, double* r_out, int32_t prec, void* ws,
+                          size_t ws_bytes, void* stream);
+fh_status fh_eval_backward_saved(const double* nodes, int64_t n, int32_t d, const double* x,
+                                 int64_t m, const double* grad_r, double* grad_values,
+                                 double* grad_x, double* grad_nodes, int32_t prec, void* ws,
+                                 size_t ws_bytes, void* stream);
 
 /* Batched evaluation of `count` independent interpolants of uneven sizes in
  * one captured HIP graph.  Instance i owns nodes/values

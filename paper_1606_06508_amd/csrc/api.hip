@@ -80,6 +80,10 @@ size_t fh_workspace_size(int32_t op, int64_t n, int64_t m, int32_t d, int32_t pr
       BackwardBufs b;
       return layout_backward(nullptr, n, m, prec == FH_FP32_SPLIT, &t, &b);
     }
+    case FH_OP_BACKWARD_SAVED: {
+      BackwardBufs b;
+      return layout_backward(nullptr, n, m, prec == FH_FP32_SPLIT, &t, &b, true);
+    }
     case FH_OP_LEBESGUE_MAX: {
       double *lam, *xk;
       return layout_lebesgue_max(nullptr, n, &t, &lam, &xk);
@@ -352,6 +356,62 @@ fh_status fh_eval_backward(const double* nodes, const double* values, int64_t n,
   if (e == hipSuccess)
     e = launch_backward(nodes, x, grad_r, n, d, m, t, b, reinterpret_cast<int32_t*>(status) + 1,
                         grad_values, m > 0 ? grad_x : nullptr, grad_nodes, s);
+  return finish(e, ws, s);
+}
+
+fh_status fh_eval_forward(const double* nodes, const double* values, int64_t n, int32_t d,
+                          const double* x, int64_t m, double* r_out, int32_t prec, void* ws,
+                          size_t ws_bytes, void* stream) {
+  fh_status st = check_problem(nodes, n, d);
+  if (st != FH_OK) return st;
+  if (values == nullptr || m < 0 || (m > 0 && (x == nullptr || r_out == nullptr)))
+    return FH_E_ARG;
+  if (prec != FH_FP64 && prec != FH_FP32_SPLIT) return FH_E_ARG;
+  st = check_ws(ws, ws_bytes, fh_workspace_size(FH_OP_BACKWARD_SAVED, n, m, d, prec));
+  if (st != FH_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  NodeTable t;
+  BackwardBufs b;
+  const bool split = prec == FH_FP32_SPLIT;
+  layout_backward(ws, n, m, split, &t, &b, true);
+  uint32_t* status = static_cast<uint32_t*>(ws);
+  hipError_t e = launch_pack(nodes, values, nullptr, n, d, t, split, status, s);
+  if (e == hipSuccess && m > 0) {
+    if (split) {
+      const EvalConfig cfg = choose_eval_config(prec, n, d, m, true, false);
+      e = launch_eval_split(x, m, t, n, reinterpret_cast<int32_t*>(status) + 1, status + 3,
+                            r_out, nullptr, cfg, s);
+    } else {
+      e = launch_forward_saved(x, m, t, n, b, r_out, s);
+    }
+  } else if (e == hipSuccess && !split) {
+    e = launch_forward_saved(x, 0, t, n, b, nullptr, s);  // padding records only
+  }
+  return finish(e, ws, s);
+}
+
+fh_status fh_eval_backward_saved(const double* nodes, int64_t n, int32_t d, const double* x,
+                                 int64_t m, const double* grad_r, double* grad_values,
+                                 double* grad_x, double* grad_nodes, int32_t prec, void* ws,
+                                 size_t ws_bytes, void* stream) {
+  fh_status st = check_problem(nodes, n, d);
+  if (st != FH_OK) return st;
+  if (m < 0 || (m > 0 && (x == nullptr || grad_r == nullptr))) return FH_E_ARG;
+  if (prec != FH_FP64 && prec != FH_FP32_SPLIT) return FH_E_ARG;
+  st = check_ws(ws, ws_bytes, fh_workspace_size(FH_OP_BACKWARD_SAVED, n, m, d, prec));
+  if (st != FH_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  NodeTable t;
+  BackwardBufs b;
+  const bool split = prec == FH_FP32_SPLIT;
+  layout_backward(ws, n, m, split, &t, &b, true);
+  uint32_t* status = static_cast<uint32_t*>(ws);
+  const hipError_t e =
+      split ? launch_backward(nodes, x, grad_r, n, d, m, t, b,
+                              reinterpret_cast<int32_t*>(status) + 1, grad_values,
+                              m > 0 ? grad_x : nullptr, grad_nodes, s)
+            : launch_backward_saved(nodes, x, grad_r, n, d, m, t, b, grad_values, grad_x,
+                                    grad_nodes, s);
   return finish(e, ws, s);
 }
 

@@ -44,8 +44,11 @@ namespace fhk {
 // DERIV: the derivative r'(x) = (r E - F) / D of the interpolant (dL/dx_p
 // with g_p = 1; the node formula at hits) is written to dx and r to r_out;
 // g, the records and the padding are not used (m_pad = m).  EF: E and F are
-// summed (for dx; without them pass 1 writes only the records).
-template <int P, bool DERIV, bool EF>
+// summed (for dx; without them pass 1 writes only the records).  SAVE (with
+// neither): the forward of the saved-state adjoint -- r to r_out and the
+// records for g_p = 1 with r in place of c r: {x, 1/D, r, 1 at a hit,
+// r'(x_j) at a hit}, which k_bwd_scale_records later scales by g.
+template <int P, bool DERIV, bool EF, bool SAVE = false>
 __global__ void __launch_bounds__(256)
     k_bwd_points(const double* __restrict__ x, const double* __restrict__ g, int64_t m,
                  int64_t m_pad, const double* __restrict__ tx, const double* __restrict__ tw,
@@ -104,7 +107,7 @@ __global__ void __launch_bounds__(256)
       }
       continue;
     }
-    const double gp = DERIV ? 1.0 : g[idx];
+    const double gp = (DERIV || SAVE) ? 1.0 : g[idx];
     const double t = xp[j];
     double dxp, rv, c = 0.0, cr = 0.0, hg = 0.0, hgr = 0.0, xr = t;
     if (!__builtin_isfinite(t)) {
@@ -122,6 +125,9 @@ __global__ void __launch_bounds__(256)
     if (EF && dx) dx[idx] = dxp;
     if (DERIV) {
       if (r_out) r_out[idx] = rv;
+    } else if (SAVE) {
+      r_out[idx] = rv;
+      rec.x[idx] = xr; rec.c[idx] = c; rec.cr[idx] = rv; rec.hg[idx] = hg; rec.hgr[idx] = hgr;
     } else {
       rec.x[idx] = xr; rec.c[idx] = c; rec.cr[idx] = cr; rec.hg[idx] = hg; rec.hgr[idx] = hgr;
     }
@@ -129,75 +135,160 @@ __global__ void __launch_bounds__(256)
 }
 
 // ---------------------------------------------------------------- pass 2 --
-// grid: x = node tiles of 64*Q nodes, y = groups of four chunks of `chunk`
-// points (chunk a multiple of G); wave w of the block takes chunk
-// 4*blockIdx.y + w.  Reciprocals are taken G points at a time.  FULL: all
-// four sums and both hit sums (the node gradient needs them); otherwise S1
-// and H1 only (dL/df), the others written as zeros.
-template <int Q, int G, bool FULL>
+// grid: x = node tile groups, y = groups of four chunks of `chunk` points
+// (chunk a multiple of G); wave w of the block takes chunk 4*blockIdx.y + w
+// and the node tiles (64*Q nodes each) blockIdx.x, blockIdx.x + gridDim.x,
+// ...  Reciprocals are taken G points at a time.  SUMS: 2 all four node
+// sums and both hit sums (the node gradient needs them), 1 S1 and H1 only
+// (dL/df; the others written as zeros), 0 none (no node partials written).
+// PT (G = 8, saved-state adjoint): also the point side of the same pairs,
+// sum_k (w_k r_p - w_k f_k) t_pk^2 = dL/dx_p / c_p (rr = r_p), summed over
+// the wave's nodes across lanes (wave_sum8, through LDS) and over its tiles in place:
+// gpart[blockIdx.x][p] (each wave owns its chunk's slots of its tile group;
+// the lane that adds a slot is the lane that wrote it).  Padding nodes
+// (k >= n) sit far beyond the last node with zero weight: they add nothing,
+// and never make a group product zero.
+template <int Q, int G, int SUMS, bool PT>
 __global__ void __launch_bounds__(256)
-    k_bwd_nodes(PointRecs rec, int64_t chunk, int64_t chunks,
-                const double* __restrict__ tx, int64_t n_pad, double* __restrict__ part) {
+    k_bwd_nodes(const double* __restrict__ rec_x, const double* __restrict__ rec_c,
+                const double* __restrict__ rec_cr, const double* __restrict__ rec_hg,
+                const double* __restrict__ rec_hgr, const double* __restrict__ rr, int64_t chunk,
+                int64_t chunks, const double* __restrict__ tx, const double* __restrict__ tw,
+                const double* __restrict__ twf, int64_t n, int64_t n_pad,
+                double* __restrict__ part, double* __restrict__ gpart, int64_t m_pad) {
+  static_assert(!PT || G == 8, "the point-side sums run over groups of eight points");
+  __shared__ double red[PT ? 4 : 1][PT ? 8 * 64 : 1];
   const int lane = threadIdx.x & 63;
   const int64_t c = (int64_t)blockIdx.y * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (c >= chunks) return;
-  const int64_t k0 = (int64_t)blockIdx.x * 64 * Q + lane;
+  const int64_t tiles = (n_pad + 64 * Q - 1) / (64 * Q);
   const int64_t p0 = c * chunk;
-  const double* __restrict__ rx = rec.x + p0;
-  const double* __restrict__ rc = rec.c + p0;
-  const double* __restrict__ rcr = rec.cr + p0;
-  double xk[Q], S1[Q], S2[Q], S3[Q], S4[Q], H1[Q], H2[Q];
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int64_t k = k0 + q * 64;
-    xk[q] = tx[k < n_pad ? k : n_pad - 1];
-    S1[q] = S2[q] = S3[q] = S4[q] = H1[q] = H2[q] = 0.0;
-  }
-  for (int p = 0; p < (int)chunk; p += G) {
-    double px[G], pc[G], pcr[G];
-#pragma unroll
-    for (int i = 0; i < G; ++i) {
-      px[i] = rx[p + i];
-      pc[i] = rc[p + i];
-      pcr[i] = FULL ? rcr[p + i] : 0.0;
-    }
+  // the records are read-only here: wave-uniform scalar loads
+  const double* rx = rec_x + p0;
+  const double* rc = rec_c + p0;
+  const double* rcr = rec_cr + p0;
+  // beyond the far point of pass 1's padding records as well
+  const double far = tx[n - 1] + 2.0 * ((tx[n - 1] - tx[0]) + 1.0);
+  const int slot = lane >> 3;
+  double* lds = red[PT ? threadIdx.x >> 6 : 0];
+  double* __restrict__ gp_out = PT ? gpart + (int64_t)blockIdx.x * m_pad + p0 : nullptr;
+  for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const bool first = tile == (int64_t)blockIdx.x;
+    const int64_t k0 = tile * 64 * Q + lane;
+    double xk[Q], wk[Q], wfk[Q], S1[Q], S2[Q], S3[Q], S4[Q], H1[Q], H2[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      double dl[G], t[G];
+      const int64_t k = k0 + q * 64;
+      const bool real = k < n;
+      xk[q] = real ? tx[k] : far;
+      wk[q] = PT && real ? tw[k] : 0.0;
+      wfk[q] = PT && real ? twf[k] : 0.0;
+      S1[q] = S2[q] = S3[q] = S4[q] = H1[q] = H2[q] = 0.0;
+    }
+    for (int p = 0; p < (int)chunk; p += G) {
+      double px[G], pc[G], pcr[G], pr[G], gs[G];
 #pragma unroll
-      for (int i = 0; i < G; ++i) dl[i] = px[i] - xk[q];
-      const bool bad = group_reciprocals<G>(dl, t);
-      if (!bad) {
+      for (int i = 0; i < G; ++i) {
+        px[i] = rx[p + i];
+        pc[i] = SUMS >= 1 ? rc[p + i] : 0.0;
+        pcr[i] = SUMS == 2 ? rcr[p + i] : 0.0;
+        pr[i] = PT ? rr[p0 + p + i] : 0.0;
+        gs[i] = 0.0;
+      }
 #pragma unroll
-        for (int i = 0; i < G; ++i) {
-          S1[q] = __builtin_fma(pc[i], t[i], S1[q]);
-          if constexpr (FULL) {
-            const double t2 = t[i] * t[i];
-            S2[q] = __builtin_fma(pcr[i], t[i], S2[q]);
-            S3[q] = __builtin_fma(pc[i], t2, S3[q]);
-            S4[q] = __builtin_fma(pcr[i], t2, S4[q]);
+      for (int q = 0; q < Q; ++q) {
+        double dl[G], t[G];
+#pragma unroll
+        for (int i = 0; i < G; ++i) dl[i] = px[i] - xk[q];
+        const bool bad = group_reciprocals<G>(dl, t);
+        if (!bad) {
+#pragma unroll
+          for (int i = 0; i < G; ++i) {
+            if constexpr (SUMS >= 1) S1[q] = __builtin_fma(pc[i], t[i], S1[q]);
+            if constexpr (SUMS == 2 || PT) {
+              const double t2 = t[i] * t[i];
+              if constexpr (SUMS == 2) {
+                S2[q] = __builtin_fma(pcr[i], t[i], S2[q]);
+                S3[q] = __builtin_fma(pc[i], t2, S3[q]);
+                S4[q] = __builtin_fma(pcr[i], t2, S4[q]);
+              }
+              if constexpr (PT)
+                gs[i] = __builtin_fma(__builtin_fma(wk[q], pr[i], -wfk[q]), t2, gs[i]);
+            }
           }
+        } else {
+          // pair by pair: a zero difference is a hit on this node
+          for (int i = 0; i < G; ++i)
+            bwd_pair_exact<SUMS, PT>(px[i], pc[i], pcr[i], rec_hg[p0 + p + i],
+                                     rec_hgr[p0 + p + i], xk[q], S1[q], S2[q], S3[q], S4[q],
+                                     H1[q], H2[q], wk[q], wfk[q], pr[i], &gs[i]);
         }
-      } else {
-        // pair by pair: a zero difference is a hit on this node
-        for (int i = 0; i < G; ++i)
-          bwd_pair_exact<FULL>(rec, p0 + p + i, xk[q], S1[q], S2[q], S3[q], S4[q], H1[q],
-                               H2[q]);
+      }
+      if constexpr (PT) {
+        const double z = wave_sum8(gs, lds);
+        if ((lane & 7) == 0) {
+          double* o = gp_out + p + slot;
+          *o = first ? z : *o + z;
+        }
+      }
+    }
+    if constexpr (SUMS >= 1) {
+      double* out = part + c * kPartFields * n_pad;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int64_t k = k0 + q * 64;
+        if (k >= n_pad) continue;
+        out[0 * n_pad + k] = S1[q];
+        out[1 * n_pad + k] = S2[q];
+        out[2 * n_pad + k] = S3[q];
+        out[3 * n_pad + k] = S4[q];
+        out[4 * n_pad + k] = H1[q];
+        out[5 * n_pad + k] = H2[q];
       }
     }
   }
-  double* out = part + c * kPartFields * n_pad;
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int64_t k = k0 + q * 64;
-    if (k >= n_pad) continue;
-    out[0 * n_pad + k] = S1[q];
-    out[1 * n_pad + k] = S2[q];
-    out[2 * n_pad + k] = S3[q];
-    out[3 * n_pad + k] = S4[q];
-    out[4 * n_pad + k] = H1[q];
-    out[5 * n_pad + k] = H2[q];
+}
+
+// Saved-state adjoint, before pass 2: the records for the loss weights g
+// from the forward's records for g = 1 (saved: {x, 1/D, r, 1 at a hit,
+// r'(x_j) at a hit}; rec.x is saved.x): c = g / D, c r, g and g r'(x_j) at
+// a hit, zeros for padding and for points the forward set aside (1/D = 0).
+__global__ void __launch_bounds__(256)
+    k_bwd_scale_records(PointRecs saved, const double* __restrict__ g, int64_t m, int64_t m_pad,
+                        PointRecs rec) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= m_pad) return;
+  const double gp = p < m ? g[p] : 0.0;
+  const double inv_d = saved.c[p];
+  const bool hit = saved.hg[p] != 0.0;
+  const double c = inv_d == 0.0 ? 0.0 : gp * inv_d;
+  rec.c[p] = c;
+  rec.cr[p] = inv_d == 0.0 ? 0.0 : c * saved.cr[p];
+  rec.hg[p] = hit ? gp : 0.0;
+  rec.hgr[p] = hit ? gp * saved.hgr[p] : 0.0;
+}
+
+// Saved-state adjoint, after pass 2: dL/dx_p = c_p times the point-side sum
+// over the tile groups (fixed order); g_p r'(x_j) at a hit, NaN at a NaN or
+// infinite point.
+__global__ void __launch_bounds__(256)
+    k_bwd_point_grad(const double* __restrict__ x, const double* __restrict__ g, int64_t m,
+                     int64_t m_pad, PointRecs saved, const double* __restrict__ c,
+                     const double* __restrict__ gpart, int32_t groups, double* __restrict__ dx) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= m) return;
+  const double xp = x[p];
+  double v;
+  if (!__builtin_isfinite(xp)) {
+    v = __builtin_nan("");
+  } else if (saved.hg[p] != 0.0) {
+    v = g[p] * saved.hgr[p];
+  } else {
+    double acc = 0.0;
+    for (int32_t j = 0; j < groups; ++j) acc += gpart[(int64_t)j * m_pad + p];
+    v = c[p] * acc;
   }
+  dx[p] = v;
 }
 
 // ---------------------------------------------------------------- pass 3 --
@@ -303,19 +394,24 @@ static int64_t resident_blocks(const void* kernel) {
   return r;
 }
 
-static const void* bwd_nodes_kernel(int q, int g) {
+// The five record arrays of a PointRecs as kernel arguments.
+#define FH_RECS(r) (r).x, (r).c, (r).cr, (r).hg, (r).hgr
+
+static const void* bwd_nodes_kernel(int q, int g, bool saved) {
+  if (saved) return reinterpret_cast<const void*>(k_bwd_nodes<2, 8, 2, true>);
   switch (q * 10 + g) {
-    case 14: return reinterpret_cast<const void*>(k_bwd_nodes<1, 4, true>);
-    case 24: return reinterpret_cast<const void*>(k_bwd_nodes<2, 4, true>);
-    case 18: return reinterpret_cast<const void*>(k_bwd_nodes<1, 8, true>);
-    default: return reinterpret_cast<const void*>(k_bwd_nodes<2, 8, true>);
+    case 14: return reinterpret_cast<const void*>(k_bwd_nodes<1, 4, 2, false>);
+    case 24: return reinterpret_cast<const void*>(k_bwd_nodes<2, 4, 2, false>);
+    case 18: return reinterpret_cast<const void*>(k_bwd_nodes<1, 8, 2, false>);
+    default: return reinterpret_cast<const void*>(k_bwd_nodes<2, 8, 2, false>);
   }
 }
 
-BackwardPlan plan_backward(int64_t n, int64_t m, bool split) {
+BackwardPlan plan_backward(int64_t n, int64_t m, bool split, bool saved) {
   BackwardPlan p;
   p.n_pad = round_up(n, kNodePad);
   p.split = split;
+  saved = saved && !split;
   // binary64: two points per lane in pass 1, two nodes per lane and
   // inversion over eight points in pass 2 (measured best on the 2049-node
   // gradient workload); split: one node per lane up to 4096 nodes
@@ -327,14 +423,18 @@ BackwardPlan plan_backward(int64_t n, int64_t m, bool split) {
   // second, partly filled round would leave most of the chip idle for as
   // long as the first.  binary64: blocks of four waves, each a 64 q node
   // tile and one chunk; split: blocks of 256 q nodes sharing one chunk.
+  p.groups = 0;
   int64_t chunks;
   if (split) {
     const int64_t tiles = (p.n_pad + 256 * p.q - 1) / (256 * p.q);
     const int64_t rows = resident_blocks(bwd_nodes_split_kernel(p.q)) / tiles;
     chunks = rows > 1 ? rows : 1;
   } else {
+    // saved-state adjoint: a wave takes every groups-th tile for its chunk
     const int64_t tiles = (p.n_pad + 64 * p.q - 1) / (64 * p.q);
-    const int64_t rows = resident_blocks(bwd_nodes_kernel(p.q, p.g)) / tiles;
+    p.groups = saved ? (int32_t)(tiles < kMaxTileGroups ? tiles : kMaxTileGroups) : 0;
+    const int64_t rows =
+        resident_blocks(bwd_nodes_kernel(p.q, p.g, saved)) / (saved ? p.groups : tiles);
     chunks = 4 * (rows > 1 ? rows : 1);
   }
   const int64_t align = split ? kTile : 8;
@@ -350,9 +450,9 @@ BackwardPlan plan_backward(int64_t n, int64_t m, bool split) {
 }
 
 size_t layout_backward(void* ws, int64_t n, int64_t m, bool split, NodeTable* t,
-                       BackwardBufs* b) {
+                       BackwardBufs* b, bool saved) {
   size_t off = layout_tables(ws, n, t);
-  const BackwardPlan p = plan_backward(n, m, split);
+  const BackwardPlan p = plan_backward(n, m, split, saved);
   char* base = static_cast<char*>(ws);
   auto take = [&](size_t bytes) {
     char* q = base ? base + off : nullptr;
@@ -367,6 +467,15 @@ size_t layout_backward(void* ws, int64_t n, int64_t m, bool split, NodeTable* t,
   b->sums = reinterpret_cast<double*>(take(sizeof(double) * kPartFields * p.n_pad));
   b->dw = reinterpret_cast<double*>(take(sizeof(double) * p.n_pad));
   b->dxd = reinterpret_cast<double*>(take(sizeof(double) * p.n_pad));
+  b->saved = PointRecs{};
+  b->gpart = nullptr;
+  if (p.groups > 0) {
+    // the forward's records (g = 1) share the point coordinates with rec
+    b->saved.x = b->rec.x;
+    double** sf[] = {&b->saved.c, &b->saved.cr, &b->saved.hg, &b->saved.hgr};
+    for (double** f : sf) *f = reinterpret_cast<double*>(take(sizeof(double) * p.m_pad));
+    b->gpart = reinterpret_cast<double*>(take(sizeof(double) * p.groups * p.m_pad));
+  }
   return off;
 }
 
@@ -397,19 +506,21 @@ static hipError_t launch_bwd_points(const BackwardPlan& p, const double* x, cons
 
 // full: all four sums (the node gradient is wanted), else S1 only
 static hipError_t launch_bwd_nodes(const BackwardPlan& p, const PointRecs& rec, const NodeTable& t,
-                                   double* part, bool full, hipStream_t s) {
+                                   int64_t n, double* part, bool full, hipStream_t s) {
   const dim3 grid((unsigned)((p.n_pad + 64 * p.q - 1) / (64 * p.q)),
                   (unsigned)((p.chunks + 3) / 4));
   const int v = p.q * 10 + p.g;
   switch (v) {
-#define FH_NODES_CASE(Q, G)                                                                  \
-  case Q * 10 + G:                                                                         \
-    if (full)                                                                              \
-      k_bwd_nodes<Q, G, true><<<grid, 256, 0, s>>>(rec, p.chunk, p.chunks, t.x, t.n_pad,   \
-                                                   part);                                  \
-    else                                                                                   \
-      k_bwd_nodes<Q, G, false><<<grid, 256, 0, s>>>(rec, p.chunk, p.chunks, t.x, t.n_pad,  \
-                                                    part);                                 \
+#define FH_NODES_CASE(Q, G)                                                                 \
+  case Q * 10 + G:                                                                        \
+    if (full)                                                                             \
+      k_bwd_nodes<Q, G, 2, false><<<grid, 256, 0, s>>>(FH_RECS(rec), nullptr, p.chunk,    \
+                                                       p.chunks, t.x, t.w, t.wf, n, t.n_pad, \
+                                                       part, nullptr, p.m_pad);           \
+    else                                                                                  \
+      k_bwd_nodes<Q, G, 1, false><<<grid, 256, 0, s>>>(FH_RECS(rec), nullptr, p.chunk,    \
+                                                       p.chunks, t.x, t.w, t.wf, n, t.n_pad, \
+                                                       part, nullptr, p.m_pad);           \
     break;
     FH_NODES_CASE(1, 4)
     FH_NODES_CASE(2, 4)
@@ -420,6 +531,10 @@ static hipError_t launch_bwd_nodes(const BackwardPlan& p, const PointRecs& rec, 
   }
   return hipGetLastError();
 }
+
+static hipError_t launch_node_tail(const double* nodes, int64_t n, int32_t d, const NodeTable& t,
+                                   const BackwardBufs& b, const int32_t* scale_exp, double* df,
+                                   double* dxn, hipStream_t s);
 
 hipError_t launch_backward(const double* nodes, const double* x, const double* g, int64_t n,
                            int32_t d, int64_t m, const NodeTable& t, const BackwardBufs& b,
@@ -438,24 +553,80 @@ hipError_t launch_backward(const double* nodes, const double* x, const double* g
     e = launch_bwd_points(p, x, g, m, t, n, dx, b.rec, s);
     if (e != hipSuccess) return e;
     if (nodes_pass) {
-      e = launch_bwd_nodes(p, b.rec, t, b.part, full, s);
+      e = launch_bwd_nodes(p, b.rec, t, n, b.part, full, s);
       if (e != hipSuccess) return e;
     }
   }
   if (!nodes_pass) return hipSuccess;
+  return launch_node_tail(nodes, n, d, t, b, p.split ? scale_exp : nullptr, df, dxn, s);
+}
+
+// Passes 3 and 4 from the chunk partials of pass 2.
+static hipError_t launch_node_tail(const double* nodes, int64_t n, int32_t d, const NodeTable& t,
+                                   const BackwardBufs& b, const int32_t* scale_exp, double* df,
+                                   double* dxn, hipStream_t s) {
+  const BackwardPlan& p = b.plan;
+  hipError_t e;
   const dim3 g3((unsigned)((p.n_pad + 63) / 64), (unsigned)kPartFields);
   k_bwd_reduce<<<g3, 256, 0, s>>>(b.part, p.chunks, p.n_pad, b.sums);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // per-node passes in 64-thread blocks: n is small, so spread it over CUs
   const dim3 g4((unsigned)((n + 63) / 64));
-  k_bwd_finish<<<g4, 64, 0, s>>>(b.sums, p.n_pad, n, t.w, t.f, p.split ? scale_exp : nullptr, df,
-                                 b.dw, b.dxd);
+  k_bwd_finish<<<g4, 64, 0, s>>>(b.sums, p.n_pad, n, t.w, t.f, scale_exp, df, b.dw, b.dxd);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (dxn) {
     k_bwd_chain<<<dim3((unsigned)((n + 3) / 4)), 256, 0, s>>>(nodes, n, d, b.dw, b.dxd, dxn);
     e = hipGetLastError();
   }
   return e;
+}
+
+// --------------------------------------------------- saved-state adjoint --
+hipError_t launch_forward_saved(const double* x, int64_t m, const NodeTable& t, int64_t n,
+                                const BackwardBufs& b, double* r, hipStream_t s) {
+  const BackwardPlan& p = b.plan;
+  if (p.groups <= 0) return hipErrorInvalidValue;
+  constexpr int P = 2;
+  const dim3 grid((unsigned)((p.m_pad + 256 * P - 1) / (256 * P)));
+  k_bwd_points<P, false, false, true><<<grid, 256, 0, s>>>(
+      x, nullptr, m, p.m_pad, t.x, t.w, t.wf, t.f, t.n_pad, n, nullptr, b.saved, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_backward_saved(const double* nodes, const double* x, const double* g,
+                                 int64_t n, int32_t d, int64_t m, const NodeTable& t,
+                                 const BackwardBufs& b, double* df, double* dx, double* dxn,
+                                 hipStream_t s) {
+  const BackwardPlan& p = b.plan;
+  if (p.groups <= 0) return hipErrorInvalidValue;
+  if (m == 0) dx = nullptr;  // no points: node sums of the padding records (zeros) only
+  if (df == nullptr && dx == nullptr && dxn == nullptr) return hipSuccess;
+  hipError_t e;
+  k_bwd_scale_records<<<dim3((unsigned)((p.m_pad + 255) / 256)), 256, 0, s>>>(b.saved, g, m,
+                                                                              p.m_pad, b.rec);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int sums = dxn ? 2 : (df ? 1 : 0);
+  const bool pt = dx != nullptr;
+  const dim3 grid((unsigned)p.groups, (unsigned)((p.chunks + 3) / 4));
+#define FH_SAVED_CASE(S, PT)                                                                 \
+  if (sums == S && pt == PT)                                                                \
+    k_bwd_nodes<2, 8, S, PT><<<grid, 256, 0, s>>>(FH_RECS(b.rec), b.saved.cr, p.chunk,      \
+                                                  p.chunks, t.x, t.w, t.wf, n, t.n_pad,     \
+                                                  b.part, b.gpart, p.m_pad);
+  FH_SAVED_CASE(2, true)
+  FH_SAVED_CASE(2, false)
+  FH_SAVED_CASE(1, true)
+  FH_SAVED_CASE(1, false)
+  FH_SAVED_CASE(0, true)
+#undef FH_SAVED_CASE
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (dx) {
+    k_bwd_point_grad<<<dim3((unsigned)((m + 255) / 256)), 256, 0, s>>>(
+        x, g, m, p.m_pad, b.saved, b.rec.c, b.gpart, p.groups, dx);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (sums == 0) return hipSuccess;
+  return launch_node_tail(nodes, n, d, t, b, nullptr, df, dxn, s);
 }
 
 // ---------------------------------------------------------- derivative --

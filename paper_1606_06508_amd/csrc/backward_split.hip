@@ -229,7 +229,9 @@ __global__ void __launch_bounds__(kStage)
                   S4[q] = __builtin_fma(pcr, t2, S4[q]);
                 }
               } else {
-                bwd_pair_exact<FULL>(rec, pp, xk[q], S1[q], S2[q], S3[q], S4[q], H1[q], H2[q]);
+                bwd_pair_exact<FULL ? 2 : 1>(rec.x[pp], rec.c[pp], rec.cr[pp], rec.hg[pp],
+                                             rec.hgr[pp], xk[q], S1[q], S2[q], S3[q], S4[q],
+                                             H1[q], H2[q]);
               }
             }
           } else {

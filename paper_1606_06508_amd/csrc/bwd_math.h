@@ -72,27 +72,81 @@ __device__ inline void bwd_point_exact(double x, double gp, const double* __rest
   }
 }
 
-// One (point p, node xk) pair of the per-node pass by IEEE division; a zero
-// difference is a hit of the point on this node.  FULL: all sums, else S1
-// and H1 only (the node gradient is not wanted).
-template <bool FULL = true>
-__device__ inline void bwd_pair_exact(const PointRecs& rec, int64_t p, double xk, double& S1,
-                                      double& S2, double& S3, double& S4, double& H1,
-                                      double& H2) {
-  const double dl = rec.x[p] - xk;
+// One (point, node xk) pair of the per-node pass by IEEE division, from the
+// point's record {x, c, c r, g at a hit, g r'(x_j) at a hit}; a zero
+// difference is a hit of the point on this node.  SUMS: 2 all node sums,
+// 1 S1 and H1 only (the node gradient is not wanted), 0 none.  PT: the
+// point-side term (w_k r_p - w_k f_k) t^2 of dL/dx_p / c_p is added to gp
+// (rp = r_p; nothing at a hit).
+template <int SUMS = 2, bool PT = false>
+__device__ inline void bwd_pair_exact(double px, double pc, double pcr, double phg, double phgr,
+                                      double xk, double& S1, double& S2, double& S3, double& S4,
+                                      double& H1, double& H2, double wk = 0.0, double wfk = 0.0,
+                                      double rp = 0.0, double* gp = nullptr) {
+  const double dl = px - xk;
   if (dl == 0.0) {
-    H1 += rec.hg[p];
-    if (FULL) H2 += rec.hgr[p];
+    if (SUMS >= 1) H1 += phg;
+    if (SUMS == 2) H2 += phgr;
   } else {
     const double ti = 1.0 / dl;
-    S1 = __builtin_fma(rec.c[p], ti, S1);
-    if (FULL) {
+    if (SUMS >= 1) S1 = __builtin_fma(pc, ti, S1);
+    if (SUMS == 2 || PT) {
       const double t2 = ti * ti;
-      S2 = __builtin_fma(rec.cr[p], ti, S2);
-      S3 = __builtin_fma(rec.c[p], t2, S3);
-      S4 = __builtin_fma(rec.cr[p], t2, S4);
+      if (SUMS == 2) {
+        S2 = __builtin_fma(pcr, ti, S2);
+        S3 = __builtin_fma(pc, t2, S3);
+        S4 = __builtin_fma(pcr, t2, S4);
+      }
+      if (PT) *gp = __builtin_fma(__builtin_fma(wk, rp, -wfk), t2, *gp);
     }
   }
+}
+
+// ---- sums across the 64 lanes of a wave ----
+// A DPP lane move inside 16-lane rows (every source lane valid); binary64
+// values move as two 32-bit halves.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const uint64_t u = static_cast<uint64_t>(__double_as_longlong(v));
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(static_cast<uint32_t>(u)), CTRL,
+                                             0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(static_cast<uint32_t>(u >> 32)),
+                                             CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(static_cast<long long>(
+      (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo)));
+}
+
+// Orders this wave's LDS accesses across lanes (no workgroup barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Transposed wave sum of eight values per lane through the wave's own
+// 4 KB of LDS (lds[8][64]): afterwards lane l holds the sum over all 64
+// lanes of v[l >> 3] (the same bits on its group of eight lanes), in a fixed
+// order: lane l adds the values of lanes 8 (l & 7) .. 8 (l & 7) + 7 in
+// order, then the eight lanes of the group combine by DPP (quad_perm xor 1,
+// xor 2, row_half_mirror).  Eight LDS stores, four 16-byte loads and 16
+// VALU instructions per call.
+__device__ __forceinline__ double wave_sum8(const double (&v)[8], double* lds) {
+  const int lane = threadIdx.x & 63;
+  wave_lds_sync();  // the previous call's loads are done
+#pragma unroll
+  for (int j = 0; j < 8; ++j) lds[j * 64 + lane] = v[j];
+  wave_lds_sync();
+  const double2* src = reinterpret_cast<const double2*>(lds + (lane >> 3) * 64 + (lane & 7) * 8);
+  double z = 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const double2 q = src[r];
+    z = r == 0 ? q.x + q.y : (z + q.x) + q.y;
+  }
+  z += dpp_f64<0xB1>(z);   // quad_perm [1,0,3,2]
+  z += dpp_f64<0x4E>(z);   // quad_perm [2,3,0,1]
+  z += dpp_f64<0x141>(z);  // row_half_mirror
+  return z;
 }
 
 }  // namespace fhk

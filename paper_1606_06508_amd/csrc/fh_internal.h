@@ -76,8 +76,12 @@ struct BackwardPlan {
   int p;       // points per lane in the per-point pass (binary64)
   int q;       // nodes per lane in the per-node pass
   int g;       // points per simultaneous inversion in the per-node pass (binary64)
+  int groups;  // saved-state adjoint: node tile groups of the fused pass (0: not planned)
   bool split;  // precision-split passes 1 and 2
 };
+// At most this many node tile groups in the saved-state adjoint's fused pass
+// (its point-side partial sums take groups * m_pad doubles).
+constexpr int32_t kMaxTileGroups = 64;
 struct BackwardBufs {
   BackwardPlan plan;
   PointRecs rec;  // per-point records of pass 1 (five [m_pad] arrays)
@@ -86,11 +90,17 @@ struct BackwardBufs {
   double* sums;   // [6][n_pad] node sums over all chunks
   double* dw;     // [n_pad] dL/dw_k
   double* dxd;    // [n_pad] direct dL/dx_k at fixed weights
+  // saved-state adjoint (binary64, FH_OP_BACKWARD_SAVED) only, else null:
+  PointRecs saved;  // the forward's records for g = 1: {x (= rec.x), 1/D, r,
+                    // 1 at a hit, r'(x_j) at a hit}
+  double* gpart;    // [groups][m_pad] point-side sums per node tile group
 };
-BackwardPlan plan_backward(int64_t n, int64_t m, bool split);
-// Workspace layout of FH_OP_BACKWARD (node tables, then the buffers above).
+// saved: plan the saved-state adjoint (binary64 only; split plans ignore it).
+BackwardPlan plan_backward(int64_t n, int64_t m, bool split, bool saved = false);
+// Workspace layout of FH_OP_BACKWARD, or of FH_OP_BACKWARD_SAVED when saved
+// (node tables, then the buffers above).
 size_t layout_backward(void* ws, int64_t n, int64_t m, bool split, NodeTable* t,
-                       BackwardBufs* b);
+                       BackwardBufs* b, bool saved = false);
 
 // Several interpolants on the same nodes and points (fh_eval_multi).
 constexpr int kMultiMax = 64;
@@ -159,6 +169,15 @@ hipError_t launch_backward(const double* nodes, const double* x, const double* g
                            int32_t d, int64_t m, const NodeTable& t, const BackwardBufs& b,
                            const int32_t* scale_exp, double* df, double* dx, double* dxn,
                            hipStream_t s);
+// Saved-state adjoint (binary64): the forward writes r and b.saved; the
+// backward scales the saved records by g and runs one fused pass over the
+// (point, node) pairs for the node sums and dL/dx_p together.
+hipError_t launch_forward_saved(const double* x, int64_t m, const NodeTable& t, int64_t n,
+                                const BackwardBufs& b, double* r, hipStream_t s);
+hipError_t launch_backward_saved(const double* nodes, const double* x, const double* g,
+                                 int64_t n, int32_t d, int64_t m, const NodeTable& t,
+                                 const BackwardBufs& b, double* df, double* dx, double* dxn,
+                                 hipStream_t s);
 // The per-node split kernel for q nodes per lane (occupancy queries).
 const void* bwd_nodes_split_kernel(int q);
 // nodes_pass: run the per-node pass (dL/df or the node gradient wanted);

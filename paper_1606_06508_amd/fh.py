@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libfh.so")
 FH_OK, FH_E_ARG, FH_E_DEGREE, FH_E_NODES, FH_E_NONFINITE, FH_E_RANGE = 0, 1, 2, 3, 4, 5
 FH_E_WORKSPACE, FH_E_HIP, FH_E_UNSUPPORTED, FH_E_TOO_LARGE = 6, 7, 8, 9
 FH_FP64, FH_FP32_SPLIT = 0, 1
-FH_OP_WEIGHTS, FH_OP_EVAL, FH_OP_BACKWARD, FH_OP_LEBESGUE_MAX = 0, 1, 2, 3
+FH_OP_WEIGHTS, FH_OP_EVAL, FH_OP_BACKWARD, FH_OP_LEBESGUE_MAX, FH_OP_BACKWARD_SAVED = 0, 1, 2, 3, 4
 FH_MAX_NODES = 1 << 28  # largest node count of one interpolant
 FH_NOALLOC_MAX_NODES = 43648  # largest node count of fh_eval_noalloc
 PRECISIONS = {"fp64": FH_FP64, "split": FH_FP32_SPLIT, "fp32_split": FH_FP32_SPLIT}
@@ -66,6 +66,9 @@ def load():
                                  ctypes.c_int),
             "fh_eval_deriv": ([vp, vp, i64, i32, vp, i64, vp, vp, vp, i32, vp, sz, vp],
                               ctypes.c_int),
+            "fh_eval_forward": ([vp, vp, i64, i32, vp, i64, vp, i32, vp, sz, vp], ctypes.c_int),
+            "fh_eval_backward_saved": ([vp, i64, i32, vp, i64, vp, vp, vp, vp, i32, vp, sz, vp],
+                                       ctypes.c_int),
             "fh_lebesgue_max": ([vp, i64, i32, vp, i32, i32, vp, vp, vp, i32, vp, sz, vp],
                                 ctypes.c_int),
             "fh_multi_workspace_size": ([i64, i32], sz),
@@ -331,6 +334,52 @@ def eval_backward(nodes, values, d, x, grad_r, *, need_values=True, need_x=True,
     _check(lib.fh_eval_backward(_ptr(xn), _ptr(f), n, int(d), _ptr(t), m, _ptr(g), _ptr(gv),
                                 _ptr(gx), _ptr(gn), prec, _ptr(buf), buf.numel(),
                                 _stream(t.device)), "fh_eval_backward")
+    return gv, gx, gn
+
+
+class Saved:
+    """State of fh_eval_forward for fh_eval_backward_saved: the arguments of
+    the forward and its own workspace (node table, 1/D_p, r_p and the hit
+    data per point).  Keep it, unchanged, until the last backward."""
+
+    def __init__(self, nodes, d, x, precision, ws):
+        self.nodes, self.d, self.x, self.prec, self.ws = nodes, int(d), x, precision, ws
+
+
+def eval_forward(nodes, values, d, x, *, precision="fp64", ws=None):
+    """(r, Saved): r(x) and the state its adjoint needs (fh_eval_forward),
+    kept in ws (a Workspace of its own, grown as needed; a new one when
+    None)."""
+    lib = load()
+    xn, f, t = _f64(nodes, "nodes"), _f64(values, "values"), _f64(x, "x")
+    n, m = xn.numel(), t.numel()
+    if f.numel() != n:
+        raise ValueError("values must match nodes")
+    prec = _prec(precision)
+    r = torch.empty_like(t)
+    ws = ws or Workspace(t.device)
+    buf = ws.reserve(workspace_size(FH_OP_BACKWARD_SAVED, n, m, d, prec))
+    _check(lib.fh_eval_forward(_ptr(xn), _ptr(f), n, int(d), _ptr(t), m, _ptr(r), prec,
+                               _ptr(buf), buf.numel(), _stream(t.device)), "fh_eval_forward")
+    return r, Saved(xn, d, t, prec, ws)
+
+
+def eval_backward_saved(saved, grad_r, *, need_values=True, need_x=True, need_nodes=True):
+    """Adjoint of L = sum_p grad_r[p] r(x_p) from the state of eval_forward
+    (fh_eval_backward_saved): (dL/dvalues, dL/dx, dL/dnodes), None for the
+    ones not requested."""
+    lib = load()
+    xn, t, g = saved.nodes, saved.x, _f64(grad_r, "grad_r")
+    n, m = xn.numel(), t.numel()
+    if g.numel() != m:
+        raise ValueError("grad_r must match x")
+    gv = torch.empty_like(xn) if need_values else None
+    gx = torch.empty_like(t) if need_x else None
+    gn = torch.empty_like(xn) if need_nodes else None
+    buf = saved.ws.buf
+    _check(lib.fh_eval_backward_saved(_ptr(xn), n, saved.d, _ptr(t), m, _ptr(g), _ptr(gv),
+                                      _ptr(gx), _ptr(gn), saved.prec, _ptr(buf), buf.numel(),
+                                      _stream(t.device)), "fh_eval_backward_saved")
     return gv, gx, gn
 
 

@@ -52,6 +52,15 @@ def test_workspace_sizes():
     bw64 = lib.fh_workspace_size(fh.FH_OP_BACKWARD, 2049, 10 ** 6, 4, 0)
     bw32 = lib.fh_workspace_size(fh.FH_OP_BACKWARD, 2049, 10 ** 6, 4, 1)
     assert bw64 > 40 * 10 ** 6 and bw32 > 56 * 10 ** 6
+    # the saved-state adjoint adds four per-point arrays and the point-side
+    # sums of up to 64 node tile groups (binary64); split: as the adjoint
+    sv64 = lib.fh_workspace_size(fh.FH_OP_BACKWARD_SAVED, 2049, 10 ** 6, 4, 0)
+    sv32 = lib.fh_workspace_size(fh.FH_OP_BACKWARD_SAVED, 2049, 10 ** 6, 4, 1)
+    assert bw64 + 32 * 10 ** 6 < sv64 <= bw64 + (32 + 8 * 64) * 10 ** 6 + (1 << 30)
+    assert sv32 == bw32
+    big = lib.fh_workspace_size(fh.FH_OP_BACKWARD_SAVED, 10 ** 5, 10 ** 4, 4, 0)
+    assert 0 < big < lib.fh_workspace_size(fh.FH_OP_BACKWARD, 10 ** 5, 10 ** 4, 4, 0) + \
+        (32 + 8 * 64) * (10 ** 4 + 4096) + (1 << 30)
     # invalid problems report 0
     assert lib.fh_workspace_size(fh.FH_OP_EVAL, 0, 10, 0, 0) == 0
     assert lib.fh_workspace_size(fh.FH_OP_EVAL, 5, 10, 5, 0) == 0
@@ -87,6 +96,36 @@ def test_eval_host_validation(args, code):
     got = lib.fh_eval(a["nodes"], a["values"], a["n"], a["d"], a["x"], a["m"], a["r"], a["lam"],
                       a["w"], a["prec"], a["ws"], a["ws_bytes"], a["stream"])
     assert got == code
+
+
+def test_saved_adjoint_host_validation():
+    """fh_eval_forward / fh_eval_backward_saved reject bad host arguments
+    before any launch."""
+    lib = fh.load()
+    ws = 1 << 40
+    fwd = lambda **k: lib.fh_eval_forward(*[k.get(a, b) for a, b in (
+        ("nodes", P), ("values", P), ("n", 10), ("d", 3), ("x", P), ("m", 100), ("r", P2),
+        ("prec", 0), ("ws", P), ("ws_bytes", ws), ("stream", None))])
+    bwd = lambda **k: lib.fh_eval_backward_saved(*[k.get(a, b) for a, b in (
+        ("nodes", P), ("n", 10), ("d", 3), ("x", P), ("m", 100), ("g", P2), ("gv", P2),
+        ("gx", P2), ("gn", P2), ("prec", 0), ("ws", P), ("ws_bytes", ws), ("stream", None))])
+    for call in (fwd, bwd):
+        assert call(nodes=None) == fh.FH_E_ARG
+        assert call(d=10) == fh.FH_E_DEGREE
+        assert call(m=-1) == fh.FH_E_ARG
+        assert call(x=None) == fh.FH_E_ARG
+        assert call(prec=3) == fh.FH_E_ARG
+        assert call(ws=None) == fh.FH_E_WORKSPACE
+        assert call(ws_bytes=4096) == fh.FH_E_WORKSPACE
+        assert call(ws=ctypes.c_void_p(0x100008)) == fh.FH_E_WORKSPACE
+    assert fwd(values=None) == fh.FH_E_ARG
+    assert fwd(r=None) == fh.FH_E_ARG
+    assert bwd(g=None) == fh.FH_E_ARG
+    # the forward's size is the one checked
+    need = lib.fh_workspace_size(fh.FH_OP_BACKWARD_SAVED, 10, 100, 3, 0)
+    assert need > lib.fh_workspace_size(fh.FH_OP_BACKWARD, 10, 100, 3, 0)
+    assert fwd(ws_bytes=need - 1) == fh.FH_E_WORKSPACE
+    assert bwd(ws_bytes=need - 1) == fh.FH_E_WORKSPACE
 
 
 def test_weights_and_lebesgue_host_validation():

@@ -35,14 +35,23 @@ def _np(t):
     return None if t is None else t.cpu().numpy()
 
 
-def _gpu_bwd(nodes, vals, d, pts, g):
-    gv, gx, gn = fh.eval_backward(_t(nodes), _t(vals), d, _t(pts), _t(g))
+def _gpu_bwd(nodes, vals, d, pts, g, saved=False):
+    """The two-pass adjoint (fh_eval_backward), or with saved=True the
+    saved-state one (fh_eval_forward, then fh_eval_backward_saved)."""
+    if saved:
+        _, st = fh.eval_forward(_t(nodes), _t(vals), d, _t(pts))
+        gv, gx, gn = fh.eval_backward_saved(st, _t(g))
+    else:
+        gv, gx, gn = fh.eval_backward(_t(nodes), _t(vals), d, _t(pts), _t(g))
     torch.cuda.synchronize()
     return _np(gv), _np(gx), _np(gn)
 
 
-def _check_against_oracle(nodes, vals, d, pts, g, dense_chain=True):
-    gv, gx, gn = _gpu_bwd(nodes, vals, d, pts, g)
+MODES = pytest.mark.parametrize("saved", [False, True], ids=["two_pass", "saved"])
+
+
+def _check_against_oracle(nodes, vals, d, pts, g, dense_chain=True, saved=False):
+    gv, gx, gn = _gpu_bwd(nodes, vals, d, pts, g, saved)
     o = oracle.backward(nodes, vals, d, pts, g)
     scales = metrics.grad_scales(nodes, vals, d, pts, g)
     err = metrics.grad_errors(gv, gx, gn, o, scales, *((nodes, d) if dense_chain else ()))
@@ -51,30 +60,33 @@ def _check_against_oracle(nodes, vals, d, pts, g, dense_chain=True):
 
 
 # ------------------------------------------------------------- parity --
-def test_grad_workload_reduced():
+@MODES
+def test_grad_workload_reduced(saved):
     c = inputs.grad_workload(n=513, m=6007)
-    _check_against_oracle(c["nodes"], c["values"], c["d"], c["points"], c["grad"])
+    _check_against_oracle(c["nodes"], c["values"], c["d"], c["points"], c["grad"], saved=saved)
 
 
+@MODES
 @pytest.mark.parametrize("n,d", [(1, 0), (2, 1), (5, 0), (5, 4), (64, 3), (65, 7), (130, 10)])
-def test_shapes_with_hits_and_nan(n, d):
+def test_shapes_with_hits_and_nan(n, d, saved):
     g = np.random.default_rng(100 + n + d)
     nodes = inputs.equispaced(n) + (g.uniform(-0.2, 0.2, n) * (2.0 / max(n - 1, 1)) if n > 2 else 0)
     nodes = np.sort(nodes)
     vals = g.standard_normal(n)
     pts = np.concatenate([g.uniform(-1.1, 1.1, size=1001), nodes[:: max(1, n // 5)], [np.nan]])
     grad = g.standard_normal(pts.size)
-    gv, gx, gn, o = _check_against_oracle(nodes, vals, d, pts, grad)
+    gv, gx, gn, o = _check_against_oracle(nodes, vals, d, pts, grad, saved=saved)
     assert np.isnan(gx[-1])
 
 
-def test_full_size_identities_and_sampled_points():
+@MODES
+def test_full_size_identities_and_sampled_points(saved):
     """The full 10^6-point workload: identities that hold at any size, and
     dL/dx_p against the oracle on a seeded sample of points (each dL/dx_p
     depends on its own point only)."""
     c = inputs.grad_workload()
     nodes, vals, d, pts, g = c["nodes"], c["values"], c["d"], c["points"], c["grad"]
-    gv, gx, gn = _gpu_bwd(nodes, vals, d, pts, g)
+    gv, gx, gn = _gpu_bwd(nodes, vals, d, pts, g, saved)
     assert np.all(np.isfinite(gv)) and np.all(np.isfinite(gx)) and np.all(np.isfinite(gn))
     # partition of unity: sum_k dL/df_k = sum_p g_p
     assert abs(gv.sum() - g.sum()) <= 1e-11 * np.abs(g).sum()
@@ -89,7 +101,8 @@ def test_full_size_identities_and_sampled_points():
     metrics.check_grad(metrics.grad_errors(None, gx[idx], None, o, scales), TOL)
 
 
-def test_polynomial_data():
+@MODES
+def test_polynomial_data(saved):
     """Data from a polynomial of degree <= d: dL/dx_p = g_p p'(x_p) and
     dL/dx_k + p'(x_k) dL/df_k = 0."""
     g = np.random.default_rng(3)
@@ -99,20 +112,21 @@ def test_polynomial_data():
     vals = np.polyval(poly, nodes)
     pts = g.uniform(-1, 1, size=20000)
     grad = g.standard_normal(pts.size)
-    gv, gx, gn = _gpu_bwd(nodes, vals, d, pts, grad)
+    gv, gx, gn = _gpu_bwd(nodes, vals, d, pts, grad, saved)
     dp = grad * np.polyval(np.polyder(poly), pts)
     assert np.allclose(gx, dp, rtol=1e-9, atol=1e-9 * np.abs(dp).max())
     moved = gn + np.polyval(np.polyder(poly), nodes) * gv
     assert np.abs(moved).max() <= 1e-10 * (np.abs(gn).sum() + np.abs(gv).sum())
 
 
-def test_central_differences():
+@MODES
+def test_central_differences(saved):
     """Central differences (h = 1e-6) of the HIP forward pass (weights
     recomputed) against the adjoint, within 10 (h^2 M3/6 + 2u sum|g r|/h),
     M3 estimated from differences at 10h."""
     c = inputs.grad_workload(n=257, m=4001)
     nodes, vals, d, pts, g = c["nodes"], c["values"], c["d"], c["points"], c["grad"]
-    gv, gx, gn = _gpu_bwd(nodes, vals, d, pts, g)
+    gv, gx, gn = _gpu_bwd(nodes, vals, d, pts, g, saved)
     xn, f, t, gt = _t(nodes), _t(vals), _t(pts), _t(g)
 
     def L(nodes_=None, vals_=None, pts_=None):
@@ -142,10 +156,11 @@ def test_central_differences():
             assert abs(a - ref[k]) <= tol, (kind, k, a, ref[k], tol)
 
 
-def test_deterministic():
+@MODES
+def test_deterministic(saved):
     c = inputs.grad_workload(n=1025, m=100003)
-    a = _gpu_bwd(c["nodes"], c["values"], c["d"], c["points"], c["grad"])
-    b = _gpu_bwd(c["nodes"], c["values"], c["d"], c["points"], c["grad"])
+    a = _gpu_bwd(c["nodes"], c["values"], c["d"], c["points"], c["grad"], saved)
+    b = _gpu_bwd(c["nodes"], c["values"], c["d"], c["points"], c["grad"], saved)
     for u, v in zip(a, b):
         assert np.array_equal(u, v)
 
@@ -180,9 +195,89 @@ def test_autograd_function_and_gradcheck():
     x = _t(g.uniform(-1, 1, 25)).requires_grad_()
     assert torch.autograd.gradcheck(lambda a, b, c: FhEval.apply(a, b, c, 3), (nodes, vals, x),
                                     eps=1e-6, atol=1e-6, rtol=1e-5)
-    # backward of a loss equals fh_eval_backward
-    r = interpolate(nodes, vals, x, 3)
+    # backward of a loss equals the adjoint calls: fh_eval_backward without
+    # saved state, fh_eval_backward_saved (the default) with it
     w = torch.linspace(-1, 1, 25, dtype=torch.float64, device=DEV)
+    r = interpolate(nodes, vals, x, 3, saved=False)
     (r * w).sum().backward()
     gv, gx, gn = fh.eval_backward(nodes.detach(), vals.detach(), 3, x.detach(), w)
     assert torch.equal(nodes.grad, gn) and torch.equal(vals.grad, gv) and torch.equal(x.grad, gx)
+    for a in (nodes, vals, x):
+        a.grad = None
+    r = interpolate(nodes, vals, x, 3)
+    (r * w).sum().backward()
+    r2, st = fh.eval_forward(nodes.detach(), vals.detach(), 3, x.detach())
+    assert torch.equal(r, r2)
+    gv, gx, gn = fh.eval_backward_saved(st, w)
+    assert torch.equal(nodes.grad, gn) and torch.equal(vals.grad, gv) and torch.equal(x.grad, gx)
+    assert torch.autograd.gradcheck(lambda a, b, c: FhEval.apply(a, b, c, 3, "fp64", False),
+                                    (nodes, vals, x), eps=1e-6, atol=1e-6, rtol=1e-5)
+
+
+# ------------------------------------------------- saved-state adjoint --
+@pytest.mark.parametrize("need", [(True, False, False), (False, True, False), (False, False, True),
+                                  (True, True, False), (True, False, True), (False, True, True)])
+def test_saved_partial_outputs_match_full(need):
+    """fh_eval_backward_saved computes only what is asked (dL/dx_p alone runs
+    the point side of the fused pass without node sums) and each output has
+    the bits of the full call, hits and a NaN point included."""
+    c = inputs.grad_workload(n=129, m=5000)
+    pts = c["points"].copy()
+    pts[:5] = c["nodes"][[0, 3, 64, 100, 128]]
+    pts[5] = np.nan
+    _, st = fh.eval_forward(_t(c["nodes"]), _t(c["values"]), c["d"], _t(pts))
+    g = _t(c["grad"])
+    full = fh.eval_backward_saved(st, g)
+    part = fh.eval_backward_saved(st, g, need_values=need[0], need_x=need[1], need_nodes=need[2])
+    assert torch.isnan(full[1][5])
+    for want, a, b in zip(need, part, full):
+        if want:
+            assert torch.equal(torch.isnan(a), torch.isnan(b))
+            assert torch.equal(a.nan_to_num(0.0), b.nan_to_num(0.0))
+        else:
+            assert a is None
+
+
+def test_saved_state_is_reusable():
+    """The backward reads the forward's state without changing it: two
+    backwards with different loss weights in either order give the same
+    bits as each alone."""
+    c = inputs.grad_workload(n=300, m=20011)
+    _, st = fh.eval_forward(_t(c["nodes"]), _t(c["values"]), c["d"], _t(c["points"]))
+    g1 = _t(c["grad"])
+    g2 = _t(np.random.default_rng(4).standard_normal(c["points"].size))
+    a1 = fh.eval_backward_saved(st, g1)
+    a2 = fh.eval_backward_saved(st, g2)
+    b1 = fh.eval_backward_saved(st, g1)
+    for u, v in zip(a1, b1):
+        assert torch.equal(u, v)
+    _, st2 = fh.eval_forward(_t(c["nodes"]), _t(c["values"]), c["d"], _t(c["points"]))
+    for u, v in zip(a2, fh.eval_backward_saved(st2, g2)):
+        assert torch.equal(u, v)
+
+
+def test_saved_forward_values():
+    """r of fh_eval_forward against the oracle at the binary64 bar, hits and
+    non-finite points included."""
+    c = inputs.grad_workload(n=1025, m=30000)
+    pts = c["points"].copy()
+    pts[:4] = c["nodes"][[0, 1, 512, 1024]]
+    pts[4:7] = [np.nan, np.inf, -np.inf]
+    r, _ = fh.eval_forward(_t(c["nodes"]), _t(c["values"]), c["d"], _t(pts))
+    r = _np(r)
+    ro, lo, so = oracle.evaluate(c["nodes"], c["values"], c["d"], pts[7:])
+    assert np.array_equal(r[:4], c["values"][[0, 1, 512, 1024]])
+    assert np.all(np.isnan(r[4:7]))
+    metrics.check_fp64(metrics.parity(r[7:], None, ro, lo, so))
+
+
+@pytest.mark.parametrize("n", [8191, 8193, 9000])
+def test_saved_many_node_tiles(n):
+    """More node tiles than tile groups (n > 64 tiles of 128 nodes): each
+    wave adds the point-side sums of several tiles in place."""
+    g = np.random.default_rng(n)
+    nodes = inputs.equispaced(n)
+    vals = np.sin(7 * nodes) + 0.1 * g.standard_normal(n)
+    pts = np.concatenate([g.uniform(-1, 1, 1500), nodes[::1000]])
+    grad = g.standard_normal(pts.size)
+    _check_against_oracle(nodes, vals, 3, pts, grad, saved=True)
