@@ -143,11 +143,12 @@ def workspace_size(op, n, m, d, precision="fp64"):
 
 
 class Workspace:
-    """A zeroed, 256-byte aligned device workspace that grows on demand.
+    """A 256-byte aligned device workspace that grows on demand.
 
-    The first 256 bytes hold the device status word, so the buffer is
-    zero-filled when (re)allocated.  Calls that share a Workspace must be
-    ordered on one stream."""
+    The first 256 bytes hold the device status word and are zero-filled when
+    the buffer is (re)allocated; the library writes everything else before
+    reading it, so the rest is left as allocated.  Calls that share a
+    Workspace must be ordered on one stream."""
 
     def __init__(self, device=None, nbytes=0):
         self.device = torch.device(device) if device is not None else torch.device("cuda")
@@ -157,7 +158,8 @@ class Workspace:
 
     def reserve(self, nbytes):
         if self.buf is None or self.buf.numel() < nbytes:
-            self.buf = torch.zeros(max(int(nbytes), 256), dtype=torch.uint8, device=self.device)
+            self.buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=self.device)
+            self.buf[:256].zero_()
             assert self.buf.data_ptr() % 256 == 0
         return self.buf
 
