@@ -378,7 +378,8 @@ fh_status fh_eval_forward(const double* nodes, const double* values, int64_t n, 
   hipError_t e = launch_pack(nodes, values, nullptr, n, d, t, split, status, s);
   if (e == hipSuccess && m > 0) {
     if (split) {
-      const EvalConfig cfg = choose_eval_config(prec, n, d, m, true, false);
+      // as fh_eval_prepared chooses (the same r bits as fh_eval)
+      const EvalConfig cfg = choose_eval_config(prec, n, 0, m, true, false);
       e = launch_eval_split(x, m, t, n, reinterpret_cast<int32_t*>(status) + 1, status + 3,
                             r_out, nullptr, cfg, s);
     } else {

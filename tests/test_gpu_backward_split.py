@@ -136,3 +136,6 @@ def test_autograd_split():
     gv, gx, gn = fh.eval_backward(nodes.detach(), vals.detach(), 3, x.detach(), w,
                                   precision="split")
     assert torch.equal(nodes.grad, gn) and torch.equal(vals.grad, gv) and torch.equal(x.grad, gx)
+    # the split forward of the saved-state pair is fh_eval's split evaluation
+    assert torch.equal(r.detach(), fh.evaluate(nodes.detach(), vals.detach(), 3, x.detach(),
+                                               precision="split"))
