@@ -300,8 +300,9 @@ fh_status fh_eval_backward(const double* nodes, const double* values, int64_t n,
 /* The adjoint in two steps that share their work, for callers that run a
  * forward evaluation and later its adjoint (automatic differentiation).
  *
- * fh_eval_forward: r(x_p) into r_out [m] (as fh_eval, binary64 sums in
- * groups of eight reciprocals) and, in ws, the node table and what the
+ * fh_eval_forward: r(x_p) into r_out [m] (binary64: the bits of fh_eval
+ * with launch variant 4, sums in node order with groups of eight
+ * reciprocals; split: fh_eval's split evaluation) and, in ws, the node table and what the
  * adjoint needs per point, for unit loss weights: 1/D_p, r_p, and at an exact
  * hit x_p == x_j the flag and the node formula r'(x_j) (Schneider & Werner
  * 1986).  NaN and infinite points give r = NaN.

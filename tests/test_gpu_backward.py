@@ -271,6 +271,25 @@ def test_saved_forward_values():
     metrics.check_fp64(metrics.parity(r[7:], None, ro, lo, so))
 
 
+def test_saved_forward_bits_of_eval_variant():
+    """fh_eval_forward's r has the bits of fh_eval with binary64 launch
+    variant 4 (two points per lane, groups of eight, plain sums: the same
+    operations in the same order), hits and NaN included."""
+    c = inputs.grad_workload(n=777, m=20011)
+    pts = c["points"].copy()
+    pts[:3] = c["nodes"][[0, 5, 776]]
+    pts[3] = np.nan
+    args = (_t(c["nodes"]), _t(c["values"]), c["d"], _t(pts))
+    r, _ = fh.eval_forward(*args)
+    fh.tune_force("fp64", 4)
+    try:
+        r4 = fh.evaluate(*args)
+    finally:
+        fh.tune_force("fp64", -1)
+    assert torch.equal(torch.isnan(r), torch.isnan(r4))
+    assert torch.equal(r.nan_to_num(0.0), r4.nan_to_num(0.0))
+
+
 @pytest.mark.parametrize("n", [8191, 8193, 9000])
 def test_saved_many_node_tiles(n):
     """More node tiles than tile groups (n > 64 tiles of 128 nodes): each
