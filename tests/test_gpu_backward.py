@@ -271,6 +271,23 @@ def test_saved_forward_values():
     metrics.check_fp64(metrics.parity(r[7:], None, ro, lo, so))
 
 
+@MODES
+def test_no_points(saved):
+    """m = 0: every node gradient is zero, dL/dx is empty."""
+    c = inputs.grad_workload(n=65, m=10)
+    nodes, vals = _t(c["nodes"]), _t(c["values"])
+    x = torch.empty(0, dtype=torch.float64, device=DEV)
+    if saved:
+        r, st = fh.eval_forward(nodes, vals, c["d"], x)
+        assert r.numel() == 0
+        gv, gx, gn = fh.eval_backward_saved(st, x)
+    else:
+        gv, gx, gn = fh.eval_backward(nodes, vals, c["d"], x, x)
+    torch.cuda.synchronize()
+    assert gx.numel() == 0
+    assert torch.count_nonzero(gv) == 0 and torch.count_nonzero(gn) == 0
+
+
 def test_saved_forward_bits_of_eval_variant():
     """fh_eval_forward's r has the bits of fh_eval with binary64 launch
     variant 4 (two points per lane, groups of eight, plain sums: the same
