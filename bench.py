@@ -444,11 +444,24 @@ def run_backward_form(dev, reps, with_cpu):
                           reps)
         ms_bsx = _time_ms(lambda: fh.eval_backward_saved(st, g, need_values=False,
                                                          need_nodes=False), reps)
+        # ... and with the derivative kept by the forward (dL/dx = g r')
+        wsd = fh.Workspace(dev, fh.workspace_size(fh.FH_OP_BACKWARD_SAVED, n, m, c["d"], prec))
+        ms_fd = _time_ms(lambda: fh.eval_forward(nodes, vals, c["d"], x, derivative=True,
+                                                 precision=prec, ws=wsd), reps)
+        _, std = fh.eval_forward(nodes, vals, c["d"], x, derivative=True, precision=prec,
+                                 ws=wsd)
+        ms_bd = _time_ms(lambda: fh.eval_backward_saved(std, g), reps)
+        ms_bdx = _time_ms(lambda: fh.eval_backward_saved(std, g, need_values=False,
+                                                         need_nodes=False), reps)
         out[prec]["saved_state"] = {
             "forward_ms": ms_fs, "backward_ms": ms_bs, "backward_values_only_ms": ms_bsv,
             "backward_points_only_ms": ms_bsx,
             "backward_over_forward": ms_bs / ms_fs,
-            "step_ms": ms_fs + ms_bs, "step_ms_without_state": ms_f + ms_b}
+            "step_ms": ms_fs + ms_bs, "step_ms_without_state": ms_f + ms_b,
+            "with_derivative": {"forward_ms": ms_fd, "backward_ms": ms_bd,
+                                "backward_points_only_ms": ms_bdx,
+                                "backward_over_forward": ms_bd / ms_fd,
+                                "step_ms": ms_fd + ms_bd}}
         if ref is not None:
             got = fh.eval_backward(nodes, vals, c["d"], x, g, precision=prec, ws=ws)
             out[prec]["max_scaled_error"] = {
@@ -457,10 +470,11 @@ def run_backward_form(dev, reps, with_cpu):
             _, dr = fh.eval_deriv(nodes, vals, c["d"], x, precision=prec, ws=ws)
             out[prec]["max_scaled_error"]["deriv"] = float(
                 np.max(np.abs(dr.cpu().numpy() - dr_o) / np.maximum(s_o, 1e-300)))
-            got = fh.eval_backward_saved(st, g)
-            out[prec]["saved_state"]["max_scaled_error"] = {
-                name: float(np.max(np.abs(t.cpu().numpy() - r) / np.maximum(s, 1e-300)))
-                for name, t, (r, s) in zip(("dvalues", "dpoints", "dnodes"), got, ref)}
+            for key, state in (("max_scaled_error", st), ("max_scaled_error_with_derivative", std)):
+                got = fh.eval_backward_saved(state, g)
+                out[prec]["saved_state"][key] = {
+                    name: float(np.max(np.abs(t.cpu().numpy() - r) / np.maximum(s, 1e-300)))
+                    for name, t, (r, s) in zip(("dvalues", "dpoints", "dnodes"), got, ref)}
     out["split_backward_speedup_vs_fp64"] = out["fp64"]["backward_ms"] / out["split"]["backward_ms"]
     return out
 

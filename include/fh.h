@@ -298,39 +298,45 @@ fh_status fh_eval_backward(const double* nodes, const double* values, int64_t n,
                            size_t ws_bytes, void* stream);
 
 /* The adjoint in two steps that share their work, for callers that run a
- * forward evaluation and later its adjoint (automatic differentiation).
+ * forward evaluation and later its adjoint (automatic differentiation; the
+ * saved-state form of the adjoint of L = sum_p grad_r[p] r(x_p)).
  *
- * fh_eval_forward: r(x_p) into r_out [m] (binary64: the bits of fh_eval
- * with launch variant 4, sums in node order with groups of eight
- * reciprocals; split: fh_eval's split evaluation) and, in ws, the node table and what the
- * adjoint needs per point, for unit loss weights: 1/D_p, r_p, and at an exact
- * hit x_p == x_j the flag and the node formula r'(x_j) (Schneider & Werner
- * 1986).  NaN and infinite points give r = NaN.
+ * fh_eval_forward: r(x_p) into r_out [m] and, in ws, the node table and what
+ * the adjoint needs per point for unit loss weights: 1/D_p, r_p, and at an
+ * exact hit x_p == x_j the flag and the node formula r'(x_j) (Schneider &
+ * Werner 1986).  NaN and infinite points give r = NaN.  dr_out [m]
+ * (nullable): also the derivative r'(x_p) there, as fh_eval_deriv computes
+ * it (the same bits), for a caller that will want dL/dx_p.  Binary64 r has
+ * the bits of fh_eval with launch variant 4 without dr_out and of
+ * fh_eval_deriv with it; split r: fh_eval's split evaluation, or
+ * fh_eval_deriv's with dr_out.
  *
  * fh_eval_backward_saved: the gradients of fh_eval_backward (same
  * definitions, hit rules, outputs and NULL conventions) from that state and
- * the loss weights grad_r [m], without evaluating N_p and D_p again: one pass
- * over the (point, node) pairs forms each reciprocal once and adds both the
- * per-node sums S1..S4 (in a fixed order) and the per-point sums of
- * dL/dx_p (across the lanes of a wave, then over node tile groups in a
- * fixed order; deterministic).  The state is read, not changed: the backward
- * may run any number of times on one forward.
+ * the loss weights grad_r [m], without evaluating N_p and D_p again.  dr
+ * (nullable): the forward's dr_out; with it dL/dx_p = grad_r[p] dr[p] and
+ * the node gradients come from one pass over the (point, node) pairs with
+ * the per-node sums S1..S4; without it, binary64, that same pass also forms
+ * dL/dx_p, each reciprocal formed once for both: per point, the terms over
+ * the lane's nodes, then across the wave (an LDS transpose) and over node
+ * tile groups, all in a fixed order (deterministic).  The state is read, not
+ * changed: the backward may run any number of times on one forward.
  *
  * Both take ws of fh_workspace_size(FH_OP_BACKWARD_SAVED, n, m, d, prec) and
  * must see the same nodes, n, d, x, m and prec; values are read by the
  * forward only.  Between the two calls the workspace must not be used by
- * another call.  prec = FH_FP32_SPLIT: the forward is the split evaluation
- * of fh_eval and the backward runs the split fh_eval_backward on the node
- * table the forward packed (no shared per-point state).  Errors as in
+ * another call.  prec = FH_FP32_SPLIT: the backward runs the split
+ * fh_eval_backward passes that the requested gradients need on the node table
+ * the forward packed (no shared per-point state).  Errors as in
  * fh_eval_backward; a backward on a workspace its forward did not fill
  * gives unspecified values. */
 fh_status fh_eval_forward(const double* nodes, const double* values, int64_t n, int32_t d,
-                          const double* x, int64_t m, double* r_out, int32_t prec, void* ws,
-                          size_t ws_bytes, void* stream);
+                          const double* x, int64_t m, double* r_out, double* dr_out,
+                          int32_t prec, void* ws, size_t ws_bytes, void* stream);
 fh_status fh_eval_backward_saved(const double* nodes, int64_t n, int32_t d, const double* x,
-                                 int64_t m, const double* grad_r, double* grad_values,
-                                 double* grad_x, double* grad_nodes, int32_t prec, void* ws,
-                                 size_t ws_bytes, void* stream);
+                                 int64_t m, const double* dr, const double* grad_r,
+                                 double* grad_values, double* grad_x, double* grad_nodes,
+                                 int32_t prec, void* ws, size_t ws_bytes, void* stream);
 
 /* Batched evaluation of `count` independent interpolants of uneven sizes in
  * one captured HIP graph.  Instance i owns nodes/values

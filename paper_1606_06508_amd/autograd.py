@@ -1,9 +1,10 @@
 """torch.autograd front of the HIP path: r = FhEval.apply(nodes, values, x, d).
 
 The forward pass is fh_eval_forward, which evaluates r and keeps, in its own
-workspace, what the adjoint needs per point (1/D, r and the hit data); the
-backward pass is fh_eval_backward_saved, which forms every reciprocal
-1/(x_p - x_k) once for the node sums and dL/dx_p together.  The gradients are
+workspace, what the adjoint needs per point (1/D, r and the hit data) and,
+when x requires a gradient, the derivative r'(x); the backward pass is
+fh_eval_backward_saved: dL/dx = grad_r r'(x) and one pass over the (point,
+node) pairs for the node sums.  The gradients are
 with respect to the values, the evaluation points and the nodes (total
 derivative, through the weights).  No gradient flows to d (an integer).
 With saved=False the forward is fh_eval and the backward the two-pass
@@ -21,7 +22,8 @@ class FhEval(torch.autograd.Function):
         ctx.d = int(d)
         ctx.precision = precision
         if saved:
-            r, ctx.state = fh.eval_forward(nodes, values, int(d), x, precision=precision)
+            r, ctx.state = fh.eval_forward(nodes, values, int(d), x, precision=precision,
+                                           derivative=ctx.needs_input_grad[2])
         else:
             r = fh.evaluate(nodes, values, int(d), x, precision=precision)
             ctx.state = None

@@ -360,8 +360,8 @@ fh_status fh_eval_backward(const double* nodes, const double* values, int64_t n,
 }
 
 fh_status fh_eval_forward(const double* nodes, const double* values, int64_t n, int32_t d,
-                          const double* x, int64_t m, double* r_out, int32_t prec, void* ws,
-                          size_t ws_bytes, void* stream) {
+                          const double* x, int64_t m, double* r_out, double* dr_out,
+                          int32_t prec, void* ws, size_t ws_bytes, void* stream) {
   fh_status st = check_problem(nodes, n, d);
   if (st != FH_OK) return st;
   if (values == nullptr || m < 0 || (m > 0 && (x == nullptr || r_out == nullptr)))
@@ -377,24 +377,27 @@ fh_status fh_eval_forward(const double* nodes, const double* values, int64_t n, 
   uint32_t* status = static_cast<uint32_t*>(ws);
   hipError_t e = launch_pack(nodes, values, nullptr, n, d, t, split, status, s);
   if (e == hipSuccess && m > 0) {
-    if (split) {
+    if (split && dr_out) {
+      e = launch_eval_deriv_split(x, m, t, n, reinterpret_cast<int32_t*>(status) + 1, r_out,
+                                  dr_out, s);
+    } else if (split) {
       // as fh_eval_prepared chooses (the same r bits as fh_eval)
       const EvalConfig cfg = choose_eval_config(prec, n, 0, m, true, false);
       e = launch_eval_split(x, m, t, n, reinterpret_cast<int32_t*>(status) + 1, status + 3,
                             r_out, nullptr, cfg, s);
     } else {
-      e = launch_forward_saved(x, m, t, n, b, r_out, s);
+      e = launch_forward_saved(x, m, t, n, b, r_out, dr_out, s);
     }
   } else if (e == hipSuccess && !split) {
-    e = launch_forward_saved(x, 0, t, n, b, nullptr, s);  // padding records only
+    e = launch_forward_saved(x, 0, t, n, b, nullptr, nullptr, s);  // padding records only
   }
   return finish(e, ws, s);
 }
 
 fh_status fh_eval_backward_saved(const double* nodes, int64_t n, int32_t d, const double* x,
-                                 int64_t m, const double* grad_r, double* grad_values,
-                                 double* grad_x, double* grad_nodes, int32_t prec, void* ws,
-                                 size_t ws_bytes, void* stream) {
+                                 int64_t m, const double* dr, const double* grad_r,
+                                 double* grad_values, double* grad_x, double* grad_nodes,
+                                 int32_t prec, void* ws, size_t ws_bytes, void* stream) {
   fh_status st = check_problem(nodes, n, d);
   if (st != FH_OK) return st;
   if (m < 0 || (m > 0 && (x == nullptr || grad_r == nullptr))) return FH_E_ARG;
@@ -407,12 +410,21 @@ fh_status fh_eval_backward_saved(const double* nodes, int64_t n, int32_t d, cons
   const bool split = prec == FH_FP32_SPLIT;
   layout_backward(ws, n, m, split, &t, &b, true);
   uint32_t* status = static_cast<uint32_t*>(ws);
-  const hipError_t e =
-      split ? launch_backward(nodes, x, grad_r, n, d, m, t, b,
-                              reinterpret_cast<int32_t*>(status) + 1, grad_values,
-                              m > 0 ? grad_x : nullptr, grad_nodes, s)
-            : launch_backward_saved(nodes, x, grad_r, n, d, m, t, b, grad_values, grad_x,
-                                    grad_nodes, s);
+  hipError_t e = hipSuccess;
+  if (split) {
+    double* dx = m > 0 ? grad_x : nullptr;
+    if (dx && dr) {  // dL/dx_p = g_p r'(x_p) from the forward's derivative
+      e = launch_point_grad_from_derivative(grad_r, dr, m, dx, s);
+      dx = nullptr;
+    }
+    if (e == hipSuccess && (dx || grad_values || grad_nodes))
+      e = launch_backward(nodes, x, grad_r, n, d, m, t, b,
+                          reinterpret_cast<int32_t*>(status) + 1, grad_values, dx, grad_nodes,
+                          s);
+  } else {
+    e = launch_backward_saved(nodes, x, dr, grad_r, n, d, m, t, b, grad_values, grad_x,
+                              grad_nodes, s);
+  }
   return finish(e, ws, s);
 }
 

@@ -268,6 +268,16 @@ __global__ void __launch_bounds__(256)
   rec.hgr[p] = hit ? gp * saved.hgr[p] : 0.0;
 }
 
+// Saved-state adjoint whose forward kept r'(x_p): dL/dx_p = g_p r'(x_p) (NaN
+// at a NaN or infinite point, whose r' is NaN; the node formula at a hit).
+__global__ void __launch_bounds__(256)
+    k_bwd_point_grad_from_derivative(const double* __restrict__ g,
+                                     const double* __restrict__ dr, int64_t m,
+                                     double* __restrict__ dx) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < m) dx[p] = g[p] * dr[p];
+}
+
 // Saved-state adjoint, after pass 2: dL/dx_p = c_p times the point-side sum
 // over the tile groups (fixed order); g_p r'(x_j) at a hit, NaN at a NaN or
 // infinite point.
@@ -583,25 +593,41 @@ static hipError_t launch_node_tail(const double* nodes, int64_t n, int32_t d, co
 
 // --------------------------------------------------- saved-state adjoint --
 hipError_t launch_forward_saved(const double* x, int64_t m, const NodeTable& t, int64_t n,
-                                const BackwardBufs& b, double* r, hipStream_t s) {
+                                const BackwardBufs& b, double* r, double* dr, hipStream_t s) {
   const BackwardPlan& p = b.plan;
   if (p.groups <= 0) return hipErrorInvalidValue;
   constexpr int P = 2;
   const dim3 grid((unsigned)((p.m_pad + 256 * P - 1) / (256 * P)));
-  k_bwd_points<P, false, false, true><<<grid, 256, 0, s>>>(
-      x, nullptr, m, p.m_pad, t.x, t.w, t.wf, t.f, t.n_pad, n, nullptr, b.saved, r);
+  if (dr)  // E and F as well: r' = (r E - F) / D, the derivative pass's bits
+    k_bwd_points<P, false, true, true><<<grid, 256, 0, s>>>(
+        x, nullptr, m, p.m_pad, t.x, t.w, t.wf, t.f, t.n_pad, n, dr, b.saved, r);
+  else
+    k_bwd_points<P, false, false, true><<<grid, 256, 0, s>>>(
+        x, nullptr, m, p.m_pad, t.x, t.w, t.wf, t.f, t.n_pad, n, nullptr, b.saved, r);
   return hipGetLastError();
 }
 
-hipError_t launch_backward_saved(const double* nodes, const double* x, const double* g,
-                                 int64_t n, int32_t d, int64_t m, const NodeTable& t,
-                                 const BackwardBufs& b, double* df, double* dx, double* dxn,
-                                 hipStream_t s) {
+hipError_t launch_point_grad_from_derivative(const double* g, const double* dr, int64_t m,
+                                             double* dx, hipStream_t s) {
+  if (m == 0) return hipSuccess;
+  k_bwd_point_grad_from_derivative<<<dim3((unsigned)((m + 255) / 256)), 256, 0, s>>>(g, dr, m,
+                                                                                  dx);
+  return hipGetLastError();
+}
+
+hipError_t launch_backward_saved(const double* nodes, const double* x, const double* dr,
+                                 const double* g, int64_t n, int32_t d, int64_t m,
+                                 const NodeTable& t, const BackwardBufs& b, double* df,
+                                 double* dx, double* dxn, hipStream_t s) {
   const BackwardPlan& p = b.plan;
   if (p.groups <= 0) return hipErrorInvalidValue;
   if (m == 0) dx = nullptr;  // no points: node sums of the padding records (zeros) only
-  if (df == nullptr && dx == nullptr && dxn == nullptr) return hipSuccess;
   hipError_t e;
+  if (dx && dr) {  // the forward kept r': no point-side sums in the pass below
+    if ((e = launch_point_grad_from_derivative(g, dr, m, dx, s)) != hipSuccess) return e;
+    dx = nullptr;
+  }
+  if (df == nullptr && dx == nullptr && dxn == nullptr) return hipSuccess;
   k_bwd_scale_records<<<dim3((unsigned)((p.m_pad + 255) / 256)), 256, 0, s>>>(b.saved, g, m,
                                                                               p.m_pad, b.rec);
   if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -172,12 +172,17 @@ hipError_t launch_backward(const double* nodes, const double* x, const double* g
 // Saved-state adjoint (binary64): the forward writes r and b.saved; the
 // backward scales the saved records by g and runs one fused pass over the
 // (point, node) pairs for the node sums and dL/dx_p together.
+// dr (nullable): the forward also writes r'(x_p) there (E and F summed too),
+// and the backward then takes dL/dx_p = g_p r'(x_p) from it.
 hipError_t launch_forward_saved(const double* x, int64_t m, const NodeTable& t, int64_t n,
-                                const BackwardBufs& b, double* r, hipStream_t s);
-hipError_t launch_backward_saved(const double* nodes, const double* x, const double* g,
-                                 int64_t n, int32_t d, int64_t m, const NodeTable& t,
-                                 const BackwardBufs& b, double* df, double* dx, double* dxn,
-                                 hipStream_t s);
+                                const BackwardBufs& b, double* r, double* dr, hipStream_t s);
+hipError_t launch_backward_saved(const double* nodes, const double* x, const double* dr,
+                                 const double* g, int64_t n, int32_t d, int64_t m,
+                                 const NodeTable& t, const BackwardBufs& b, double* df,
+                                 double* dx, double* dxn, hipStream_t s);
+// dx[p] = g[p] dr[p] for p < m.
+hipError_t launch_point_grad_from_derivative(const double* g, const double* dr, int64_t m,
+                                             double* dx, hipStream_t s);
 // The per-node split kernel for q nodes per lane (occupancy queries).
 const void* bwd_nodes_split_kernel(int q);
 // nodes_pass: run the per-node pass (dL/df or the node gradient wanted);

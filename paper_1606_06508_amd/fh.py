@@ -66,9 +66,10 @@ def load():
                                  ctypes.c_int),
             "fh_eval_deriv": ([vp, vp, i64, i32, vp, i64, vp, vp, vp, i32, vp, sz, vp],
                               ctypes.c_int),
-            "fh_eval_forward": ([vp, vp, i64, i32, vp, i64, vp, i32, vp, sz, vp], ctypes.c_int),
-            "fh_eval_backward_saved": ([vp, i64, i32, vp, i64, vp, vp, vp, vp, i32, vp, sz, vp],
-                                       ctypes.c_int),
+            "fh_eval_forward": ([vp, vp, i64, i32, vp, i64, vp, vp, i32, vp, sz, vp],
+                                ctypes.c_int),
+            "fh_eval_backward_saved": ([vp, i64, i32, vp, i64, vp, vp, vp, vp, vp, i32, vp, sz,
+                                        vp], ctypes.c_int),
             "fh_lebesgue_max": ([vp, i64, i32, vp, i32, i32, vp, vp, vp, i32, vp, sz, vp],
                                 ctypes.c_int),
             "fh_multi_workspace_size": ([i64, i32], sz),
@@ -341,17 +342,20 @@ def eval_backward(nodes, values, d, x, grad_r, *, need_values=True, need_x=True,
 
 class Saved:
     """State of fh_eval_forward for fh_eval_backward_saved: the arguments of
-    the forward and its own workspace (node table, 1/D_p, r_p and the hit
-    data per point).  Keep it, unchanged, until the last backward."""
+    the forward, its own workspace (node table, 1/D_p, r_p and the hit data
+    per point) and, when the forward formed it, the derivative r'(x_p) (dr).
+    Keep it, unchanged, until the last backward."""
 
-    def __init__(self, nodes, d, x, precision, ws):
+    def __init__(self, nodes, d, x, precision, ws, dr):
         self.nodes, self.d, self.x, self.prec, self.ws = nodes, int(d), x, precision, ws
+        self.dr = dr
 
 
-def eval_forward(nodes, values, d, x, *, precision="fp64", ws=None):
+def eval_forward(nodes, values, d, x, *, derivative=False, precision="fp64", ws=None):
     """(r, Saved): r(x) and the state its adjoint needs (fh_eval_forward),
     kept in ws (a Workspace of its own, grown as needed; a new one when
-    None)."""
+    None).  derivative: also form r'(x) (Saved.dr), from which the backward
+    takes dL/dx = grad_r r'(x) -- for callers that will want dL/dx."""
     lib = load()
     xn, f, t = _f64(nodes, "nodes"), _f64(values, "values"), _f64(x, "x")
     n, m = xn.numel(), t.numel()
@@ -359,11 +363,13 @@ def eval_forward(nodes, values, d, x, *, precision="fp64", ws=None):
         raise ValueError("values must match nodes")
     prec = _prec(precision)
     r = torch.empty_like(t)
+    dr = torch.empty_like(t) if derivative else None
     ws = ws or Workspace(t.device)
     buf = ws.reserve(workspace_size(FH_OP_BACKWARD_SAVED, n, m, d, prec))
-    _check(lib.fh_eval_forward(_ptr(xn), _ptr(f), n, int(d), _ptr(t), m, _ptr(r), prec,
-                               _ptr(buf), buf.numel(), _stream(t.device)), "fh_eval_forward")
-    return r, Saved(xn, d, t, prec, ws)
+    _check(lib.fh_eval_forward(_ptr(xn), _ptr(f), n, int(d), _ptr(t), m, _ptr(r), _ptr(dr),
+                               prec, _ptr(buf), buf.numel(), _stream(t.device)),
+           "fh_eval_forward")
+    return r, Saved(xn, d, t, prec, ws, dr)
 
 
 def eval_backward_saved(saved, grad_r, *, need_values=True, need_x=True, need_nodes=True):
@@ -379,9 +385,10 @@ def eval_backward_saved(saved, grad_r, *, need_values=True, need_x=True, need_no
     gx = torch.empty_like(t) if need_x else None
     gn = torch.empty_like(xn) if need_nodes else None
     buf = saved.ws.buf
-    _check(lib.fh_eval_backward_saved(_ptr(xn), n, saved.d, _ptr(t), m, _ptr(g), _ptr(gv),
-                                      _ptr(gx), _ptr(gn), saved.prec, _ptr(buf), buf.numel(),
-                                      _stream(t.device)), "fh_eval_backward_saved")
+    _check(lib.fh_eval_backward_saved(_ptr(xn), n, saved.d, _ptr(t), m, _ptr(saved.dr),
+                                      _ptr(g), _ptr(gv), _ptr(gx), _ptr(gn), saved.prec,
+                                      _ptr(buf), buf.numel(), _stream(t.device)),
+           "fh_eval_backward_saved")
     return gv, gx, gn
 
 

@@ -105,10 +105,11 @@ def test_saved_adjoint_host_validation():
     ws = 1 << 40
     fwd = lambda **k: lib.fh_eval_forward(*[k.get(a, b) for a, b in (
         ("nodes", P), ("values", P), ("n", 10), ("d", 3), ("x", P), ("m", 100), ("r", P2),
-        ("prec", 0), ("ws", P), ("ws_bytes", ws), ("stream", None))])
+        ("dr", None), ("prec", 0), ("ws", P), ("ws_bytes", ws), ("stream", None))])
     bwd = lambda **k: lib.fh_eval_backward_saved(*[k.get(a, b) for a, b in (
-        ("nodes", P), ("n", 10), ("d", 3), ("x", P), ("m", 100), ("g", P2), ("gv", P2),
-        ("gx", P2), ("gn", P2), ("prec", 0), ("ws", P), ("ws_bytes", ws), ("stream", None))])
+        ("nodes", P), ("n", 10), ("d", 3), ("x", P), ("m", 100), ("dr", None), ("g", P2),
+        ("gv", P2), ("gx", P2), ("gn", P2), ("prec", 0), ("ws", P), ("ws_bytes", ws),
+        ("stream", None))])
     for call in (fwd, bwd):
         assert call(nodes=None) == fh.FH_E_ARG
         assert call(d=10) == fh.FH_E_DEGREE

@@ -36,10 +36,12 @@ def _np(t):
 
 
 def _gpu_bwd(nodes, vals, d, pts, g, saved=False):
-    """The two-pass adjoint (fh_eval_backward), or with saved=True the
-    saved-state one (fh_eval_forward, then fh_eval_backward_saved)."""
+    """The two-pass adjoint (fh_eval_backward, saved falsy), or the
+    saved-state one (fh_eval_forward, then fh_eval_backward_saved): saved
+    "fused" without the derivative (dL/dx_p from the fused pass), "deriv"
+    with it (dL/dx_p = g_p r'(x_p) from the forward)."""
     if saved:
-        _, st = fh.eval_forward(_t(nodes), _t(vals), d, _t(pts))
+        _, st = fh.eval_forward(_t(nodes), _t(vals), d, _t(pts), derivative=saved == "deriv")
         gv, gx, gn = fh.eval_backward_saved(st, _t(g))
     else:
         gv, gx, gn = fh.eval_backward(_t(nodes), _t(vals), d, _t(pts), _t(g))
@@ -47,7 +49,8 @@ def _gpu_bwd(nodes, vals, d, pts, g, saved=False):
     return _np(gv), _np(gx), _np(gn)
 
 
-MODES = pytest.mark.parametrize("saved", [False, True], ids=["two_pass", "saved"])
+MODES = pytest.mark.parametrize("saved", [False, "fused", "deriv"],
+                                ids=["two_pass", "saved", "saved_deriv"])
 
 
 def _check_against_oracle(nodes, vals, d, pts, g, dense_chain=True, saved=False):
@@ -206,7 +209,8 @@ def test_autograd_function_and_gradcheck():
         a.grad = None
     r = interpolate(nodes, vals, x, 3)
     (r * w).sum().backward()
-    r2, st = fh.eval_forward(nodes.detach(), vals.detach(), 3, x.detach())
+    # x requires a gradient: the forward keeps r' (dL/dx = g r')
+    r2, st = fh.eval_forward(nodes.detach(), vals.detach(), 3, x.detach(), derivative=True)
     assert torch.equal(r, r2)
     gv, gx, gn = fh.eval_backward_saved(st, w)
     assert torch.equal(nodes.grad, gn) and torch.equal(vals.grad, gv) and torch.equal(x.grad, gx)
@@ -215,9 +219,10 @@ def test_autograd_function_and_gradcheck():
 
 
 # ------------------------------------------------- saved-state adjoint --
+@pytest.mark.parametrize("derivative", [False, True])
 @pytest.mark.parametrize("need", [(True, False, False), (False, True, False), (False, False, True),
                                   (True, True, False), (True, False, True), (False, True, True)])
-def test_saved_partial_outputs_match_full(need):
+def test_saved_partial_outputs_match_full(need, derivative):
     """fh_eval_backward_saved computes only what is asked (dL/dx_p alone runs
     the point side of the fused pass without node sums) and each output has
     the bits of the full call, hits and a NaN point included."""
@@ -225,7 +230,8 @@ def test_saved_partial_outputs_match_full(need):
     pts = c["points"].copy()
     pts[:5] = c["nodes"][[0, 3, 64, 100, 128]]
     pts[5] = np.nan
-    _, st = fh.eval_forward(_t(c["nodes"]), _t(c["values"]), c["d"], _t(pts))
+    _, st = fh.eval_forward(_t(c["nodes"]), _t(c["values"]), c["d"], _t(pts),
+                            derivative=derivative)
     g = _t(c["grad"])
     full = fh.eval_backward_saved(st, g)
     part = fh.eval_backward_saved(st, g, need_values=need[0], need_x=need[1], need_nodes=need[2])
@@ -278,7 +284,7 @@ def test_no_points(saved):
     nodes, vals = _t(c["nodes"]), _t(c["values"])
     x = torch.empty(0, dtype=torch.float64, device=DEV)
     if saved:
-        r, st = fh.eval_forward(nodes, vals, c["d"], x)
+        r, st = fh.eval_forward(nodes, vals, c["d"], x, derivative=saved == "deriv")
         assert r.numel() == 0
         gv, gx, gn = fh.eval_backward_saved(st, x)
     else:
@@ -286,6 +292,32 @@ def test_no_points(saved):
     torch.cuda.synchronize()
     assert gx.numel() == 0
     assert torch.count_nonzero(gv) == 0 and torch.count_nonzero(gn) == 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "split"])
+def test_saved_forward_derivative(precision):
+    """With the derivative the forward returns fh_eval_deriv's r and r' bit
+    for bit, and dL/dx_p = g_p r'(x_p) exactly (one product)."""
+    c = inputs.grad_workload(n=300, m=9001)
+    pts = c["points"].copy()
+    pts[:2] = c["nodes"][[0, 150]]
+    pts[2] = np.nan
+    args = (_t(c["nodes"]), _t(c["values"]), c["d"], _t(pts))
+    r, st = fh.eval_forward(*args, derivative=True, precision=precision)
+    r2, dr2 = fh.eval_deriv(*args, precision=precision)
+    for u, v in ((r, r2), (st.dr, dr2)):
+        assert torch.equal(torch.isnan(u), torch.isnan(v))
+        assert torch.equal(u.nan_to_num(0.0), v.nan_to_num(0.0))
+    g = _t(c["grad"])
+    gx = fh.eval_backward_saved(st, g, need_values=False, need_nodes=False)[1]
+    want = g * dr2
+    assert torch.equal(torch.isnan(gx), torch.isnan(want))
+    assert torch.equal(gx.nan_to_num(0.0), want.nan_to_num(0.0))
+    # the node gradients do not depend on whether the forward formed r'
+    _, st0 = fh.eval_forward(*args, precision=precision)
+    for u, v in zip(fh.eval_backward_saved(st, g, need_x=False),
+                    fh.eval_backward_saved(st0, g, need_x=False)):
+        assert (u is None and v is None) or torch.equal(u, v)
 
 
 def test_saved_forward_bits_of_eval_variant():
@@ -316,4 +348,4 @@ def test_saved_many_node_tiles(n):
     vals = np.sin(7 * nodes) + 0.1 * g.standard_normal(n)
     pts = np.concatenate([g.uniform(-1, 1, 1500), nodes[::1000]])
     grad = g.standard_normal(pts.size)
-    _check_against_oracle(nodes, vals, 3, pts, grad, saved=True)
+    _check_against_oracle(nodes, vals, 3, pts, grad, saved="fused")

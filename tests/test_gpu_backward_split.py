@@ -135,7 +135,12 @@ def test_autograd_split():
     (r * w).sum().backward()
     gv, gx, gn = fh.eval_backward(nodes.detach(), vals.detach(), 3, x.detach(), w,
                                   precision="split")
-    assert torch.equal(nodes.grad, gn) and torch.equal(vals.grad, gv) and torch.equal(x.grad, gx)
-    # the split forward of the saved-state pair is fh_eval's split evaluation
+    # node gradients: the split passes; dL/dx = g r' with r' of the split
+    # derivative, which the forward formed (x requires a gradient)
+    assert torch.equal(nodes.grad, gn) and torch.equal(vals.grad, gv)
+    r2, dr2 = fh.eval_deriv(nodes.detach(), vals.detach(), 3, x.detach(), precision="split")
+    assert torch.equal(r.detach(), r2) and torch.equal(x.grad, w * dr2)
+    # without a gradient for x the forward is fh_eval's split evaluation
+    r = interpolate(nodes, vals, x.detach(), 3, precision="split")
     assert torch.equal(r.detach(), fh.evaluate(nodes.detach(), vals.detach(), 3, x.detach(),
                                                precision="split"))
