@@ -307,9 +307,9 @@ fh_status fh_eval_backward(const double* nodes, const double* values, int64_t n,
  * Werner 1986).  NaN and infinite points give r = NaN.  dr_out [m]
  * (nullable): also the derivative r'(x_p) there, as fh_eval_deriv computes
  * it (the same bits), for a caller that will want dL/dx_p.  Binary64 r has
- * the bits of fh_eval with launch variant 4 without dr_out and of
- * fh_eval_deriv with it; split r: fh_eval's split evaluation, or
- * fh_eval_deriv's with dr_out.
+ * the bits of fh_eval with launch variant 4 (and of fh_eval_deriv) with or
+ * without dr_out; split r: fh_eval's split evaluation without dr_out,
+ * fh_eval_deriv's with it.
  *
  * fh_eval_backward_saved: the gradients of fh_eval_backward (same
  * definitions, hit rules, outputs and NULL conventions) from that state and

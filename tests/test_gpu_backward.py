@@ -313,8 +313,12 @@ def test_saved_forward_derivative(precision):
     want = g * dr2
     assert torch.equal(torch.isnan(gx), torch.isnan(want))
     assert torch.equal(gx.nan_to_num(0.0), want.nan_to_num(0.0))
-    # the node gradients do not depend on whether the forward formed r'
-    _, st0 = fh.eval_forward(*args, precision=precision)
+    # the node gradients do not depend on whether the forward formed r', nor
+    # does the binary64 r
+    r0, st0 = fh.eval_forward(*args, precision=precision)
+    if precision == "fp64":
+        assert torch.equal(torch.isnan(r0), torch.isnan(r))
+        assert torch.equal(r0.nan_to_num(0.0), r.nan_to_num(0.0))
     for u, v in zip(fh.eval_backward_saved(st, g, need_x=False),
                     fh.eval_backward_saved(st0, g, need_x=False)):
         assert (u is None and v is None) or torch.equal(u, v)
