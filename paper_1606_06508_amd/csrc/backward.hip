@@ -143,9 +143,9 @@ __global__ void __launch_bounds__(256)
 // (dL/df; the others written as zeros), 0 none (no node partials written).
 // PT (G = 8, saved-state adjoint): also the point side of the same pairs,
 // sum_k (w_k r_p - w_k f_k) t_pk^2 = dL/dx_p / c_p (rr = r_p), summed over
-// the wave's nodes across lanes (wave_sum8, through LDS) and over its tiles in place:
-// gpart[blockIdx.x][p] (each wave owns its chunk's slots of its tile group;
-// the lane that adds a slot is the lane that wrote it).  Padding nodes
+// the wave's nodes across lanes (wave_sum8, through LDS) and over its tiles
+// in place: gpart[blockIdx.x][p] (each wave owns its chunk's slots of its
+// tile group; the lane that adds a slot is the lane that wrote it).  Padding nodes
 // (k >= n) sit far beyond the last node with zero weight: they add nothing,
 // and never make a group product zero.
 template <int Q, int G, int SUMS, bool PT>
