@@ -325,9 +325,12 @@ fh_status fh_eval_backward(const double* nodes, const double* values, int64_t n,
  * Both take ws of fh_workspace_size(FH_OP_BACKWARD_SAVED, n, m, d, prec) and
  * must see the same nodes, n, d, x, m and prec; values are read by the
  * forward only.  Between the two calls the workspace must not be used by
- * another call.  prec = FH_FP32_SPLIT: the backward runs the split
- * fh_eval_backward passes that the requested gradients need on the node table
- * the forward packed (no shared per-point state).  Errors as in
+ * another call.  prec = FH_FP32_SPLIT: with dr_out the forward runs the
+ * split point pass for unit loss weights (r and r' with fh_eval_deriv's
+ * bits) and keeps its binary64 and binary32 point records; the backward
+ * scales them by grad_r and runs the split node pass alone.  Without dr_out
+ * the forward is fh_eval's split evaluation and the backward the split
+ * fh_eval_backward passes on the node table the forward packed.  Errors as in
  * fh_eval_backward; a backward on a workspace its forward did not fill
  * gives unspecified values. */
 fh_status fh_eval_forward(const double* nodes, const double* values, int64_t n, int32_t d,

@@ -378,8 +378,8 @@ fh_status fh_eval_forward(const double* nodes, const double* values, int64_t n, 
   hipError_t e = launch_pack(nodes, values, nullptr, n, d, t, split, status, s);
   if (e == hipSuccess && m > 0) {
     if (split && dr_out) {
-      e = launch_eval_deriv_split(x, m, t, n, reinterpret_cast<int32_t*>(status) + 1, r_out,
-                                  dr_out, s);
+      e = launch_forward_saved_split(x, m, t, n, reinterpret_cast<int32_t*>(status) + 1, b,
+                                     r_out, dr_out, s);
     } else if (split) {
       // as fh_eval_prepared chooses (the same r bits as fh_eval)
       const EvalConfig cfg = choose_eval_config(prec, n, 0, m, true, false);
@@ -390,6 +390,9 @@ fh_status fh_eval_forward(const double* nodes, const double* values, int64_t n, 
     }
   } else if (e == hipSuccess && !split) {
     e = launch_forward_saved(x, 0, t, n, b, nullptr, nullptr, s);  // padding records only
+  } else if (e == hipSuccess && dr_out) {
+    e = launch_forward_saved_split(x, 0, t, n, reinterpret_cast<int32_t*>(status) + 1, b,
+                                   nullptr, nullptr, s);
   }
   return finish(e, ws, s);
 }
@@ -411,16 +414,19 @@ fh_status fh_eval_backward_saved(const double* nodes, int64_t n, int32_t d, cons
   layout_backward(ws, n, m, split, &t, &b, true);
   uint32_t* status = static_cast<uint32_t*>(ws);
   hipError_t e = hipSuccess;
-  if (split) {
-    double* dx = m > 0 ? grad_x : nullptr;
-    if (dx && dr) {  // dL/dx_p = g_p r'(x_p) from the forward's derivative
-      e = launch_point_grad_from_derivative(grad_r, dr, m, dx, s);
-      dx = nullptr;
+  if (split && dr) {
+    // the forward kept r' and the records for g = 1: dL/dx_p = g_p r'(x_p),
+    // the node gradients from the records scaled by g and the node pass
+    if (m > 0 && grad_x) e = launch_point_grad_from_derivative(grad_r, dr, m, grad_x, s);
+    if (e == hipSuccess && (grad_values || grad_nodes)) {
+      e = launch_backward_saved_split(grad_r, m, t, b, grad_nodes != nullptr, s);
+      if (e == hipSuccess)
+        e = launch_backward_tail(nodes, n, d, t, b, reinterpret_cast<int32_t*>(status) + 1,
+                                 grad_values, grad_nodes, s);
     }
-    if (e == hipSuccess && (dx || grad_values || grad_nodes))
-      e = launch_backward(nodes, x, grad_r, n, d, m, t, b,
-                          reinterpret_cast<int32_t*>(status) + 1, grad_values, dx, grad_nodes,
-                          s);
+  } else if (split) {
+    e = launch_backward(nodes, x, grad_r, n, d, m, t, b, reinterpret_cast<int32_t*>(status) + 1,
+                        grad_values, m > 0 ? grad_x : nullptr, grad_nodes, s);
   } else {
     e = launch_backward_saved(nodes, x, dr, grad_r, n, d, m, t, b, grad_values, grad_x,
                               grad_nodes, s);

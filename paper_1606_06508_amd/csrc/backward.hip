@@ -479,12 +479,15 @@ size_t layout_backward(void* ws, int64_t n, int64_t m, bool split, NodeTable* t,
   b->dxd = reinterpret_cast<double*>(take(sizeof(double) * p.n_pad));
   b->saved = PointRecs{};
   b->gpart = nullptr;
-  if (p.groups > 0) {
+  b->saved32 = nullptr;
+  if (saved) {
     // the forward's records (g = 1) share the point coordinates with rec
     b->saved.x = b->rec.x;
     double** sf[] = {&b->saved.c, &b->saved.cr, &b->saved.hg, &b->saved.hgr};
     for (double** f : sf) *f = reinterpret_cast<double*>(take(sizeof(double) * p.m_pad));
-    b->gpart = reinterpret_cast<double*>(take(sizeof(double) * p.groups * p.m_pad));
+    if (p.groups > 0)
+      b->gpart = reinterpret_cast<double*>(take(sizeof(double) * p.groups * p.m_pad));
+    if (split) b->saved32 = reinterpret_cast<float4*>(take(sizeof(float4) * p.m_pad));
   }
   return off;
 }
@@ -589,6 +592,12 @@ static hipError_t launch_node_tail(const double* nodes, int64_t n, int32_t d, co
     e = hipGetLastError();
   }
   return e;
+}
+
+hipError_t launch_backward_tail(const double* nodes, int64_t n, int32_t d, const NodeTable& t,
+                                const BackwardBufs& b, const int32_t* scale_exp, double* df,
+                                double* dxn, hipStream_t s) {
+  return launch_node_tail(nodes, n, d, t, b, scale_exp, df, dxn, s);
 }
 
 // --------------------------------------------------- saved-state adjoint --

@@ -50,8 +50,12 @@ __device__ __forceinline__ bool in_binary32_range(double v) {
 
 // ---------------------------------------------------------------- pass 1 --
 // DERIV: write r (r_out) and the derivative r' (dx) only, as if g_p = 1;
-// no records (m_pad = m).  EF: E and F are summed (for dx).
-template <int P, bool DERIV, bool EF>
+// no records (m_pad = m).  EF: E and F are summed (for dx).  SAVE (with EF,
+// not DERIV): the forward of the saved-state adjoint -- r, r' and the
+// records for g_p = 1 with r in place of c r, and in rec32 {head, tail,
+// 1 if the point took the binary64 path else 0, 0}, from which
+// k_bwd_scale_records_split builds the records for the loss weights.
+template <int P, bool DERIV, bool EF, bool SAVE = false>
 __global__ void __launch_bounds__(kStage)
     k_bwd_points_split(const double* __restrict__ x, const double* __restrict__ g, int64_t m,
                        int64_t m_pad, const float4* __restrict__ s4, int64_t n_pad,
@@ -127,7 +131,7 @@ __global__ void __launch_bounds__(kStage)
     if (idx >= m_pad) continue;
     double xr = xp[j], c = 0.0, cr = 0.0, hg = 0.0, hgr = 0.0;
     if (idx < m) {
-      const double gp = DERIV ? 1.0 : g[idx];
+      const double gp = (DERIV || SAVE) ? 1.0 : g[idx];
       double dxp, rv;
       if (!__builtin_isfinite(xp[j])) {
         dxp = rv = __builtin_nan("");
@@ -143,11 +147,16 @@ __global__ void __launch_bounds__(kStage)
         cr = ldexp(cr, e);
       }
       if (EF && dx) dx[idx] = dxp;
-      if (DERIV && r_out) r_out[idx] = rv;
+      if ((DERIV || SAVE) && r_out) r_out[idx] = rv;
+      if (SAVE) cr = rv;
     }
     if (DERIV) continue;
     rec.x[idx] = xr; rec.c[idx] = c; rec.cr[idx] = cr; rec.hg[idx] = hg; rec.hgr[idx] = hgr;
     const float h = (float)xr, l = (float)(xr - (double)h), nan = __builtin_nanf("");
+    if (SAVE) {
+      rec32[idx] = make_float4(h, l, bad[j] ? 1.0f : 0.0f, 0.0f);
+      continue;
+    }
     float4 r32;
     if (c == 0.0 && cr == 0.0)
       r32 = make_float4(h, l, 0.0f, 0.0f);
@@ -159,6 +168,39 @@ __global__ void __launch_bounds__(kStage)
       r32 = make_float4(h, l, nan, nan);
     rec32[idx] = r32;
   }
+}
+
+// Saved-state adjoint, before pass 2: the records for the loss weights g
+// from the forward's records for g = 1 (saved, saved32; see SAVE above; the
+// point coordinates rec.x are shared): c = g c1, c r, g and g r'(x_j) at a
+// hit, and the binary32 record coded as pass 1 codes it.
+__global__ void __launch_bounds__(256)
+    k_bwd_scale_records_split(PointRecs saved, const float4* __restrict__ saved32,
+                              const double* __restrict__ g, int64_t m, int64_t m_pad,
+                              PointRecs rec, float4* __restrict__ rec32) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= m_pad) return;
+  const double gp = p < m ? g[p] : 0.0;
+  const double c1 = saved.c[p];
+  const bool hit = saved.hg[p] != 0.0;
+  const double c = c1 == 0.0 ? 0.0 : gp * c1;
+  const double cr = c1 == 0.0 ? 0.0 : c * saved.cr[p];
+  rec.c[p] = c;
+  rec.cr[p] = cr;
+  rec.hg[p] = hit ? gp : 0.0;
+  rec.hgr[p] = hit ? gp * saved.hgr[p] : 0.0;
+  const float4 s32 = saved32[p];
+  const float nan = __builtin_nanf("");
+  float4 r32;
+  if (c == 0.0 && cr == 0.0)
+    r32 = make_float4(s32.x, s32.y, 0.0f, 0.0f);
+  else if (s32.z != 0.0f)
+    r32 = make_float4(nan, nan, 0.0f, 0.0f);
+  else if (in_binary32_range(c) && in_binary32_range(cr))
+    r32 = make_float4(s32.x, s32.y, (float)c, (float)cr);
+  else
+    r32 = make_float4(s32.x, s32.y, nan, nan);
+  rec32[p] = r32;
 }
 
 // ---------------------------------------------------------------- pass 2 --
@@ -289,6 +331,33 @@ hipError_t launch_backward_split_passes(const double* x, const double* g, int64_
                                                               b.rec, b.rec32, nullptr);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !nodes_pass) return e;
+  if (p.q == 2)
+    full ? launch_nodes_split<2, true>(p, t, b, s) : launch_nodes_split<2, false>(p, t, b, s);
+  else
+    full ? launch_nodes_split<1, true>(p, t, b, s) : launch_nodes_split<1, false>(p, t, b, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_forward_saved_split(const double* x, int64_t m, const NodeTable& t, int64_t n,
+                                      const int32_t* scale, const BackwardBufs& b, double* r,
+                                      double* dr, hipStream_t s) {
+  const BackwardPlan& p = b.plan;
+  if (b.saved32 == nullptr) return hipErrorInvalidValue;
+  constexpr int P = 1;
+  const dim3 g1((unsigned)((p.m_pad + kStage * P - 1) / (kStage * P)));
+  k_bwd_points_split<P, false, true, true><<<g1, kStage, 0, s>>>(
+      x, nullptr, m, p.m_pad, t.s, t.n_pad, t.x, t.w, t.f, n, scale, dr, b.saved, b.saved32, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_backward_saved_split(const double* g, int64_t m, const NodeTable& t,
+                                       const BackwardBufs& b, bool full, hipStream_t s) {
+  const BackwardPlan& p = b.plan;
+  if (b.saved32 == nullptr) return hipErrorInvalidValue;
+  k_bwd_scale_records_split<<<dim3((unsigned)((p.m_pad + 255) / 256)), 256, 0, s>>>(
+      b.saved, b.saved32, g, m, p.m_pad, b.rec, b.rec32);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   if (p.q == 2)
     full ? launch_nodes_split<2, true>(p, t, b, s) : launch_nodes_split<2, false>(p, t, b, s);
   else

@@ -90,10 +90,11 @@ struct BackwardBufs {
   double* sums;   // [6][n_pad] node sums over all chunks
   double* dw;     // [n_pad] dL/dw_k
   double* dxd;    // [n_pad] direct dL/dx_k at fixed weights
-  // saved-state adjoint (binary64, FH_OP_BACKWARD_SAVED) only, else null:
+  // saved-state adjoint (FH_OP_BACKWARD_SAVED) only, else null:
   PointRecs saved;  // the forward's records for g = 1: {x (= rec.x), 1/D, r,
-                    // 1 at a hit, r'(x_j) at a hit}
-  double* gpart;    // [groups][m_pad] point-side sums per node tile group
+                    // 1 at a hit, r'(x_j) at a hit} (split: 2^e / D)
+  double* gpart;    // [groups][m_pad] point-side sums per node tile group (binary64)
+  float4* saved32;  // [m_pad] {head, tail, binary64-path flag, 0} (split)
 };
 // saved: plan the saved-state adjoint (binary64 only; split plans ignore it).
 BackwardPlan plan_backward(int64_t n, int64_t m, bool split, bool saved = false);
@@ -180,6 +181,21 @@ hipError_t launch_backward_saved(const double* nodes, const double* x, const dou
                                  const double* g, int64_t n, int32_t d, int64_t m,
                                  const NodeTable& t, const BackwardBufs& b, double* df,
                                  double* dx, double* dxn, hipStream_t s);
+// Split saved state (prec FH_FP32_SPLIT, forward with r'): the split point
+// pass for g = 1 writes r, r' and b.saved / b.saved32; the backward scales
+// them by g into b.rec / b.rec32 and runs the split node pass (full: all
+// four sums).
+hipError_t launch_forward_saved_split(const double* x, int64_t m, const NodeTable& t, int64_t n,
+                                      const int32_t* scale, const BackwardBufs& b, double* r,
+                                      double* dr, hipStream_t s);
+hipError_t launch_backward_saved_split(const double* g, int64_t m, const NodeTable& t,
+                                       const BackwardBufs& b, bool full, hipStream_t s);
+// Passes 3 and 4 of the adjoint (chunk reduction, per-node finish, weight
+// chain) from the chunk partials in b.part; scale_exp: the split scaling
+// exponent (null for binary64).
+hipError_t launch_backward_tail(const double* nodes, int64_t n, int32_t d, const NodeTable& t,
+                                const BackwardBufs& b, const int32_t* scale_exp, double* df,
+                                double* dxn, hipStream_t s);
 // dx[p] = g[p] dr[p] for p < m.
 hipError_t launch_point_grad_from_derivative(const double* g, const double* dr, int64_t m,
                                              double* dx, hipStream_t s);

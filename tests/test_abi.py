@@ -57,7 +57,7 @@ def test_workspace_sizes():
     sv64 = lib.fh_workspace_size(fh.FH_OP_BACKWARD_SAVED, 2049, 10 ** 6, 4, 0)
     sv32 = lib.fh_workspace_size(fh.FH_OP_BACKWARD_SAVED, 2049, 10 ** 6, 4, 1)
     assert bw64 + 32 * 10 ** 6 < sv64 <= bw64 + (32 + 8 * 64) * 10 ** 6 + (1 << 30)
-    assert sv32 == bw32
+    assert bw32 + 48 * 10 ** 6 <= sv32 <= bw32 + 48 * (10 ** 6 + 8192) + (1 << 20)
     big = lib.fh_workspace_size(fh.FH_OP_BACKWARD_SAVED, 10 ** 5, 10 ** 4, 4, 0)
     assert 0 < big < lib.fh_workspace_size(fh.FH_OP_BACKWARD, 10 ** 5, 10 ** 4, 4, 0) + \
         (32 + 8 * 64) * (10 ** 4 + 4096) + (1 << 30)

@@ -34,30 +34,43 @@ def _np(t):
     return None if t is None else t.cpu().numpy()
 
 
-def _gpu_bwd(nodes, vals, d, pts, g, precision="split"):
-    gv, gx, gn = fh.eval_backward(_t(nodes), _t(vals), d, _t(pts), _t(g), precision=precision)
+def _gpu_bwd(nodes, vals, d, pts, g, precision="split", saved=False):
+    """The two-pass adjoint, or with saved=True the saved-state one whose
+    forward kept r' and the point records for unit loss weights."""
+    if saved:
+        _, st = fh.eval_forward(_t(nodes), _t(vals), d, _t(pts), derivative=True,
+                                precision=precision)
+        gv, gx, gn = fh.eval_backward_saved(st, _t(g))
+    else:
+        gv, gx, gn = fh.eval_backward(_t(nodes), _t(vals), d, _t(pts), _t(g),
+                                      precision=precision)
     torch.cuda.synchronize()
     return _np(gv), _np(gx), _np(gn)
 
 
-def _check(nodes, vals, d, pts, g, precision="split"):
-    gv, gx, gn = _gpu_bwd(nodes, vals, d, pts, g, precision)
+SAVED = pytest.mark.parametrize("saved", [False, True], ids=["two_pass", "saved_deriv"])
+
+
+def _check(nodes, vals, d, pts, g, precision="split", saved=False):
+    gv, gx, gn = _gpu_bwd(nodes, vals, d, pts, g, precision, saved)
     o = oracle.backward(nodes, vals, d, pts, g)
     err = metrics.grad_errors(gv, gx, gn, o, metrics.grad_scales(nodes, vals, d, pts, g), nodes, d)
     metrics.check_grad(err, TOLS[precision])
     return err
 
 
-def test_reduced_workload():
+@SAVED
+def test_reduced_workload(saved):
     c = inputs.grad_workload(n=513, m=6007)
-    err = _check(c["nodes"], c["values"], c["d"], c["points"], c["grad"])
+    err = _check(c["nodes"], c["values"], c["d"], c["points"], c["grad"], saved=saved)
     # binary32 terms: the split gradients are not binary64-accurate
     assert max(err["dvalues"], err["dpoints"], err["dnodes"]) > metrics.GRAD_TOL
 
 
 @pytest.mark.parametrize("n,d", [(1, 0), (2, 1), (5, 0), (5, 4), (64, 3), (65, 7), (130, 10),
                                  (300, 2)])
-def test_shapes_with_hits_and_nan(n, d):
+@SAVED
+def test_shapes_with_hits_and_nan(n, d, saved):
     g = np.random.default_rng(200 + n + d)
     nodes = inputs.equispaced(n) + (g.uniform(-0.2, 0.2, n) * (2.0 / max(n - 1, 1)) if n > 2 else 0)
     nodes = np.sort(nodes)
@@ -65,13 +78,14 @@ def test_shapes_with_hits_and_nan(n, d):
     pts = np.concatenate([g.uniform(-1.1, 1.1, size=1001), nodes[:: max(1, n // 5)], [np.nan],
                           nodes[-1:] + 1e-15])
     grad = g.standard_normal(pts.size)
-    _check(nodes, vals, d, pts, grad)
-    gv, gx, gn = _gpu_bwd(nodes, vals, d, pts, grad)
+    _check(nodes, vals, d, pts, grad, saved=saved)
+    gv, gx, gn = _gpu_bwd(nodes, vals, d, pts, grad, saved=saved)
     assert np.isnan(gx[-2]) and np.all(np.isfinite(gv)) and np.all(np.isfinite(gn))
 
 
+@SAVED
 @pytest.mark.parametrize("case", ["tiny_span", "huge_span", "far_points", "huge_g", "tiny_g"])
-def test_range_fallbacks(case):
+def test_range_fallbacks(case, saved):
     g = np.random.default_rng(7)
     n, d = 97, 4
     nodes = inputs.equispaced(n)
@@ -89,16 +103,17 @@ def test_range_fallbacks(case):
         grad[::2] *= 1e60
     elif case == "tiny_g":
         grad *= 1e-60
-    _check(nodes, vals, d, pts, grad)
+    _check(nodes, vals, d, pts, grad, saved=saved)
 
 
+@SAVED
 @pytest.mark.parametrize("precision", ["fp64", "split"])
-def test_full_workload_every_output(precision):
+def test_full_workload_every_output(precision, saved):
     """n = 2049, d = 4, 10^6 points: every gradient entry against the oracle
     (C oracle adjoint and C error scales)."""
     c = inputs.grad_workload()
     nodes, vals, d, pts, g = c["nodes"], c["values"], c["d"], c["points"], c["grad"]
-    gv, gx, gn = _gpu_bwd(nodes, vals, d, pts, g, precision)
+    gv, gx, gn = _gpu_bwd(nodes, vals, d, pts, g, precision, saved)
     o = oracle.backward(nodes, vals, d, pts, g)
     s_df, s_dx, s_dn = oracle.grad_scales(nodes, vals, d, pts, g)
     tol = TOLS[precision]
@@ -107,10 +122,11 @@ def test_full_workload_every_output(precision):
     assert np.all(np.abs(gn - o["d_nodes"]) <= tol * s_dn)
 
 
-def test_deterministic():
+@SAVED
+def test_deterministic(saved):
     c = inputs.grad_workload(n=1025, m=100003)
-    a = _gpu_bwd(c["nodes"], c["values"], c["d"], c["points"], c["grad"])
-    b = _gpu_bwd(c["nodes"], c["values"], c["d"], c["points"], c["grad"])
+    a = _gpu_bwd(c["nodes"], c["values"], c["d"], c["points"], c["grad"], saved=saved)
+    b = _gpu_bwd(c["nodes"], c["values"], c["d"], c["points"], c["grad"], saved=saved)
     for u, v in zip(a, b):
         assert np.array_equal(u, v)
 
@@ -144,3 +160,25 @@ def test_autograd_split():
     r = interpolate(nodes, vals, x.detach(), 3, precision="split")
     assert torch.equal(r.detach(), fh.evaluate(nodes.detach(), vals.detach(), 3, x.detach(),
                                                precision="split"))
+
+
+@pytest.mark.parametrize("need", [(True, False, False), (False, True, False), (False, False, True),
+                                  (True, True, False), (True, False, True), (False, True, True)])
+def test_saved_partial_outputs_match_full(need):
+    """Split saved state with r': each requested gradient has the bits of
+    the full call, and the state survives repeated backwards."""
+    c = inputs.grad_workload(n=129, m=5000)
+    pts = c["points"].copy()
+    pts[:3] = c["nodes"][[0, 64, 128]]
+    _, st = fh.eval_forward(_t(c["nodes"]), _t(c["values"]), c["d"], _t(pts), derivative=True,
+                            precision="split")
+    g = _t(c["grad"])
+    full = fh.eval_backward_saved(st, g)
+    part = fh.eval_backward_saved(st, g, need_values=need[0], need_x=need[1], need_nodes=need[2])
+    again = fh.eval_backward_saved(st, g)
+    for want, a, b, b2 in zip(need, part, full, again):
+        assert torch.equal(b, b2)
+        if want:
+            assert torch.equal(a, b)
+        else:
+            assert a is None

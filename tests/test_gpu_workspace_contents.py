@@ -64,13 +64,15 @@ def test_adjoints(precision):
     rb = fh.eval_backward(nodes, vals, d, x, g, precision=precision, ws=b)
     for u, v in zip(ra, rb):
         _same(u, v)
-    a, b = _pair(fh.workspace_size(fh.FH_OP_BACKWARD_SAVED, n, m, d, precision))
-    outs = []
-    for ws in (a, b):
-        r, st = fh.eval_forward(nodes, vals, d, x, precision=precision, ws=ws)
-        outs.append((r,) + fh.eval_backward_saved(st, g))
-    for u, v in zip(*outs):
-        _same(u, v)
+    for derivative in (False, True):
+        a, b = _pair(fh.workspace_size(fh.FH_OP_BACKWARD_SAVED, n, m, d, precision))
+        outs = []
+        for ws in (a, b):
+            r, st = fh.eval_forward(nodes, vals, d, x, precision=precision, ws=ws,
+                                    derivative=derivative)
+            outs.append((r,) + fh.eval_backward_saved(st, g))
+        for u, v in zip(*outs):
+            _same(u, v)
 
 
 def test_lebesgue_max_and_multi():
