@@ -67,9 +67,19 @@ __device__ __forceinline__ void eval_f64_points(const double* __restrict__ x, in
     A[j] = 0.0;
     bad[j] = false;
   }
-  // node slice of this wave (n_pad is a multiple of 64, hence of S * G)
-  const int64_t slice_len = n_pad / S;
-  const int64_t k_begin = slice * slice_len, k_end = k_begin + slice_len;
+  // node slice of this wave: the records up to the first multiple of 16 at
+  // or after n -- the zero-weight padding beyond it adds nothing and is not
+  // visited (n_pad, a multiple of 64, holds it) -- cut into S slices of
+  // whole 16-record units (every group and block length divides 16, so
+  // variants that differ only in G or U slice alike: a block variant whose
+  // weights do not alternate keeps its plain twin's bits), the last one
+  // shorter
+  constexpr int64_t kUnit = 16;
+  static_assert(kUnit % G == 0 && (U == 0 || kUnit % U == 0), "groups and blocks divide 16");
+  const int64_t n_loop = (n + kUnit - 1) / kUnit * kUnit;
+  const int64_t slice_len = ((n_loop + S - 1) / S + kUnit - 1) / kUnit * kUnit;
+  const int64_t k_begin = slice * slice_len < n_loop ? slice * slice_len : n_loop;
+  const int64_t k_end = k_begin + slice_len < n_loop ? k_begin + slice_len : n_loop;
 
   bool blocks = false;
   if constexpr (U > 0) {
