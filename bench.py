@@ -88,6 +88,15 @@ def measured_traffic(n, m):
     return rec.get("hbm_bytes_per_launch")
 
 
+def _variant_info(n, m):
+    """The binary64 launch variant a launch of m points on n nodes runs."""
+    vid = fh.tune_get("fp64", n, m)
+    shape = dict((v[0], v[1:]) for v in fh.variants("fp64"))[vid]
+    return {"id": vid, "points_per_lane": shape[0], "node_split": shape[2],
+            "node_block": fh.variant_lebesgue_block("fp64", vid),
+            "node_pairs": fh.variant_node_pairs("fp64", vid)}
+
+
 def run_sines(dev, steps, warmup):
     """The headline step: the node tables of all nine degrees (weights and
     packing, fh_prepare_many: one launch) and the fused r + Lambda evaluation
@@ -735,7 +744,8 @@ def main():
                      "kernel": "k_eval_f64_many (fused r + Lebesgue, FP64, nine degrees "
                                "per launch)",
                      "kernel_ms_avg": k_ms,
-                     "kernel_Gpair_s": pairs_step / (k_ms * 1e-3) / 1e9},
+                     "kernel_Gpair_s": pairs_step / (k_ms * 1e-3) / 1e9,
+                     "launch_variant": _variant_info(n, len(res["degrees"]) * m)},
     }
     print(f"[bench] sines done: {value:.1f} Gpair/s, kernel {k_ms:.3f} ms", file=sys.stderr,
           flush=True)

@@ -151,7 +151,7 @@ fh_status fh_eval(const double* nodes, const double* values, int64_t n, int32_t 
  * device-side node checks report only under FH_SYNC_CHECK=1 (no workspace
  * is exposed to read them back later). */
 #define FH_NOALLOC_SCRATCH_BYTES ((size_t)2 << 20)
-#define FH_NOALLOC_MAX_NODES 43648LL
+#define FH_NOALLOC_MAX_NODES 28288LL
 fh_status fh_eval_noalloc(const double* nodes, const double* values, int64_t n, int32_t d,
                           const double* x, int64_t m, double* r_out, double* lambda_out,
                           const double* w, int32_t prec, void* stream);
@@ -390,6 +390,11 @@ fh_status fh_batch_status(fh_batch* b, void* stream, uint32_t* bits_out);
  *                  depend on whether Lambda is requested.  Batched split
  *                  variants take tiles of 32, batched binary64 variants 16 or
  *                  plain sums;
+ *   fh_variant_node_pairs  1 if a binary64 variant sums its node blocks
+ *                  by pairs of records (k, k+2) -- one rational term per pair,
+ *                  w_a/(x - x_a) + w_b/(x - x_b) = (B x'' + J)/(x''^2 - hh^2) --
+ *                  with the blocks next to each point summed node by node
+ *                  afterwards, 0 otherwise, -1 for a bad family or id;
  *   fh_variant_strip_points  points one block covers (single-interpolant
  *                  families) or one work item (batched families), -1 for a
  *                  bad family or id;
@@ -409,6 +414,7 @@ int32_t fh_variant_count(int32_t prec);
 fh_status fh_variant_shape(int32_t prec, int32_t id, int32_t* points_per_lane, int32_t* group,
                            int32_t* node_split);
 int32_t fh_variant_lebesgue_block(int32_t prec, int32_t id);
+int32_t fh_variant_node_pairs(int32_t prec, int32_t id);
 int64_t fh_variant_strip_points(int32_t prec, int32_t id);
 fh_status fh_tune_set(int32_t prec, int64_t n, int64_t m, int32_t id);
 fh_status fh_tune_force(int32_t prec, int32_t id);

@@ -140,6 +140,8 @@ fh_status fh_prepare_many(const double* nodes, const double* values, int64_t n,
     a.w[c] = t.w;
     a.wf[c] = t.wf;
     a.f[c] = t.f;
+    a.pr[c] = t.pr;
+    a.pok[c] = t.pok;
     a.status[c] = static_cast<uint32_t*>(ws_host[c]);
     a.d[c] = d;
   }
@@ -178,6 +180,8 @@ fh_status fh_eval_prepared_many(void* const* ws_host, size_t ws_bytes, int32_t K
     a.w[c] = t.w;
     a.wf[c] = t.wf;
     a.f[c] = t.f;
+    a.pr[c] = t.pr;
+    a.pok[c] = t.pok;
     a.alt[c] = static_cast<uint32_t*>(ws_host[c]) + 3;
     a.r[c] = r_host ? r_host[c] : nullptr;
     a.lam[c] = lambda_host ? lambda_host[c] : nullptr;

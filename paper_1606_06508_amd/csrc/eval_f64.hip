@@ -42,14 +42,22 @@ namespace fhk {
 // U > 0: the sums are taken by blocks of U nodes (accumulate_f64_blocks)
 // when the table's weights alternate in sign, which *alt says (written by
 // the packing); D, hence r, is then the same with and without Lambda.
-template <int P, int G, int S, bool R, bool L, int U>
+// PAIRS (U = 16): when every block of the table passed the pack's test
+// (summary words pok), the blocks are summed by node pairs
+// (accumulate_f64_pairs) from the pair records pr and the blocks next to
+// each point node by node afterwards (pair_fix_points); otherwise as U = 16
+// without pairs.
+template <int P, int G, int S, bool R, bool L, int U, bool PAIRS>
 __device__ __forceinline__ void eval_f64_points(const double* __restrict__ x, int64_t m,
                                                 const double* __restrict__ tx,
                                                 const double* __restrict__ tw,
-                                                const double* __restrict__ twf, int64_t n_pad,
+                                                const double* __restrict__ twf,
+                                                const double* __restrict__ pr,
+                                                const uint32_t* __restrict__ pok, int64_t n_pad,
                                                 const double* __restrict__ f, int64_t n,
                                                 const uint32_t* __restrict__ alt,
                                                 double* __restrict__ r, double* __restrict__ lam) {
+  static_assert(!PAIRS || U == kPairBlock, "pair records come in blocks of 16");
   constexpr int PG = 4 / S;  // point groups per block
   const int lane = threadIdx.x & 63;
   // wave index, made provably wave-uniform so node loads stay scalar
@@ -81,11 +89,18 @@ __device__ __forceinline__ void eval_f64_points(const double* __restrict__ x, in
   const int64_t k_begin = slice * slice_len < n_loop ? slice * slice_len : n_loop;
   const int64_t k_end = k_begin + slice_len < n_loop ? k_begin + slice_len : n_loop;
 
-  bool blocks = false;
+  bool blocks = false, pairs = false;
+  int32_t rlast[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) rlast[j] = -1;
   if constexpr (U > 0) {
     blocks = __builtin_amdgcn_readfirstlane(*alt) != 0;
-    if (blocks)
+    if constexpr (PAIRS) pairs = blocks && pair_table_ok(pok, n_loop);
+    if (pairs) {
+      accumulate_f64_pairs<P, R, L>(xp, pr, k_begin, k_end, N, D, A, bad, rlast);
+    } else if (blocks) {
       accumulate_f64_blocks<P, G, U, R, L>(xp, tx, tw, twf, k_begin, k_end, N, D, A, bad);
+    }
   }
   if (!blocks) accumulate_f64<P, G, R, L>(xp, tx, tw, twf, k_begin, k_end, N, D, A, bad);
 
@@ -93,6 +108,7 @@ __device__ __forceinline__ void eval_f64_points(const double* __restrict__ x, in
     // fixed-order reduction of the S partial sums of each group through LDS
     __shared__ double red[PG][S - 1][3][64 * P];
     __shared__ int redbad[PG][S - 1][64 * P];
+    __shared__ int redmask[PG][S - 1][PAIRS ? 64 * P : 1];
     if (slice > 0) {
 #pragma unroll
       for (int j = 0; j < P; ++j) {
@@ -100,6 +116,7 @@ __device__ __forceinline__ void eval_f64_points(const double* __restrict__ x, in
         red[pg][slice - 1][1][j * 64 + lane] = D[j];
         red[pg][slice - 1][2][j * 64 + lane] = A[j];
         redbad[pg][slice - 1][j * 64 + lane] = bad[j];
+        if constexpr (PAIRS) redmask[pg][slice - 1][j * 64 + lane] = rlast[j];
       }
     }
     __syncthreads();
@@ -112,6 +129,23 @@ __device__ __forceinline__ void eval_f64_points(const double* __restrict__ x, in
         D[j] += red[pg][s][1][j * 64 + lane];
         A[j] += red[pg][s][2][j * 64 + lane];
         bad[j] |= redbad[pg][s][j * 64 + lane] != 0;
+        if constexpr (PAIRS) {
+          // the last masked block over all slices (-1: none)
+          const int32_t rl = redmask[pg][s][j * 64 + lane];
+          rlast[j] = rl > rlast[j] ? rl : rlast[j];
+        }
+      }
+    }
+  }
+
+  if constexpr (PAIRS) {
+    if (pairs) {
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        // every finite point has a masked block; a NaN point is flagged
+        if (!bad[j] && rlast[j] >= 0)
+          pair_fix_point<G, R, L>(xp[j], rlast[j], tx, tw, twf, N[j], D[j], A[j]);
+        bad[j] |= !(fabs(D[j]) <= 0x1.fffffffffffffp+1023);
       }
     }
   }
@@ -128,7 +162,7 @@ __device__ __forceinline__ void eval_f64_points(const double* __restrict__ x, in
     } else {
       double a = A[j];
       if constexpr (L && U > 0)
-        if (blocks) a = lebesgue_block_fix<G, U>(xp[j], tx, tw, n, a);
+        if (blocks && !pairs) a = lebesgue_block_fix<G, U>(xp[j], tx, tw, n, a);
       rv = N[j] / D[j];
       lv = a / fabs(D[j]);
     }
@@ -137,79 +171,84 @@ __device__ __forceinline__ void eval_f64_points(const double* __restrict__ x, in
   }
 }
 
-template <int P, int G, int S, bool R, bool L, int U>
+template <int P, int G, int S, bool R, bool L, int U, bool PAIRS>
 __global__ void __launch_bounds__(256)
     k_eval_f64(const double* __restrict__ x, int64_t m, const double* __restrict__ tx,
-               const double* __restrict__ tw, const double* __restrict__ twf, int64_t n_pad,
+               const double* __restrict__ tw, const double* __restrict__ twf,
+               const double* __restrict__ pr, const uint32_t* __restrict__ pok, int64_t n_pad,
                const double* __restrict__ f, int64_t n, const uint32_t* __restrict__ alt,
                double* __restrict__ r, double* __restrict__ lam) {
-  eval_f64_points<P, G, S, R, L, U>(x, m, tx, tw, twf, n_pad, f, n, alt, r, lam);
+  eval_f64_points<P, G, S, R, L, U, PAIRS>(x, m, tx, tw, twf, pr, pok, n_pad, f, n, alt, r, lam);
 }
 
 // Several tables on the same points: table blockIdx.y, the points of
 // blockIdx.x as in k_eval_f64.  One launch instead of one per table saves
 // the drain of each launch's last blocks and the gap before the next.
-template <int P, int G, int S, bool R, bool L, int U>
+template <int P, int G, int S, bool R, bool L, int U, bool PAIRS>
 __global__ void __launch_bounds__(256)
     k_eval_f64_many(const double* __restrict__ x, int64_t m, int64_t n_pad, int64_t n,
                     EvalMany a) {
   const int i = blockIdx.y;
-  eval_f64_points<P, G, S, R, L, U>(x, m, a.x[i], a.w[i], a.wf[i], n_pad, a.f[i], n, a.alt[i],
-                                    a.r[i], a.lam[i]);
+  eval_f64_points<P, G, S, R, L, U, PAIRS>(x, m, a.x[i], a.w[i], a.wf[i], a.pr[i], a.pok[i],
+                                           n_pad, a.f[i], n, a.alt[i], a.r[i], a.lam[i]);
 }
 
-template <int P, int G, int S, int U>
+template <int P, int G, int S, int U, bool PAIRS>
 static hipError_t launch_many_v(const double* x, int64_t m, int64_t n, int64_t n_pad,
                                 const EvalMany& a, int32_t K, bool r, bool lam, hipStream_t s) {
   const int64_t per = 64LL * P * (4 / S);  // points per block
   const dim3 grid((unsigned)((m + per - 1) / per), (unsigned)K), block(256);
   if (r && lam)
-    k_eval_f64_many<P, G, S, true, true, U><<<grid, block, 0, s>>>(x, m, n_pad, n, a);
+    k_eval_f64_many<P, G, S, true, true, U, PAIRS><<<grid, block, 0, s>>>(x, m, n_pad, n, a);
   else if (r)
-    k_eval_f64_many<P, G, S, true, false, U><<<grid, block, 0, s>>>(x, m, n_pad, n, a);
+    k_eval_f64_many<P, G, S, true, false, U, PAIRS><<<grid, block, 0, s>>>(x, m, n_pad, n, a);
   else
-    k_eval_f64_many<P, G, S, false, true, U><<<grid, block, 0, s>>>(x, m, n_pad, n, a);
+    k_eval_f64_many<P, G, S, false, true, U, PAIRS><<<grid, block, 0, s>>>(x, m, n_pad, n, a);
   return hipGetLastError();
 }
 
-template <int P, int G, int S, int U>
+template <int P, int G, int S, int U, bool PAIRS>
 static hipError_t launch_v(const double* x, int64_t m, const NodeTable& t, int64_t n,
                            const uint32_t* alt, double* r, double* lam, hipStream_t s) {
   const int64_t per = 64LL * P * (4 / S);  // points per block
   const dim3 grid((unsigned)((m + per - 1) / per)), block(256);
   if (r && lam)
-    k_eval_f64<P, G, S, true, true, U><<<grid, block, 0, s>>>(x, m, t.x, t.w, t.wf, t.n_pad, t.f,
-                                                              n, alt, r, lam);
+    k_eval_f64<P, G, S, true, true, U, PAIRS><<<grid, block, 0, s>>>(
+        x, m, t.x, t.w, t.wf, t.pr, t.pok, t.n_pad, t.f, n, alt, r, lam);
   else if (r)
-    k_eval_f64<P, G, S, true, false, U><<<grid, block, 0, s>>>(x, m, t.x, t.w, t.wf, t.n_pad,
-                                                               t.f, n, alt, r, lam);
+    k_eval_f64<P, G, S, true, false, U, PAIRS><<<grid, block, 0, s>>>(
+        x, m, t.x, t.w, t.wf, t.pr, t.pok, t.n_pad, t.f, n, alt, r, lam);
   else
-    k_eval_f64<P, G, S, false, true, U><<<grid, block, 0, s>>>(x, m, t.x, t.w, t.wf, t.n_pad,
-                                                               t.f, n, alt, r, lam);
+    k_eval_f64<P, G, S, false, true, U, PAIRS><<<grid, block, 0, s>>>(
+        x, m, t.x, t.w, t.wf, t.pr, t.pok, t.n_pad, t.f, n, alt, r, lam);
   return hipGetLastError();
 }
 
 // Variant table: id -> (points per lane P, group size G, node split S,
-// Lebesgue block U; U = 0: plain sums).
+// Lebesgue block U; U = 0: plain sums, node pairs: 1 for sums by node pairs
+// in blocks of U = 16, G then the group of the node-by-node blocks).
 #define FH_F64_VARIANTS(X)                                                                    \
-  X(0, 1, 4, 1, 0) X(1, 2, 4, 1, 0) X(2, 4, 4, 1, 0) X(3, 1, 8, 1, 0) X(4, 2, 8, 1, 0)        \
-  X(5, 4, 8, 1, 0) X(6, 1, 4, 4, 0) X(7, 2, 4, 4, 0) X(8, 4, 4, 4, 0) X(9, 1, 8, 4, 0)        \
-  X(10, 2, 8, 4, 0) X(11, 4, 8, 4, 0) X(12, 1, 8, 2, 0) X(13, 2, 8, 2, 0) X(14, 4, 8, 2, 0)   \
-  X(15, 1, 8, 4, 16) X(16, 2, 8, 4, 16) X(17, 1, 8, 2, 16) X(18, 2, 8, 2, 16)
+  X(0, 1, 4, 1, 0, 0) X(1, 2, 4, 1, 0, 0) X(2, 4, 4, 1, 0, 0) X(3, 1, 8, 1, 0, 0)             \
+  X(4, 2, 8, 1, 0, 0) X(5, 4, 8, 1, 0, 0) X(6, 1, 4, 4, 0, 0) X(7, 2, 4, 4, 0, 0)             \
+  X(8, 4, 4, 4, 0, 0) X(9, 1, 8, 4, 0, 0) X(10, 2, 8, 4, 0, 0) X(11, 4, 8, 4, 0, 0)           \
+  X(12, 1, 8, 2, 0, 0) X(13, 2, 8, 2, 0, 0) X(14, 4, 8, 2, 0, 0) X(15, 1, 8, 4, 16, 0)        \
+  X(16, 2, 8, 4, 16, 0) X(17, 1, 8, 2, 16, 0) X(18, 2, 8, 2, 16, 0) X(19, 1, 8, 2, 16, 1)     \
+  X(20, 2, 8, 2, 16, 1) X(21, 2, 8, 4, 16, 1) X(22, 4, 8, 2, 16, 1) X(23, 2, 8, 1, 16, 1)     \
+  X(24, 4, 8, 1, 16, 1)
 
 int f64_variant_count() {
-#define FH_COUNT(id, p, g, s, u) +1
+#define FH_COUNT(id, p, g, s, u, pairs) +1
   return 0 FH_F64_VARIANTS(FH_COUNT);
 #undef FH_COUNT
 }
 
 void f64_variant_shape(int id, int* p, int* g, int* s) {
   switch (id) {
-#define FH_SHAPE(vid, vp, vg, vs, vu) \
-  case vid:                           \
-    *p = vp;                          \
-    *g = vg;                          \
-    *s = vs;                          \
+#define FH_SHAPE(vid, vp, vg, vs, vu, vpairs) \
+  case vid:                                   \
+    *p = vp;                                  \
+    *g = vg;                                  \
+    *s = vs;                                  \
     return;
     FH_F64_VARIANTS(FH_SHAPE)
 #undef FH_SHAPE
@@ -219,11 +258,21 @@ void f64_variant_shape(int id, int* p, int* g, int* s) {
 
 int f64_variant_block(int id) {
   switch (id) {
-#define FH_BLOCK(vid, vp, vg, vs, vu) \
+#define FH_BLOCK(vid, vp, vg, vs, vu, vpairs) \
   case vid: return vu;
     FH_F64_VARIANTS(FH_BLOCK)
 #undef FH_BLOCK
     default: return 0;
+  }
+}
+
+bool f64_variant_pairs(int id) {
+  switch (id) {
+#define FH_PAIRS(vid, vp, vg, vs, vu, vpairs) \
+  case vid: return vpairs != 0;
+    FH_F64_VARIANTS(FH_PAIRS)
+#undef FH_PAIRS
+    default: return false;
   }
 }
 
@@ -232,8 +281,8 @@ hipError_t launch_eval_f64(const double* x, int64_t m, const NodeTable& t, int64
                            hipStream_t s) {
   if (m == 0) return hipSuccess;
   switch (cfg.variant) {
-#define FH_CASE(vid, vp, vg, vs, vu) \
-  case vid: return launch_v<vp, vg, vs, vu>(x, m, t, n, alt, r, lam, s);
+#define FH_CASE(vid, vp, vg, vs, vu, vpairs) \
+  case vid: return launch_v<vp, vg, vs, vu, vpairs != 0>(x, m, t, n, alt, r, lam, s);
     FH_F64_VARIANTS(FH_CASE)
 #undef FH_CASE
     default: return hipErrorInvalidValue;
@@ -245,8 +294,8 @@ hipError_t launch_eval_f64_many(const double* x, int64_t m, int64_t n, int64_t n
                                 const EvalConfig& cfg, hipStream_t s) {
   if (m == 0 || K == 0) return hipSuccess;
   switch (cfg.variant) {
-#define FH_CASE(vid, vp, vg, vs, vu) \
-  case vid: return launch_many_v<vp, vg, vs, vu>(x, m, n, n_pad, a, K, r, lam, s);
+#define FH_CASE(vid, vp, vg, vs, vu, vpairs) \
+  case vid: return launch_many_v<vp, vg, vs, vu, vpairs != 0>(x, m, n, n_pad, a, K, r, lam, s);
     FH_F64_VARIANTS(FH_CASE)
 #undef FH_CASE
     default: return hipErrorInvalidValue;

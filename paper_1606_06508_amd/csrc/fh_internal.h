@@ -37,6 +37,9 @@ struct NodeTable {
   double* f;      // [n_pad] f_k (exact-hit branch)
   float4* s;      // [n_pad] split form: {binary32 head of x_k, binary32 tail
                   // x_k - head, binary32 of w_k 2^-e, binary32 of w_k f_k 2^-ef}
+  double* pr;     // [n_pad / kPairBlock][kPairRec] node-pair records (binary64)
+  uint32_t* pok;  // [ceil(n_pad / 256)] bit i of word w: pair block 16 w + i passed
+                  // the pack's test (or lies beyond the nodes)
   int64_t n_pad;
 };
 
@@ -55,6 +58,7 @@ EvalConfig choose_eval_config(int32_t prec, int64_t n, int32_t d, int64_t m, boo
 int f64_variant_count();
 void f64_variant_shape(int id, int* p, int* g, int* s);
 int f64_variant_block(int id);  // Lebesgue block length U, 0 for plain sums
+bool f64_variant_pairs(int id);  // sums by node pairs (pair_math.h)
 int split_variant_count();
 void split_variant_shape(int id, int* p, int* g, int* s);
 int split_variant_block(int id);  // node tile of the block sums, 0 for plain sums
@@ -136,6 +140,8 @@ struct PackMany {
   double* w[kPackMany];
   double* wf[kPackMany];
   double* f[kPackMany];
+  double* pr[kPackMany];
+  uint32_t* pok[kPackMany];
   uint32_t* status[kPackMany];
   int32_t d[kPackMany];
 };
@@ -152,6 +158,8 @@ struct EvalMany {
   const double* w[kEvalMany];
   const double* wf[kEvalMany];
   const double* f[kEvalMany];
+  const double* pr[kEvalMany];
+  const uint32_t* pok[kEvalMany];
   const uint32_t* alt[kEvalMany];
   double* r[kEvalMany];
   double* lam[kEvalMany];

@@ -7,6 +7,17 @@
 
 namespace fhk {
 
+// Node-pair records of the binary64 pair variants.  The node table is cut
+// into blocks of kPairBlock records; block b holds the pairs (4i, 4i+2)
+// ("even", i = 0..3) and (4i+1, 4i+3) ("odd") of its records in kPairRec
+// doubles: {c, ok, lo, hi} (lo, hi: the nodes just before and after the
+// block, -inf / +inf at the ends), then for the even and the odd pairs in
+// turn the four m, the four -hh^2 and the four B, J, C and K
+// (pack_pair_records).
+constexpr int64_t kPairBlock = 16;
+constexpr int64_t kPairHead = 4;
+constexpr int64_t kPairRec = kPairHead + 48;
+
 // true if v is +-0, subnormal, infinite or NaN (everything but normal)
 __device__ __forceinline__ bool not_normal(double v) {
   return __builtin_amdgcn_class(v, 0x2F7);
@@ -322,6 +333,174 @@ __device__ __forceinline__ double lebesgue_block_fix(double v, const double* __r
   if (j == 0 || j >= n || j % U == 0) return A;
   const int64_t b = j - j % U;
   return lebesgue_block_replace<G, U>(v, tx + b, tw + b, A);
+}
+
+// ---- Sums by node pairs ----
+//
+// Two records (a, a+2) of a block contribute, to D (B, J) or N (C, K),
+//   w_a / (x - x_a) + w_{a+2} / (x - x_{a+2}) = (B x'' + J) / (x''^2 - hh^2),
+// x'' = (x - c) - m (record layout and coefficients: pack_pair_records).
+// Per pair that is one subtraction, three multiply-adds, one reciprocal of
+// a simultaneous inversion of four denominators and one multiply-add per
+// sum: 9 issue slots for two (point, node) pairs with both sums against 12
+// node by node.  The even pairs of a block form E, its odd pairs O, so the
+// block's Lebesgue term is |E - O| as in accumulate_f64_blocks.
+//
+// Accuracy.  The pair form evaluates (d_a, d_b) = x'' +- hh through x - c
+// and the rounded m, hh, and its numerators through the monomials B x'' and
+// J, so its error is relative to distances of the block's size: at a point
+// at distance delta >= s from the block (s the smaller node spacing just
+// outside it, spans 2 hh <= rho s and |a'|, |b'| <= sigma s by the pack's
+// test), each pair term w_a / d_a + w_b / d_b is perturbed relatively by at
+// most about (2 + 4 sigma + rho / 2) u through the differences,
+// (1 + rho / 4) u through the denominator x''^2 - hh^2, (2 + 3 rho / 2) u
+// through the numerator, and the reciprocal's 27 u: (32 + 4 sigma + 9 rho / 4) u,
+// at most 114 u with sigma <= 16, rho <= 8 (a few u for blocks further away).
+// Closer to the block, the terms have no such bound, so the blocks of the
+// point's two neighbouring nodes x_{j-1} < x <= x_j (one block, or two when
+// the point lies between blocks) are masked out of the loop and summed node
+// by node afterwards (pair_fix_points): every other block is then at least
+// one outer spacing away from the point.  Block b holds node j-1 or j
+// exactly when lo_b < x <= hi_b, lo_b and hi_b the nodes just before and
+// after it: two compares with scalar operands per block and point, no
+// search.
+//
+// Masking multiplies the block's sums by 0 or 1, so a non-finite value in a
+// masked block (a hit, or a denominator that cancels to zero) still makes D
+// NaN and sends the lane to eval_point_exact; finite garbage vanishes.
+
+// One pair group (four pairs; entries at g: m[4], -hh^2[4], B, J, C, K) at
+// the P points x1 = x - c: S = sum (B x'' + J) / q, Nb (+)= sum (C x'' + K) / q;
+// first_n: Nb starts at the group's terms.
+template <int P, bool R>
+__device__ __forceinline__ void pair_group(const double (&x1)[P], const double* __restrict__ g,
+                                           double (&Nb)[P], double (&S)[P], bool first_n) {
+  double pm[4], pq[4], pB[4], pJ[4], pC[4], pK[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    pm[i] = g[i];
+    pq[i] = g[4 + i];
+    pB[i] = g[8 + i];
+    pJ[i] = g[12 + i];
+    pC[i] = R ? g[16 + i] : 0.0;
+    pK[i] = R ? g[20 + i] : 0.0;
+  }
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    double q[4], nd[4], nn[4], y[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double xx = x1[j] - pm[i];
+      q[i] = __builtin_fma(xx, xx, pq[i]);
+      nd[i] = __builtin_fma(pB[i], xx, pJ[i]);
+      if (R) nn[i] = __builtin_fma(pC[i], xx, pK[i]);
+    }
+    group_product_reciprocals<4>(q, y);
+    S[j] = nd[0] * y[0];
+#pragma unroll
+    for (int i = 1; i < 4; ++i) S[j] = __builtin_fma(nd[i], y[i], S[j]);
+    if (R) {
+      Nb[j] = first_n ? nn[0] * y[0] : __builtin_fma(nn[0], y[0], Nb[j]);
+#pragma unroll
+      for (int i = 1; i < 4; ++i) Nb[j] = __builtin_fma(nn[i], y[i], Nb[j]);
+    }
+  }
+}
+
+// Fused sums by node pairs over the records [k_begin, k_end) (wave-uniform,
+// multiples of kPairBlock; every block of the table passed the pack's test):
+// for each block its pair sums, then N += Nb, D += E + O, A += |E - O|,
+// each times 0 where the block holds a node next to the point
+// (lo_b < x <= hi_b); the last such block is kept in rlast (untouched if
+// none).  Lane flags as in accumulate_f64 (D not finite).
+//
+// A VOP3 instruction reads at most one SGPR, so B x'' + J and C x'' + K
+// cannot take both coefficients from the scalar unit: J and K are copied to
+// VGPRs (16 moves per block, shared by the lane's P points; vector loads of
+// them instead leave their latency exposed, measured slower).
+template <int P, bool R, bool L>
+__device__ __forceinline__ void accumulate_f64_pairs(const double (&xp)[P],
+                                                     const double* __restrict__ pr,
+                                                     int64_t k_begin, int64_t k_end,
+                                                     double (&N)[P], double (&D)[P],
+                                                     double (&A)[P], bool (&bad)[P],
+                                                     int32_t (&rlast)[P]) {
+  const int b0 = (int)(k_begin / kPairBlock);
+  const int nb = (int)((k_end - k_begin) / kPairBlock);
+  for (int ib = 0; ib < nb; ++ib) {
+    const int b = b0 + ib;
+    const double* __restrict__ rec = pr + (int64_t)b * kPairRec;
+    double Nb[P], E[P], O[P];
+    const double c = rec[0], lo_b = rec[2], hi_b = rec[3];
+    double x1[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) x1[j] = xp[j] - c;
+    pair_group<P, R>(x1, rec + kPairHead, Nb, E, true);
+    // the odd group's entries load into the SGPRs of the even group's
+    // (48 SGPRs each)
+    __builtin_amdgcn_sched_barrier(0);
+    pair_group<P, R>(x1, rec + kPairHead + 24, Nb, O, false);
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      const bool near = xp[j] > lo_b && xp[j] <= hi_b;
+      const double f = near ? 0.0 : 1.0;
+      rlast[j] = near ? b : rlast[j];
+      if (R) N[j] = __builtin_fma(f, Nb[j], N[j]);
+      D[j] = __builtin_fma(f, E[j] + O[j], D[j]);
+      if (L) A[j] = __builtin_fma(f, fabs(E[j] - O[j]), A[j]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < P; ++j) bad[j] |= !(fabs(D[j]) <= 0x1.fffffffffffffp+1023);
+}
+
+// True when every block of the records [0, n_loop) passed the pack's test
+// (the pack's summary words: bit i of word w for block 16 w + i).
+__device__ __forceinline__ bool pair_table_ok(const uint32_t* __restrict__ pok, int64_t n_loop) {
+  const int64_t words = (n_loop / kPairBlock + 15) / 16;
+  uint32_t all = 0xFFFFu;
+  for (int64_t i = 0; i < words; ++i) all &= pok[i];
+  return __builtin_amdgcn_readfirstlane(all) == 0xFFFFu;
+}
+
+// The masked blocks of accumulate_f64_pairs at the point v (not flagged),
+// node by node: block rlast, and block rlast - 1 too when v is at or below
+// the first node of block rlast (v then lies between the two blocks);
+// N += v_k t, D += w_k t, A += |w_k| |t| with t from groups of G
+// differences.  The loads take 32-bit byte offsets from the table bases,
+// so one offset per group serves all of its loads.
+template <int G, bool R, bool L>
+__device__ __forceinline__ void pair_fix_point(double v, int32_t rlast,
+                                               const double* __restrict__ tx,
+                                               const double* __restrict__ tw,
+                                               const double* __restrict__ twf, double& N,
+                                               double& D, double& A) {
+  const char* __restrict__ bx = reinterpret_cast<const char*>(tx);
+  const char* __restrict__ bw = reinterpret_cast<const char*>(tw);
+  const char* __restrict__ bv = reinterpret_cast<const char*>(twf);
+  const uint32_t first = (uint32_t)rlast * (uint32_t)kPairBlock;
+  const bool two = rlast > 0 && v <= tx[first];
+#pragma unroll 1
+  for (int32_t b = rlast - (two ? 1 : 0); b <= rlast; ++b) {
+#pragma unroll 1
+    for (int h = 0; h < (int)kPairBlock; h += G) {
+      const uint32_t off = ((uint32_t)b * (uint32_t)kPairBlock + (uint32_t)h) * 8u;
+      double dl[G], t[G], wk[G], vk[G];
+#pragma unroll
+      for (int i = 0; i < G; ++i) {
+        dl[i] = v - *reinterpret_cast<const double*>(bx + off + 8 * i);
+        wk[i] = *reinterpret_cast<const double*>(bw + off + 8 * i);
+        vk[i] = R ? *reinterpret_cast<const double*>(bv + off + 8 * i) : 0.0;
+      }
+      group_product_reciprocals<G>(dl, t);
+#pragma unroll
+      for (int i = 0; i < G; ++i) {
+        if (R) N = __builtin_fma(vk[i], t[i], N);
+        D = __builtin_fma(wk[i], t[i], D);
+        if (L) A = __builtin_fma(fabs(wk[i]), fabs(t[i]), A);
+      }
+    }
+  }
 }
 
 }  // namespace fhk

@@ -20,7 +20,7 @@ FH_E_WORKSPACE, FH_E_HIP, FH_E_UNSUPPORTED, FH_E_TOO_LARGE = 6, 7, 8, 9
 FH_FP64, FH_FP32_SPLIT = 0, 1
 FH_OP_WEIGHTS, FH_OP_EVAL, FH_OP_BACKWARD, FH_OP_LEBESGUE_MAX, FH_OP_BACKWARD_SAVED = 0, 1, 2, 3, 4
 FH_MAX_NODES = 1 << 28  # largest node count of one interpolant
-FH_NOALLOC_MAX_NODES = 43648  # largest node count of fh_eval_noalloc
+FH_NOALLOC_MAX_NODES = 28288  # largest node count of fh_eval_noalloc
 PRECISIONS = {"fp64": FH_FP64, "split": FH_FP32_SPLIT, "fp32_split": FH_FP32_SPLIT}
 FH_TUNE_BATCHED_FP64, FH_TUNE_BATCHED_SPLIT = 2, 3
 # kernel families of the tuner: the two precisions of fh_eval and the two of
@@ -87,6 +87,7 @@ def load():
             "fh_variant_shape": ([i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                   ctypes.POINTER(i32)], ctypes.c_int),
             "fh_variant_lebesgue_block": ([i32, i32], i32),
+            "fh_variant_node_pairs": ([i32, i32], i32),
             "fh_variant_strip_points": ([i32, i32], i64),
             "fh_batch_variant": ([vp], i32),
             "fh_batch_strip_points": ([vp], i64),
@@ -517,6 +518,14 @@ def variant_lebesgue_block(precision, variant):
     if u < 0:
         raise FhError(FH_E_ARG, "fh_variant_lebesgue_block")
     return u
+
+
+def variant_node_pairs(precision, variant):
+    """True if a binary64 variant sums its node blocks by pairs of records."""
+    v = load().fh_variant_node_pairs(_family(precision), int(variant))
+    if v < 0:
+        raise FhError(FH_E_ARG, "fh_variant_node_pairs")
+    return bool(v)
 
 
 def variant_strip_points(precision, variant):

@@ -40,6 +40,12 @@ def test_status_strings():
     assert fh.status_string(99) == "unknown status"
 
 
+def lib_pairs_bad_id():
+    lib = fh.load()
+    assert lib.fh_variant_node_pairs(7, 0) == -1
+    return lib.fh_variant_node_pairs(0, 99)
+
+
 def test_workspace_sizes():
     lib = fh.load()
     assert lib.fh_workspace_size(fh.FH_OP_WEIGHTS, 10, 0, 2, 0) == 256
@@ -219,16 +225,21 @@ def test_batched_variant_tables():
 
 
 def test_lebesgue_block_variants():
-    """Binary64 variants 15..18 take the Lebesgue sum by blocks of 16 nodes,
-    split variants 8..11 by tiles of 32 (the block counterparts of plain
-    shapes); every other single variant uses plain sums.  Batched split
-    variants take tiles of 32, batched binary64 ones plain sums."""
+    """Binary64 variants 15..24 take the Lebesgue sum by blocks of 16 nodes,
+    19..24 of them summing each block by node pairs; split variants 8..11 by
+    tiles of 32 (the block counterparts of plain shapes); every other single
+    variant uses plain sums.  Batched split variants take tiles of 32,
+    batched binary64 ones plain sums."""
     blocks = {vid: fh.variant_lebesgue_block("fp64", vid) for vid, *_ in fh.variants("fp64")}
-    assert {vid for vid, u in blocks.items() if u} == {15, 16, 17, 18}
+    assert {vid for vid, u in blocks.items() if u} == set(range(15, 25))
     assert set(blocks.values()) == {0, 16}
+    pairs = {vid for vid, *_ in fh.variants("fp64") if fh.variant_node_pairs("fp64", vid)}
+    assert pairs == set(range(19, 25))
+    assert not any(fh.variant_node_pairs(f, 0) for f in ("split", "batched_fp64", "batched_split"))
     shapes = {vid: (p, g, s) for vid, p, g, s in fh.variants("fp64")}
-    for vid in (15, 16, 17, 18):
+    for vid in range(15, 25):
         assert shapes[vid] in [shapes[v] for v, u in blocks.items() if u == 0]
+    assert lib_pairs_bad_id() == -1
     sb = {vid: fh.variant_lebesgue_block("split", vid) for vid, *_ in fh.variants("split")}
     assert {vid for vid, u in sb.items() if u} == {8, 9, 10, 11} and set(sb.values()) == {0, 32}
     sshapes = {vid: (p, g, s) for vid, p, g, s in fh.variants("split")}
@@ -417,7 +428,7 @@ def test_fh_log_reports_choices():
     p = _run_py(code, {"FH_LOG": "1"})
     assert p.returncode == 0, p.stderr
     lines = [ln for ln in p.stderr.splitlines() if ln.startswith("[fh]")]
-    assert lines == ["[fh] fp64 n=1001 m=1000000: variant 17 (built-in)",
+    assert lines == ["[fh] fp64 n=1001 m=1000000: variant 22 (built-in)",
                      "[fh] batched_split n=1041 m=204421648: variant 5 (built-in)"], p.stderr
     q = _run_py(code, {"FH_LOG": "0"})
     assert q.returncode == 0 and "[fh]" not in q.stderr
@@ -434,7 +445,7 @@ def test_autotune_cache_for_another_architecture_is_ignored(tmp_path):
     code = "from paper_1606_06508_amd import fh\nprint(fh.tune_get('fp64', 1001, 10**6))\n"
     p = _run_py(code, {"FH_LOG": "1", "FH_AUTOTUNE_CACHE": str(path)})
     assert p.returncode == 0, p.stderr
-    assert p.stdout.strip() == "17"
+    assert p.stdout.strip() == "22"
     assert "made for 'gfx000'" in p.stderr and "ignored" in p.stderr
     q = _run_py(code, {"FH_LOG": "1", "FH_AUTOTUNE_CACHE": str(tmp_path / "missing.json")})
-    assert q.stdout.strip() == "17" and "cannot open" in q.stderr
+    assert q.stdout.strip() == "22" and "cannot open" in q.stderr

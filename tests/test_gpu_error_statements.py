@@ -6,7 +6,12 @@ each reciprocal carries at most 27 u (the hardware estimate, at most
 product tree that do not cancel), the difference 1 u and the weighted value
 1 u; recursive summation adds at most n u; with the oracle's own 3 u the
 computed r and Lambda differ from the oracle's by at most (n + 33) u in
-e_cond terms.
+e_cond terms.  The node-pair variants evaluate two terms at once through the
+block's coordinates: at a point at least one outer node spacing s from the
+block (pair spans at most 8 s and node offsets from the block's anchor at most
+16 s, the pack's test) each pair term carries at most about
+(32 + 4 * 16 + 9 * 8 / 4) u = 114 u instead of 29 u, so their bound is
+(n + 33 + 85) u; the blocks next to the point are summed node by node.
 
 FP32-split: the float-float difference 2 u32, the reciprocal 2 u32 (one ulp,
 G = 1) or 6 u32 (G = 4: the ulp of v_rcp_f32 plus four roundings), the
@@ -58,7 +63,7 @@ def test_fp64_first_order_bound(n, d):
         finally:
             fh.tune_force("fp64", -1)
         st = metrics.parity(r, lam, r_o, lam_o, s_o)
-        bound = (n + 33) * U64
+        bound = (n + 33 + (85 if fh.variant_node_pairs("fp64", vid) else 0)) * U64
         assert st["e_cond_max"] <= bound and st["e_cond_lam_max"] <= bound, (vid, grp, st)
 
 

@@ -53,7 +53,7 @@ def test_bits_independent_of_call_shape(n, m, K):
         assert _bits_equal(many[0][c], r1) and _bits_equal(many[1][c], l1), (n, m, K, c)
 
 
-@pytest.mark.parametrize("vid", [3, 10, 15, 17, 18])
+@pytest.mark.parametrize("vid", [3, 10, 15, 17, 18, 20, 22])
 @pytest.mark.parametrize("mode", ["both", "r", "lambda"])
 def test_bits_of_single_calls(vid, mode):
     nodes, vals, pts = _case(1001, 20011, 7)
@@ -98,16 +98,18 @@ def test_counts_and_one_by_one_tables(K, m):
                            lam_metric="cond")
 
 
-def test_caller_weights_table_among_library_tables():
+@pytest.mark.parametrize("vid", [17, 22])
+def test_caller_weights_table_among_library_tables(vid):
     """A table prepared with caller weights that do not alternate takes
-    plain sums inside the same launch as block-sum tables."""
+    plain sums inside the same launch as block-sum (17) or node-pair (22)
+    tables."""
     nodes, vals, pts = _case(300, 5000, 3)
     w_pos = np.random.default_rng(2).uniform(0.5, 2.0, 300)
     preps = [fh.Prepared(_t(nodes), _t(vals), 3),
              fh.Prepared(_t(nodes), _t(vals), 3, weights=_t(w_pos)),
              fh.Prepared(_t(nodes), _t(vals), 5)]
     x = _t(pts)
-    fh.tune_force("fp64", 17)
+    fh.tune_force("fp64", vid)
     try:
         r, lam = fh.eval_many(preps, x, lebesgue=True)
         single = [p(x, lebesgue=True) for p in preps]

@@ -1,0 +1,152 @@
+"""The node-pair launch variants of the binary64 evaluation.
+
+Two records (a, a+2) of a 16-node block give one rational term
+(B x'' + J) / (x''^2 - hh^2) for w_a/(x - x_a) + w_{a+2}/(x - x_{a+2})
+(and C, K for the weighted values), with x'' measured from the block's
+anchor and the pair's midpoint.  The blocks holding the nodes next to a
+point (one, or two for a point between blocks) are masked out of the loop
+and summed node by node; a table whose blocks are too wide next to the node
+spacings around them (the pack's test) is summed by the node-block variant
+of the same shape instead.  Checked against the oracle at the points where
+the masking decides (every node, one ulp on either side of the nodes at the
+block edges, midpoints between blocks, just outside the end nodes, far
+away), and bit for bit against the node-block twin for a table that fails
+the test.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import metrics, oracle
+from paper_1606_06508_amd import fh, inputs
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+U64 = 2.0 ** -53
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def _pair_variants():
+    return [v for v in fh.variants("fp64") if fh.variant_node_pairs("fp64", v[0])]
+
+
+def _run(nodes, vals, d, pts, vid, lebesgue=True):
+    fh.tune_force("fp64", vid)
+    try:
+        out = fh.evaluate(_t(nodes), _t(vals), d, _t(pts), lebesgue=lebesgue)
+    finally:
+        fh.tune_force("fp64", -1)
+    torch.cuda.synchronize()
+    return out
+
+
+def _edge_points(nodes):
+    n = nodes.size
+    edges = sorted({k for b in range(0, n, 16) for k in (b - 1, b, b + 15, b + 16) if 0 <= k < n})
+    e = nodes[edges]
+    gaps = np.diff(nodes)
+    mids = nodes[:-1] + 0.5 * gaps
+    return np.concatenate([
+        nodes,                                           # every node: hits
+        np.nextafter(e, np.inf), np.nextafter(e, -np.inf),  # one ulp beside the block edges
+        mids[[k for k in edges if k < n - 1]],           # between the edge nodes
+        [nodes[0] - 1e-9, nodes[-1] + 1e-9, nodes[0] - 0.3, nodes[-1] + 0.3, -10.0, 1e6],
+        [np.nan, np.inf, -np.inf]])
+
+
+@pytest.mark.parametrize("kind,n,d", [("equispaced", 257, 3), ("cheb2", 300, 5),
+                                      ("jittered", 1001, 8), ("equispaced", 17, 2),
+                                      ("jittered", 33, 4), ("equispaced", 4, 1)])
+def test_block_edges_against_oracle(kind, n, d):
+    g = np.random.default_rng(n + 7 * d)
+    nodes = {"equispaced": inputs.equispaced, "cheb2": inputs.cheb2}.get(
+        kind, lambda k: inputs.jittered_nodes(k, g, rel=0.3))(n)
+    vals = np.sin(3 * nodes) + 0.1 * g.standard_normal(n)
+    pts = np.concatenate([_edge_points(nodes), g.uniform(nodes[0], nodes[-1], 5000)])
+    r_o, lam_o, s_o = oracle.evaluate(nodes, vals, d, pts)
+    hit = np.isin(pts, nodes)
+    for vid, p, grp, s in _pair_variants():
+        r, lam = _run(nodes, vals, d, pts, vid)
+        r, lam = r.cpu().numpy(), lam.cpu().numpy()
+        st = metrics.parity(r, lam, r_o, lam_o, s_o)
+        metrics.check_fp64(st, lam_metric="cond")
+        bound = (n + 33 + 85) * U64
+        assert st["e_cond_max"] <= bound and st["e_cond_lam_max"] <= bound, (vid, st)
+        assert np.array_equal(r[hit], vals[np.searchsorted(nodes, pts[hit])]), vid
+        assert np.all(lam[hit] == 1.0), vid
+        assert np.array_equal(np.isnan(r), np.isnan(r_o)), vid
+
+
+def _wide_block_nodes(n, g):
+    """Equispaced nodes whose fourth block is stretched 20 times: its pair
+    spans are 40 times the spacing just outside it."""
+    h = np.ones(n - 1)
+    h[48:63] = 20.0
+    x = np.concatenate([[0.0], np.cumsum(h)])
+    return -1.0 + 2.0 * x / x[-1]
+
+
+def test_table_failing_the_pack_test_takes_block_sums():
+    g = np.random.default_rng(3)
+    n, d = 200, 3
+    nodes = _wide_block_nodes(n, g)
+    vals = np.cos(2 * nodes)
+    pts = np.concatenate([_edge_points(nodes), g.uniform(-1, 1, 4000)])
+    r_o, lam_o, s_o = oracle.evaluate(nodes, vals, d, pts)
+    twins = {(p, s): vid for vid, p, grp, s in fh.variants("fp64")
+             if fh.variant_lebesgue_block("fp64", vid) and not fh.variant_node_pairs("fp64", vid)}
+    checked = 0
+    for vid, p, grp, s in _pair_variants():
+        r, lam = _run(nodes, vals, d, pts, vid)
+        st = metrics.parity(r.cpu().numpy(), lam.cpu().numpy(), r_o, lam_o, s_o)
+        metrics.check_fp64(st, lam_metric="cond")
+        # same slicing: the bits of a node-block variant (points per lane do
+        # not change them)
+        twin = next((t for (tp, ts), t in twins.items() if ts == s), None)
+        if twin is None:
+            continue
+        r2, lam2 = _run(nodes, vals, d, pts, twin)
+        for a, b in ((r, r2), (lam, lam2)):
+            a, b = a.cpu().numpy(), b.cpu().numpy()
+            assert np.array_equal(np.isnan(a), np.isnan(b)), vid
+            assert np.array_equal(a[~np.isnan(a)].view(np.uint64),
+                                  b[~np.isnan(b)].view(np.uint64)), (vid, twin)
+        checked += 1
+    assert checked >= 2
+
+
+def test_pairs_change_the_bits_of_a_passing_table():
+    """On a table that passes the test the pair variants do take the pair
+    path: their bits differ from the node-block twin's (the same sums in
+    another order), both within the oracle's bar."""
+    g = np.random.default_rng(4)
+    nodes = inputs.equispaced(513)
+    vals = g.standard_normal(513)
+    pts = g.uniform(-1, 1, 20000)
+    r1, _ = _run(nodes, vals, 4, pts, 22)
+    r2, _ = _run(nodes, vals, 4, pts, 18)
+    assert not torch.equal(r1, r2)
+
+
+def test_lebesgue_only_and_r_only_bits():
+    g = np.random.default_rng(6)
+    nodes = inputs.jittered_nodes(700, g, rel=0.3)
+    vals = g.standard_normal(700)
+    pts = np.concatenate([_edge_points(nodes), g.uniform(-1, 1, 3000)])
+    for vid, *_ in _pair_variants():
+        r, lam = _run(nodes, vals, 5, pts, vid)
+        r_only = _run(nodes, vals, 5, pts, vid, lebesgue=False)
+        fh.tune_force("fp64", vid)
+        try:
+            lam_only = fh.lebesgue(_t(nodes), 5, _t(pts))
+        finally:
+            fh.tune_force("fp64", -1)
+        for a, b in ((r, r_only), (lam, lam_only)):
+            a, b = a.cpu().numpy(), b.cpu().numpy()
+            assert np.array_equal(np.isnan(a), np.isnan(b)), vid
+            assert np.array_equal(a[~np.isnan(a)].view(np.uint64),
+                                  b[~np.isnan(b)].view(np.uint64)), vid
