@@ -45,9 +45,10 @@ namespace fhk {
 // PAIRS (U = 16): when every block of the table passed the pack's test
 // (summary words pok), the blocks are summed by node pairs
 // (accumulate_f64_pairs) from the pair records pr and the blocks next to
-// each point node by node afterwards (pair_fix_points); otherwise as U = 16
-// without pairs.
-template <int P, int G, int S, bool R, bool L, int U, bool PAIRS>
+// each point node by node afterwards (pair_fix_point); otherwise as U = 16
+// without pairs.  JKL: the pair terms' J and K are staged in LDS first
+// (jk_lds, n_loop doubles; the launch passes that much dynamic LDS).
+template <int P, int G, int S, bool R, bool L, int U, bool PAIRS, bool JKL>
 __device__ __forceinline__ void eval_f64_points(const double* __restrict__ x, int64_t m,
                                                 const double* __restrict__ tx,
                                                 const double* __restrict__ tw,
@@ -56,8 +57,10 @@ __device__ __forceinline__ void eval_f64_points(const double* __restrict__ x, in
                                                 const uint32_t* __restrict__ pok, int64_t n_pad,
                                                 const double* __restrict__ f, int64_t n,
                                                 const uint32_t* __restrict__ alt,
-                                                double* __restrict__ r, double* __restrict__ lam) {
+                                                double* __restrict__ r, double* __restrict__ lam,
+                                                double* jk_lds) {
   static_assert(!PAIRS || U == kPairBlock, "pair records come in blocks of 16");
+  static_assert(PAIRS || !JKL, "LDS staging serves the pair variants");
   constexpr int PG = 4 / S;  // point groups per block
   const int lane = threadIdx.x & 63;
   // wave index, made provably wave-uniform so node loads stay scalar
@@ -96,8 +99,13 @@ __device__ __forceinline__ void eval_f64_points(const double* __restrict__ x, in
   if constexpr (U > 0) {
     blocks = __builtin_amdgcn_readfirstlane(*alt) != 0;
     if constexpr (PAIRS) pairs = blocks && pair_table_ok(pok, n_loop);
+    if constexpr (JKL) {
+      // every thread of the block takes part before any wave branches
+      if (pairs) pair_stage_jk(pr, n_loop, jk_lds);
+      __syncthreads();
+    }
     if (pairs) {
-      accumulate_f64_pairs<P, R, L>(xp, pr, k_begin, k_end, N, D, A, bad, rlast);
+      accumulate_f64_pairs<P, R, L, JKL>(xp, pr, jk_lds, k_begin, k_end, N, D, A, bad, rlast);
     } else if (blocks) {
       accumulate_f64_blocks<P, G, U, R, L>(xp, tx, tw, twf, k_begin, k_end, N, D, A, bad);
     }
@@ -171,57 +179,91 @@ __device__ __forceinline__ void eval_f64_points(const double* __restrict__ x, in
   }
 }
 
-template <int P, int G, int S, bool R, bool L, int U, bool PAIRS>
+template <int P, int G, int S, bool R, bool L, int U, bool PAIRS, bool JKL>
 __global__ void __launch_bounds__(256)
     k_eval_f64(const double* __restrict__ x, int64_t m, const double* __restrict__ tx,
                const double* __restrict__ tw, const double* __restrict__ twf,
                const double* __restrict__ pr, const uint32_t* __restrict__ pok, int64_t n_pad,
                const double* __restrict__ f, int64_t n, const uint32_t* __restrict__ alt,
                double* __restrict__ r, double* __restrict__ lam) {
-  eval_f64_points<P, G, S, R, L, U, PAIRS>(x, m, tx, tw, twf, pr, pok, n_pad, f, n, alt, r, lam);
+  extern __shared__ double jk_lds[];
+  eval_f64_points<P, G, S, R, L, U, PAIRS, JKL>(x, m, tx, tw, twf, pr, pok, n_pad, f, n, alt, r,
+                                                lam, jk_lds);
 }
 
 // Several tables on the same points: table blockIdx.y, the points of
 // blockIdx.x as in k_eval_f64.  One launch instead of one per table saves
 // the drain of each launch's last blocks and the gap before the next.
-template <int P, int G, int S, bool R, bool L, int U, bool PAIRS>
+template <int P, int G, int S, bool R, bool L, int U, bool PAIRS, bool JKL>
 __global__ void __launch_bounds__(256)
     k_eval_f64_many(const double* __restrict__ x, int64_t m, int64_t n_pad, int64_t n,
                     EvalMany a) {
+  extern __shared__ double jk_lds[];
   const int i = blockIdx.y;
-  eval_f64_points<P, G, S, R, L, U, PAIRS>(x, m, a.x[i], a.w[i], a.wf[i], a.pr[i], a.pok[i],
-                                           n_pad, a.f[i], n, a.alt[i], a.r[i], a.lam[i]);
+  eval_f64_points<P, G, S, R, L, U, PAIRS, JKL>(x, m, a.x[i], a.w[i], a.wf[i], a.pr[i],
+                                                a.pok[i], n_pad, a.f[i], n, a.alt[i], a.r[i],
+                                                a.lam[i], jk_lds);
+}
+
+// Dynamic LDS of a pair variant's launch: J and K of the node range when it
+// is at most kPairLdsRecords records (then the JKL kernel runs), else 0.
+static size_t pair_lds_bytes(int64_t n) {
+  const int64_t n_loop = round_up(n, kPairBlock);
+  return n_loop <= kPairLdsRecords ? sizeof(double) * (size_t)n_loop : 0;
+}
+
+template <int P, int G, int S, int U, bool PAIRS, bool JKL>
+static hipError_t launch_many_k(const double* x, int64_t m, int64_t n, int64_t n_pad,
+                                const EvalMany& a, int32_t K, bool r, bool lam, size_t lds,
+                                hipStream_t s) {
+  const int64_t per = 64LL * P * (4 / S);  // points per block
+  const dim3 grid((unsigned)((m + per - 1) / per), (unsigned)K), block(256);
+  if (r && lam)
+    k_eval_f64_many<P, G, S, true, true, U, PAIRS, JKL><<<grid, block, lds, s>>>(x, m, n_pad, n,
+                                                                                a);
+  else if (r)
+    k_eval_f64_many<P, G, S, true, false, U, PAIRS, JKL><<<grid, block, lds, s>>>(x, m, n_pad, n,
+                                                                                 a);
+  else
+    k_eval_f64_many<P, G, S, false, true, U, PAIRS, JKL><<<grid, block, lds, s>>>(x, m, n_pad, n,
+                                                                                 a);
+  return hipGetLastError();
 }
 
 template <int P, int G, int S, int U, bool PAIRS>
 static hipError_t launch_many_v(const double* x, int64_t m, int64_t n, int64_t n_pad,
                                 const EvalMany& a, int32_t K, bool r, bool lam, hipStream_t s) {
+  const size_t lds = PAIRS ? pair_lds_bytes(n) : 0;
+  if constexpr (PAIRS)
+    if (lds > 0) return launch_many_k<P, G, S, U, true, true>(x, m, n, n_pad, a, K, r, lam, lds, s);
+  return launch_many_k<P, G, S, U, PAIRS, false>(x, m, n, n_pad, a, K, r, lam, 0, s);
+}
+
+template <int P, int G, int S, int U, bool PAIRS, bool JKL>
+static hipError_t launch_k(const double* x, int64_t m, const NodeTable& t, int64_t n,
+                           const uint32_t* alt, double* r, double* lam, size_t lds,
+                           hipStream_t s) {
   const int64_t per = 64LL * P * (4 / S);  // points per block
-  const dim3 grid((unsigned)((m + per - 1) / per), (unsigned)K), block(256);
+  const dim3 grid((unsigned)((m + per - 1) / per)), block(256);
   if (r && lam)
-    k_eval_f64_many<P, G, S, true, true, U, PAIRS><<<grid, block, 0, s>>>(x, m, n_pad, n, a);
+    k_eval_f64<P, G, S, true, true, U, PAIRS, JKL><<<grid, block, lds, s>>>(
+        x, m, t.x, t.w, t.wf, t.pr, t.pok, t.n_pad, t.f, n, alt, r, lam);
   else if (r)
-    k_eval_f64_many<P, G, S, true, false, U, PAIRS><<<grid, block, 0, s>>>(x, m, n_pad, n, a);
+    k_eval_f64<P, G, S, true, false, U, PAIRS, JKL><<<grid, block, lds, s>>>(
+        x, m, t.x, t.w, t.wf, t.pr, t.pok, t.n_pad, t.f, n, alt, r, lam);
   else
-    k_eval_f64_many<P, G, S, false, true, U, PAIRS><<<grid, block, 0, s>>>(x, m, n_pad, n, a);
+    k_eval_f64<P, G, S, false, true, U, PAIRS, JKL><<<grid, block, lds, s>>>(
+        x, m, t.x, t.w, t.wf, t.pr, t.pok, t.n_pad, t.f, n, alt, r, lam);
   return hipGetLastError();
 }
 
 template <int P, int G, int S, int U, bool PAIRS>
 static hipError_t launch_v(const double* x, int64_t m, const NodeTable& t, int64_t n,
                            const uint32_t* alt, double* r, double* lam, hipStream_t s) {
-  const int64_t per = 64LL * P * (4 / S);  // points per block
-  const dim3 grid((unsigned)((m + per - 1) / per)), block(256);
-  if (r && lam)
-    k_eval_f64<P, G, S, true, true, U, PAIRS><<<grid, block, 0, s>>>(
-        x, m, t.x, t.w, t.wf, t.pr, t.pok, t.n_pad, t.f, n, alt, r, lam);
-  else if (r)
-    k_eval_f64<P, G, S, true, false, U, PAIRS><<<grid, block, 0, s>>>(
-        x, m, t.x, t.w, t.wf, t.pr, t.pok, t.n_pad, t.f, n, alt, r, lam);
-  else
-    k_eval_f64<P, G, S, false, true, U, PAIRS><<<grid, block, 0, s>>>(
-        x, m, t.x, t.w, t.wf, t.pr, t.pok, t.n_pad, t.f, n, alt, r, lam);
-  return hipGetLastError();
+  const size_t lds = PAIRS ? pair_lds_bytes(n) : 0;
+  if constexpr (PAIRS)
+    if (lds > 0) return launch_k<P, G, S, U, true, true>(x, m, t, n, alt, r, lam, lds, s);
+  return launch_k<P, G, S, U, PAIRS, false>(x, m, t, n, alt, r, lam, 0, s);
 }
 
 // Variant table: id -> (points per lane P, group size G, node split S,

@@ -371,19 +371,22 @@ __device__ __forceinline__ double lebesgue_block_fix(double v, const double* __r
 
 // One pair group (four pairs; entries at g: m[4], -hh^2[4], B, J, C, K) at
 // the P points x1 = x - c: S = sum (B x'' + J) / q, Nb (+)= sum (C x'' + K) / q;
-// first_n: Nb starts at the group's terms.
-template <int P, bool R>
+// first_n: Nb starts at the group's terms.  JKL: the group's J[4], K[4]
+// come from jk (LDS, staged by pair_stage_jk), read into VGPRs by the LDS
+// pipe.
+template <int P, bool R, bool JKL>
 __device__ __forceinline__ void pair_group(const double (&x1)[P], const double* __restrict__ g,
-                                           double (&Nb)[P], double (&S)[P], bool first_n) {
+                                           const double* jk, double (&Nb)[P], double (&S)[P],
+                                           bool first_n) {
   double pm[4], pq[4], pB[4], pJ[4], pC[4], pK[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     pm[i] = g[i];
     pq[i] = g[4 + i];
     pB[i] = g[8 + i];
-    pJ[i] = g[12 + i];
+    pJ[i] = JKL ? jk[i] : g[12 + i];
     pC[i] = R ? g[16 + i] : 0.0;
-    pK[i] = R ? g[20 + i] : 0.0;
+    pK[i] = R ? (JKL ? jk[4 + i] : g[20 + i]) : 0.0;
   }
 #pragma unroll
   for (int j = 0; j < P; ++j) {
@@ -415,16 +418,18 @@ __device__ __forceinline__ void pair_group(const double (&x1)[P], const double* 
 // none).  Lane flags as in accumulate_f64 (D not finite).
 //
 // A VOP3 instruction reads at most one SGPR, so B x'' + J and C x'' + K
-// cannot take both coefficients from the scalar unit: J and K are copied to
-// VGPRs (16 moves per block, shared by the lane's P points; vector loads of
-// them instead leave their latency exposed, measured slower).
-template <int P, bool R, bool L>
+// cannot take both coefficients from the scalar unit.  With JKL (the
+// table's J and K staged in jk_lds by pair_stage_jk) they come from LDS
+// broadcast reads, which use the LDS pipe; without it they are copied from
+// SGPRs to VGPRs, 16 moves per block shared by the lane's P points (vector
+// loads from memory instead left their latency exposed, measured slower).
+template <int P, bool R, bool L, bool JKL>
 __device__ __forceinline__ void accumulate_f64_pairs(const double (&xp)[P],
                                                      const double* __restrict__ pr,
-                                                     int64_t k_begin, int64_t k_end,
-                                                     double (&N)[P], double (&D)[P],
-                                                     double (&A)[P], bool (&bad)[P],
-                                                     int32_t (&rlast)[P]) {
+                                                     const double* jk_lds, int64_t k_begin,
+                                                     int64_t k_end, double (&N)[P],
+                                                     double (&D)[P], double (&A)[P],
+                                                     bool (&bad)[P], int32_t (&rlast)[P]) {
   const int b0 = (int)(k_begin / kPairBlock);
   const int nb = (int)((k_end - k_begin) / kPairBlock);
   for (int ib = 0; ib < nb; ++ib) {
@@ -435,11 +440,12 @@ __device__ __forceinline__ void accumulate_f64_pairs(const double (&xp)[P],
     double x1[P];
 #pragma unroll
     for (int j = 0; j < P; ++j) x1[j] = xp[j] - c;
-    pair_group<P, R>(x1, rec + kPairHead, Nb, E, true);
+    const double* jk = jk_lds + b * (int)kPairBlock;
+    pair_group<P, R, JKL>(x1, rec + kPairHead, jk, Nb, E, true);
     // the odd group's entries load into the SGPRs of the even group's
     // (48 SGPRs each)
     __builtin_amdgcn_sched_barrier(0);
-    pair_group<P, R>(x1, rec + kPairHead + 24, Nb, O, false);
+    pair_group<P, R, JKL>(x1, rec + kPairHead + 24, jk + 8, Nb, O, false);
 #pragma unroll
     for (int j = 0; j < P; ++j) {
       const bool near = xp[j] > lo_b && xp[j] <= hi_b;
@@ -452,6 +458,27 @@ __device__ __forceinline__ void accumulate_f64_pairs(const double (&xp)[P],
   }
 #pragma unroll
   for (int j = 0; j < P; ++j) bad[j] |= !(fabs(D[j]) <= 0x1.fffffffffffffp+1023);
+}
+
+// Largest node range whose J and K the pair variants stage in LDS (8 B per
+// record: 32 KB).
+constexpr int64_t kPairLdsRecords = 4096;
+
+// Copies J and K of the blocks [0, n_loop / 16) from the pair records into
+// jk_lds ([block][J even[4], K even[4], J odd[4], K odd[4]]), all threads of
+// the block taking part; the caller synchronizes.
+__device__ __forceinline__ void pair_stage_jk(const double* __restrict__ pr, int64_t n_loop,
+                                              double* jk_lds) {
+  const int chunks = (int)(n_loop / kPairBlock) * 4;
+  for (int i = threadIdx.x; i < chunks; i += blockDim.x) {
+    const int b = i >> 2, g = (i >> 1) & 1, k = i & 1;
+    const double* src = pr + (int64_t)b * kPairRec + kPairHead + 24 * g + (k ? 20 : 12);
+    double* dst = jk_lds + b * kPairBlock + 8 * g + 4 * k;
+    const double2 a = reinterpret_cast<const double2*>(src)[0];
+    const double2 c = reinterpret_cast<const double2*>(src)[1];
+    reinterpret_cast<double2*>(dst)[0] = a;
+    reinterpret_cast<double2*>(dst)[1] = c;
+  }
 }
 
 // True when every block of the records [0, n_loop) passed the pack's test
