@@ -22,15 +22,16 @@
 // P, node split S, the binary64 Lebesgue block U (0 = plain sums; 16 = sums
 // by node blocks, one multiply-add per pair for D and the Lebesgue sum, the
 // block around each point corrected afterwards; the batch's weights are the
-// library's, which alternate in sign) and passes per strip Q.  Binary64
-// variants with U = 16 pad each instance to a multiple of 16 records, the
-// others to 8.  The split kernel always takes its sums by node tiles (with
+// library's, which alternate in sign), passes per strip Q, and for U = 16
+// sums by node pairs (pair_math.h; an instance with a block that fails the
+// pair test takes the node-block sums).  Binary64 variants with U = 16 pad
+// each instance to a multiple of 16 records, the others to 8.  The split kernel always takes its sums by node tiles (with
 // or without Lambda, so r does not depend on it); its variants are P and Q.
 //
 // Graph.  fh_batch_create captures, on a private stream: a one-thread kernel
 // that resets the item counter (a kernel rather than a memset node), the
-// weight/packing pass for all instances, the split packing pass if needed,
-// and the persistent evaluation kernel.  fh_eval_batched is one
+// weight/packing pass for all instances, the split or node-pair packing pass
+// if needed, and the persistent evaluation kernel.  fh_eval_batched is one
 // hipGraphLaunch.
 #include <algorithm>
 #include <cstdio>
@@ -50,8 +51,11 @@ namespace fhk {
 struct InstDesc {
   int64_t noff, n, toff, n_pad, poff, m;
   int32_t d, strips;
-  int32_t shift;  // split: ef - e of the instance's table (written by its packing)
-  int32_t wide;   // split: 1 if the instance takes binary64 terms (written by its packing)
+  int32_t shift;       // split: ef - e of the instance's table (written by its packing)
+  int32_t wide;        // split: 1 if the instance takes binary64 terms (written by its packing)
+  int32_t pairs_bad;   // binary64 pair variants: blocks of the instance that failed the
+                       // pair test (written by k_batch_pack_pairs; 0: sums by node pairs)
+  int32_t reserved;
 };
 
 constexpr int64_t kBatchPad = 8;
@@ -118,6 +122,30 @@ __global__ void __launch_bounds__(256)
   if (threadIdx.x == 0) inst[blockIdx.x].wide = wide;
 }
 
+// One block per instance: the node-pair records of its blocks of 16 records
+// (pair_record_header / pair_record_pair, one thread per block of records)
+// and the number of blocks that failed the pair test.
+__global__ void __launch_bounds__(256)
+    k_batch_pack_pairs(InstDesc* __restrict__ inst, const double* __restrict__ tx,
+                       const double* __restrict__ tw, const double* __restrict__ twf,
+                       double* __restrict__ tpr) {
+  __shared__ int bad_blocks;
+  if (threadIdx.x == 0) bad_blocks = 0;
+  __syncthreads();
+  const InstDesc ds = inst[blockIdx.x];
+  const double* x = tx + ds.toff;
+  int mine = 0;
+  for (int64_t b = threadIdx.x; b * kPairBlock < ds.n_pad; b += blockDim.x) {
+    const int64_t k0 = b * kPairBlock;
+    double* rec = tpr + (ds.toff / kPairBlock + b) * kPairRec;
+    for (int t = 0; t < 8; ++t) pair_record_pair(x, ds.n, k0, tw + ds.toff + k0, twf + ds.toff + k0, t, rec);
+    mine += pair_record_header(x, ds.n, k0, tw + ds.toff + k0, twf + ds.toff + k0, rec) ? 0 : 1;
+  }
+  if (mine) atomicAdd(&bad_blocks, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) inst[blockIdx.x].pairs_bad = bad_blocks;
+}
+
 __global__ void k_batch_reset(uint32_t* counter) { *counter = 0u; }
 
 // ------------------------------------------------------ persistent eval --
@@ -132,14 +160,19 @@ __device__ __forceinline__ int next_item(uint32_t* counter, int* s_item) {
 
 // Binary64: wave (slice, pg) of the block owns the 64 * P points pg of the
 // pass and the node slice `slice` (whole node groups, or whole blocks of U
-// records); the S partial sums meet in LDS in wave order.
-template <int P, int G, int S, bool R, bool L, int U>
+// records); the S partial sums meet in LDS in wave order.  PAIRS (U = 16):
+// an instance whose blocks all passed the pair test is summed by node pairs
+// from its records in tpr (J and K copied to VGPRs), the blocks next to
+// each point node by node afterwards, as in k_eval_f64; the others as
+// U = 16 without pairs.
+template <int P, int G, int S, bool R, bool L, int U, bool PAIRS>
 __global__ void __launch_bounds__(256)
     k_batch_f64(const InstDesc* __restrict__ inst, const int2* __restrict__ items, int n_items,
                 int32_t passes, uint32_t* counter, const double* __restrict__ x,
                 double* __restrict__ r, double* __restrict__ lam, const double* __restrict__ tx,
                 const double* __restrict__ tw, const double* __restrict__ twf,
-                const double* __restrict__ tf) {
+                const double* __restrict__ tf, const double* __restrict__ tpr) {
+  static_assert(!PAIRS || U == kPairBlock, "pair records come in blocks of 16");
   constexpr int PG = 4 / S;  // point groups per block
   constexpr int64_t kPass = 64LL * P * PG;
   constexpr int64_t kUnit = U > 0 ? U : G;
@@ -155,6 +188,8 @@ __global__ void __launch_bounds__(256)
     const int64_t strip = __builtin_amdgcn_readfirstlane(it.y);
     const double* px = x + ds.poff;
     const double *ix = tx + ds.toff, *iw = tw + ds.toff, *iwf = twf + ds.toff, *iff = tf + ds.toff;
+    const bool pairs = PAIRS && __builtin_amdgcn_readfirstlane(ds.pairs_bad) == 0;
+    const double* ipr = PAIRS ? tpr + (ds.toff / kPairBlock) * kPairRec : tpr;
     // node slice of this wave: whole units, the last slices possibly shorter
     const int64_t units = ds.n_pad / kUnit;
     const int64_t per_slice = (units + S - 1) / S;
@@ -167,14 +202,19 @@ __global__ void __launch_bounds__(256)
       const int64_t base = pass0 + pg * 64 * P + lane;
       double xp[P], N[P], D[P], A[P];
       bool bad[P];
+      int32_t rlast[P];
 #pragma unroll
       for (int j = 0; j < P; ++j) {
         const int64_t idx = base + j * 64;
         xp[j] = px[idx < ds.m ? idx : ds.m - 1];
         N[j] = D[j] = A[j] = 0.0;
         bad[j] = false;
+        rlast[j] = -1;
       }
-      if constexpr (U > 0)
+      if (pairs)
+        accumulate_f64_pairs<P, R, L, false>(xp, ipr, ipr, u0 * kUnit, u1 * kUnit, N, D, A, bad,
+                                             rlast);
+      else if constexpr (U > 0)
         accumulate_f64_blocks<P, G, U, R, L>(xp, ix, iw, iwf, u0 * kUnit, u1 * kUnit, N, D, A,
                                              bad);
       else
@@ -182,6 +222,7 @@ __global__ void __launch_bounds__(256)
       if constexpr (S > 1) {
         __shared__ double red[PG][S - 1][3][64 * P];
         __shared__ int redbad[PG][S - 1][64 * P];
+        __shared__ int redmask[PG][S - 1][PAIRS ? 64 * P : 1];
         if (slice > 0) {
 #pragma unroll
           for (int j = 0; j < P; ++j) {
@@ -189,6 +230,7 @@ __global__ void __launch_bounds__(256)
             red[pg][slice - 1][1][j * 64 + lane] = D[j];
             red[pg][slice - 1][2][j * 64 + lane] = A[j];
             redbad[pg][slice - 1][j * 64 + lane] = bad[j];
+            if constexpr (PAIRS) redmask[pg][slice - 1][j * 64 + lane] = rlast[j];
           }
         }
         __syncthreads();
@@ -201,11 +243,25 @@ __global__ void __launch_bounds__(256)
               D[j] += red[pg][h][1][j * 64 + lane];
               A[j] += red[pg][h][2][j * 64 + lane];
               bad[j] |= redbad[pg][h][j * 64 + lane] != 0;
+              if constexpr (PAIRS) {
+                const int32_t rl = redmask[pg][h][j * 64 + lane];
+                rlast[j] = rl > rlast[j] ? rl : rlast[j];
+              }
             }
           }
         }
         __syncthreads();  // the partial sums are read: the next pass may write
         if (slice > 0) continue;
+      }
+      if constexpr (PAIRS) {
+        if (pairs) {
+#pragma unroll
+          for (int j = 0; j < P; ++j) {
+            if (!bad[j] && rlast[j] >= 0)
+              pair_fix_point<G, R, L>(xp[j], rlast[j], ix, iw, iwf, N[j], D[j], A[j]);
+            bad[j] |= !(fabs(D[j]) <= 0x1.fffffffffffffp+1023);
+          }
+        }
       }
 #pragma unroll
       for (int j = 0; j < P; ++j) {
@@ -218,7 +274,8 @@ __global__ void __launch_bounds__(256)
           lv = e.l;
         } else {
           double a = A[j];
-          if constexpr (L && U > 0) a = lebesgue_block_fix<G, U>(xp[j], ix, iw, ds.n, a);
+          if constexpr (L && U > 0)
+            if (!pairs) a = lebesgue_block_fix<G, U>(xp[j], ix, iw, ds.n, a);
           rv = N[j] / D[j];
           lv = a / fabs(D[j]);
         }
@@ -327,39 +384,45 @@ __global__ void __launch_bounds__(kStage)
 }
 
 // Variant tables.  Binary64: id -> (points per lane P, group G, node split
-// S, Lebesgue block U, passes per strip Q).  Split: id -> (P, Q), with node
-// quads inverted together (G = 4) and sums by 32-node tiles.
+// S, Lebesgue block U, passes per strip Q, node pairs).  Split: id -> (P, Q),
+// with node quads inverted together (G = 4) and sums by 32-node tiles.
 #define FH_BATCH_F64_VARIANTS(X)                                                               \
-  X(0, 1, 8, 1, 0, 1) X(1, 2, 8, 1, 0, 1) X(2, 4, 8, 1, 0, 1) X(3, 1, 8, 2, 0, 1)             \
-  X(4, 2, 8, 2, 0, 1) X(5, 4, 8, 2, 0, 1) X(6, 1, 8, 1, 16, 1) X(7, 2, 8, 1, 16, 1)           \
-  X(8, 4, 8, 1, 16, 1) X(9, 1, 8, 2, 16, 1) X(10, 2, 8, 2, 16, 1) X(11, 4, 8, 2, 16, 1)       \
-  X(12, 1, 8, 1, 0, 4) X(13, 2, 8, 1, 0, 4) X(14, 4, 8, 1, 0, 4) X(15, 2, 8, 2, 0, 4)         \
-  X(16, 2, 8, 1, 16, 4) X(17, 4, 8, 1, 16, 4)
+  X(0, 1, 8, 1, 0, 1, 0) X(1, 2, 8, 1, 0, 1, 0) X(2, 4, 8, 1, 0, 1, 0)                        \
+  X(3, 1, 8, 2, 0, 1, 0) X(4, 2, 8, 2, 0, 1, 0) X(5, 4, 8, 2, 0, 1, 0)                        \
+  X(6, 1, 8, 1, 16, 1, 0) X(7, 2, 8, 1, 16, 1, 0) X(8, 4, 8, 1, 16, 1, 0)                     \
+  X(9, 1, 8, 2, 16, 1, 0) X(10, 2, 8, 2, 16, 1, 0) X(11, 4, 8, 2, 16, 1, 0)                   \
+  X(12, 1, 8, 1, 0, 4, 0) X(13, 2, 8, 1, 0, 4, 0) X(14, 4, 8, 1, 0, 4, 0)                     \
+  X(15, 2, 8, 2, 0, 4, 0) X(16, 2, 8, 1, 16, 4, 0) X(17, 4, 8, 1, 16, 4, 0)                   \
+  X(18, 2, 8, 1, 16, 1, 1) X(19, 4, 8, 1, 16, 1, 1) X(20, 2, 8, 2, 16, 1, 1)                  \
+  X(21, 4, 8, 2, 16, 1, 1) X(22, 2, 8, 1, 16, 4, 1) X(23, 4, 8, 1, 16, 4, 1)
 #define FH_BATCH_SPLIT_VARIANTS(X) \
   X(0, 1, 1) X(1, 2, 1) X(2, 4, 1) X(3, 8, 1) X(4, 1, 4) X(5, 2, 4) X(6, 4, 4) X(7, 8, 4)
 
 struct BatchShape {
   int p, g, s, u, q;
+  bool pairs;
 };
 
 BatchShape batch_shape(int id, bool split) {
   if (split) {
     switch (id) {
 #define FH_SHAPE(vid, vp, vq) \
-  case vid: return {vp, 4, 1, kTile, vq};
+  case vid: return {vp, 4, 1, kTile, vq, false};
       FH_BATCH_SPLIT_VARIANTS(FH_SHAPE)
 #undef FH_SHAPE
-      default: return {0, 0, 0, 0, 0};
+      default: return {0, 0, 0, 0, 0, false};
     }
   }
   switch (id) {
-#define FH_SHAPE(vid, vp, vg, vs, vu, vq) \
-  case vid: return {vp, vg, vs, vu, vq};
+#define FH_SHAPE(vid, vp, vg, vs, vu, vq, vpairs) \
+  case vid: return {vp, vg, vs, vu, vq, vpairs != 0};
     FH_BATCH_F64_VARIANTS(FH_SHAPE)
 #undef FH_SHAPE
-    default: return {0, 0, 0, 0, 0};
+    default: return {0, 0, 0, 0, 0, false};
   }
 }
+
+bool batched_variant_pairs(int id, bool split) { return batch_shape(id, split).pairs; }
 
 int batched_variant_count(bool split) {
 #define FH_COUNT(...) +1
@@ -395,6 +458,7 @@ struct fh_batch {
   int2* items = nullptr;
   uint32_t* ctrl = nullptr;  // [0] item counter, [1] sticky status bits
   double *tx = nullptr, *tw = nullptr, *twf = nullptr, *tf = nullptr;
+  double* tpr = nullptr;  // node-pair records (binary64 pair variants)
   float4* s4 = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -404,21 +468,22 @@ namespace {
 
 using F64Kernel = void (*)(const InstDesc*, const int2*, int, int32_t, uint32_t*, const double*,
                            double*, double*, const double*, const double*, const double*,
-                           const double*);
+                           const double*, const double*);
 using SplitKernel = void (*)(const InstDesc*, const int2*, int, int32_t, uint32_t*,
                              const double*, double*, double*, const float4*, const double*,
                              const double*, const double*, const double*);
 
-template <int P, int G, int S, int U>
+template <int P, int G, int S, int U, bool PAIRS>
 F64Kernel f64_kernel(bool r, bool l) {
-  return r && l ? k_batch_f64<P, G, S, true, true, U>
-                : (r ? k_batch_f64<P, G, S, true, false, U> : k_batch_f64<P, G, S, false, true, U>);
+  return r && l ? k_batch_f64<P, G, S, true, true, U, PAIRS>
+                : (r ? k_batch_f64<P, G, S, true, false, U, PAIRS>
+                     : k_batch_f64<P, G, S, false, true, U, PAIRS>);
 }
 
 F64Kernel pick_f64(int id, bool r, bool l) {
   switch (id) {
-#define FH_CASE(vid, vp, vg, vs, vu, vq) \
-  case vid: return f64_kernel<vp, vg, vs, vu>(r, l);
+#define FH_CASE(vid, vp, vg, vs, vu, vq, vpairs) \
+  case vid: return f64_kernel<vp, vg, vs, vu, vpairs != 0>(r, l);
     FH_BATCH_F64_VARIANTS(FH_CASE)
 #undef FH_CASE
     default: return nullptr;
@@ -518,6 +583,8 @@ fh_status fh_batch_create(fh_batch** out, int32_t count, const int64_t* n_host,
     ds.strips = (int32_t)((ds.m + strip_pts - 1) / strip_pts);
     ds.shift = 0;
     ds.wide = 0;
+    ds.pairs_bad = 1;  // until k_batch_pack_pairs has looked
+    ds.reserved = 0;
     toff[i] = total_pad;
     noff += ds.n;
     poff += ds.m;
@@ -557,6 +624,8 @@ fh_status fh_batch_create(fh_batch** out, int32_t count, const int64_t* n_host,
   const size_t o_twf = take(sizeof(double) * total_pad);
   const size_t o_tf = take(sizeof(double) * total_pad);
   const size_t o_s4 = prec == FH_FP32_SPLIT ? take(sizeof(float4) * total_pad) : 0;
+  const size_t o_pr =
+      shape.pairs ? take(sizeof(double) * kPairRec * (size_t)(total_pad / kPairBlock)) : 0;
   if (hipGetDevice(&b->device) != hipSuccess || hipMalloc(&b->mem, off) != hipSuccess) {
     b->mem = nullptr;
     free_batch(b);
@@ -572,6 +641,7 @@ fh_status fh_batch_create(fh_batch** out, int32_t count, const int64_t* n_host,
   b->twf = reinterpret_cast<double*>(base + o_twf);
   b->tf = reinterpret_cast<double*>(base + o_tf);
   b->s4 = prec == FH_FP32_SPLIT ? reinterpret_cast<float4*>(base + o_s4) : nullptr;
+  b->tpr = shape.pairs ? reinterpret_cast<double*>(base + o_pr) : nullptr;
 
   hipStream_t user = static_cast<hipStream_t>(stream);
   hipStream_t cs = nullptr;
@@ -616,6 +686,8 @@ fh_status fh_batch_create(fh_batch** out, int32_t count, const int64_t* n_host,
         b->ctrl + 1);
     if (prec == FH_FP32_SPLIT)
       k_batch_pack_split<<<(unsigned)count, 256, 0, cs>>>(b->inst, b->tx, b->tw, b->twf, b->s4);
+    if (shape.pairs)
+      k_batch_pack_pairs<<<(unsigned)count, 256, 0, cs>>>(b->inst, b->tx, b->tw, b->twf, b->tpr);
     if (items > 0) {
       const int n_it = (int)b->n_items;
       if (split)
@@ -623,7 +695,7 @@ fh_status fh_batch_create(fh_batch** out, int32_t count, const int64_t* n_host,
                                    lambda_cat, b->s4, b->tx, b->tw, b->twf, b->tf);
       else
         kf<<<grid, block, 0, cs>>>(b->inst, b->items, n_it, b->passes, b->ctrl, x_cat, r_cat,
-                                   lambda_cat, b->tx, b->tw, b->twf, b->tf);
+                                   lambda_cat, b->tx, b->tw, b->twf, b->tf, b->tpr);
       e = hipGetLastError();
     }
     hipError_t e2 = hipStreamEndCapture(cs, &b->graph);

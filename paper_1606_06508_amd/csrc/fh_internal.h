@@ -65,6 +65,7 @@ int split_variant_block(int id);  // node tile of the block sums, 0 for plain su
 int batched_variant_count(bool split);
 void batched_variant_shape(int id, int* p, int* g, int* s, bool split);
 int batched_variant_block(int id, bool split);      // Lebesgue block / node tile, 0 for plain
+bool batched_variant_pairs(int id, bool split);     // binary64 sums by node pairs
 int64_t batched_variant_strip(int id, bool split);  // points of one work item
 // Variants of one family with the same bit class give the same bits for the
 // same point and table (they differ only in points per lane or strip length).

@@ -70,7 +70,7 @@ constexpr Builtin kBuiltin[] = {
     {FH_FP32_SPLIT, 6, 14, 4},  {FH_FP32_SPLIT, 10, 20, 9}, {FH_FP32_SPLIT, 12, 20, 9},
     {FH_FP32_SPLIT, 13, 20, 9}, {FH_FP32_SPLIT, 13, 24, 9},
     // the 4096-instance batch (mean n 1041, 2.04e8 points)
-    {FH_TUNE_BATCHED_FP64, 11, 28, 2}, {FH_TUNE_BATCHED_SPLIT, 11, 28, 5},
+    {FH_TUNE_BATCHED_FP64, 11, 28, 23}, {FH_TUNE_BATCHED_SPLIT, 11, 28, 5},
 };
 
 // Untuned shapes: two points per lane with the node range split over the
@@ -273,7 +273,8 @@ int32_t fh_variant_lebesgue_block(int32_t prec, int32_t id) {
 
 int32_t fh_variant_node_pairs(int32_t prec, int32_t id) {
   if (!valid_family(prec) || id < 0 || id >= variant_count(prec)) return -1;
-  return prec == FH_FP64 && f64_variant_pairs(id) ? 1 : 0;
+  if (prec == FH_FP64) return f64_variant_pairs(id) ? 1 : 0;
+  return batched_variant_pairs(id, prec == FH_TUNE_BATCHED_SPLIT) ? 1 : 0;
 }
 
 int64_t fh_variant_strip_points(int32_t prec, int32_t id) {

@@ -33,94 +33,27 @@ __global__ void __launch_bounds__(256) k_weights(const double* __restrict__ x, i
 
 __global__ void k_set_word(uint32_t* p, uint32_t v) { *p = v; }
 
-// Node-pair records of the binary64 pair variants (layout and use in
-// pair_math.h).  Block b holds records 16b .. 16b+15 (records at or
-// beyond n repeat x_{n-1} with zero weight).  With the block's anchor
-// c = (x_first + x_last) / 2 and, for each pair (a, a+2) of its even or odd
-// records, a' = x_a - c, b' = x_{a+2} - c, m = (a' + b') / 2,
-// hh = (b' - a') / 2,
-//   B = w_a + w_{a+2},  J = (w_{a+2} - w_a) hh,
-//   C = v_a + v_{a+2},  K = (v_{a+2} - v_a) hh      (v = w f as stored),
-// the pair's two terms are, with x'' = (x - c) - m,
-//   w_a / (x - x_a) + w_{a+2} / (x - x_{a+2}) = (B x'' + J) / (x''^2 - hh^2)
-// and likewise (C x'' + K) / (x''^2 - hh^2) for v.  The header {c, ok, lo,
-// hi} holds lo, hi = the nodes just before and after the block (-inf, +inf
-// at the ends) and
-// ok = 1 when every entry is finite and at most 2^480 in magnitude (so the
-// products with x'' stay finite wherever x''^2 does) and the block is narrow
-// next to the node spacings s_l, s_r just outside it: pair spans 2 hh at
-// most kPairSpanMax and |a'|, |b'| at most kPairExtentMax times min(s_l, s_r).
-// A point outside the block and beyond those spacings is then at least
-// min(s_l, s_r) from every node of the block, which bounds the first-order
-// error of the pair terms there (pair_math.h).  A table with a block that
-// fails the test is summed node by node (the pair variants check the
-// summary words pok first).  One thread per pair (threads 0..7 of each
-// group of 16) and one per header (thread 8, which returns whether the block
-// passed or holds no node); w and v of the CUDA block's 256 records come
-// from LDS (sw, swf).
-constexpr double kPairSpanMax = 8.0, kPairExtentMax = 16.0;
-
-__device__ __forceinline__ void pair_entries(const double* __restrict__ x, int64_t n, int64_t k0,
-                                             double c, int a, const double* sw,
-                                             const double* swf, double (&o)[6], double* ext,
-                                             double* span) {
-#pragma clang fp contract(off)
-  const int64_t ka = k0 + a, kb = k0 + a + 2;
-  const double ap = x[ka < n ? ka : n - 1] - c, bp = x[kb < n ? kb : n - 1] - c;
-  const double m = 0.5 * (ap + bp), hh = 0.5 * (bp - ap);
-  const double wa = sw[a], wb = sw[a + 2], va = swf[a], vb = swf[a + 2];
-  o[0] = m;
-  o[1] = -(hh * hh);
-  o[2] = wa + wb;
-  o[3] = (wb - wa) * hh;
-  o[4] = va + vb;
-  o[5] = (vb - va) * hh;
-  *ext = fmax(fabs(ap), fabs(bp));
-  *span = bp - ap;
-}
-
+// Node-pair records of the binary64 pair variants (layout, construction
+// and use in pair_math.h).  A table with a block that fails the pack's test
+// is summed node by node (the pair variants check the summary words pok
+// first).  One thread per pair (threads 0..7 of each group of 16) and one
+// per header (thread 8, which returns whether the block passed or holds no
+// node); w and v of the CUDA block's 256 records come from LDS (sw, swf).
 __device__ bool pack_pair_records(const double* __restrict__ x, int64_t n, int64_t n_pad,
                                   int64_t base, const double* sw, const double* swf,
                                   double* __restrict__ pr) {
-#pragma clang fp contract(off)
   const int tid = threadIdx.x, lb = tid >> 4, t16 = tid & 15;
   const int64_t b = (base >> 4) + lb, k0 = b * kPairBlock;
   if (t16 > 8) return false;
   if (k0 >= n_pad) return t16 == 8;
-  const double c = 0.5 * (x[k0 < n ? k0 : n - 1] + x[k0 + 15 < n ? k0 + 15 : n - 1]);
   double* __restrict__ rec = pr + b * kPairRec;
   const double* bw = sw + lb * 16;
   const double* bv = swf + lb * 16;
   if (t16 < 8) {
-    const int g = t16 >> 2, i = t16 & 3;
-    double o[6], ext, span;
-    pair_entries(x, n, k0, c, 4 * i + g, bw, bv, o, &ext, &span);
-#pragma unroll
-    for (int f = 0; f < 6; ++f) rec[kPairHead + 24 * g + 4 * f + i] = o[f];
+    pair_record_pair(x, n, k0, bw, bv, t16, rec);
     return false;
   }
-  bool ok = k0 < n && fabs(c) <= 0x1p480;
-  double ext_max = 0.0, span_max = 0.0;
-  for (int t = 0; t < 8; ++t) {
-    double o[6], ext, span;
-    pair_entries(x, n, k0, c, 4 * (t & 3) + (t >> 2), bw, bv, o, &ext, &span);
-    for (int f = 0; f < 6; ++f) ok = ok && fabs(o[f]) <= 0x1p480;
-    ext_max = fmax(ext_max, ext);
-    span_max = fmax(span_max, span);
-  }
-  const double inf = __builtin_inf();
-  const double sl = k0 >= 1 && k0 < n ? x[k0] - x[k0 - 1] : inf;
-  const double sr = k0 + 16 < n ? x[k0 + 16] - x[k0 + 15] : inf;
-  const double so = fmin(sl, sr);
-  ok = ok && so > 0.0 && so < inf && span_max <= kPairSpanMax * so &&
-       ext_max <= kPairExtentMax * so;
-  rec[0] = c;
-  rec[1] = ok ? 1.0 : 0.0;
-  // the nodes just outside the block (lo < x <= hi: the block holds a node
-  // next to x)
-  rec[2] = k0 >= 1 && k0 <= n ? x[k0 - 1] : -inf;
-  rec[3] = k0 + 16 < n ? x[k0 + 16] : inf;
-  return ok || k0 >= n;
+  return pair_record_header(x, n, k0, bw, bv, rec);
 }
 
 // The pair records of the CUDA block's 16 node blocks and their summary

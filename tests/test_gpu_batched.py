@@ -126,7 +126,8 @@ def test_edge_instances():
 
 def _bit_class(family, vid):
     shape = {v[0]: v[1:] for v in fh.variants(family)}[vid]
-    return shape[1], shape[2], fh.variant_lebesgue_block(family, vid)
+    return (shape[1], shape[2], fh.variant_lebesgue_block(family, vid),
+            fh.variant_node_pairs(family, vid))
 
 
 @pytest.mark.parametrize("precision", ["fp64", "split"])
@@ -340,3 +341,55 @@ def test_split_batch_ill_conditioned_instances(lebesgue):
     finally:
         fh.tune_force("fp64", -1)
     b.close()
+
+
+def test_pair_variants_fall_back_per_instance():
+    """Binary64 pair variants: an instance with a block too wide next to the
+    node spacings around it (one block stretched 20 times) is summed by the
+    node-block code inside the same launch, with the bits of the node-block
+    variant of the same shape; the other instances take the pair sums.
+    Every instance within the oracle's bar."""
+    g = np.random.default_rng(31)
+    h = np.ones(199)
+    h[48:63] = 20.0
+    wide = -1.0 + 2.0 * np.concatenate([[0.0], np.cumsum(h)]) / (1.0 + h.sum())
+    specs = [(wide, 3), (inputs.equispaced(300), 4), (inputs.cheb2(129), 2), (wide, 5)]
+    n = np.array([x.size for x, _ in specs])
+    d = np.array([dd for _, dd in specs], dtype=np.int32)
+    m = np.array([1500, 1200, 900, 700])
+    pts = [np.concatenate([x[::5], g.uniform(-1, 1, int(mi) - x[::5].size)])
+           for (x, _), mi in zip(specs, m)]
+    c = {"n": n, "d": d, "m": m, "nodes": np.concatenate([x for x, _ in specs]),
+         "values": np.concatenate([np.cos(3 * x) for x, _ in specs]),
+         "points": np.concatenate(pts)}
+    c["node_off"] = np.concatenate([[0], np.cumsum(n)])
+    c["pt_off"] = np.concatenate([[0], np.cumsum(m)])
+    shapes = {v[0]: v[1:] for v in fh.variants("batched_fp64")}
+    strips = {v: fh.variant_strip_points("batched_fp64", v) for v in shapes}
+    pair_ids = [v for v in shapes if fh.variant_node_pairs("batched_fp64", v)]
+    assert pair_ids
+    for vid in pair_ids:
+        twin = next(t for t in shapes if shapes[t] == shapes[vid] and strips[t] == strips[vid]
+                    and fh.variant_lebesgue_block("batched_fp64", t) == 16
+                    and not fh.variant_node_pairs("batched_fp64", t))
+        outs = {}
+        for v in (vid, twin):
+            fh.tune_force("batched_fp64", v)
+            try:
+                b, (r, lam) = _batch(c)
+            finally:
+                fh.tune_force("batched_fp64", -1)
+            outs[v] = (r.cpu().numpy(), lam.cpu().numpy())
+            b.close()
+        r, lam = outs[vid]
+        for i in range(n.size):
+            ns, ps = _slices(c, i)
+            r_o, lam_o, s_o = oracle.evaluate(c["nodes"][ns], c["values"][ns], int(d[i]),
+                                              c["points"][ps])
+            metrics.check_fp64(metrics.parity(r[ps], lam[ps], r_o, lam_o, s_o), lam_metric="cond")
+            if specs[i][0] is wide:
+                for a, b_ in ((r[ps], outs[twin][0][ps]), (lam[ps], outs[twin][1][ps])):
+                    assert np.array_equal(a.view(np.uint64), b_.view(np.uint64)), (vid, twin, i)
+        # the passing instances do take the pair sums
+        ps = _slices(c, 1)[1]
+        assert not np.array_equal(r[ps], outs[twin][0][ps]), vid
