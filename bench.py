@@ -38,6 +38,7 @@ import argparse
 import ctypes
 import hashlib
 import json
+import re
 import os
 import sys
 import time
@@ -64,11 +65,19 @@ def _t(a, dev):
     return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
 
 
+def _code_only(text):
+    """C/C++ source without comments and blank space, so that a record of a
+    kernel's counters survives edits of its comments."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def _src_hash(paths):
     h = hashlib.sha256()
     for path in paths:
-        with open(path, "rb") as fh_:
-            h.update(fh_.read())
+        with open(path, encoding="utf-8") as fh_:
+            h.update(_code_only(fh_.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -430,7 +430,7 @@ __device__ __forceinline__ bool pair_record_header(const double* __restrict__ x,
 //
 // Two records (a, a+2) of a block contribute, to D (B, J) or N (C, K),
 //   w_a / (x - x_a) + w_{a+2} / (x - x_{a+2}) = (B x'' + J) / (x''^2 - hh^2),
-// x'' = (x - c) - m (record layout and coefficients: pack_pair_records).
+// x'' = (x - c) - m (record layout and coefficients above).
 // Per pair that is one subtraction, three multiply-adds, one reciprocal of
 // a simultaneous inversion of four denominators and one multiply-add per
 // sum: 9 issue slots for two (point, node) pairs with both sums against 12
@@ -450,7 +450,7 @@ __device__ __forceinline__ bool pair_record_header(const double* __restrict__ x,
 // Closer to the block, the terms have no such bound, so the blocks of the
 // point's two neighbouring nodes x_{j-1} < x <= x_j (one block, or two when
 // the point lies between blocks) are masked out of the loop and summed node
-// by node afterwards (pair_fix_points): every other block is then at least
+// by node afterwards (pair_fix_point): every other block is then at least
 // one outer spacing away from the point.  Block b holds node j-1 or j
 // exactly when lo_b < x <= hi_b, lo_b and hi_b the nodes just before and
 // after it: two compares with scalar operands per block and point, no
