@@ -129,7 +129,7 @@ def test_pairs_change_the_bits_of_a_passing_table():
     pts = g.uniform(-1, 1, 20000)
     r1, _ = _run(nodes, vals, 4, pts, 22)
     r2, _ = _run(nodes, vals, 4, pts, 18)
-    assert not torch.equal(r1, r2)
+    assert not torch.isnan(r1).any() and not torch.equal(r1, r2)
 
 
 def test_lebesgue_only_and_r_only_bits():
@@ -150,3 +150,65 @@ def test_lebesgue_only_and_r_only_bits():
             assert np.array_equal(np.isnan(a), np.isnan(b)), vid
             assert np.array_equal(a[~np.isnan(a)].view(np.uint64),
                                   b[~np.isnan(b)].view(np.uint64)), vid
+
+
+def _stretched(n, factor, block=3):
+    """Unit node spacing except inside one block, whose internal spacing is
+    `factor` times larger: its half-extent is about 7.5 * factor outer
+    spacings (the pack's limit is 16), its pair spans 2 * factor."""
+    h = np.ones(n - 1)
+    h[16 * block:16 * block + 15] = factor
+    x = np.concatenate([[0.0], np.cumsum(h)])
+    return -1.0 + 2.0 * x / x[-1]
+
+
+@pytest.mark.parametrize("factor,passes", [(2.1, True), (2.2, False)])
+def test_block_at_the_width_limit(factor, passes):
+    """A block just inside (half-extent 15.75 outer spacings) and just
+    outside (16.5) the pack's limit: inside, the pair sums are used and the
+    points nearest to the block that it does not mask (one outer spacing
+    away, and one ulp closer) meet the pair variants' bound; outside, the
+    table takes the node-block sums (the bits of the node-block twin)."""
+    g = np.random.default_rng(12)
+    n, d = 160, 4
+    nodes = _stretched(n, factor)
+    vals = np.sin(4 * nodes) + 0.05 * g.standard_normal(n)
+    b0, b1 = 48, 63  # the stretched block's first and last node
+    near = []
+    for k in (b0 - 1, b1 + 1):  # the nodes just outside it
+        for t in (1e-9, 1e-3, 0.25, 0.5, 0.75, 1 - 1e-3):
+            near += [nodes[k - 1] + t * (nodes[k] - nodes[k - 1]),
+                     nodes[k] + t * (nodes[k + 1] - nodes[k])]
+    near = np.array(near)
+    pts = np.concatenate([near, np.nextafter(near, np.inf), np.nextafter(near, -np.inf),
+                          _edge_points(nodes), g.uniform(-1, 1, 3000)])
+    r_o, lam_o, s_o = oracle.evaluate(nodes, vals, d, pts)
+    r22, lam22 = _run(nodes, vals, d, pts, 22)
+    r18, lam18 = _run(nodes, vals, d, pts, 18)
+    st = metrics.parity(r22.cpu().numpy(), lam22.cpu().numpy(), r_o, lam_o, s_o)
+    bound = (n + 33 + 85) * U64
+    assert st["e_cond_max"] <= bound and st["e_cond_lam_max"] <= bound, st
+    def bits(t):
+        a = t.cpu().numpy()
+        return np.where(np.isnan(a), np.nan, a).view(np.uint64)  # one NaN pattern
+    same = (np.array_equal(bits(r22), bits(r18)) and np.array_equal(bits(lam22), bits(lam18)))
+    assert same != passes
+
+
+@pytest.mark.parametrize("scale", [1e-7, 1e7, 1e-60, 1e60])
+def test_scaled_spans(scale):
+    """Node spans far from 1: the block coordinates scale with the nodes,
+    and spans whose pair denominators leave the binary64 range send the
+    points to the exact branch; either way within the oracle's bar."""
+    g = np.random.default_rng(13)
+    nodes = inputs.equispaced(257) * scale
+    vals = g.standard_normal(257)
+    pts = np.concatenate([g.uniform(-1, 1, 4000) * scale, nodes[::9],
+                          np.nextafter(nodes[16::16], np.inf)])
+    r_o, lam_o, s_o = oracle.evaluate(nodes, vals, 3, pts)
+    for vid, *_ in _pair_variants():
+        r, lam = _run(nodes, vals, 3, pts, vid)
+        st = metrics.parity(r.cpu().numpy(), lam.cpu().numpy(), r_o, lam_o, s_o)
+        metrics.check_fp64(st, lam_metric="cond")
+        bound = (257 + 33 + 85) * U64
+        assert st["e_cond_max"] <= bound and st["e_cond_lam_max"] <= bound, (vid, scale, st)
