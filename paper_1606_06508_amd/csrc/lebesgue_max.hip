@@ -31,7 +31,10 @@
 // products of 8 differences, one reciprocal each), with the Lebesgue sum
 // taken by blocks of 16 nodes when the weights alternate in sign (one
 // multiply-add per pair for both sums; the block around the interval, the
-// same for every sample of the wave, takes plain sums); a flagged
+// same for every sample of the wave, takes plain sums), and those blocks
+// summed by node pairs when the table passed the pair test (pair_math.h;
+// the blocks of the interval's two nodes, again the same for every sample,
+// node by node in the loop: no masks); a flagged
 // sample (a hit
 // on a node, which the zoom produces only once the bracket is below the
 // spacing of binary64 numbers, or an extreme product) is recomputed with one
@@ -62,7 +65,8 @@ __device__ __forceinline__ bool better(double v, int i, double bv, int bi) {
 
 template <int P, int NS>
 __global__ void __launch_bounds__(256)
-    k_lebesgue_max(const double* __restrict__ tx, const double* __restrict__ tw, int64_t n_pad,
+    k_lebesgue_max(const double* __restrict__ tx, const double* __restrict__ tw,
+                   const double* __restrict__ pr, const uint32_t* __restrict__ pok, int64_t n_pad,
                    int64_t n, int32_t samples, int32_t rounds, const uint32_t* __restrict__ alt,
                    double* __restrict__ lam_out, double* __restrict__ x_out) {
   constexpr int IG = 4 / NS;  // intervals per block
@@ -88,6 +92,11 @@ __global__ void __launch_bounds__(256)
   // they share one (that block gets plain sums)
   const bool blocks = __builtin_amdgcn_readfirstlane(*alt) != 0;
   const int64_t plain_block = (k + 1) % kLmU != 0 ? k - k % kLmU : -1;
+  // node pairs: the blocks of x_k and x_{k+1} are the ones next to every
+  // sample (the loop runs over the padded table, whose blocks beyond the
+  // nodes pass the test)
+  const bool pairs = blocks && pair_table_ok(pok, n_pad);
+  const int32_t near_lo = (int32_t)(k / kPairBlock), near_hi = (int32_t)((k + 1) / kPairBlock);
 
   double lo = tx[k], hi = tx[k + 1];
   double best = -INFINITY, best_x = NAN;
@@ -104,7 +113,10 @@ __global__ void __launch_bounds__(256)
       A[j] = 0.0;
       bad[j] = false;
     }
-    if (blocks)
+    if (pairs)
+      accumulate_f64_pairs_known<P, kLmG, false, true>(xp, pr, tx, tw, tw, k_begin, k_end,
+                                                       near_lo, near_hi, N, D, A, bad);
+    else if (blocks)
       accumulate_f64_blocks<P, kLmG, kLmU, false, true, true>(xp, tx, tw, nullptr, k_begin, k_end,
                                                                N, D, A, bad, plain_block);
     else
@@ -248,8 +260,8 @@ hipError_t launch_lm(const NodeTable& t, int64_t n, int32_t samples, int32_t rou
                      const uint32_t* alt, double* lam, double* xk, hipStream_t s) {
   constexpr int IG = 4 / NS;
   const int64_t blocks = (n - 1 + IG - 1) / IG;
-  k_lebesgue_max<P, NS><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(t.x, t.w, t.n_pad, n, samples,
-                                                                     rounds, alt, lam, xk);
+  k_lebesgue_max<P, NS><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(
+      t.x, t.w, t.pr, t.pok, t.n_pad, n, samples, rounds, alt, lam, xk);
   return hipGetLastError();
 }
 
