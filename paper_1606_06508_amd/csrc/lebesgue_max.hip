@@ -58,6 +58,72 @@ __device__ __forceinline__ double sample_at(double lo, double h, int i) {
   return lo + step;
 }
 
+// accumulate_f64_pairs for points that share their neighbouring nodes: all
+// of the wave's points lie between the same two nodes, so the blocks that
+// hold them, [near_lo, near_hi] (wave-uniform), are the same for every
+// lane and are summed node by node right in the loop (groups of G,
+// records through scalar loads, the Lebesgue sum from |w_k| |t_k|); every
+// other block takes the pair sums with no mask.  Lane flags as in
+// accumulate_f64.
+template <int P, int G, bool R, bool L>
+__device__ __forceinline__ void accumulate_f64_pairs_known(
+    const double (&xp)[P], const double* __restrict__ pr, const double* __restrict__ tx,
+    const double* __restrict__ tw, const double* __restrict__ twf, int64_t k_begin,
+    int64_t k_end, int32_t near_lo, int32_t near_hi, double (&N)[P], double (&D)[P],
+    double (&A)[P], bool (&bad)[P]) {
+  static_assert((int)kPairBlock % G == 0, "blocks of whole node groups");
+  const int b0 = (int)(k_begin / kPairBlock);
+  const int nb = (int)((k_end - k_begin) / kPairBlock);
+  for (int ib = 0; ib < nb; ++ib) {
+    const int b = b0 + ib;
+    if (b >= near_lo && b <= near_hi) {
+      const double* __restrict__ px = tx + (int64_t)b * kPairBlock;
+      const double* __restrict__ pw = tw + (int64_t)b * kPairBlock;
+      const double* __restrict__ pv = twf + (int64_t)b * kPairBlock;
+#pragma unroll 1
+      for (int h = 0; h < (int)kPairBlock; h += G) {
+        double xk[G], wk[G], vk[G];
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+          xk[i] = px[h + i];
+          wk[i] = pw[h + i];
+          vk[i] = R ? pv[h + i] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+          double dl[G], t[G];
+#pragma unroll
+          for (int i = 0; i < G; ++i) dl[i] = xp[j] - xk[i];
+          group_product_reciprocals<G>(dl, t);
+#pragma unroll
+          for (int i = 0; i < G; ++i) {
+            if (R) N[j] = __builtin_fma(vk[i], t[i], N[j]);
+            D[j] = __builtin_fma(wk[i], t[i], D[j]);
+            if (L) A[j] = __builtin_fma(fabs(wk[i]), fabs(t[i]), A[j]);
+          }
+        }
+      }
+      continue;
+    }
+    const double* __restrict__ rec = pr + (int64_t)b * kPairRec;
+    double Nb[P], E[P], O[P], x1[P];
+    const double c = rec[0];
+#pragma unroll
+    for (int j = 0; j < P; ++j) x1[j] = xp[j] - c;
+    pair_group<P, R, false>(x1, rec + kPairHead, rec, Nb, E, true);
+    __builtin_amdgcn_sched_barrier(0);
+    pair_group<P, R, false>(x1, rec + kPairHead + 24, rec, Nb, O, false);
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      if (R) N[j] += Nb[j];
+      D[j] += E[j] + O[j];
+      if (L) A[j] += fabs(E[j] - O[j]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < P; ++j) bad[j] |= !(fabs(D[j]) <= 0x1.fffffffffffffp+1023);
+}
+
 // (value, index) order of the search: larger value first, then smaller index
 __device__ __forceinline__ bool better(double v, int i, double bv, int bi) {
   return v > bv || (v == bv && i < bi);
