@@ -34,6 +34,12 @@
 // finite after the node loop is flagged and recomputes its point with the
 // exact-hit branch (r = f_j bit-for-bit, Lambda = 1) or one IEEE division
 // per pair.  The loop itself holds no test and no branch.
+//
+// Node pairs (the default launch variants).  Two nodes of a 16-node block
+// give one rational term in the block's coordinates, so one reciprocal and
+// one multiply-add per sum serve two nodes (pair_math.h: the identity, its
+// error bound, the pack's test); the one or two blocks next to each point
+// are masked out of the loop and summed node by node afterwards.
 #include "fh_internal.h"
 #include "pair_math.h"
 
