@@ -54,7 +54,8 @@ struct InstDesc {
   int32_t shift;       // split: ef - e of the instance's table (written by its packing)
   int32_t wide;        // split: 1 if the instance takes binary64 terms (written by its packing)
   int32_t pairs_bad;   // binary64 pair variants: blocks of the instance that failed the
-                       // pair test (written by k_batch_pack_pairs; 0: sums by node pairs)
+                       // pair test (written by k_batch_pack_pairs; 0: the pair loop
+                       // takes no per-block test)
   int32_t reserved;
 };
 
@@ -161,10 +162,10 @@ __device__ __forceinline__ int next_item(uint32_t* counter, int* s_item) {
 // Binary64: wave (slice, pg) of the block owns the 64 * P points pg of the
 // pass and the node slice `slice` (whole node groups, or whole blocks of U
 // records); the S partial sums meet in LDS in wave order.  PAIRS (U = 16):
-// an instance whose blocks all passed the pair test is summed by node pairs
-// from its records in tpr (J and K copied to VGPRs), the blocks next to
-// each point node by node afterwards, as in k_eval_f64; the others as
-// U = 16 without pairs.
+// every instance is summed by node pairs from its records in tpr (J and K
+// copied to VGPRs), the blocks next to each point node by node afterwards,
+// as in k_eval_f64; in an instance with blocks that failed the pair test
+// (pairs_bad) the loop takes those blocks node by node.
 template <int P, int G, int S, bool R, bool L, int U, bool PAIRS>
 __global__ void __launch_bounds__(256)
     k_batch_f64(const InstDesc* __restrict__ inst, const int2* __restrict__ items, int n_items,
@@ -188,7 +189,7 @@ __global__ void __launch_bounds__(256)
     const int64_t strip = __builtin_amdgcn_readfirstlane(it.y);
     const double* px = x + ds.poff;
     const double *ix = tx + ds.toff, *iw = tw + ds.toff, *iwf = twf + ds.toff, *iff = tf + ds.toff;
-    const bool pairs = PAIRS && __builtin_amdgcn_readfirstlane(ds.pairs_bad) == 0;
+    const bool mixed = PAIRS && __builtin_amdgcn_readfirstlane(ds.pairs_bad) != 0;
     const double* ipr = PAIRS ? tpr + (ds.toff / kPairBlock) * kPairRec : tpr;
     // node slice of this wave: whole units, the last slices possibly shorter
     const int64_t units = ds.n_pad / kUnit;
@@ -211,10 +212,14 @@ __global__ void __launch_bounds__(256)
         bad[j] = false;
         rlast[j] = -1;
       }
-      if (pairs)
-        accumulate_f64_pairs<P, R, L, false>(xp, ipr, ipr, u0 * kUnit, u1 * kUnit, N, D, A, bad,
-                                             rlast);
-      else if constexpr (U > 0)
+      if constexpr (PAIRS) {
+        if (mixed)
+          accumulate_f64_pairs<P, R, L, false, true>(xp, ipr, ipr, ix, iw, iwf, u0 * kUnit,
+                                                     u1 * kUnit, N, D, A, bad, rlast);
+        else
+          accumulate_f64_pairs<P, R, L, false, false>(xp, ipr, ipr, ix, iw, iwf, u0 * kUnit,
+                                                      u1 * kUnit, N, D, A, bad, rlast);
+      } else if constexpr (U > 0)
         accumulate_f64_blocks<P, G, U, R, L>(xp, ix, iw, iwf, u0 * kUnit, u1 * kUnit, N, D, A,
                                              bad);
       else
@@ -254,13 +259,11 @@ __global__ void __launch_bounds__(256)
         if (slice > 0) continue;
       }
       if constexpr (PAIRS) {
-        if (pairs) {
 #pragma unroll
-          for (int j = 0; j < P; ++j) {
-            if (!bad[j] && rlast[j] >= 0)
-              pair_fix_point<G, R, L>(xp[j], rlast[j], ix, iw, iwf, N[j], D[j], A[j]);
-            bad[j] |= !(fabs(D[j]) <= 0x1.fffffffffffffp+1023);
-          }
+        for (int j = 0; j < P; ++j) {
+          if (!bad[j] && rlast[j] >= 0)
+            pair_fix_point<G, R, L>(xp[j], rlast[j], ix, iw, iwf, N[j], D[j], A[j]);
+          bad[j] |= !(fabs(D[j]) <= 0x1.fffffffffffffp+1023);
         }
       }
 #pragma unroll
@@ -274,8 +277,7 @@ __global__ void __launch_bounds__(256)
           lv = e.l;
         } else {
           double a = A[j];
-          if constexpr (L && U > 0)
-            if (!pairs) a = lebesgue_block_fix<G, U>(xp[j], ix, iw, ds.n, a);
+          if constexpr (L && U > 0 && !PAIRS) a = lebesgue_block_fix<G, U>(xp[j], ix, iw, ds.n, a);
           rv = N[j] / D[j];
           lv = a / fabs(D[j]);
         }

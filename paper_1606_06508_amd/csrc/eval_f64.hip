@@ -39,7 +39,9 @@
 // give one rational term in the block's coordinates, so one reciprocal and
 // one multiply-add per sum serve two nodes (pair_math.h: the identity, its
 // error bound, the pack's test); the one or two blocks next to each point
-// are masked out of the loop and summed node by node afterwards.
+// are masked out of the loop and summed node by node afterwards, and a
+// block too wide for the bound next to the node spacings around it is
+// summed node by node in the loop.
 #include "fh_internal.h"
 #include "pair_math.h"
 
@@ -48,12 +50,13 @@ namespace fhk {
 // U > 0: the sums are taken by blocks of U nodes (accumulate_f64_blocks)
 // when the table's weights alternate in sign, which *alt says (written by
 // the packing); D, hence r, is then the same with and without Lambda.
-// PAIRS (U = 16): when every block of the table passed the pack's test
-// (summary words pok), the blocks are summed by node pairs
-// (accumulate_f64_pairs) from the pair records pr and the blocks next to
-// each point node by node afterwards (pair_fix_point); otherwise as U = 16
-// without pairs.  JKL: the pair terms' J and K are staged in LDS first
-// (jk_lds, n_loop doubles; the launch passes that much dynamic LDS).
+// PAIRS (U = 16): the blocks are summed by node pairs (accumulate_f64_pairs)
+// from the pair records pr and the blocks next to each point node by node
+// afterwards (pair_fix_point); when some block of the table failed the
+// pack's test (summary words pok), the loop checks each block's flag and
+// takes the failing ones node by node.  JKL: the pair terms' J and K are
+// staged in LDS first (jk_lds, n_loop doubles; the launch passes that much
+// dynamic LDS).
 template <int P, int G, int S, bool R, bool L, int U, bool PAIRS, bool JKL>
 __device__ __forceinline__ void eval_f64_points(const double* __restrict__ x, int64_t m,
                                                 const double* __restrict__ tx,
@@ -98,20 +101,26 @@ __device__ __forceinline__ void eval_f64_points(const double* __restrict__ x, in
   const int64_t k_begin = slice * slice_len < n_loop ? slice * slice_len : n_loop;
   const int64_t k_end = k_begin + slice_len < n_loop ? k_begin + slice_len : n_loop;
 
-  bool blocks = false, pairs = false;
+  bool blocks = false;
   int32_t rlast[P];
 #pragma unroll
   for (int j = 0; j < P; ++j) rlast[j] = -1;
   if constexpr (U > 0) {
     blocks = __builtin_amdgcn_readfirstlane(*alt) != 0;
-    if constexpr (PAIRS) pairs = blocks && pair_table_ok(pok, n_loop);
-    if constexpr (JKL) {
-      // every thread of the block takes part before any wave branches
-      if (pairs) pair_stage_jk(pr, n_loop, jk_lds);
-      __syncthreads();
-    }
-    if (pairs) {
-      accumulate_f64_pairs<P, R, L, JKL>(xp, pr, jk_lds, k_begin, k_end, N, D, A, bad, rlast);
+    if constexpr (PAIRS) {
+      if constexpr (JKL) {
+        // every thread of the block takes part before any wave branches
+        if (blocks) pair_stage_jk(pr, n_loop, jk_lds);
+        __syncthreads();
+      }
+      if (blocks) {
+        if (pair_table_ok(pok, n_loop))
+          accumulate_f64_pairs<P, R, L, JKL, false>(xp, pr, jk_lds, tx, tw, twf, k_begin, k_end,
+                                                    N, D, A, bad, rlast);
+        else
+          accumulate_f64_pairs<P, R, L, JKL, true>(xp, pr, jk_lds, tx, tw, twf, k_begin, k_end,
+                                                   N, D, A, bad, rlast);
+      }
     } else if (blocks) {
       accumulate_f64_blocks<P, G, U, R, L>(xp, tx, tw, twf, k_begin, k_end, N, D, A, bad);
     }
@@ -153,7 +162,7 @@ __device__ __forceinline__ void eval_f64_points(const double* __restrict__ x, in
   }
 
   if constexpr (PAIRS) {
-    if (pairs) {
+    if (blocks) {
 #pragma unroll
       for (int j = 0; j < P; ++j) {
         // every finite point has a masked block; a NaN point is flagged
@@ -175,8 +184,8 @@ __device__ __forceinline__ void eval_f64_points(const double* __restrict__ x, in
       lv = e.l;
     } else {
       double a = A[j];
-      if constexpr (L && U > 0)
-        if (blocks && !pairs) a = lebesgue_block_fix<G, U>(xp[j], tx, tw, n, a);
+      if constexpr (L && U > 0 && !PAIRS)
+        if (blocks) a = lebesgue_block_fix<G, U>(xp[j], tx, tw, n, a);
       rv = N[j] / D[j];
       lv = a / fabs(D[j]);
     }

@@ -28,13 +28,12 @@
 // no LDS and no barrier.
 //
 // Sums use the simultaneous inversion of the evaluation kernels (group
-// products of 8 differences, one reciprocal each), with the Lebesgue sum
-// taken by blocks of 16 nodes when the weights alternate in sign (one
-// multiply-add per pair for both sums; the block around the interval, the
-// same for every sample of the wave, takes plain sums), and those blocks
-// summed by node pairs when the table passed the pair test (pair_math.h;
-// the blocks of the interval's two nodes, again the same for every sample,
-// node by node in the loop: no masks); a flagged
+// products of 8 differences, one reciprocal each).  When the weights
+// alternate in sign the blocks of 16 nodes are summed by node pairs
+// (pair_math.h), the Lebesgue sum from the block's even and odd sums; the
+// blocks of the interval's two nodes, the same for every sample of the
+// wave, and the blocks that failed the pair test are summed node by node in
+// the loop (no masks).  A flagged
 // sample (a hit
 // on a node, which the zoom produces only once the bracket is below the
 // spacing of binary64 numbers, or an extreme product) is recomputed with one
@@ -48,8 +47,7 @@ namespace fhk {
 
 namespace {
 
-constexpr int kLmG = 8;   // nodes per simultaneous inversion
-constexpr int kLmU = 16;  // node block of the Lebesgue sums
+constexpr int kLmG = 8;  // nodes per simultaneous inversion
 
 // t_i = lo + (i + 1) h, product and sum rounded separately
 __device__ __forceinline__ double sample_at(double lo, double h, int i) {
@@ -62,10 +60,11 @@ __device__ __forceinline__ double sample_at(double lo, double h, int i) {
 // of the wave's points lie between the same two nodes, so the blocks that
 // hold them, [near_lo, near_hi] (wave-uniform), are the same for every
 // lane and are summed node by node right in the loop (groups of G,
-// records through scalar loads, the Lebesgue sum from |w_k| |t_k|); every
-// other block takes the pair sums with no mask.  Lane flags as in
-// accumulate_f64.
-template <int P, int G, bool R, bool L>
+// records through scalar loads, the Lebesgue sum from |w_k| |t_k|), and so
+// are, with MIXED (some block of the table failed the pack's test), the
+// blocks whose flag says they failed it; every other block takes the pair
+// sums with no mask.  Lane flags as in accumulate_f64.
+template <int P, int G, bool R, bool L, bool MIXED>
 __device__ __forceinline__ void accumulate_f64_pairs_known(
     const double (&xp)[P], const double* __restrict__ pr, const double* __restrict__ tx,
     const double* __restrict__ tw, const double* __restrict__ twf, int64_t k_begin,
@@ -76,7 +75,8 @@ __device__ __forceinline__ void accumulate_f64_pairs_known(
   const int nb = (int)((k_end - k_begin) / kPairBlock);
   for (int ib = 0; ib < nb; ++ib) {
     const int b = b0 + ib;
-    if (b >= near_lo && b <= near_hi) {
+    const double* __restrict__ rec = pr + (int64_t)b * kPairRec;
+    if ((b >= near_lo && b <= near_hi) || (MIXED && !pair_block_passed(rec))) {
       const double* __restrict__ px = tx + (int64_t)b * kPairBlock;
       const double* __restrict__ pw = tw + (int64_t)b * kPairBlock;
       const double* __restrict__ pv = twf + (int64_t)b * kPairBlock;
@@ -105,7 +105,6 @@ __device__ __forceinline__ void accumulate_f64_pairs_known(
       }
       continue;
     }
-    const double* __restrict__ rec = pr + (int64_t)b * kPairRec;
     double Nb[P], E[P], O[P], x1[P];
     const double c = rec[0];
 #pragma unroll
@@ -152,16 +151,12 @@ __global__ void __launch_bounds__(256)
 
   const int64_t slice_len = n_pad / NS;
   const int64_t k_begin = part * slice_len, k_end = k_begin + slice_len;
-  // Lebesgue sums by node blocks when the weights alternate in sign; every
-  // sample of the wave lies in interval k, so the one block that can hold
-  // nodes on both sides of it is known: the block of x_k and x_{k+1}, if
-  // they share one (that block gets plain sums)
-  const bool blocks = __builtin_amdgcn_readfirstlane(*alt) != 0;
-  const int64_t plain_block = (k + 1) % kLmU != 0 ? k - k % kLmU : -1;
-  // node pairs: the blocks of x_k and x_{k+1} are the ones next to every
-  // sample (the loop runs over the padded table, whose blocks beyond the
-  // nodes pass the test)
-  const bool pairs = blocks && pair_table_ok(pok, n_pad);
+  // sums by node pairs when the weights alternate in sign; every sample of
+  // the wave lies in interval k, so the blocks of x_k and x_{k+1} are the
+  // ones next to every sample (the loop runs over the padded table, whose
+  // blocks beyond the nodes pass the test)
+  const bool pairs = __builtin_amdgcn_readfirstlane(*alt) != 0;
+  const bool mixed = pairs && !pair_table_ok(pok, n_pad);
   const int32_t near_lo = (int32_t)(k / kPairBlock), near_hi = (int32_t)((k + 1) / kPairBlock);
 
   double lo = tx[k], hi = tx[k + 1];
@@ -179,12 +174,12 @@ __global__ void __launch_bounds__(256)
       A[j] = 0.0;
       bad[j] = false;
     }
-    if (pairs)
-      accumulate_f64_pairs_known<P, kLmG, false, true>(xp, pr, tx, tw, tw, k_begin, k_end,
-                                                       near_lo, near_hi, N, D, A, bad);
-    else if (blocks)
-      accumulate_f64_blocks<P, kLmG, kLmU, false, true, true>(xp, tx, tw, nullptr, k_begin, k_end,
-                                                               N, D, A, bad, plain_block);
+    if (mixed)
+      accumulate_f64_pairs_known<P, kLmG, false, true, true>(xp, pr, tx, tw, tw, k_begin, k_end,
+                                                             near_lo, near_hi, N, D, A, bad);
+    else if (pairs)
+      accumulate_f64_pairs_known<P, kLmG, false, true, false>(xp, pr, tx, tw, tw, k_begin, k_end,
+                                                              near_lo, near_hi, N, D, A, bad);
     else
       accumulate_f64<P, kLmG, false, true>(xp, tx, tw, nullptr, k_begin, k_end, N, D, A, bad);
 

@@ -198,53 +198,23 @@ __device__ __forceinline__ int64_t nodes_below(double v, const double* __restric
 // costs one multiply-add for both sums (two with the plain scheme), each
 // block four additions.  Without L the block sums still form D, so r does
 // not depend on whether Lambda is requested.  The one block that holds
-// nodes on both sides of the point is wrong in A: either the caller
-// replaces its term afterwards (lebesgue_block_fix), or, when that block is
-// the same for all points of the wave (KNOWN_BLOCK: the block starting at
-// record plain_block), the loop takes plain sums on it.  Lane flags as in
-// accumulate_f64 (D not finite).
-template <int P, int G, int U, bool R, bool L, bool KNOWN_BLOCK = false>
+// nodes on both sides of the point is wrong in A: the caller replaces its
+// term afterwards (lebesgue_block_fix).  Lane flags as in accumulate_f64
+// (D not finite).
+template <int P, int G, int U, bool R, bool L>
 __device__ __forceinline__ void accumulate_f64_blocks(const double (&xp)[P],
                                                       const double* __restrict__ tx,
                                                       const double* __restrict__ tw,
                                                       const double* __restrict__ twf,
                                                       int64_t k_begin, int64_t k_end,
                                                       double (&N)[P], double (&D)[P],
-                                                      double (&A)[P], bool (&bad)[P],
-                                                      int64_t plain_block = -1) {
+                                                      double (&A)[P], bool (&bad)[P]) {
   static_assert(U % G == 0, "blocks of whole node groups");
   const double* __restrict__ px = tx + k_begin;
   const double* __restrict__ pw = tw + k_begin;
   const double* __restrict__ pv = twf + k_begin;
   const int cnt = (int)(k_end - k_begin);
   for (int k = 0; k < cnt; k += U) {
-    if (KNOWN_BLOCK && k_begin + k == plain_block) {
-      // the block around the points: plain sums, right on any block
-#pragma unroll 1
-      for (int h = 0; h < U; h += G) {
-        double xk[G], wk[G], vk[G];
-#pragma unroll
-        for (int i = 0; i < G; ++i) {
-          xk[i] = px[k + h + i];
-          wk[i] = pw[k + h + i];
-          vk[i] = R ? pv[k + h + i] : 0.0;
-        }
-#pragma unroll
-        for (int j = 0; j < P; ++j) {
-          double dl[G], t[G];
-#pragma unroll
-          for (int i = 0; i < G; ++i) dl[i] = xp[j] - xk[i];
-          group_product_reciprocals<G>(dl, t);
-#pragma unroll
-          for (int i = 0; i < G; ++i) {
-            if (R) N[j] = __builtin_fma(vk[i], t[i], N[j]);
-            D[j] = __builtin_fma(wk[i], t[i], D[j]);
-            if (L) A[j] = __builtin_fma(fabs(wk[i]), fabs(t[i]), A[j]);
-          }
-        }
-      }
-      continue;
-    }
     // E = sum of w_k t_k over the block's even records, O over its odd ones
     // (lebesgue_block_replace repeats these operations in this order)
     double E[P], O[P];
@@ -354,7 +324,9 @@ __device__ __forceinline__ double lebesgue_block_fix(double v, const double* __r
 // kPairExtentMax times min(s_l, s_r).  A point outside the block and beyond
 // those spacings is then at least min(s_l, s_r) from every node of the
 // block, which bounds the first-order error of the pair terms there (see
-// the accuracy note below).  x: the table's n nodes; bw, bv: the block's 16
+// the accuracy note below).  A block with no node below n (only padding,
+// zero weights) has ok = 1 as well.  The sums take a block with ok = 0 node
+// by node (pair_block_nodes).  x: the table's n nodes; bw, bv: the block's 16
 // weights and weighted values.  Contraction is off: the records do not
 // depend on the compiler's choice of fused operations.
 constexpr double kPairSpanMax = 8.0, kPairExtentMax = 16.0;
@@ -395,8 +367,8 @@ __device__ __forceinline__ void pair_record_pair(const double* __restrict__ x, i
   for (int f = 0; f < 6; ++f) rec[kPairHead + 24 * g + 4 * f + i] = o[f];
 }
 
-// The header of the block at k0; returns whether the block passed the test
-// or holds no node.
+// The header of the block at k0; returns its ok (the block passed the test
+// or holds no node).
 __device__ __forceinline__ bool pair_record_header(const double* __restrict__ x, int64_t n,
                                                    int64_t k0, const double* bw,
                                                    const double* bv, double* __restrict__ rec) {
@@ -415,15 +387,16 @@ __device__ __forceinline__ bool pair_record_header(const double* __restrict__ x,
   const double sl = k0 >= 1 && k0 < n ? x[k0] - x[k0 - 1] : inf;
   const double sr = k0 + 16 < n ? x[k0 + 16] - x[k0 + 15] : inf;
   const double so = fmin(sl, sr);
-  ok = ok && so > 0.0 && so < inf && span_max <= kPairSpanMax * so &&
-       ext_max <= kPairExtentMax * so;
+  ok = (ok && so > 0.0 && so < inf && span_max <= kPairSpanMax * so &&
+        ext_max <= kPairExtentMax * so) ||
+       k0 >= n;
   rec[0] = c;
   rec[1] = ok ? 1.0 : 0.0;
   // the nodes just outside the block (lo < x <= hi: the block holds a node
   // next to x)
   rec[2] = k0 >= 1 && k0 <= n ? x[k0 - 1] : -inf;
   rec[3] = k0 + 16 < n ? x[k0 + 16] : inf;
-  return ok || k0 >= n;
+  return ok;
 }
 
 // ---- Sums by node pairs ----
@@ -501,12 +474,62 @@ __device__ __forceinline__ void pair_group(const double (&x1)[P], const double* 
   }
 }
 
+// Whether the block's record passed the pack's test: the high word of its
+// flag (1.0 or 0.0), an integer the scalar unit can branch on.
+__device__ __forceinline__ bool pair_block_passed(const double* __restrict__ rec) {
+  return __double2hiint(rec[1]) != 0;
+}
+
+// The sums of a block that failed the pack's test, node by node from the
+// node table (px, pw, pv: the block's 16 records) in two groups of 8: the
+// same quantities as the pair groups give, Nb = sum v_k t_k and E, O the
+// sums of w_k t_k over the block's even and odd records.
+template <int P, bool R>
+__device__ __forceinline__ void pair_block_nodes(const double (&xp)[P],
+                                                 const double* __restrict__ px,
+                                                 const double* __restrict__ pw,
+                                                 const double* __restrict__ pv, double (&Nb)[P],
+                                                 double (&E)[P], double (&O)[P]) {
+  constexpr int G = 8;
+#pragma unroll
+  for (int j = 0; j < P; ++j) Nb[j] = E[j] = O[j] = 0.0;
+#pragma unroll 1
+  for (int h = 0; h < (int)kPairBlock; h += G) {
+    double xk[G], wk[G], vk[G];
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      xk[i] = px[h + i];
+      wk[i] = pw[h + i];
+      vk[i] = R ? pv[h + i] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      double dl[G], t[G];
+#pragma unroll
+      for (int i = 0; i < G; ++i) dl[i] = xp[j] - xk[i];
+      group_product_reciprocals<G>(dl, t);
+#pragma unroll
+      for (int i = 0; i < G; ++i) {
+        if (R) Nb[j] = __builtin_fma(vk[i], t[i], Nb[j]);
+        if (i & 1)
+          O[j] = __builtin_fma(wk[i], t[i], O[j]);
+        else
+          E[j] = __builtin_fma(wk[i], t[i], E[j]);
+      }
+    }
+  }
+}
+
 // Fused sums by node pairs over the records [k_begin, k_end) (wave-uniform,
-// multiples of kPairBlock; every block of the table passed the pack's test):
-// for each block its pair sums, then N += Nb, D += E + O, A += |E - O|,
-// each times 0 where the block holds a node next to the point
-// (lo_b < x <= hi_b); the last such block is kept in rlast (untouched if
-// none).  Lane flags as in accumulate_f64 (D not finite).
+// multiples of kPairBlock): for each block its pair sums, then N += Nb,
+// D += E + O, A += |E - O|, each times 0 where the block holds a node next
+// to the point (lo_b < x <= hi_b); the last such block is kept in rlast
+// (untouched if none).  MIXED: some block of the table failed the pack's
+// test; each block then checks its flag (wave-uniform, a scalar branch) and
+// a failing one takes its sums node by node from the node table tx, tw, twf
+// (pair_block_nodes), masked alike.  Without MIXED every block passed and
+// the loop holds no such test.  Lane flags as in accumulate_f64 (D not
+// finite).
 //
 // A VOP3 instruction reads at most one SGPR, so B x'' + J and C x'' + K
 // cannot take both coefficients from the scalar unit.  With JKL (the
@@ -514,29 +537,34 @@ __device__ __forceinline__ void pair_group(const double (&x1)[P], const double* 
 // broadcast reads, which use the LDS pipe; without it they are copied from
 // SGPRs to VGPRs, 16 moves per block shared by the lane's P points (vector
 // loads from memory instead left their latency exposed, measured slower).
-template <int P, bool R, bool L, bool JKL>
-__device__ __forceinline__ void accumulate_f64_pairs(const double (&xp)[P],
-                                                     const double* __restrict__ pr,
-                                                     const double* jk_lds, int64_t k_begin,
-                                                     int64_t k_end, double (&N)[P],
-                                                     double (&D)[P], double (&A)[P],
-                                                     bool (&bad)[P], int32_t (&rlast)[P]) {
+template <int P, bool R, bool L, bool JKL, bool MIXED>
+__device__ __forceinline__ void accumulate_f64_pairs(
+    const double (&xp)[P], const double* __restrict__ pr, const double* jk_lds,
+    const double* __restrict__ tx, const double* __restrict__ tw, const double* __restrict__ twf,
+    int64_t k_begin, int64_t k_end, double (&N)[P], double (&D)[P], double (&A)[P],
+    bool (&bad)[P], int32_t (&rlast)[P]) {
   const int b0 = (int)(k_begin / kPairBlock);
   const int nb = (int)((k_end - k_begin) / kPairBlock);
   for (int ib = 0; ib < nb; ++ib) {
     const int b = b0 + ib;
     const double* __restrict__ rec = pr + (int64_t)b * kPairRec;
     double Nb[P], E[P], O[P];
-    const double c = rec[0], lo_b = rec[2], hi_b = rec[3];
-    double x1[P];
+    const double lo_b = rec[2], hi_b = rec[3];
+    if (!MIXED || pair_block_passed(rec)) {
+      const double c = rec[0];
+      double x1[P];
 #pragma unroll
-    for (int j = 0; j < P; ++j) x1[j] = xp[j] - c;
-    const double* jk = jk_lds + b * (int)kPairBlock;
-    pair_group<P, R, JKL>(x1, rec + kPairHead, jk, Nb, E, true);
-    // the odd group's entries load into the SGPRs of the even group's
-    // (48 SGPRs each)
-    __builtin_amdgcn_sched_barrier(0);
-    pair_group<P, R, JKL>(x1, rec + kPairHead + 24, jk + 8, Nb, O, false);
+      for (int j = 0; j < P; ++j) x1[j] = xp[j] - c;
+      const double* jk = jk_lds + b * (int)kPairBlock;
+      pair_group<P, R, JKL>(x1, rec + kPairHead, jk, Nb, E, true);
+      // the odd group's entries load into the SGPRs of the even group's
+      // (48 SGPRs each)
+      __builtin_amdgcn_sched_barrier(0);
+      pair_group<P, R, JKL>(x1, rec + kPairHead + 24, jk + 8, Nb, O, false);
+    } else {
+      const int64_t k0 = (int64_t)b * kPairBlock;
+      pair_block_nodes<P, R>(xp, tx + k0, tw + k0, twf + k0, Nb, E, O);
+    }
 #pragma unroll
     for (int j = 0; j < P; ++j) {
       const bool near = xp[j] > lo_b && xp[j] <= hi_b;

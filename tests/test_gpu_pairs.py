@@ -5,13 +5,14 @@ Two records (a, a+2) of a 16-node block give one rational term
 (and C, K for the weighted values), with x'' measured from the block's
 anchor and the pair's midpoint.  The blocks holding the nodes next to a
 point (one, or two for a point between blocks) are masked out of the loop
-and summed node by node; a table whose blocks are too wide next to the node
-spacings around them (the pack's test) is summed by the node-block variant
-of the same shape instead.  Checked against the oracle at the points where
-the masking decides (every node, one ulp on either side of the nodes at the
-block edges, midpoints between blocks, just outside the end nodes, far
-away), and bit for bit against the node-block twin for a table that fails
-the test.
+and summed node by node; a block too wide next to the node spacings around
+it (the pack's test) is summed node by node inside the loop, the other
+blocks of its table still by pairs.  Checked against the oracle at the
+points where the masking decides (every node, one ulp on either side of the
+nodes at the block edges, midpoints between blocks, just outside the end
+nodes, far away), on tables whose blocks all pass and on tables with
+failing blocks (Chebyshev nodes whose last node starts a block of its own,
+strongly jittered nodes, a stretched block).
 """
 import numpy as np
 import pytest
@@ -81,7 +82,7 @@ def test_block_edges_against_oracle(kind, n, d):
         assert np.array_equal(np.isnan(r), np.isnan(r_o)), vid
 
 
-def _wide_block_nodes(n, g):
+def _wide_block_nodes(n):
     """Equispaced nodes whose fourth block is stretched 20 times: its pair
     spans are 40 times the spacing just outside it."""
     h = np.ones(n - 1)
@@ -90,33 +91,56 @@ def _wide_block_nodes(n, g):
     return -1.0 + 2.0 * x / x[-1]
 
 
-def test_table_failing_the_pack_test_takes_block_sums():
-    g = np.random.default_rng(3)
-    n, d = 200, 3
-    nodes = _wide_block_nodes(n, g)
-    vals = np.cos(2 * nodes)
+def _failing_blocks(nodes):
+    """The blocks of 16 nodes that fail the pack's test, restated on the
+    host: pair spans (x_{k+2} - x_k) at most 8 and distances from the
+    block's anchor (the midpoint of its first and last record) at most 16
+    times the smaller node spacing just outside the block; records beyond
+    the last node repeat it; a block with no spacing outside it fails."""
+    n = nodes.size
+    out = []
+    for k0 in range(0, n, 16):
+        xs = nodes[np.minimum(np.arange(k0, k0 + 16), n - 1)]
+        c = 0.5 * (xs[0] + xs[15])
+        ext = np.abs(xs - c).max()
+        span = (xs[2:] - xs[:-2]).max()
+        sl = nodes[k0] - nodes[k0 - 1] if k0 >= 1 else np.inf
+        sr = nodes[k0 + 16] - nodes[k0 + 15] if k0 + 16 < n else np.inf
+        so = min(sl, sr)
+        if not (so < np.inf and span <= 8 * so and ext <= 16 * so):
+            out.append(k0 // 16)
+    return out
+
+
+@pytest.mark.parametrize("kind,n,d", [("cheb2", 4097, 3), ("cheb2", 1025, 6),
+                                      ("jittered", 4097, 5), ("wide", 200, 3)])
+def test_tables_with_failing_blocks(kind, n, d):
+    """The failing blocks are summed node by node inside the pair loop and
+    every other block by pairs: within the pair variants' bound at the
+    block edges, hits and random points, with hits exact, and with bits
+    that differ from the node-block variant's (the passing blocks still take
+    pairs)."""
+    g = np.random.default_rng(5)
+    nodes = {"cheb2": inputs.cheb2, "wide": _wide_block_nodes}.get(
+        kind, lambda k: inputs.jittered_nodes(k, g, rel=0.3))(n)
+    failing = _failing_blocks(nodes)
+    assert failing and len(failing) < (n + 15) // 16, failing
+    vals = np.cos(2 * nodes) + 0.1 * g.standard_normal(n)
     pts = np.concatenate([_edge_points(nodes), g.uniform(-1, 1, 4000)])
     r_o, lam_o, s_o = oracle.evaluate(nodes, vals, d, pts)
-    twins = {(p, s): vid for vid, p, grp, s in fh.variants("fp64")
-             if fh.variant_lebesgue_block("fp64", vid) and not fh.variant_node_pairs("fp64", vid)}
-    checked = 0
-    for vid, p, grp, s in _pair_variants():
+    hit = np.isin(pts, nodes)
+    bound = (n + 33 + 85) * U64
+    for vid, *_ in _pair_variants():
         r, lam = _run(nodes, vals, d, pts, vid)
-        st = metrics.parity(r.cpu().numpy(), lam.cpu().numpy(), r_o, lam_o, s_o)
+        r, lam = r.cpu().numpy(), lam.cpu().numpy()
+        st = metrics.parity(r, lam, r_o, lam_o, s_o)
         metrics.check_fp64(st, lam_metric="cond")
-        # same slicing: the bits of a node-block variant (points per lane do
-        # not change them)
-        twin = next((t for (tp, ts), t in twins.items() if ts == s), None)
-        if twin is None:
-            continue
-        r2, lam2 = _run(nodes, vals, d, pts, twin)
-        for a, b in ((r, r2), (lam, lam2)):
-            a, b = a.cpu().numpy(), b.cpu().numpy()
-            assert np.array_equal(np.isnan(a), np.isnan(b)), vid
-            assert np.array_equal(a[~np.isnan(a)].view(np.uint64),
-                                  b[~np.isnan(b)].view(np.uint64)), (vid, twin)
-        checked += 1
-    assert checked >= 2
+        assert st["e_cond_max"] <= bound and st["e_cond_lam_max"] <= bound, (vid, st)
+        assert np.array_equal(r[hit], vals[np.searchsorted(nodes, pts[hit])]), vid
+        assert np.all(lam[hit] == 1.0), vid
+    r22, _ = _run(nodes, vals, d, pts, 22)
+    r18, _ = _run(nodes, vals, d, pts, 18)
+    assert not torch.equal(r22, r18)
 
 
 def test_pairs_change_the_bits_of_a_passing_table():
@@ -165,13 +189,14 @@ def _stretched(n, factor, block=3):
 @pytest.mark.parametrize("factor,passes", [(2.1, True), (2.2, False)])
 def test_block_at_the_width_limit(factor, passes):
     """A block just inside (half-extent 15.75 outer spacings) and just
-    outside (16.5) the pack's limit: inside, the pair sums are used and the
-    points nearest to the block that it does not mask (one outer spacing
-    away, and one ulp closer) meet the pair variants' bound; outside, the
-    table takes the node-block sums (the bits of the node-block twin)."""
+    outside (16.5) the pack's limit: inside, the pair sums are used on it,
+    outside, it is summed node by node; either way the points nearest to the
+    block that it does not mask (one outer spacing away, and one ulp closer)
+    meet the pair variants' bound."""
     g = np.random.default_rng(12)
     n, d = 160, 4
     nodes = _stretched(n, factor)
+    assert (_failing_blocks(nodes) == [3]) != passes
     vals = np.sin(4 * nodes) + 0.05 * g.standard_normal(n)
     b0, b1 = 48, 63  # the stretched block's first and last node
     near = []
@@ -183,16 +208,11 @@ def test_block_at_the_width_limit(factor, passes):
     pts = np.concatenate([near, np.nextafter(near, np.inf), np.nextafter(near, -np.inf),
                           _edge_points(nodes), g.uniform(-1, 1, 3000)])
     r_o, lam_o, s_o = oracle.evaluate(nodes, vals, d, pts)
-    r22, lam22 = _run(nodes, vals, d, pts, 22)
-    r18, lam18 = _run(nodes, vals, d, pts, 18)
-    st = metrics.parity(r22.cpu().numpy(), lam22.cpu().numpy(), r_o, lam_o, s_o)
     bound = (n + 33 + 85) * U64
-    assert st["e_cond_max"] <= bound and st["e_cond_lam_max"] <= bound, st
-    def bits(t):
-        a = t.cpu().numpy()
-        return np.where(np.isnan(a), np.nan, a).view(np.uint64)  # one NaN pattern
-    same = (np.array_equal(bits(r22), bits(r18)) and np.array_equal(bits(lam22), bits(lam18)))
-    assert same != passes
+    for vid, *_ in _pair_variants():
+        r, lam = _run(nodes, vals, d, pts, vid)
+        st = metrics.parity(r.cpu().numpy(), lam.cpu().numpy(), r_o, lam_o, s_o)
+        assert st["e_cond_max"] <= bound and st["e_cond_lam_max"] <= bound, (vid, st)
 
 
 @pytest.mark.parametrize("scale", [1e-7, 1e7, 1e-60, 1e60])
