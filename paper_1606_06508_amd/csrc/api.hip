@@ -85,8 +85,8 @@ size_t fh_workspace_size(int32_t op, int64_t n, int64_t m, int32_t d, int32_t pr
       return layout_backward(nullptr, n, m, prec == FH_FP32_SPLIT, &t, &b, true);
     }
     case FH_OP_LEBESGUE_MAX: {
-      double *lam, *xk;
-      return layout_lebesgue_max(nullptr, n, &t, &lam, &xk);
+      LebesgueBufs b;
+      return layout_lebesgue_max(nullptr, n, &t, &b);
     }
     default: return 0;
   }
@@ -277,12 +277,12 @@ fh_status fh_lebesgue_max(const double* nodes, int64_t n, int32_t d, const doubl
   if (st != FH_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   NodeTable t;
-  double *lam, *xk;
-  layout_lebesgue_max(ws, n, &t, &lam, &xk);
+  LebesgueBufs b;
+  layout_lebesgue_max(ws, n, &t, &b);
   hipError_t e = launch_pack(nodes, nullptr, w, n, d, t, false, static_cast<uint32_t*>(ws), s);
   if (e == hipSuccess)
-    e = launch_lebesgue_max(t, n, samples, rounds, static_cast<uint32_t*>(ws) + 3,
-                            lam_out ? lam_out : lam, x_out ? x_out : xk, best_out, s);
+    e = launch_lebesgue_max(t, n, samples, rounds, static_cast<uint32_t*>(ws) + 3, b,
+                            lam_out ? lam_out : b.lam, x_out ? x_out : b.xk, best_out, s);
   return finish(e, ws, s);
 }
 

@@ -222,15 +222,25 @@ hipError_t launch_eval_deriv(const double* x, int64_t m, const NodeTable& t, int
                              double* dr, hipStream_t s);
 hipError_t launch_eval_deriv_split(const double* x, int64_t m, const NodeTable& t, int64_t n,
                                    const int32_t* scale, double* r, double* dr, hipStream_t s);
-// Workspace layout of FH_OP_LEBESGUE_MAX: node tables, then per-interval
-// maxima and their locations ([n-1] each).  Returns bytes used.
-size_t layout_lebesgue_max(void* ws, int64_t n, NodeTable* t, double** lam, double** xk);
+// Workspace of FH_OP_LEBESGUE_MAX beyond the node tables: per-interval
+// maxima and their locations ([n-1] each), the octet records of the node
+// blocks (written by the search's own packing) and their summary word.
+struct LebesgueBufs {
+  double* lam;
+  double* xk;
+  double* oct;
+  uint32_t* oct_ok;
+};
+// Workspace layout of FH_OP_LEBESGUE_MAX: node tables, then LebesgueBufs.
+// Returns bytes used.
+size_t layout_lebesgue_max(void* ws, int64_t n, NodeTable* t, LebesgueBufs* bufs);
 // Per-interval maxima of Lambda (lam, xk: [n-1], not null) by the grid zoom
 // of `rounds` rounds of `samples` samples; best (if not null) = {the
-// constant, its location}; alt: status word 3 (weights alternate in sign).
+// constant, its location}; alt: status word 3 (weights alternate in sign);
+// bufs: octet records and summary word, written here first.
 hipError_t launch_lebesgue_max(const NodeTable& t, int64_t n, int32_t samples, int32_t rounds,
-                               const uint32_t* alt, double* lam, double* xk, double* best,
-                               hipStream_t s);
+                               const uint32_t* alt, const LebesgueBufs& bufs, double* lam,
+                               double* xk, double* best, hipStream_t s);
 hipError_t launch_eval_split(const double* x, int64_t m, const NodeTable& t, int64_t n,
                              const int32_t* scale, const uint32_t* alt, double* r, double* lam,
                              const EvalConfig& cfg, hipStream_t s);

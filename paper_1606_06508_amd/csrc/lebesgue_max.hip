@@ -33,7 +33,9 @@
 // (pair_math.h), the Lebesgue sum from the block's even and odd sums; the
 // blocks of the interval's two nodes, the same for every sample of the
 // wave, and the blocks that failed the pair test are summed node by node in
-// the loop (no masks).  A flagged
+// the loop (no masks), and the blocks far from the interval by octets (the
+// block's eight even and eight odd nodes, each as one rational function;
+// see "Octets" below).  A flagged
 // sample (a hit
 // on a node, which the zoom produces only once the bracket is below the
 // spacing of binary64 numbers, or an extreme product) is recomputed with one
@@ -56,25 +58,169 @@ __device__ __forceinline__ double sample_at(double lo, double h, int i) {
   return lo + step;
 }
 
+// ---- Octets: the blocks far from the wave's interval ----
+//
+// The even records of a 16-node block (0, 2, ..., 14), and likewise its odd
+// ones, have weights of one sign, and their eight terms add up to one
+// rational function of the octet's coordinate y = (x - c) - m (c the block's
+// anchor, m the midpoint of the octet's first and last offset a' = x_k - c,
+// r_i = a'_i - m its roots):
+//   sum_i w_i / (y - r_i) = P(y) / Q(y),   Q(y) = prod_i (y - r_i),
+//   P(y) = sum_i w_i prod_{j != i} (y - r_j),
+// Q monic of degree 8 and P of degree 7, both evaluated from their
+// monomial coefficients by Horner's rule: one subtraction and 8 + 7
+// operations for eight nodes, and one reciprocal (simultaneous inversion)
+// for the block's two octets.  Horner's rule errs by at most about k u
+// sum_k |c_k| |y|^k, and the coefficients as multiplied out carry errors of
+// the same form; relative to the sum of |w_i / (y - r_i)| both amount to
+// about (8 + 8 + 7 + 7) u times F(y) = prod_i (|y| + |r_i|) / |y - r_i|,
+// which falls as |y| grows.  The search takes a block's octets only for
+// samples with at least kOctetGap whole blocks between the block and the
+// blocks of their interval, so the closest served samples are the nodes
+// x_{16b - 16 kOctetGap - 1} and x_{16b + 16 (kOctetGap + 1)}; the pack
+// passes a block when F at those nodes is at most kOctetFactorMax for both
+// octets (equispaced nodes: F <= 2.24, Chebyshev nodes <= 5.7), its
+// coordinates and coefficients lie where every intermediate stays a normal
+// number, and the table uses octets only when every block passed.
+constexpr int kOctetGap = 2;
+constexpr double kOctetFactorMax = 8.0;
+// per block: c, then for the even and the odd octet m, Q[0..7] (Q = y^8 +
+// sum_k Q[k] y^k) and P[0..7] (P = sum_k P[k] y^k); one spare
+constexpr int64_t kOctetRec = 36;
+
+// coefficients t[0..deg] times (y - r), in place (t has room for deg + 2)
+__device__ __forceinline__ void times_root(double* t, int deg, double r) {
+  t[deg + 1] = t[deg];
+  for (int k = deg; k >= 1; --k) t[k] = __builtin_fma(-r, t[k], t[k - 1]);
+  t[0] = -r * t[0];
+}
+
+// The octet record of block b of the table (x, w: n nodes and weights;
+// records at or beyond n repeat x_{n-1} with zero weight); returns whether
+// it passed (see above).  A block with no node below n passes.
+__device__ bool octet_record(const double* __restrict__ x, const double* __restrict__ w,
+                             int64_t n, int64_t b, double* __restrict__ rec) {
+#pragma clang fp contract(off)
+  const int64_t k0 = b * kPairBlock;
+  const double c = pair_anchor(x, n, k0);
+  rec[0] = c;
+  rec[kOctetRec - 1] = 0.0;
+  bool ok = true;
+  for (int g = 0; g < 2; ++g) {
+    double a[8], wi[8], r[8];
+    for (int i = 0; i < 8; ++i) {
+      const int64_t k = k0 + g + 2 * i;
+      a[i] = x[k < n ? k : n - 1] - c;
+      wi[i] = k < n ? w[k] : 0.0;
+    }
+    const double m = 0.5 * (a[0] + a[7]);
+    double rho = 0.0;
+    for (int i = 0; i < 8; ++i) {
+      r[i] = a[i] - m;
+      rho = fmax(rho, fabs(r[i]));
+    }
+    double q[9] = {1.0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int i = 0; i < 8; ++i) times_root(q, i, r[i]);
+    double p[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int i = 0; i < 8; ++i) {
+      double t[8] = {1.0, 0, 0, 0, 0, 0, 0, 0};
+      int deg = 0;
+      for (int j = 0; j < 8; ++j)
+        if (j != i) times_root(t, deg++, r[j]);
+      for (int k = 0; k < 8; ++k) p[k] = __builtin_fma(wi[i], t[k], p[k]);
+    }
+    double* o = rec + 1 + 17 * g;
+    o[0] = m;
+    for (int k = 0; k < 8; ++k) {
+      o[1 + k] = q[k];
+      o[9 + k] = p[k];
+      ok = ok && fabs(q[k]) <= 0x1p400 && fabs(p[k]) <= 0x1p400;
+    }
+    // the samples the octet serves lie beyond the two closest ones, and
+    // within the table's end nodes
+    const int64_t side[2] = {k0 - 16 * kOctetGap - 1, k0 + 16 * (kOctetGap + 1)};
+    for (int e = 0; e < 2; ++e) {
+      if (side[e] < 0 || side[e] > n - 1) continue;
+      const double y = (x[side[e]] - c) - m;
+      double f = 1.0, near = INFINITY;
+      for (int i = 0; i < 8; ++i) {
+        const double dy = fabs(y - r[i]);
+        f *= (fabs(y) + fabs(r[i])) / dy;
+        near = fmin(near, dy);
+      }
+      ok = ok && f <= kOctetFactorMax && near >= 0x1p-50;
+    }
+    const double far = fmax(fabs((x[0] - c) - m), fabs((x[n - 1] - c) - m));
+    ok = ok && far + rho <= 0x1p50;
+  }
+  return ok || k0 >= n;
+}
+
+// One workgroup: the octet records of the blocks [0, n_pad / 16) and
+// *all_ok = 1 when every block passed.
+__global__ void __launch_bounds__(256)
+    k_pack_octets(const double* __restrict__ x, const double* __restrict__ w, int64_t n,
+                  int64_t n_pad, double* __restrict__ oct, uint32_t* __restrict__ all_ok) {
+  __shared__ int failed;
+  if (threadIdx.x == 0) failed = 0;
+  __syncthreads();
+  int mine = 0;
+  for (int64_t b = threadIdx.x; b * kPairBlock < n_pad; b += blockDim.x)
+    mine |= octet_record(x, w, n, b, oct + b * kOctetRec) ? 0 : 1;
+  if (mine) atomicOr(&failed, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) *all_ok = failed ? 0u : 1u;
+}
+
+// Q (monic, degree 8) and P (degree 7) of one octet at y
+__device__ __forceinline__ void octet_eval(const double* __restrict__ o, double y, double& Q,
+                                           double& Pv) {
+  Q = y + o[8];
+  for (int k = 7; k >= 1; --k) Q = __builtin_fma(Q, y, o[k]);
+  Pv = __builtin_fma(o[16], y, o[15]);
+  for (int k = 14; k >= 9; --k) Pv = __builtin_fma(Pv, y, o[k]);
+}
+
 // accumulate_f64_pairs for points that share their neighbouring nodes: all
 // of the wave's points lie between the same two nodes, so the blocks that
 // hold them, [near_lo, near_hi] (wave-uniform), are the same for every
 // lane and are summed node by node right in the loop (groups of G,
 // records through scalar loads, the Lebesgue sum from |w_k| |t_k|), and so
 // are, with MIXED (some block of the table failed the pack's test), the
-// blocks whose flag says they failed it; every other block takes the pair
-// sums with no mask.  Lane flags as in accumulate_f64.
+// blocks whose flag says they failed it.  With octets (wave-uniform: every
+// block passed the octet test), the blocks below far_lo or above far_hi
+// take their two octets' rational functions from oct (D and A only); every
+// other block takes the pair sums with no mask.  Lane flags as in
+// accumulate_f64.
 template <int P, int G, bool R, bool L, bool MIXED>
 __device__ __forceinline__ void accumulate_f64_pairs_known(
-    const double (&xp)[P], const double* __restrict__ pr, const double* __restrict__ tx,
-    const double* __restrict__ tw, const double* __restrict__ twf, int64_t k_begin,
-    int64_t k_end, int32_t near_lo, int32_t near_hi, double (&N)[P], double (&D)[P],
-    double (&A)[P], bool (&bad)[P]) {
+    const double (&xp)[P], const double* __restrict__ pr, const double* __restrict__ oct,
+    const double* __restrict__ tx, const double* __restrict__ tw, const double* __restrict__ twf,
+    int64_t k_begin, int64_t k_end, int32_t near_lo, int32_t near_hi, bool octets,
+    int32_t far_lo, int32_t far_hi, double (&N)[P], double (&D)[P], double (&A)[P],
+    bool (&bad)[P]) {
   static_assert((int)kPairBlock % G == 0, "blocks of whole node groups");
   const int b0 = (int)(k_begin / kPairBlock);
   const int nb = (int)((k_end - k_begin) / kPairBlock);
   for (int ib = 0; ib < nb; ++ib) {
     const int b = b0 + ib;
+    if (!R && octets && (b < far_lo || b > far_hi)) {
+      const double* __restrict__ o = oct + (int64_t)b * kOctetRec;
+      const double c = o[0];
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        const double x1 = xp[j] - c;
+        double Qe, Pe, Qo, Po;
+        octet_eval(o + 1, x1 - o[1], Qe, Pe);
+        octet_eval(o + 18, x1 - o[18], Qo, Po);
+        // one reciprocal for both octets
+        const double y = rcp_refined(Qe * Qo);
+        const double E = Pe * (y * Qo), O = Po * (y * Qe);
+        D[j] += E + O;
+        if (L) A[j] += fabs(E - O);
+      }
+      continue;
+    }
     const double* __restrict__ rec = pr + (int64_t)b * kPairRec;
     if ((b >= near_lo && b <= near_hi) || (MIXED && !pair_block_passed(rec))) {
       const double* __restrict__ px = tx + (int64_t)b * kPairBlock;
@@ -131,7 +277,8 @@ __device__ __forceinline__ bool better(double v, int i, double bv, int bi) {
 template <int P, int NS>
 __global__ void __launch_bounds__(256)
     k_lebesgue_max(const double* __restrict__ tx, const double* __restrict__ tw,
-                   const double* __restrict__ pr, const uint32_t* __restrict__ pok, int64_t n_pad,
+                   const double* __restrict__ pr, const uint32_t* __restrict__ pok,
+                   const double* __restrict__ oct, const uint32_t* __restrict__ oct_ok, int64_t n_pad,
                    int64_t n, int32_t samples, int32_t rounds, const uint32_t* __restrict__ alt,
                    double* __restrict__ lam_out, double* __restrict__ x_out) {
   constexpr int IG = 4 / NS;  // intervals per block
@@ -157,7 +304,11 @@ __global__ void __launch_bounds__(256)
   // blocks beyond the nodes pass the test)
   const bool pairs = __builtin_amdgcn_readfirstlane(*alt) != 0;
   const bool mixed = pairs && !pair_table_ok(pok, n_pad);
+  // octets for the blocks with kOctetGap whole blocks between them and the
+  // interval's blocks, when every block of the table passed the octet test
+  const bool octets = pairs && __builtin_amdgcn_readfirstlane(*oct_ok) != 0;
   const int32_t near_lo = (int32_t)(k / kPairBlock), near_hi = (int32_t)((k + 1) / kPairBlock);
+  const int32_t far_lo = near_lo - kOctetGap, far_hi = near_hi + kOctetGap;
 
   double lo = tx[k], hi = tx[k + 1];
   double best = -INFINITY, best_x = NAN;
@@ -175,11 +326,13 @@ __global__ void __launch_bounds__(256)
       bad[j] = false;
     }
     if (mixed)
-      accumulate_f64_pairs_known<P, kLmG, false, true, true>(xp, pr, tx, tw, tw, k_begin, k_end,
-                                                             near_lo, near_hi, N, D, A, bad);
+      accumulate_f64_pairs_known<P, kLmG, false, true, true>(
+          xp, pr, oct, tx, tw, tw, k_begin, k_end, near_lo, near_hi, octets, far_lo, far_hi, N, D,
+          A, bad);
     else if (pairs)
-      accumulate_f64_pairs_known<P, kLmG, false, true, false>(xp, pr, tx, tw, tw, k_begin, k_end,
-                                                              near_lo, near_hi, N, D, A, bad);
+      accumulate_f64_pairs_known<P, kLmG, false, true, false>(
+          xp, pr, oct, tx, tw, tw, k_begin, k_end, near_lo, near_hi, octets, far_lo, far_hi, N, D,
+          A, bad);
     else
       accumulate_f64<P, kLmG, false, true>(xp, tx, tw, nullptr, k_begin, k_end, N, D, A, bad);
 
@@ -318,51 +471,61 @@ __global__ void __launch_bounds__(256)
 
 template <int P, int NS>
 hipError_t launch_lm(const NodeTable& t, int64_t n, int32_t samples, int32_t rounds,
-                     const uint32_t* alt, double* lam, double* xk, hipStream_t s) {
+                     const uint32_t* alt, const LebesgueBufs& bufs, double* lam, double* xk,
+                     hipStream_t s) {
   constexpr int IG = 4 / NS;
   const int64_t blocks = (n - 1 + IG - 1) / IG;
   k_lebesgue_max<P, NS><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(
-      t.x, t.w, t.pr, t.pok, t.n_pad, n, samples, rounds, alt, lam, xk);
+      t.x, t.w, t.pr, t.pok, bufs.oct, bufs.oct_ok, t.n_pad, n, samples, rounds, alt, lam, xk);
   return hipGetLastError();
 }
 
 template <int P>
 hipError_t launch_lm_p(const NodeTable& t, int64_t n, int32_t samples, int32_t rounds,
-                       const uint32_t* alt, double* lam, double* xk, hipStream_t s) {
+                       const uint32_t* alt, const LebesgueBufs& bufs, double* lam, double* xk,
+                       hipStream_t s) {
   const int64_t intervals = n - 1;
   // enough waves for the chip: about 4 per SIMD (1024 SIMDs)
-  if (intervals >= 4096) return launch_lm<P, 1>(t, n, samples, rounds, alt, lam, xk, s);
-  if (intervals >= 2048) return launch_lm<P, 2>(t, n, samples, rounds, alt, lam, xk, s);
-  return launch_lm<P, 4>(t, n, samples, rounds, alt, lam, xk, s);
+  if (intervals >= 4096) return launch_lm<P, 1>(t, n, samples, rounds, alt, bufs, lam, xk, s);
+  if (intervals >= 2048) return launch_lm<P, 2>(t, n, samples, rounds, alt, bufs, lam, xk, s);
+  return launch_lm<P, 4>(t, n, samples, rounds, alt, bufs, lam, xk, s);
 }
 
 }  // namespace
 
-size_t layout_lebesgue_max(void* ws, int64_t n, NodeTable* t, double** lam, double** xk) {
+size_t layout_lebesgue_max(void* ws, int64_t n, NodeTable* t, LebesgueBufs* bufs) {
   size_t off = layout_tables(ws, n, t);
   char* base = static_cast<char*>(ws);
   const size_t bytes = sizeof(double) * (size_t)(n > 1 ? n - 1 : 1);
-  *lam = base ? reinterpret_cast<double*>(base + off) : nullptr;
+  bufs->lam = base ? reinterpret_cast<double*>(base + off) : nullptr;
   off = align_up(off + bytes);
-  *xk = base ? reinterpret_cast<double*>(base + off) : nullptr;
+  bufs->xk = base ? reinterpret_cast<double*>(base + off) : nullptr;
   off = align_up(off + bytes);
+  bufs->oct = base ? reinterpret_cast<double*>(base + off) : nullptr;
+  off = align_up(off + sizeof(double) * (size_t)(t->n_pad / kPairBlock * kOctetRec));
+  bufs->oct_ok = base ? reinterpret_cast<uint32_t*>(base + off) : nullptr;
+  off = align_up(off + sizeof(uint32_t));
   return off;
 }
 
 hipError_t launch_lebesgue_max(const NodeTable& t, int64_t n, int32_t samples, int32_t rounds,
-                               const uint32_t* alt, double* lam, double* xk, double* best,
-                               hipStream_t s) {
+                               const uint32_t* alt, const LebesgueBufs& bufs, double* lam,
+                               double* xk, double* best, hipStream_t s) {
   hipError_t e = hipSuccess;
   if (n > 1) {
+    k_pack_octets<<<dim3(1), dim3(256), 0, s>>>(t.x, t.w, n, t.n_pad, bufs.oct, bufs.oct_ok);
+    e = hipGetLastError();
     const int p = (samples + 63) / 64;
-    if (p <= 1)
-      e = launch_lm_p<1>(t, n, samples, rounds, alt, lam, xk, s);
+    if (e != hipSuccess)
+      return e;
+    else if (p <= 1)
+      e = launch_lm_p<1>(t, n, samples, rounds, alt, bufs, lam, xk, s);
     else if (p <= 2)
-      e = launch_lm_p<2>(t, n, samples, rounds, alt, lam, xk, s);
+      e = launch_lm_p<2>(t, n, samples, rounds, alt, bufs, lam, xk, s);
     else if (p <= 4)
-      e = launch_lm_p<4>(t, n, samples, rounds, alt, lam, xk, s);
+      e = launch_lm_p<4>(t, n, samples, rounds, alt, bufs, lam, xk, s);
     else
-      e = launch_lm_p<8>(t, n, samples, rounds, alt, lam, xk, s);
+      e = launch_lm_p<8>(t, n, samples, rounds, alt, bufs, lam, xk, s);
   }
   if (e != hipSuccess || best == nullptr) return e;
   k_lebesgue_best<<<dim3(1), dim3(256), 0, s>>>(lam, xk, n - 1, t.x, best);

@@ -115,3 +115,28 @@ def test_full_table_sampled():
         ks = None if n <= 257 else np.unique(np.concatenate(
             [[0, n - 2], g.choice(n - 1, 22, replace=False)]))
         _check(c["nodes"], c["d"], 256, 5, ks)
+
+
+@pytest.mark.parametrize("scale", [1e-60, 1e-7, 1e7, 1e60])
+def test_scaled_nodes(scale):
+    """Nodes scaled far from 1: the octet records (the blocks far from an
+    interval: eight same-parity nodes as one rational function in monomial
+    form) are used only where every intermediate stays a normal number, so
+    at 1e-60 and 1e60 the search runs without them; Lambda does not change
+    with the scale, and every maximum meets the oracle's bar."""
+    nodes = inputs.equispaced(1025) * scale
+    ks = np.arange(0, 1024, 29)
+    lam, _ = _check(nodes, 2, 64, 1, ks)
+    lam1, _, _ = _gpu(nodes / scale, 2, 64, 1)
+    assert np.all(np.abs(lam - lam1[ks]) <= _tol(lam1[ks]))
+
+
+def test_table_without_octets():
+    """One block twenty times wider than the spacing around it fails both
+    the pair test and the octet test: the whole table runs without octets
+    (that block node by node, the others by pairs) and meets the oracle's
+    bar on every interval."""
+    h = np.ones(1024)
+    h[16 * 30:16 * 30 + 15] = 20.0
+    x = np.concatenate([[0.0], np.cumsum(h)])
+    _check(-1.0 + 2.0 * x / x[-1], 3, 64, 1)
