@@ -61,7 +61,7 @@ FLOPS_PER_PAIR_RL = 7
 CLOCK_WARMUP_MS = 100.0  # untimed steps before the W warm-up steps (run_sines)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_eval_f64_sines.json")
 EVAL_SRC = [os.path.join(ROOT, "paper_1606_06508_amd", "csrc", f)
-            for f in ("eval_f64.hip", "pair_math.h")]
+            for f in ("eval_f64.hip", "pair_math.h", "octets.hip")]
 
 
 def _t(a, dev):

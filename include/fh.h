@@ -103,7 +103,13 @@ typedef enum {
 #define FH_FLAG_RANGE 0x4u     /* a weight product is zero, subnormal or infinite */
 
 /* Bytes of workspace an operation needs (0 on bad arguments).  `m` is the
- * number of evaluation points; for FH_OP_WEIGHTS it is ignored. */
+ * number of evaluation points; for FH_OP_WEIGHTS it is ignored.  For
+ * FH_OP_EVAL in binary64 the size includes, beyond the node tables, the
+ * octet records and room for m points sorted by node block, which the
+ * octet launch variants use (fh_variant_octets).  The evaluation calls
+ * check only for the node tables; with fh_workspace_size(FH_OP_EVAL, n, m,
+ * d, prec) bytes they can run the octet variants for up to m points, and
+ * with less room they run the pair variant of the same shape. */
 size_t fh_workspace_size(int32_t op, int64_t n, int64_t m, int32_t d, int32_t prec);
 
 /* Node weights w_k of the definition above (Floater & Hormann 2007, the
@@ -395,6 +401,19 @@ fh_status fh_batch_status(fh_batch* b, void* stream, uint32_t* bits_out);
  *                  w_a/(x - x_a) + w_b/(x - x_b) = (B x'' + J)/(x''^2 - hh^2) --
  *                  with the blocks next to each point summed node by node
  *                  afterwards, 0 otherwise, -1 for a bad family or id;
+ *   fh_variant_octets  1 if a binary64 variant also sums the node blocks
+ *                  far from a point by octets (the eight even, and the eight
+ *                  odd, records of a block as one rational function in
+ *                  monomial form; a block serves the points at least two
+ *                  whole blocks beyond the blocks of their neighbouring
+ *                  nodes, and only tables whose every block passed the
+ *                  octet error test use them), 0 otherwise, -1 for a bad
+ *                  family or id.  Such a launch sorts the points by node
+ *                  block first, which needs the workspace room that
+ *                  fh_workspace_size(FH_OP_EVAL, n, m, ...) includes for m
+ *                  points (n <= 65536, m < 2^31); with less room the call
+ *                  runs the pair variant of the same shape (other bits),
+ *                  as fh_eval_noalloc always does;
  *   fh_variant_strip_points  points one block covers (single-interpolant
  *                  families) or one work item (batched families), -1 for a
  *                  bad family or id;
@@ -415,6 +434,7 @@ fh_status fh_variant_shape(int32_t prec, int32_t id, int32_t* points_per_lane, i
                            int32_t* node_split);
 int32_t fh_variant_lebesgue_block(int32_t prec, int32_t id);
 int32_t fh_variant_node_pairs(int32_t prec, int32_t id);
+int32_t fh_variant_octets(int32_t prec, int32_t id);
 int64_t fh_variant_strip_points(int32_t prec, int32_t id);
 fh_status fh_tune_set(int32_t prec, int64_t n, int64_t m, int32_t id);
 fh_status fh_tune_force(int32_t prec, int32_t id);

@@ -51,6 +51,31 @@ fh_status finish(hipError_t e, void* ws, hipStream_t s) {
 
 }  // namespace
 
+namespace {
+
+// The smallest evaluation workspace: the node tables (the octet variants
+// also need the room layout_octets reports, else their pair twin runs).
+size_t eval_ws_min(int64_t n) {
+  fhk::NodeTable t;
+  return fhk::layout_tables(nullptr, n, &t);
+}
+
+bool octets_usable(int64_t n, int64_t m, size_t ws_bytes) {
+  fhk::OctetBufs b;
+  return fhk::octets_possible(n, m) && ws_bytes >= fhk::layout_octets(nullptr, n, m, &b);
+}
+
+// The tuned variant for the shape; an octet variant gives way to its pair
+// twin where its buffers do not fit.
+fhk::EvalConfig eval_config(int32_t prec, int64_t n, int64_t m, bool want_r, bool want_l,
+                            bool octets) {
+  fhk::EvalConfig c = fhk::choose_eval_config(prec, n, 0, m, want_r, want_l);
+  if (prec == FH_FP64 && !octets) c.variant = fhk::f64_variant_octet_twin(c.variant);
+  return c;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* fh_status_string(int32_t s) {
@@ -75,7 +100,12 @@ size_t fh_workspace_size(int32_t op, int64_t n, int64_t m, int32_t d, int32_t pr
   NodeTable t;
   switch (op) {
     case FH_OP_WEIGHTS: return kStatusBytes;
-    case FH_OP_EVAL: return layout_tables(nullptr, n, &t);
+    case FH_OP_EVAL: {
+      // binary64: room for the octet variants' records and m sorted points
+      if (prec == FH_FP32_SPLIT) return layout_tables(nullptr, n, &t);
+      OctetBufs b;
+      return layout_octets(nullptr, n, m, &b);
+    }
     case FH_OP_BACKWARD: {
       BackwardBufs b;
       return layout_backward(nullptr, n, m, prec == FH_FP32_SPLIT, &t, &b);
@@ -108,7 +138,7 @@ fh_status fh_prepare(const double* nodes, const double* values, int64_t n, int32
   fh_status st = check_problem(nodes, n, d);
   if (st != FH_OK) return st;
   if (prec != FH_FP64 && prec != FH_FP32_SPLIT) return FH_E_ARG;
-  st = check_ws(ws, ws_bytes, fh_workspace_size(FH_OP_EVAL, n, 0, d, prec));
+  st = check_ws(ws, ws_bytes, eval_ws_min(n));
   if (st != FH_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   NodeTable t;
@@ -130,7 +160,7 @@ fh_status fh_prepare_many(const double* nodes, const double* values, int64_t n,
   for (int32_t c = 0; c < K; ++c) {
     const int32_t d = d_host[c];
     if (d < 0 || (int64_t)d > n - 1) return FH_E_DEGREE;
-    fh_status st = check_ws(ws_host[c], ws_bytes, fh_workspace_size(FH_OP_EVAL, n, 0, d, prec));
+    fh_status st = check_ws(ws_host[c], ws_bytes, eval_ws_min(n));
     if (st != FH_OK) return st;
     for (int32_t e = 0; e < c; ++e)
       if (ws_host[e] == ws_host[c]) return FH_E_ARG;  // one table per workspace
@@ -169,7 +199,7 @@ fh_status fh_eval_prepared_many(void* const* ws_host, size_t ws_bytes, int32_t K
   EvalMany a{};
   int64_t n_pad = 0;
   for (int32_t c = 0; c < K; ++c) {
-    fh_status st = check_ws(ws_host[c], ws_bytes, fh_workspace_size(FH_OP_EVAL, n, m, 0, prec));
+    fh_status st = check_ws(ws_host[c], ws_bytes, eval_ws_min(n));
     if (st != FH_OK) return st;
     if ((r_host && r_host[c] == nullptr) || (lambda_host && lambda_host[c] == nullptr))
       return FH_E_ARG;
@@ -192,11 +222,35 @@ fh_status fh_eval_prepared_many(void* const* ws_host, size_t ws_bytes, int32_t K
   // points: the variant tuned for the launch's K * m points is taken only if
   // it sums in the same order as that call's variant
   const bool want_r = r_host != nullptr, want_l = lambda_host != nullptr;
-  const EvalConfig one = choose_eval_config(prec, n, 0, m, want_r, want_l);
-  EvalConfig cfg = choose_eval_config(prec, n, 0, m * K, want_r, want_l);
+  const bool oct = octets_usable(n, m, ws_bytes);
+  const EvalConfig one = eval_config(prec, n, m, want_r, want_l, oct);
+  EvalConfig cfg = eval_config(prec, n, m * K, want_r, want_l, oct);
   if (bit_class(prec, cfg.variant) != bit_class(prec, one.variant)) cfg = one;
-  if (launch_eval_f64_many(x, m, n, n_pad, a, K, r_host != nullptr, lambda_host != nullptr, cfg,
-                           s) != hipSuccess)
+  const double* xe = x;
+  if (f64_variant_octets(cfg.variant)) {
+    // every table's octet records, then the points sorted once for all
+    OctetTables ot{};
+    OctetBufs b0{};
+    for (int32_t c = 0; c < K; ++c) {
+      OctetBufs b;
+      layout_octets(ws_host[c], n, m, &b);
+      if (c == 0) b0 = b;
+      ot.x[c] = a.x[c];
+      ot.w[c] = a.w[c];
+      ot.wf[c] = a.wf[c];
+      ot.rec[c] = b.rec;
+      ot.ok[c] = b.ok;
+      a.oc[c] = b.rec;
+      a.ook[c] = b.ok;
+    }
+    a.order = b0.order;
+    xe = b0.xs;
+    if (launch_octet_records(ot, K, n, n_pad, s) != hipSuccess ||
+        launch_sort_points(x, m, a.x[0], n_pad, b0, s) != hipSuccess)
+      return FH_E_HIP;
+  }
+  if (launch_eval_f64_many(xe, m, n, n_pad, a, K, r_host != nullptr, lambda_host != nullptr,
+                           cfg, s) != hipSuccess)
     return FH_E_HIP;
   if (sync_check_enabled()) {
     for (int32_t c = 0; c < K; ++c) {
@@ -213,20 +267,39 @@ fh_status fh_eval_prepared(void* ws, size_t ws_bytes, int64_t n, int32_t prec, c
   if (n < 1 || n > FH_MAX_NODES || m < 0 || (m > 0 && x == nullptr)) return FH_E_ARG;
   if (m > 0 && r_out == nullptr && lambda_out == nullptr) return FH_E_ARG;
   if (prec != FH_FP64 && prec != FH_FP32_SPLIT) return FH_E_ARG;
-  fh_status st = check_ws(ws, ws_bytes, fh_workspace_size(FH_OP_EVAL, n, m, 0, prec));
+  fh_status st = check_ws(ws, ws_bytes, eval_ws_min(n));
   if (st != FH_OK) return st;
   if (m == 0) return FH_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
   NodeTable t;
   layout_tables(ws, n, &t);
+  const bool oct = prec == FH_FP64 && octets_usable(n, m, ws_bytes);
   const EvalConfig cfg =
-      choose_eval_config(prec, n, 0, m, r_out != nullptr, lambda_out != nullptr);
-  const hipError_t e = prec == FH_FP32_SPLIT
-                           ? launch_eval_split(x, m, t, n, static_cast<int32_t*>(ws) + 1,
-                                               static_cast<uint32_t*>(ws) + 3, r_out,
-                                               lambda_out, cfg, s)
-                           : launch_eval_f64(x, m, t, n, static_cast<uint32_t*>(ws) + 3, r_out,
-                                             lambda_out, cfg, s);
+      eval_config(prec, n, m, r_out != nullptr, lambda_out != nullptr, oct);
+  if (prec == FH_FP32_SPLIT)
+    return finish(launch_eval_split(x, m, t, n, static_cast<int32_t*>(ws) + 1,
+                                    static_cast<uint32_t*>(ws) + 3, r_out, lambda_out, cfg, s),
+                  ws, s);
+  OctetArgs oa{};
+  const double* xe = x;
+  hipError_t e = hipSuccess;
+  if (f64_variant_octets(cfg.variant)) {
+    OctetBufs b;
+    layout_octets(ws, n, m, &b);
+    OctetTables ot{};
+    ot.x[0] = t.x;
+    ot.w[0] = t.w;
+    ot.wf[0] = t.wf;
+    ot.rec[0] = b.rec;
+    ot.ok[0] = b.ok;
+    e = launch_octet_records(ot, 1, n, t.n_pad, s);
+    if (e == hipSuccess) e = launch_sort_points(x, m, t.x, t.n_pad, b, s);
+    oa = OctetArgs{b.rec, b.ok, b.order};
+    xe = b.xs;
+  }
+  if (e == hipSuccess)
+    e = launch_eval_f64(xe, m, t, n, static_cast<uint32_t*>(ws) + 3, r_out, lambda_out, cfg, oa,
+                        s);
   return finish(e, ws, s);
 }
 
@@ -240,7 +313,7 @@ static fh_status eval_common(const double* nodes, const double* values, int64_t 
   if (m > 0 && r_out == nullptr && lambda_out == nullptr) return FH_E_ARG;
   if (r_out != nullptr && values == nullptr) return FH_E_ARG;
   if (prec != FH_FP64 && prec != FH_FP32_SPLIT) return FH_E_ARG;
-  st = check_ws(ws, ws_bytes, fh_workspace_size(FH_OP_EVAL, n, m, d, prec));
+  st = check_ws(ws, ws_bytes, eval_ws_min(n));
   if (st != FH_OK) return st;
   st = fh_prepare(nodes, values, n, d, w, prec, ws, ws_bytes, stream);
   if (st != FH_OK) return st;
@@ -325,7 +398,7 @@ fh_status fh_eval_deriv(const double* nodes, const double* values, int64_t n, in
   if (values == nullptr || m < 0 || (m > 0 && (x == nullptr || dr_out == nullptr)))
     return FH_E_ARG;
   if (prec != FH_FP64 && prec != FH_FP32_SPLIT) return FH_E_ARG;
-  st = check_ws(ws, ws_bytes, fh_workspace_size(FH_OP_EVAL, n, m, d, prec));
+  st = check_ws(ws, ws_bytes, eval_ws_min(n));
   if (st != FH_OK) return st;
   st = fh_prepare(nodes, values, n, d, w, prec, ws, ws_bytes, stream);
   if (st != FH_OK || m == 0) return st;

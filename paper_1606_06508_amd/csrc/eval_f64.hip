@@ -57,7 +57,7 @@ namespace fhk {
 // takes the failing ones node by node.  JKL: the pair terms' J and K are
 // staged in LDS first (jk_lds, n_loop doubles; the launch passes that much
 // dynamic LDS).
-template <int P, int G, int S, bool R, bool L, int U, bool PAIRS, bool JKL>
+template <int P, int G, int S, bool R, bool L, int U, bool PAIRS, bool JKL, bool OCT>
 __device__ __forceinline__ void eval_f64_points(const double* __restrict__ x, int64_t m,
                                                 const double* __restrict__ tx,
                                                 const double* __restrict__ tw,
@@ -67,7 +67,7 @@ __device__ __forceinline__ void eval_f64_points(const double* __restrict__ x, in
                                                 const double* __restrict__ f, int64_t n,
                                                 const uint32_t* __restrict__ alt,
                                                 double* __restrict__ r, double* __restrict__ lam,
-                                                double* jk_lds) {
+                                                double* jk_lds, const OctetArgs& oa) {
   static_assert(!PAIRS || U == kPairBlock, "pair records come in blocks of 16");
   static_assert(PAIRS || !JKL, "LDS staging serves the pair variants");
   constexpr int PG = 4 / S;  // point groups per block
@@ -114,12 +114,30 @@ __device__ __forceinline__ void eval_f64_points(const double* __restrict__ x, in
         __syncthreads();
       }
       if (blocks) {
+        OctetView ov{};
+        if constexpr (OCT) {
+          // the smallest and largest of the wave's points (NaN ignored)
+          double lo = xp[0], hi = xp[0];
+#pragma unroll
+          for (int j = 1; j < P; ++j) {
+            lo = fmin(lo, xp[j]);
+            hi = fmax(hi, xp[j]);
+          }
+          for (int off = 32; off > 0; off >>= 1) {
+            lo = fmin(lo, __shfl_xor(lo, off, 64));
+            hi = fmax(hi, __shfl_xor(hi, off, 64));
+          }
+          ov.rec = oa.rec;
+          ov.on = __builtin_amdgcn_readfirstlane(*oa.ok) != 0;
+          ov.xmin = uniform_f64(lo);
+          ov.xmax = uniform_f64(hi);
+        }
         if (pair_table_ok(pok, n_loop))
-          accumulate_f64_pairs<P, R, L, JKL, false>(xp, pr, jk_lds, tx, tw, twf, k_begin, k_end,
-                                                    N, D, A, bad, rlast);
+          accumulate_f64_pairs<P, R, L, JKL, false, OCT>(xp, pr, jk_lds, tx, tw, twf, k_begin,
+                                                         k_end, N, D, A, bad, rlast, &ov);
         else
-          accumulate_f64_pairs<P, R, L, JKL, true>(xp, pr, jk_lds, tx, tw, twf, k_begin, k_end,
-                                                   N, D, A, bad, rlast);
+          accumulate_f64_pairs<P, R, L, JKL, true, OCT>(xp, pr, jk_lds, tx, tw, twf, k_begin,
+                                                        k_end, N, D, A, bad, rlast, &ov);
       }
     } else if (blocks) {
       accumulate_f64_blocks<P, G, U, R, L>(xp, tx, tw, twf, k_begin, k_end, N, D, A, bad);
@@ -189,35 +207,39 @@ __device__ __forceinline__ void eval_f64_points(const double* __restrict__ x, in
       rv = N[j] / D[j];
       lv = a / fabs(D[j]);
     }
-    if (R) r[idx] = rv;
-    if (L) lam[idx] = lv;
+    // octet launches run over the points sorted: each result goes to the
+    // point's original position
+    const int64_t dst = OCT ? (int64_t)oa.order[idx] : idx;
+    if (R) r[dst] = rv;
+    if (L) lam[dst] = lv;
   }
 }
 
-template <int P, int G, int S, bool R, bool L, int U, bool PAIRS, bool JKL>
+template <int P, int G, int S, bool R, bool L, int U, bool PAIRS, bool JKL, bool OCT>
 __global__ void __launch_bounds__(256)
     k_eval_f64(const double* __restrict__ x, int64_t m, const double* __restrict__ tx,
                const double* __restrict__ tw, const double* __restrict__ twf,
                const double* __restrict__ pr, const uint32_t* __restrict__ pok, int64_t n_pad,
                const double* __restrict__ f, int64_t n, const uint32_t* __restrict__ alt,
-               double* __restrict__ r, double* __restrict__ lam) {
+               double* __restrict__ r, double* __restrict__ lam, OctetArgs oa) {
   extern __shared__ double jk_lds[];
-  eval_f64_points<P, G, S, R, L, U, PAIRS, JKL>(x, m, tx, tw, twf, pr, pok, n_pad, f, n, alt, r,
-                                                lam, jk_lds);
+  eval_f64_points<P, G, S, R, L, U, PAIRS, JKL, OCT>(x, m, tx, tw, twf, pr, pok, n_pad, f, n, alt,
+                                                     r, lam, jk_lds, oa);
 }
 
 // Several tables on the same points: table blockIdx.y, the points of
 // blockIdx.x as in k_eval_f64.  One launch instead of one per table saves
 // the drain of each launch's last blocks and the gap before the next.
-template <int P, int G, int S, bool R, bool L, int U, bool PAIRS, bool JKL>
+template <int P, int G, int S, bool R, bool L, int U, bool PAIRS, bool JKL, bool OCT>
 __global__ void __launch_bounds__(256)
     k_eval_f64_many(const double* __restrict__ x, int64_t m, int64_t n_pad, int64_t n,
                     EvalMany a) {
   extern __shared__ double jk_lds[];
   const int i = blockIdx.y;
-  eval_f64_points<P, G, S, R, L, U, PAIRS, JKL>(x, m, a.x[i], a.w[i], a.wf[i], a.pr[i],
-                                                a.pok[i], n_pad, a.f[i], n, a.alt[i], a.r[i],
-                                                a.lam[i], jk_lds);
+  eval_f64_points<P, G, S, R, L, U, PAIRS, JKL, OCT>(x, m, a.x[i], a.w[i], a.wf[i], a.pr[i],
+                                                     a.pok[i], n_pad, a.f[i], n, a.alt[i], a.r[i],
+                                                     a.lam[i], jk_lds,
+                                                     OctetArgs{a.oc[i], a.ook[i], a.order});
 }
 
 // Dynamic LDS of a pair variant's launch: J and K of the node range when it
@@ -227,63 +249,68 @@ static size_t pair_lds_bytes(int64_t n) {
   return n_loop <= kPairLdsRecords ? sizeof(double) * (size_t)n_loop : 0;
 }
 
-template <int P, int G, int S, int U, bool PAIRS, bool JKL>
+template <int P, int G, int S, int U, bool PAIRS, bool JKL, bool OCT>
 static hipError_t launch_many_k(const double* x, int64_t m, int64_t n, int64_t n_pad,
                                 const EvalMany& a, int32_t K, bool r, bool lam, size_t lds,
                                 hipStream_t s) {
   const int64_t per = 64LL * P * (4 / S);  // points per block
   const dim3 grid((unsigned)((m + per - 1) / per), (unsigned)K), block(256);
   if (r && lam)
-    k_eval_f64_many<P, G, S, true, true, U, PAIRS, JKL><<<grid, block, lds, s>>>(x, m, n_pad, n,
-                                                                                a);
+    k_eval_f64_many<P, G, S, true, true, U, PAIRS, JKL, OCT>
+        <<<grid, block, lds, s>>>(x, m, n_pad, n, a);
   else if (r)
-    k_eval_f64_many<P, G, S, true, false, U, PAIRS, JKL><<<grid, block, lds, s>>>(x, m, n_pad, n,
-                                                                                 a);
+    k_eval_f64_many<P, G, S, true, false, U, PAIRS, JKL, OCT>
+        <<<grid, block, lds, s>>>(x, m, n_pad, n, a);
   else
-    k_eval_f64_many<P, G, S, false, true, U, PAIRS, JKL><<<grid, block, lds, s>>>(x, m, n_pad, n,
-                                                                                 a);
+    k_eval_f64_many<P, G, S, false, true, U, PAIRS, JKL, OCT>
+        <<<grid, block, lds, s>>>(x, m, n_pad, n, a);
   return hipGetLastError();
 }
 
-template <int P, int G, int S, int U, bool PAIRS>
+template <int P, int G, int S, int U, bool PAIRS, bool OCT>
 static hipError_t launch_many_v(const double* x, int64_t m, int64_t n, int64_t n_pad,
                                 const EvalMany& a, int32_t K, bool r, bool lam, hipStream_t s) {
   const size_t lds = PAIRS ? pair_lds_bytes(n) : 0;
   if constexpr (PAIRS)
-    if (lds > 0) return launch_many_k<P, G, S, U, true, true>(x, m, n, n_pad, a, K, r, lam, lds, s);
-  return launch_many_k<P, G, S, U, PAIRS, false>(x, m, n, n_pad, a, K, r, lam, 0, s);
+    if (lds > 0)
+      return launch_many_k<P, G, S, U, true, true, OCT>(x, m, n, n_pad, a, K, r, lam, lds, s);
+  return launch_many_k<P, G, S, U, PAIRS, false, OCT>(x, m, n, n_pad, a, K, r, lam, 0, s);
 }
 
-template <int P, int G, int S, int U, bool PAIRS, bool JKL>
+template <int P, int G, int S, int U, bool PAIRS, bool JKL, bool OCT>
 static hipError_t launch_k(const double* x, int64_t m, const NodeTable& t, int64_t n,
                            const uint32_t* alt, double* r, double* lam, size_t lds,
-                           hipStream_t s) {
+                           const OctetArgs& oa, hipStream_t s) {
   const int64_t per = 64LL * P * (4 / S);  // points per block
   const dim3 grid((unsigned)((m + per - 1) / per)), block(256);
   if (r && lam)
-    k_eval_f64<P, G, S, true, true, U, PAIRS, JKL><<<grid, block, lds, s>>>(
-        x, m, t.x, t.w, t.wf, t.pr, t.pok, t.n_pad, t.f, n, alt, r, lam);
+    k_eval_f64<P, G, S, true, true, U, PAIRS, JKL, OCT><<<grid, block, lds, s>>>(
+        x, m, t.x, t.w, t.wf, t.pr, t.pok, t.n_pad, t.f, n, alt, r, lam, oa);
   else if (r)
-    k_eval_f64<P, G, S, true, false, U, PAIRS, JKL><<<grid, block, lds, s>>>(
-        x, m, t.x, t.w, t.wf, t.pr, t.pok, t.n_pad, t.f, n, alt, r, lam);
+    k_eval_f64<P, G, S, true, false, U, PAIRS, JKL, OCT><<<grid, block, lds, s>>>(
+        x, m, t.x, t.w, t.wf, t.pr, t.pok, t.n_pad, t.f, n, alt, r, lam, oa);
   else
-    k_eval_f64<P, G, S, false, true, U, PAIRS, JKL><<<grid, block, lds, s>>>(
-        x, m, t.x, t.w, t.wf, t.pr, t.pok, t.n_pad, t.f, n, alt, r, lam);
+    k_eval_f64<P, G, S, false, true, U, PAIRS, JKL, OCT><<<grid, block, lds, s>>>(
+        x, m, t.x, t.w, t.wf, t.pr, t.pok, t.n_pad, t.f, n, alt, r, lam, oa);
   return hipGetLastError();
 }
 
-template <int P, int G, int S, int U, bool PAIRS>
+template <int P, int G, int S, int U, bool PAIRS, bool OCT>
 static hipError_t launch_v(const double* x, int64_t m, const NodeTable& t, int64_t n,
-                           const uint32_t* alt, double* r, double* lam, hipStream_t s) {
+                           const uint32_t* alt, double* r, double* lam, const OctetArgs& oa,
+                           hipStream_t s) {
   const size_t lds = PAIRS ? pair_lds_bytes(n) : 0;
   if constexpr (PAIRS)
-    if (lds > 0) return launch_k<P, G, S, U, true, true>(x, m, t, n, alt, r, lam, lds, s);
-  return launch_k<P, G, S, U, PAIRS, false>(x, m, t, n, alt, r, lam, 0, s);
+    if (lds > 0)
+      return launch_k<P, G, S, U, true, true, OCT>(x, m, t, n, alt, r, lam, lds, oa, s);
+  return launch_k<P, G, S, U, PAIRS, false, OCT>(x, m, t, n, alt, r, lam, 0, oa, s);
 }
 
 // Variant table: id -> (points per lane P, group size G, node split S,
 // Lebesgue block U; U = 0: plain sums, node pairs: 1 for sums by node pairs
-// in blocks of U = 16, G then the group of the node-by-node blocks).
+// in blocks of U = 16, G then the group of the node-by-node blocks, 2 for
+// node pairs and octets: the launch sorts the points by the block of their
+// neighbouring nodes and sums the blocks far from a point by octets).
 #define FH_F64_VARIANTS(X)                                                                    \
   X(0, 1, 4, 1, 0, 0) X(1, 2, 4, 1, 0, 0) X(2, 4, 4, 1, 0, 0) X(3, 1, 8, 1, 0, 0)             \
   X(4, 2, 8, 1, 0, 0) X(5, 4, 8, 1, 0, 0) X(6, 1, 4, 4, 0, 0) X(7, 2, 4, 4, 0, 0)             \
@@ -291,7 +318,7 @@ static hipError_t launch_v(const double* x, int64_t m, const NodeTable& t, int64
   X(12, 1, 8, 2, 0, 0) X(13, 2, 8, 2, 0, 0) X(14, 4, 8, 2, 0, 0) X(15, 1, 8, 4, 16, 0)        \
   X(16, 2, 8, 4, 16, 0) X(17, 1, 8, 2, 16, 0) X(18, 2, 8, 2, 16, 0) X(19, 1, 8, 2, 16, 1)     \
   X(20, 2, 8, 2, 16, 1) X(21, 2, 8, 4, 16, 1) X(22, 4, 8, 2, 16, 1) X(23, 2, 8, 1, 16, 1)     \
-  X(24, 4, 8, 1, 16, 1)
+  X(24, 4, 8, 1, 16, 1) X(25, 4, 8, 2, 16, 2) X(26, 2, 8, 2, 16, 2)
 
 int f64_variant_count() {
 #define FH_COUNT(id, p, g, s, u, pairs) +1
@@ -333,13 +360,36 @@ bool f64_variant_pairs(int id) {
   }
 }
 
+bool f64_variant_octets(int id) {
+  switch (id) {
+#define FH_OCTETS(vid, vp, vg, vs, vu, vpairs) \
+  case vid: return vpairs == 2;
+    FH_F64_VARIANTS(FH_OCTETS)
+#undef FH_OCTETS
+    default: return false;
+  }
+}
+
+int f64_variant_octet_twin(int id) {
+  if (!f64_variant_octets(id)) return id;
+  int p, g, s;
+  f64_variant_shape(id, &p, &g, &s);
+  for (int k = 0; k < f64_variant_count(); ++k) {
+    int kp, kg, ks;
+    f64_variant_shape(k, &kp, &kg, &ks);
+    if (f64_variant_pairs(k) && !f64_variant_octets(k) && kp == p && kg == g && ks == s) return k;
+  }
+  return id;
+}
+
 hipError_t launch_eval_f64(const double* x, int64_t m, const NodeTable& t, int64_t n,
                            const uint32_t* alt, double* r, double* lam, const EvalConfig& cfg,
-                           hipStream_t s) {
+                           const OctetArgs& oa, hipStream_t s) {
   if (m == 0) return hipSuccess;
   switch (cfg.variant) {
 #define FH_CASE(vid, vp, vg, vs, vu, vpairs) \
-  case vid: return launch_v<vp, vg, vs, vu, vpairs != 0>(x, m, t, n, alt, r, lam, s);
+  case vid:                                   \
+    return launch_v<vp, vg, vs, vu, vpairs != 0, vpairs == 2>(x, m, t, n, alt, r, lam, oa, s);
     FH_F64_VARIANTS(FH_CASE)
 #undef FH_CASE
     default: return hipErrorInvalidValue;
@@ -352,7 +402,8 @@ hipError_t launch_eval_f64_many(const double* x, int64_t m, int64_t n, int64_t n
   if (m == 0 || K == 0) return hipSuccess;
   switch (cfg.variant) {
 #define FH_CASE(vid, vp, vg, vs, vu, vpairs) \
-  case vid: return launch_many_v<vp, vg, vs, vu, vpairs != 0>(x, m, n, n_pad, a, K, r, lam, s);
+  case vid:                                   \
+    return launch_many_v<vp, vg, vs, vu, vpairs != 0, vpairs == 2>(x, m, n, n_pad, a, K, r, lam, s);
     FH_F64_VARIANTS(FH_CASE)
 #undef FH_CASE
     default: return hipErrorInvalidValue;

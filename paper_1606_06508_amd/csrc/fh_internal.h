@@ -47,6 +47,16 @@ struct NodeTable {
 // status block).  Returns bytes used.
 size_t layout_tables(void* ws, int64_t n, NodeTable* t);
 
+// Octet launch variants (binary64): the table's octet records and summary
+// word (pair_math.h, written by launch_octet_records) and the original
+// position of each sorted point (order[i]: where sorted point i came from,
+// written by launch_sort_points).  The other variants ignore it.
+struct OctetArgs {
+  const double* rec;
+  const uint32_t* ok;
+  const int32_t* order;
+};
+
 // Launch configuration of an evaluation kernel: an index into the kernel's
 // variant table (points per lane, node group, node split), chosen per
 // problem shape by the tuner (tune.hip).
@@ -59,6 +69,8 @@ int f64_variant_count();
 void f64_variant_shape(int id, int* p, int* g, int* s);
 int f64_variant_block(int id);  // Lebesgue block length U, 0 for plain sums
 bool f64_variant_pairs(int id);  // sums by node pairs (pair_math.h)
+bool f64_variant_octets(int id);  // pairs, and octets for the blocks far from the points
+int f64_variant_octet_twin(int id);  // the pair variant of the same shape
 int split_variant_count();
 void split_variant_shape(int id, int* p, int* g, int* s);
 int split_variant_block(int id);  // node tile of the block sums, 0 for plain sums
@@ -164,16 +176,56 @@ struct EvalMany {
   const uint32_t* alt[kEvalMany];
   double* r[kEvalMany];
   double* lam[kEvalMany];
+  const double* oc[kEvalMany];    // octet variants: each table's octet records
+  const uint32_t* ook[kEvalMany];  // and summary word
+  const int32_t* order;            // original positions of the sorted points
 };
+// The octet variants' buffers in an evaluation workspace, after the node
+// tables: the table's octet records ([n_pad / kPairBlock][kOctetEvalRec])
+// and summary word, and room for m points sorted by node block (per-block
+// counts and cursors, each point's block, the sorted points and their
+// original positions; a launch over several tables sorts into its first
+// table's workspace).
+struct OctetBufs {
+  double* rec;
+  uint32_t* ok;
+  int32_t* count;
+  int32_t* cursor;
+  int32_t* key;
+  double* xs;
+  int32_t* order;
+};
+// Returns the bytes of an evaluation workspace with room for m sorted
+// points (the size fh_workspace_size reports for FH_OP_EVAL in binary64).
+size_t layout_octets(void* ws, int64_t n, int64_t m, OctetBufs* b);
+// Whether the octet variants serve n nodes and m points at all.
+bool octets_possible(int64_t n, int64_t m);
+// Octet records and summary words of K tables of n nodes (one workgroup
+// each).
+struct OctetTables {
+  const double* x[kEvalMany];
+  const double* w[kEvalMany];
+  const double* wf[kEvalMany];
+  double* rec[kEvalMany];
+  uint32_t* ok[kEvalMany];
+};
+hipError_t launch_octet_records(const OctetTables& a, int32_t K, int64_t n, int64_t n_pad,
+                                hipStream_t s);
+// The m points x sorted by node block of the table tx into b.xs, with their
+// original positions in b.order.
+hipError_t launch_sort_points(const double* x, int64_t m, const double* tx, int64_t n_pad,
+                              const OctetBufs& b, hipStream_t s);
 // r / lam: whether every table's r / Lambda is written.
 hipError_t launch_eval_f64_many(const double* x, int64_t m, int64_t n, int64_t n_pad,
                                 const EvalMany& a, int32_t K, bool r, bool lam,
                                 const EvalConfig& cfg, hipStream_t s);
 // alt: status word 3 of the workspace (1 if the table's weights alternate
 // in sign, written by launch_pack), read by the Lebesgue-block variants.
+// Octet variants: x are the points sorted by launch_sort_points and oa
+// names the table's octet records and the points' original positions.
 hipError_t launch_eval_f64(const double* x, int64_t m, const NodeTable& t, int64_t n,
                            const uint32_t* alt, double* r, double* lam, const EvalConfig& cfg,
-                           hipStream_t s);
+                           const OctetArgs& oa, hipStream_t s);
 // scale_exp: the split scaling exponent (status word 1) when b.plan.split.
 hipError_t launch_backward(const double* nodes, const double* x, const double* g, int64_t n,
                            int32_t d, int64_t m, const NodeTable& t, const BackwardBufs& b,

@@ -60,100 +60,24 @@ __device__ __forceinline__ double sample_at(double lo, double h, int i) {
 
 // ---- Octets: the blocks far from the wave's interval ----
 //
-// The even records of a 16-node block (0, 2, ..., 14), and likewise its odd
-// ones, have weights of one sign, and their eight terms add up to one
-// rational function of the octet's coordinate y = (x - c) - m (c the block's
-// anchor, m the midpoint of the octet's first and last offset a' = x_k - c,
-// r_i = a'_i - m its roots):
-//   sum_i w_i / (y - r_i) = P(y) / Q(y),   Q(y) = prod_i (y - r_i),
-//   P(y) = sum_i w_i prod_{j != i} (y - r_j),
-// Q monic of degree 8 and P of degree 7, both evaluated from their
-// monomial coefficients by Horner's rule: one subtraction and 8 + 7
-// operations for eight nodes, and one reciprocal (simultaneous inversion)
-// for the block's two octets.  Horner's rule errs by at most about k u
-// sum_k |c_k| |y|^k, and the coefficients as multiplied out carry errors of
-// the same form; relative to the sum of |w_i / (y - r_i)| both amount to
-// about (8 + 8 + 7 + 7) u times F(y) = prod_i (|y| + |r_i|) / |y - r_i|,
-// which falls as |y| grows.  The search takes a block's octets only for
-// samples with at least kOctetGap whole blocks between the block and the
-// blocks of their interval, so the closest served samples are the nodes
-// x_{16b - 16 kOctetGap - 1} and x_{16b + 16 (kOctetGap + 1)}; the pack
-// passes a block when F at those nodes is at most kOctetFactorMax for both
-// octets (equispaced nodes: F <= 2.24, Chebyshev nodes <= 5.7), its
-// coordinates and coefficients lie where every intermediate stays a normal
-// number, and the table uses octets only when every block passed.
-constexpr int kOctetGap = 2;
-constexpr double kOctetFactorMax = 8.0;
-// per block: c, then for the even and the odd octet m, Q[0..7] (Q = y^8 +
-// sum_k Q[k] y^k) and P[0..7] (P = sum_k P[k] y^k); one spare
+// The search takes the octets of pair_math.h (D only) for the blocks with at
+// least kOctetGap whole blocks between them and the blocks of the wave's
+// interval; the table uses them only if every block passed the octet test.
+// Record per block: c, then for the even and the odd octet m, Q[0..7] and
+// PD[0..7]; one spare.
 constexpr int64_t kOctetRec = 36;
 
-// coefficients t[0..deg] times (y - r), in place (t has room for deg + 2)
-__device__ __forceinline__ void times_root(double* t, int deg, double r) {
-  t[deg + 1] = t[deg];
-  for (int k = deg; k >= 1; --k) t[k] = __builtin_fma(-r, t[k], t[k - 1]);
-  t[0] = -r * t[0];
-}
-
-// The octet record of block b of the table (x, w: n nodes and weights;
-// records at or beyond n repeat x_{n-1} with zero weight); returns whether
-// it passed (see above).  A block with no node below n passes.
+// The octet record of block b of the table (x, w: n nodes and weights);
+// returns whether both octets passed (a block with no node below n passes).
 __device__ bool octet_record(const double* __restrict__ x, const double* __restrict__ w,
                              int64_t n, int64_t b, double* __restrict__ rec) {
-#pragma clang fp contract(off)
   const int64_t k0 = b * kPairBlock;
   const double c = pair_anchor(x, n, k0);
   rec[0] = c;
   rec[kOctetRec - 1] = 0.0;
-  bool ok = true;
-  for (int g = 0; g < 2; ++g) {
-    double a[8], wi[8], r[8];
-    for (int i = 0; i < 8; ++i) {
-      const int64_t k = k0 + g + 2 * i;
-      a[i] = x[k < n ? k : n - 1] - c;
-      wi[i] = k < n ? w[k] : 0.0;
-    }
-    const double m = 0.5 * (a[0] + a[7]);
-    double rho = 0.0;
-    for (int i = 0; i < 8; ++i) {
-      r[i] = a[i] - m;
-      rho = fmax(rho, fabs(r[i]));
-    }
-    double q[9] = {1.0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int i = 0; i < 8; ++i) times_root(q, i, r[i]);
-    double p[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int i = 0; i < 8; ++i) {
-      double t[8] = {1.0, 0, 0, 0, 0, 0, 0, 0};
-      int deg = 0;
-      for (int j = 0; j < 8; ++j)
-        if (j != i) times_root(t, deg++, r[j]);
-      for (int k = 0; k < 8; ++k) p[k] = __builtin_fma(wi[i], t[k], p[k]);
-    }
-    double* o = rec + 1 + 17 * g;
-    o[0] = m;
-    for (int k = 0; k < 8; ++k) {
-      o[1 + k] = q[k];
-      o[9 + k] = p[k];
-      ok = ok && fabs(q[k]) <= 0x1p400 && fabs(p[k]) <= 0x1p400;
-    }
-    // the samples the octet serves lie beyond the two closest ones, and
-    // within the table's end nodes
-    const int64_t side[2] = {k0 - 16 * kOctetGap - 1, k0 + 16 * (kOctetGap + 1)};
-    for (int e = 0; e < 2; ++e) {
-      if (side[e] < 0 || side[e] > n - 1) continue;
-      const double y = (x[side[e]] - c) - m;
-      double f = 1.0, near = INFINITY;
-      for (int i = 0; i < 8; ++i) {
-        const double dy = fabs(y - r[i]);
-        f *= (fabs(y) + fabs(r[i])) / dy;
-        near = fmin(near, dy);
-      }
-      ok = ok && f <= kOctetFactorMax && near >= 0x1p-50;
-    }
-    const double far = fmax(fabs((x[0] - c) - m), fabs((x[n - 1] - c) - m));
-    ok = ok && far + rho <= 0x1p50;
-  }
-  return ok || k0 >= n;
+  const bool e = octet_coefficients<false>(x, w, nullptr, n, k0, c, 0, rec + 1);
+  const bool o = octet_coefficients<false>(x, w, nullptr, n, k0, c, 1, rec + 18);
+  return (e && o) || k0 >= n;
 }
 
 // One workgroup: the octet records of the blocks [0, n_pad / 16) and
@@ -172,14 +96,6 @@ __global__ void __launch_bounds__(256)
   if (threadIdx.x == 0) *all_ok = failed ? 0u : 1u;
 }
 
-// Q (monic, degree 8) and P (degree 7) of one octet at y
-__device__ __forceinline__ void octet_eval(const double* __restrict__ o, double y, double& Q,
-                                           double& Pv) {
-  Q = y + o[8];
-  for (int k = 7; k >= 1; --k) Q = __builtin_fma(Q, y, o[k]);
-  Pv = __builtin_fma(o[16], y, o[15]);
-  for (int k = 14; k >= 9; --k) Pv = __builtin_fma(Pv, y, o[k]);
-}
 
 // accumulate_f64_pairs for points that share their neighbouring nodes: all
 // of the wave's points lie between the same two nodes, so the blocks that
@@ -210,9 +126,9 @@ __device__ __forceinline__ void accumulate_f64_pairs_known(
 #pragma unroll
       for (int j = 0; j < P; ++j) {
         const double x1 = xp[j] - c;
-        double Qe, Pe, Qo, Po;
-        octet_eval(o + 1, x1 - o[1], Qe, Pe);
-        octet_eval(o + 18, x1 - o[18], Qo, Po);
+        double Qe, Pe, Qo, Po, unused;
+        octet_eval<false>(o + 1, x1 - o[1], Qe, Pe, unused);
+        octet_eval<false>(o + 18, x1 - o[18], Qo, Po, unused);
         // one reciprocal for both octets
         const double y = rcp_refined(Qe * Qo);
         const double E = Pe * (y * Qo), O = Po * (y * Qe);

@@ -54,16 +54,17 @@ fh_status fh_eval_noalloc(const double* nodes, const double* values, int64_t n, 
   if (d < 0 || (int64_t)d > n - 1) return FH_E_DEGREE;
   if (m < 0 || (m > 0 && (x == nullptr || r_out == nullptr))) return FH_E_ARG;
   if (prec != FH_FP64 && prec != FH_FP32_SPLIT) return FH_E_ARG;
-  const size_t need = fh_workspace_size(FH_OP_EVAL, n, m, d, prec);
-  if (n > FH_NOALLOC_MAX_NODES || need == 0 || need > FH_NOALLOC_SCRATCH_BYTES)
-    return FH_E_TOO_LARGE;
+  // the node tables; offered no room beyond them, fh_eval runs no octet
+  // variant (those sort the points into the workspace)
+  fhk::NodeTable t;
+  const size_t need = fhk::layout_tables(nullptr, n, &t);
+  if (n > FH_NOALLOC_MAX_NODES || need > FH_NOALLOC_SCRATCH_BYTES) return FH_E_TOO_LARGE;
   void* ws = scratch_ptr();
   if (ws == nullptr) return FH_E_HIP;
   hipStream_t s = static_cast<hipStream_t>(stream);
   k_noalloc_clear_status<<<1, 64, 0, s>>>(static_cast<uint32_t*>(ws));
   if (hipGetLastError() != hipSuccess) return FH_E_HIP;
-  return fh_eval(nodes, values, n, d, x, m, r_out, lambda_out, w, prec, ws,
-                 FH_NOALLOC_SCRATCH_BYTES, stream);
+  return fh_eval(nodes, values, n, d, x, m, r_out, lambda_out, w, prec, ws, need, stream);
 }
 
 }  // extern "C"

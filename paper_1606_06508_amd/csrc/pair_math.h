@@ -474,6 +474,183 @@ __device__ __forceinline__ void pair_group(const double (&x1)[P], const double* 
   }
 }
 
+// ---- Octets: node blocks far from the points ----
+//
+// The even records of a 16-node block (0, 2, ..., 14), and likewise its odd
+// ones, have weights of one sign, and their eight terms add up to one
+// rational function of the octet's coordinate y = (x - c) - m (c the block's
+// anchor, m the midpoint of the octet's first and last offset a' = x_k - c,
+// r_i = a'_i - m its roots):
+//   sum_i w_i / (y - r_i) = PD(y) / Q(y),   Q(y) = prod_i (y - r_i),
+//   PD(y) = sum_i w_i prod_{j != i} (y - r_j),
+// and likewise PN with the weighted values v_i.  Q is monic of degree 8,
+// PD and PN of degree 7, all evaluated from their monomial coefficients by
+// Horner's rule: one subtraction and 8 + 7 (+ 7) operations for eight
+// nodes, and one reciprocal for the block's two octets.  Horner's rule errs
+// by at most about k u sum_k |c_k| |y|^k, and the coefficients as
+// multiplied out carry errors of the same form; relative to the sum of
+// |w_i / (y - r_i)| both amount to about (8 + 8 + 7 + 7) u times
+// F(y) = prod_i (|y| + |r_i|) / |y - r_i|, which falls as |y| grows.  A block
+// takes octets only for points with at least kOctetGap whole blocks between
+// it and the blocks of the points' neighbouring nodes, so the closest
+// points it serves are the nodes x_{16b - 16 kOctetGap - 1} and
+// x_{16b + 16 (kOctetGap + 1)}; an octet passes when F there is at most
+// kOctetFactorMax (equispaced nodes: F <= 2.24, Chebyshev nodes <= 5.7)
+// and its coordinates (|y| <= 2^50, distances >= 2^-50) and coefficients
+// (<= 2^400) keep every intermediate a normal number.
+constexpr int kOctetGap = 2;
+constexpr double kOctetFactorMax = 8.0;
+
+// coefficients t[0..deg] times (y - r), in place (t has room for deg + 2)
+__device__ __forceinline__ void octet_times_root(double* t, int deg, double r) {
+  t[deg + 1] = t[deg];
+  for (int k = deg; k >= 1; --k) t[k] = __builtin_fma(-r, t[k], t[k - 1]);
+  t[0] = -r * t[0];
+}
+
+// Octet g (0: even, 1: odd records) of the block at k0 with anchor c (x,
+// w, v: the table's n nodes, weights and weighted values; records at or
+// beyond n repeat x_{n-1} with zero weight): o[0] = m, o[1..8] = Q[0..7]
+// (Q = y^8 + sum_k Q[k] y^k), o[9..16] = PD[0..7] and, with V,
+// o[17..24] = PN[0..7]; returns whether it passed.
+template <bool V>
+__device__ bool octet_coefficients(const double* __restrict__ x, const double* __restrict__ w,
+                                   const double* __restrict__ v, int64_t n, int64_t k0, double c,
+                                   int g, double* __restrict__ o) {
+#pragma clang fp contract(off)
+  double a[8], wi[8], vi[8], r[8];
+  for (int i = 0; i < 8; ++i) {
+    const int64_t k = k0 + g + 2 * i;
+    a[i] = x[k < n ? k : n - 1] - c;
+    wi[i] = k < n ? w[k] : 0.0;
+    vi[i] = V && k < n ? v[k] : 0.0;
+  }
+  const double m = 0.5 * (a[0] + a[7]);
+  double rho = 0.0;
+  for (int i = 0; i < 8; ++i) {
+    r[i] = a[i] - m;
+    rho = fmax(rho, fabs(r[i]));
+  }
+  double q[9] = {1.0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int i = 0; i < 8; ++i) octet_times_root(q, i, r[i]);
+  double pd[8] = {0, 0, 0, 0, 0, 0, 0, 0}, pn[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int i = 0; i < 8; ++i) {
+    double t[8] = {1.0, 0, 0, 0, 0, 0, 0, 0};
+    int deg = 0;
+    for (int j = 0; j < 8; ++j)
+      if (j != i) octet_times_root(t, deg++, r[j]);
+    for (int k = 0; k < 8; ++k) {
+      pd[k] = __builtin_fma(wi[i], t[k], pd[k]);
+      if (V) pn[k] = __builtin_fma(vi[i], t[k], pn[k]);
+    }
+  }
+  bool ok = true;
+  o[0] = m;
+  for (int k = 0; k < 8; ++k) {
+    o[1 + k] = q[k];
+    o[9 + k] = pd[k];
+    if (V) o[17 + k] = pn[k];
+    ok = ok && fabs(q[k]) <= 0x1p400 && fabs(pd[k]) <= 0x1p400 && fabs(pn[k]) <= 0x1p400;
+  }
+  // the points the octet serves lie beyond the two closest ones
+  const int64_t side[2] = {k0 - 16 * kOctetGap - 1, k0 + 16 * (kOctetGap + 1)};
+  for (int e = 0; e < 2; ++e) {
+    if (side[e] < 0 || side[e] > n - 1) continue;
+    const double y = (x[side[e]] - c) - m;
+    double f = 1.0, near = __builtin_inf();
+    for (int i = 0; i < 8; ++i) {
+      const double dy = fabs(y - r[i]);
+      f *= (fabs(y) + fabs(r[i])) / dy;
+      near = fmin(near, dy);
+    }
+    ok = ok && f <= kOctetFactorMax && near >= 0x1p-50;
+  }
+  const double far = fmax(fabs((x[0] - c) - m), fabs((x[n - 1] - c) - m));
+  return ok && far + rho <= 0x1p50;
+}
+
+// Q and PD (and with V, PN) of one octet (o as written above) at y
+template <bool V>
+__device__ __forceinline__ void octet_eval(const double* __restrict__ o, double y, double& Q,
+                                           double& PD, double& PN) {
+  Q = y + o[8];
+  for (int k = 7; k >= 1; --k) Q = __builtin_fma(Q, y, o[k]);
+  PD = __builtin_fma(o[16], y, o[15]);
+  for (int k = 14; k >= 9; --k) PD = __builtin_fma(PD, y, o[k]);
+  if (V) {
+    PN = __builtin_fma(o[24], y, o[23]);
+    for (int k = 22; k >= 17; --k) PN = __builtin_fma(PN, y, o[k]);
+  }
+}
+
+// Octet records of the evaluation: per block c, then the even and the odd
+// octet with both numerators (25 doubles each), then the closest points the
+// octets serve on either side, L = x_{16b - 16 kOctetGap - 1} and
+// R = x_{16b + 16 (kOctetGap + 1)} (-inf / +inf where there is no such
+// node: no point is served on that side), one spare.  A point x takes the
+// block's octets exactly when x <= L or x >= R.
+constexpr int64_t kOctetEvalRec = 54;
+
+// The evaluation's octet record of block b; returns whether both octets
+// passed (a block with no node below n passes).
+__device__ inline bool octet_eval_record(const double* __restrict__ x,
+                                         const double* __restrict__ w,
+                                         const double* __restrict__ v, int64_t n, int64_t b,
+                                         double* __restrict__ rec) {
+  const int64_t k0 = b * kPairBlock;
+  const double c = pair_anchor(x, n, k0);
+  const int64_t kl = k0 - 16 * kOctetGap - 1, kr = k0 + 16 * (kOctetGap + 1);
+  rec[0] = c;
+  rec[51] = kl >= 0 && kl < n ? x[kl] : -__builtin_inf();
+  rec[52] = kr < n ? x[kr] : __builtin_inf();
+  rec[kOctetEvalRec - 1] = 0.0;
+  const bool e = octet_coefficients<true>(x, w, v, n, k0, c, 0, rec + 1);
+  const bool o = octet_coefficients<true>(x, w, v, n, k0, c, 1, rec + 26);
+  return (e && o) || k0 >= n;
+}
+
+// A wave-uniform double as a scalar value (the same in every lane)
+__device__ __forceinline__ double uniform_f64(double v) {
+  const int64_t b = __builtin_bit_cast(int64_t, v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)b);
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __builtin_bit_cast(double, ((int64_t)hi << 32) | (int64_t)(uint32_t)lo);
+}
+
+// One block's sums from its two octets' values at a point: E = PDe / Qe,
+// O = PDo / Qo (one reciprocal of Qe Qo) and Nb = PNe / Qe + PNo / Qo.  No
+// contraction: every caller gets the same bits.
+template <bool R>
+__device__ __forceinline__ void octet_combine(double Qe, double PDe, double PNe, double Qo,
+                                              double PDo, double PNo, double& Nb, double& E,
+                                              double& O) {
+#pragma clang fp contract(off)
+  const double y = rcp_refined(Qe * Qo);
+  const double te = y * Qo, to = y * Qe;
+  E = PDe * te;
+  O = PDo * to;
+  if (R) Nb = __builtin_fma(PNe, te, PNo * to);
+}
+
+// What a wave knows of the octets (wave-uniform): the table's octet
+// records, whether every block passed the octet test, and the smallest and
+// largest of the wave's points.  Block b serves the points at or beyond its
+// record's L and R; the launch sorts the points by the block of their
+// neighbouring nodes, so that most blocks serve every point of a wave.
+struct OctetView {
+  const double* rec;
+  bool on;
+  double xmin, xmax;
+  // (the compares run on the vector unit; readfirstlane makes the result a
+  // scalar the branch can take)
+  __device__ __forceinline__ bool far_for_all(const double* __restrict__ o) const {
+    return __builtin_amdgcn_readfirstlane((int)(xmax <= o[51] || xmin >= o[52])) != 0;
+  }
+  __device__ __forceinline__ bool far_for_some(const double* __restrict__ o) const {
+    return __builtin_amdgcn_readfirstlane((int)(xmin <= o[51] || xmax >= o[52])) != 0;
+  }
+};
+
 // Whether the block's record passed the pack's test: the high word of its
 // flag (1.0 or 0.0), an integer the scalar unit can branch on.
 __device__ __forceinline__ bool pair_block_passed(const double* __restrict__ rec) {
@@ -537,16 +714,40 @@ __device__ __forceinline__ void pair_block_nodes(const double (&xp)[P],
 // broadcast reads, which use the LDS pipe; without it they are copied from
 // SGPRs to VGPRs, 16 moves per block shared by the lane's P points (vector
 // loads from memory instead left their latency exposed, measured slower).
-template <int P, bool R, bool L, bool JKL, bool MIXED>
+template <int P, bool R, bool L, bool JKL, bool MIXED, bool OCT = false>
 __device__ __forceinline__ void accumulate_f64_pairs(
     const double (&xp)[P], const double* __restrict__ pr, const double* jk_lds,
     const double* __restrict__ tx, const double* __restrict__ tw, const double* __restrict__ twf,
     int64_t k_begin, int64_t k_end, double (&N)[P], double (&D)[P], double (&A)[P],
-    bool (&bad)[P], int32_t (&rlast)[P]) {
+    bool (&bad)[P], int32_t (&rlast)[P], const OctetView* ov = nullptr) {
   const int b0 = (int)(k_begin / kPairBlock);
   const int nb = (int)((k_end - k_begin) / kPairBlock);
   for (int ib = 0; ib < nb; ++ib) {
     const int b = b0 + ib;
+    if constexpr (OCT) {
+      const double* __restrict__ o = ov->rec + (int64_t)b * kOctetEvalRec;
+      if (ov->on && ov->far_for_all(o)) {
+        // the block serves every point of the wave: its octets, no mask
+        double x1[P], Qe[P], PDe[P], PNe[P];
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+          x1[j] = xp[j] - o[0];
+          octet_eval<R>(o + 1, x1[j] - o[1], Qe[j], PDe[j], PNe[j]);
+        }
+        // the odd octet's coefficients load into the SGPRs of the even one's
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+          double Qo, PDo, PNo, Nb, E, O;
+          octet_eval<R>(o + 26, x1[j] - o[26], Qo, PDo, PNo);
+          octet_combine<R>(Qe[j], PDe[j], PNe[j], Qo, PDo, PNo, Nb, E, O);
+          if (R) N[j] += Nb;
+          D[j] += E + O;
+          if (L) A[j] += fabs(E - O);
+        }
+        continue;
+      }
+    }
     const double* __restrict__ rec = pr + (int64_t)b * kPairRec;
     double Nb[P], E[P], O[P];
     const double lo_b = rec[2], hi_b = rec[3];
@@ -564,6 +765,23 @@ __device__ __forceinline__ void accumulate_f64_pairs(
     } else {
       const int64_t k0 = (int64_t)b * kPairBlock;
       pair_block_nodes<P, R>(xp, tx + k0, tw + k0, twf + k0, Nb, E, O);
+    }
+    if constexpr (OCT) {
+      const double* __restrict__ o = ov->rec + (int64_t)b * kOctetEvalRec;
+      if (ov->on && ov->far_for_some(o)) {
+        // the points the block serves take its octets (never masked: the
+        // block holds neither of their neighbouring nodes)
+        const double lo_o = o[51], hi_o = o[52];
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+          if (!(xp[j] <= lo_o || xp[j] >= hi_o)) continue;
+          const double x1 = xp[j] - o[0];
+          double Qe, PDe, PNe, Qo, PDo, PNo;
+          octet_eval<R>(o + 1, x1 - o[1], Qe, PDe, PNe);
+          octet_eval<R>(o + 26, x1 - o[26], Qo, PDo, PNo);
+          octet_combine<R>(Qe, PDe, PNe, Qo, PDo, PNo, Nb[j], E[j], O[j]);
+        }
+      }
     }
 #pragma unroll
     for (int j = 0; j < P; ++j) {

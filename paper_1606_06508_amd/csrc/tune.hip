@@ -65,7 +65,7 @@ struct Builtin {
 // (n = 1001: the single-call shape takes the variant of the nine-degree
 // launch, 1 % slower than its own best, so both sum in the same order.)
 constexpr Builtin kBuiltin[] = {
-    {FH_FP64, 6, 14, 16},       {FH_FP64, 10, 20, 22},      {FH_FP64, 10, 24, 22},
+    {FH_FP64, 6, 14, 16},       {FH_FP64, 10, 20, 25},      {FH_FP64, 10, 24, 25},
     {FH_FP64, 12, 20, 21},      {FH_FP64, 13, 20, 21},      {FH_FP64, 13, 24, 22},
     {FH_FP32_SPLIT, 6, 14, 4},  {FH_FP32_SPLIT, 10, 20, 9}, {FH_FP32_SPLIT, 12, 20, 9},
     {FH_FP32_SPLIT, 13, 20, 9}, {FH_FP32_SPLIT, 13, 24, 9},
@@ -230,7 +230,8 @@ int bit_class(int32_t prec, int id) {
   if (prec == FH_FP64) {
     int p, g, s;
     f64_variant_shape(id, &p, &g, &s);
-    return (f64_variant_pairs(id) ? 1 << 24 : 0) | (g << 16) | (s << 8) | f64_variant_block(id);
+    return (f64_variant_octets(id) ? 1 << 25 : 0) | (f64_variant_pairs(id) ? 1 << 24 : 0) |
+           (g << 16) | (s << 8) | f64_variant_block(id);
   }
   if (prec == FH_FP32_SPLIT) {
     int p, g, s;
@@ -275,6 +276,11 @@ int32_t fh_variant_node_pairs(int32_t prec, int32_t id) {
   if (!valid_family(prec) || id < 0 || id >= variant_count(prec)) return -1;
   if (prec == FH_FP64) return f64_variant_pairs(id) ? 1 : 0;
   return batched_variant_pairs(id, prec == FH_TUNE_BATCHED_SPLIT) ? 1 : 0;
+}
+
+int32_t fh_variant_octets(int32_t prec, int32_t id) {
+  if (!valid_family(prec) || id < 0 || id >= variant_count(prec)) return -1;
+  return prec == FH_FP64 && f64_variant_octets(id) ? 1 : 0;
 }
 
 int64_t fh_variant_strip_points(int32_t prec, int32_t id) {

@@ -88,6 +88,7 @@ def load():
                                   ctypes.POINTER(i32)], ctypes.c_int),
             "fh_variant_lebesgue_block": ([i32, i32], i32),
             "fh_variant_node_pairs": ([i32, i32], i32),
+            "fh_variant_octets": ([i32, i32], i32),
             "fh_variant_strip_points": ([i32, i32], i64),
             "fh_batch_variant": ([vp], i32),
             "fh_batch_strip_points": ([vp], i64),
@@ -395,7 +396,11 @@ def eval_backward_saved(saved, grad_r, *, need_values=True, need_x=True, need_no
 
 class Prepared:
     """An interpolant whose node table lives in its own workspace, for
-    evaluation on many point batches (fh_prepare + fh_eval_prepared)."""
+    evaluation on many point batches (fh_prepare + fh_eval_prepared).
+    m_hint: the point count the workspace has room for beyond the table;
+    binary64 calls with up to that many points can run the octet launch
+    variants (they sort the points into the workspace), larger calls run
+    the pair variant of the same shape."""
 
     def __init__(self, nodes, values, d, *, weights=None, precision="fp64", m_hint=0,
                  _pack=True):
@@ -525,6 +530,14 @@ def variant_node_pairs(precision, variant):
     v = load().fh_variant_node_pairs(_family(precision), int(variant))
     if v < 0:
         raise FhError(FH_E_ARG, "fh_variant_node_pairs")
+    return bool(v)
+
+
+def variant_octets(precision, variant):
+    """True if a binary64 variant also sums the node blocks far from a point by octets."""
+    v = load().fh_variant_octets(_family(precision), int(variant))
+    if v < 0:
+        raise FhError(FH_E_ARG, "fh_variant_octets")
     return bool(v)
 
 

@@ -50,9 +50,12 @@ def test_workspace_sizes():
     lib = fh.load()
     assert lib.fh_workspace_size(fh.FH_OP_WEIGHTS, 10, 0, 2, 0) == 256
     a = lib.fh_workspace_size(fh.FH_OP_EVAL, 1001, 10 ** 6, 3, 0)
+    a0 = lib.fh_workspace_size(fh.FH_OP_EVAL, 1001, 0, 3, 0)
     b = lib.fh_workspace_size(fh.FH_OP_EVAL, 4097, 10 ** 6, 3, 1)
-    assert 256 < a < b
-    assert a % 256 == 0
+    # binary64: room for the octet variants' sorted points (16 B each: the
+    # point, its node block, its original position); split: the tables only
+    assert a - a0 >= 16 * 10 ** 6 and 256 < a0 < b
+    assert a % 256 == 0 and b == lib.fh_workspace_size(fh.FH_OP_EVAL, 4097, 0, 3, 1)
     # the adjoint holds a 40-byte binary64 record per point, and the split
     # adjoint a 16-byte binary32 record besides
     bw64 = lib.fh_workspace_size(fh.FH_OP_BACKWARD, 2049, 10 ** 6, 4, 0)
@@ -146,7 +149,7 @@ def test_weights_and_lebesgue_host_validation():
 
 def test_lebesgue_max_host_validation_and_workspace():
     lib = fh.load()
-    a = lib.fh_workspace_size(fh.FH_OP_EVAL, 1001, 0, 3, 0)
+    a = lib.fh_workspace_size(fh.FH_OP_EVAL, 1001, 0, 3, 1)  # the node tables
     b = lib.fh_workspace_size(fh.FH_OP_LEBESGUE_MAX, 1001, 0, 3, 0)
     assert b >= a + 2 * 8 * 1000 and b % 256 == 0
     assert lib.fh_workspace_size(fh.FH_OP_LEBESGUE_MAX, 1, 0, 0, 0) > 0
@@ -225,20 +228,26 @@ def test_batched_variant_tables():
 
 
 def test_lebesgue_block_variants():
-    """Binary64 variants 15..24 take the Lebesgue sum by blocks of 16 nodes,
-    19..24 of them summing each block by node pairs; split variants 8..11 by
+    """Binary64 variants 15..26 take the Lebesgue sum by blocks of 16 nodes,
+    19..26 of them summing each block by node pairs and 25..26 the blocks
+    far from a point by octets (their shapes are those of pair variants 22
+    and 20); split variants 8..11 by
     tiles of 32 (the block counterparts of plain shapes); every other single
     variant uses plain sums.  Batched split variants take tiles of 32,
     batched binary64 ones plain sums."""
     blocks = {vid: fh.variant_lebesgue_block("fp64", vid) for vid, *_ in fh.variants("fp64")}
-    assert {vid for vid, u in blocks.items() if u} == set(range(15, 25))
+    assert {vid for vid, u in blocks.items() if u} == set(range(15, 27))
     assert set(blocks.values()) == {0, 16}
     pairs = {vid for vid, *_ in fh.variants("fp64") if fh.variant_node_pairs("fp64", vid)}
-    assert pairs == set(range(19, 25))
+    assert pairs == set(range(19, 27))
+    octets = {vid for vid, *_ in fh.variants("fp64") if fh.variant_octets("fp64", vid)}
+    assert octets == {25, 26}
+    assert not any(fh.variant_octets(f, 0) for f in ("split", "batched_fp64", "batched_split"))
     assert not any(fh.variant_node_pairs(f, 0) for f in ("split", "batched_fp64", "batched_split"))
     shapes = {vid: (p, g, s) for vid, p, g, s in fh.variants("fp64")}
-    for vid in range(15, 25):
+    for vid in range(15, 27):
         assert shapes[vid] in [shapes[v] for v, u in blocks.items() if u == 0]
+    assert shapes[25] == shapes[22] and shapes[26] == shapes[20]
     assert lib_pairs_bad_id() == -1
     sb = {vid: fh.variant_lebesgue_block("split", vid) for vid, *_ in fh.variants("split")}
     assert {vid for vid, u in sb.items() if u} == {8, 9, 10, 11} and set(sb.values()) == {0, 32}
@@ -342,9 +351,10 @@ def test_noalloc_host_validation_and_limit():
               and 2 << 20)
     top = int(re.search(r"#define FH_NOALLOC_MAX_NODES (\d+)LL", hdr).group(1))
     assert top == fh.FH_NOALLOC_MAX_NODES
-    for prec in (0, 1):
-        assert lib.fh_workspace_size(fh.FH_OP_EVAL, top, 10, 3, prec) <= cap
-        assert lib.fh_workspace_size(fh.FH_OP_EVAL, top + 1, 10, 3, prec) > cap
+    # the node tables (a split-precision evaluation workspace holds just
+    # those; the array never holds the octet variants' sorted points)
+    assert lib.fh_workspace_size(fh.FH_OP_EVAL, top, 10, 3, 1) <= cap
+    assert lib.fh_workspace_size(fh.FH_OP_EVAL, top + 1, 10, 3, 1) > cap
 
     def call(**kw):
         a = dict(nodes=P, values=P, n=10, d=3, x=P, m=100, r=P2, lam=None, w=None, prec=0)
@@ -428,7 +438,7 @@ def test_fh_log_reports_choices():
     p = _run_py(code, {"FH_LOG": "1"})
     assert p.returncode == 0, p.stderr
     lines = [ln for ln in p.stderr.splitlines() if ln.startswith("[fh]")]
-    assert lines == ["[fh] fp64 n=1001 m=1000000: variant 22 (built-in)",
+    assert lines == ["[fh] fp64 n=1001 m=1000000: variant 25 (built-in)",
                      "[fh] batched_split n=1041 m=204421648: variant 5 (built-in)"], p.stderr
     q = _run_py(code, {"FH_LOG": "0"})
     assert q.returncode == 0 and "[fh]" not in q.stderr
@@ -445,7 +455,7 @@ def test_autotune_cache_for_another_architecture_is_ignored(tmp_path):
     code = "from paper_1606_06508_amd import fh\nprint(fh.tune_get('fp64', 1001, 10**6))\n"
     p = _run_py(code, {"FH_LOG": "1", "FH_AUTOTUNE_CACHE": str(path)})
     assert p.returncode == 0, p.stderr
-    assert p.stdout.strip() == "22"
+    assert p.stdout.strip() == "25"
     assert "made for 'gfx000'" in p.stderr and "ignored" in p.stderr
     q = _run_py(code, {"FH_LOG": "1", "FH_AUTOTUNE_CACHE": str(tmp_path / "missing.json")})
-    assert q.stdout.strip() == "22" and "cannot open" in q.stderr
+    assert q.stdout.strip() == "25" and "cannot open" in q.stderr

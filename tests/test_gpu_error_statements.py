@@ -12,6 +12,9 @@ block (pair spans at most 8 s and node offsets from the block's anchor at most
 16 s, the pack's test) each pair term carries at most about
 (32 + 4 * 16 + 9 * 8 / 4) u = 114 u instead of 29 u, so their bound is
 (n + 33 + 85) u; the blocks next to the point are summed node by node.
+The octet variants sum the blocks far from a point by octets, rational
+functions of eight nodes in monomial form, whose terms carry at most about
+30 F u + 30 u with the pack's F <= 8 (270 u): their bound is (n + 33 + 245) u.
 
 FP32-split: the float-float difference 2 u32, the reciprocal 2 u32 (one ulp,
 G = 1) or 6 u32 (G = 4: the ulp of v_rcp_f32 plus four roundings), the
@@ -63,7 +66,9 @@ def test_fp64_first_order_bound(n, d):
         finally:
             fh.tune_force("fp64", -1)
         st = metrics.parity(r, lam, r_o, lam_o, s_o)
-        bound = (n + 33 + (85 if fh.variant_node_pairs("fp64", vid) else 0)) * U64
+        extra = 245 if fh.variant_octets("fp64", vid) else (
+            85 if fh.variant_node_pairs("fp64", vid) else 0)
+        bound = (n + 33 + extra) * U64
         assert st["e_cond_max"] <= bound and st["e_cond_lam_max"] <= bound, (vid, grp, st)
 
 

@@ -53,7 +53,7 @@ def test_bits_independent_of_call_shape(n, m, K):
         assert _bits_equal(many[0][c], r1) and _bits_equal(many[1][c], l1), (n, m, K, c)
 
 
-@pytest.mark.parametrize("vid", [3, 10, 15, 17, 18, 20, 22])
+@pytest.mark.parametrize("vid", [3, 10, 15, 17, 18, 20, 22, 25])
 @pytest.mark.parametrize("mode", ["both", "r", "lambda"])
 def test_bits_of_single_calls(vid, mode):
     nodes, vals, pts = _case(1001, 20011, 7)
@@ -98,7 +98,7 @@ def test_counts_and_one_by_one_tables(K, m):
                            lam_metric="cond")
 
 
-@pytest.mark.parametrize("vid", [17, 22])
+@pytest.mark.parametrize("vid", [17, 22, 25])
 def test_caller_weights_table_among_library_tables(vid):
     """A table prepared with caller weights that do not alternate takes
     plain sums inside the same launch as block-sum (17) or node-pair (22)

@@ -35,6 +35,12 @@ def _pair_variants():
     return [v for v in fh.variants("fp64") if fh.variant_node_pairs("fp64", v[0])]
 
 
+def _bound(vid, n):
+    """First-order e_cond bound of a pair variant: (n + 33 + 85) u, and
+    (n + 33 + 245) u where the blocks far from the point take octets."""
+    return (n + 33 + (245 if fh.variant_octets("fp64", vid) else 85)) * U64
+
+
 def _run(nodes, vals, d, pts, vid, lebesgue=True):
     fh.tune_force("fp64", vid)
     try:
@@ -75,7 +81,7 @@ def test_block_edges_against_oracle(kind, n, d):
         r, lam = r.cpu().numpy(), lam.cpu().numpy()
         st = metrics.parity(r, lam, r_o, lam_o, s_o)
         metrics.check_fp64(st, lam_metric="cond")
-        bound = (n + 33 + 85) * U64
+        bound = _bound(vid, n)
         assert st["e_cond_max"] <= bound and st["e_cond_lam_max"] <= bound, (vid, st)
         assert np.array_equal(r[hit], vals[np.searchsorted(nodes, pts[hit])]), vid
         assert np.all(lam[hit] == 1.0), vid
@@ -129,12 +135,12 @@ def test_tables_with_failing_blocks(kind, n, d):
     pts = np.concatenate([_edge_points(nodes), g.uniform(-1, 1, 4000)])
     r_o, lam_o, s_o = oracle.evaluate(nodes, vals, d, pts)
     hit = np.isin(pts, nodes)
-    bound = (n + 33 + 85) * U64
     for vid, *_ in _pair_variants():
         r, lam = _run(nodes, vals, d, pts, vid)
         r, lam = r.cpu().numpy(), lam.cpu().numpy()
         st = metrics.parity(r, lam, r_o, lam_o, s_o)
         metrics.check_fp64(st, lam_metric="cond")
+        bound = _bound(vid, n)
         assert st["e_cond_max"] <= bound and st["e_cond_lam_max"] <= bound, (vid, st)
         assert np.array_equal(r[hit], vals[np.searchsorted(nodes, pts[hit])]), vid
         assert np.all(lam[hit] == 1.0), vid
@@ -208,10 +214,10 @@ def test_block_at_the_width_limit(factor, passes):
     pts = np.concatenate([near, np.nextafter(near, np.inf), np.nextafter(near, -np.inf),
                           _edge_points(nodes), g.uniform(-1, 1, 3000)])
     r_o, lam_o, s_o = oracle.evaluate(nodes, vals, d, pts)
-    bound = (n + 33 + 85) * U64
     for vid, *_ in _pair_variants():
         r, lam = _run(nodes, vals, d, pts, vid)
         st = metrics.parity(r.cpu().numpy(), lam.cpu().numpy(), r_o, lam_o, s_o)
+        bound = _bound(vid, n)
         assert st["e_cond_max"] <= bound and st["e_cond_lam_max"] <= bound, (vid, st)
 
 
@@ -230,5 +236,5 @@ def test_scaled_spans(scale):
         r, lam = _run(nodes, vals, 3, pts, vid)
         st = metrics.parity(r.cpu().numpy(), lam.cpu().numpy(), r_o, lam_o, s_o)
         metrics.check_fp64(st, lam_metric="cond")
-        bound = (257 + 33 + 85) * U64
+        bound = _bound(vid, 257)
         assert st["e_cond_max"] <= bound and st["e_cond_lam_max"] <= bound, (vid, scale, st)
