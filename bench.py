@@ -106,7 +106,8 @@ def _variant_info(n, m):
     shape = dict((v[0], v[1:]) for v in fh.variants("fp64"))[vid]
     return {"id": vid, "points_per_lane": shape[0], "node_split": shape[2],
             "node_block": fh.variant_lebesgue_block("fp64", vid),
-            "node_pairs": fh.variant_node_pairs("fp64", vid)}
+            "node_pairs": fh.variant_node_pairs("fp64", vid),
+            "octets": fh.variant_octets("fp64", vid)}
 
 
 def run_sines(dev, steps, warmup):

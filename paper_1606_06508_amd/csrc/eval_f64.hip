@@ -47,6 +47,20 @@
 
 namespace fhk {
 
+// Workgroups go to the eight XCDs in turn (linear id modulo 8), each XCD
+// with its own L2.  xcd_block maps the linear id g of G to the logical block
+// so that each XCD takes one contiguous run of logical blocks: the octet
+// variants' results, written to the points' original positions, then fill
+// their cache lines inside one L2 (their sorted points keep the chunk of
+// original positions they came from), instead of reaching HBM as partial
+// lines from eight.  A bijection of 0..G-1.
+__device__ __forceinline__ int64_t xcd_block(int64_t g, int64_t G) {
+  constexpr int64_t kXcds = 8;
+  const int64_t q = G / kXcds, r = G % kXcds;
+  const int64_t x = g % kXcds, k = g / kXcds;
+  return x * q + (x < r ? x : r) + k;
+}
+
 // U > 0: the sums are taken by blocks of U nodes (accumulate_f64_blocks)
 // when the table's weights alternate in sign, which *alt says (written by
 // the packing); D, hence r, is then the same with and without Lambda.
@@ -67,7 +81,8 @@ __device__ __forceinline__ void eval_f64_points(const double* __restrict__ x, in
                                                 const double* __restrict__ f, int64_t n,
                                                 const uint32_t* __restrict__ alt,
                                                 double* __restrict__ r, double* __restrict__ lam,
-                                                double* jk_lds, const OctetArgs& oa) {
+                                                double* jk_lds, const OctetArgs& oa,
+                                                int64_t blk) {
   static_assert(!PAIRS || U == kPairBlock, "pair records come in blocks of 16");
   static_assert(PAIRS || !JKL, "LDS staging serves the pair variants");
   constexpr int PG = 4 / S;  // point groups per block
@@ -75,7 +90,7 @@ __device__ __forceinline__ void eval_f64_points(const double* __restrict__ x, in
   // wave index, made provably wave-uniform so node loads stay scalar
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int slice = wave % S, pg = wave / S;
-  const int64_t base = ((int64_t)blockIdx.x * PG + pg) * 64 * P + lane;
+  const int64_t base = (blk * PG + pg) * 64 * P + lane;
   double xp[P], N[P], D[P], A[P];
   bool bad[P];
 #pragma unroll
@@ -223,8 +238,9 @@ __global__ void __launch_bounds__(256)
                const double* __restrict__ f, int64_t n, const uint32_t* __restrict__ alt,
                double* __restrict__ r, double* __restrict__ lam, OctetArgs oa) {
   extern __shared__ double jk_lds[];
+  const int64_t blk = OCT ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
   eval_f64_points<P, G, S, R, L, U, PAIRS, JKL, OCT>(x, m, tx, tw, twf, pr, pok, n_pad, f, n, alt,
-                                                     r, lam, jk_lds, oa);
+                                                     r, lam, jk_lds, oa, blk);
 }
 
 // Several tables on the same points: table blockIdx.y, the points of
@@ -235,11 +251,18 @@ __global__ void __launch_bounds__(256)
     k_eval_f64_many(const double* __restrict__ x, int64_t m, int64_t n_pad, int64_t n,
                     EvalMany a) {
   extern __shared__ double jk_lds[];
-  const int i = blockIdx.y;
+  int i = blockIdx.y;
+  int64_t blk = blockIdx.x;
+  if constexpr (OCT) {
+    const int64_t l = xcd_block((int64_t)blockIdx.y * gridDim.x + blockIdx.x,
+                                (int64_t)gridDim.x * gridDim.y);
+    i = (int)(l / gridDim.x);
+    blk = l % gridDim.x;
+  }
   eval_f64_points<P, G, S, R, L, U, PAIRS, JKL, OCT>(x, m, a.x[i], a.w[i], a.wf[i], a.pr[i],
                                                      a.pok[i], n_pad, a.f[i], n, a.alt[i], a.r[i],
                                                      a.lam[i], jk_lds,
-                                                     OctetArgs{a.oc[i], a.ook[i], a.order});
+                                                     OctetArgs{a.oc[i], a.ook[i], a.order}, blk);
 }
 
 // Dynamic LDS of a pair variant's launch: J and K of the node range when it

@@ -182,15 +182,14 @@ struct EvalMany {
 };
 // The octet variants' buffers in an evaluation workspace, after the node
 // tables: the table's octet records ([n_pad / kPairBlock][kOctetEvalRec])
-// and summary word, and room for m points sorted by node block (per-block
-// counts and cursors, each point's block, the sorted points and their
-// original positions; a launch over several tables sorts into its first
-// table's workspace).
+// and summary word, and room for m points sorted by node block (per tile
+// of the sort its count, then sorted start, per block; each point's block;
+// the sorted points and their original positions; a launch over several
+// tables sorts into its first table's workspace).
 struct OctetBufs {
   double* rec;
   uint32_t* ok;
-  int32_t* count;
-  int32_t* cursor;
+  int32_t* hist;
   int32_t* key;
   double* xs;
   int32_t* order;

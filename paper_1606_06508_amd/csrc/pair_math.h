@@ -591,24 +591,6 @@ __device__ __forceinline__ void octet_eval(const double* __restrict__ o, double 
 // block's octets exactly when x <= L or x >= R.
 constexpr int64_t kOctetEvalRec = 54;
 
-// The evaluation's octet record of block b; returns whether both octets
-// passed (a block with no node below n passes).
-__device__ inline bool octet_eval_record(const double* __restrict__ x,
-                                         const double* __restrict__ w,
-                                         const double* __restrict__ v, int64_t n, int64_t b,
-                                         double* __restrict__ rec) {
-  const int64_t k0 = b * kPairBlock;
-  const double c = pair_anchor(x, n, k0);
-  const int64_t kl = k0 - 16 * kOctetGap - 1, kr = k0 + 16 * (kOctetGap + 1);
-  rec[0] = c;
-  rec[51] = kl >= 0 && kl < n ? x[kl] : -__builtin_inf();
-  rec[52] = kr < n ? x[kr] : __builtin_inf();
-  rec[kOctetEvalRec - 1] = 0.0;
-  const bool e = octet_coefficients<true>(x, w, v, n, k0, c, 0, rec + 1);
-  const bool o = octet_coefficients<true>(x, w, v, n, k0, c, 1, rec + 26);
-  return (e && o) || k0 >= n;
-}
-
 // A wave-uniform double as a scalar value (the same in every lane)
 __device__ __forceinline__ double uniform_f64(double v) {
   const int64_t b = __builtin_bit_cast(int64_t, v);
