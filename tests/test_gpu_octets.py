@@ -59,11 +59,27 @@ def _bits(a):
     return np.where(np.isnan(a), np.nan, a).view(np.uint64)
 
 
+def _served_edges(nodes):
+    """Midpoints just beyond the closest points each block's octets serve
+    (L = x_{16b-33}, R = x_{16b+48}): where the octets' error factor is
+    largest."""
+    n = nodes.size
+    out = []
+    for k0 in range(0, n, 16):
+        kl, kr = k0 - 33, k0 + 48
+        if kl >= 1:
+            out.append(nodes[kl] - 0.5 * (nodes[kl] - nodes[kl - 1]))
+        if kr + 1 < n:
+            out.append(nodes[kr] + 0.5 * (nodes[kr + 1] - nodes[kr]))
+    return np.array(out)
+
+
 def _points(nodes, g, m):
     n = nodes.size
     e = nodes[sorted({k for b in range(0, n, 16) for k in (b - 1, b, b + 15, b + 16)
                       if 0 <= k < n})]
-    return np.concatenate([nodes, np.nextafter(e, np.inf), np.nextafter(e, -np.inf),
+    return np.concatenate([nodes, _served_edges(nodes), np.nextafter(e, np.inf),
+                           np.nextafter(e, -np.inf),
                            0.5 * (nodes[:-1] + nodes[1:]),
                            [nodes[0] - 1e-9, nodes[-1] + 1e-9, -3.0, 5.0, np.nan, np.inf],
                            g.uniform(nodes[0], nodes[-1], m)])
