@@ -106,5 +106,5 @@ def test_library_loads_a_saved_table(tmp_path):
     p = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120,
                        cwd=root, env=dict(os.environ, FH_AUTOTUNE_CACHE=str(path), FH_LOG="1"))
     assert p.returncode == 0, p.stderr
-    assert p.stdout.split() == ["3", "13", "22"], (p.stdout, p.stderr)
+    assert p.stdout.split() == ["3", "13", "25"], (p.stdout, p.stderr)
     assert "2 entries installed" in p.stderr
