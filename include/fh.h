@@ -413,7 +413,7 @@ fh_status fh_batch_status(fh_batch* b, void* stream, uint32_t* bits_out);
  *                  fh_workspace_size(FH_OP_EVAL, n, m, ...) includes for m
  *                  points (n <= 65536, m < 2^31); with less room the call
  *                  runs the pair variant of the same shape (other bits),
- *                  as fh_eval_noalloc always does;
+ *                  as fh_eval_noalloc always does, and FH_LOG=1 reports it;
  *   fh_variant_strip_points  points one block covers (single-interpolant
  *                  families) or one work item (batched families), -1 for a
  *                  bad family or id;

@@ -2,6 +2,7 @@
 // launch.  All device work is enqueued on the caller's stream; nothing here
 // allocates (the batched entry points, which own device memory, are in
 // batched.hip).
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 
@@ -70,7 +71,15 @@ bool octets_usable(int64_t n, int64_t m, size_t ws_bytes) {
 fhk::EvalConfig eval_config(int32_t prec, int64_t n, int64_t m, bool want_r, bool want_l,
                             bool octets) {
   fhk::EvalConfig c = fhk::choose_eval_config(prec, n, 0, m, want_r, want_l);
-  if (prec == FH_FP64 && !octets) c.variant = fhk::f64_variant_octet_twin(c.variant);
+  if (prec == FH_FP64 && !octets) {
+    const int twin = fhk::f64_variant_octet_twin(c.variant);
+    if (twin != c.variant && fhk::log_enabled())
+      std::fprintf(stderr,
+                   "[fh] fp64 n=%lld m=%lld: variant %d has no workspace room for the sorted "
+                   "points (fh_workspace_size(FH_OP_EVAL, n, m, ...)): variant %d runs\n",
+                   (long long)n, (long long)m, c.variant, twin);
+    c.variant = twin;
+  }
   return c;
 }
 

@@ -201,3 +201,30 @@ def test_many_tables_each_with_the_bits_of_its_own_call():
     for i, (nodes, v, d) in enumerate(tables):
         r1, lam1 = _run(nodes, v, d, pts, 25)
         assert np.array_equal(_bits(r[i]), _bits(r1)) and np.array_equal(_bits(lam[i]), _bits(lam1))
+
+
+def test_log_reports_the_twin_for_a_small_workspace():
+    """FH_LOG=1: a call whose workspace has no room for the sorted points
+    says which pair variant runs instead of the octet variant."""
+    import os
+    import subprocess
+    import sys
+    code = (
+        "import numpy as np, torch\n"
+        "from paper_1606_06508_amd import fh, inputs\n"
+        "x = torch.from_numpy(inputs.equispaced(1001)).cuda()\n"
+        "p = torch.rand(5000, dtype=torch.float64, device='cuda') * 2 - 1\n"
+        "nb = fh.workspace_size(fh.FH_OP_EVAL, 1001, 0, 3)\n"
+        "ws = torch.zeros(nb, dtype=torch.uint8, device='cuda')\n"
+        "r = torch.empty_like(p)\n"
+        "fh.tune_force('fp64', 25)\n"
+        "st = fh.load().fh_eval(fh._ptr(x), fh._ptr(x), 1001, 3, fh._ptr(p), 5000, fh._ptr(r),\n"
+        "                       None, None, fh.FH_FP64, fh._ptr(ws), nb, fh._stream(x.device))\n"
+        "torch.cuda.synchronize()\n"
+        "print(st)\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120,
+                       cwd=root, env=dict(os.environ, FH_LOG="1"))
+    assert p.returncode == 0 and p.stdout.strip() == "0", p.stderr
+    assert "variant 25 has no workspace room for the sorted points" in p.stderr
+    assert "variant 22 runs" in p.stderr
